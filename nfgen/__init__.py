@@ -1,0 +1,13 @@
+"""Seeded synthetic input generators for the n-field block solver.
+
+This package only builds inputs: assembled block matrices, near-nullspace
+vectors per field and right-hand sides, on structured Q1 meshes.  It holds
+none of the solver's arithmetic (no aggregation, no smoothing, no Krylov
+method).  Both the GPU library's tests/benchmarks and the CPU oracle's tests
+take their inputs from here, the way they would read a file from disk.
+"""
+from .systems import (Field, BlockSystem, tsi2d, fsi3d, lung3d, request_trace,
+                      uniform_rhs)
+
+__all__ = ["Field", "BlockSystem", "tsi2d", "fsi3d", "lung3d", "request_trace",
+           "uniform_rhs"]

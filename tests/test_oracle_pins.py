@@ -1,0 +1,470 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own code: each compares it with a
+closed form, an invariant, a brute-force check on a tiny input, a dense
+library factorisation, or the paper's matrix form of a method.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import nfgen
+import oracle
+from oracle import Oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_tsi(nel=6, **kw):
+    return nfgen.tsi2d(nel=nel, **kw)
+
+
+# --------------------------------------------------------------- splitmix64
+def test_splitmix64_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    gamma = 0x9E3779B97F4A7C15
+    for k, hexval in rows:
+        assert oracle.splitmix64((int(k) * gamma) % 2**64) == int(hexval, 16)
+
+
+# ------------------------------------------------------------- block SpMV
+def test_block_matvec_matches_dense():
+    s = small_tsi(8)
+    o = Oracle(s.fields, s.blocks, "BGS(LU)")
+    x = np.random.default_rng(1).standard_normal(s.n)
+    A = s.assembled().toarray()
+    y = o.matvec(x)
+    ref = A @ x
+    bound = 1e-14 * (np.abs(A) @ np.abs(x))
+    assert np.all(np.abs(y - ref) <= bound + 1e-300)
+
+
+# ------------------------------------------------------------ node graph
+@pytest.mark.parametrize("field,b", [(0, 2), (1, 1)])
+def test_node_graph_brute_force(field, b):
+    s = small_tsi(5)
+    A = s.blocks[field][field]
+    gp, ga = oracle.node_graph(A, b)
+    D = A.toarray() != 0
+    nn = A.shape[0] // b
+    for u in range(nn):
+        blk = D[b * u:b * u + b].reshape(b, nn, b).any(axis=(0, 2))
+        blk[u] = False
+        assert list(ga[gp[u]:gp[u + 1]]) == list(np.nonzero(blk)[0])
+
+
+# ---------------------------------------------------------------- MIS-2
+def _dist2(gp, ga, n):
+    adj = np.zeros((n, n), bool)
+    for u in range(n):
+        adj[u, ga[gp[u]:gp[u + 1]]] = True
+    a2 = adj | (adj.astype(int) @ adj.astype(int) > 0)
+    np.fill_diagonal(a2, False)
+    return adj, a2
+
+
+def _random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.random((n, n)) < p
+    M = M | M.T
+    np.fill_diagonal(M, False)
+    gp = np.zeros(n + 1, np.int64)
+    adj = []
+    for u in range(n):
+        nb = np.nonzero(M[u])[0]
+        adj.extend(nb)
+        gp[u + 1] = len(adj)
+    return gp, np.array(adj, np.int32)
+
+
+GRAPHS = [("tsi-structure", lambda: oracle.node_graph(small_tsi(9).blocks[0][0], 2)),
+          ("tsi-thermo", lambda: oracle.node_graph(small_tsi(9).blocks[1][1], 1)),
+          ("random-sparse", lambda: _random_graph(150, 0.02, 3)),
+          ("random-dense", lambda: _random_graph(120, 0.1, 4)),
+          ("isolated", lambda: _random_graph(60, 0.0, 5))]
+
+
+@pytest.mark.parametrize("name,make", GRAPHS)
+@pytest.mark.parametrize("seed", [0, 7])
+def test_mis2_independent_maximal_partition(name, make, seed):
+    gp, ga = make()
+    n = len(gp) - 1
+    st, agg, na = oracle.mis2_aggregate(gp, ga, seed)
+    adj, a2 = _dist2(gp, ga, n)
+    roots = np.nonzero(st == 1)[0]
+    assert set(np.unique(st)) <= {1, 2}
+    # independence: roots pairwise at distance >= 3
+    assert not a2[np.ix_(roots, roots)].any()
+    # maximality: every non-root within distance 2 of a root
+    others = np.nonzero(st != 1)[0]
+    assert a2[np.ix_(others, roots)].any(axis=1).all()
+    # partition with one root per aggregate; roots numbered in node order
+    assert na == len(roots)
+    assert np.all(agg >= 0) and np.all(agg < na)
+    assert list(agg[roots]) == list(range(na))
+    # every node is at most 2 steps from its own root, inside its aggregate
+    for u in others:
+        r = roots[agg[u]]
+        assert adj[u, r] or (adj[u] & adj[:, r] & (agg == agg[u])).any()
+
+
+def test_mis2_deterministic_and_seeded():
+    gp, ga = oracle.node_graph(small_tsi(12).blocks[1][1], 1)
+    a = oracle.mis2_aggregate(gp, ga, 3)
+    b = oracle.mis2_aggregate(gp, ga, 3)
+    c = oracle.mis2_aggregate(gp, ga, 4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert not np.array_equal(a[0], c[0])
+
+
+def test_mis2_matches_definition_bruteforce():
+    """Synchronous rounds re-derived by brute force over (key, id) tuples."""
+    gp, ga = _random_graph(80, 0.05, 11)
+    n = 80
+    _, a2 = _dist2(gp, ga, n)
+    seed = 5
+    key = [oracle.splitmix64(seed ^ oracle.splitmix64(u)) for u in range(n)]
+    st = np.zeros(n, int)
+    while (st == 0).any():
+        und = st == 0
+        new = [u for u in range(n) if und[u] and all(
+            (key[w], w) < (key[u], u) for w in np.nonzero(a2[u] & und)[0])]
+        st[new] = 1
+        near = a2[:, st == 1].any(axis=1)
+        st[und & near & (st == 0)] = 2
+    got, _, _ = oracle.mis2_aggregate(gp, ga, seed)
+    assert np.array_equal(got, st)
+
+
+# ------------------------------------------------------ tentative prolongator
+def test_tentative_orthonormal_and_reproduces_nullspace():
+    s = small_tsi(10)
+    A = s.blocks[0][0]
+    gp, ga = oracle.node_graph(A, 2)
+    _, agg, na = oracle.mis2_aggregate(gp, ga, 0)
+    B = s.fields[0].nullspace
+    P, Bc, ndead = oracle.tentative(agg, na, 2, B)
+    assert ndead == 0
+    PtP = (P.T @ P).toarray()
+    assert np.allclose(PtP, np.eye(P.shape[1]), atol=1e-14)
+    assert np.max(np.abs(P @ Bc.T - B.T)) < 1e-14
+    # R factors upper triangular with positive diagonal
+    for a in range(na):
+        R = Bc[:, 3 * a:3 * a + 3].T
+        assert np.allclose(np.tril(R, -1), 0) and np.all(np.diag(R) > 0)
+
+
+def test_tentative_dead_column():
+    # one aggregate of a single 2-dof node with 3 rigid modes -> rank 2
+    B = np.array([[1.0, 0.0], [0.0, 1.0], [2.0, -3.0]])   # third = 2 e1 - 3 e2
+    P, Bc, ndead = oracle.tentative(np.array([0]), 1, 2, B)
+    assert ndead == 1
+    assert np.allclose(P.toarray()[:, 2], 0.0)
+    assert np.max(np.abs(P @ Bc.T - B.T)) < 1e-14
+
+
+# ---------------------------------------------------------- hierarchy pins
+@pytest.fixture(scope="module")
+def tsi_ctx():
+    s = nfgen.tsi2d(nel=16)
+    return s, Oracle(s.fields, s.blocks, "BGS(AMG)", sweeps=2, coarse_max=40)
+
+
+def test_power_lambda_close_to_eig(tsi_ctx):
+    s, o = tsi_ctx
+    A = s.blocks[1][1]
+    d = A.diagonal()
+    ev = np.max(np.abs(np.linalg.eigvals(A.toarray() / d[:, None])))
+    lam = o.lam(1, 0)
+    assert lam == oracle.power_lambda(A, 0, 10)
+    assert 0.5 * ev < lam <= ev * (1 + 1e-12)
+
+
+def _check_P_reproduces_nullspace(o, h, A, B):
+    P = o.matrix(h, 0, "P")
+    Bc = o.nullspace(h, 1)
+    AB = np.abs(A @ B.T).max(axis=1)
+    free = AB < 1e-12                     # rows where A B = 0
+    assert free.sum() > 0.5 * A.shape[0]
+    err = np.abs(P @ Bc.T - B.T).max(axis=1)
+    assert err[free].max() < 1e-12
+    # and the tentative part alone reproduces B exactly on every row
+    assert o.nlevels(h) >= 2
+
+
+def test_smoothed_P_reproduces_rigid_modes(tsi_ctx):
+    s, o = tsi_ctx
+    _check_P_reproduces_nullspace(o, 0, s.blocks[0][0], s.fields[0].nullspace)
+
+
+def test_smoothed_P_reproduces_constant_mode():
+    """Pure Laplacian grounded at one node: constants are in the kernel of every
+    row that does not touch the grounded node."""
+    s = nfgen.tsi2d(nel=16, heat_mass=False, coupling=False)
+    K = s.blocks[1][1][1:, 1:].tocsr()
+    f = nfgen.Field("heat", K.shape[0], 1, np.ones((1, K.shape[0])))
+    o = Oracle([f], [[K]], "AMG", coarse_max=40)
+    _check_P_reproduces_nullspace(o, 0, K, f.nullspace)
+
+
+def test_galerkin_rap_and_transpose(tsi_ctx):
+    s, o = tsi_ctx
+    for h in range(o.hier_count()):
+        for l in range(o.nlevels(h) - 1):
+            A = o.matrix(h, l, "A")
+            P = o.matrix(h, l, "P")
+            R = o.matrix(h, l, "R")
+            Ac = o.matrix(h, l + 1, "A")
+            # R == P^T bitwise (pattern and values)
+            PT = sp.csr_matrix(P.T)
+            PT.sort_indices()
+            assert np.array_equal(R.indptr, PT.indptr) and np.array_equal(R.indices, PT.indices)
+            assert np.array_equal(R.data, PT.data)
+            dense = P.toarray().T @ A.toarray() @ P.toarray()
+            scale = np.abs(dense).max()
+            assert np.abs(Ac.toarray() - dense).max() < 1e-13 * scale
+            sym = np.abs(Ac - Ac.T).max() / scale
+            assert sym < 1e-14
+
+
+def test_one_level_is_exact():
+    s = nfgen.tsi2d(nel=4)
+    o = Oracle(s.fields, s.blocks, "BGS[sweeps=1,order=fwd](AMG)", coarse_max=1000)
+    assert [o.nlevels(h) for h in range(o.hier_count())] == [1, 1]
+    r = np.random.default_rng(0).standard_normal(s.n)
+    z = o.precond_apply(r)
+    n0 = s.fields[0].ndof
+    # forward BGS with exact block solves: field 0 solve, then field 1
+    z0 = np.linalg.solve(s.blocks[0][0].toarray(), r[:n0])
+    z1 = np.linalg.solve(s.blocks[1][1].toarray(), r[n0:] - s.blocks[1][0] @ z0)
+    assert np.allclose(z, np.concatenate([z0, z1]), rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Chebyshev
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_chebyshev_closed_form(degree):
+    n, c = 40, 0.3
+    A = sp.diags([np.full(n - 1, c), np.ones(n), np.full(n - 1, c)], [-1, 0, 1], format="csr")
+    k = np.arange(1, n + 1)
+    lam_k = 1 + 2 * c * np.cos(k * np.pi / (n + 1))
+    V = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(np.arange(1, n + 1), k) * np.pi / (n + 1))
+    lam = lam_k.max()
+    lo, hi = lam / 30.0, 1.1 * lam
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    T = lambda m, t: np.cos(m * np.arccos(t)) if abs(t) <= 1 else np.cosh(m * np.arccosh(abs(t))) * (np.sign(t) ** m)
+    for j in range(n):
+        v = V[:, j]
+        x = oracle.chebyshev(A, lam, A @ v, degree=degree)
+        p = T(degree, (th - lam_k[j]) / de) / T(degree, th / de)
+        assert np.abs(x - (1 - p) * v).max() < 1e-14
+
+
+# ---------------------------------------------------------------- V-cycle
+def test_vcycle_symmetric_contraction():
+    s = nfgen.tsi2d(nel=10)
+    sub = [s.fields[1]]
+    blocks = [[s.blocks[1][1]]]
+    o = Oracle(sub, blocks, "AMG", coarse_max=20)
+    assert o.nlevels(0) >= 2
+    n = s.fields[1].ndof
+    M = o.precond_apply(np.eye(n))          # row i = M e_i  (M symmetric)
+    A = blocks[0][0].toarray()
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    ev = sla.eigvals(np.eye(n) - M.T @ A).real
+    assert ev.min() > -1e-10 and ev.max() < 1.0
+
+
+# -------------------------------------------------------------------- BGS
+def _bgs_dense_formula(s, r, sweeps, order):
+    A = s.assembled().toarray()
+    n0 = s.fields[0].ndof
+    M = np.zeros_like(A)
+    M[:n0, :n0] = A[:n0, :n0]
+    M[n0:, n0:] = A[n0:, n0:]
+    if order == "fwd":
+        M[n0:, :n0] = A[n0:, :n0]
+    else:
+        M[:n0, n0:] = A[:n0, n0:]
+    E = np.eye(len(A)) - np.linalg.solve(M, A)
+    return (np.eye(len(A)) - np.linalg.matrix_power(E, sweeps)) @ np.linalg.solve(A, r)
+
+
+@pytest.mark.parametrize("order", ["fwd", "bwd"])
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_bgs_exact_blocks_stationary_iteration(order, sweeps):
+    s = nfgen.tsi2d(nel=5, alpha=0.3, cba=0.2)
+    o = Oracle(s.fields, s.blocks, f"BGS[sweeps={sweeps},order={order}](LU)")
+    r = np.random.default_rng(2).standard_normal(s.n)
+    z = o.precond_apply(r)
+    ref = _bgs_dense_formula(s, r, sweeps, order)
+    assert np.abs(z - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("order,drop", [("fwd", (0, 1)), ("bwd", (1, 0))])
+def test_bgs_block_triangular_one_iteration(order, drop):
+    s = nfgen.tsi2d(nel=5)
+    s.blocks[drop[0]][drop[1]] = None
+    o = Oracle(s.fields, s.blocks, f"BGS[sweeps=1,order={order}](LU)")
+    x, st = o.gmres(s.rhs[0], rtol=1e-12)
+    assert st["iters"] == 1 and st["status"] == 0
+    xd = np.linalg.solve(s.assembled().toarray(), s.rhs[0])
+    assert np.abs(x - xd).max() < 1e-10 * np.abs(xd).max()
+
+
+# ------------------------------------------------------------------- SIMPLE
+def _simple_dense(A11, A12, A21, A22, dt):
+    S = A22 - A21 @ np.diag(1 / dt) @ A12
+    n1 = len(A11)
+    L = np.block([[A11, np.zeros_like(A12)], [A21, S]])
+    U = np.block([[np.eye(n1), np.diag(1 / dt) @ A12], [np.zeros_like(A21), np.eye(len(A22))]])
+    return L @ U
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_simple_matches_matrix_form(mode):
+    s = nfgen.tsi2d(nel=5, alpha=0.2, cba=0.1)
+    A = s.assembled().toarray()
+    n0 = s.fields[0].ndof
+    A11, A12, A21, A22 = A[:n0, :n0], A[:n0, n0:], A[n0:, :n0], A[n0:, n0:]
+    B11 = s.blocks[0][0].toarray()
+    dt = {0: np.abs(B11).sum(1), 1: np.abs(B11.sum(1)), 2: np.diag(B11)}[mode]
+    if mode == 1:
+        B = s.blocks[0][0]
+        if np.min(dt) < 1e-12:
+            pytest.skip("literal row sums vanish on this operator")
+    o = Oracle(s.fields, s.blocks, "SIMPLE(LU;LU)", simplec_mode=mode)
+    r = np.random.default_rng(3).standard_normal(s.n)
+    z = o.precond_apply(r)
+    M = _simple_dense(A11, A12, A21, A22, dt)
+    ref = np.linalg.solve(M, r)
+    assert np.abs(z - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_simple_exact_when_A11_diagonal():
+    """A11 diagonal and positive: the SIMPLEC diagonal equals A11, so M_SIMPLE = A."""
+    rng = np.random.default_rng(4)
+    n1, n2 = 30, 12
+    A11 = sp.diags(rng.uniform(1, 2, n1), format="csr")
+    A12 = sp.random(n1, n2, 0.3, random_state=1, format="csr")
+    A21 = sp.random(n2, n1, 0.3, random_state=2, format="csr")
+    fields = [nfgen.Field("a", n1, 1, np.ones((1, n1))), nfgen.Field("b", n2, 1, np.ones((1, n2)))]
+    o = Oracle(fields, [[A11, A12], [A21, None]], "SIMPLE(LU;LU)")
+    b = rng.standard_normal(n1 + n2)
+    x, st = o.gmres(b, rtol=1e-12)
+    assert st["iters"] == 1
+    A = sp.bmat([[A11, A12], [A21, None]]).toarray()
+    assert np.abs(A @ x - b).max() < 1e-10
+
+
+# ------------------------------------------------------------ monolithic AMG
+def test_mono_amg_one_field_is_single_field_amg():
+    s = nfgen.tsi2d(nel=12)
+    f = [s.fields[0]]
+    b = [[s.blocks[0][0]]]
+    o1 = Oracle(f, b, "AMG", coarse_max=30)
+    o2 = Oracle(f, b, "AMG(BGS)", coarse_max=30)
+    r = np.random.default_rng(5).standard_normal(f[0].ndof)
+    z1, z2 = o1.precond_apply(r), o2.precond_apply(r)
+    assert np.abs(z1 - z2).max() < 1e-13 * np.abs(z1).max()
+
+
+def test_mono_amg_decoupled_is_per_field_amg():
+    s = nfgen.tsi2d(nel=16, coupling=False)
+    o1 = Oracle(s.fields, s.blocks, "BGS[sweeps=1](AMG)", coarse_max=200)
+    o2 = Oracle(s.fields, s.blocks, "AMG(BGS)", coarse_max=200)
+    assert o2.nlevels(0) == o1.nlevels(0) == o1.nlevels(1)
+    r = np.random.default_rng(6).standard_normal(s.n)
+    z1, z2 = o1.precond_apply(r), o2.precond_apply(r)
+    assert np.abs(z1 - z2).max() < 1e-12 * np.abs(z1).max()
+
+
+def test_mono_amg_coarse_blocks_are_RiAijPj():
+    s = nfgen.tsi2d(nel=16)
+    o = Oracle(s.fields, s.blocks, "AMG(BGS)", coarse_max=100)
+    assert o.nlevels(0) >= 2
+    for l in range(o.nlevels(0) - 1):
+        for i in range(2):
+            for j in range(2):
+                Aij = o.matrix(0, l, "A", i, j).toarray()
+                Ri = o.matrix(0, l, "R", i).toarray()
+                Pj = o.matrix(0, l, "P", j).toarray()
+                Ac = o.matrix(0, l + 1, "A", i, j).toarray()
+                ref = Ri @ Aij @ Pj
+                assert np.abs(Ac - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1e-300)
+    # whole-matrix form: R A P with block-diagonal R, P
+    A = sp.bmat([[o.matrix(0, 0, "A", i, j) for j in range(2)] for i in range(2)]).toarray()
+    P = sla.block_diag(*[o.matrix(0, 0, "P", i).toarray() for i in range(2)])
+    Ac = sp.bmat([[o.matrix(0, 1, "A", i, j) for j in range(2)] for i in range(2)]).toarray()
+    assert np.abs(Ac - P.T @ A @ P).max() < 1e-13 * np.abs(Ac).max()
+
+
+# -------------------------------------------------------------------- GMRES
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_gmres_minimal_residual_over_krylov_space(k):
+    s = nfgen.tsi2d(nel=4)
+    o = Oracle(s.fields, s.blocks, "BGS(AMG)", coarse_max=10)
+    A = s.assembled().toarray()
+    b = s.rhs[0]
+    x, st = o.gmres(b, restart=50, maxit=k, rtol=1e-30)
+    assert st["iters"] == k
+    # x must minimise ||b - A x|| over x in M K_k(A M, b)
+    cols = []
+    v = b.copy()
+    for _ in range(k):
+        mv = o.precond_apply(v)
+        cols.append(mv)
+        v = A @ mv
+    K = np.array(cols).T
+    Q, _ = np.linalg.qr(K)
+    c, *_ = np.linalg.lstsq(A @ Q, b, rcond=None)
+    best = np.linalg.norm(b - A @ Q @ c)
+    got = np.linalg.norm(b - A @ x)
+    assert abs(got - best) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_gmres_restart_and_flexible_reach_tolerance():
+    s = nfgen.tsi2d(nel=8)
+    o = Oracle(s.fields, s.blocks, "BGS(AMG)", sweeps=2, coarse_max=30)
+    A = s.assembled()
+    xd = spla.spsolve(A.tocsc(), s.rhs[0])
+    for restart, flexible in [(50, 0), (3, 0), (50, 1), (4, 1)]:
+        x, st = o.gmres(s.rhs[0], restart=restart, flexible=flexible, rtol=1e-10)
+        rel = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+        assert st["status"] == 0 and rel < 1e-10 and abs(rel - st["relres"]) < 1e-12
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-7
+
+
+def test_end_to_end_tsi_full_size_vs_sparse_lu():
+    s = nfgen.tsi2d()
+    o = Oracle(s.fields, s.blocks, "BGS(AMG)", sweeps=2, order="bwd")
+    x, st = o.gmres(s.rhs[0], restart=50, rtol=1e-8)
+    A = s.assembled()
+    xd = spla.spsolve(A.tocsc(), s.rhs[0])
+    assert st["status"] == 0
+    assert np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0]) < 1e-8
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-6
+
+
+# -------------------------------------------------------------- error paths
+def test_errors():
+    s = nfgen.tsi2d(nel=4)
+    with pytest.raises(oracle.OracleError) as e:
+        Oracle(s.fields, s.blocks, "BGS(AMG", sweeps=2)
+    assert e.value.code == -1
+    bad = [[s.blocks[0][0], s.blocks[0][1]], [s.blocks[1][0], None]]
+    with pytest.raises(oracle.OracleError) as e:
+        Oracle(s.fields, bad, "BGS(AMG)")
+    assert e.value.code == -3
+    o = Oracle(s.fields, s.blocks, "BGS(AMG)", coarse_max=10)
+    b = s.rhs[0].copy()
+    b[3] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        o.gmres(b)
+    assert e.value.code == -5
+    x, st = o.gmres(s.rhs[0], maxit=1, rtol=1e-14)
+    assert st["status"] == 1 and st["iters"] == 1
