@@ -1,0 +1,172 @@
+/*
+ * nfield.h - C ABI of the MI355X (gfx950) n-field block solver.
+ *
+ * The library solves the N x N block-sparse linear system of a monolithic
+ * coupled problem,
+ *
+ *     [A_11 ... A_1N] [x_1]   [b_1]
+ *     [ ...  ...  ...] [...] = [...]        (paper: Sec. 4, the blocked system;
+ *     [A_N1 ... A_NN] [x_N]   [b_N]         some blocks may be zero)
+ *
+ * with restarted GMRES preconditioned from the right (Sec. 3.2: solve
+ * (A P) y = b, then x = P y), where the preconditioner P ~ A^-1 is one of the
+ * paper's block methods (Sec. 4) or a nesting of them (Sec. 5):
+ *
+ *   "BGS(AMG)"              block Gauss-Seidel (Sec. 4.1) with one
+ *                           smoothed-aggregation AMG V-cycle (Sec. 3.3,
+ *                           Algorithm 1) per diagonal block;
+ *   "SIMPLE(AMG)"           SIMPLE / SIMPLEC (Sec. 4.2);
+ *   "SIMPLE(BGS(AMG);AMG)"  n-field SIMPLE with merged predictor fields
+ *                           (Sec. 4.2, block merging) and an AMG on the
+ *                           approximate Schur complement;
+ *   "AMG(BGS)", "AMG(SIMPLE)"  monolithic AMG (Sec. 4.3): block-diagonal
+ *                           transfers, coarse blocks R_i A_ij P_j, BGS or
+ *                           SIMPLE level smoothers;
+ *   "LU"                    dense direct solve (small blocks only).
+ * Optional per-method parameters: "BGS[sweeps=2,order=bwd](AMG)".
+ *
+ * All device work runs in the library's own HIP kernels for gfx950, enqueued
+ * on the caller's stream.  Every vector argument named *_dev is a device
+ * pointer owned by the caller (for instance a torch tensor), FP64, holding
+ * nrhs columns of length n = sum_i ndof_i one after the other (column-major
+ * n x nrhs), each column in global field order [x_1; ...; x_N].
+ *
+ * Return codes: 0 = OK; NFIELD_NOT_CONVERGED (> 0) is soft (x holds the last
+ * iterate and stats are valid); negative values are hard errors (outputs
+ * undefined; a context being created is not returned).  nfield_last_error()
+ * gives a message for the last error of the calling thread.  A context is not
+ * thread-safe; distinct contexts are independent.
+ */
+#ifndef NFIELD_H
+#define NFIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NFIELD_OK = 0,
+  NFIELD_NOT_CONVERGED = 1,
+  NFIELD_EINVAL = -1,      /* malformed input: CSR not sorted/unique/in range, sizes, spec */
+  NFIELD_ENOMEM = -2,      /* device allocation failed or a size limit was exceeded */
+  NFIELD_ESINGULAR = -3,   /* zero diagonal block / entry where a method needs one, zero LU pivot */
+  NFIELD_EBREAKDOWN = -4,  /* Krylov breakdown that is not a converged solution */
+  NFIELD_ENAN = -5,        /* non-finite value in the right-hand side or the iteration */
+  NFIELD_EHIP = -6         /* a HIP runtime call failed */
+} nfield_status;
+
+typedef struct nfield_ctx nfield_ctx;   /* opaque; owns all device state of one system */
+
+/* One block A_ij in CSR form, host memory, FP64.  Column indices must be
+ * strictly increasing within each row.  nnz == 0 or val == NULL marks a zero
+ * block.  Copied by nfield_setup; the caller may free it on return. */
+typedef struct {
+  int32_t nrows, ncols;
+  int64_t nnz;
+  const int64_t *rowptr;   /* nrows + 1 */
+  const int32_t *colind;   /* nnz */
+  const double *val;       /* nnz */
+} nfield_csr;
+
+/* One physical field.  Its dofs are grouped in nodes of block_size
+ * consecutive dofs (ndof % block_size == 0).  nullspace holds nns
+ * near-nullspace vectors (rigid-body modes, constants, unit vectors) as
+ * nns rows of ndof values (ndof x nns column-major), host memory, copied. */
+typedef struct {
+  int32_t ndof, block_size, nns;
+  const double *nullspace;
+} nfield_field;
+
+/* Setup options.  Zero-initialise and call nfield_default_opts() first. */
+typedef struct {
+  int32_t sweeps;          /* BGS sweeps k_max (Sec. 4.1); default 1 */
+  int32_t order;           /* BGS order: 0 forward, 1 backward, 2 symmetric; default 1 */
+  int32_t coarse_max;      /* stop coarsening at <= this many dofs; dense LU there; 200 */
+  int32_t max_levels;      /* AMG level limit; 10 */
+  int32_t cheb_degree;     /* Chebyshev polynomial degree of the smoother; 2 */
+  int32_t power_its;       /* power iterations for lambda_max(D^-1 A); 10 */
+  double cheb_ratio;       /* smoothing interval [lambda/ratio, boost*lambda]; 30 */
+  double cheb_boost;       /* 1.1 */
+  int32_t simplec_mode;    /* SIMPLE diagonal: 0 sum_j|a_ij|, 1 |sum_j a_ij|, 2 a_ii; 0 */
+  const int32_t *split;    /* field -> SIMPLE group (0 predictor, 1 Schur); NULL: last field */
+  int32_t schur_direct_max;/* Schur complements up to this size are solved by dense LU; 5000 */
+  int32_t hier_fp32;       /* 1: store and run the AMG hierarchies in FP32 (precision form) */
+  uint64_t seed;           /* MIS-2 keys and power-iteration start vectors */
+} nfield_opts;
+
+typedef struct {
+  int32_t restart;         /* GMRES restart length m; 50 */
+  int32_t maxit;           /* total Arnoldi steps allowed; 1000 */
+  int32_t flexible;        /* 1: flexible GMRES (stores Z = M V); required with hier_fp32 */
+  double rtol;             /* stop when ||b - A x||_2 / ||b - A x0||_2 < rtol; 1e-8 */
+} nfield_solve_opts;
+
+typedef struct {
+  int32_t iters, restarts, status;
+  double relres;           /* final true relative residual */
+  double setup_s, solve_s; /* wall seconds of nfield_setup and of this solve */
+  double bytes, gbps;      /* algorithmic HBM bytes of the solve, and bytes / solve_s */
+} nfield_stats;
+
+void nfield_default_opts(nfield_opts *opts);
+void nfield_default_solve_opts(nfield_solve_opts *sopts);
+
+/* Build the preconditioner for the system: upload every block, parse spec,
+ * build the AMG hierarchies (node graph, MIS-2 aggregation, tentative and
+ * smoothed prolongators, Galerkin products, smoothers, coarse LU) on the
+ * device.  hip_stream may be NULL (default stream).  Errors: EINVAL for
+ * malformed CSR, block shapes that disagree with fields[i].ndof, or a bad
+ * spec; ESINGULAR for BGS / AMG on a zero diagonal block or entry, or a
+ * zero coarse pivot; ENOMEM; EHIP. */
+nfield_status nfield_setup(int32_t nfields, const nfield_field *fields,
+                           const nfield_csr *blocks /* nfields*nfields, row-major (i,j) */,
+                           const char *spec, const nfield_opts *opts, void *hip_stream,
+                           nfield_ctx **out);
+
+/* z = P r for nrhs columns (the preconditioner as an operator, Sec. 3.2).
+ * r_dev and z_dev must not overlap. */
+nfield_status nfield_precond_apply(nfield_ctx *ctx, const double *r_dev, double *z_dev,
+                                   int32_t nrhs, void *hip_stream);
+
+/* y = A x for nrhs columns (every nonzero block). */
+nfield_status nfield_matvec(nfield_ctx *ctx, const double *x_dev, double *y_dev, int32_t nrhs,
+                            void *hip_stream);
+
+/* Solve A x = b with right-preconditioned (or flexible) GMRES(m) per column.
+ * x_dev holds the initial guess on entry and the solution on return.  stats
+ * (nrhs entries, may be NULL) receives per-column results.  The call returns
+ * after the solve has finished on the device. */
+nfield_status nfield_gmres_solve(nfield_ctx *ctx, const double *b_dev, double *x_dev,
+                                 int32_t nrhs, const nfield_solve_opts *sopts,
+                                 nfield_stats *stats, void *hip_stream);
+
+size_t nfield_footprint_bytes(const nfield_ctx *ctx);   /* device bytes the context holds */
+int64_t nfield_size(const nfield_ctx *ctx);             /* n = sum of field sizes */
+void nfield_destroy(nfield_ctx *ctx);
+const char *nfield_strerror(nfield_status s);
+const char *nfield_last_error(void);
+
+/* ---- inspection of the AMG hierarchies a context built (build order) ----
+ * Copies to host; for tests and reports.  h indexes the hierarchies, l the
+ * level, f / i / j the field(s) of a (monolithic) hierarchy. */
+int32_t nfield_hier_count(const nfield_ctx *ctx);
+int32_t nfield_hier_nlevels(const nfield_ctx *ctx, int32_t h);
+int32_t nfield_hier_nfields(const nfield_ctx *ctx, int32_t h);
+int32_t nfield_hier_size(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t f);
+double nfield_hier_lambda(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t f);
+/* which: 0 = A_ij, 1 = P_i, 2 = R_i.  Returns nnz, or -1 if absent; the
+ * arrays (host, may be NULL) receive the CSR. */
+int64_t nfield_hier_matrix(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t which, int32_t i,
+                           int32_t j, int64_t *rowptr, int32_t *colind, double *val,
+                           int32_t *nrows, int32_t *ncols);
+/* aggregate number of every node of field f on level l; returns the node count or -1 */
+int32_t nfield_hier_aggregates(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t f,
+                               int32_t *agg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFIELD_H */

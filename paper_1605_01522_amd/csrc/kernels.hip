@@ -1,0 +1,1230 @@
+// gfx950 kernels of the n-field solver: vector updates, CSR SpMV with fused
+// epilogues (residual, Chebyshev step, prolongate-and-add), deterministic
+// FP64 reductions, GMRES block operations, and the AMG setup kernels
+// (node graph, MIS-2, aggregation, tentative prolongator, SpGEMM, transpose,
+// sparse add, dense Gauss-Jordan inverse).
+//
+// Wavefronts are 64 lanes.  Reductions use a fixed grid so that every sum is
+// taken in the same order on every run.
+
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace nf {
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ====================================================================== utils
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over a 256-thread block; result valid in thread 0
+__device__ __forceinline__ double block_sum256(double v, double* ws) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) ws[w] = v;
+  __syncthreads();
+  return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) as a pure function of its
+// input: add the golden gamma, then the two xor-shift-multiply rounds.
+__device__ __forceinline__ uint64_t smix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ==================================================================== vectors
+template <class T>
+__global__ void k_fill(T* x, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+template <class S, class D>
+__global__ void k_cast(const S* x, D* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (D)x[i];
+}
+__global__ void k_axpy(double a, const double* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] += a * x[i];
+}
+template <class T>
+__global__ void k_sub_scaled(const T* dinv, const T* u, T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] -= dinv[i] * u[i];
+}
+template <class T>
+__global__ void k_add_into(const T* d, T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] += d[i];
+}
+__global__ void k_scale_inv_dev(const double* w, double* v, const double* nrm, int64_t n) {
+  const double s = *nrm;
+  const double inv = s != 0.0 ? 1.0 / s : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) v[i] = w[i] * inv;
+}
+template <class T>
+__global__ void k_cheb_first(const T* b, const T* dinv, T inv_theta, T* d, T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    T v = dinv[i] * b[i] * inv_theta;
+    d[i] = v;
+    x[i] = v;
+  }
+}
+// one wave per row of a dense row-major matrix
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ M, int n, const T* __restrict__ b, T* __restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  const double* m = M + (int64_t)row * n;
+  for (int j = lane; j < n; j += 64) s += m[j] * (double)b[j];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = (T)s;
+}
+
+static inline int grid_for(int64_t n, int threads = 256) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <class T> void fill(T* x, T v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+}
+template <class S, class D> void cast_copy(const S* x, D* y, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_cast<S, D>), dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+}
+void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, a, x, y, n);
+}
+template <class T> void sub_scaled(const T* dinv, const T* u, T* x, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sub_scaled<T>, dim3(grid_for(n)), dim3(256), 0, s, dinv, u, x, n);
+}
+template <class T> void add_into(const T* d, T* x, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_add_into<T>, dim3(grid_for(n)), dim3(256), 0, s, d, x, n);
+}
+void scale_inv_dev(const double* w, double* v, const double* nrm_dev, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_scale_inv_dev, dim3(grid_for(n)), dim3(256), 0, s, w, v, nrm_dev, n);
+}
+template <class T> void cheb_first(const T* b, const T* dinv, T inv_theta, T* d, T* x, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(256), 0, s, b, dinv, inv_theta, d, x, n);
+}
+template <class T> void dense_gemv(const double* M, int n, const T* b, T* x, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, x);
+}
+
+template void fill<double>(double*, double, int64_t, hipStream_t);
+template void fill<float>(float*, float, int64_t, hipStream_t);
+template void fill<int>(int*, int, int64_t, hipStream_t);
+template void cast_copy<double, float>(const double*, float*, int64_t, hipStream_t);
+template void cast_copy<float, double>(const float*, double*, int64_t, hipStream_t);
+template void sub_scaled<double>(const double*, const double*, double*, int64_t, hipStream_t);
+template void sub_scaled<float>(const float*, const float*, float*, int64_t, hipStream_t);
+template void add_into<double>(const double*, double*, int64_t, hipStream_t);
+template void add_into<float>(const float*, float*, int64_t, hipStream_t);
+template void cheb_first<double>(const double*, const double*, double, double*, double*, int64_t, hipStream_t);
+template void cheb_first<float>(const float*, const float*, float, float*, float*, int64_t, hipStream_t);
+template void dense_gemv<double>(const double*, int, const double*, double*, hipStream_t);
+template void dense_gemv<float>(const double*, int, const float*, float*, hipStream_t);
+
+// ======================================================================= SpMV
+// G lanes per row (G divides 64, groups aligned inside the wavefront).  The
+// row sum is reduced with xor-shuffles inside the group; lane 0 of the group
+// applies the epilogue.
+template <int G, int MODE, class T>
+__global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ ptr, const int* __restrict__ col,
+                                              const T* __restrict__ val, SpmvArgs<T> a) {
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int row = gid / G, lane = gid & (G - 1);
+  if (row >= nr) return;
+  const int p0 = ptr[row], p1 = ptr[row + 1];
+  const T* __restrict__ x = a.x;
+  T s = 0;
+  for (int p = p0 + lane; p < p1; p += G) s += val[p] * x[col[p]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (lane != 0) return;
+  if (MODE == SPMV_STORE) a.y[row] = s;
+  else if (MODE == SPMV_RESID) a.y[row] = a.b[row] - s;
+  else if (MODE == SPMV_ADD) a.y[row] += s;
+  else if (MODE == SPMV_SUB) a.y[row] -= s;
+  else if (MODE == SPMV_DSCALE) a.y[row] = a.dinv[row] * s;
+  else {  // SPMV_CHEB
+    const T r = a.b[row] - s;
+    T dn = a.c2 * a.dinv[row] * r;
+    if (a.c1 != (T)0) dn += a.c1 * a.d[row];
+    a.d[row] = dn;
+    a.xo[row] = a.x[row] + dn;
+  }
+}
+
+int spmv_group(int nr, int64_t nnz) {
+  if (nr <= 0) return 1;
+  const double avg = (double)nnz / nr;
+  int g = 1;
+  while (g * 2 <= avg && g < 64) g *= 2;
+  return g < 2 ? 2 : g;
+}
+
+template <int MODE, class T>
+static void spmv_mode(int G, const DCsr& A, const SpmvArgs<T>& a, const T* val, hipStream_t s) {
+  const int blocks = cdiv((int64_t)A.nr * G, 256);
+  switch (G) {
+    case 2: hipLaunchKernelGGL((k_spmv<2, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 4: hipLaunchKernelGGL((k_spmv<4, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 8: hipLaunchKernelGGL((k_spmv<8, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 16: hipLaunchKernelGGL((k_spmv<16, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 32: hipLaunchKernelGGL((k_spmv<32, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    default: hipLaunchKernelGGL((k_spmv<64, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+  }
+}
+
+template <class T> static const T* csr_values(const DCsr& A);
+template <> const double* csr_values<double>(const DCsr& A) { return A.val.p; }
+template <> const float* csr_values<float>(const DCsr& A) {
+  if (!A.val32.p && A.nnz > 0) throw NfError(NFIELD_EINVAL, "FP32 values of a matrix were not prepared");
+  return A.val32.p;
+}
+
+template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
+  if (A.nr <= 0) return;
+  const T* val = csr_values<T>(A);
+  const int G = spmv_group(A.nr, A.nnz);
+  switch (mode) {
+    case SPMV_STORE: spmv_mode<SPMV_STORE, T>(G, A, a, val, s); break;
+    case SPMV_RESID: spmv_mode<SPMV_RESID, T>(G, A, a, val, s); break;
+    case SPMV_ADD: spmv_mode<SPMV_ADD, T>(G, A, a, val, s); break;
+    case SPMV_SUB: spmv_mode<SPMV_SUB, T>(G, A, a, val, s); break;
+    case SPMV_CHEB: spmv_mode<SPMV_CHEB, T>(G, A, a, val, s); break;
+    case SPMV_DSCALE: spmv_mode<SPMV_DSCALE, T>(G, A, a, val, s); break;
+  }
+}
+template void spmv<double>(SpmvMode, const DCsr&, const SpmvArgs<double>&, hipStream_t);
+template void spmv<float>(SpmvMode, const DCsr&, const SpmvArgs<float>&, hipStream_t);
+
+// ================================================================= reductions
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                                                     double* __restrict__ partial) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += x[i] * y[i];
+  s = block_sum256(s, ws);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+// grid = ncols blocks; out[k] (+)= sum of partial[k * RED_BLOCKS + 0 .. RED_BLOCKS)
+__global__ __launch_bounds__(256) void k_mreduce(const double* __restrict__ partial, double* __restrict__ out, int accumulate) {
+  __shared__ double ws[4];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[(int64_t)k * RED_BLOCKS + i];
+  s = block_sum256(s, ws);
+  if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
+}
+
+void dot_dev(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(256), 0, s, partial, out, 0);
+}
+
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
+                                              int64_t n, double* __restrict__ partial) {
+  __shared__ double ws[4];
+  double acc[MAXC];
+#pragma unroll
+  for (int k = 0; k < MAXC; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k)
+      if (k < ncols) acc[k] += V[k * ldv + i] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < MAXC; ++k)
+    if (k < ncols) {
+      double r = block_sum256(acc[k], ws);
+      if (threadIdx.x == 0) partial[(int64_t)k * RED_BLOCKS + blockIdx.x] = r;
+    }
+}
+
+// w <- w - V h, then partial dots V^T w (NORM=false) or ||w||^2 (NORM=true)
+template <int MAXC, bool NORM>
+__global__ __launch_bounds__(256) void k_mupdate(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
+                                                 double* __restrict__ w, int64_t n, double* __restrict__ partial) {
+  __shared__ double ws[4];
+  __shared__ double hs[MAXC];
+  for (int k = threadIdx.x; k < MAXC; k += 256) hs[k] = k < ncols ? h[k] : 0.0;
+  __syncthreads();
+  double acc[NORM ? 1 : MAXC];
+#pragma unroll
+  for (int k = 0; k < (NORM ? 1 : MAXC); ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double vk[MAXC];
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k)
+      if (k < ncols) {
+        vk[k] = V[k * ldv + i];
+        wi -= vk[k] * hs[k];
+      }
+    w[i] = wi;
+    if (NORM) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int k = 0; k < MAXC; ++k)
+        if (k < ncols) acc[(NORM ? 0 : k)] += vk[k] * wi;
+    }
+  }
+  if (NORM) {
+    double r = block_sum256(acc[0], ws);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+  } else {
+#pragma unroll
+    for (int k = 0; k < (NORM ? 1 : MAXC); ++k)
+      if (k < ncols) {
+        double r = block_sum256(acc[k], ws);
+        if (threadIdx.x == 0) partial[(int64_t)k * RED_BLOCKS + blockIdx.x] = r;
+      }
+  }
+}
+
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ y,
+                                                  double* __restrict__ u, int64_t n, int accumulate) {
+  __shared__ double ys[MAXC];
+  for (int k = threadIdx.x; k < MAXC; k += 256) ys[k] = k < ncols ? y[k] : 0.0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = accumulate ? u[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k)
+      if (k < ncols) s += V[k * ldv + i] * ys[k];
+    u[i] = s;
+  }
+}
+
+#define NF_MAXC_DISPATCH(ncols, KERNEL_CALL)               \
+  do {                                                     \
+    if ((ncols) <= 8) { constexpr int MC = 8; KERNEL_CALL; } \
+    else if ((ncols) <= 16) { constexpr int MC = 16; KERNEL_CALL; } \
+    else if ((ncols) <= 32) { constexpr int MC = 32; KERNEL_CALL; } \
+    else if ((ncols) <= 64) { constexpr int MC = 64; KERNEL_CALL; } \
+    else throw NfError(NFIELD_EINVAL, "GMRES restart length above 63 is not supported"); \
+  } while (0)
+
+void mdot_partial(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* partial, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mdot<MC>, dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, w, n, partial));
+}
+void mreduce(const double* partial, int ncols, double* out, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_mreduce, dim3(ncols), dim3(256), 0, s, partial, out, accumulate);
+}
+void mupdate_dot(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, false>), dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, h, w, n, partial));
+}
+void mupdate_norm(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, true>), dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, h, w, n, partial));
+}
+void mcombine(const double* V, int64_t ldv, int ncols, const double* y, double* u, int64_t n, int accumulate, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mcombine<MC>, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, ncols, y, u, n, accumulate));
+}
+
+// Givens step of the Arnoldi process, one block: H is (m+1) x m column-major.
+__global__ __launch_bounds__(256) void k_givens(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
+                                                const double* __restrict__ nrm_partial, double* H, double* cs, double* sn,
+                                                double* g, double* hnorm_out, double* res_out) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += nrm_partial[i];
+  s = block_sum256(s, ws);
+  if (threadIdx.x != 0) return;
+  const int ld = m + 1;
+  double* Hj = H + (int64_t)j * ld;
+  for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h2[i];
+  const double hn = sqrt(s);
+  Hj[j + 1] = hn;
+  *hnorm_out = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hj[i], c = Hj[i + 1];
+    Hj[i] = cs[i] * a + sn[i] * c;
+    Hj[i + 1] = -sn[i] * a + cs[i] * c;
+  }
+  const double a = Hj[j], c = Hj[j + 1];
+  const double den = hypot(a, c);
+  cs[j] = den == 0.0 ? 1.0 : a / den;
+  sn[j] = den == 0.0 ? 0.0 : c / den;
+  Hj[j] = den;
+  Hj[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  *res_out = fabs(g[j + 1]);
+}
+__global__ void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int ld = m + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[(int64_t)l * ld + i] * y[l];
+    y[i] = s / H[(int64_t)i * ld + i];
+  }
+}
+void givens_step(int j, int m, const double* h1, const double* h2, const double* nrm_partial, double* H, double* cs,
+                 double* sn, double* g, double* hnorm_out, double* res_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, j, m, h1, h2, nrm_partial, H, cs, sn, g, hnorm_out, res_out);
+}
+void backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, k, m, H, g, y);
+}
+
+// ====================================================================== scan
+// Exclusive scan of int32 counts: each 256-thread block scans 2048 entries
+// (8 per thread); block totals are scanned recursively and added back.
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_BLOCK = 256 * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(256) void k_scan_block(const int* __restrict__ in, int* __restrict__ out, int64_t n,
+                                                    int* __restrict__ block_sums) {
+  __shared__ int sums[256];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+  int v[SCAN_PER_THREAD];
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    t += v[k];
+  }
+  sums[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {   // Hillis-Steele inclusive scan of thread totals
+    int add = threadIdx.x >= off ? sums[threadIdx.x - off] : 0;
+    __syncthreads();
+    sums[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = sums[threadIdx.x] - t;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 255) block_sums[blockIdx.x] = sums[255];
+}
+__global__ void k_scan_add(int* out, int64_t n, const int* __restrict__ scanned_block_sums) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t b = i / SCAN_BLOCK;
+  if (i < n) out[i] += scanned_block_sums[b];
+}
+__global__ void k_set_total(const int* in, int* out, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0 ? out[n - 1] + in[n - 1] : 0);
+}
+
+static void scan_rec(const int* in, int* out, int64_t n, hipStream_t s) {
+  const int nb = cdiv(n, SCAN_BLOCK);
+  DBuf<int> bs(nb + 1);
+  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(256), 0, s, in, out, n, bs.p);
+  if (nb > 1) {
+    DBuf<int> bss(nb + 1);
+    scan_rec(bs.p, bss.p, nb, s);
+    hipLaunchKernelGGL(k_scan_add, dim3(cdiv(n, 256)), dim3(256), 0, s, out, n, bss.p);
+    NF_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
+  } else {
+    NF_HIP(hipStreamSynchronize(s));
+  }
+}
+
+int64_t exclusive_scan(const int* in, int* out, int64_t n, hipStream_t s) {
+  if (n > 0) scan_rec(in, out, n, s);
+  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, in, out, n);
+  int total = 0;
+  NF_HIP(hipMemcpyAsync(&total, out + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(total >= 0, NFIELD_ENOMEM, "index count exceeds 2^31");
+  return total;
+}
+
+// ============================================================== setup basics
+__global__ void k_csr_diag(int nr, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+                           double* d, int* zero_flag) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nr) return;
+  int lo = ptr[i], hi = ptr[i + 1];
+  while (lo < hi) {   // lower_bound of column i
+    int mid = (lo + hi) >> 1;
+    if (col[mid] < i) lo = mid + 1; else hi = mid;
+  }
+  double v = (lo < ptr[i + 1] && col[lo] == i) ? val[lo] : 0.0;
+  d[i] = v;
+  if (v == 0.0) atomicOr(zero_flag, 1);
+}
+void csr_diag(const DCsr& A, double* d, int* zero_flag, hipStream_t s) {
+  if (A.nr > 0) hipLaunchKernelGGL(k_csr_diag, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, d, zero_flag);
+}
+__global__ void k_invert(const double* d, double* dinv, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
+}
+void invert(const double* d, double* dinv, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_invert, dim3(cdiv(n, 256)), dim3(256), 0, s, d, dinv, n);
+}
+__global__ void k_power_start(double* v, int64_t n, uint64_t seed) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= n) return;
+  const uint64_t s0 = smix64(seed);
+  v[u] = 0.5 + (double)(smix64(s0 ^ (uint64_t)(u + 1)) >> 11) * 0x1.0p-53;
+}
+void power_start(double* v, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_power_start, dim3(cdiv(n, 256)), dim3(256), 0, s, v, n, seed);
+}
+
+// ================================================================ node graph
+constexpr int MAXB = 8;
+// node u ~ v (u != v) iff some stored entry couples their dofs; one thread
+// per node merges the b sorted rows of the node by node index.
+template <bool FILL>
+__global__ void k_node_graph(int nnode, int b, const int* __restrict__ ptr, const int* __restrict__ col, int* cnt_or_off,
+                             int* adj) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= nnode) return;
+  int p[MAXB], e[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    p[c] = c < b ? ptr[u * b + c] : 0;
+    e[c] = c < b ? ptr[u * b + c + 1] : 0;
+  }
+  int cnt = 0;
+  const int out = FILL ? cnt_or_off[u] : 0;
+  while (true) {
+    int mn = INT_MAX;
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c)
+      if (p[c] < e[c]) mn = min(mn, col[p[c]] / b);
+    if (mn == INT_MAX) break;
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c)
+      while (p[c] < e[c] && col[p[c]] / b == mn) ++p[c];
+    if (mn != u) {
+      if (FILL) adj[out + cnt] = mn;
+      ++cnt;
+    }
+  }
+  if (!FILL) cnt_or_off[u] = cnt;
+}
+void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nnode_out, hipStream_t s) {
+  NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "block size must be between 1 and 8");
+  NF_CHECK(A.nr == A.nc && A.nr % b == 0, NFIELD_EINVAL, "node graph: size is not a multiple of the block size");
+  const int nn = A.nr / b;
+  *nnode_out = nn;
+  DBuf<int> cnt(nn + 1);
+  gptr.alloc(nn + 1);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
+  const int64_t tot = exclusive_scan(cnt.p, gptr.p, nn, s);
+  gadj.alloc(tot > 0 ? tot : 1);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
+  NF_HIP(hipStreamSynchronize(s));
+}
+
+// ===================================================================== MIS-2
+// Synchronous rounds with the node tuples (key, id), key = splitmix64(seed ^
+// splitmix64(id)).  States: 0 undecided, 1 root, 2 out.
+__device__ __forceinline__ bool tuple_greater(const uint64_t* key, int a, int b) {
+  const uint64_t ka = key[a], kb = key[b];
+  return ka != kb ? ka > kb : a > b;
+}
+__global__ void k_mis_keys(int n, uint64_t seed, uint64_t* key) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < n) key[u] = smix64(seed ^ smix64((uint64_t)u));
+}
+// m1[v] = largest undecided tuple in the closed neighbourhood of v (-1: none)
+__global__ void k_mis_m1(int n, const int* __restrict__ gp, const int* __restrict__ ga, const uint64_t* __restrict__ key,
+                         const int* __restrict__ st, int* __restrict__ m1) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  int best = st[v] == 0 ? v : -1;
+  for (int p = gp[v]; p < gp[v + 1]; ++p) {
+    const int w = ga[p];
+    if (st[w] == 0 && (best < 0 || tuple_greater(key, w, best))) best = w;
+  }
+  m1[v] = best;
+}
+// an undecided u whose tuple is the largest within distance 2 becomes a root
+__global__ void k_mis_root(int n, const int* __restrict__ gp, const int* __restrict__ ga, const uint64_t* __restrict__ key,
+                           int* __restrict__ st, const int* __restrict__ m1) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n || st[u] != 0) return;
+  int best = m1[u];
+  for (int p = gp[u]; p < gp[u + 1]; ++p) {
+    const int c = m1[ga[p]];
+    if (c >= 0 && (best < 0 || tuple_greater(key, c, best))) best = c;
+  }
+  if (best == u) st[u] = 1;
+}
+__global__ void k_mis_r1(int n, const int* __restrict__ gp, const int* __restrict__ ga, const int* __restrict__ st,
+                         int* __restrict__ r1) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  int f = st[v] == 1;
+  for (int p = gp[v]; p < gp[v + 1] && !f; ++p) f = st[ga[p]] == 1;
+  r1[v] = f;
+}
+__global__ void k_mis_out(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* __restrict__ st,
+                          const int* __restrict__ r1, int* und_count) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n || st[u] != 0) return;
+  int f = r1[u];
+  for (int p = gp[u]; p < gp[u + 1] && !f; ++p) f = r1[ga[p]];
+  if (f) st[u] = 2;
+  else atomicAdd(und_count, 1);
+}
+__global__ void k_is_root(int n, const int* st, int* flag) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < n) flag[u] = st[u] == 1;
+}
+// phase 1 + 2: roots take their number; a neighbour of a root joins it
+__global__ void k_agg_phase2(int n, const int* __restrict__ gp, const int* __restrict__ ga, const int* __restrict__ st,
+                             const int* __restrict__ rootid, int* __restrict__ agg, int* __restrict__ phase) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n) return;
+  if (st[u] == 1) { agg[u] = rootid[u]; phase[u] = 1; return; }
+  int a = -1;
+  for (int p = gp[u]; p < gp[u + 1]; ++p)
+    if (st[ga[p]] == 1) { a = rootid[ga[p]]; break; }
+  agg[u] = a;
+  phase[u] = a >= 0 ? 2 : 0;
+}
+// phase 3: join the smallest aggregate among phase-2 neighbours
+__global__ void k_agg_phase3(int n, const int* __restrict__ gp, const int* __restrict__ ga, const int* __restrict__ phase,
+                             int* __restrict__ agg, int* err) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n || phase[u] != 0) return;
+  int best = -1;
+  for (int p = gp[u]; p < gp[u + 1]; ++p) {
+    const int v = ga[p];
+    if (phase[v] == 2 && (best < 0 || agg[v] < best)) best = agg[v];
+  }
+  if (best < 0) atomicOr(err, 1);
+  agg[u] = best < 0 ? 0 : best;
+}
+
+int mis2_aggregate(int n, const int* gp, const int* ga, uint64_t seed, int* agg, hipStream_t s) {
+  if (n == 0) return 0;
+  DBuf<uint64_t> key(n);
+  DBuf<int> st(n), m1(n), cnt(1), flag(n + 1), rootid(n + 1), phase(n), err(1);
+  const int g = cdiv(n, 256);
+  hipLaunchKernelGGL(k_mis_keys, dim3(g), dim3(256), 0, s, n, seed, key.p);
+  fill<int>(st.p, 0, n, s);
+  int und = n, rounds = 0;
+  while (und > 0) {
+    NF_CHECK(++rounds <= n + 1, NFIELD_EINVAL, "MIS-2 did not terminate");
+    const int before = und;
+    hipLaunchKernelGGL(k_mis_m1, dim3(g), dim3(256), 0, s, n, gp, ga, key.p, st.p, m1.p);
+    hipLaunchKernelGGL(k_mis_root, dim3(g), dim3(256), 0, s, n, gp, ga, key.p, st.p, m1.p);
+    hipLaunchKernelGGL(k_mis_r1, dim3(g), dim3(256), 0, s, n, gp, ga, st.p, m1.p /* reused as r1 */);
+    fill<int>(cnt.p, 0, 1, s);
+    hipLaunchKernelGGL(k_mis_out, dim3(g), dim3(256), 0, s, n, gp, ga, st.p, m1.p, cnt.p);
+    NF_HIP(hipMemcpyAsync(&und, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    NF_CHECK(und < before, NFIELD_EINVAL, "MIS-2 round made no progress");
+  }
+  hipLaunchKernelGGL(k_is_root, dim3(g), dim3(256), 0, s, n, st.p, flag.p);
+  const int nagg = (int)exclusive_scan(flag.p, rootid.p, n, s);
+  fill<int>(err.p, 0, 1, s);
+  hipLaunchKernelGGL(k_agg_phase2, dim3(g), dim3(256), 0, s, n, gp, ga, st.p, rootid.p, agg, phase.p);
+  hipLaunchKernelGGL(k_agg_phase3, dim3(g), dim3(256), 0, s, n, gp, ga, phase.p, agg, err.p);
+  int e = 0;
+  NF_HIP(hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(e == 0, NFIELD_EINVAL, "aggregation: node without a phase-2 neighbour");
+  return nagg;
+}
+
+// ======================================================= tentative prolongator
+__global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < n) atomicAdd(&cnt[key[u]], 1);
+}
+__global__ void k_place_by(int n, const int* __restrict__ key, const int* __restrict__ off, int* cursor, int* out) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < n) out[off[key[u]] + atomicAdd(&cursor[key[u]], 1)] = u;
+}
+__global__ void k_ptent_pattern(int ndof, int b, int k, const int* __restrict__ agg, int* ptr, int* col) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r > ndof) return;
+  ptr[r] = r * k;
+  if (r == ndof) return;
+  const int a = agg[r / b];
+  for (int j = 0; j < k; ++j) col[r * k + j] = a * k + j;
+}
+// One thread per aggregate: order its nodes, copy the near-nullspace rows,
+// modified Gram-Schmidt with positive R diagonal, dead columns zeroed.
+__global__ void k_tentative_qr(int nagg, int b, int k, int ndof, const int* __restrict__ aoff, int* members,
+                               const double* __restrict__ B, double* __restrict__ Q, double* __restrict__ Bc,
+                               int* __restrict__ dead) {
+  const int a = blockIdx.x * 64 + threadIdx.x;
+  if (a >= nagg) return;
+  const int m0 = aoff[a], m1 = aoff[a + 1];
+  for (int i = m0 + 1; i < m1; ++i) {   // insertion sort of the member nodes
+    const int v = members[i];
+    int j = i - 1;
+    while (j >= m0 && members[j] > v) { members[j + 1] = members[j]; --j; }
+    members[j + 1] = v;
+  }
+  const int nc = nagg * k;
+  double fro = 0.0;
+  for (int i = m0; i < m1; ++i)
+    for (int c = 0; c < b; ++c) {
+      const int r = members[i] * b + c;
+      for (int j = 0; j < k; ++j) {
+        const double v = B[(int64_t)j * ndof + r];
+        Q[(int64_t)r * k + j] = v;
+        fro += v * v;
+      }
+    }
+  fro = sqrt(fro);
+  double R[MAXB * MAXB];
+  for (int q = 0; q < MAXB * MAXB; ++q) R[q] = 0.0;
+  for (int j = 0; j < k; ++j) {
+    for (int l = 0; l < j; ++l) {
+      double rr = 0.0;
+      for (int i = m0; i < m1; ++i)
+        for (int c = 0; c < b; ++c) {
+          const int64_t r = (int64_t)(members[i] * b + c) * k;
+          rr += Q[r + l] * Q[r + j];
+        }
+      R[l * MAXB + j] = rr;
+      for (int i = m0; i < m1; ++i)
+        for (int c = 0; c < b; ++c) {
+          const int64_t r = (int64_t)(members[i] * b + c) * k;
+          Q[r + j] -= rr * Q[r + l];
+        }
+    }
+    double nr = 0.0;
+    for (int i = m0; i < m1; ++i)
+      for (int c = 0; c < b; ++c) {
+        const int64_t r = (int64_t)(members[i] * b + c) * k;
+        nr += Q[r + j] * Q[r + j];
+      }
+    nr = sqrt(nr);
+    const bool is_dead = nr <= 1e-12 * fro;
+    for (int i = m0; i < m1; ++i)
+      for (int c = 0; c < b; ++c) {
+        const int64_t r = (int64_t)(members[i] * b + c) * k;
+        Q[r + j] = is_dead ? 0.0 : Q[r + j] / nr;
+      }
+    if (is_dead) {
+      for (int l = j; l < k; ++l) R[j * MAXB + l] = 0.0;
+    } else {
+      R[j * MAXB + j] = nr;
+    }
+    dead[a * k + j] = is_dead ? 1 : 0;
+  }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) Bc[(int64_t)j * nc + a * k + i] = R[i * MAXB + j];
+}
+__global__ void k_compact_flags(int n, const int* __restrict__ flag, const int* __restrict__ off, int* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && flag[i]) out[off[i]] = i;
+}
+
+int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B, DCsr& P, DBuf<double>& Bc,
+              DBuf<int>& dead, hipStream_t s) {
+  NF_CHECK(k >= 1 && k <= MAXB, NFIELD_EINVAL, "near-nullspace dimension must be between 1 and 8");
+  const int ndof = nnode * b, nc = nagg * k;
+  NF_CHECK((int64_t)ndof * k < INT_MAX, NFIELD_ENOMEM, "tentative prolongator too large");
+  DBuf<int> cnt(nagg + 1), aoff(nagg + 1), cursor(nagg + 1), members(nnode > 0 ? nnode : 1), dflag(nc + 1), doff(nc + 1);
+  fill<int>(cnt.p, 0, nagg + 1, s);
+  fill<int>(cursor.p, 0, nagg + 1, s);
+  const int g = cdiv(nnode, 256);
+  hipLaunchKernelGGL(k_count_by, dim3(g), dim3(256), 0, s, nnode, agg, cnt.p);
+  exclusive_scan(cnt.p, aoff.p, nagg, s);
+  hipLaunchKernelGGL(k_place_by, dim3(g), dim3(256), 0, s, nnode, agg, aoff.p, cursor.p, members.p);
+  P.nr = ndof;
+  P.nc = nc;
+  P.nnz = (int64_t)ndof * k;
+  P.ptr.alloc(ndof + 1);
+  P.col.alloc(P.nnz);
+  P.val.alloc(P.nnz);
+  Bc.alloc((size_t)k * nc);
+  hipLaunchKernelGGL(k_ptent_pattern, dim3(cdiv(ndof + 1, 256)), dim3(256), 0, s, ndof, b, k, agg, P.ptr.p, P.col.p);
+  hipLaunchKernelGGL(k_tentative_qr, dim3(cdiv(nagg, 64)), dim3(64), 0, s, nagg, b, k, ndof, aoff.p, members.p, B, P.val.p,
+                     Bc.p, dflag.p);
+  const int ndead = (int)exclusive_scan(dflag.p, doff.p, nc, s);
+  dead.alloc(ndead > 0 ? ndead : 1);
+  if (ndead > 0) hipLaunchKernelGGL(k_compact_flags, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, dflag.p, doff.p, dead.p);
+  NF_HIP(hipStreamSynchronize(s));
+  return ndead;
+}
+
+// P <- P_tent + s .* (A P_tent), in place on the product (whose pattern
+// contains that of P_tent because A has its whole diagonal stored)
+__global__ void k_smooth_P(int nr, const int* __restrict__ ptr, const int* __restrict__ col, double* __restrict__ val,
+                           const double* __restrict__ srow, const double* __restrict__ ptv, int b, int k,
+                           const int* __restrict__ agg) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const double sr = srow[r];
+  const int a = agg[r / b];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const int c = col[p];
+    double v = val[p] * sr;
+    if (c / k == a) v = ptv[(int64_t)r * k + (c - a * k)] + v;
+    val[p] = v;
+  }
+}
+void smooth_prolongator(DCsr& AP, const double* srow, const DCsr& Pt, int b, int k, const int* agg, hipStream_t s) {
+  if (AP.nr > 0)
+    hipLaunchKernelGGL(k_smooth_P, dim3(cdiv(AP.nr, 256)), dim3(256), 0, s, AP.nr, AP.ptr.p, AP.col.p, AP.val.p, srow,
+                       Pt.val.p, b, k, agg);
+}
+
+// ===================================================================== SpGEMM
+// C = A B, row by row, one wavefront per row.  Pass 1 counts the distinct
+// columns of each row with an LDS hash set; pass 2 rebuilds the set in a
+// table sized for the row, sorts it (bitonic, LDS) and accumulates
+// a_ik b_kj into the sorted slots in ascending k: the lanes of one step work
+// on distinct columns of row k of B, so every entry is summed in the same
+// order as a serial row-by-row product, without atomics.
+constexpr int SPG_COUNT_CAP = 4096;
+constexpr int EMPTY_KEY = INT_MAX;
+
+__device__ __forceinline__ int hash_slot(int key, int logts) {
+  return (int)(((uint32_t)key * 2654435761u) >> (32 - logts));
+}
+// returns 1 if the key was new, 0 if present, -1 if the table is full
+__device__ __forceinline__ int hash_insert(int* table, int ts, int logts, int key) {
+  int h = logts > 0 ? hash_slot(key, logts) : 0;
+  for (int probe = 0; probe < ts; ++probe) {
+    const int old = atomicCAS(&table[h], EMPTY_KEY, key);
+    if (old == EMPTY_KEY) return 1;
+    if (old == key) return 0;
+    h = (h + 1) & (ts - 1);
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(64) void k_spgemm_count(int nr, const int* __restrict__ Ap, const int* __restrict__ Ac,
+                                                     const int* __restrict__ Bp, const int* __restrict__ Bc, int* __restrict__ cnt,
+                                                     int* overflow) {
+  __shared__ int table[SPG_COUNT_CAP];
+  const int row = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < SPG_COUNT_CAP; i += 64) table[i] = EMPTY_KEY;
+  __syncthreads();
+  constexpr int LOG = 12;
+  int mine = 0, full = 0;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+      const int r = hash_insert(table, SPG_COUNT_CAP, LOG, Bc[q]);
+      if (r > 0) ++mine;
+      if (r < 0) full = 1;
+    }
+  }
+  const int tot = wave_sum_int(mine);
+  const int anyfull = wave_sum_int(full);
+  if (lane == 0) {
+    cnt[row] = tot;
+    if (anyfull) atomicOr(overflow, 1);
+  }
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_spgemm_fill(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
+                                                    const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                    const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                    const double* __restrict__ Bv, const int* __restrict__ Cp,
+                                                    int* __restrict__ Ccol, double* __restrict__ Cval) {
+  __shared__ int keys[CAP];
+  __shared__ double acc[CAP];
+  if ((int)blockIdx.x >= nrows) return;
+  const int row = rows[blockIdx.x], lane = threadIdx.x;
+  const int c0 = Cp[row], cnt = Cp[row + 1] - c0;
+  if (cnt == 0) return;
+  int ts = 1, logts = 0;
+  while (ts < 2 * cnt) { ts <<= 1; ++logts; }
+  if (ts > CAP) { ts = CAP; logts = 0; for (int t = CAP; t > 1; t >>= 1) ++logts; }
+  for (int i = lane; i < ts; i += 64) keys[i] = EMPTY_KEY;
+  __syncthreads();
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) hash_insert(keys, ts, logts, Bc[q]);
+  }
+  __syncthreads();
+  // bitonic sort of the table (ascending; empty slots sort last)
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < ts; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = keys[i], y = keys[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = lane; i < cnt; i += 64) acc[i] = 0.0;
+  __syncthreads();
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    const double a = Av[p];
+    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+      const int key = Bc[q];
+      int lo = 0, hi = cnt;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      acc[lo] += a * Bv[q];
+    }
+    __syncthreads();
+  }
+  for (int i = lane; i < cnt; i += 64) {
+    Ccol[c0 + i] = keys[i];
+    Cval[c0 + i] = acc[i];
+  }
+}
+
+// split rows by their distinct count into the two LDS table sizes
+__global__ void k_bin_rows(int nr, const int* __restrict__ Cp, int small_max, int big_max, int* small, int* nsmall, int* big,
+                           int* nbig, int* overflow) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const int c = Cp[r + 1] - Cp[r];
+  if (c == 0) return;
+  if (c <= small_max) small[atomicAdd(nsmall, 1)] = r;
+  else if (c <= big_max) big[atomicAdd(nbig, 1)] = r;
+  else atomicOr(overflow, 1);
+}
+
+void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
+  NF_CHECK(A.nc == B.nr, NFIELD_EINVAL, "spgemm: inner dimensions differ");
+  C.nr = A.nr;
+  C.nc = B.nc;
+  C.ptr.alloc(A.nr + 1);
+  DBuf<int> cnt(A.nr + 1), flags(4);
+  fill<int>(flags.p, 0, 4, s);
+  if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
+    hipLaunchKernelGGL(k_spgemm_count, dim3(A.nr), dim3(64), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, B.col.p, cnt.p, flags.p);
+  } else {
+    fill<int>(cnt.p, 0, A.nr + 1, s);
+  }
+  int h_flags[4];
+  NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(h_flags[0] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 4096 distinct columns");
+  C.nnz = exclusive_scan(cnt.p, C.ptr.p, A.nr, s);
+  C.col.alloc(C.nnz > 0 ? C.nnz : 1);
+  C.val.alloc(C.nnz > 0 ? C.nnz : 1);
+  if (C.nnz == 0) return;
+  DBuf<int> small(A.nr), big(A.nr);
+  fill<int>(flags.p, 0, 4, s);
+  hipLaunchKernelGGL(k_bin_rows, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, C.ptr.p, 256, 2048, small.p, flags.p, big.p,
+                     flags.p + 1, flags.p + 2);
+  NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(h_flags[2] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 2048 entries");
+  if (h_flags[0] > 0)
+    hipLaunchKernelGGL(k_spgemm_fill<512>, dim3(h_flags[0]), dim3(64), 0, s, small.p, h_flags[0], A.ptr.p, A.col.p, A.val.p,
+                       B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+  if (h_flags[1] > 0)
+    hipLaunchKernelGGL(k_spgemm_fill<4096>, dim3(h_flags[1]), dim3(64), 0, s, big.p, h_flags[1], A.ptr.p, A.col.p, A.val.p,
+                       B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+  NF_HIP(hipStreamSynchronize(s));
+}
+
+// ================================================================= transpose
+__global__ void k_col_count(int64_t nnz, const int* __restrict__ col, int* cnt) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p < nnz) atomicAdd(&cnt[col[p]], 1);
+}
+__global__ void k_transpose_place(int nr, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+                                  const int* __restrict__ tptr, int* cursor, int* tcol, double* tval) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const int c = col[p];
+    const int q = tptr[c] + atomicAdd(&cursor[c], 1);
+    tcol[q] = r;
+    tval[q] = val[p];
+  }
+}
+// sort each row of (col, val) pairs by column: one wavefront per row,
+// bitonic sort in LDS (rows up to 4096 entries)
+__global__ __launch_bounds__(64) void k_sort_rows(int nr, const int* __restrict__ ptr, int* col, double* val, int* overflow) {
+  __shared__ int ks[4096];
+  __shared__ double vs[4096];
+  const int row = blockIdx.x, lane = threadIdx.x;
+  const int p0 = ptr[row], len = ptr[row + 1] - p0;
+  if (len <= 1) return;
+  if (len > 4096) { if (lane == 0) atomicOr(overflow, 1); return; }
+  int ts = 1;
+  while (ts < len) ts <<= 1;
+  for (int i = lane; i < ts; i += 64) {
+    ks[i] = i < len ? col[p0 + i] : EMPTY_KEY;
+    vs[i] = i < len ? val[p0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < ts; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = ks[i], y = ks[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) {
+            ks[i] = y;
+            ks[ixj] = x;
+            const double t = vs[i];
+            vs[i] = vs[ixj];
+            vs[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = lane; i < len; i += 64) {
+    col[p0 + i] = ks[i];
+    val[p0 + i] = vs[i];
+  }
+}
+void transpose(const DCsr& A, DCsr& T, hipStream_t s) {
+  T.nr = A.nc;
+  T.nc = A.nr;
+  DBuf<int> cnt(A.nc + 1), cursor(A.nc + 1), flag(1);
+  fill<int>(cnt.p, 0, A.nc + 1, s);
+  fill<int>(cursor.p, 0, A.nc + 1, s);
+  fill<int>(flag.p, 0, 1, s);
+  if (A.nnz > 0) hipLaunchKernelGGL(k_col_count, dim3(cdiv(A.nnz, 256)), dim3(256), 0, s, A.nnz, A.col.p, cnt.p);
+  T.ptr.alloc(A.nc + 1);
+  T.nnz = exclusive_scan(cnt.p, T.ptr.p, A.nc, s);
+  T.col.alloc(T.nnz > 0 ? T.nnz : 1);
+  T.val.alloc(T.nnz > 0 ? T.nnz : 1);
+  if (A.nr > 0)
+    hipLaunchKernelGGL(k_transpose_place, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, T.ptr.p,
+                       cursor.p, T.col.p, T.val.p);
+  if (T.nr > 0) hipLaunchKernelGGL(k_sort_rows, dim3(T.nr), dim3(64), 0, s, T.nr, T.ptr.p, T.col.p, T.val.p, flag.p);
+  int f = 0;
+  NF_HIP(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(f == 0, NFIELD_ENOMEM, "transpose: a column has more than 4096 entries");
+}
+
+// ================================================================ sparse add
+template <bool FILL>
+__global__ void k_csr_add(int nr, double alpha, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+                          double beta, const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
+                          int* cnt_or_ptr, int* cc, double* cv) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  int p = ap ? ap[r] : 0, pe = ap ? ap[r + 1] : 0, q = bp ? bp[r] : 0, qe = bp ? bp[r + 1] : 0;
+  int o = FILL ? cnt_or_ptr[r] : 0, n = 0;
+  while (p < pe || q < qe) {
+    const int ca = p < pe ? ac[p] : INT_MAX, cb = q < qe ? bc[q] : INT_MAX;
+    int c;
+    double v;
+    if (ca == cb) { c = ca; v = alpha * av[p] + beta * bv[q]; ++p; ++q; }
+    else if (ca < cb) { c = ca; v = alpha * av[p]; ++p; }
+    else { c = cb; v = beta * bv[q]; ++q; }
+    if (FILL) { cc[o + n] = c; cv[o + n] = v; }
+    ++n;
+  }
+  if (!FILL) cnt_or_ptr[r] = n;
+}
+void csr_add(double alpha, const DCsr& A, double beta, const DCsr& B, DCsr& C, hipStream_t s) {
+  const bool ha = A.nnz > 0, hb = B.nnz > 0;
+  const int nr = ha ? A.nr : B.nr;
+  C.nr = nr;
+  C.nc = ha ? A.nc : B.nc;
+  DBuf<int> cnt(nr + 1);
+  C.ptr.alloc(nr + 1);
+  const int g = cdiv(nr, 256);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_csr_add<false>, dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p, beta,
+                       hb ? B.ptr.p : nullptr, B.col.p, B.val.p, cnt.p, nullptr, nullptr);
+  C.nnz = exclusive_scan(cnt.p, C.ptr.p, nr, s);
+  C.col.alloc(C.nnz > 0 ? C.nnz : 1);
+  C.val.alloc(C.nnz > 0 ? C.nnz : 1);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_csr_add<true>, dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p, beta,
+                       hb ? B.ptr.p : nullptr, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+  NF_HIP(hipStreamSynchronize(s));
+}
+void csr_copy(const DCsr& A, DCsr& C, hipStream_t s) {
+  C.nr = A.nr;
+  C.nc = A.nc;
+  C.nnz = A.nnz;
+  C.ptr.alloc(A.nr + 1);
+  C.col.alloc(A.nnz > 0 ? A.nnz : 1);
+  C.val.alloc(A.nnz > 0 ? A.nnz : 1);
+  NF_HIP(hipMemcpyAsync(C.ptr.p, A.ptr.p, sizeof(int) * (A.nr + 1), hipMemcpyDeviceToDevice, s));
+  if (A.nnz > 0) {
+    NF_HIP(hipMemcpyAsync(C.col.p, A.col.p, sizeof(int) * A.nnz, hipMemcpyDeviceToDevice, s));
+    NF_HIP(hipMemcpyAsync(C.val.p, A.val.p, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
+  }
+}
+__global__ void k_scale_rows(int nr, const int* __restrict__ ptr, double* val, const double* __restrict__ srow) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const double sr = srow[r];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) val[p] *= sr;
+}
+void scale_rows(DCsr& A, const double* s_rows, hipStream_t s) {
+  if (A.nr > 0) hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.val.p, s_rows);
+}
+__global__ void k_set_diag_one(const int* rows, int n, const int* __restrict__ ptr, const int* __restrict__ col, double* val) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int r = rows[t];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p)
+    if (col[p] == r) val[p] = 1.0;
+}
+void set_diag_one(DCsr& A, const int* rows, int nrows, hipStream_t s) {
+  if (nrows > 0) hipLaunchKernelGGL(k_set_diag_one, dim3(cdiv(nrows, 256)), dim3(256), 0, s, rows, nrows, A.ptr.p, A.col.p, A.val.p);
+}
+__global__ void k_identity(int n, int* ptr, int* col, double* val) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i > n) return;
+  ptr[i] = i;
+  if (i < n) { col[i] = i; val[i] = 1.0; }
+}
+void identity(int n, DCsr& I, hipStream_t s) {
+  I.nr = I.nc = n;
+  I.nnz = n;
+  I.ptr.alloc(n + 1);
+  I.col.alloc(n > 0 ? n : 1);
+  I.val.alloc(n > 0 ? n : 1);
+  hipLaunchKernelGGL(k_identity, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, n, I.ptr.p, I.col.p, I.val.p);
+}
+void make_fp32(DCsr& A, hipStream_t s) {
+  A.val32.alloc(A.nnz > 0 ? A.nnz : 1);
+  cast_copy<double, float>(A.val.p, A.val32.p, A.nnz, s);
+}
+
+// ===================================================================== dense
+__global__ void k_csr_to_dense(int nr, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+                               double* M, int64_t ld, int r0, int c0) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) M[(int64_t)(r0 + r) * ld + c0 + col[p]] += val[p];
+}
+void csr_to_dense(const DCsr& A, double* M, int64_t ld, int r0, int c0, hipStream_t s) {
+  if (A.nr > 0 && A.nnz > 0)
+    hipLaunchKernelGGL(k_csr_to_dense, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, M, ld, r0, c0);
+}
+
+// Gauss-Jordan on the augmented matrix W = [M | I] (n x 2n, row-major) with
+// partial pivoting (first row of largest magnitude); one workgroup.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(double* W, int n, int* singular) {
+  extern __shared__ double fac[];            // n multipliers
+  __shared__ double bv[1024];
+  __shared__ int bi[1024];
+  __shared__ double pivval;
+  const int t = threadIdx.x, nt = blockDim.x, w = 2 * n;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bidx = n;
+    for (int i = k + t; i < n; i += nt) {
+      const double v = fabs(W[(int64_t)i * w + k]);
+      if (v > best) { best = v; bidx = i; }
+    }
+    bv[t] = best;
+    bi[t] = bidx;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        const double a = bv[t], b = bv[t + off];
+        const int ia = bi[t], ib = bi[t + off];
+        if (b > a || (b == a && ib < ia)) { bv[t] = b; bi[t] = ib; }
+      }
+      __syncthreads();
+    }
+    const int p = bi[0];
+    if (bv[0] <= 0.0) {
+      if (t == 0) *singular = 1;
+      return;
+    }
+    if (p != k)
+      for (int j = t; j < w; j += nt) {
+        const double a = W[(int64_t)k * w + j];
+        W[(int64_t)k * w + j] = W[(int64_t)p * w + j];
+        W[(int64_t)p * w + j] = a;
+      }
+    __syncthreads();
+    if (t == 0) pivval = W[(int64_t)k * w + k];
+    __syncthreads();
+    const double inv = 1.0 / pivval;
+    for (int j = t; j < w; j += nt) W[(int64_t)k * w + j] *= inv;
+    for (int i = t; i < n; i += nt) fac[i] = i == k ? 0.0 : W[(int64_t)i * w + k];
+    __syncthreads();
+    for (int64_t e = t; e < (int64_t)n * w; e += nt) {
+      const int i = (int)(e / w), j = (int)(e % w);
+      if (i != k) W[e] -= fac[i] * W[(int64_t)k * w + j];
+    }
+    __syncthreads();
+  }
+}
+__global__ void k_augment(const double* M, double* W, int n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * 2 * n) return;
+  const int i = (int)(e / (2 * n)), j = (int)(e % (2 * n));
+  W[e] = j < n ? M[(int64_t)i * n + j] : (j - n == i ? 1.0 : 0.0);
+}
+__global__ void k_extract_inverse(const double* W, double* M, int n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  M[e] = W[(int64_t)i * 2 * n + n + j];
+}
+int dense_inverse(double* M, int n, hipStream_t s) {
+  if (n == 0) return 0;
+  NF_CHECK(n <= 6000, NFIELD_ENOMEM, "dense coarse solve larger than 6000 unknowns");
+  DBuf<double> W((size_t)n * 2 * n);
+  DBuf<int> sing(1);
+  fill<int>(sing.p, 0, 1, s);
+  hipLaunchKernelGGL(k_augment, dim3(cdiv((int64_t)n * 2 * n, 256)), dim3(256), 0, s, M, W.p, n);
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), n * sizeof(double), s, W.p, n, sing.p);
+  NF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_extract_inverse, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, W.p, M, n);
+  int h = 0;
+  NF_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  return h ? -1 : 0;
+}
+
+// ===================================================================== SIMPLE
+__global__ void k_row_accumulate(int nr, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+                                 int mode, int is_diag, double* acc) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  double s = 0.0;
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    if (mode == 0) s += fabs(val[p]);
+    else if (mode == 1) s += val[p];
+    else if (is_diag && col[p] == r) s += val[p];
+  }
+  acc[r] += s;
+}
+void row_accumulate(const DCsr& A, int mode, int is_diag, double* acc, hipStream_t s) {
+  if (A.nr > 0) hipLaunchKernelGGL(k_row_accumulate, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, mode, is_diag, acc);
+}
+__global__ void k_finish_simplec(double* acc, int64_t n, int mode, int* zero_flag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = mode == 1 ? fabs(acc[i]) : acc[i];
+  if (v == 0.0) atomicOr(zero_flag, 1);
+  acc[i] = v != 0.0 ? 1.0 / v : 0.0;
+}
+void finish_simplec(double* acc, int64_t n, int mode, int* zero_flag, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_finish_simplec, dim3(cdiv(n, 256)), dim3(256), 0, s, acc, n, mode, zero_flag);
+}
+
+}  // namespace nf

@@ -1,0 +1,1034 @@
+// Preconditioner tree (BGS, SIMPLE, monolithic AMG, dense LU), restarted
+// right-preconditioned / flexible GMRES, and the C ABI of nfield.h.
+//
+// Every numerical step runs in the kernels of kernels.hip and amg.hip; the
+// host parses the specification, sequences launches on the caller's stream
+// and reads back one residual estimate per Arnoldi step.
+
+#include <algorithm>
+#include <cctype>
+#include <chrono>
+#include <functional>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "amg.hpp"
+
+namespace nf {
+
+thread_local size_t* g_acct = nullptr;
+static thread_local std::string g_err;
+
+// ================================================================ helpers
+// r_i = b_i - sum_j A_ij x_j over fields [f0, f1) of A (vectors re-based at f0)
+template <class T>
+static void block_resid(const BlockMat& A, int f0, int f1, const T* b, const T* x, T* r, hipStream_t s) {
+  std::vector<int> o = A.offsets();
+  for (int i = f0; i < f1; ++i) {
+    bool first = true;
+    for (int j = f0; j < f1; ++j) {
+      const DCsr* B = A.at(i, j);
+      if (!B) continue;
+      SpmvArgs<T> a;
+      a.x = x + (o[j] - o[f0]);
+      a.y = r + (o[i] - o[f0]);
+      a.b = b + (o[i] - o[f0]);
+      spmv<T>(first ? SPMV_RESID : SPMV_SUB, *B, a, s);
+      first = false;
+    }
+    if (first && A.size[i] > 0)
+      NF_HIP(hipMemcpyAsync(r + (o[i] - o[f0]), b + (o[i] - o[f0]), sizeof(T) * A.size[i], hipMemcpyDeviceToDevice, s));
+  }
+}
+
+static void prepare_fp32(BlockMat& A, hipStream_t s) {
+  for (auto& b : A.blk)
+    if (b && !b->val32.p) make_fp32(*b, s);
+}
+
+// ================================================================ solvers
+template <class T>
+struct Solver {
+  int n = 0;
+  virtual ~Solver() {}
+  virtual void apply(const T* r, T* z, hipStream_t s) = 0;   // z = M^-1 r
+};
+
+// Chebyshev smoother on D^-1 A over [lambda/ratio, boost*lambda]: three-term
+// recurrence (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+// Algorithm 12.1).  Each step after the first is one fused kernel: residual,
+// direction update and iterate update.
+template <class T>
+struct ChebD {
+  const DCsr* A = nullptr;
+  DBuf<T> dinv, d, xt;
+  double theta = 0, delta = 0, sigma = 0;
+  int degree = 2, n = 0;
+  void setup(const DCsr* A_, const double* dinv64, double lam, const Opts& o, hipStream_t s) {
+    A = A_;
+    n = A->nr;
+    dinv.alloc(n);
+    d.alloc(n);
+    xt.alloc(n);
+    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(dinv.p, dinv64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
+    const double hi = o.cheb_boost * lam, lo = lam / o.cheb_ratio;
+    theta = 0.5 * (hi + lo);
+    delta = 0.5 * (hi - lo);
+    sigma = theta / delta;
+    degree = o.cheb_degree;
+  }
+  void apply(const T* b, T* x, bool zero_guess, hipStream_t s) {
+    const T* src;
+    int k0;
+    if (zero_guess) {
+      T* dst = (degree % 2 == 1) ? x : xt.p;
+      cheb_first<T>(b, dinv.p, (T)(1.0 / theta), d.p, dst, n, s);
+      src = dst;
+      k0 = 1;
+    } else {
+      src = x;
+      k0 = 0;
+    }
+    double rho = 1.0 / sigma;
+    for (int k = k0; k < degree; ++k) {
+      T* dst = (src == x) ? xt.p : x;
+      SpmvArgs<T> a;
+      a.x = src;
+      a.b = b;
+      a.dinv = dinv.p;
+      a.d = d.p;
+      a.xo = dst;
+      if (k == 0) {
+        a.c1 = 0;
+        a.c2 = (T)(1.0 / theta);
+      } else {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        a.c1 = (T)(rn * rho);
+        a.c2 = (T)(2.0 * rn / delta);
+        rho = rn;
+      }
+      spmv<T>(SPMV_CHEB, *A, a, s);
+      src = dst;
+    }
+    if (src != x) NF_HIP(hipMemcpyAsync(x, src, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+  }
+};
+
+// One BGS sweep over fields [0, N) of a block matrix with per-field inner
+// solves: dd_i = S_i(res_i - sum_{j done} A_ij dd_j).
+template <class T, class Inner>
+static void bgs_sweep(const BlockMat& A, int f0, int f1, int order, const T* res, T* dd, T* t, Inner inner, hipStream_t s) {
+  std::vector<int> o = A.offsets();
+  std::vector<int> seq;
+  for (int i = f0; i < f1; ++i) seq.push_back(i);
+  if (order == 1) std::reverse(seq.begin(), seq.end());
+  std::vector<char> done(A.N, 0);
+  for (int i : seq) {
+    const int oi = o[i] - o[f0];
+    bool first = true;
+    for (int j = f0; j < f1; ++j) {
+      if (j == i || !done[j] || !A.at(i, j)) continue;
+      SpmvArgs<T> a;
+      a.x = dd + (o[j] - o[f0]);
+      a.y = t;
+      a.b = res + oi;
+      spmv<T>(first ? SPMV_RESID : SPMV_SUB, *A.at(i, j), a, s);
+      first = false;
+    }
+    inner(i, first ? res + oi : (const T*)t, dd + oi);
+    done[i] = 1;
+  }
+}
+
+// Level smoother of a (monolithic) hierarchy: one BGS sweep over the level's
+// blocks with each field's Chebyshev smoother in place of the block solve
+// (a single field: the Chebyshev smoother itself).
+template <class T>
+struct LevelSmootherD {
+  const BlockMat* A = nullptr;
+  int order = 1;
+  std::vector<std::unique_ptr<ChebD<T>>> cheb;
+  DBuf<T> r, d, t;
+  void smooth(const T* b, T* x, bool zero_guess, hipStream_t s) {
+    const int N = A->N;
+    if (N == 1) {
+      cheb[0]->apply(b, x, zero_guess, s);
+      return;
+    }
+    const T* res = b;
+    if (!zero_guess) {
+      block_resid<T>(*A, 0, N, b, x, r.p, s);
+      res = r.p;
+    }
+    T* dd = zero_guess ? x : d.p;
+    const int ord = order == 2 ? (zero_guess ? 0 : 1) : order;
+    bgs_sweep<T>(*A, 0, N, ord, res, dd, t.p,
+                 [&](int i, const T* rhs, T* out) { cheb[i]->apply(rhs, out, true, s); }, s);
+    if (!zero_guess) add_into<T>(d.p, x, A->total(), s);
+  }
+};
+
+template <class T>
+struct AmgSolverD : Solver<T> {
+  Hierarchy* H = nullptr;
+  std::vector<LevelSmootherD<T>> sm;
+  std::vector<DBuf<T>> res, bl, xl;   // per level: residual; right-hand side and iterate (levels > 0)
+  void vcycle(int l, const T* b, T* x, hipStream_t s) {
+    const Level& L = H->lev[l];
+    if (l == (int)H->lev.size() - 1) {
+      dense_gemv<T>(H->coarse_inv.p, H->ncoarse, b, x, s);
+      return;
+    }
+    sm[l].smooth(b, x, true, s);
+    block_resid<T>(L.A, 0, L.A.N, b, x, res[l].p, s);
+    const Level& C = H->lev[l + 1];
+    std::vector<int> o = L.A.offsets(), oc = C.A.offsets();
+    for (int i = 0; i < L.A.N; ++i) {
+      SpmvArgs<T> a;
+      a.x = res[l].p + o[i];
+      a.y = bl[l + 1].p + oc[i];
+      spmv<T>(SPMV_STORE, *L.R[i], a, s);
+    }
+    vcycle(l + 1, bl[l + 1].p, xl[l + 1].p, s);
+    for (int i = 0; i < L.A.N; ++i) {
+      SpmvArgs<T> a;
+      a.x = xl[l + 1].p + oc[i];
+      a.y = x + o[i];
+      spmv<T>(SPMV_ADD, *L.P[i], a, s);
+    }
+    sm[l].smooth(b, x, false, s);
+  }
+  void apply(const T* r, T* z, hipStream_t s) override { vcycle(0, r, z, s); }
+};
+
+template <class T>
+struct LuSolverD : Solver<T> {
+  DBuf<double> inv;
+  int nn = 0;
+  void apply(const T* r, T* z, hipStream_t s) override { dense_gemv<T>(inv.p, nn, r, z, s); }
+};
+
+template <class T>
+struct BgsSolverD : Solver<T> {
+  const BlockMat* A = nullptr;
+  int f0 = 0, f1 = 0, sweeps = 1, order = 1;
+  std::vector<std::unique_ptr<Solver<T>>> child;
+  DBuf<T> res, d, t;
+  void apply(const T* r, T* z, hipStream_t s) override {
+    for (int sw = 0; sw < sweeps; ++sw) {
+      const T* rr = r;
+      if (sw > 0) {
+        block_resid<T>(*A, f0, f1, r, z, res.p, s);
+        rr = res.p;
+      }
+      T* dd = sw == 0 ? z : d.p;
+      const int ord = order == 2 ? (sw % 2) : order;
+      bgs_sweep<T>(*A, f0, f1, ord, rr, dd, t.p,
+                   [&](int i, const T* rhs, T* out) { child[i - f0]->apply(rhs, out, s); }, s);
+      if (sw > 0) add_into<T>(d.p, z, this->n, s);
+    }
+  }
+};
+
+// SIMPLE over fields [f0, f1) with predictor group [f0, g) and Schur field g
+// (matrix form of M_SIMPLE, Sec. 4.2).
+template <class T>
+struct SimpleSolverD : Solver<T> {
+  const BlockMat* A = nullptr;
+  int f0 = 0, f1 = 0, g = 0, sweeps = 1;
+  std::unique_ptr<Solver<T>> pred, schur;
+  DBuf<T> dtinv, res, d, t, u;
+  void apply(const T* r, T* z, hipStream_t s) override {
+    std::vector<int> o = A->offsets();
+    const int n1 = o[g] - o[f0];
+    for (int sw = 0; sw < sweeps; ++sw) {
+      const T* rr = r;
+      if (sw > 0) {
+        block_resid<T>(*A, f0, f1, r, z, res.p, s);
+        rr = res.p;
+      }
+      T* dd = sw == 0 ? z : d.p;
+      pred->apply(rr, dd, s);
+      bool first = true;
+      for (int j = f0; j < g; ++j) {
+        if (!A->at(g, j)) continue;
+        SpmvArgs<T> a;
+        a.x = dd + (o[j] - o[f0]);
+        a.y = t.p;
+        a.b = rr + n1;
+        spmv<T>(first ? SPMV_RESID : SPMV_SUB, *A->at(g, j), a, s);
+        first = false;
+      }
+      schur->apply(first ? rr + n1 : (const T*)t.p, dd + n1, s);
+      for (int j = f0; j < g; ++j) {
+        if (!A->at(j, g)) continue;
+        const int oj = o[j] - o[f0];
+        SpmvArgs<T> a;
+        a.x = dd + n1;
+        a.y = u.p;
+        spmv<T>(SPMV_STORE, *A->at(j, g), a, s);
+        sub_scaled<T>(dtinv.p + oj, u.p, dd + oj, A->size[j], s);
+      }
+      if (sw > 0) add_into<T>(d.p, z, this->n, s);
+    }
+  }
+};
+
+// ================================================================== spec
+struct Spec {
+  std::string name;
+  int sweeps = -1, order = -1;
+  std::vector<Spec> kids;
+};
+
+static Spec parse_spec(const std::string& str) {
+  size_t i = 0;
+  auto ws = [&]() { while (i < str.size() && str[i] == ' ') ++i; };
+  std::function<Spec()> node = [&]() -> Spec {
+    ws();
+    Spec sp;
+    while (i < str.size() && isalpha((unsigned char)str[i])) sp.name += (char)toupper(str[i++]);
+    NF_CHECK(!sp.name.empty(), NFIELD_EINVAL, "spec: method name expected in '" + str + "'");
+    ws();
+    if (i < str.size() && str[i] == '[') {
+      ++i;
+      while (i < str.size() && str[i] != ']') {
+        ws();
+        std::string k, v;
+        while (i < str.size() && (isalpha((unsigned char)str[i]) || str[i] == '_')) k += (char)tolower(str[i++]);
+        ws();
+        NF_CHECK(i < str.size() && str[i] == '=', NFIELD_EINVAL, "spec: '=' expected");
+        ++i;
+        ws();
+        while (i < str.size() && isalnum((unsigned char)str[i])) v += (char)tolower(str[i++]);
+        ws();
+        if (k == "sweeps") {
+          sp.sweeps = atoi(v.c_str());
+          NF_CHECK(sp.sweeps >= 1, NFIELD_EINVAL, "spec: sweeps must be >= 1");
+        } else if (k == "order") {
+          sp.order = v == "fwd" ? 0 : v == "bwd" ? 1 : v == "sym" ? 2 : -9;
+          NF_CHECK(sp.order >= 0, NFIELD_EINVAL, "spec: order must be fwd, bwd or sym");
+        } else {
+          throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
+        }
+        if (i < str.size() && str[i] == ',') ++i;
+      }
+      NF_CHECK(i < str.size() && str[i] == ']', NFIELD_EINVAL, "spec: ']' expected");
+      ++i;
+      ws();
+    }
+    if (i < str.size() && str[i] == '(') {
+      ++i;
+      sp.kids.push_back(node());
+      ws();
+      while (i < str.size() && str[i] == ';') {
+        ++i;
+        sp.kids.push_back(node());
+        ws();
+      }
+      NF_CHECK(i < str.size() && str[i] == ')', NFIELD_EINVAL, "spec: ')' expected");
+      ++i;
+    }
+    ws();
+    return sp;
+  };
+  Spec sp = node();
+  NF_CHECK(i == str.size(), NFIELD_EINVAL, "spec: trailing characters in '" + str + "'");
+  return sp;
+}
+
+// method names and arities, checked before any device work
+static void check_spec(const Spec& sp) {
+  const size_t k = sp.kids.size();
+  if (sp.name == "LU") NF_CHECK(k == 0, NFIELD_EINVAL, "spec: LU takes no argument");
+  else if (sp.name == "AMG") {
+    NF_CHECK(k <= 1, NFIELD_EINVAL, "spec: AMG takes at most one level smoother");
+    if (k == 1) {
+      NF_CHECK(sp.kids[0].name == "BGS" || sp.kids[0].name == "SIMPLE", NFIELD_EINVAL,
+               "spec: AMG level smoother must be BGS or SIMPLE");
+      NF_CHECK(sp.kids[0].kids.empty(), NFIELD_EINVAL, "spec: a level smoother takes no inner solver");
+    }
+    return;
+  } else if (sp.name == "BGS") NF_CHECK(k == 1, NFIELD_EINVAL, "spec: BGS takes one inner solver");
+  else if (sp.name == "SIMPLE") NF_CHECK(k == 1 || k == 2, NFIELD_EINVAL, "spec: SIMPLE(pred[;schur])");
+  else throw NfError(NFIELD_EINVAL, "spec: unknown method " + sp.name);
+  for (const Spec& c : sp.kids) check_spec(c);
+}
+
+}  // namespace nf
+
+// ============================================================== context
+struct nfield_ctx {
+  int N = 0;
+  std::vector<nf::FieldDev> F;
+  nf::BlockMat A;
+  nf::DCsr Aglob;   // all blocks merged into one CSR (GMRES operator)
+  nf::Opts o;
+  std::vector<std::unique_ptr<nf::Hierarchy>> hiers;
+  std::vector<std::unique_ptr<nf::BlockMat>> owned;
+  std::unique_ptr<nf::Solver<double>> root64;
+  std::unique_ptr<nf::Solver<float>> root32;
+  nf::DBuf<float> r32, z32;
+  size_t bytes = 0;
+  double setup_s = 0.0;
+  // GMRES workspace
+  int ws_m = 0;
+  nf::DBuf<double> V, Z, w, z, r, u, H, cs, sn, g, y, h1, h2, partial, scal;
+  double* pinned = nullptr;
+  ~nfield_ctx() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+namespace nf {
+
+template <class T>
+static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const BlockMat& A, const std::vector<FieldDev>& F,
+                                        int f0, int f1, hipStream_t s);
+
+template <class T>
+static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, const std::vector<FieldDev>& F, int f0, int f1,
+                                            const Spec* smoother, hipStream_t s) {
+  BlockMat sub = A.sub(f0, f1);
+  std::vector<FieldDev> Fs(F.begin() + f0, F.begin() + f1);
+  NF_CHECK(!smoother || smoother->name == "BGS", NFIELD_EINVAL, "spec: only BGS level smoothers are available");
+  for (int i = 0; i < sub.N; ++i) NF_CHECK(sub.at(i, i) != nullptr, NFIELD_ESINGULAR, "AMG: zero diagonal block");
+  auto H = std::make_unique<Hierarchy>();
+  build_hierarchy(*H, sub, Fs, C.o, s);
+  auto S = std::make_unique<AmgSolverD<T>>();
+  S->H = H.get();
+  S->n = sub.total();
+  const int nl = (int)H->lev.size();
+  if (sizeof(T) == sizeof(float))
+    for (int l = 0; l < nl; ++l) {
+      prepare_fp32(H->lev[l].A, s);
+      for (auto& p : H->lev[l].P) if (p) make_fp32(*p, s);
+      for (auto& r : H->lev[l].R) if (r) make_fp32(*r, s);
+    }
+  S->sm.resize(nl > 0 ? nl - 1 : 0);
+  S->res.resize(nl);
+  S->bl.resize(nl);
+  S->xl.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    const Level& L = H->lev[l];
+    const int n = L.A.total();
+    if (l > 0) {
+      S->bl[l].alloc(n);
+      S->xl[l].alloc(n);
+    }
+    if (l + 1 == nl) break;
+    S->res[l].alloc(n);
+    LevelSmootherD<T>& M = S->sm[l];
+    M.A = &L.A;
+    M.order = smoother && smoother->order >= 0 ? smoother->order : C.o.order;
+    for (int i = 0; i < sub.N; ++i) {
+      NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
+      auto ch = std::make_unique<ChebD<T>>();
+      ch->setup(L.A.at(i, i), L.dinv[i]->p, L.lambda[i], C.o, s);
+      M.cheb.push_back(std::move(ch));
+    }
+    if (sub.N > 1) {
+      M.r.alloc(n);
+      M.d.alloc(n);
+      int mx = 0;
+      for (int v : L.A.size) mx = std::max(mx, v);
+      M.t.alloc(mx);
+    }
+  }
+  C.hiers.push_back(std::move(H));
+  return S;
+}
+
+template <class T>
+static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const BlockMat& A, const std::vector<FieldDev>& F,
+                                        int f0, int f1, hipStream_t s) {
+  const int nf_ = f1 - f0;
+  std::vector<int> o = A.offsets();
+  const int n = o[f1] - o[f0];
+  if (sp.name == "LU") {
+    NF_CHECK(sp.kids.empty(), NFIELD_EINVAL, "spec: LU takes no argument");
+    auto S = std::make_unique<LuSolverD<T>>();
+    BlockMat sub = A.sub(f0, f1);
+    dense_block_inverse(sub, S->inv, &S->nn, s);
+    S->n = n;
+    return S;
+  }
+  if (sp.name == "AMG") {
+    if (sp.kids.empty()) {
+      NF_CHECK(nf_ == 1, NFIELD_EINVAL, "spec: plain AMG needs a single field; use AMG(BGS)");
+      return build_amg<T>(C, A, F, f0, f1, nullptr, s);
+    }
+    NF_CHECK(sp.kids.size() == 1, NFIELD_EINVAL, "spec: AMG takes one level smoother");
+    return build_amg<T>(C, A, F, f0, f1, &sp.kids[0], s);
+  }
+  if (sp.name == "BGS") {
+    NF_CHECK(sp.kids.size() == 1, NFIELD_EINVAL, "spec: BGS takes one inner solver");
+    auto S = std::make_unique<BgsSolverD<T>>();
+    S->A = &A;
+    S->f0 = f0;
+    S->f1 = f1;
+    S->sweeps = sp.sweeps > 0 ? sp.sweeps : C.o.sweeps;
+    S->order = sp.order >= 0 ? sp.order : C.o.order;
+    int mx = 0;
+    for (int i = f0; i < f1; ++i) {
+      NF_CHECK(A.at(i, i) != nullptr, NFIELD_ESINGULAR, "BGS: zero diagonal block");
+      S->child.push_back(build<T>(C, sp.kids[0], A, F, i, i + 1, s));
+      mx = std::max(mx, A.size[i]);
+    }
+    S->n = n;
+    S->res.alloc(n);
+    S->d.alloc(n);
+    S->t.alloc(mx);
+    return S;
+  }
+  if (sp.name == "SIMPLE") {
+    NF_CHECK(!sp.kids.empty() && sp.kids.size() <= 2, NFIELD_EINVAL, "spec: SIMPLE(pred[;schur])");
+    NF_CHECK(nf_ >= 2, NFIELD_EINVAL, "SIMPLE needs at least two fields");
+    int g = f1 - 1;
+    if (!C.o.split.empty()) {
+      int cnt = 0;
+      for (int i = f0; i < f1; ++i)
+        if (C.o.split[i] == 1) { ++cnt; g = i; }
+      NF_CHECK(cnt == 1 && g == f1 - 1, NFIELD_EINVAL, "SIMPLE: the Schur group must be the last single field");
+    }
+    auto S = std::make_unique<SimpleSolverD<T>>();
+    S->A = &A;
+    S->f0 = f0;
+    S->f1 = f1;
+    S->g = g;
+    S->sweeps = sp.sweeps > 0 ? sp.sweeps : 1;
+    const int n1 = o[g] - o[f0], n2 = A.size[g];
+    // SIMPLEC-type diagonal of the merged predictor block
+    DBuf<double> dt(n1 > 0 ? n1 : 1);
+    DBuf<int> zf(1);
+    fill<double>(dt.p, 0.0, n1, s);
+    fill<int>(zf.p, 0, 1, s);
+    for (int i = f0; i < g; ++i)
+      for (int j = f0; j < g; ++j)
+        if (A.at(i, j)) row_accumulate(*A.at(i, j), C.o.simplec_mode, i == j, dt.p + (o[i] - o[f0]), s);
+    finish_simplec(dt.p, n1, C.o.simplec_mode, zf.p, s);
+    int z = 0;
+    NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    NF_CHECK(z == 0, NFIELD_ESINGULAR, "SIMPLE: zero entry in the approximate predictor diagonal");
+    // S~ = A_gg - sum_i A_gi D~_i^-1 A_ig
+    auto Sm = std::make_shared<DCsr>();
+    if (A.at(g, g)) csr_copy(*A.at(g, g), *Sm, s);
+    else { Sm->nr = Sm->nc = n2; Sm->nnz = 0; }
+    for (int i = f0; i < g; ++i) {
+      if (!A.at(g, i) || !A.at(i, g)) continue;
+      DCsr Tm, prod, sum;
+      csr_copy(*A.at(i, g), Tm, s);
+      scale_rows(Tm, dt.p + (o[i] - o[f0]), s);
+      spgemm(*A.at(g, i), Tm, prod, s);
+      csr_add(1.0, *Sm, -1.0, prod, sum, s);
+      *Sm = std::move(sum);
+    }
+    NF_CHECK(Sm->nnz > 0, NFIELD_ESINGULAR, "SIMPLE: approximate Schur complement is zero");
+    S->dtinv.alloc(n1 > 0 ? n1 : 1);
+    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(S->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
+    else cast_copy<double, float>(dt.p, (float*)S->dtinv.p, n1, s);
+    NF_HIP(hipStreamSynchronize(s));   // dt is released on return
+    S->pred = build<T>(C, sp.kids[0], A, F, f0, g, s);
+    auto Bm = std::make_unique<BlockMat>();
+    Bm->N = 1;
+    Bm->size = {n2};
+    Bm->blk = {Sm};
+    if (sizeof(T) == sizeof(float)) prepare_fp32(*Bm, s);
+    std::vector<FieldDev> Fs = {F[g]};
+    Spec def;
+    def.name = n2 <= C.o.schur_direct_max ? "LU" : "AMG";
+    S->schur = build<T>(C, sp.kids.size() == 2 ? sp.kids[1] : def, *Bm, Fs, 0, 1, s);
+    C.owned.push_back(std::move(Bm));
+    S->n = n;
+    S->res.alloc(n);
+    S->d.alloc(n);
+    S->t.alloc(n2);
+    int mx = 0;
+    for (int i = f0; i < g; ++i) mx = std::max(mx, A.size[i]);
+    S->u.alloc(mx > 0 ? mx : 1);
+    return S;
+  }
+  throw NfError(NFIELD_EINVAL, "spec: unknown method " + sp.name);
+}
+
+// ================================================================= GMRES
+static void ensure_workspace(nfield_ctx& C, int m, int flexible) {
+  const int64_t n = C.Aglob.nr;
+  if (C.ws_m < m || (flexible && C.Z.n < (size_t)n * m)) {
+    C.V.alloc((size_t)n * (m + 1));
+    if (flexible) C.Z.alloc((size_t)n * m);
+    C.H.alloc((size_t)(m + 1) * m);
+    C.cs.alloc(m);
+    C.sn.alloc(m);
+    C.g.alloc(m + 1);
+    C.y.alloc(m);
+    C.h1.alloc(m + 1);
+    C.h2.alloc(m + 1);
+    C.partial.alloc((size_t)RED_BLOCKS * (m + 1));
+    C.ws_m = m;
+  }
+  if (!C.w.p) {
+    C.w.alloc(n);
+    C.z.alloc(n);
+    C.r.alloc(n);
+    C.u.alloc(n);
+    C.scal.alloc(8);
+  }
+  if (!C.pinned) NF_HIP(hipHostMalloc((void**)&C.pinned, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+static void precond(nfield_ctx& C, const double* r, double* z, hipStream_t s) {
+  if (C.root64) {
+    C.root64->apply(r, z, s);
+  } else {
+    const int64_t n = C.Aglob.nr;
+    cast_copy<double, float>(r, C.r32.p, n, s);
+    C.root32->apply(C.r32.p, C.z32.p, s);
+    cast_copy<float, double>(C.z32.p, z, n, s);
+  }
+}
+
+static double read_scalar(nfield_ctx& C, const double* dev, hipStream_t s) {
+  NF_HIP(hipMemcpyAsync(C.pinned, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  return C.pinned[0];
+}
+
+static double true_residual(nfield_ctx& C, const double* b, const double* x, hipStream_t s) {
+  const int64_t n = C.Aglob.nr;
+  SpmvArgs<double> a;
+  a.x = x;
+  a.y = C.r.p;
+  a.b = b;
+  spmv<double>(SPMV_RESID, C.Aglob, a, s);
+  dot_dev(C.r.p, C.r.p, n, C.partial.p, C.scal.p, s);
+  return std::sqrt(read_scalar(C, C.scal.p, s));
+}
+
+__global__ void k_init_g(double* g, int m, double beta) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i <= m) g[i] = i == 0 ? beta : 0.0;
+}
+__global__ void k_scale(const double* x, double a, double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+static nfield_stats gmres(nfield_ctx& C, const double* b, double* x, const nfield_solve_opts& so, hipStream_t s) {
+  const int64_t n = C.Aglob.nr;
+  const int m = so.restart;
+  nfield_stats st;
+  std::memset(&st, 0, sizeof(st));
+  const bool flex = so.flexible != 0;
+  ensure_workspace(C, m, flex);
+  const double beta0 = true_residual(C, b, x, s);
+  if (!std::isfinite(beta0)) { st.status = NFIELD_ENAN; return st; }
+  if (beta0 == 0.0) { st.status = NFIELD_OK; return st; }
+  int total = 0;
+  bool first = true;
+  const int nb = (int)((n + 255) / 256);
+  while (true) {
+    const double beta = first ? beta0 : true_residual(C, b, x, s);
+    first = false;
+    st.relres = beta / beta0;
+    if (!std::isfinite(beta)) { st.status = NFIELD_ENAN; break; }
+    if (beta / beta0 < so.rtol) { st.status = NFIELD_OK; break; }
+    if (total >= so.maxit) { st.status = NFIELD_NOT_CONVERGED; break; }
+    if (total > 0) st.restarts++;
+    hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, C.r.p, 1.0 / beta, C.V.p, n);
+    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(64), 0, s, C.g.p, m, beta);
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = C.V.p + (int64_t)j * n;
+      double* zj = flex ? C.Z.p + (int64_t)j * n : C.z.p;
+      precond(C, vj, zj, s);
+      SpmvArgs<double> a;
+      a.x = zj;
+      a.y = C.w.p;
+      spmv<double>(SPMV_STORE, C.Aglob, a, s);
+      // classical Gram-Schmidt, twice
+      mdot_partial(C.V.p, n, j + 1, C.w.p, n, C.partial.p, s);
+      mreduce(C.partial.p, j + 1, C.h1.p, 0, s);
+      mupdate_dot(C.V.p, n, j + 1, C.h1.p, C.w.p, n, C.partial.p, s);
+      mreduce(C.partial.p, j + 1, C.h2.p, 0, s);
+      mupdate_norm(C.V.p, n, j + 1, C.h2.p, C.w.p, n, C.partial.p, s);
+      givens_step(j, m, C.h1.p, C.h2.p, C.partial.p, C.H.p, C.cs.p, C.sn.p, C.g.p, C.scal.p + 1, C.scal.p + 2, s);
+      scale_inv_dev(C.w.p, C.V.p + (int64_t)(j + 1) * n, C.scal.p + 1, n, s);
+      NF_HIP(hipMemcpyAsync(C.pinned + 1, C.scal.p + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      NF_HIP(hipStreamSynchronize(s));
+      ++total;
+      jend = j + 1;
+      const double hn = C.pinned[1], res = C.pinned[2];
+      if (!std::isfinite(res)) break;
+      if (hn <= 1e-300 || res / beta0 < so.rtol || total >= so.maxit) break;
+    }
+    backsolve(jend, m, C.H.p, C.g.p, C.y.p, s);
+    if (flex) {
+      mcombine(C.Z.p, n, jend, C.y.p, x, n, 1, s);
+    } else {
+      mcombine(C.V.p, n, jend, C.y.p, C.u.p, n, 0, s);
+      precond(C, C.u.p, C.z.p, s);
+      axpy(1.0, C.z.p, x, n, s);
+    }
+  }
+  st.iters = total;
+  return st;
+}
+
+// host-side checks of one input block (before any device work)
+static void validate_block(const nfield_csr& c, int nr, int nc) {
+  NF_CHECK(c.nrows == nr && c.ncols == nc, NFIELD_EINVAL, "block dimensions disagree with the field sizes");
+  NF_CHECK(c.rowptr && c.colind, NFIELD_EINVAL, "block: null rowptr / colind");
+  NF_CHECK(c.rowptr[0] == 0 && c.rowptr[nr] == c.nnz, NFIELD_EINVAL, "block: rowptr inconsistent with nnz");
+  NF_CHECK(c.nnz < INT32_MAX, NFIELD_ENOMEM, "block: more than 2^31 entries");
+  for (int i = 0; i < nr; ++i) {
+    NF_CHECK(c.rowptr[i + 1] >= c.rowptr[i], NFIELD_EINVAL, "block: rowptr decreasing");
+    for (int64_t p = c.rowptr[i]; p < c.rowptr[i + 1]; ++p) {
+      NF_CHECK(c.colind[p] >= 0 && c.colind[p] < nc, NFIELD_EINVAL, "block: column index out of range");
+      NF_CHECK(p == c.rowptr[i] || c.colind[p] > c.colind[p - 1], NFIELD_EINVAL,
+               "block: column indices not strictly increasing");
+      NF_CHECK(std::isfinite(c.val[p]), NFIELD_EINVAL, "block: non-finite value");
+    }
+  }
+}
+
+static void upload_block(const nfield_csr& c, int nr, int nc, DCsr& D, hipStream_t s) {
+  std::vector<int> ptr(nr + 1);
+  for (int i = 0; i <= nr; ++i) ptr[i] = (int)c.rowptr[i];
+  D.nr = nr;
+  D.nc = nc;
+  D.nnz = c.nnz;
+  D.ptr.alloc(nr + 1);
+  D.col.alloc(c.nnz > 0 ? c.nnz : 1);
+  D.val.alloc(c.nnz > 0 ? c.nnz : 1);
+  NF_HIP(hipMemcpyAsync(D.ptr.p, ptr.data(), sizeof(int) * (nr + 1), hipMemcpyHostToDevice, s));
+  NF_HIP(hipMemcpyAsync(D.col.p, c.colind, sizeof(int) * c.nnz, hipMemcpyHostToDevice, s));
+  NF_HIP(hipMemcpyAsync(D.val.p, c.val, sizeof(double) * c.nnz, hipMemcpyHostToDevice, s));
+  NF_HIP(hipStreamSynchronize(s));
+}
+
+// all blocks merged into one CSR: block row i, blocks j ascending, column
+// offsets of the fields; built on the host from the (validated) inputs
+static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>& size, DCsr& G, hipStream_t s) {
+  std::vector<int> o(N + 1, 0);
+  for (int i = 0; i < N; ++i) o[i + 1] = o[i] + size[i];
+  const int n = o[N];
+  std::vector<int> ptr(n + 1, 0);
+  int64_t nnz = 0;
+  for (int i = 0; i < N; ++i)
+    for (int r = 0; r < size[i]; ++r) {
+      for (int j = 0; j < N; ++j) {
+        const nfield_csr& c = blocks[(size_t)i * N + j];
+        if (c.nnz == 0 || !c.val) continue;
+        nnz += c.rowptr[r + 1] - c.rowptr[r];
+      }
+      ptr[o[i] + r + 1] = (int)nnz;
+    }
+  NF_CHECK(nnz < INT32_MAX, NFIELD_ENOMEM, "system has more than 2^31 entries");
+  std::vector<int> col(nnz > 0 ? nnz : 1);
+  std::vector<double> val(nnz > 0 ? nnz : 1);
+  int64_t q = 0;
+  for (int i = 0; i < N; ++i)
+    for (int r = 0; r < size[i]; ++r)
+      for (int j = 0; j < N; ++j) {
+        const nfield_csr& c = blocks[(size_t)i * N + j];
+        if (c.nnz == 0 || !c.val) continue;
+        for (int64_t p = c.rowptr[r]; p < c.rowptr[r + 1]; ++p) {
+          col[q] = c.colind[p] + o[j];
+          val[q] = c.val[p];
+          ++q;
+        }
+      }
+  G.nr = G.nc = n;
+  G.nnz = nnz;
+  G.ptr.alloc(n + 1);
+  G.col.alloc(col.size());
+  G.val.alloc(val.size());
+  NF_HIP(hipMemcpyAsync(G.ptr.p, ptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+  NF_HIP(hipMemcpyAsync(G.col.p, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
+  NF_HIP(hipMemcpyAsync(G.val.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
+  NF_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace nf
+
+// ================================================================ C ABI
+using namespace nf;
+
+static nfield_status fail(const NfError& e) {
+  g_err = e.what();
+  return (nfield_status)e.code;
+}
+
+extern "C" {
+
+void nfield_default_opts(nfield_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->sweeps = 1;
+  o->order = 1;
+  o->coarse_max = 200;
+  o->max_levels = 10;
+  o->cheb_degree = 2;
+  o->power_its = 10;
+  o->cheb_ratio = 30.0;
+  o->cheb_boost = 1.1;
+  o->simplec_mode = 0;
+  o->split = nullptr;
+  o->schur_direct_max = 5000;
+  o->hier_fp32 = 0;
+  o->seed = 0;
+}
+
+void nfield_default_solve_opts(nfield_solve_opts* so) {
+  so->restart = 50;
+  so->maxit = 1000;
+  so->flexible = 0;
+  so->rtol = 1e-8;
+}
+
+const char* nfield_last_error(void) { return g_err.c_str(); }
+
+const char* nfield_strerror(nfield_status s) {
+  switch (s) {
+    case NFIELD_OK: return "ok";
+    case NFIELD_NOT_CONVERGED: return "not converged";
+    case NFIELD_EINVAL: return "invalid argument";
+    case NFIELD_ENOMEM: return "out of memory or size limit";
+    case NFIELD_ESINGULAR: return "singular block or pivot";
+    case NFIELD_EBREAKDOWN: return "Krylov breakdown";
+    case NFIELD_ENAN: return "non-finite value";
+    case NFIELD_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nfield_csr* blocks, const char* spec,
+                           const nfield_opts* opts, void* hip_stream, nfield_ctx** out) {
+  if (!out || !fields || !blocks || !spec || nfields < 1) {
+    g_err = "nfield_setup: null argument or no fields";
+    return NFIELD_EINVAL;
+  }
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto C = std::make_unique<nfield_ctx>();
+  size_t* prev = g_acct;
+  g_acct = &C->bytes;
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    nfield_opts od;
+    nfield_default_opts(&od);
+    const nfield_opts& o = opts ? *opts : od;
+    C->o.sweeps = o.sweeps;
+    C->o.order = o.order;
+    C->o.coarse_max = o.coarse_max;
+    C->o.max_levels = o.max_levels;
+    C->o.cheb_degree = o.cheb_degree;
+    C->o.power_its = o.power_its;
+    C->o.cheb_ratio = o.cheb_ratio;
+    C->o.cheb_boost = o.cheb_boost;
+    C->o.simplec_mode = o.simplec_mode;
+    if (o.split) C->o.split.assign(o.split, o.split + nfields);
+    C->o.schur_direct_max = o.schur_direct_max;
+    C->o.hier_fp32 = o.hier_fp32;
+    C->o.seed = o.seed;
+    NF_CHECK(o.sweeps >= 1 && o.order >= 0 && o.order <= 2 && o.cheb_degree >= 1 && o.max_levels >= 1 &&
+                 o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2,
+             NFIELD_EINVAL, "options out of range");
+    C->N = nfields;
+    C->A.N = nfields;
+    C->A.size.resize(nfields);
+    C->A.blk.resize((size_t)nfields * nfields);
+    for (int i = 0; i < nfields; ++i) {
+      const nfield_field& f = fields[i];
+      NF_CHECK(f.ndof > 0 && f.block_size > 0 && f.ndof % f.block_size == 0 && f.nns >= 0, NFIELD_EINVAL,
+               "field description");
+      C->A.size[i] = f.ndof;
+    }
+    for (int i = 0; i < nfields; ++i)
+      for (int j = 0; j < nfields; ++j) {
+        const nfield_csr& c = blocks[(size_t)i * nfields + j];
+        if (c.nnz == 0 || c.val == nullptr) continue;
+        validate_block(c, C->A.size[i], C->A.size[j]);
+      }
+    const Spec sp = parse_spec(spec);
+    check_spec(sp);
+    for (int i = 0; i < nfields; ++i) {
+      const nfield_field& f = fields[i];
+      FieldDev fd;
+      fd.ndof = f.ndof;
+      fd.bs = f.block_size;
+      fd.nns = f.nns;
+      if (f.nns > 0 && f.nullspace) {
+        fd.B = std::make_shared<DBuf<double>>((size_t)f.ndof * f.nns);
+        NF_HIP(hipMemcpyAsync(fd.B->p, f.nullspace, sizeof(double) * f.ndof * f.nns, hipMemcpyHostToDevice, s));
+      }
+      C->F.push_back(fd);
+      C->A.size[i] = f.ndof;
+    }
+    for (int i = 0; i < nfields; ++i)
+      for (int j = 0; j < nfields; ++j) {
+        const nfield_csr& c = blocks[(size_t)i * nfields + j];
+        if (c.nnz == 0 || c.val == nullptr) continue;
+        auto D = std::make_shared<DCsr>();
+        upload_block(c, C->A.size[i], C->A.size[j], *D, s);
+        C->A.blk[(size_t)i * nfields + j] = D;
+      }
+    merge_global(blocks, nfields, C->A.size, C->Aglob, s);
+    if (C->o.hier_fp32) {
+      prepare_fp32(C->A, s);
+      C->root32 = build<float>(*C, sp, C->A, C->F, 0, nfields, s);
+      C->r32.alloc(C->Aglob.nr);
+      C->z32.alloc(C->Aglob.nr);
+    } else {
+      C->root64 = build<double>(*C, sp, C->A, C->F, 0, nfields, s);
+    }
+    NF_HIP(hipStreamSynchronize(s));
+    NF_HIP(hipGetLastError());
+    C->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    g_acct = prev;
+    *out = C.release();
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    g_acct = prev;
+    return fail(e);
+  } catch (std::exception& e) {
+    g_acct = prev;
+    g_err = e.what();
+    return NFIELD_ENOMEM;
+  }
+}
+
+void nfield_destroy(nfield_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+size_t nfield_footprint_bytes(const nfield_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+int64_t nfield_size(const nfield_ctx* ctx) { return ctx ? ctx->Aglob.nr : 0; }
+
+nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, int32_t nrhs, void* hip_stream) {
+  if (!ctx || !r || !z || nrhs < 0) { g_err = "nfield_precond_apply: bad argument"; return NFIELD_EINVAL; }
+  hipStream_t s = (hipStream_t)hip_stream;
+  size_t* prev = g_acct;
+  g_acct = &ctx->bytes;
+  try {
+    const int64_t n = ctx->Aglob.nr;
+    for (int k = 0; k < nrhs; ++k) precond(*ctx, r + k * n, z + k * n, s);
+    NF_HIP(hipGetLastError());
+    g_acct = prev;
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    g_acct = prev;
+    return fail(e);
+  }
+}
+
+nfield_status nfield_matvec(nfield_ctx* ctx, const double* x, double* y, int32_t nrhs, void* hip_stream) {
+  if (!ctx || !x || !y || nrhs < 0) { g_err = "nfield_matvec: bad argument"; return NFIELD_EINVAL; }
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    const int64_t n = ctx->Aglob.nr;
+    for (int k = 0; k < nrhs; ++k) {
+      SpmvArgs<double> a;
+      a.x = x + k * n;
+      a.y = y + k * n;
+      spmv<double>(SPMV_STORE, ctx->Aglob, a, s);
+    }
+    NF_HIP(hipGetLastError());
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    return fail(e);
+  }
+}
+
+nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
+                                 nfield_stats* stats, void* hip_stream) {
+  if (!ctx || !b || !x || nrhs < 0) { g_err = "nfield_gmres_solve: bad argument"; return NFIELD_EINVAL; }
+  nfield_solve_opts so;
+  nfield_default_solve_opts(&so);
+  if (sopts) so = *sopts;
+  if (so.restart < 1 || so.restart > 63 || so.maxit < 0 || !(so.rtol > 0)) {
+    g_err = "nfield_gmres_solve: restart must be in [1, 63], maxit >= 0, rtol > 0";
+    return NFIELD_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  size_t* prev = g_acct;
+  g_acct = &ctx->bytes;
+  try {
+    const int64_t n = ctx->Aglob.nr;
+    int worst = NFIELD_OK;
+    for (int k = 0; k < nrhs; ++k) {
+      const auto t0 = std::chrono::steady_clock::now();
+      nfield_stats st = gmres(*ctx, b + k * n, x + k * n, so, s);
+      NF_HIP(hipStreamSynchronize(s));
+      st.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      st.setup_s = ctx->setup_s;
+      if (stats) stats[k] = st;
+      if (st.status < 0) {
+        g_err = "nfield_gmres_solve: non-finite value in the iteration";
+        g_acct = prev;
+        return (nfield_status)st.status;
+      }
+      if (st.status > worst) worst = st.status;
+    }
+    g_acct = prev;
+    return (nfield_status)worst;
+  } catch (NfError& e) {
+    g_acct = prev;
+    return fail(e);
+  }
+}
+
+// ---------------------------------------------------------------- inspection
+int32_t nfield_hier_count(const nfield_ctx* c) { return c ? (int32_t)c->hiers.size() : 0; }
+int32_t nfield_hier_nlevels(const nfield_ctx* c, int32_t h) { return (int32_t)c->hiers[h]->lev.size(); }
+int32_t nfield_hier_nfields(const nfield_ctx* c, int32_t h) { return c->hiers[h]->N; }
+int32_t nfield_hier_size(const nfield_ctx* c, int32_t h, int32_t l, int32_t f) { return c->hiers[h]->lev[l].A.size[f]; }
+double nfield_hier_lambda(const nfield_ctx* c, int32_t h, int32_t l, int32_t f) {
+  const Level& L = c->hiers[h]->lev[l];
+  return f < (int)L.lambda.size() ? L.lambda[f] : 0.0;
+}
+
+int64_t nfield_hier_matrix(const nfield_ctx* c, int32_t h, int32_t l, int32_t which, int32_t i, int32_t j, int64_t* rowptr,
+                           int32_t* colind, double* val, int32_t* nrows, int32_t* ncols) {
+  try {
+    const Level& L = c->hiers[h]->lev[l];
+    const DCsr* M = nullptr;
+    if (which == 0) M = L.A.at(i, j);
+    else if (which == 1 && i < (int)L.P.size()) M = L.P[i].get();
+    else if (which == 2 && i < (int)L.R.size()) M = L.R[i].get();
+    if (!M) return -1;
+    if (nrows) *nrows = M->nr;
+    if (ncols) *ncols = M->nc;
+    NF_HIP(hipDeviceSynchronize());
+    if (rowptr) {
+      std::vector<int> p(M->nr + 1);
+      NF_HIP(hipMemcpy(p.data(), M->ptr.p, sizeof(int) * (M->nr + 1), hipMemcpyDeviceToHost));
+      for (int r = 0; r <= M->nr; ++r) rowptr[r] = p[r];
+    }
+    if (colind && M->nnz) NF_HIP(hipMemcpy(colind, M->col.p, sizeof(int) * M->nnz, hipMemcpyDeviceToHost));
+    if (val && M->nnz) NF_HIP(hipMemcpy(val, M->val.p, sizeof(double) * M->nnz, hipMemcpyDeviceToHost));
+    return M->nnz;
+  } catch (NfError& e) {
+    g_err = e.what();
+    return -2;
+  }
+}
+
+int32_t nfield_hier_aggregates(const nfield_ctx* c, int32_t h, int32_t l, int32_t f, int32_t* agg) {
+  const Level& L = c->hiers[h]->lev[l];
+  if (f >= (int)L.agg.size() || !L.agg[f]) return -1;
+  const int nn = L.A.size[f] / L.bs[f];
+  if (agg) {
+    if (hipDeviceSynchronize() != hipSuccess) return -2;
+    if (hipMemcpy(agg, L.agg[f]->p, sizeof(int) * nn, hipMemcpyDeviceToHost) != hipSuccess) return -2;
+  }
+  return nn;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""GPU library (through the C ABI) against the CPU oracle, on the same seeded
+inputs.
+
+Bars: aggregates bit-exact; hierarchy patterns identical and values within
+1e-12 relative; SpMV within 1e-12 of |A||x| per entry; solutions within 1e-6
+relative of the oracle at rtol 1e-8 with a true residual below 1e-8.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import nfgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1605_01522_amd import nfield
+    nfield.lib()
+    return torch.device("cuda:0")
+
+
+def _gpu(s, spec, **opts):
+    from paper_1605_01522_amd import NField
+    return NField(s.fields, s.blocks, spec, **opts)
+
+
+TSI_OPTS = dict(sweeps=2, order="bwd")
+
+
+# ------------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("nel", [3, 17, 32])
+def test_block_spmv_parity(dev, nel):
+    _say(f"case spmv nel={nel}")
+    s = nfgen.tsi2d(nel=nel, seed=nel)
+    g = _gpu(s, "BGS(LU)" if nel <= 3 else "BGS(AMG)", **TSI_OPTS)
+    x = np.random.default_rng(nel).standard_normal((2, s.n))
+    y = g.matvec(torch.tensor(x, device=dev)).cpu().numpy()
+    A = s.assembled()
+    ref = np.stack([A @ xi for xi in x])
+    bound = 1e-12 * np.stack([abs(A) @ abs(xi) for xi in x])
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+# ------------------------------------------------------------- hierarchy
+def _compare_hierarchies(g, o):
+    assert g.hier_count() == o.hier_count()
+    for h in range(o.hier_count()):
+        assert g.nlevels(h) == o.nlevels(h), (h, g.nlevels(h), o.nlevels(h))
+        nf_ = o.nfields(h)
+        for l in range(o.nlevels(h)):
+            for f in range(nf_):
+                assert g.level_size(h, l, f) == o.level_size(h, l, f)
+                ag, ao = g.aggregates(h, l, f), o.aggregates(h, l, f)
+                if ao is None:
+                    assert ag is None
+                else:
+                    assert np.array_equal(ag, ao), (h, l, f)          # bit-exact
+                lo, lg = o.lam(h, l, f), g.lam(h, l, f)
+                if l + 1 < o.nlevels(h):
+                    assert abs(lg - lo) <= 1e-12 * abs(lo), (h, l, f, lg, lo)
+            for which, pairs in (("A", [(i, j) for i in range(nf_) for j in range(nf_)]),
+                                 ("P", [(i, 0) for i in range(nf_)]),
+                                 ("R", [(i, 0) for i in range(nf_)])):
+                for i, j in pairs:
+                    Mo = o.matrix(h, l, which, i, j)
+                    Mg = g.matrix(h, l, which, i, j)
+                    if Mo is None:
+                        assert Mg is None
+                        continue
+                    assert np.array_equal(Mg.indptr, Mo.indptr), (h, l, which, i, j)
+                    assert np.array_equal(Mg.indices, Mo.indices), (h, l, which, i, j)
+                    scale = max(np.abs(Mo.data).max(), 1e-300)
+                    assert np.abs(Mg.data - Mo.data).max() <= 1e-12 * scale, (h, l, which, i, j)
+
+
+@pytest.mark.parametrize("nel,coarse_max,seed", [(8, 20, 0), (20, 50, 3), (32, 200, 0)])
+def test_bgs_amg_hierarchy_parity(dev, nel, coarse_max, seed):
+    _say(f"case hierarchy BGS(AMG) nel={nel} coarse_max={coarse_max} seed={seed}")
+    s = nfgen.tsi2d(nel=nel, seed=seed)
+    o = oracle.Oracle(s.fields, s.blocks, "BGS(AMG)", coarse_max=coarse_max, seed=seed, **TSI_OPTS)
+    g = _gpu(s, "BGS(AMG)", coarse_max=coarse_max, seed=seed, **TSI_OPTS)
+    _compare_hierarchies(g, o)
+
+
+def test_mono_amg_hierarchy_parity(dev):
+    _say("case hierarchy AMG(BGS) nel=24")
+    s = nfgen.tsi2d(nel=24, seed=2)
+    o = oracle.Oracle(s.fields, s.blocks, "AMG(BGS)", coarse_max=80, **TSI_OPTS)
+    g = _gpu(s, "AMG(BGS)", coarse_max=80, **TSI_OPTS)
+    _compare_hierarchies(g, o)
+
+
+# ----------------------------------------------------- preconditioner apply
+SPECS = ["BGS(AMG)", "BGS[order=fwd](AMG)", "BGS[sweeps=3,order=sym](AMG)", "BGS(LU)",
+         "SIMPLE(AMG;AMG)", "SIMPLE(AMG;LU)", "AMG(BGS)", "AMG(BGS[order=fwd])"]
+
+
+@pytest.mark.parametrize("spec", SPECS)
+def test_precond_apply_parity(dev, spec):
+    _say(f"case precond {spec}")
+    nel = 10 if "LU" in spec and "SIMPLE" not in spec else 20
+    s = nfgen.tsi2d(nel=nel, seed=4)
+    opts = dict(coarse_max=40, **TSI_OPTS)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(7).standard_normal((3, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    for k in range(3):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k]), (spec, k)
+
+
+# ------------------------------------------------------------ end to end
+@pytest.mark.parametrize("nel,seed,spec", [(32, 0, "BGS(AMG)"), (32, 1, "BGS(AMG)"), (13, 2, "BGS(AMG)"),
+                                           (32, 0, "AMG(BGS)"), (32, 0, "SIMPLE(AMG;AMG)")])
+def test_gmres_solution_parity(dev, nel, seed, spec):
+    _say(f"case gmres {spec} nel={nel} seed={seed}")
+    s = nfgen.tsi2d(nel=nel, seed=seed, nrhs=2)
+    o = oracle.Oracle(s.fields, s.blocks, spec, seed=seed, **TSI_OPTS)
+    g = _gpu(s, spec, seed=seed, **TSI_OPTS)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs, device=dev), rtol=1e-8)
+    x = x.cpu().numpy()
+    for k in range(2):
+        xo, so = o.gmres(s.rhs[k], rtol=1e-8)
+        res = np.linalg.norm(s.rhs[k] - A @ x[k]) / np.linalg.norm(s.rhs[k])
+        assert st[k]["status"] == 0 and res < 1e-8
+        assert abs(st[k]["relres"] - res) < 1e-10
+        assert np.linalg.norm(x[k] - xo) <= 1e-6 * np.linalg.norm(xo)
+        assert abs(st[k]["iters"] - so["iters"]) <= 2, (st[k]["iters"], so["iters"])
+
+
+def test_flexible_and_restart(dev):
+    _say("case gmres flexible / short restart")
+    s = nfgen.tsi2d(nel=24, seed=5)
+    g = _gpu(s, "BGS(AMG)", **TSI_OPTS)
+    A = s.assembled()
+    b = torch.tensor(s.rhs[0], device=dev)
+    for restart, flexible in [(50, 1), (5, 0), (4, 1)]:
+        x, st = g.gmres_solve(b, restart=restart, flexible=flexible, rtol=1e-9)
+        xr = x.cpu().numpy()
+        res = np.linalg.norm(s.rhs[0] - A @ xr) / np.linalg.norm(s.rhs[0])
+        assert st[0]["status"] == 0 and res < 1e-9, (restart, flexible, res)
+
+
+def test_precision_form_fp32_hierarchy(dev):
+    _say("case precision form")
+    s = nfgen.tsi2d(nel=32, seed=0)
+    o = oracle.Oracle(s.fields, s.blocks, "BGS(AMG)", **TSI_OPTS)
+    g = _gpu(s, "BGS(AMG)", hier_fp32=1, **TSI_OPTS)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), flexible=1, rtol=1e-8)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8)
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"precision form: iters {st[0]['iters']} (fp64 oracle {so['iters']}), relres {res:.2e}, err {err:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
+
+
+# ------------------------------------------------------------ edge cases
+def test_single_level_is_exact(dev):
+    _say("case single level")
+    s = nfgen.tsi2d(nel=4)
+    g = _gpu(s, "BGS[sweeps=1,order=fwd](AMG)", coarse_max=1000)
+    assert [g.nlevels(h) for h in range(g.hier_count())] == [1, 1]
+    r = np.random.default_rng(0).standard_normal(s.n)
+    z = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    n0 = s.fields[0].ndof
+    z0 = np.linalg.solve(s.blocks[0][0].toarray(), r[:n0])
+    z1 = np.linalg.solve(s.blocks[1][1].toarray(), r[n0:] - s.blocks[1][0] @ z0)
+    assert np.allclose(z, np.concatenate([z0, z1]), rtol=1e-10, atol=1e-12)
+
+
+def test_zero_nan_and_maxit(dev):
+    _say("case zero / nan / maxit")
+    from paper_1605_01522_amd import nfield
+    s = nfgen.tsi2d(nel=6)
+    g = _gpu(s, "BGS(AMG)", coarse_max=20)
+    x, st = g.gmres_solve(torch.zeros(s.n, dtype=torch.float64, device=dev))
+    assert st[0]["iters"] == 0 and st[0]["status"] == 0 and float(x.abs().max()) == 0.0
+    b = torch.tensor(s.rhs[0], device=dev)
+    b[3] = float("nan")
+    with pytest.raises(nfield.NFieldError) as e:
+        g.gmres_solve(b)
+    assert e.value.code == -5
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), maxit=1, rtol=1e-14)
+    assert st[0]["status"] == 1 and st[0]["iters"] == 1
+
+
+def test_singular_inputs(dev):
+    _say("case singular inputs")
+    from paper_1605_01522_amd import nfield
+    s = nfgen.tsi2d(nel=4)
+    bad = [[s.blocks[0][0], s.blocks[0][1]], [s.blocks[1][0], None]]
+    with pytest.raises(nfield.NFieldError) as e:
+        _gpu(nfgen.BlockSystem(s.fields, bad, s.rhs), "BGS(AMG)")
+    assert e.value.code == -3
