@@ -23,7 +23,11 @@
  *                           transfers, coarse blocks R_i A_ij P_j, BGS or
  *                           SIMPLE level smoothers;
  *   "LU"                    dense direct solve (small blocks only).
- * Optional per-method parameters: "BGS[sweeps=2,order=bwd](AMG)".
+ * Optional per-method parameters: "BGS[sweeps=2,order=bwd](AMG)" (sweeps and
+ * order of one BGS / SIMPLE node), "AMG[degree=1]" (Chebyshev smoother degree
+ * of one hierarchy; degree 1 is damped Jacobi), "AMG[smoother=sgs,omega=0.69,
+ * steps=1]" (symmetric multicolour Gauss-Seidel with damping omega instead of
+ * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7).
  *
  * All device work runs in the library's own HIP kernels for gfx950, enqueued
  * on the caller's stream.  Every vector argument named *_dev is a device
@@ -142,6 +146,26 @@ nfield_status nfield_matvec(nfield_ctx *ctx, const double *x_dev, double *y_dev,
 nfield_status nfield_gmres_solve(nfield_ctx *ctx, const double *b_dev, double *x_dev,
                                  int32_t nrhs, const nfield_solve_opts *sopts,
                                  nfield_stats *stats, void *hip_stream);
+
+/* Replace the values of the nonzero block (i, j), keeping its pattern (the
+ * next Newton step of the paper's monolithic scheme, Sec. 2).  val holds the
+ * block's nnz values in its CSR order, in device memory (on_device = 1,
+ * enqueued on hip_stream) or host memory (copied before return).  The
+ * preconditioner keeps using the old values until nfield_rebuild. */
+nfield_status nfield_update_values(nfield_ctx *ctx, int32_t i, int32_t j, const double *val,
+                                   int32_t on_device, void *hip_stream);
+
+/* Rebuild the whole preconditioner (hierarchies, smoothers, Schur
+ * complements, coarse inverses) from the device-resident blocks. */
+nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
+
+/* Launch timing of the SpMV kernels (HIP events on the launch stream).
+ * nfield_prof_enable(1) clears and starts recording, 0 stops.  prof_read
+ * returns the number of kernel variants and fills up to max entries: key =
+ * 100*lanes_per_row + 10*mode + (1 if FP32), launches, total milliseconds,
+ * total algorithmic bytes (matrix once, operand once, epilogue streams). */
+void nfield_prof_enable(int32_t on);
+int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);
 
 size_t nfield_footprint_bytes(const nfield_ctx *ctx);   /* device bytes the context holds */
 int64_t nfield_size(const nfield_ctx *ctx);             /* n = sum of field sizes */

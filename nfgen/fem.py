@@ -175,3 +175,100 @@ def renumber(keep_mask):
     m = np.full(keep_mask.shape[0], -1, dtype=np.int64)
     m[keep_mask] = np.arange(int(keep_mask.sum()))
     return m
+
+
+# --------------------------------------------------------------------------
+# Structured hex grids: assembly straight into a 27-point node stencil
+# --------------------------------------------------------------------------
+_LOCAL3 = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                    [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]])
+
+
+def grid_nodes(dims):
+    """(i, j, k) of every node of an (nx+1, ny+1, nz+1) grid, id = (k*ny1+j)*nx1+i."""
+    nx1, ny1, nz1 = dims
+    k, j, i = np.meshgrid(np.arange(nz1), np.arange(ny1), np.arange(nx1), indexing="ij")
+    return np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
+
+
+def stencil_assemble(nel_dims, ncomp, pair_block):
+    """Sum hex element matrices into st[node, slot, c, d] (slot = 27-point
+    neighbour offset, lexicographic in (dz, dy, dx)).
+
+    pair_block(a, b) returns the (nel, ncomp, ncomp) block of every element
+    matrix coupling local node a (rows) to local node b (columns), elements
+    in the order of grid_conn_3d.
+    """
+    nx, ny, nz = nel_dims
+    dims = (nx + 1, ny + 1, nz + 1)
+    nn = dims[0] * dims[1] * dims[2]
+    conn = grid_conn_3d(nx, ny, nz)
+    st = np.zeros((nn, 27, ncomp, ncomp))
+    for a in range(8):
+        rows = conn[:, a]                       # distinct for a fixed a
+        for b in range(8):
+            d = _LOCAL3[b] - _LOCAL3[a]
+            slot = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1)
+            st[rows, slot] += pair_block(a, b)
+    return st, dims
+
+
+def stencil_to_csr(st, dims, row_map, col_map, nrows, ncols, comp_pairs=None, dirichlet=None):
+    """CSR from a node stencil.
+
+    row_map / col_map: old dof (node*ncomp + comp) -> new index or -1; both
+    must be increasing on the kept dofs so that rows and columns come out
+    sorted.  comp_pairs (ncomp, ncomp) bool: component couplings to store.
+    dirichlet: bool per old dof; such rows and columns keep only their
+    diagonal, set to 1.
+    """
+    nn, _, nc, _ = st.shape
+    nx1, ny1, nz1 = dims
+    ijk = grid_nodes(dims)
+    offs = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    nb_ijk = ijk[:, None, :] + offs[None, :, :]
+    inside = np.all((nb_ijk >= 0) & (nb_ijk < np.array(dims)), axis=2)
+    nb = (nb_ijk[..., 2] * ny1 + nb_ijk[..., 1]) * nx1 + nb_ijk[..., 0]
+    nb = np.where(inside, nb, 0)
+    if comp_pairs is None:
+        comp_pairs = np.ones((nc, nc), bool)
+    u = np.arange(nn)
+    rdof = u[:, None] * nc + np.arange(nc)[None, :]                 # (nn, c)
+    cdof = nb[:, :, None] * nc + np.arange(nc)[None, None, :]       # (nn, s, d)
+    R = np.broadcast_to(rdof[:, :, None, None], (nn, nc, 27, nc))
+    Cd = np.broadcast_to(cdof[:, None, :, :], (nn, nc, 27, nc))
+    keep = (np.broadcast_to(inside[:, None, :, None], R.shape)
+            & np.broadcast_to(comp_pairs[None, :, None, :], R.shape))
+    V = np.ascontiguousarray(np.transpose(st, (0, 2, 1, 3)))      # (nn, c, s, d)
+    if dirichlet is not None:
+        dr = dirichlet[R]
+        dc = dirichlet[Cd]
+        diag = (R == Cd)
+        keep &= (~dr & ~dc) | diag
+        V = np.where(diag & dr, 1.0, V)
+    rows = row_map[R]
+    cols = col_map[Cd]
+    keep &= (rows >= 0) & (cols >= 0)
+    rows = rows[keep]
+    cols = cols[keep].astype(np.int32)
+    vals = V[keep]
+    ptr = np.zeros(nrows + 1, np.int64)
+    ptr[1:] = np.bincount(rows, minlength=nrows)
+    np.cumsum(ptr, out=ptr)
+    M = sp.csr_matrix((vals, cols, ptr), shape=(nrows, ncols))
+    M.has_sorted_indices = True
+    return M
+
+
+def gauss_tensors_3d(h):
+    """Constant per-element tensors of a cube of side h (2x2x2 Gauss):
+    L[a,b] = int grad N_a . grad N_b,  C[d,a,b] = int N_a dN_b/dx_d,
+    G[c,a,b] = int dN_a/dx_c N_b,  D[c,d,a,b] = int dN_a/dx_c dN_b/dx_d,
+    M[a,b] = int N_a N_b."""
+    N, dN, w = q1_3d(h, h, h)
+    L = np.einsum("q,qad,qbd->ab", w, dN, dN)
+    Cm = np.einsum("q,qa,qbd->dab", w, N, dN)
+    G = np.einsum("q,qac,qb->cab", w, dN, N)
+    D = np.einsum("q,qac,qbd->cdab", w, dN, dN)
+    M = np.einsum("q,qa,qb->ab", w, N, N)
+    return L, Cm, G, D, M

@@ -151,10 +151,149 @@ def tsi2d(nel=32, E=1.0, nu=0.3, kappa=1.0, dt=0.1, alpha=1e-2, cba=1e-3,
     return sys_
 
 
+# --------------------------------------------------------------------------
+# 3-field FSI-like system (solid S, grid motion G, fluid F)
+# --------------------------------------------------------------------------
+def _advection_field(centers, seed, kmax=2):
+    """a = curl(psi), psi_c = sum_k alpha_{c,k} sin(pi k.x) over integer wave
+    vectors with 0 < |k| <= kmax, scaled so that max |a| = 1 over the points."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xADF]))
+    ks = [np.array(k) for k in np.ndindex(kmax + 1, kmax + 1, kmax + 1)
+          if 0 < np.linalg.norm(k) <= kmax]
+    a = np.zeros_like(centers)
+    for k in ks:
+        alpha = rng.standard_normal(3)
+        phase = np.pi * centers @ k
+        c = np.cos(phase)
+        # grad psi_c = alpha_c pi k cos(pi k.x);  curl: (d_y psi_z - d_z psi_y, ...)
+        g = np.pi * c[:, None] * k[None, :]
+        a[:, 0] += alpha[2] * g[:, 1] - alpha[1] * g[:, 2]
+        a[:, 1] += alpha[0] * g[:, 2] - alpha[2] * g[:, 0]
+        a[:, 2] += alpha[1] * g[:, 0] - alpha[0] * g[:, 1]
+    return a / np.max(np.linalg.norm(a, axis=1))
+
+
+def fsi3d(n=40, layers=8, nu=1e-2, E=1e3, nu_s=0.3, dt=1.0, seed=0, nrhs=1):
+    """Fluid (PSPG-stabilised Q1-Q1 Oseen, 4 dof/node) on an n^3 hex box,
+    ALE grid motion (vector Laplacian) on the same mesh, and a Q1 elastic slab
+    of n x n x layers elements on the fluid's top face.
+
+    Fluid: no-slip on the five faces other than the top; those velocity dofs
+    stay as identity rows (uniform 4 dofs per node).  ALE: zero on the same
+    five faces; its interior nodes are the G unknowns.  Structure: lateral
+    faces clamped; its bottom (interface) nodes match the fluid's top-face
+    nodes.  The interface displacements of S and G are condensed onto the
+    fluid interface velocities, d = dt * u (the solid-interface rows are
+    added to the fluid interface momentum rows), which gives the block
+    pattern [SS 0 SF; 0 GG GF; FS 0 FF].  Field order (S, G, F).
+    """
+    h = 1.0 / n
+    # ---------------- fluid grid: 4 dofs per node (u, v, w, p)
+    fdims = (n + 1, n + 1, n + 1)
+    fijk = fem.grid_nodes(fdims)
+    nfn = fijk.shape[0]
+    wall = (fijk[:, 0] == 0) | (fijk[:, 0] == n) | (fijk[:, 1] == 0) | (fijk[:, 1] == n) | (fijk[:, 2] == 0)
+    top_int = (fijk[:, 2] == n) & ~wall
+    conn = fem.grid_conn_3d(n, n, n)
+    centers = (fijk[conn[:, 0]] + 0.5) * h
+    a = _advection_field(centers, seed)
+    amag = np.linalg.norm(a, axis=1)
+    tau = ((2 * amag / h) ** 2 + (4 * nu / h ** 2) ** 2) ** -0.5
+    L, Cm, G, D, _ = fem.gauss_tensors_3d(h)
+
+    def fluid_pair(ia, ib):
+        blk = np.zeros((conn.shape[0], 4, 4))
+        conv = a @ Cm[:, ia, ib]                                  # sum_d a_d int N_a dN_b/dx_d
+        for c in range(3):
+            blk[:, c, c] = nu * L[ia, ib] + conv
+            blk[:, c, 3] = -G[c, ia, ib]                          # -int dN_a/dx_c N_b
+            blk[:, 3, c] = G[c, ib, ia] + tau * (a @ D[c, :, ia, ib])   # div + PSPG convection
+        blk[:, 3, 3] = tau * L[ia, ib]                            # PSPG pressure Laplacian
+        return blk
+
+    stF, _ = fem.stencil_assemble((n, n, n), 4, fluid_pair)
+    fdir = np.zeros(nfn * 4, bool)
+    for c in range(3):
+        fdir[np.nonzero(wall)[0] * 4 + c] = True
+    nF = nfn * 4
+    ident = np.arange(nF)
+    fpairs = np.ones((4, 4), bool)
+    fpairs[:3, :3] = np.eye(3, dtype=bool)
+    AFF = fem.stencil_to_csr(stF, fdims, ident, ident, nF, nF, fpairs, dirichlet=fdir)
+    del stF
+
+    # fluid interface velocity dof of each top-face node
+    def fluid_vel_dof(node, c):
+        return node * 4 + c
+
+    # ---------------- ALE on the fluid grid: 3 dofs per node
+    Lap = L.copy()
+    stG, _ = fem.stencil_assemble((n, n, n), 3, lambda ia, ib: np.broadcast_to(
+        np.eye(3) * Lap[ia, ib], (conn.shape[0], 3, 3)))
+    interior = (fijk[:, 0] > 0) & (fijk[:, 0] < n) & (fijk[:, 1] > 0) & (fijk[:, 1] < n) & \
+               (fijk[:, 2] > 0) & (fijk[:, 2] < n)
+    g_int_dof = np.repeat(interior, 3)
+    gmap = fem.renumber(g_int_dof)
+    nG = int(g_int_dof.sum())
+    g_if = np.full(nfn * 3, -1, np.int64)            # ALE interface dof -> fluid velocity dof
+    ifn = np.nonzero(top_int)[0]
+    for c in range(3):
+        g_if[ifn * 3 + c] = fluid_vel_dof(ifn, c)
+    gpairs = np.eye(3, dtype=bool)
+    AGG = fem.stencil_to_csr(stG, fdims, gmap, gmap, nG, nG, gpairs)
+    AGF = fem.stencil_to_csr(stG, fdims, gmap, g_if, nG, nF, gpairs) * dt
+    del stG
+
+    # ---------------- structure slab: nodes (i, j, k), k = 0 on the interface
+    sdims = (n + 1, n + 1, layers + 1)
+    sijk = fem.grid_nodes(sdims)
+    nsn = sijk.shape[0]
+    clamped = (sijk[:, 0] == 0) | (sijk[:, 0] == n) | (sijk[:, 1] == 0) | (sijk[:, 1] == n)
+    s_free = ~clamped & (sijk[:, 2] > 0)
+    s_if = ~clamped & (sijk[:, 2] == 0)
+    Ke = fem.ke_elastic(fem.q1_3d(h, h, h), E, nu_s).reshape(8, 3, 8, 3)
+    sconn = fem.grid_conn_3d(n, n, layers)
+    stS, _ = fem.stencil_assemble((n, n, layers), 3, lambda ia, ib: np.broadcast_to(
+        Ke[ia, :, ib, :], (sconn.shape[0], 3, 3)))
+    smap = fem.renumber(np.repeat(s_free, 3))
+    nS = int(np.repeat(s_free, 3).sum())
+    # structure interface node (i, j, 0) <-> fluid node (i, j, n)
+    s_to_f = np.full(nsn * 3, -1, np.int64)
+    sn_if = np.nonzero(s_if)[0]
+    fnode = (n * (n + 1) + sijk[sn_if, 1]) * (n + 1) + sijk[sn_if, 0]
+    for c in range(3):
+        s_to_f[sn_if * 3 + c] = fluid_vel_dof(fnode, c)
+    ASS = fem.stencil_to_csr(stS, sdims, smap, smap, nS, nS)
+    ASF = fem.stencil_to_csr(stS, sdims, smap, s_to_f, nS, nF) * dt
+    AFS = fem.stencil_to_csr(stS, sdims, s_to_f, smap, nF, nS)
+    AFF_s = fem.stencil_to_csr(stS, sdims, s_to_f, s_to_f, nF, nF) * dt
+    del stS
+    AFF = (AFF + AFF_s).tocsr()
+    AFF.sort_indices()
+
+    xyz_s = sijk[s_free] * h + np.array([0.0, 0.0, 1.0])
+    nsS = rigid_modes_3d(xyz_s, xyz_s.mean(axis=0))
+    nsG = np.zeros((3, nG))
+    for c in range(3):
+        nsG[c, c::3] = 1.0
+    nsF = np.zeros((4, nF))
+    for c in range(4):
+        nsF[c, c::4] = 1.0
+    nsF[:, fdir] = 0.0
+    fields = [Field("solid", nS, 3, nsS), Field("grid", nG, 3, nsG), Field("fluid", nF, 4, nsF)]
+    blocks = [[ASS, None, ASF], [None, AGG, AGF], [AFS, None, AFF]]
+    for row in blocks:
+        for B in row:
+            if B is not None:
+                B.sort_indices()
+    return BlockSystem(fields, blocks, uniform_rhs(nS + nG + nF, nrhs, seed),
+                       meta=dict(kind="fsi3d", n=n, layers=layers, seed=seed,
+                                 split=[0, 0, 1]))
+
+
 def _not_yet(*a, **k):
     raise NotImplementedError
 
 
-fsi3d = _not_yet
 lung3d = _not_yet
 request_trace = _not_yet

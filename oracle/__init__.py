@@ -99,6 +99,9 @@ def lib():
         L.orc_chebyshev.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                     C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_int32]
+        L.orc_color_nodes.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]
+        L.orc_sgs.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                              C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_splitmix64.argtypes = [C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         _lib = L
@@ -312,6 +315,26 @@ def chebyshev(A, lam, b, x0=None, ratio=30.0, boost=1.1, degree=2):
     x = np.zeros_like(b) if x0 is None else np.ascontiguousarray(x0, np.float64).copy()
     rc = lib().orc_chebyshev(A.shape[0], _p(p), _p(c), _p(v), lam, ratio, boost, degree, _p(b),
                              _p(x), 1 if x0 is None else 0)
+    if rc != 0:
+        raise OracleError(rc, lib().orc_last_error().decode())
+    return x
+
+
+def color_nodes(gptr, gadj, seed):
+    n = len(gptr) - 1
+    gptr = np.ascontiguousarray(gptr, np.int64)
+    gadj = np.ascontiguousarray(gadj, np.int32)
+    col = np.zeros(n, np.int32)
+    nc = lib().orc_color_nodes(n, _p(gptr), _p(gadj), seed, _p(col))
+    return col, nc
+
+
+def sgs(A, b, rhs, omega=1.0, steps=1, seed=0, x0=None):
+    p, c, v = _csr_arrays(A)
+    rhs = np.ascontiguousarray(rhs, np.float64)
+    x = np.zeros_like(rhs) if x0 is None else np.ascontiguousarray(x0, np.float64).copy()
+    rc = lib().orc_sgs(A.shape[0], _p(p), _p(c), _p(v), b, omega, steps, seed, _p(rhs), _p(x),
+                       1 if x0 is None else 0)
     if rc != 0:
         raise OracleError(rc, lib().orc_last_error().decode())
     return x

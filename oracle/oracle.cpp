@@ -307,6 +307,50 @@ static std::vector<int> aggregate(const Graph& G, const std::vector<int>& state,
   return agg;
 }
 
+// Greedy colouring of the node graph in Jones-Plassmann order with the same
+// (key, id) tuples as MIS-2: in each round, every uncoloured node whose tuple
+// is the largest among its uncoloured neighbours takes the smallest colour
+// not used by its already coloured neighbours.  All decisions of a round use
+// the colours at the start of the round, so no two neighbours share a colour.
+static std::vector<int> color_nodes(const Graph& G, uint64_t seed, int* ncolors) {
+  const int n = G.n;
+  std::vector<uint64_t> key(n);
+  for (int u = 0; u < n; ++u) key[u] = splitmix64(seed ^ splitmix64((uint64_t)u));
+  std::vector<int> color(n, -1);
+  int left = n, nc = 0;
+  while (left > 0) {
+    std::vector<int> pick;
+    for (int u = 0; u < n; ++u) {
+      if (color[u] >= 0) continue;
+      bool is_max = true;
+      for (int64_t p = G.ptr[u]; p < G.ptr[u + 1] && is_max; ++p) {
+        const int v = G.adj[p];
+        if (color[v] < 0 && (key[v] != key[u] ? key[v] > key[u] : v > u)) is_max = false;
+      }
+      if (is_max) pick.push_back(u);
+    }
+    std::vector<int> chosen(pick.size());
+    for (size_t t = 0; t < pick.size(); ++t) {
+      const int u = pick[t];
+      std::vector<char> used(G.ptr[u + 1] - G.ptr[u] + 2, 0);
+      for (int64_t p = G.ptr[u]; p < G.ptr[u + 1]; ++p) {
+        const int c = color[G.adj[p]];
+        if (c >= 0 && c < (int)used.size()) used[c] = 1;
+      }
+      int c = 0;
+      while (used[c]) ++c;
+      chosen[t] = c;
+    }
+    for (size_t t = 0; t < pick.size(); ++t) {
+      color[pick[t]] = chosen[t];
+      nc = std::max(nc, chosen[t] + 1);
+    }
+    left -= (int)pick.size();
+  }
+  *ncolors = nc;
+  return color;
+}
+
 // Tentative prolongator.  For aggregate a, B_a stacks the near-nullspace rows
 // of its dofs (nodes ascending, then dofs ascending), k columns.  Modified
 // Gram-Schmidt gives B_a = Q_a R_a with positive diagonal; Q_a becomes the
@@ -500,14 +544,62 @@ struct BlockMat {
 };
 
 // ----------------------------------------------------------- smoothers
-// Chebyshev polynomial smoother on D^-1 A over [lambda/ratio, boost*lambda]
-// (three-term recurrence, Saad "Iterative Methods for Sparse Linear Systems",
-// 2nd ed., Algorithm 12.1).  With zero_guess the first residual is b itself.
+// Field smoother, one of
+//  * Chebyshev polynomial on D^-1 A over [lambda/ratio, boost*lambda]
+//    (three-term recurrence, Saad "Iterative Methods for Sparse Linear
+//    Systems", 2nd ed., Algorithm 12.1); with zero_guess the first residual
+//    is b itself; degree 1 is damped Jacobi;
+//  * symmetric multicolour Gauss-Seidel with damping omega (the Gauss-Seidel
+//    family of smoothers the paper runs inside its AMG): nodes of one colour
+//    are relaxed together, colours forward then backward; the dofs of one
+//    node are updated together from the values before the node's update.
 struct Cheb {
   const Csr* A = nullptr;
   std::vector<double> dinv;
   double lambda = 0.0, lo = 0.0, hi = 0.0;
   int degree = 2;
+  int kind = 0;                       // 0 Chebyshev, 1 multicolour SGS
+  int bs = 1, steps = 1;
+  double omega = 1.0;
+  std::vector<std::vector<int>> color_nodes;   // nodes of each colour, ascending
+  void setup_sgs(const Csr* A_, int b, double om, int st, uint64_t seed) {
+    A = A_;
+    std::vector<double> d = diagonal(*A);
+    dinv.resize(d.size());
+    for (size_t i = 0; i < d.size(); ++i) {
+      if (d[i] == 0.0) throw Error(ESINGULAR, "Gauss-Seidel smoother: zero diagonal entry");
+      dinv[i] = 1.0 / d[i];
+    }
+    kind = 1;
+    bs = b;
+    omega = om;
+    steps = st;
+    Graph G = node_graph(*A, b);
+    int nc = 0;
+    std::vector<int> col = orc::color_nodes(G, seed, &nc);
+    color_nodes.assign(nc, {});
+    for (int u = 0; u < G.n; ++u) color_nodes[col[u]].push_back(u);
+  }
+  void relax_color(int c, const double* b, double* x) const {
+    std::vector<double> upd(bs);
+    for (int u : color_nodes[c]) {
+      for (int q = 0; q < bs; ++q) {
+        const int r = u * bs + q;
+        double s = b[r];
+        for (int64_t p = A->ptr[r]; p < A->ptr[r + 1]; ++p) s -= A->val[p] * x[A->col[p]];
+        upd[q] = omega * dinv[r] * s;
+      }
+      for (int q = 0; q < bs; ++q) x[u * bs + q] += upd[q];
+    }
+  }
+  void apply_sgs(const double* b, double* x, bool zero_guess) const {
+    if (zero_guess) std::fill(x, x + A->nr, 0.0);
+    const int nc = (int)color_nodes.size();
+    for (int st = 0; st < steps; ++st) {
+      for (int c = 0; c < nc; ++c) relax_color(c, b, x);
+      for (int c = nc - 1; c >= 0; --c) relax_color(c, b, x);
+    }
+  }
   void setup(const Csr* A_, double lam, const Opts& o) {
     A = A_;
     std::vector<double> d = diagonal(*A);
@@ -522,6 +614,7 @@ struct Cheb {
     degree = o.cheb_degree;
   }
   void apply(const double* b, double* x, bool zero_guess) const {
+    if (kind == 1) { apply_sgs(b, x, zero_guess); return; }
     const int n = A->nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     std::vector<double> r(n), d(n);
@@ -904,7 +997,8 @@ struct SimpleSolver : Solver {
 // in brackets: "BGS[sweeps=2,order=bwd](AMG)".
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1;
+  double omega = -1.0;
   std::vector<Spec> kids;
 };
 
@@ -928,12 +1022,20 @@ struct Parser {
         ws();
         if (s[i++] != '=') throw Error(EINVAL_, "spec: '=' expected");
         ws();
-        while (isalnum((unsigned char)s[i])) v += (char)tolower(s[i++]);
+        while (isalnum((unsigned char)s[i]) || s[i] == '.') v += (char)tolower(s[i++]);
         ws();
         if (k == "sweeps") sp.sweeps = atoi(v.c_str());
         else if (k == "order") sp.order = v == "fwd" ? 0 : v == "bwd" ? 1 : v == "sym" ? 2 : -9;
+        else if (k == "degree") sp.degree = atoi(v.c_str());
+        else if (k == "smoother") sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : -9;
+        else if (k == "omega") sp.omega = atof(v.c_str());
+        else if (k == "steps") sp.steps = atoi(v.c_str());
         else throw Error(EINVAL_, "spec: unknown parameter " + k);
-        if (sp.order == -9 || (k == "sweeps" && sp.sweeps < 1)) throw Error(EINVAL_, "spec: bad value " + v);
+        if (sp.smoother == -9 || (k == "omega" && !(sp.omega > 0.0 && sp.omega < 2.0)) ||
+            (k == "steps" && sp.steps < 1))
+          throw Error(EINVAL_, "spec: bad value " + v);
+        if (sp.order == -9 || (k == "sweeps" && sp.sweeps < 1) || (k == "degree" && sp.degree < 1))
+          throw Error(EINVAL_, "spec: bad value " + v);
         if (s[i] == ',') ++i;
       }
       if (s[i] != ']') throw Error(EINVAL_, "spec: ']' expected");
@@ -977,8 +1079,14 @@ static std::unique_ptr<Solver> build(Ctx& C, const Spec& sp, const BlockMat& A, 
                                      const std::vector<FieldDesc>& F);
 
 static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int f1,
-                                         const std::vector<FieldDesc>& F, const Spec* smoother) {
+                                         const std::vector<FieldDesc>& F, const Spec* smoother,
+                                         const Spec& amg) {
   auto S = std::make_unique<AmgSolver>();
+  Opts lo = C.o;                       // this hierarchy's smoother degree
+  if (amg.degree > 0) lo.cheb_degree = amg.degree;
+  const bool sgs = amg.smoother == 1;
+  const double omega = amg.omega > 0.0 ? amg.omega : 1.0;
+  const int steps = amg.steps > 0 ? amg.steps : 1;
   BlockMat sub = sub_blocks(A, f0, f1);
   std::vector<FieldDesc> Fs(F.begin() + f0, F.begin() + f1);
   for (int i = 0; i < sub.N; ++i)
@@ -997,7 +1105,10 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
     M.A = &L.A;
     M.cheb.resize(sub.N);
     const int nchb = M.kind == 1 ? sub.N - 1 : sub.N;
-    for (int i = 0; i < nchb; ++i) M.cheb[i].setup(L.A.at(i, i), L.lambda[i], C.o);
+    for (int i = 0; i < nchb; ++i) {
+      if (sgs) M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
+      else M.cheb[i].setup(L.A.at(i, i), L.lambda[i], lo);
+    }
     if (M.kind == 1) {
       if (sub.N < 2) throw Error(EINVAL_, "AMG(SIMPLE) needs at least two fields");
       M.ngroup1 = sub.N - 1;
@@ -1008,7 +1119,7 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
       else {
         std::vector<double> d = diagonal(M.Stilde), dinv(d.size());
         for (size_t r = 0; r < d.size(); ++r) dinv[r] = 1.0 / d[r];
-        M.schur_cheb.setup(&M.Stilde, power_lambda(M.Stilde, dinv, C.o.seed, C.o.power_its), C.o);
+        M.schur_cheb.setup(&M.Stilde, power_lambda(M.Stilde, dinv, C.o.seed, C.o.power_its), lo);
       }
     }
   }
@@ -1030,11 +1141,11 @@ static std::unique_ptr<Solver> build(Ctx& C, const Spec& sp, const BlockMat& A, 
   if (sp.name == "AMG") {
     if (sp.kids.empty()) {
       if (nf != 1) throw Error(EINVAL_, "spec: plain AMG needs a single field; use AMG(BGS) or AMG(SIMPLE)");
-      return build_amg(C, A, f0, f1, F, nullptr);
+      return build_amg(C, A, f0, f1, F, nullptr, sp);
     }
     if (sp.kids.size() != 1 || (sp.kids[0].name != "BGS" && sp.kids[0].name != "SIMPLE"))
       throw Error(EINVAL_, "spec: AMG level smoother must be BGS or SIMPLE");
-    return build_amg(C, A, f0, f1, F, &sp.kids[0]);
+    return build_amg(C, A, f0, f1, F, &sp.kids[0], sp);
   }
   if (sp.name == "BGS") {
     if (sp.kids.size() != 1) throw Error(EINVAL_, "spec: BGS takes one inner solver");
@@ -1456,5 +1567,33 @@ int orc_chebyshev(int32_t n, const int64_t* rowptr, const int32_t* col, const do
 }
 
 uint64_t orc_splitmix64(uint64_t x) { return orc::splitmix64(x); }
+
+// greedy colouring of a node graph; returns the number of colours
+int orc_color_nodes(int32_t nnode, const int64_t* gptr, const int32_t* gadj, uint64_t seed, int32_t* color) {
+  orc::Graph G;
+  G.n = nnode;
+  G.ptr.assign(gptr, gptr + nnode + 1);
+  G.adj.assign(gadj, gadj + gptr[nnode]);
+  int nc = 0;
+  std::vector<int> c = orc::color_nodes(G, seed, &nc);
+  std::copy(c.begin(), c.end(), color);
+  return nc;
+}
+
+// one application of the multicolour SGS smoother (for splitting-form tests)
+int orc_sgs(int32_t n, const int64_t* rowptr, const int32_t* col, const double* val, int32_t b, double omega,
+            int32_t steps, uint64_t seed, const double* rhs, double* x, int32_t zero_guess) {
+  try {
+    orc::Csr A;
+    A.nr = A.nc = n;
+    A.ptr.assign(rowptr, rowptr + n + 1);
+    A.col.assign(col, col + rowptr[n]);
+    A.val.assign(val, val + rowptr[n]);
+    orc::Cheb c;
+    c.setup_sgs(&A, b, omega, steps, seed);
+    c.apply(rhs, x, zero_guess != 0);
+    return 0;
+  } catch (orc::Error& e) { g_err = e.what(); return e.code; }
+}
 
 }  // extern "C"

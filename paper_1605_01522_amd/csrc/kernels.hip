@@ -8,6 +8,7 @@
 // taken in the same order on every run.
 
 #include <climits>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -196,10 +197,82 @@ template <> const float* csr_values<float>(const DCsr& A) {
   return A.val32.p;
 }
 
+// ---- launch timing ----
+namespace {
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  std::vector<int> key;
+  std::vector<double> bytes;
+  size_t used = 0;
+};
+Prof g_prof;
+}  // namespace
+
+void prof_enable(int on) {
+  if (on && g_prof.ev.empty()) {
+    g_prof.ev.resize(2 * 32768);
+    for (auto& e : g_prof.ev) NF_HIP(hipEventCreate(&e));
+  }
+  g_prof.on = on != 0;
+  g_prof.used = 0;
+  g_prof.key.clear();
+  g_prof.bytes.clear();
+}
+
+int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes) {
+  std::vector<int> keys;
+  std::vector<int64_t> cnt;
+  std::vector<double> t, b;
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    NF_HIP(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    float e = 0.f;
+    NF_HIP(hipEventElapsedTime(&e, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != g_prof.key[i]) ++k;
+    if (k == keys.size()) { keys.push_back(g_prof.key[i]); cnt.push_back(0); t.push_back(0); b.push_back(0); }
+    cnt[k] += 1;
+    t[k] += e;
+    b[k] += g_prof.bytes[i];
+  }
+  const int n = (int)keys.size() < max ? (int)keys.size() : max;
+  for (int k = 0; k < n; ++k) {
+    key[k] = keys[k];
+    count[k] = cnt[k];
+    ms[k] = t[k];
+    bytes[k] = b[k];
+  }
+  return (int)keys.size();
+}
+
+int prof_begin(hipStream_t s) {
+  if (!g_prof.on || g_prof.used >= g_prof.ev.size() / 2) return -1;
+  NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
+  return (int)g_prof.used;
+}
+void prof_end(int slot, hipStream_t s, int key, double bytes) {
+  if (slot < 0) return;
+  NF_HIP(hipEventRecord(g_prof.ev[2 * (size_t)slot + 1], s));
+  g_prof.key.push_back(key);
+  g_prof.bytes.push_back(bytes);
+  g_prof.used = (size_t)slot + 1;
+}
+
+// algorithmic bytes of one launch: matrix once, operand once, epilogue streams
+template <class T>
+static double spmv_bytes(SpmvMode mode, const DCsr& A) {
+  const double s = sizeof(T);
+  double b = (double)A.nnz * (s + 4) + 4.0 * (A.nr + 1) + s * A.nc;
+  const int streams = mode == SPMV_STORE ? 1 : mode == SPMV_CHEB ? 5 : 2;
+  return b + streams * s * A.nr;
+}
+
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
   if (A.nr <= 0) return;
   const T* val = csr_values<T>(A);
   const int G = spmv_group(A.nr, A.nnz);
+  const bool timed = g_prof.on && g_prof.used < g_prof.ev.size() / 2;
+  if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   switch (mode) {
     case SPMV_STORE: spmv_mode<SPMV_STORE, T>(G, A, a, val, s); break;
     case SPMV_RESID: spmv_mode<SPMV_RESID, T>(G, A, a, val, s); break;
@@ -207,6 +280,12 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
     case SPMV_SUB: spmv_mode<SPMV_SUB, T>(G, A, a, val, s); break;
     case SPMV_CHEB: spmv_mode<SPMV_CHEB, T>(G, A, a, val, s); break;
     case SPMV_DSCALE: spmv_mode<SPMV_DSCALE, T>(G, A, a, val, s); break;
+  }
+  if (timed) {
+    NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
+    g_prof.key.push_back(G * 100 + (int)mode * 10 + (sizeof(T) == 4 ? 1 : 0));
+    g_prof.bytes.push_back(spmv_bytes<T>(mode, A));
+    ++g_prof.used;
   }
 }
 template void spmv<double>(SpmvMode, const DCsr&, const SpmvArgs<double>&, hipStream_t);
@@ -646,6 +725,153 @@ int mis2_aggregate(int n, const int* gp, const int* ga, uint64_t seed, int* agg,
   NF_CHECK(e == 0, NFIELD_EINVAL, "aggregation: node without a phase-2 neighbour");
   return nagg;
 }
+
+// ================================================== multicolour Gauss-Seidel
+__global__ void k_color_pick(int n, const int* __restrict__ gp, const int* __restrict__ ga, const uint64_t* __restrict__ key,
+                             const int* __restrict__ color, int* __restrict__ flag, int* npick) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n) return;
+  int f = 0;
+  if (color[u] < 0) {
+    f = 1;
+    for (int p = gp[u]; p < gp[u + 1]; ++p) {
+      const int v = ga[p];
+      if (color[v] < 0 && tuple_greater(key, v, u)) { f = 0; break; }
+    }
+    if (f) atomicAdd(npick, 1);
+  }
+  flag[u] = f;
+}
+// smallest colour unused by the (already coloured) neighbours; colours < 256
+__global__ void k_color_assign(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* __restrict__ color,
+                               const int* __restrict__ flag, int* maxc, int* err) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n || !flag[u]) return;
+  uint64_t m[4] = {0, 0, 0, 0};
+  for (int p = gp[u]; p < gp[u + 1]; ++p) {
+    const int c = color[ga[p]];
+    if (c >= 0 && c < 256) m[c >> 6] |= 1ull << (c & 63);
+  }
+  int c = -1;
+  for (int w = 0; w < 4 && c < 0; ++w)
+    if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+  if (c < 0) { atomicOr(err, 1); c = 0; }
+  color[u] = c;
+  atomicMax(maxc, c + 1);
+}
+
+int color_nodes(int n, const int* gp, const int* ga, uint64_t seed, int* color, hipStream_t s) {
+  if (n == 0) return 0;
+  DBuf<uint64_t> key(n);
+  DBuf<int> flag(n), cnt(4);
+  const int g = cdiv(n, 256);
+  hipLaunchKernelGGL(k_mis_keys, dim3(g), dim3(256), 0, s, n, seed, key.p);
+  fill<int>(color, -1, n, s);
+  fill<int>(cnt.p, 0, 4, s);
+  int left = n, rounds = 0;
+  int h[4];
+  while (left > 0) {
+    NF_CHECK(++rounds <= n + 1, NFIELD_EINVAL, "colouring did not terminate");
+    fill<int>(cnt.p, 0, 1, s);
+    hipLaunchKernelGGL(k_color_pick, dim3(g), dim3(256), 0, s, n, gp, ga, key.p, color, flag.p, cnt.p);
+    hipLaunchKernelGGL(k_color_assign, dim3(g), dim3(256), 0, s, n, gp, ga, color, flag.p, cnt.p + 1, cnt.p + 2);
+    NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    NF_CHECK(h[0] > 0, NFIELD_EINVAL, "colouring round made no progress");
+    NF_CHECK(h[2] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+    left -= h[0];
+  }
+  return h[1];
+}
+
+// one group of G lanes per node; the node's b row sums are reduced first,
+// then lane 0 writes the b updates
+template <int G, class T>
+__global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
+                                                   const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinv, T omega,
+                                                   const T* __restrict__ rhs, T* __restrict__ x) {
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int t = gid / G, lane = gid & (G - 1);
+  if (t >= nnodes) return;
+  const int u = nodes[t];
+  T upd[MAXB];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    if (q >= b) break;
+    const int r = u * b + q;
+    T acc = 0;
+    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) acc += val[p] * x[col[p]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    upd[q] = omega * dinv[r] * (rhs[r] - acc);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+      if (q >= b) break;
+      x[u * b + q] += upd[q];
+    }
+  }
+}
+
+template <class T>
+void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega, const T* rhs, T* x,
+               hipStream_t s) {
+  if (nnodes <= 0) return;
+  const T* val = csr_values<T>(A);
+  const int G = spmv_group(A.nr, A.nnz);
+  const int blocks = cdiv((int64_t)nnodes * G, 256);
+  switch (G) {
+    case 2: hipLaunchKernelGGL((k_sgs_color<2, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+    case 4: hipLaunchKernelGGL((k_sgs_color<4, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+    case 8: hipLaunchKernelGGL((k_sgs_color<8, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+    case 16: hipLaunchKernelGGL((k_sgs_color<16, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+    case 32: hipLaunchKernelGGL((k_sgs_color<32, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+    default: hipLaunchKernelGGL((k_sgs_color<64, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
+  }
+}
+__global__ void k_color_traffic(int nnodes, const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+                                const int* __restrict__ col, int stamp, int* touched, unsigned long long* out) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nnodes) return;
+  const int u = nodes[t];
+  unsigned long long e = 0, d = 0;
+  for (int q = 0; q < b; ++q) {
+    const int r = u * b + q;
+    e += ptr[r + 1] - ptr[r];
+    for (int p = ptr[r]; p < ptr[r + 1]; ++p)
+      if (atomicExch(&touched[col[p]], stamp) != stamp) ++d;
+  }
+  atomicAdd(&out[0], e);
+  atomicAdd(&out[1], d);
+}
+void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,
+                   std::vector<int64_t>& ncols, hipStream_t s) {
+  const int nc = (int)off.size() - 1;
+  DBuf<int> touched(A.nc > 0 ? A.nc : 1);
+  DBuf<unsigned long long> out(2 * (nc > 0 ? nc : 1));
+  fill<int>(touched.p, -1, A.nc, s);
+  fill<unsigned long long>(out.p, 0ull, 2 * (int64_t)nc, s);
+  for (int c = 0; c < nc; ++c) {
+    const int m = off[c + 1] - off[c];
+    if (m > 0)
+      hipLaunchKernelGGL(k_color_traffic, dim3(cdiv(m, 256)), dim3(256), 0, s, m, nodes + off[c], b, A.ptr.p, A.col.p, c,
+                         touched.p, out.p + 2 * c);
+  }
+  std::vector<unsigned long long> h(2 * nc);
+  NF_HIP(hipMemcpyAsync(h.data(), out.p, sizeof(unsigned long long) * 2 * nc, hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  nnz.resize(nc);
+  ncols.resize(nc);
+  for (int c = 0; c < nc; ++c) {
+    nnz[c] = (int64_t)h[2 * c];
+    ncols[c] = (int64_t)h[2 * c + 1];
+  }
+}
+
+template void sgs_color<double>(const DCsr&, int, const int*, int, const double*, double, const double*, double*, hipStream_t);
+template void sgs_color<float>(const DCsr&, int, const int*, int, const float*, float, const float*, float*, hipStream_t);
 
 // ======================================================= tentative prolongator
 __global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {

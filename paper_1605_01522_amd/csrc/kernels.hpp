@@ -33,6 +33,16 @@ struct SpmvArgs {
 };
 // lanes per row chosen from the mean row length
 int spmv_group(int nr, int64_t nnz);
+
+// Optional per-launch timing of the SpMV kernels with HIP events on the
+// launch stream, keyed by (lanes per row, mode, FP32?), with the algorithmic
+// bytes of every launch.
+void prof_enable(int on);
+int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes);
+// bracket any other launch: slot = prof_begin(s) (-1 if not recording), then
+// prof_end(slot, s, key, bytes) after the launch
+int prof_begin(hipStream_t s);
+void prof_end(int slot, hipStream_t s, int key, double bytes);
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s);
 
 // ------------------------------------------------------------ reductions (FP64, deterministic)
@@ -53,6 +63,19 @@ void givens_step(int j, int m, const double* h1, const double* h2, const double*
                  double* H, double* cs, double* sn, double* g, double* hnorm_out, double* res_out, hipStream_t s);
 // y = H(0:k,0:k)^-1 g (upper triangular, after rotations)
 void backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
+
+// ------------------------------------------------------------ multicolour Gauss-Seidel
+// greedy colouring of a node graph (Jones-Plassmann order, splitmix64 keys);
+// returns the number of colours and fills color[node]
+int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int* color, hipStream_t s);
+// relax all nodes of one colour: x_r += omega dinv_r (b_r - A_r x) for the b
+// dofs of each listed node, all from the values before the node's update
+template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega,
+                                  const T* rhs, T* x, hipStream_t s);
+// per colour: stored entries of its rows and distinct columns they touch
+// (algorithmic bytes of one colour sweep)
+void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,
+                   std::vector<int64_t>& ncols, hipStream_t s);
 
 // ------------------------------------------------------------ setup
 int64_t exclusive_scan(const int* in, int* out, int64_t n, hipStream_t s);   // out[n] = total; returns total

@@ -61,7 +61,13 @@ struct Solver {
 // Algorithm 12.1).  Each step after the first is one fused kernel: residual,
 // direction update and iterate update.
 template <class T>
-struct ChebD {
+struct FieldSmootherD {
+  virtual ~FieldSmootherD() {}
+  virtual void apply(const T* b, T* x, bool zero_guess, hipStream_t s) = 0;
+};
+
+template <class T>
+struct ChebD : FieldSmootherD<T> {
   const DCsr* A = nullptr;
   DBuf<T> dinv, d, xt;
   double theta = 0, delta = 0, sigma = 0;
@@ -80,7 +86,7 @@ struct ChebD {
     sigma = theta / delta;
     degree = o.cheb_degree;
   }
-  void apply(const T* b, T* x, bool zero_guess, hipStream_t s) {
+  void apply(const T* b, T* x, bool zero_guess, hipStream_t s) override {
     const T* src;
     int k0;
     if (zero_guess) {
@@ -117,6 +123,70 @@ struct ChebD {
   }
 };
 
+// Symmetric multicolour Gauss-Seidel with damping omega: colours forward,
+// then backward; the nodes of one colour are relaxed by one kernel.
+template <class T>
+struct SgsD : FieldSmootherD<T> {
+  const DCsr* A = nullptr;
+  int b = 1, steps = 1, n = 0;
+  T omega = 1;
+  DBuf<T> dinv;
+  DBuf<int> nodes;                 // nodes grouped by colour
+  std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
+  void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s) {
+    A = A_;
+    b = b_;
+    n = A->nr;
+    omega = (T)om;
+    steps = st;
+    dinv.alloc(n);
+    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(dinv.p, dinv64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
+    DBuf<int> gptr, gadj;
+    int nn = 0;
+    node_graph(*A, b, gptr, gadj, &nn, s);
+    DBuf<int> color(nn > 0 ? nn : 1);
+    const int nc = color_nodes(nn, gptr.p, gadj.p, seed, color.p, s);
+    std::vector<int> hc(nn);
+    NF_HIP(hipMemcpyAsync(hc.data(), color.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    // group node ids by colour (ascending within a colour)
+    off.assign(nc + 1, 0);
+    for (int c : hc) off[c + 1]++;
+    for (int c = 0; c < nc; ++c) off[c + 1] += off[c];
+    std::vector<int> list(nn > 0 ? nn : 1), cur(off.begin(), off.end() - 1);
+    for (int u = 0; u < nn; ++u) list[cur[hc[u]]++] = u;
+    nodes.alloc(list.size());
+    NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
+    NF_HIP(hipStreamSynchronize(s));
+    // algorithmic bytes of each colour sweep: its rows' entries and row
+    // pointers, node list, right-hand side, D^-1, own x read and written,
+    // and every distinct column value it reads
+    std::vector<int64_t> cnnz, ccols;
+    color_traffic(*A, b, nodes.p, off, cnnz, ccols, s);
+    cbytes.resize(nc);
+    const double sz = sizeof(T);
+    for (int c = 0; c < nc; ++c) {
+      const double rows = (double)(off[c + 1] - off[c]) * b;
+      cbytes[c] = cnnz[c] * (sz + 4) + rows * (4 + 3 * sz) + 4.0 * (off[c + 1] - off[c]) + sz * ccols[c];
+    }
+  }
+  std::vector<double> cbytes;
+  void relax(int c, const T* rhs, T* x, hipStream_t s) {
+    const int slot = prof_begin(s);
+    sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, x, s);
+    prof_end(slot, s, spmv_group(A->nr, A->nnz) * 100 + 60 + (sizeof(T) == 4 ? 1 : 0), cbytes[c]);
+  }
+  void apply(const T* rhs, T* x, bool zero_guess, hipStream_t s) override {
+    if (zero_guess) fill<T>(x, (T)0, n, s);
+    const int nc = (int)off.size() - 1;
+    for (int st = 0; st < steps; ++st) {
+      for (int c = 0; c < nc; ++c) relax(c, rhs, x, s);
+      for (int c = nc - 1; c >= 0; --c) relax(c, rhs, x, s);
+    }
+  }
+};
+
 // One BGS sweep over fields [0, N) of a block matrix with per-field inner
 // solves: dd_i = S_i(res_i - sum_{j done} A_ij dd_j).
 template <class T, class Inner>
@@ -150,7 +220,7 @@ template <class T>
 struct LevelSmootherD {
   const BlockMat* A = nullptr;
   int order = 1;
-  std::vector<std::unique_ptr<ChebD<T>>> cheb;
+  std::vector<std::unique_ptr<FieldSmootherD<T>>> cheb;
   DBuf<T> r, d, t;
   void smooth(const T* b, T* x, bool zero_guess, hipStream_t s) {
     const int N = A->N;
@@ -280,7 +350,8 @@ struct SimpleSolverD : Solver<T> {
 // ================================================================== spec
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1;
+  double omega = -1.0;
   std::vector<Spec> kids;
 };
 
@@ -303,7 +374,7 @@ static Spec parse_spec(const std::string& str) {
         NF_CHECK(i < str.size() && str[i] == '=', NFIELD_EINVAL, "spec: '=' expected");
         ++i;
         ws();
-        while (i < str.size() && isalnum((unsigned char)str[i])) v += (char)tolower(str[i++]);
+        while (i < str.size() && (isalnum((unsigned char)str[i]) || str[i] == '.')) v += (char)tolower(str[i++]);
         ws();
         if (k == "sweeps") {
           sp.sweeps = atoi(v.c_str());
@@ -311,6 +382,18 @@ static Spec parse_spec(const std::string& str) {
         } else if (k == "order") {
           sp.order = v == "fwd" ? 0 : v == "bwd" ? 1 : v == "sym" ? 2 : -9;
           NF_CHECK(sp.order >= 0, NFIELD_EINVAL, "spec: order must be fwd, bwd or sym");
+        } else if (k == "degree") {
+          sp.degree = atoi(v.c_str());
+          NF_CHECK(sp.degree >= 1, NFIELD_EINVAL, "spec: degree must be >= 1");
+        } else if (k == "smoother") {
+          sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : -9;
+          NF_CHECK(sp.smoother >= 0, NFIELD_EINVAL, "spec: smoother must be cheb or sgs");
+        } else if (k == "omega") {
+          sp.omega = atof(v.c_str());
+          NF_CHECK(sp.omega > 0.0 && sp.omega < 2.0, NFIELD_EINVAL, "spec: omega must be in (0, 2)");
+        } else if (k == "steps") {
+          sp.steps = atoi(v.c_str());
+          NF_CHECK(sp.steps >= 1, NFIELD_EINVAL, "spec: steps must be >= 1");
         } else {
           throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
         }
@@ -371,6 +454,8 @@ struct nfield_ctx {
   std::vector<std::unique_ptr<nf::BlockMat>> owned;
   std::unique_ptr<nf::Solver<double>> root64;
   std::unique_ptr<nf::Solver<float>> root32;
+  nf::Spec spec;
+  std::vector<std::shared_ptr<nf::DBuf<int>>> gpos;   // per block: entry -> position in Aglob
   nf::DBuf<float> r32, z32;
   size_t bytes = 0;
   double setup_s = 0.0;
@@ -391,7 +476,12 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
 
 template <class T>
 static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, const std::vector<FieldDev>& F, int f0, int f1,
-                                            const Spec* smoother, hipStream_t s) {
+                                            const Spec* smoother, const Spec& amg, hipStream_t s) {
+  Opts lo = C.o;   // smoother polynomial degree of this hierarchy
+  if (amg.degree > 0) lo.cheb_degree = amg.degree;
+  const bool sgs = amg.smoother == 1;
+  const double omega = amg.omega > 0.0 ? amg.omega : 1.0;
+  const int steps = amg.steps > 0 ? amg.steps : 1;
   BlockMat sub = A.sub(f0, f1);
   std::vector<FieldDev> Fs(F.begin() + f0, F.begin() + f1);
   NF_CHECK(!smoother || smoother->name == "BGS", NFIELD_EINVAL, "spec: only BGS level smoothers are available");
@@ -426,9 +516,15 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     M.order = smoother && smoother->order >= 0 ? smoother->order : C.o.order;
     for (int i = 0; i < sub.N; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
-      auto ch = std::make_unique<ChebD<T>>();
-      ch->setup(L.A.at(i, i), L.dinv[i]->p, L.lambda[i], C.o, s);
-      M.cheb.push_back(std::move(ch));
+      if (sgs) {
+        auto g = std::make_unique<SgsD<T>>();
+        g->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s);
+        M.cheb.push_back(std::move(g));
+      } else {
+        auto ch = std::make_unique<ChebD<T>>();
+        ch->setup(L.A.at(i, i), L.dinv[i]->p, L.lambda[i], lo, s);
+        M.cheb.push_back(std::move(ch));
+      }
     }
     if (sub.N > 1) {
       M.r.alloc(n);
@@ -459,10 +555,10 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
   if (sp.name == "AMG") {
     if (sp.kids.empty()) {
       NF_CHECK(nf_ == 1, NFIELD_EINVAL, "spec: plain AMG needs a single field; use AMG(BGS)");
-      return build_amg<T>(C, A, F, f0, f1, nullptr, s);
+      return build_amg<T>(C, A, F, f0, f1, nullptr, sp, s);
     }
     NF_CHECK(sp.kids.size() == 1, NFIELD_EINVAL, "spec: AMG takes one level smoother");
-    return build_amg<T>(C, A, F, f0, f1, &sp.kids[0], s);
+    return build_amg<T>(C, A, F, f0, f1, &sp.kids[0], sp, s);
   }
   if (sp.name == "BGS") {
     NF_CHECK(sp.kids.size() == 1, NFIELD_EINVAL, "spec: BGS takes one inner solver");
@@ -713,7 +809,8 @@ static void upload_block(const nfield_csr& c, int nr, int nc, DCsr& D, hipStream
 
 // all blocks merged into one CSR: block row i, blocks j ascending, column
 // offsets of the fields; built on the host from the (validated) inputs
-static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>& size, DCsr& G, hipStream_t s) {
+static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>& size, DCsr& G,
+                         std::vector<std::shared_ptr<DBuf<int>>>& gpos, hipStream_t s) {
   std::vector<int> o(N + 1, 0);
   for (int i = 0; i < N; ++i) o[i + 1] = o[i] + size[i];
   const int n = o[N];
@@ -731,6 +828,12 @@ static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>
   NF_CHECK(nnz < INT32_MAX, NFIELD_ENOMEM, "system has more than 2^31 entries");
   std::vector<int> col(nnz > 0 ? nnz : 1);
   std::vector<double> val(nnz > 0 ? nnz : 1);
+  std::vector<std::vector<int>> pos((size_t)N * N);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const nfield_csr& c = blocks[(size_t)i * N + j];
+      if (c.nnz > 0 && c.val) pos[(size_t)i * N + j].resize(c.nnz);
+    }
   int64_t q = 0;
   for (int i = 0; i < N; ++i)
     for (int r = 0; r < size[i]; ++r)
@@ -740,9 +843,16 @@ static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>
         for (int64_t p = c.rowptr[r]; p < c.rowptr[r + 1]; ++p) {
           col[q] = c.colind[p] + o[j];
           val[q] = c.val[p];
+          pos[(size_t)i * N + j][p] = (int)q;
           ++q;
         }
       }
+  gpos.assign((size_t)N * N, nullptr);
+  for (size_t b = 0; b < pos.size(); ++b) {
+    if (pos[b].empty()) continue;
+    gpos[b] = std::make_shared<DBuf<int>>(pos[b].size());
+    NF_HIP(hipMemcpyAsync(gpos[b]->p, pos[b].data(), sizeof(int) * pos[b].size(), hipMemcpyHostToDevice, s));
+  }
   G.nr = G.nc = n;
   G.nnz = nnz;
   G.ptr.alloc(n + 1);
@@ -752,6 +862,30 @@ static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>
   NF_HIP(hipMemcpyAsync(G.col.p, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice, s));
   NF_HIP(hipMemcpyAsync(G.val.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
   NF_HIP(hipStreamSynchronize(s));
+}
+
+// (re)build the preconditioner tree from the device-resident blocks
+static void build_tree(nfield_ctx& C, hipStream_t s) {
+  C.root64.reset();
+  C.root32.reset();
+  C.hiers.clear();
+  C.owned.clear();
+  if (C.o.hier_fp32) {
+    for (auto& b : C.A.blk)
+      if (b) make_fp32(*b, s);
+    C.root32 = build<float>(C, C.spec, C.A, C.F, 0, C.N, s);
+    if (!C.r32.p) {
+      C.r32.alloc(C.Aglob.nr);
+      C.z32.alloc(C.Aglob.nr);
+    }
+  } else {
+    C.root64 = build<double>(C, C.spec, C.A, C.F, 0, C.N, s);
+  }
+}
+
+__global__ void k_scatter_vals(const double* v, const int* pos, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[pos[i]] = v[i];
 }
 
 }  // namespace nf
@@ -877,15 +1011,9 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
         upload_block(c, C->A.size[i], C->A.size[j], *D, s);
         C->A.blk[(size_t)i * nfields + j] = D;
       }
-    merge_global(blocks, nfields, C->A.size, C->Aglob, s);
-    if (C->o.hier_fp32) {
-      prepare_fp32(C->A, s);
-      C->root32 = build<float>(*C, sp, C->A, C->F, 0, nfields, s);
-      C->r32.alloc(C->Aglob.nr);
-      C->z32.alloc(C->Aglob.nr);
-    } else {
-      C->root64 = build<double>(*C, sp, C->A, C->F, 0, nfields, s);
-    }
+    merge_global(blocks, nfields, C->A.size, C->Aglob, C->gpos, s);
+    C->spec = sp;
+    build_tree(*C, s);
     NF_HIP(hipStreamSynchronize(s));
     NF_HIP(hipGetLastError());
     C->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -982,6 +1110,55 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
     g_acct = prev;
     return fail(e);
   }
+}
+
+nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const double* val, int32_t on_device,
+                                   void* hip_stream) {
+  if (!ctx || !val || i < 0 || j < 0 || i >= ctx->N || j >= ctx->N || !ctx->A.at(i, j)) {
+    g_err = "nfield_update_values: bad argument or zero block";
+    return NFIELD_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    DCsr& B = *ctx->A.blk[(size_t)i * ctx->N + j];
+    NF_HIP(hipMemcpyAsync(B.val.p, val, sizeof(double) * B.nnz, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    const auto& pos = ctx->gpos[(size_t)i * ctx->N + j];
+    if (B.nnz > 0)
+      hipLaunchKernelGGL(k_scatter_vals, dim3((unsigned)((B.nnz + 255) / 256)), dim3(256), 0, s, B.val.p, pos->p, B.nnz,
+                         ctx->Aglob.val.p);
+    NF_HIP(hipGetLastError());
+    if (!on_device) NF_HIP(hipStreamSynchronize(s));
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    return fail(e);
+  }
+}
+
+nfield_status nfield_rebuild(nfield_ctx* ctx, void* hip_stream) {
+  if (!ctx) { g_err = "nfield_rebuild: null context"; return NFIELD_EINVAL; }
+  hipStream_t s = (hipStream_t)hip_stream;
+  size_t* prev = g_acct;
+  g_acct = &ctx->bytes;
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    build_tree(*ctx, s);
+    NF_HIP(hipStreamSynchronize(s));
+    NF_HIP(hipGetLastError());
+    ctx->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    g_acct = prev;
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    g_acct = prev;
+    return fail(e);
+  }
+}
+
+void nfield_prof_enable(int32_t on) {
+  try { prof_enable(on); } catch (NfError& e) { g_err = e.what(); }
+}
+
+int32_t nfield_prof_read(int32_t max, int32_t* key, int64_t* count, double* ms, double* bytes) {
+  try { return prof_read(max, key, count, ms, bytes); } catch (NfError& e) { g_err = e.what(); return -1; }
 }
 
 // ---------------------------------------------------------------- inspection

@@ -50,6 +50,7 @@ class nfield_stats(C.Structure):
 # every symbol include/nfield.h declares
 EXPORTS = ["nfield_default_opts", "nfield_default_solve_opts", "nfield_setup",
            "nfield_precond_apply", "nfield_matvec", "nfield_gmres_solve",
+           "nfield_update_values", "nfield_rebuild", "nfield_prof_enable", "nfield_prof_read",
            "nfield_footprint_bytes", "nfield_size", "nfield_destroy", "nfield_strerror",
            "nfield_last_error", "nfield_hier_count", "nfield_hier_nlevels", "nfield_hier_nfields",
            "nfield_hier_size", "nfield_hier_lambda", "nfield_hier_matrix", "nfield_hier_aggregates"]
@@ -77,6 +78,13 @@ def lib():
     L.nfield_matvec.restype = C.c_int
     L.nfield_gmres_solve.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.nfield_gmres_solve.restype = C.c_int
+    L.nfield_update_values.argtypes = [vp, i32, i32, vp, i32, vp]
+    L.nfield_update_values.restype = C.c_int
+    L.nfield_rebuild.argtypes = [vp, vp]
+    L.nfield_rebuild.restype = C.c_int
+    L.nfield_prof_enable.argtypes = [i32]
+    L.nfield_prof_read.argtypes = [i32, vp, vp, vp, vp]
+    L.nfield_prof_read.restype = i32
     L.nfield_footprint_bytes.argtypes = [vp]
     L.nfield_footprint_bytes.restype = C.c_size_t
     L.nfield_size.argtypes = [vp]
@@ -227,6 +235,57 @@ def nfield_gmres_solve(ctx, b, x, restart=50, maxit=1000, flexible=0, rtol=1e-8,
     return rc, stats
 
 
+def nfield_update_values(ctx, i, j, val, stream=None):
+    """val: a float64 CUDA tensor (device copy) or a numpy array (host copy)."""
+    import torch
+    if isinstance(val, torch.Tensor):
+        ptr, on_dev = C.c_void_p(val.data_ptr()), 1
+        if not (val.is_cuda and val.dtype == torch.float64 and val.is_contiguous()):
+            raise TypeError("val must be a contiguous float64 CUDA tensor")
+    else:
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        ptr, on_dev = _p(val), 0
+    rc = lib().nfield_update_values(ctx, i, j, ptr, on_dev, _stream(stream))
+    if rc != 0:
+        raise NFieldError(rc, "nfield_update_values")
+
+
+def nfield_rebuild(ctx, stream=None):
+    rc = lib().nfield_rebuild(ctx, _stream(stream))
+    if rc != 0:
+        raise NFieldError(rc, "nfield_rebuild")
+
+
+def nfield_prof_enable(on):
+    lib().nfield_prof_enable(1 if on else 0)
+
+
+SPMV_MODES = {0: "store", 1: "resid", 2: "add", 3: "sub", 4: "cheb", 5: "dscale", 6: "sgs"}
+# kernel names as the profiler prints them
+KERNEL_NAMES = {m: f"k_spmv<{{lanes}}, {m}, {{t}}>" for m in range(6)}
+KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {t}>"
+
+
+def kernel_name(p):
+    mode = [k for k, v in SPMV_MODES.items() if v == p["mode"]][0]
+    return KERNEL_NAMES[mode].format(lanes=p["lanes"], t="float" if p["fp32"] else "double")
+
+
+def nfield_prof_read(max_keys=64):
+    """Per SpMV kernel variant: dict(lanes, mode, fp32, launches, ms, bytes)."""
+    key = np.zeros(max_keys, np.int32)
+    cnt = np.zeros(max_keys, np.int64)
+    ms = np.zeros(max_keys, np.float64)
+    by = np.zeros(max_keys, np.float64)
+    n = lib().nfield_prof_read(max_keys, _p(key), _p(cnt), _p(ms), _p(by))
+    out = []
+    for k in range(min(n, max_keys)):
+        out.append(dict(lanes=int(key[k]) // 100, mode=SPMV_MODES[(int(key[k]) // 10) % 10],
+                        fp32=bool(key[k] % 10), launches=int(cnt[k]), ms=float(ms[k]),
+                        bytes=float(by[k])))
+    return out
+
+
 def nfield_footprint_bytes(ctx):
     return lib().nfield_footprint_bytes(ctx)
 
@@ -279,6 +338,12 @@ class NField:
 
     def footprint_bytes(self):
         return nfield_footprint_bytes(self.ctx)
+
+    def update_values(self, i, j, val, stream=None):
+        nfield_update_values(self.ctx, i, j, val, stream)
+
+    def rebuild(self, stream=None):
+        nfield_rebuild(self.ctx, stream)
 
     # ---- hierarchy inspection (host copies) ----
     def hier_count(self):

@@ -105,7 +105,9 @@ def test_mono_amg_hierarchy_parity(dev):
 
 # ----------------------------------------------------- preconditioner apply
 SPECS = ["BGS(AMG)", "BGS[order=fwd](AMG)", "BGS[sweeps=3,order=sym](AMG)", "BGS(LU)",
-         "SIMPLE(AMG;AMG)", "SIMPLE(AMG;LU)", "AMG(BGS)", "AMG(BGS[order=fwd])"]
+         "SIMPLE(AMG;AMG)", "SIMPLE(AMG;LU)", "AMG(BGS)", "AMG(BGS[order=fwd])",
+         "BGS(AMG[smoother=sgs,omega=0.8])", "BGS(AMG[smoother=sgs,omega=1.1,steps=2])",
+         "AMG[smoother=sgs,omega=0.9](BGS)", "BGS(AMG[degree=3])"]
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -209,3 +211,88 @@ def test_singular_inputs(dev):
     with pytest.raises(nfield.NFieldError) as e:
         _gpu(nfgen.BlockSystem(s.fields, bad, s.rhs), "BGS(AMG)")
     assert e.value.code == -3
+
+
+# ------------------------------------------------- 3-field FSI-like system
+FSI_SPEC = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
+FSI_OPTS = dict(split=[0, 0, 1])
+
+
+@pytest.mark.parametrize("n,layers", [(6, 2), (12, 3)])
+def test_fsi_hierarchy_precond_and_solution_parity(dev, n, layers):
+    _say(f"case fsi3d n={n} layers={layers}")
+    s = nfgen.fsi3d(n=n, layers=layers, seed=n)
+    o = oracle.Oracle(s.fields, s.blocks, FSI_SPEC, **FSI_OPTS)
+    g = _gpu(s, FSI_SPEC, **FSI_OPTS)
+    _compare_hierarchies(g, o)
+    r = np.random.default_rng(n).standard_normal((2, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k])
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8, maxit=1000)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=1000)
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    assert st[0]["status"] == 0 and res < 1e-8
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert abs(st[0]["iters"] - so["iters"]) <= 2, (st[0]["iters"], so["iters"])
+
+
+@pytest.fixture(scope="module")
+def fsi_full():
+    s = nfgen.fsi3d(n=40, layers=8, seed=0)
+    return s
+
+
+def test_fsi_full_size_sampled_parity(dev, fsi_full):
+    """The benchmarked 0.49M-dof system: SpMV rows sampled one by one, every
+    aggregate of the finest level of every hierarchy bit-exact, one
+    preconditioner application against the oracle, and the solve's true
+    residual."""
+    _say("case fsi3d full size (n=40, layers=8)")
+    s = fsi_full
+    g = _gpu(s, FSI_SPEC, **FSI_OPTS)
+    A = s.assembled()
+    rng = np.random.default_rng(11)
+    xv = rng.standard_normal(s.n)
+    y = g.matvec(torch.tensor(xv, device=dev)).cpu().numpy()
+    rows = rng.choice(s.n, 2000, replace=False)
+    for r in rows:
+        lo, hi = A.indptr[r], A.indptr[r + 1]
+        ref = float(np.dot(A.data[lo:hi], xv[A.indices[lo:hi]]))
+        bound = 1e-12 * float(np.dot(np.abs(A.data[lo:hi]), np.abs(xv[A.indices[lo:hi]])))
+        assert abs(y[r] - ref) <= bound, r
+    o = oracle.Oracle(s.fields, s.blocks, FSI_SPEC, **FSI_OPTS)
+    assert g.hier_count() == o.hier_count()
+    for h in range(o.hier_count()):
+        assert g.nlevels(h) == o.nlevels(h)
+        assert np.array_equal(g.aggregates(h, 0), o.aggregates(h, 0)), h
+        for l in range(o.nlevels(h)):
+            assert g.level_size(h, l) == o.level_size(h, l)
+    r = rng.standard_normal(s.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-9 * np.linalg.norm(zo)
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8, maxit=1000)
+    x = x.cpu().numpy()
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    _say(f"full-size fsi3d: iters {st[0]['iters']} relres {res:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8
+
+
+def test_rebuild_after_value_update(dev):
+    _say("case rebuild after update_values")
+    s = nfgen.tsi2d(nel=20, seed=3)
+    g = _gpu(s, "BGS(AMG)", **TSI_OPTS)
+    s2 = nfgen.tsi2d(nel=20, seed=3, E=2.0, alpha=3e-2)
+    for i in range(2):
+        for j in range(2):
+            g.update_values(i, j, torch.tensor(s2.blocks[i][j].data, device=dev))
+    g.rebuild()
+    o = oracle.Oracle(s2.fields, s2.blocks, "BGS(AMG)", **TSI_OPTS)
+    _compare_hierarchies(g, o)
+    x, st = g.gmres_solve(torch.tensor(s2.rhs[0], device=dev))
+    xo, _ = o.gmres(s2.rhs[0])
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-6 * np.linalg.norm(xo)

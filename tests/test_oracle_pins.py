@@ -468,3 +468,61 @@ def test_errors():
     assert e.value.code == -5
     x, st = o.gmres(s.rhs[0], maxit=1, rtol=1e-14)
     assert st["status"] == 1 and st["iters"] == 1
+
+
+# --------------------------------------------------- multicolour Gauss-Seidel
+@pytest.mark.parametrize("name,make", GRAPHS)
+def test_coloring_valid_and_matches_definition(name, make):
+    gp, ga = make()
+    n = len(gp) - 1
+    seed = 3
+    col, nc = oracle.color_nodes(gp, ga, seed)
+    adj, _ = _dist2(gp, ga, n)
+    assert col.min() == 0 and col.max() == nc - 1
+    i, j = np.nonzero(adj)
+    assert np.all(col[i] != col[j])
+    # re-derive the rounds by brute force from the definition
+    key = [oracle.splitmix64(seed ^ oracle.splitmix64(u)) for u in range(n)]
+    ref = np.full(n, -1)
+    while (ref < 0).any():
+        pick = [u for u in range(n) if ref[u] < 0 and all(
+            (key[v], v) < (key[u], u) for v in np.nonzero(adj[u])[0] if ref[v] < 0)]
+        new = {}
+        for u in pick:
+            used = {ref[v] for v in np.nonzero(adj[u])[0] if ref[v] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            new[u] = c
+        for u, c in new.items():
+            ref[u] = c
+    assert np.array_equal(col, ref)
+
+
+@pytest.mark.parametrize("field,b,omega", [(0, 2, 0.69), (1, 1, 1.0), (0, 2, 1.3)])
+def test_sgs_equals_colour_splitting(field, b, omega):
+    """One symmetric sweep = the forward then backward SOR splittings in which
+    'earlier' means an earlier colour and a node's own dofs count as not yet
+    updated."""
+    s = nfgen.tsi2d(nel=5, seed=1)
+    A = s.blocks[field][field]
+    gp, ga = oracle.node_graph(A, b)
+    col, nc = oracle.color_nodes(gp, ga, 0)
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    cr = np.repeat(col, b)
+    D = np.diag(np.diag(Ad))
+    Lf = np.where(cr[None, :] < cr[:, None], Ad, 0.0)
+    Lb = np.where(cr[None, :] > cr[:, None], Ad, 0.0)
+    rng = np.random.default_rng(2)
+    rhs, x0 = rng.standard_normal(n), rng.standard_normal(n)
+    Uf = Ad - D - Lf
+    Ub = Ad - D - Lb
+    x1 = np.linalg.solve(D / omega + Lf, rhs + (D / omega - D - Uf) @ x0)
+    x2 = np.linalg.solve(D / omega + Lb, rhs + (D / omega - D - Ub) @ x1)
+    got = oracle.sgs(A, b, rhs, omega=omega, steps=1, seed=0, x0=x0)
+    assert np.abs(got - x2).max() < 1e-11 * np.abs(x2).max()
+    # zero initial guess
+    y1 = np.linalg.solve(D / omega + Lf, rhs)
+    y2 = np.linalg.solve(D / omega + Lb, rhs + (D / omega - D - Ub) @ y1)
+    assert np.abs(oracle.sgs(A, b, rhs, omega=omega) - y2).max() < 1e-11 * np.abs(y2).max()
