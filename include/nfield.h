@@ -162,8 +162,11 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
 /* Launch timing of the SpMV kernels (HIP events on the launch stream).
  * nfield_prof_enable(1) clears and starts recording, 0 stops.  prof_read
  * returns the number of kernel variants and fills up to max entries: key =
- * 100*lanes_per_row + 10*mode + (1 if FP32), launches, total milliseconds,
- * total algorithmic bytes (matrix once, operand once, epilogue streams). */
+ * ((16*lanes_per_row + rows_per_node_group)*10 + kind)*10 + (1 if FP32),
+ * kind 0-5 = SpMV epilogue (store, residual, add, subtract, Chebyshev step,
+ * diagonal scaling), 6 = Gauss-Seidel colour sweep (timed per sweep, counted
+ * per colour launch); launches, total milliseconds, total algorithmic bytes
+ * (matrix once, operand once, epilogue streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);
 

@@ -204,6 +204,7 @@ struct Prof {
   std::vector<hipEvent_t> ev;   // pairs
   std::vector<int> key;
   std::vector<double> bytes;
+  std::vector<int> count;       // launches bracketed by each pair
   size_t used = 0;
 };
 Prof g_prof;
@@ -218,7 +219,10 @@ void prof_enable(int on) {
   g_prof.used = 0;
   g_prof.key.clear();
   g_prof.bytes.clear();
+  g_prof.count.clear();
 }
+
+bool prof_recording() { return g_prof.on; }
 
 int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes) {
   std::vector<int> keys;
@@ -231,7 +235,7 @@ int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes) {
     size_t k = 0;
     while (k < keys.size() && keys[k] != g_prof.key[i]) ++k;
     if (k == keys.size()) { keys.push_back(g_prof.key[i]); cnt.push_back(0); t.push_back(0); b.push_back(0); }
-    cnt[k] += 1;
+    cnt[k] += g_prof.count[i];
     t[k] += e;
     b[k] += g_prof.bytes[i];
   }
@@ -250,11 +254,12 @@ int prof_begin(hipStream_t s) {
   NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   return (int)g_prof.used;
 }
-void prof_end(int slot, hipStream_t s, int key, double bytes) {
+void prof_end(int slot, hipStream_t s, int key, double bytes, int count) {
   if (slot < 0) return;
   NF_HIP(hipEventRecord(g_prof.ev[2 * (size_t)slot + 1], s));
   g_prof.key.push_back(key);
   g_prof.bytes.push_back(bytes);
+  g_prof.count.push_back(count);
   g_prof.used = (size_t)slot + 1;
 }
 
@@ -283,8 +288,9 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
   }
   if (timed) {
     NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
-    g_prof.key.push_back(G * 100 + (int)mode * 10 + (sizeof(T) == 4 ? 1 : 0));
+    g_prof.key.push_back(((G * 16) * 10 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
     g_prof.bytes.push_back(spmv_bytes<T>(mode, A));
+    g_prof.count.push_back(1);
     ++g_prof.used;
   }
 }
@@ -727,109 +733,122 @@ int mis2_aggregate(int n, const int* gp, const int* ga, uint64_t seed, int* agg,
 }
 
 // ================================================== multicolour Gauss-Seidel
-__global__ void k_color_pick(int n, const int* __restrict__ gp, const int* __restrict__ ga, const uint64_t* __restrict__ key,
-                             const int* __restrict__ color, int* __restrict__ flag, int* npick) {
+// One round of greedy colouring in node order: an uncoloured node whose
+// smaller-index neighbours are all coloured takes the smallest colour they do
+// not use.  The result equals the sequential greedy colouring in node order
+// (a node's colour depends only on its smaller neighbours' final colours); a
+// node that sees a neighbour coloured earlier in the same round merely
+// finishes a round sooner.
+__global__ void k_color_round(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* color, int* left,
+                              int* err) {
   const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= n) return;
-  int f = 0;
-  if (color[u] < 0) {
-    f = 1;
-    for (int p = gp[u]; p < gp[u + 1]; ++p) {
-      const int v = ga[p];
-      if (color[v] < 0 && tuple_greater(key, v, u)) { f = 0; break; }
-    }
-    if (f) atomicAdd(npick, 1);
-  }
-  flag[u] = f;
-}
-// smallest colour unused by the (already coloured) neighbours; colours < 256
-__global__ void k_color_assign(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* __restrict__ color,
-                               const int* __restrict__ flag, int* maxc, int* err) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= n || !flag[u]) return;
+  if (u >= n || __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
   uint64_t m[4] = {0, 0, 0, 0};
   for (int p = gp[u]; p < gp[u + 1]; ++p) {
-    const int c = color[ga[p]];
-    if (c >= 0 && c < 256) m[c >> 6] |= 1ull << (c & 63);
+    const int v = ga[p];
+    if (v >= u) continue;
+    const int c = __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c < 0) {
+      atomicAdd(left, 1);
+      return;
+    }
+    if (c < 256) m[c >> 6] |= 1ull << (c & 63);
   }
   int c = -1;
   for (int w = 0; w < 4 && c < 0; ++w)
     if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
   if (c < 0) { atomicOr(err, 1); c = 0; }
-  color[u] = c;
-  atomicMax(maxc, c + 1);
+  __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__global__ void k_max_int(const int* x, int n, int* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) atomicMax(out, x[i] + 1);
 }
 
-int color_nodes(int n, const int* gp, const int* ga, uint64_t seed, int* color, hipStream_t s) {
+int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* color, hipStream_t s) {
   if (n == 0) return 0;
-  DBuf<uint64_t> key(n);
-  DBuf<int> flag(n), cnt(4);
+  constexpr int K = 16;                 // rounds per host check
+  DBuf<int> cnt(K + 2);
   const int g = cdiv(n, 256);
-  hipLaunchKernelGGL(k_mis_keys, dim3(g), dim3(256), 0, s, n, seed, key.p);
   fill<int>(color, -1, n, s);
-  fill<int>(cnt.p, 0, 4, s);
-  int left = n, rounds = 0;
-  int h[4];
-  while (left > 0) {
-    NF_CHECK(++rounds <= n + 1, NFIELD_EINVAL, "colouring did not terminate");
-    fill<int>(cnt.p, 0, 1, s);
-    hipLaunchKernelGGL(k_color_pick, dim3(g), dim3(256), 0, s, n, gp, ga, key.p, color, flag.p, cnt.p);
-    hipLaunchKernelGGL(k_color_assign, dim3(g), dim3(256), 0, s, n, gp, ga, color, flag.p, cnt.p + 1, cnt.p + 2);
+  int rounds = 0;
+  while (true) {
+    fill<int>(cnt.p, 0, K + 2, s);
+    for (int r = 0; r < K; ++r)
+      hipLaunchKernelGGL(k_color_round, dim3(g), dim3(256), 0, s, n, gp, ga, color, cnt.p + r, cnt.p + K);
+    rounds += K;
+    int h[K + 2];
     NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
-    NF_CHECK(h[0] > 0, NFIELD_EINVAL, "colouring round made no progress");
-    NF_CHECK(h[2] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
-    left -= h[0];
+    NF_CHECK(h[K] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+    if (h[K - 1] == 0) break;
+    NF_CHECK(rounds <= n + K, NFIELD_EINVAL, "colouring did not terminate");
   }
-  return h[1];
+  fill<int>(cnt.p, 0, 1, s);
+  hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p);
+  int nc = 0;
+  NF_HIP(hipMemcpyAsync(&nc, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  return nc;
 }
 
-// one group of G lanes per node; the node's b row sums are reduced first,
-// then lane 0 writes the b updates
-template <int G, class T>
+// One group of B2*G lanes per node (B2 = b rounded up to a power of two,
+// G lanes per row, B2*G <= 64 so the group lies inside one wavefront): every
+// row of the node is summed at once, and the updates are written after all
+// of the group's loads have completed, so the node's dofs are relaxed
+// together from their old values.
+template <int G, int B2, class T>
 __global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
                                                    const int* __restrict__ ptr, const int* __restrict__ col,
                                                    const T* __restrict__ val, const T* __restrict__ dinv, T omega,
                                                    const T* __restrict__ rhs, T* __restrict__ x) {
+  constexpr int NG = G * B2;
   const int gid = blockIdx.x * 256 + threadIdx.x;
-  const int t = gid / G, lane = gid & (G - 1);
+  const int t = gid / NG, sub = gid % NG;
+  const int q = sub / G, lane = sub % G;
   if (t >= nnodes) return;
   const int u = nodes[t];
-  T upd[MAXB];
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    if (q >= b) break;
-    const int r = u * b + q;
-    T acc = 0;
+  const int r = u * b + q;
+  T acc = 0;
+  if (q < b)
     for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) acc += val[p] * x[col[p]];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    upd[q] = omega * dinv[r] * (rhs[r] - acc);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-      if (q >= b) break;
-      x[u * b + q] += upd[q];
-    }
-  }
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (q < b && lane == 0) x[r] += omega * dinv[r] * (rhs[r] - acc);
+}
+
+template <int G, int B2, class T>
+static void sgs_launch(const DCsr& A, int b, const int* nodes, int nnodes, const T* val, const T* dinv, T omega,
+                       const T* rhs, T* x, hipStream_t s) {
+  const int blocks = cdiv((int64_t)nnodes * G * B2, 256);
+  hipLaunchKernelGGL((k_sgs_color<G, B2, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val,
+                     dinv, omega, rhs, x);
+}
+
+int sgs_lanes(const DCsr& A, int b) {
+  int b2 = 1;
+  while (b2 < b) b2 <<= 1;
+  int g = spmv_group(A.nr, A.nnz);
+  while (g * b2 > 64) g >>= 1;
+  return g < 2 ? 2 : g;
 }
 
 template <class T>
 void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega, const T* rhs, T* x,
                hipStream_t s) {
   if (nnodes <= 0) return;
+  NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
   const T* val = csr_values<T>(A);
-  const int G = spmv_group(A.nr, A.nnz);
-  const int blocks = cdiv((int64_t)nnodes * G, 256);
-  switch (G) {
-    case 2: hipLaunchKernelGGL((k_sgs_color<2, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-    case 4: hipLaunchKernelGGL((k_sgs_color<4, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-    case 8: hipLaunchKernelGGL((k_sgs_color<8, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-    case 16: hipLaunchKernelGGL((k_sgs_color<16, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-    case 32: hipLaunchKernelGGL((k_sgs_color<32, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-    default: hipLaunchKernelGGL((k_sgs_color<64, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val, dinv, omega, rhs, x); break;
-  }
+  const int G = sgs_lanes(A, b);
+  const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+#define NF_SGS(GG, BB) \
+  if (G == GG && B2 == BB) return sgs_launch<GG, BB, T>(A, b, nodes, nnodes, val, dinv, omega, rhs, x, s);
+  NF_SGS(2, 1) NF_SGS(4, 1) NF_SGS(8, 1) NF_SGS(16, 1) NF_SGS(32, 1) NF_SGS(64, 1)
+  NF_SGS(2, 2) NF_SGS(4, 2) NF_SGS(8, 2) NF_SGS(16, 2) NF_SGS(32, 2)
+  NF_SGS(2, 4) NF_SGS(4, 4) NF_SGS(8, 4) NF_SGS(16, 4)
+  NF_SGS(2, 8) NF_SGS(4, 8) NF_SGS(8, 8)
+#undef NF_SGS
+  throw NfError(NFIELD_EINVAL, "Gauss-Seidel: no kernel for this lane layout");
 }
 __global__ void k_color_traffic(int nnodes, const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
                                 const int* __restrict__ col, int stamp, int* touched, unsigned long long* out) {
@@ -890,71 +909,73 @@ __global__ void k_ptent_pattern(int ndof, int b, int k, const int* __restrict__ 
   const int a = agg[r / b];
   for (int j = 0; j < k; ++j) col[r * k + j] = a * k + j;
 }
-// One thread per aggregate: order its nodes, copy the near-nullspace rows,
-// modified Gram-Schmidt with positive R diagonal, dead columns zeroed.
-__global__ void k_tentative_qr(int nagg, int b, int k, int ndof, const int* __restrict__ aoff, int* members,
-                               const double* __restrict__ B, double* __restrict__ Q, double* __restrict__ Bc,
-                               int* __restrict__ dead) {
-  const int a = blockIdx.x * 64 + threadIdx.x;
+// One wavefront per aggregate: order its nodes (lane 0), copy the
+// near-nullspace rows, then modified Gram-Schmidt with positive R diagonal
+// (each lane owns a strided set of the aggregate's rows; inner products are
+// wavefront sums); a column whose remaining norm is <= 1e-12 ||B_a||_F is
+// dead: zero in Q, zero row in R, flagged.
+__global__ __launch_bounds__(64) void k_tentative_qr(int nagg, int b, int k, int ndof, const int* __restrict__ aoff,
+                                                     int* members, const double* __restrict__ B, double* __restrict__ Q,
+                                                     double* __restrict__ Bc, int* __restrict__ dead) {
+  const int a = blockIdx.x, lane = threadIdx.x;
   if (a >= nagg) return;
   const int m0 = aoff[a], m1 = aoff[a + 1];
-  for (int i = m0 + 1; i < m1; ++i) {   // insertion sort of the member nodes
-    const int v = members[i];
-    int j = i - 1;
-    while (j >= m0 && members[j] > v) { members[j + 1] = members[j]; --j; }
-    members[j + 1] = v;
-  }
-  const int nc = nagg * k;
-  double fro = 0.0;
-  for (int i = m0; i < m1; ++i)
-    for (int c = 0; c < b; ++c) {
-      const int r = members[i] * b + c;
-      for (int j = 0; j < k; ++j) {
-        const double v = B[(int64_t)j * ndof + r];
-        Q[(int64_t)r * k + j] = v;
-        fro += v * v;
-      }
+  if (lane == 0)
+    for (int i = m0 + 1; i < m1; ++i) {   // insertion sort of the member nodes
+      const int v = members[i];
+      int j = i - 1;
+      while (j >= m0 && members[j] > v) { members[j + 1] = members[j]; --j; }
+      members[j + 1] = v;
     }
-  fro = sqrt(fro);
+  __syncthreads();
+  const int rows = (m1 - m0) * b, nc = nagg * k;
+  double fro = 0.0;
+  for (int t = lane; t < rows; t += 64) {
+    const int r = members[m0 + t / b] * b + t % b;
+    for (int j = 0; j < k; ++j) {
+      const double v = B[(int64_t)j * ndof + r];
+      Q[(int64_t)r * k + j] = v;
+      fro += v * v;
+    }
+  }
+  fro = sqrt(wave_sum(fro));
   double R[MAXB * MAXB];
   for (int q = 0; q < MAXB * MAXB; ++q) R[q] = 0.0;
   for (int j = 0; j < k; ++j) {
     for (int l = 0; l < j; ++l) {
       double rr = 0.0;
-      for (int i = m0; i < m1; ++i)
-        for (int c = 0; c < b; ++c) {
-          const int64_t r = (int64_t)(members[i] * b + c) * k;
-          rr += Q[r + l] * Q[r + j];
-        }
+      for (int t = lane; t < rows; t += 64) {
+        const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+        rr += Q[r + l] * Q[r + j];
+      }
+      rr = wave_sum(rr);
       R[l * MAXB + j] = rr;
-      for (int i = m0; i < m1; ++i)
-        for (int c = 0; c < b; ++c) {
-          const int64_t r = (int64_t)(members[i] * b + c) * k;
-          Q[r + j] -= rr * Q[r + l];
-        }
+      for (int t = lane; t < rows; t += 64) {
+        const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+        Q[r + j] -= rr * Q[r + l];
+      }
     }
     double nr = 0.0;
-    for (int i = m0; i < m1; ++i)
-      for (int c = 0; c < b; ++c) {
-        const int64_t r = (int64_t)(members[i] * b + c) * k;
-        nr += Q[r + j] * Q[r + j];
-      }
-    nr = sqrt(nr);
+    for (int t = lane; t < rows; t += 64) {
+      const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+      nr += Q[r + j] * Q[r + j];
+    }
+    nr = sqrt(wave_sum(nr));
     const bool is_dead = nr <= 1e-12 * fro;
-    for (int i = m0; i < m1; ++i)
-      for (int c = 0; c < b; ++c) {
-        const int64_t r = (int64_t)(members[i] * b + c) * k;
-        Q[r + j] = is_dead ? 0.0 : Q[r + j] / nr;
-      }
+    for (int t = lane; t < rows; t += 64) {
+      const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+      Q[r + j] = is_dead ? 0.0 : Q[r + j] / nr;
+    }
     if (is_dead) {
       for (int l = j; l < k; ++l) R[j * MAXB + l] = 0.0;
     } else {
       R[j * MAXB + j] = nr;
     }
-    dead[a * k + j] = is_dead ? 1 : 0;
+    if (lane == 0) dead[a * k + j] = is_dead ? 1 : 0;
   }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Bc[(int64_t)j * nc + a * k + i] = R[i * MAXB + j];
+  if (lane == 0)
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Bc[(int64_t)j * nc + a * k + i] = R[i * MAXB + j];
 }
 __global__ void k_compact_flags(int n, const int* __restrict__ flag, const int* __restrict__ off, int* out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -981,8 +1002,9 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
   P.val.alloc(P.nnz);
   Bc.alloc((size_t)k * nc);
   hipLaunchKernelGGL(k_ptent_pattern, dim3(cdiv(ndof + 1, 256)), dim3(256), 0, s, ndof, b, k, agg, P.ptr.p, P.col.p);
-  hipLaunchKernelGGL(k_tentative_qr, dim3(cdiv(nagg, 64)), dim3(64), 0, s, nagg, b, k, ndof, aoff.p, members.p, B, P.val.p,
-                     Bc.p, dflag.p);
+  if (nagg > 0)
+    hipLaunchKernelGGL(k_tentative_qr, dim3(nagg), dim3(64), 0, s, nagg, b, k, ndof, aoff.p, members.p, B, P.val.p, Bc.p,
+                       dflag.p);
   const int ndead = (int)exclusive_scan(dflag.p, doff.p, nc, s);
   dead.alloc(ndead > 0 ? ndead : 1);
   if (ndead > 0) hipLaunchKernelGGL(k_compact_flags, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, dflag.p, doff.p, dead.p);
@@ -1037,19 +1059,28 @@ __device__ __forceinline__ int hash_insert(int* table, int ts, int logts, int ke
   return -1;
 }
 
-__global__ __launch_bounds__(64) void k_spgemm_count(int nr, const int* __restrict__ Ap, const int* __restrict__ Ac,
-                                                     const int* __restrict__ Bp, const int* __restrict__ Bc, int* __restrict__ cnt,
-                                                     int* overflow) {
-  __shared__ int table[SPG_COUNT_CAP];
-  const int row = blockIdx.x, lane = threadIdx.x;
-  for (int i = lane; i < SPG_COUNT_CAP; i += 64) table[i] = EMPTY_KEY;
-  __syncthreads();
-  constexpr int LOG = 12;
+// distinct-column count of listed rows: WAVES rows per block, one wavefront
+// and one LDS hash table of CAP slots per row
+template <int CAP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_spgemm_count(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
+                                                             const int* __restrict__ Ac, const int* __restrict__ Bp,
+                                                             const int* __restrict__ Bc, int* __restrict__ cnt, int* overflow) {
+  __shared__ int tables[WAVES][CAP];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * WAVES + w;
+  if (idx >= nrows) return;            // whole wavefront leaves; no block barrier below
+  int* table = tables[w];
+  const int row = rows[idx];
+  for (int i = lane; i < CAP; i += 64) table[i] = EMPTY_KEY;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  int logc = 0;
+  for (int t = CAP; t > 1; t >>= 1) ++logc;
   int mine = 0, full = 0;
   for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
     const int k = Ac[p];
     for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
-      const int r = hash_insert(table, SPG_COUNT_CAP, LOG, Bc[q]);
+      const int r = hash_insert(table, CAP, logc, Bc[q]);
       if (r > 0) ++mine;
       if (r < 0) full = 1;
     }
@@ -1060,6 +1091,18 @@ __global__ __launch_bounds__(64) void k_spgemm_count(int nr, const int* __restri
     cnt[row] = tot;
     if (anyfull) atomicOr(overflow, 1);
   }
+}
+
+// upper bound of each product row's length; rows split into two lists
+__global__ void k_spgemm_bin_ub(int nr, const int* __restrict__ Ap, const int* __restrict__ Ac, const int* __restrict__ Bp,
+                                int small_max, int* small, int* nsmall, int* big, int* nbig, int* cnt) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  int ub = 0;
+  for (int p = Ap[r]; p < Ap[r + 1]; ++p) ub += Bp[Ac[p] + 1] - Bp[Ac[p]];
+  if (ub == 0) cnt[r] = 0;
+  else if (ub <= small_max) small[atomicAdd(nsmall, 1)] = r;
+  else big[atomicAdd(nbig, 1)] = r;
 }
 
 template <int CAP>
@@ -1137,21 +1180,31 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   C.nc = B.nc;
   C.ptr.alloc(A.nr + 1);
   DBuf<int> cnt(A.nr + 1), flags(4);
+  DBuf<int> small(A.nr > 0 ? A.nr : 1), big(A.nr > 0 ? A.nr : 1);
   fill<int>(flags.p, 0, 4, s);
-  if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
-    hipLaunchKernelGGL(k_spgemm_count, dim3(A.nr), dim3(64), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, B.col.p, cnt.p, flags.p);
-  } else {
-    fill<int>(cnt.p, 0, A.nr + 1, s);
-  }
+  fill<int>(cnt.p, 0, A.nr + 1, s);
   int h_flags[4];
-  NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
-  NF_HIP(hipStreamSynchronize(s));
-  NF_CHECK(h_flags[0] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 4096 distinct columns");
+  if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
+    hipLaunchKernelGGL(k_spgemm_bin_ub, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, 256, small.p,
+                       flags.p, big.p, flags.p + 1, cnt.p);
+    NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    const int ns = h_flags[0], nb = h_flags[1];
+    fill<int>(flags.p + 2, 0, 1, s);
+    if (ns > 0)
+      hipLaunchKernelGGL((k_spgemm_count<512, 4>), dim3(cdiv(ns, 4)), dim3(256), 0, s, small.p, ns, A.ptr.p, A.col.p, B.ptr.p,
+                         B.col.p, cnt.p, flags.p + 2);
+    if (nb > 0)
+      hipLaunchKernelGGL((k_spgemm_count<SPG_COUNT_CAP, 1>), dim3(nb), dim3(64), 0, s, big.p, nb, A.ptr.p, A.col.p, B.ptr.p,
+                         B.col.p, cnt.p, flags.p + 2);
+    NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    NF_CHECK(h_flags[2] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 4096 distinct columns");
+  }
   C.nnz = exclusive_scan(cnt.p, C.ptr.p, A.nr, s);
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val.alloc(C.nnz > 0 ? C.nnz : 1);
   if (C.nnz == 0) return;
-  DBuf<int> small(A.nr), big(A.nr);
   fill<int>(flags.p, 0, 4, s);
   hipLaunchKernelGGL(k_bin_rows, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, C.ptr.p, 256, 2048, small.p, flags.p, big.p,
                      flags.p + 1, flags.p + 2);

@@ -42,7 +42,8 @@ int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes);
 // bracket any other launch: slot = prof_begin(s) (-1 if not recording), then
 // prof_end(slot, s, key, bytes) after the launch
 int prof_begin(hipStream_t s);
-void prof_end(int slot, hipStream_t s, int key, double bytes);
+void prof_end(int slot, hipStream_t s, int key, double bytes, int count = 1);
+bool prof_recording();
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s);
 
 // ------------------------------------------------------------ reductions (FP64, deterministic)
@@ -72,6 +73,7 @@ int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int*
 // dofs of each listed node, all from the values before the node's update
 template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega,
                                   const T* rhs, T* x, hipStream_t s);
+int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kernel
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)
 void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,

@@ -162,27 +162,37 @@ struct SgsD : FieldSmootherD<T> {
     // algorithmic bytes of each colour sweep: its rows' entries and row
     // pointers, node list, right-hand side, D^-1, own x read and written,
     // and every distinct column value it reads
-    std::vector<int64_t> cnnz, ccols;
-    color_traffic(*A, b, nodes.p, off, cnnz, ccols, s);
-    cbytes.resize(nc);
-    const double sz = sizeof(T);
-    for (int c = 0; c < nc; ++c) {
-      const double rows = (double)(off[c + 1] - off[c]) * b;
-      cbytes[c] = cnnz[c] * (sz + 4) + rows * (4 + 3 * sz) + 4.0 * (off[c + 1] - off[c]) + sz * ccols[c];
+    // bytes of a sweep are counted only while launch timing is recording
+    sweep_bytes = 0.0;
+    if (prof_recording()) {
+      std::vector<int64_t> cnnz, ccols;
+      color_traffic(*A, b, nodes.p, off, cnnz, ccols, s);
+      const double sz = sizeof(T);
+      for (int c = 0; c < nc; ++c) {
+        const double rows = (double)(off[c + 1] - off[c]) * b;
+        sweep_bytes += cnnz[c] * (sz + 4) + rows * (4 + 3 * sz) + 4.0 * (off[c + 1] - off[c]) + sz * ccols[c];
+      }
     }
   }
-  std::vector<double> cbytes;
-  void relax(int c, const T* rhs, T* x, hipStream_t s) {
+  // algorithmic bytes of one sweep over all colours: every colour's rows'
+  // entries and pointers, node ids, right-hand side, D^-1, own x read and
+  // written, and each distinct column value it reads
+  double sweep_bytes = 0.0;
+  void sweep(bool forward, const T* rhs, T* x, hipStream_t s) {
+    const int nc = (int)off.size() - 1;
     const int slot = prof_begin(s);
-    sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, x, s);
-    prof_end(slot, s, spmv_group(A->nr, A->nnz) * 100 + 60 + (sizeof(T) == 4 ? 1 : 0), cbytes[c]);
+    for (int i = 0; i < nc; ++i) {
+      const int c = forward ? i : nc - 1 - i;
+      sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, x, s);
+    }
+    const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+    prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 10 + 6) * 10 + (sizeof(T) == 4 ? 1 : 0), sweep_bytes, nc);
   }
   void apply(const T* rhs, T* x, bool zero_guess, hipStream_t s) override {
     if (zero_guess) fill<T>(x, (T)0, n, s);
-    const int nc = (int)off.size() - 1;
     for (int st = 0; st < steps; ++st) {
-      for (int c = 0; c < nc; ++c) relax(c, rhs, x, s);
-      for (int c = nc - 1; c >= 0; --c) relax(c, rhs, x, s);
+      sweep(true, rhs, x, s);
+      sweep(false, rhs, x, s);
     }
   }
 };

@@ -263,12 +263,13 @@ def nfield_prof_enable(on):
 SPMV_MODES = {0: "store", 1: "resid", 2: "add", 3: "sub", 4: "cheb", 5: "dscale", 6: "sgs"}
 # kernel names as the profiler prints them
 KERNEL_NAMES = {m: f"k_spmv<{{lanes}}, {m}, {{t}}>" for m in range(6)}
-KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {t}>"
+KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {rows}, {t}>"
 
 
 def kernel_name(p):
     mode = [k for k, v in SPMV_MODES.items() if v == p["mode"]][0]
-    return KERNEL_NAMES[mode].format(lanes=p["lanes"], t="float" if p["fp32"] else "double")
+    return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"],
+                                     t="float" if p["fp32"] else "double")
 
 
 def nfield_prof_read(max_keys=64):
@@ -280,8 +281,10 @@ def nfield_prof_read(max_keys=64):
     n = lib().nfield_prof_read(max_keys, _p(key), _p(cnt), _p(ms), _p(by))
     out = []
     for k in range(min(n, max_keys)):
-        out.append(dict(lanes=int(key[k]) // 100, mode=SPMV_MODES[(int(key[k]) // 10) % 10],
-                        fp32=bool(key[k] % 10), launches=int(cnt[k]), ms=float(ms[k]),
+        kk = int(key[k])
+        lanes, rows = (kk // 100) // 16, (kk // 100) % 16
+        out.append(dict(lanes=lanes, rows=rows, mode=SPMV_MODES[(kk // 10) % 10],
+                        fp32=bool(kk % 10), launches=int(cnt[k]), ms=float(ms[k]),
                         bytes=float(by[k])))
     return out
 
