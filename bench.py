@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--workload", default="fsi3d", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -119,6 +120,35 @@ def main():
     xs = x.cpu().numpy()
     A = s.assembled()
     relres = float(np.linalg.norm(s.rhs[0] - A @ xs) / np.linalg.norm(s.rhs[0]))
+
+    # precision form: FP32 hierarchy and smoothers inside FP64 flexible GMRES
+    prec = None
+    if not args.no_precision_form:
+        solver32 = NField(s.fields, s.blocks, W["spec"], hier_fp32=1, **W["opts"])
+        x32 = torch.zeros_like(b)
+
+        def step32():
+            solver32.rebuild()
+            x32.zero_()
+            _, st = solver32.gmres_solve(b, x32, restart=50, flexible=1, rtol=1e-8)
+            return st[0]
+
+        step32()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st32 = [step32() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t0
+        x32h = x32.cpu().numpy()
+        prec = dict(value=round(args.steps / el32, 4), unit="solves/s",
+                    setup_ms=round(1e3 * float(np.median([t["setup_s"] for t in st32])), 3),
+                    solve_ms=round(1e3 * float(np.median([t["solve_s"] for t in st32])), 3),
+                    gmres_iters=st32[-1]["iters"],
+                    relres=float(np.linalg.norm(s.rhs[0] - A @ x32h) / np.linalg.norm(s.rhs[0])),
+                    rel_err_vs_fp64=float(np.linalg.norm(x32h - xs) / np.linalg.norm(xs)),
+                    footprint_mb=round(solver32.footprint_bytes() / 2**20, 1),
+                    fp64_footprint_mb=round(solver.footprint_bytes() / 2**20, 1))
+        solver32.close()
     ms_per_step = 1e3 * elapsed / args.steps
     dom = max(prof, key=lambda p: p["ms"]) if prof else None
     roofline = None
@@ -152,6 +182,7 @@ def main():
         "gmres_iters": iters,
         "relres": relres,
         "roofline": roofline,
+        "precision_form": prec,
         "spmv_profile": [dict(p, gbps=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1)) for p in
                          sorted(prof, key=lambda p: -p["ms"])[:6]],
     }

@@ -291,9 +291,34 @@ def fsi3d(n=40, layers=8, nu=1e-2, E=1e3, nu_s=0.3, dt=1.0, seed=0, nrhs=1):
                                  split=[0, 0, 1]))
 
 
+# --------------------------------------------------------------------------
+# Serving trace: TSI-like systems of several grid sizes with Poisson arrivals
+# --------------------------------------------------------------------------
+SERVE_GRIDS = (16, 24, 32, 48, 64, 96, 128)
+
+
+def request_trace(n_requests=512, rate=100.0, grids=SERVE_GRIDS, max_rhs=8, seed=0):
+    """Requests with Poisson arrivals (rate per second), a grid size drawn
+    uniformly from `grids` and 1..max_rhs right-hand sides each.  Every
+    request is a 2-field TSI-like system (tsi2d) of its grid size; its
+    right-hand sides come from its own seed (see request_rhs)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x7EACE]))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    arrival = np.concatenate([[0.0], np.cumsum(gaps[1:])])
+    grid = rng.choice(np.asarray(grids), n_requests)
+    nrhs = rng.integers(1, max_rhs + 1, n_requests)
+    rseed = rng.integers(0, 2**31 - 1, n_requests)
+    return [dict(id=i, arrival_s=float(arrival[i]), grid=int(grid[i]), nrhs=int(nrhs[i]),
+                 rhs_seed=int(rseed[i])) for i in range(n_requests)]
+
+
+def request_rhs(req, n):
+    """The request's right-hand sides, (nrhs, n)."""
+    return uniform_rhs(n, req["nrhs"], req["rhs_seed"])
+
+
 def _not_yet(*a, **k):
     raise NotImplementedError
 
 
 lung3d = _not_yet
-request_trace = _not_yet

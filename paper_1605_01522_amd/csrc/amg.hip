@@ -28,19 +28,20 @@ double power_lambda(const DCsr& A, const double* dinv, uint64_t seed, int its, h
   const int n = A.nr;
   DBuf<double> v(n), w(n), partial(RED_BLOCKS), nrm(1);
   power_start(v.p, n, seed, s);
-  dot_dev(v.p, v.p, n, partial.p, nrm.p, s);
+  dotm(v.p, n, v.p, n, n, 1, partial.p, nrm.p, s);
   hipLaunchKernelGGL(k_sqrt1, dim3(1), dim3(1), 0, s, nrm.p);
-  scale_inv_dev(v.p, v.p, nrm.p, n, s);
+  scale_inv_devm(v.p, n, v.p, n, nrm.p, 1, n, 1, nullptr, s);
   double lam = 0.0;
   for (int it = 0; it < its; ++it) {
     SpmvArgs<double> a;
     a.x = v.p;
     a.y = w.p;
     a.dinv = dinv;
+    a.ldx = a.ldy = n;
     spmv<double>(SPMV_DSCALE, A, a, s);
-    dot_dev(w.p, w.p, n, partial.p, nrm.p, s);
+    dotm(w.p, n, w.p, n, n, 1, partial.p, nrm.p, s);
     hipLaunchKernelGGL(k_sqrt1, dim3(1), dim3(1), 0, s, nrm.p);
-    scale_inv_dev(w.p, v.p, nrm.p, n, s);
+    scale_inv_devm(w.p, n, v.p, n, nrm.p, 1, n, 1, nullptr, s);
   }
   NF_HIP(hipMemcpyAsync(&lam, nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));

@@ -48,48 +48,81 @@ __device__ __forceinline__ uint64_t smix64(uint64_t z) {
 }
 
 // ==================================================================== vectors
+#define NF_ROWS(n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
 template <class T>
-__global__ void k_fill(T* x, T v, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+__global__ void k_fill(T* x, T v, int64_t n) { NF_ROWS(n) x[i] = v; }
+template <class S, class D>
+__global__ void k_cast(const S* x, D* y, int64_t n) { NF_ROWS(n) y[i] = (D)x[i]; }
+// multi-column kernels: column k = blockIdx.y
+template <class T>
+__global__ void k_fillm(T* x, int64_t ldx, T v, int64_t n) {
+  T* xk = x + blockIdx.y * ldx;
+  NF_ROWS(n) xk[i] = v;
 }
 template <class S, class D>
-__global__ void k_cast(const S* x, D* y, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (D)x[i];
-}
-__global__ void k_axpy(double a, const double* x, double* y, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] += a * x[i];
-}
-template <class T>
-__global__ void k_sub_scaled(const T* dinv, const T* u, T* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] -= dinv[i] * u[i];
+__global__ void k_castm(const S* x, int64_t ldx, D* y, int64_t ldy, int64_t n) {
+  const S* xk = x + blockIdx.y * ldx;
+  D* yk = y + blockIdx.y * ldy;
+  NF_ROWS(n) yk[i] = (D)xk[i];
 }
 template <class T>
-__global__ void k_add_into(const T* d, T* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] += d[i];
-}
-__global__ void k_scale_inv_dev(const double* w, double* v, const double* nrm, int64_t n) {
-  const double s = *nrm;
-  const double inv = s != 0.0 ? 1.0 / s : 1.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) v[i] = w[i] * inv;
+__global__ void k_add_intom(const T* d, int64_t ldd, T* x, int64_t ldx, int64_t n, const int* mask) {
+  if (mask && !mask[blockIdx.y]) return;
+  const T* dk = d + blockIdx.y * ldd;
+  T* xk = x + blockIdx.y * ldx;
+  NF_ROWS(n) xk[i] += dk[i];
 }
 template <class T>
-__global__ void k_cheb_first(const T* b, const T* dinv, T inv_theta, T* d, T* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    T v = dinv[i] * b[i] * inv_theta;
-    d[i] = v;
-    x[i] = v;
+__global__ void k_sub_scaledm(const T* dinv, const T* u, int64_t ldu, T* x, int64_t ldx, int64_t n) {
+  const T* uk = u + blockIdx.y * ldu;
+  T* xk = x + blockIdx.y * ldx;
+  NF_ROWS(n) xk[i] -= dinv[i] * uk[i];
+}
+template <class T>
+__global__ void k_cheb_firstm(const T* b, int64_t ldb, const T* dinv, T inv_theta, T* d, int64_t ldd, T* x, int64_t ldx,
+                              int64_t n) {
+  const T* bk = b + blockIdx.y * ldb;
+  T* dk = d + blockIdx.y * ldd;
+  T* xk = x + blockIdx.y * ldx;
+  NF_ROWS(n) {
+    const T v = dinv[i] * bk[i] * inv_theta;
+    dk[i] = v;
+    xk[i] = v;
   }
 }
-// one wave per row of a dense row-major matrix
-template <class T>
-__global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ M, int n, const T* __restrict__ b, T* __restrict__ x) {
+__global__ void k_scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride,
+                                 int64_t n, const int* mask) {
+  const int k = blockIdx.y;
+  if (mask && !mask[k]) return;
+  const double sv = nrm[k * stride];
+  const double inv = sv != 0.0 ? 1.0 / sv : 1.0;
+  const double* wk = w + k * ldw;
+  double* vk = v + k * ldv;
+  NF_ROWS(n) vk[i] = wk[i] * inv;
+}
+// one wavefront per row of a dense row-major matrix, all columns at once
+template <int NR, class T>
+__global__ __launch_bounds__(256) void k_dense_gemvm(const double* __restrict__ M, int n, const T* __restrict__ b, int64_t ldb,
+                                                    T* __restrict__ x, int64_t ldx, int nrhs) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
-  double s = 0.0;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
   const double* m = M + (int64_t)row * n;
-  for (int j = lane; j < n; j += 64) s += m[j] * (double)b[j];
-  s = wave_sum(s);
-  if (lane == 0) x[row] = (T)s;
+  for (int j = lane; j < n; j += 64) {
+    const double mj = m[j];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) acc[k] += mj * (double)b[k * ldb + j];
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= nrhs) break;
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) x[k * ldx + row] = (T)v;
+  }
 }
 
 static inline int grid_for(int64_t n, int threads = 256) {
@@ -98,6 +131,12 @@ static inline int grid_for(int64_t n, int threads = 256) {
   if (g < 1) g = 1;
   return (int)g;
 }
+static inline int grid_cols(int64_t n, int nrhs) {
+  int64_t g = (n + 255) / 256;
+  const int64_t cap = 8192 / (nrhs > 0 ? nrhs : 1);
+  if (g > cap) g = cap;
+  return g < 1 ? 1 : (int)g;
+}
 
 template <class T> void fill(T* x, T v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
@@ -105,23 +144,43 @@ template <class T> void fill(T* x, T v, int64_t n, hipStream_t s) {
 template <class S, class D> void cast_copy(const S* x, D* y, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL((k_cast<S, D>), dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
 }
-void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, a, x, y, n);
+template <class T> void fillm(T* x, int64_t ldx, T v, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0) hipLaunchKernelGGL(k_fillm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, x, ldx, v, n);
 }
-template <class T> void sub_scaled(const T* dinv, const T* u, T* x, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_sub_scaled<T>, dim3(grid_for(n)), dim3(256), 0, s, dinv, u, x, n);
+template <class S, class D> void castm(const S* x, int64_t ldx, D* y, int64_t ldy, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL((k_castm<S, D>), dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, x, ldx, y, ldy, n);
 }
-template <class T> void add_into(const T* d, T* x, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_add_into<T>, dim3(grid_for(n)), dim3(256), 0, s, d, x, n);
+template <class T> void copym(const T* x, int64_t ldx, T* y, int64_t ldy, int64_t n, int nrhs, hipStream_t s) {
+  castm<T, T>(x, ldx, y, ldy, n, nrhs, s);
 }
-void scale_inv_dev(const double* w, double* v, const double* nrm_dev, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_scale_inv_dev, dim3(grid_for(n)), dim3(256), 0, s, w, v, nrm_dev, n);
+template <class T> void add_intom(const T* d, int64_t ldd, T* x, int64_t ldx, int64_t n, int nrhs, const int* mask,
+                                  hipStream_t s) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_add_intom<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, d, ldd, x, ldx, n, mask);
 }
-template <class T> void cheb_first(const T* b, const T* dinv, T inv_theta, T* d, T* x, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(256), 0, s, b, dinv, inv_theta, d, x, n);
+template <class T> void sub_scaledm(const T* dinv, const T* u, int64_t ldu, T* x, int64_t ldx, int64_t n, int nrhs,
+                                    hipStream_t s) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_sub_scaledm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, dinv, u, ldu, x, ldx, n);
 }
-template <class T> void dense_gemv(const double* M, int n, const T* b, T* x, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, x);
+template <class T> void cheb_firstm(const T* b, int64_t ldb, const T* dinv, T inv_theta, T* d, int64_t ldd, T* x,
+                                    int64_t ldx, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_cheb_firstm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, b, ldb, dinv, inv_theta, d, ldd,
+                       x, ldx, n);
+}
+void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride, int64_t n,
+                    int nrhs, const int* mask, hipStream_t s) {
+  if (n > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_scale_inv_devm, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, w, ldw, v, ldv, nrm, stride, n,
+                       mask);
+}
+template <class T> void dense_gemvm(const double* M, int n, const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs,
+                                    hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (nrhs == 1) hipLaunchKernelGGL((k_dense_gemvm<1, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, ldb, x, ldx, nrhs);
+  else hipLaunchKernelGGL((k_dense_gemvm<NRMAX, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, ldb, x, ldx, nrhs);
 }
 
 template void fill<double>(double*, double, int64_t, hipStream_t);
@@ -129,20 +188,29 @@ template void fill<float>(float*, float, int64_t, hipStream_t);
 template void fill<int>(int*, int, int64_t, hipStream_t);
 template void cast_copy<double, float>(const double*, float*, int64_t, hipStream_t);
 template void cast_copy<float, double>(const float*, double*, int64_t, hipStream_t);
-template void sub_scaled<double>(const double*, const double*, double*, int64_t, hipStream_t);
-template void sub_scaled<float>(const float*, const float*, float*, int64_t, hipStream_t);
-template void add_into<double>(const double*, double*, int64_t, hipStream_t);
-template void add_into<float>(const float*, float*, int64_t, hipStream_t);
-template void cheb_first<double>(const double*, const double*, double, double*, double*, int64_t, hipStream_t);
-template void cheb_first<float>(const float*, const float*, float, float*, float*, int64_t, hipStream_t);
-template void dense_gemv<double>(const double*, int, const double*, double*, hipStream_t);
-template void dense_gemv<float>(const double*, int, const float*, float*, hipStream_t);
+template void fillm<double>(double*, int64_t, double, int64_t, int, hipStream_t);
+template void fillm<float>(float*, int64_t, float, int64_t, int, hipStream_t);
+template void castm<double, float>(const double*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void castm<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void copym<double>(const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void copym<float>(const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void add_intom<double>(const double*, int64_t, double*, int64_t, int64_t, int, const int*, hipStream_t);
+template void add_intom<float>(const float*, int64_t, float*, int64_t, int64_t, int, const int*, hipStream_t);
+template void sub_scaledm<double>(const double*, const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void sub_scaledm<float>(const float*, const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void cheb_firstm<double>(const double*, int64_t, const double*, double, double*, int64_t, double*, int64_t,
+                                  int64_t, int, hipStream_t);
+template void cheb_firstm<float>(const float*, int64_t, const float*, float, float*, int64_t, float*, int64_t, int64_t,
+                                 int, hipStream_t);
+template void dense_gemvm<double>(const double*, int, const double*, int64_t, double*, int64_t, int, hipStream_t);
+template void dense_gemvm<float>(const double*, int, const float*, int64_t, float*, int64_t, int, hipStream_t);
 
 // ======================================================================= SpMV
-// G lanes per row (G divides 64, groups aligned inside the wavefront).  The
-// row sum is reduced with xor-shuffles inside the group; lane 0 of the group
-// applies the epilogue.
-template <int G, int MODE, class T>
+// G lanes per row (G divides 64, groups aligned inside the wavefront), NR
+// columns at most per launch (the matrix row is read once for all columns).
+// Row sums are reduced with xor-shuffles inside the group; lane 0 of the
+// group applies the epilogue to every column.
+template <int G, int MODE, int NR, class T>
 __global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ ptr, const int* __restrict__ col,
                                               const T* __restrict__ val, SpmvArgs<T> a) {
   const int gid = blockIdx.x * 256 + threadIdx.x;
@@ -150,22 +218,37 @@ __global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ pt
   if (row >= nr) return;
   const int p0 = ptr[row], p1 = ptr[row + 1];
   const T* __restrict__ x = a.x;
-  T s = 0;
-  for (int p = p0 + lane; p < p1; p += G) s += val[p] * x[col[p]];
+  const int nrhs = a.nrhs;
+  T s[NR];
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  for (int k = 0; k < NR; ++k) s[k] = 0;
+  for (int p = p0 + lane; p < p1; p += G) {
+    const T v = val[p];
+    const int c = col[p];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) s[k] += v * x[k * a.ldx + c];
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, G);
   if (lane != 0) return;
-  if (MODE == SPMV_STORE) a.y[row] = s;
-  else if (MODE == SPMV_RESID) a.y[row] = a.b[row] - s;
-  else if (MODE == SPMV_ADD) a.y[row] += s;
-  else if (MODE == SPMV_SUB) a.y[row] -= s;
-  else if (MODE == SPMV_DSCALE) a.y[row] = a.dinv[row] * s;
-  else {  // SPMV_CHEB
-    const T r = a.b[row] - s;
-    T dn = a.c2 * a.dinv[row] * r;
-    if (a.c1 != (T)0) dn += a.c1 * a.d[row];
-    a.d[row] = dn;
-    a.xo[row] = a.x[row] + dn;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= nrhs) break;
+    if (MODE == SPMV_STORE) a.y[k * a.ldy + row] = s[k];
+    else if (MODE == SPMV_RESID) a.y[k * a.ldy + row] = a.b[k * a.ldb + row] - s[k];
+    else if (MODE == SPMV_ADD) a.y[k * a.ldy + row] += s[k];
+    else if (MODE == SPMV_SUB) a.y[k * a.ldy + row] -= s[k];
+    else if (MODE == SPMV_DSCALE) a.y[k * a.ldy + row] = a.dinv[row] * s[k];
+    else {  // SPMV_CHEB
+      const T r = a.b[k * a.ldb + row] - s[k];
+      T dn = a.c2 * a.dinv[row] * r;
+      if (a.c1 != (T)0) dn += a.c1 * a.d[k * a.ldd + row];
+      a.d[k * a.ldd + row] = dn;
+      a.xo[k * a.ldxo + row] = a.x[k * a.ldx + row] + dn;
+    }
   }
 }
 
@@ -177,17 +260,23 @@ int spmv_group(int nr, int64_t nnz) {
   return g < 2 ? 2 : g;
 }
 
-template <int MODE, class T>
+template <int MODE, int NR, class T>
 static void spmv_mode(int G, const DCsr& A, const SpmvArgs<T>& a, const T* val, hipStream_t s) {
   const int blocks = cdiv((int64_t)A.nr * G, 256);
   switch (G) {
-    case 2: hipLaunchKernelGGL((k_spmv<2, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
-    case 4: hipLaunchKernelGGL((k_spmv<4, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
-    case 8: hipLaunchKernelGGL((k_spmv<8, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
-    case 16: hipLaunchKernelGGL((k_spmv<16, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
-    case 32: hipLaunchKernelGGL((k_spmv<32, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
-    default: hipLaunchKernelGGL((k_spmv<64, MODE, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 2: hipLaunchKernelGGL((k_spmv<2, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 4: hipLaunchKernelGGL((k_spmv<4, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 8: hipLaunchKernelGGL((k_spmv<8, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 16: hipLaunchKernelGGL((k_spmv<16, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    case 32: hipLaunchKernelGGL((k_spmv<32, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
+    default: hipLaunchKernelGGL((k_spmv<64, MODE, NR, T>), dim3(blocks), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, val, a); break;
   }
+}
+template <int MODE, class T>
+static void spmv_nr(int G, const DCsr& A, const SpmvArgs<T>& a, const T* val, hipStream_t s) {
+  NF_CHECK(a.nrhs >= 1 && a.nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
+  if (a.nrhs == 1) spmv_mode<MODE, 1, T>(G, A, a, val, s);
+  else spmv_mode<MODE, NRMAX, T>(G, A, a, val, s);
 }
 
 template <class T> static const T* csr_values(const DCsr& A);
@@ -265,11 +354,11 @@ void prof_end(int slot, hipStream_t s, int key, double bytes, int count) {
 
 // algorithmic bytes of one launch: matrix once, operand once, epilogue streams
 template <class T>
-static double spmv_bytes(SpmvMode mode, const DCsr& A) {
+static double spmv_bytes(SpmvMode mode, const DCsr& A, int nrhs) {
   const double s = sizeof(T);
-  double b = (double)A.nnz * (s + 4) + 4.0 * (A.nr + 1) + s * A.nc;
+  double b = (double)A.nnz * (s + 4) + 4.0 * (A.nr + 1) + nrhs * s * A.nc;
   const int streams = mode == SPMV_STORE ? 1 : mode == SPMV_CHEB ? 5 : 2;
-  return b + streams * s * A.nr;
+  return b + nrhs * streams * s * A.nr;
 }
 
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
@@ -279,17 +368,17 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
   const bool timed = g_prof.on && g_prof.used < g_prof.ev.size() / 2;
   if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   switch (mode) {
-    case SPMV_STORE: spmv_mode<SPMV_STORE, T>(G, A, a, val, s); break;
-    case SPMV_RESID: spmv_mode<SPMV_RESID, T>(G, A, a, val, s); break;
-    case SPMV_ADD: spmv_mode<SPMV_ADD, T>(G, A, a, val, s); break;
-    case SPMV_SUB: spmv_mode<SPMV_SUB, T>(G, A, a, val, s); break;
-    case SPMV_CHEB: spmv_mode<SPMV_CHEB, T>(G, A, a, val, s); break;
-    case SPMV_DSCALE: spmv_mode<SPMV_DSCALE, T>(G, A, a, val, s); break;
+    case SPMV_STORE: spmv_nr<SPMV_STORE, T>(G, A, a, val, s); break;
+    case SPMV_RESID: spmv_nr<SPMV_RESID, T>(G, A, a, val, s); break;
+    case SPMV_ADD: spmv_nr<SPMV_ADD, T>(G, A, a, val, s); break;
+    case SPMV_SUB: spmv_nr<SPMV_SUB, T>(G, A, a, val, s); break;
+    case SPMV_CHEB: spmv_nr<SPMV_CHEB, T>(G, A, a, val, s); break;
+    case SPMV_DSCALE: spmv_nr<SPMV_DSCALE, T>(G, A, a, val, s); break;
   }
   if (timed) {
     NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
     g_prof.key.push_back(((G * 16) * 10 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
-    g_prof.bytes.push_back(spmv_bytes<T>(mode, A));
+    g_prof.bytes.push_back(spmv_bytes<T>(mode, A, a.nrhs));
     g_prof.count.push_back(1);
     ++g_prof.used;
   }
@@ -298,71 +387,91 @@ template void spmv<double>(SpmvMode, const DCsr&, const SpmvArgs<double>&, hipSt
 template void spmv<float>(SpmvMode, const DCsr&, const SpmvArgs<float>&, hipStream_t);
 
 // ================================================================= reductions
-__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
-                                                     double* __restrict__ partial) {
+// Fixed grids (RED_BLOCKS blocks per column) so that every sum is taken in
+// the same order on every run and for every batch size.
+__global__ __launch_bounds__(256) void k_dot_partialm(const double* __restrict__ x, int64_t ldx, const double* __restrict__ y,
+                                                      int64_t ldy, int64_t n, double* __restrict__ partial) {
   __shared__ double ws[4];
+  const double* xk = x + blockIdx.y * ldx;
+  const double* yk = y + blockIdx.y * ldy;
   double s = 0.0;
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += x[i] * y[i];
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += xk[i] * yk[i];
   s = block_sum256(s, ws);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * RED_BLOCKS + blockIdx.x] = s;
 }
-// grid = ncols blocks; out[k] (+)= sum of partial[k * RED_BLOCKS + 0 .. RED_BLOCKS)
-__global__ __launch_bounds__(256) void k_mreduce(const double* __restrict__ partial, double* __restrict__ out, int accumulate) {
+// grid (ncols, nrhs): out[k*os + j] (+)= sum of partial[k*ps + j*RED_BLOCKS + 0..RED_BLOCKS)
+__global__ __launch_bounds__(256) void k_mreduce(const double* __restrict__ partial, int64_t ps, double* __restrict__ out,
+                                                 int64_t os, int accumulate, const int* mask) {
   __shared__ double ws[4];
-  const int k = blockIdx.x;
+  const int j = blockIdx.x, k = blockIdx.y;
+  if (mask && !mask[k]) return;
+  const double* pk = partial + k * ps + (int64_t)j * RED_BLOCKS;
   double s = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[(int64_t)k * RED_BLOCKS + i];
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += pk[i];
   s = block_sum256(s, ws);
-  if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
+  if (threadIdx.x == 0) out[k * os + j] = accumulate ? out[k * os + j] + s : s;
 }
 
-void dot_dev(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(256), 0, s, x, y, n, partial);
-  hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(256), 0, s, partial, out, 0);
+void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n, int nrhs, double* partial, double* out,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partialm, dim3(RED_BLOCKS, nrhs), dim3(256), 0, s, x, ldx, y, ldy, n, partial);
+  hipLaunchKernelGGL(k_mreduce, dim3(1, nrhs), dim3(256), 0, s, partial, (int64_t)RED_BLOCKS, out, (int64_t)1, 0,
+                     (const int*)nullptr);
 }
 
+// column k = blockIdx.y: partial dots of V_k[0..ncols) with w_k
 template <int MAXC>
-__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
-                                              int64_t n, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
+                                              const double* __restrict__ w, int64_t ldw, double* __restrict__ partial,
+                                              int64_t ps, const int* mask) {
   __shared__ double ws[4];
+  const int kc = blockIdx.y;
+  if (mask && !mask[kc]) return;
+  const double* Vk = V + kc * vs;
+  const double* wk = w + kc * ldw;
   double acc[MAXC];
 #pragma unroll
   for (int k = 0; k < MAXC; ++k) acc[k] = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double wi = w[i];
+    const double wi = wk[i];
 #pragma unroll
     for (int k = 0; k < MAXC; ++k)
-      if (k < ncols) acc[k] += V[k * ldv + i] * wi;
+      if (k < ncols) acc[k] += Vk[k * n + i] * wi;
   }
 #pragma unroll
   for (int k = 0; k < MAXC; ++k)
     if (k < ncols) {
       double r = block_sum256(acc[k], ws);
-      if (threadIdx.x == 0) partial[(int64_t)k * RED_BLOCKS + blockIdx.x] = r;
+      if (threadIdx.x == 0) partial[kc * ps + (int64_t)k * RED_BLOCKS + blockIdx.x] = r;
     }
 }
 
-// w <- w - V h, then partial dots V^T w (NORM=false) or ||w||^2 (NORM=true)
+// w_k <- w_k - V_k h_k, then partial dots V_k^T w_k (NORM=false) or ||w_k||^2 (NORM=true)
 template <int MAXC, bool NORM>
-__global__ __launch_bounds__(256) void k_mupdate(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
-                                                 double* __restrict__ w, int64_t n, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_mupdate(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
+                                                 const double* __restrict__ h, int64_t hs, double* __restrict__ w, int64_t ldw,
+                                                 double* __restrict__ partial, int64_t ps, const int* mask) {
   __shared__ double ws[4];
-  __shared__ double hs[MAXC];
-  for (int k = threadIdx.x; k < MAXC; k += 256) hs[k] = k < ncols ? h[k] : 0.0;
+  __shared__ double hsh[MAXC];
+  const int kc = blockIdx.y;
+  if (mask && !mask[kc]) return;
+  const double* Vk = V + kc * vs;
+  double* wk = w + kc * ldw;
+  for (int k = threadIdx.x; k < MAXC; k += 256) hsh[k] = k < ncols ? h[kc * hs + k] : 0.0;
   __syncthreads();
   double acc[NORM ? 1 : MAXC];
 #pragma unroll
   for (int k = 0; k < (NORM ? 1 : MAXC); ++k) acc[k] = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double vk[MAXC];
-    double wi = w[i];
+    double wi = wk[i];
 #pragma unroll
     for (int k = 0; k < MAXC; ++k)
       if (k < ncols) {
-        vk[k] = V[k * ldv + i];
-        wi -= vk[k] * hs[k];
+        vk[k] = Vk[k * n + i];
+        wi -= vk[k] * hsh[k];
       }
-    w[i] = wi;
+    wk[i] = wi;
     if (NORM) {
       acc[0] += wi * wi;
     } else {
@@ -373,29 +482,35 @@ __global__ __launch_bounds__(256) void k_mupdate(const double* __restrict__ V, i
   }
   if (NORM) {
     double r = block_sum256(acc[0], ws);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[kc * ps + blockIdx.x] = r;
   } else {
 #pragma unroll
     for (int k = 0; k < (NORM ? 1 : MAXC); ++k)
       if (k < ncols) {
         double r = block_sum256(acc[k], ws);
-        if (threadIdx.x == 0) partial[(int64_t)k * RED_BLOCKS + blockIdx.x] = r;
+        if (threadIdx.x == 0) partial[kc * ps + (int64_t)k * RED_BLOCKS + blockIdx.x] = r;
       }
   }
 }
 
 template <int MAXC>
-__global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ y,
-                                                  double* __restrict__ u, int64_t n, int accumulate) {
-  __shared__ double ys[MAXC];
-  for (int k = threadIdx.x; k < MAXC; k += 256) ys[k] = k < ncols ? y[k] : 0.0;
+__global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, int64_t vs, int64_t n, const int* ncols,
+                                                  const double* __restrict__ y, int64_t ys, double* __restrict__ u,
+                                                  int64_t ldu, int accumulate, const int* mask) {
+  __shared__ double ysh[MAXC];
+  const int kc = blockIdx.y;
+  if (mask && !mask[kc]) return;
+  const int nck = ncols[kc];
+  const double* Vk = V + kc * vs;
+  double* uk = u + kc * ldu;
+  for (int k = threadIdx.x; k < MAXC; k += 256) ysh[k] = k < nck ? y[kc * ys + k] : 0.0;
   __syncthreads();
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    double s = accumulate ? u[i] : 0.0;
+    double sacc = accumulate ? uk[i] : 0.0;
 #pragma unroll
     for (int k = 0; k < MAXC; ++k)
-      if (k < ncols) s += V[k * ldv + i] * ys[k];
-    u[i] = s;
+      if (k < nck) sacc += Vk[k * n + i] * ysh[k];
+    uk[i] = sacc;
   }
 }
 
@@ -408,67 +523,90 @@ __global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, 
     else throw NfError(NFIELD_EINVAL, "GMRES restart length above 63 is not supported"); \
   } while (0)
 
-void mdot_partial(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* partial, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mdot<MC>, dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, w, n, partial));
+void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double* w, int64_t ldw, double* partial,
+                  const int* mask, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mdot<MC>, dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n, ncols, w,
+                                             ldw, partial, L.ps, mask));
 }
-void mreduce(const double* partial, int ncols, double* out, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_mreduce, dim3(ncols), dim3(256), 0, s, partial, out, accumulate);
+void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out, int accumulate, const int* mask,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_mreduce, dim3(ncols, L.nrhs), dim3(256), 0, s, partial, L.ps, out, L.hs, accumulate, mask);
 }
-void mupdate_dot(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, false>), dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, h, w, n, partial));
+void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
+                 double* partial, const int* mask, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, false>), dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n,
+                                             ncols, h, L.hs, w, ldw, partial, L.ps, mask));
 }
-void mupdate_norm(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, true>), dim3(RED_BLOCKS), dim3(256), 0, s, V, ldv, ncols, h, w, n, partial));
+void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
+                  double* partial, const int* mask, hipStream_t s) {
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, true>), dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n,
+                                             ncols, h, L.hs, w, ldw, partial, L.ps, mask));
 }
-void mcombine(const double* V, int64_t ldv, int ncols, const double* y, double* u, int64_t n, int accumulate, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mcombine<MC>, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, ncols, y, u, n, accumulate));
+void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
+              int64_t ldu, int accumulate, const int* mask, hipStream_t s) {
+  if (max_ncols <= 0) return;
+  NF_MAXC_DISPATCH(max_ncols, hipLaunchKernelGGL(k_mcombine<MC>, dim3(grid_cols(L.n, L.nrhs), L.nrhs), dim3(256), 0, s, V, L.vs,
+                                                 L.n, ncols, y, (int64_t)L.m, u, ldu, accumulate, mask));
 }
 
-// Givens step of the Arnoldi process, one block: H is (m+1) x m column-major.
+// Givens step of the Arnoldi process for column k = blockIdx.x: H_k is
+// (m+1) x m column-major.
 __global__ __launch_bounds__(256) void k_givens(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
-                                                const double* __restrict__ nrm_partial, double* H, double* cs, double* sn,
-                                                double* g, double* hnorm_out, double* res_out) {
+                                                int64_t hs, const double* __restrict__ nrm_partial, int64_t ps, double* H,
+                                                double* cs, double* sn, double* g, double* scal, const int* mask) {
   __shared__ double ws[4];
+  const int kc = blockIdx.x;
+  if (mask && !mask[kc]) return;
   double s = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += nrm_partial[i];
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += nrm_partial[kc * ps + i];
   s = block_sum256(s, ws);
   if (threadIdx.x != 0) return;
   const int ld = m + 1;
-  double* Hj = H + (int64_t)j * ld;
-  for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h2[i];
+  double* Hk = H + (int64_t)kc * ld * m;
+  double* csk = cs + (int64_t)kc * m;
+  double* snk = sn + (int64_t)kc * m;
+  double* gk = g + (int64_t)kc * ld;
+  double* Hj = Hk + (int64_t)j * ld;
+  for (int i = 0; i <= j; ++i) Hj[i] = h1[kc * hs + i] + h2[kc * hs + i];
   const double hn = sqrt(s);
   Hj[j + 1] = hn;
-  *hnorm_out = hn;
+  scal[2 * kc] = hn;
   for (int i = 0; i < j; ++i) {
     const double a = Hj[i], c = Hj[i + 1];
-    Hj[i] = cs[i] * a + sn[i] * c;
-    Hj[i + 1] = -sn[i] * a + cs[i] * c;
+    Hj[i] = csk[i] * a + snk[i] * c;
+    Hj[i + 1] = -snk[i] * a + csk[i] * c;
   }
   const double a = Hj[j], c = Hj[j + 1];
   const double den = hypot(a, c);
-  cs[j] = den == 0.0 ? 1.0 : a / den;
-  sn[j] = den == 0.0 ? 0.0 : c / den;
+  csk[j] = den == 0.0 ? 1.0 : a / den;
+  snk[j] = den == 0.0 ? 0.0 : c / den;
   Hj[j] = den;
   Hj[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  *res_out = fabs(g[j + 1]);
+  gk[j + 1] = -snk[j] * gk[j];
+  gk[j] = csk[j] * gk[j];
+  scal[2 * kc + 1] = fabs(gk[j + 1]);
 }
-__global__ void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int ld = m + 1;
+__global__ void k_backsolve(const int* ncols, int m, const double* H, const double* g, double* y, const int* mask) {
+  const int kc = blockIdx.x;
+  if (threadIdx.x != 0 || (mask && !mask[kc])) return;
+  const int ld = m + 1, k = ncols[kc];
+  const double* Hk = H + (int64_t)kc * ld * m;
+  const double* gk = g + (int64_t)kc * ld;
+  double* yk = y + (int64_t)kc * m;
   for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int l = i + 1; l < k; ++l) s -= H[(int64_t)l * ld + i] * y[l];
-    y[i] = s / H[(int64_t)i * ld + i];
+    double s = gk[i];
+    for (int l = i + 1; l < k; ++l) s -= Hk[(int64_t)l * ld + i] * yk[l];
+    yk[i] = s / Hk[(int64_t)i * ld + i];
   }
 }
-void givens_step(int j, int m, const double* h1, const double* h2, const double* nrm_partial, double* H, double* cs,
-                 double* sn, double* g, double* hnorm_out, double* res_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, j, m, h1, h2, nrm_partial, H, cs, sn, g, hnorm_out, res_out);
+void givens_step(const GmresLayout& L, int j, const double* h1, const double* h2, const double* nrm_partial, double* H,
+                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(L.nrhs), dim3(256), 0, s, j, L.m, h1, h2, L.hs, nrm_partial, L.ps, H, cs, sn, g, scal,
+                     mask);
 }
-void backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, k, m, H, g, y);
+void backsolve(const GmresLayout& L, const int* ncols, const double* H, const double* g, double* y, const int* mask,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(L.nrhs), dim3(64), 0, s, ncols, L.m, H, g, y, mask);
 }
 
 // ====================================================================== scan
@@ -794,14 +932,15 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
 
 // One group of B2*G lanes per node (B2 = b rounded up to a power of two,
 // G lanes per row, B2*G <= 64 so the group lies inside one wavefront): every
-// row of the node is summed at once, and the updates are written after all
-// of the group's loads have completed, so the node's dofs are relaxed
-// together from their old values.
-template <int G, int B2, class T>
+// row of the node is summed at once for all columns, and the updates are
+// written after all of the group's loads have completed, so the node's dofs
+// are relaxed together from their old values.
+template <int G, int B2, int NR, class T>
 __global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
                                                    const int* __restrict__ ptr, const int* __restrict__ col,
                                                    const T* __restrict__ val, const T* __restrict__ dinv, T omega,
-                                                   const T* __restrict__ rhs, T* __restrict__ x) {
+                                                   const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
+                                                   int nrhs) {
   constexpr int NG = G * B2;
   const int gid = blockIdx.x * 256 + threadIdx.x;
   const int t = gid / NG, sub = gid % NG;
@@ -809,20 +948,39 @@ __global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __rest
   if (t >= nnodes) return;
   const int u = nodes[t];
   const int r = u * b + q;
-  T acc = 0;
-  if (q < b)
-    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) acc += val[p] * x[col[p]];
+  T acc[NR];
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-  if (q < b && lane == 0) x[r] += omega * dinv[r] * (rhs[r] - acc);
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  if (q < b)
+    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) {
+      const T v = val[p];
+      const int c = col[p];
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nrhs) acc[k] += v * x[k * ldx + c];
+    }
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
+  if (q < b && lane == 0) {
+    const T w = omega * dinv[r];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) x[k * ldx + r] += w * (rhs[k * ldr + r] - acc[k]);
+  }
 }
 
 template <int G, int B2, class T>
 static void sgs_launch(const DCsr& A, int b, const int* nodes, int nnodes, const T* val, const T* dinv, T omega,
-                       const T* rhs, T* x, hipStream_t s) {
+                       const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
   const int blocks = cdiv((int64_t)nnodes * G * B2, 256);
-  hipLaunchKernelGGL((k_sgs_color<G, B2, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val,
-                     dinv, omega, rhs, x);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_sgs_color<G, B2, 1, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val,
+                       dinv, omega, rhs, ldr, x, ldx, nrhs);
+  else
+    hipLaunchKernelGGL((k_sgs_color<G, B2, NRMAX, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p,
+                       val, dinv, omega, rhs, ldr, x, ldx, nrhs);
 }
 
 int sgs_lanes(const DCsr& A, int b) {
@@ -834,15 +992,16 @@ int sgs_lanes(const DCsr& A, int b) {
 }
 
 template <class T>
-void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega, const T* rhs, T* x,
-               hipStream_t s) {
+void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega, const T* rhs, int64_t ldr,
+               T* x, int64_t ldx, int nrhs, hipStream_t s) {
   if (nnodes <= 0) return;
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
+  NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
   const T* val = csr_values<T>(A);
   const int G = sgs_lanes(A, b);
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
 #define NF_SGS(GG, BB) \
-  if (G == GG && B2 == BB) return sgs_launch<GG, BB, T>(A, b, nodes, nnodes, val, dinv, omega, rhs, x, s);
+  if (G == GG && B2 == BB) return sgs_launch<GG, BB, T>(A, b, nodes, nnodes, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
   NF_SGS(2, 1) NF_SGS(4, 1) NF_SGS(8, 1) NF_SGS(16, 1) NF_SGS(32, 1) NF_SGS(64, 1)
   NF_SGS(2, 2) NF_SGS(4, 2) NF_SGS(8, 2) NF_SGS(16, 2) NF_SGS(32, 2)
   NF_SGS(2, 4) NF_SGS(4, 4) NF_SGS(8, 4) NF_SGS(16, 4)
@@ -889,8 +1048,10 @@ void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int
   }
 }
 
-template void sgs_color<double>(const DCsr&, int, const int*, int, const double*, double, const double*, double*, hipStream_t);
-template void sgs_color<float>(const DCsr&, int, const int*, int, const float*, float, const float*, float*, hipStream_t);
+template void sgs_color<double>(const DCsr&, int, const int*, int, const double*, double, const double*, int64_t, double*,
+                                int64_t, int, hipStream_t);
+template void sgs_color<float>(const DCsr&, int, const int*, int, const float*, float, const float*, int64_t, float*,
+                               int64_t, int, hipStream_t);
 
 // ======================================================= tentative prolongator
 __global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {

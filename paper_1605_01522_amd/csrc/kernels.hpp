@@ -6,18 +6,29 @@
 
 namespace nf {
 
+// Multi-column vectors: nrhs columns, column k at p + k * ld (ld >= length).
+// Every apply-phase kernel processes all columns of a call; columns never
+// mix, so a column's result does not depend on the other columns.
+constexpr int NRMAX = 8;
+
 // ------------------------------------------------------------ vectors
-template <class T> void fill(T* x, T v, int64_t n, hipStream_t s);
+template <class T> void fill(T* x, T v, int64_t n, hipStream_t s);   // one column
 template <class S, class D> void cast_copy(const S* x, D* y, int64_t n, hipStream_t s);
-void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
-template <class T> void sub_scaled(const T* dinv, const T* u, T* x, int64_t n, hipStream_t s);  // x -= dinv .* u
-template <class T> void add_into(const T* d, T* x, int64_t n, hipStream_t s);                   // x += d
-// v = w / *nrm_dev (v = w if the norm is zero)
-void scale_inv_dev(const double* w, double* v, const double* nrm_dev, int64_t n, hipStream_t s);
+template <class T> void fillm(T* x, int64_t ldx, T v, int64_t n, int nrhs, hipStream_t s);
+template <class S, class D> void castm(const S* x, int64_t ldx, D* y, int64_t ldy, int64_t n, int nrhs, hipStream_t s);
+template <class T> void copym(const T* x, int64_t ldx, T* y, int64_t ldy, int64_t n, int nrhs, hipStream_t s);
+// x += d, for the columns whose mask entry is nonzero (mask may be null)
+template <class T> void add_intom(const T* d, int64_t ldd, T* x, int64_t ldx, int64_t n, int nrhs, const int* mask,
+                                  hipStream_t s);
+// x -= dinv .* u
+template <class T> void sub_scaledm(const T* dinv, const T* u, int64_t ldu, T* x, int64_t ldx, int64_t n, int nrhs,
+                                    hipStream_t s);
 // first Chebyshev step from a zero guess: d = dinv .* b * inv_theta; x = d
-template <class T> void cheb_first(const T* b, const T* dinv, T inv_theta, T* d, T* x, int64_t n, hipStream_t s);
+template <class T> void cheb_firstm(const T* b, int64_t ldb, const T* dinv, T inv_theta, T* d, int64_t ldd, T* x,
+                                    int64_t ldx, int64_t n, int nrhs, hipStream_t s);
 // x = M b with a dense row-major FP64 matrix (explicit coarse inverse)
-template <class T> void dense_gemv(const double* M, int n, const T* b, T* x, hipStream_t s);
+template <class T> void dense_gemvm(const double* M, int n, const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs,
+                                    hipStream_t s);
 
 // ------------------------------------------------------------ CSR SpMV
 enum SpmvMode { SPMV_STORE = 0, SPMV_RESID = 1, SPMV_ADD = 2, SPMV_SUB = 3, SPMV_CHEB = 4, SPMV_DSCALE = 5 };
@@ -26,10 +37,12 @@ struct SpmvArgs {
   const T* x = nullptr;     // operand
   T* y = nullptr;           // output (STORE/RESID/ADD/SUB/DSCALE)
   const T* b = nullptr;     // RESID, CHEB
-  const T* dinv = nullptr;  // CHEB, DSCALE
+  const T* dinv = nullptr;  // CHEB, DSCALE (one column, shared)
   T* d = nullptr;           // CHEB (in/out)
   T* xo = nullptr;          // CHEB output iterate (must differ from x)
   T c1 = 0, c2 = 0;         // CHEB: d = c1 d + c2 dinv (b - A x)
+  int64_t ldx = 0, ldy = 0, ldb = 0, ldd = 0, ldxo = 0;   // column strides
+  int nrhs = 1;
 };
 // lanes per row chosen from the mean row length
 int spmv_group(int nr, int64_t nnz);
@@ -49,30 +62,52 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
 // ------------------------------------------------------------ reductions (FP64, deterministic)
 constexpr int RED_BLOCKS = 480;
 constexpr int RED_THREADS = 256;
-// *out = x . y  (partial must hold RED_BLOCKS doubles)
-void dot_dev(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s);
-// GMRES block operations on V (column-major, leading dimension ldv)
-void mdot_partial(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* partial, hipStream_t s);
-void mreduce(const double* partial, int ncols, double* out, int accumulate, hipStream_t s);
-void mupdate_dot(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s);
-void mupdate_norm(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* partial, hipStream_t s);
-void mcombine(const double* V, int64_t ldv, int ncols, const double* y, double* u, int64_t n, int accumulate, hipStream_t s);
-// Arnoldi step j bookkeeping on device: reduce ||w||^2 partials into H(j+1,j),
-// h1 + h2 into H(:,j), apply the stored rotations and a new one, update g,
-// write |g_{j+1}| to res_out.  H is (m+1) x m column-major.
-void givens_step(int j, int m, const double* h1, const double* h2, const double* nrm_partial,
-                 double* H, double* cs, double* sn, double* g, double* hnorm_out, double* res_out, hipStream_t s);
-// y = H(0:k,0:k)^-1 g (upper triangular, after rotations)
-void backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
+// out[k] = x_k . y_k for nrhs columns (partial: RED_BLOCKS * nrhs doubles)
+void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n, int nrhs, double* partial, double* out,
+          hipStream_t s);
+// GMRES block operations, batched over nrhs independent columns.  Column k's
+// Krylov basis is V + k * vs (vectors j at + j * n); h / partial / H etc. use
+// the per-column strides given.  mask (device, may be null): columns with a
+// zero entry are skipped.
+struct GmresLayout {
+  int64_t n = 0;        // vector length
+  int64_t vs = 0;       // per-column stride of V (and of Z for the flexible form)
+  int64_t hs = 0;       // per-column stride of h1, h2 (m + 1)
+  int64_t ps = 0;       // per-column stride of partial ((m + 1) * RED_BLOCKS)
+  int m = 0;            // restart length
+  int nrhs = 1;
+};
+void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double* w, int64_t ldw, double* partial,
+                  const int* mask, hipStream_t s);
+void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out, int accumulate, const int* mask,
+             hipStream_t s);
+void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
+                 double* partial, const int* mask, hipStream_t s);
+void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
+                  double* partial, const int* mask, hipStream_t s);
+// u_k (+)= sum_{j < ncols_k} V_k[j] y_k[j]; ncols per column on the device, max_ncols on the host
+void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
+              int64_t ldu, int accumulate, const int* mask, hipStream_t s);
+// Arnoldi step j bookkeeping per column: reduce ||w||^2 partials into
+// H(j+1,j), h1 + h2 into H(:,j), apply the stored rotations and a new one,
+// update g, write ||w|| and |g_{j+1}| to scal[2k], scal[2k+1].
+void givens_step(const GmresLayout& L, int j, const double* h1, const double* h2, const double* nrm_partial, double* H,
+                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s);
+// y_k = H_k(0:k,0:k)^-1 g_k with k = ncols[col]
+void backsolve(const GmresLayout& L, const int* ncols, const double* H, const double* g, double* y, const int* mask,
+               hipStream_t s);
+// v_k = w_k / nrm[k * stride] (v_k = w_k if the norm is zero)
+void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride, int64_t n,
+                    int nrhs, const int* mask, hipStream_t s);
 
 // ------------------------------------------------------------ multicolour Gauss-Seidel
-// greedy colouring of a node graph (Jones-Plassmann order, splitmix64 keys);
-// returns the number of colours and fills color[node]
+// greedy colouring of a node graph in node order; returns the number of
+// colours and fills color[node]
 int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int* color, hipStream_t s);
 // relax all nodes of one colour: x_r += omega dinv_r (b_r - A_r x) for the b
 // dofs of each listed node, all from the values before the node's update
 template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega,
-                                  const T* rhs, T* x, hipStream_t s);
+                                  const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
 int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kernel
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)

@@ -22,9 +22,22 @@ thread_local size_t* g_acct = nullptr;
 static thread_local std::string g_err;
 
 // ================================================================ helpers
+// Multi-column buffers: every temporary holds NRMAX columns of its length.
+template <class T>
+struct MBuf {
+  DBuf<T> buf;
+  int64_t ld = 0;
+  void alloc(int64_t n) {
+    ld = n > 0 ? n : 1;
+    buf.alloc((size_t)ld * NRMAX);
+  }
+  T* p() const { return buf.p; }
+};
+
 // r_i = b_i - sum_j A_ij x_j over fields [f0, f1) of A (vectors re-based at f0)
 template <class T>
-static void block_resid(const BlockMat& A, int f0, int f1, const T* b, const T* x, T* r, hipStream_t s) {
+static void block_resid(const BlockMat& A, int f0, int f1, const T* b, int64_t ldb, const T* x, int64_t ldx, T* r,
+                        int64_t ldr, int nrhs, hipStream_t s) {
   std::vector<int> o = A.offsets();
   for (int i = f0; i < f1; ++i) {
     bool first = true;
@@ -33,13 +46,16 @@ static void block_resid(const BlockMat& A, int f0, int f1, const T* b, const T* 
       if (!B) continue;
       SpmvArgs<T> a;
       a.x = x + (o[j] - o[f0]);
+      a.ldx = ldx;
       a.y = r + (o[i] - o[f0]);
+      a.ldy = ldr;
       a.b = b + (o[i] - o[f0]);
+      a.ldb = ldb;
+      a.nrhs = nrhs;
       spmv<T>(first ? SPMV_RESID : SPMV_SUB, *B, a, s);
       first = false;
     }
-    if (first && A.size[i] > 0)
-      NF_HIP(hipMemcpyAsync(r + (o[i] - o[f0]), b + (o[i] - o[f0]), sizeof(T) * A.size[i], hipMemcpyDeviceToDevice, s));
+    if (first && A.size[i] > 0) copym<T>(b + (o[i] - o[f0]), ldb, r + (o[i] - o[f0]), ldr, A.size[i], nrhs, s);
   }
 }
 
@@ -53,7 +69,14 @@ template <class T>
 struct Solver {
   int n = 0;
   virtual ~Solver() {}
-  virtual void apply(const T* r, T* z, hipStream_t s) = 0;   // z = M^-1 r
+  // z = M^-1 r for nrhs <= NRMAX columns (column k at r + k ldr, z + k ldz)
+  virtual void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) = 0;
+};
+
+template <class T>
+struct FieldSmootherD {
+  virtual ~FieldSmootherD() {}
+  virtual void apply(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) = 0;
 };
 
 // Chebyshev smoother on D^-1 A over [lambda/ratio, boost*lambda]: three-term
@@ -61,15 +84,10 @@ struct Solver {
 // Algorithm 12.1).  Each step after the first is one fused kernel: residual,
 // direction update and iterate update.
 template <class T>
-struct FieldSmootherD {
-  virtual ~FieldSmootherD() {}
-  virtual void apply(const T* b, T* x, bool zero_guess, hipStream_t s) = 0;
-};
-
-template <class T>
 struct ChebD : FieldSmootherD<T> {
   const DCsr* A = nullptr;
-  DBuf<T> dinv, d, xt;
+  DBuf<T> dinv;
+  MBuf<T> d, xt;
   double theta = 0, delta = 0, sigma = 0;
   int degree = 2, n = 0;
   void setup(const DCsr* A_, const double* dinv64, double lam, const Opts& o, hipStream_t s) {
@@ -86,27 +104,39 @@ struct ChebD : FieldSmootherD<T> {
     sigma = theta / delta;
     degree = o.cheb_degree;
   }
-  void apply(const T* b, T* x, bool zero_guess, hipStream_t s) override {
+  void apply(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
     const T* src;
+    int64_t lds;
     int k0;
     if (zero_guess) {
-      T* dst = (degree % 2 == 1) ? x : xt.p;
-      cheb_first<T>(b, dinv.p, (T)(1.0 / theta), d.p, dst, n, s);
+      const bool to_x = degree % 2 == 1;   // the last write must land in x
+      T* dst = to_x ? x : xt.p();
+      const int64_t ldd = to_x ? ldx : xt.ld;
+      cheb_firstm<T>(b, ldb, dinv.p, (T)(1.0 / theta), d.p(), d.ld, dst, ldd, n, nrhs, s);
       src = dst;
+      lds = ldd;
       k0 = 1;
     } else {
       src = x;
+      lds = ldx;
       k0 = 0;
     }
     double rho = 1.0 / sigma;
     for (int k = k0; k < degree; ++k) {
-      T* dst = (src == x) ? xt.p : x;
+      const bool to_xt = src == x;
+      T* dst = to_xt ? xt.p() : x;
+      const int64_t ldd = to_xt ? xt.ld : ldx;
       SpmvArgs<T> a;
       a.x = src;
+      a.ldx = lds;
       a.b = b;
+      a.ldb = ldb;
       a.dinv = dinv.p;
-      a.d = d.p;
+      a.d = d.p();
+      a.ldd = d.ld;
       a.xo = dst;
+      a.ldxo = ldd;
+      a.nrhs = nrhs;
       if (k == 0) {
         a.c1 = 0;
         a.c2 = (T)(1.0 / theta);
@@ -118,8 +148,9 @@ struct ChebD : FieldSmootherD<T> {
       }
       spmv<T>(SPMV_CHEB, *A, a, s);
       src = dst;
+      lds = ldd;
     }
-    if (src != x) NF_HIP(hipMemcpyAsync(x, src, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    if (src != x) copym<T>(src, lds, x, ldx, n, nrhs, s);
   }
 };
 
@@ -159,48 +190,49 @@ struct SgsD : FieldSmootherD<T> {
     nodes.alloc(list.size());
     NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
     NF_HIP(hipStreamSynchronize(s));
-    // algorithmic bytes of each colour sweep: its rows' entries and row
-    // pointers, node list, right-hand side, D^-1, own x read and written,
-    // and every distinct column value it reads
     // bytes of a sweep are counted only while launch timing is recording
     sweep_bytes = 0.0;
+    sweep_bytes_x = 0.0;
     if (prof_recording()) {
       std::vector<int64_t> cnnz, ccols;
       color_traffic(*A, b, nodes.p, off, cnnz, ccols, s);
       const double sz = sizeof(T);
       for (int c = 0; c < nc; ++c) {
         const double rows = (double)(off[c + 1] - off[c]) * b;
-        sweep_bytes += cnnz[c] * (sz + 4) + rows * (4 + 3 * sz) + 4.0 * (off[c + 1] - off[c]) + sz * ccols[c];
+        sweep_bytes += cnnz[c] * (sz + 4) + rows * 4 + 4.0 * (off[c + 1] - off[c]) + rows * sz;
+        sweep_bytes_x += rows * 3 * sz + sz * ccols[c];
       }
     }
   }
   // algorithmic bytes of one sweep over all colours: every colour's rows'
-  // entries and pointers, node ids, right-hand side, D^-1, own x read and
-  // written, and each distinct column value it reads
-  double sweep_bytes = 0.0;
-  void sweep(bool forward, const T* rhs, T* x, hipStream_t s) {
+  // entries and pointers, node ids and D^-1 (once), and per right-hand side
+  // its rhs, own x read and written and each distinct column value read
+  double sweep_bytes = 0.0, sweep_bytes_x = 0.0;
+  void sweep(bool forward, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const int nc = (int)off.size() - 1;
     const int slot = prof_begin(s);
     for (int i = 0; i < nc; ++i) {
       const int c = forward ? i : nc - 1 - i;
-      sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, x, s);
+      sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     }
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-    prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 10 + 6) * 10 + (sizeof(T) == 4 ? 1 : 0), sweep_bytes, nc);
+    prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 10 + 6) * 10 + (sizeof(T) == 4 ? 1 : 0),
+             sweep_bytes + nrhs * sweep_bytes_x, nc);
   }
-  void apply(const T* rhs, T* x, bool zero_guess, hipStream_t s) override {
-    if (zero_guess) fill<T>(x, (T)0, n, s);
+  void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
+    if (zero_guess) fillm<T>(x, ldx, (T)0, n, nrhs, s);
     for (int st = 0; st < steps; ++st) {
-      sweep(true, rhs, x, s);
-      sweep(false, rhs, x, s);
+      sweep(true, rhs, ldr, x, ldx, nrhs, s);
+      sweep(false, rhs, ldr, x, ldx, nrhs, s);
     }
   }
 };
 
-// One BGS sweep over fields [0, N) of a block matrix with per-field inner
+// One BGS sweep over fields [f0, f1) of a block matrix with per-field inner
 // solves: dd_i = S_i(res_i - sum_{j done} A_ij dd_j).
 template <class T, class Inner>
-static void bgs_sweep(const BlockMat& A, int f0, int f1, int order, const T* res, T* dd, T* t, Inner inner, hipStream_t s) {
+static void bgs_sweep(const BlockMat& A, int f0, int f1, int order, const T* res, int64_t ldres, T* dd, int64_t lddd,
+                      T* t, int64_t ldt, int nrhs, Inner inner, hipStream_t s) {
   std::vector<int> o = A.offsets();
   std::vector<int> seq;
   for (int i = f0; i < f1; ++i) seq.push_back(i);
@@ -213,41 +245,51 @@ static void bgs_sweep(const BlockMat& A, int f0, int f1, int order, const T* res
       if (j == i || !done[j] || !A.at(i, j)) continue;
       SpmvArgs<T> a;
       a.x = dd + (o[j] - o[f0]);
+      a.ldx = lddd;
       a.y = t;
+      a.ldy = ldt;
       a.b = res + oi;
+      a.ldb = ldres;
+      a.nrhs = nrhs;
       spmv<T>(first ? SPMV_RESID : SPMV_SUB, *A.at(i, j), a, s);
       first = false;
     }
-    inner(i, first ? res + oi : (const T*)t, dd + oi);
+    if (first) inner(i, res + oi, ldres, dd + oi, lddd);
+    else inner(i, (const T*)t, ldt, dd + oi, lddd);
     done[i] = 1;
   }
 }
 
 // Level smoother of a (monolithic) hierarchy: one BGS sweep over the level's
-// blocks with each field's Chebyshev smoother in place of the block solve
-// (a single field: the Chebyshev smoother itself).
+// blocks with each field's smoother in place of the block solve (a single
+// field: the field smoother itself).
 template <class T>
 struct LevelSmootherD {
   const BlockMat* A = nullptr;
   int order = 1;
   std::vector<std::unique_ptr<FieldSmootherD<T>>> cheb;
-  DBuf<T> r, d, t;
-  void smooth(const T* b, T* x, bool zero_guess, hipStream_t s) {
+  MBuf<T> r, d, t;
+  void smooth(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) {
     const int N = A->N;
     if (N == 1) {
-      cheb[0]->apply(b, x, zero_guess, s);
+      cheb[0]->apply(b, ldb, x, ldx, nrhs, zero_guess, s);
       return;
     }
     const T* res = b;
+    int64_t ldres = ldb;
     if (!zero_guess) {
-      block_resid<T>(*A, 0, N, b, x, r.p, s);
-      res = r.p;
+      block_resid<T>(*A, 0, N, b, ldb, x, ldx, r.p(), r.ld, nrhs, s);
+      res = r.p();
+      ldres = r.ld;
     }
-    T* dd = zero_guess ? x : d.p;
+    T* dd = zero_guess ? x : d.p();
+    const int64_t lddd = zero_guess ? ldx : d.ld;
     const int ord = order == 2 ? (zero_guess ? 0 : 1) : order;
-    bgs_sweep<T>(*A, 0, N, ord, res, dd, t.p,
-                 [&](int i, const T* rhs, T* out) { cheb[i]->apply(rhs, out, true, s); }, s);
-    if (!zero_guess) add_into<T>(d.p, x, A->total(), s);
+    bgs_sweep<T>(*A, 0, N, ord, res, ldres, dd, lddd, t.p(), t.ld, nrhs,
+                 [&](int i, const T* rhs, int64_t ldrhs, T* out, int64_t ldout) {
+                   cheb[i]->apply(rhs, ldrhs, out, ldout, nrhs, true, s);
+                 }, s);
+    if (!zero_guess) add_intom<T>(d.p(), d.ld, x, ldx, A->total(), nrhs, nullptr, s);
   }
 };
 
@@ -255,40 +297,50 @@ template <class T>
 struct AmgSolverD : Solver<T> {
   Hierarchy* H = nullptr;
   std::vector<LevelSmootherD<T>> sm;
-  std::vector<DBuf<T>> res, bl, xl;   // per level: residual; right-hand side and iterate (levels > 0)
-  void vcycle(int l, const T* b, T* x, hipStream_t s) {
+  std::vector<MBuf<T>> res, bl, xl;   // per level: residual; right-hand side and iterate (levels > 0)
+  void vcycle(int l, const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const Level& L = H->lev[l];
     if (l == (int)H->lev.size() - 1) {
-      dense_gemv<T>(H->coarse_inv.p, H->ncoarse, b, x, s);
+      dense_gemvm<T>(H->coarse_inv.p, H->ncoarse, b, ldb, x, ldx, nrhs, s);
       return;
     }
-    sm[l].smooth(b, x, true, s);
-    block_resid<T>(L.A, 0, L.A.N, b, x, res[l].p, s);
+    sm[l].smooth(b, ldb, x, ldx, nrhs, true, s);
+    block_resid<T>(L.A, 0, L.A.N, b, ldb, x, ldx, res[l].p(), res[l].ld, nrhs, s);
     const Level& C = H->lev[l + 1];
     std::vector<int> o = L.A.offsets(), oc = C.A.offsets();
     for (int i = 0; i < L.A.N; ++i) {
       SpmvArgs<T> a;
-      a.x = res[l].p + o[i];
-      a.y = bl[l + 1].p + oc[i];
+      a.x = res[l].p() + o[i];
+      a.ldx = res[l].ld;
+      a.y = bl[l + 1].p() + oc[i];
+      a.ldy = bl[l + 1].ld;
+      a.nrhs = nrhs;
       spmv<T>(SPMV_STORE, *L.R[i], a, s);
     }
-    vcycle(l + 1, bl[l + 1].p, xl[l + 1].p, s);
+    vcycle(l + 1, bl[l + 1].p(), bl[l + 1].ld, xl[l + 1].p(), xl[l + 1].ld, nrhs, s);
     for (int i = 0; i < L.A.N; ++i) {
       SpmvArgs<T> a;
-      a.x = xl[l + 1].p + oc[i];
+      a.x = xl[l + 1].p() + oc[i];
+      a.ldx = xl[l + 1].ld;
       a.y = x + o[i];
+      a.ldy = ldx;
+      a.nrhs = nrhs;
       spmv<T>(SPMV_ADD, *L.P[i], a, s);
     }
-    sm[l].smooth(b, x, false, s);
+    sm[l].smooth(b, ldb, x, ldx, nrhs, false, s);
   }
-  void apply(const T* r, T* z, hipStream_t s) override { vcycle(0, r, z, s); }
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
+    vcycle(0, r, ldr, z, ldz, nrhs, s);
+  }
 };
 
 template <class T>
 struct LuSolverD : Solver<T> {
   DBuf<double> inv;
   int nn = 0;
-  void apply(const T* r, T* z, hipStream_t s) override { dense_gemv<T>(inv.p, nn, r, z, s); }
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
+    dense_gemvm<T>(inv.p, nn, r, ldr, z, ldz, nrhs, s);
+  }
 };
 
 template <class T>
@@ -296,19 +348,24 @@ struct BgsSolverD : Solver<T> {
   const BlockMat* A = nullptr;
   int f0 = 0, f1 = 0, sweeps = 1, order = 1;
   std::vector<std::unique_ptr<Solver<T>>> child;
-  DBuf<T> res, d, t;
-  void apply(const T* r, T* z, hipStream_t s) override {
+  MBuf<T> res, d, t;
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
     for (int sw = 0; sw < sweeps; ++sw) {
       const T* rr = r;
+      int64_t ldrr = ldr;
       if (sw > 0) {
-        block_resid<T>(*A, f0, f1, r, z, res.p, s);
-        rr = res.p;
+        block_resid<T>(*A, f0, f1, r, ldr, z, ldz, res.p(), res.ld, nrhs, s);
+        rr = res.p();
+        ldrr = res.ld;
       }
-      T* dd = sw == 0 ? z : d.p;
+      T* dd = sw == 0 ? z : d.p();
+      const int64_t lddd = sw == 0 ? ldz : d.ld;
       const int ord = order == 2 ? (sw % 2) : order;
-      bgs_sweep<T>(*A, f0, f1, ord, rr, dd, t.p,
-                   [&](int i, const T* rhs, T* out) { child[i - f0]->apply(rhs, out, s); }, s);
-      if (sw > 0) add_into<T>(d.p, z, this->n, s);
+      bgs_sweep<T>(*A, f0, f1, ord, rr, ldrr, dd, lddd, t.p(), t.ld, nrhs,
+                   [&](int i, const T* rhs, int64_t ldrhs, T* out, int64_t ldout) {
+                     child[i - f0]->apply(rhs, ldrhs, out, ldout, nrhs, s);
+                   }, s);
+      if (sw > 0) add_intom<T>(d.p(), d.ld, z, ldz, this->n, nrhs, nullptr, s);
     }
   }
 };
@@ -320,39 +377,51 @@ struct SimpleSolverD : Solver<T> {
   const BlockMat* A = nullptr;
   int f0 = 0, f1 = 0, g = 0, sweeps = 1;
   std::unique_ptr<Solver<T>> pred, schur;
-  DBuf<T> dtinv, res, d, t, u;
-  void apply(const T* r, T* z, hipStream_t s) override {
+  DBuf<T> dtinv;
+  MBuf<T> res, d, t, u;
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
     std::vector<int> o = A->offsets();
     const int n1 = o[g] - o[f0];
     for (int sw = 0; sw < sweeps; ++sw) {
       const T* rr = r;
+      int64_t ldrr = ldr;
       if (sw > 0) {
-        block_resid<T>(*A, f0, f1, r, z, res.p, s);
-        rr = res.p;
+        block_resid<T>(*A, f0, f1, r, ldr, z, ldz, res.p(), res.ld, nrhs, s);
+        rr = res.p();
+        ldrr = res.ld;
       }
-      T* dd = sw == 0 ? z : d.p;
-      pred->apply(rr, dd, s);
+      T* dd = sw == 0 ? z : d.p();
+      const int64_t lddd = sw == 0 ? ldz : d.ld;
+      pred->apply(rr, ldrr, dd, lddd, nrhs, s);
       bool first = true;
       for (int j = f0; j < g; ++j) {
         if (!A->at(g, j)) continue;
         SpmvArgs<T> a;
         a.x = dd + (o[j] - o[f0]);
-        a.y = t.p;
+        a.ldx = lddd;
+        a.y = t.p();
+        a.ldy = t.ld;
         a.b = rr + n1;
+        a.ldb = ldrr;
+        a.nrhs = nrhs;
         spmv<T>(first ? SPMV_RESID : SPMV_SUB, *A->at(g, j), a, s);
         first = false;
       }
-      schur->apply(first ? rr + n1 : (const T*)t.p, dd + n1, s);
+      if (first) schur->apply(rr + n1, ldrr, dd + n1, lddd, nrhs, s);
+      else schur->apply(t.p(), t.ld, dd + n1, lddd, nrhs, s);
       for (int j = f0; j < g; ++j) {
         if (!A->at(j, g)) continue;
         const int oj = o[j] - o[f0];
         SpmvArgs<T> a;
         a.x = dd + n1;
-        a.y = u.p;
+        a.ldx = lddd;
+        a.y = u.p();
+        a.ldy = u.ld;
+        a.nrhs = nrhs;
         spmv<T>(SPMV_STORE, *A->at(j, g), a, s);
-        sub_scaled<T>(dtinv.p + oj, u.p, dd + oj, A->size[j], s);
+        sub_scaledm<T>(dtinv.p + oj, u.p(), u.ld, dd + oj, lddd, A->size[j], nrhs, s);
       }
-      if (sw > 0) add_into<T>(d.p, z, this->n, s);
+      if (sw > 0) add_intom<T>(d.p(), d.ld, z, ldz, this->n, nrhs, nullptr, s);
     }
   }
 };
@@ -472,9 +541,12 @@ struct nfield_ctx {
   // GMRES workspace
   int ws_m = 0;
   nf::DBuf<double> V, Z, w, z, r, u, H, cs, sn, g, y, h1, h2, partial, scal;
+  nf::DBuf<int> imask;
   double* pinned = nullptr;
+  int* pinned_i = nullptr;
   ~nfield_ctx() {
     if (pinned) (void)hipHostFree(pinned);
+    if (pinned_i) (void)hipHostFree(pinned_i);
   }
 };
 
@@ -662,127 +734,189 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
 }
 
 // ================================================================= GMRES
+// Krylov workspace sized for NRMAX columns of restart length m.
 static void ensure_workspace(nfield_ctx& C, int m, int flexible) {
   const int64_t n = C.Aglob.nr;
-  if (C.ws_m < m || (flexible && C.Z.n < (size_t)n * m)) {
-    C.V.alloc((size_t)n * (m + 1));
-    if (flexible) C.Z.alloc((size_t)n * m);
-    C.H.alloc((size_t)(m + 1) * m);
-    C.cs.alloc(m);
-    C.sn.alloc(m);
-    C.g.alloc(m + 1);
-    C.y.alloc(m);
-    C.h1.alloc(m + 1);
-    C.h2.alloc(m + 1);
-    C.partial.alloc((size_t)RED_BLOCKS * (m + 1));
+  if (C.ws_m < m || (flexible && C.Z.n < (size_t)n * m * NRMAX)) {
+    C.V.alloc((size_t)n * (m + 1) * NRMAX);
+    if (flexible) C.Z.alloc((size_t)n * m * NRMAX);
+    C.H.alloc((size_t)(m + 1) * m * NRMAX);
+    C.cs.alloc((size_t)m * NRMAX);
+    C.sn.alloc((size_t)m * NRMAX);
+    C.g.alloc((size_t)(m + 1) * NRMAX);
+    C.y.alloc((size_t)m * NRMAX);
+    C.h1.alloc((size_t)(m + 1) * NRMAX);
+    C.h2.alloc((size_t)(m + 1) * NRMAX);
+    C.partial.alloc((size_t)RED_BLOCKS * (m + 1) * NRMAX);
     C.ws_m = m;
   }
   if (!C.w.p) {
-    C.w.alloc(n);
-    C.z.alloc(n);
-    C.r.alloc(n);
-    C.u.alloc(n);
-    C.scal.alloc(8);
+    C.w.alloc((size_t)n * NRMAX);
+    C.z.alloc((size_t)n * NRMAX);
+    C.r.alloc((size_t)n * NRMAX);
+    C.u.alloc((size_t)n * NRMAX);
+    C.scal.alloc(4 * NRMAX);
+    C.imask.alloc(3 * NRMAX);
   }
-  if (!C.pinned) NF_HIP(hipHostMalloc((void**)&C.pinned, 8 * sizeof(double), hipHostMallocDefault));
+  if (!C.pinned) NF_HIP(hipHostMalloc((void**)&C.pinned, 64 * sizeof(double), hipHostMallocDefault));
+  if (!C.pinned_i) NF_HIP(hipHostMalloc((void**)&C.pinned_i, 64 * sizeof(int), hipHostMallocDefault));
 }
 
-static void precond(nfield_ctx& C, const double* r, double* z, hipStream_t s) {
+static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
   if (C.root64) {
-    C.root64->apply(r, z, s);
+    C.root64->apply(r, ldr, z, ldz, nrhs, s);
   } else {
     const int64_t n = C.Aglob.nr;
-    cast_copy<double, float>(r, C.r32.p, n, s);
-    C.root32->apply(C.r32.p, C.z32.p, s);
-    cast_copy<float, double>(C.z32.p, z, n, s);
+    castm<double, float>(r, ldr, C.r32.p, n, n, nrhs, s);
+    C.root32->apply(C.r32.p, n, C.z32.p, n, nrhs, s);
+    castm<float, double>(C.z32.p, n, z, ldz, n, nrhs, s);
   }
 }
 
-static double read_scalar(nfield_ctx& C, const double* dev, hipStream_t s) {
-  NF_HIP(hipMemcpyAsync(C.pinned, dev, sizeof(double), hipMemcpyDeviceToHost, s));
-  NF_HIP(hipStreamSynchronize(s));
-  return C.pinned[0];
-}
-
-static double true_residual(nfield_ctx& C, const double* b, const double* x, hipStream_t s) {
+// ||b_k - A x_k|| for nrhs columns, read back to host res[k]
+static void true_residuals(nfield_ctx& C, const double* b, int64_t ldb, const double* x, int64_t ldx, int nrhs,
+                           double* res, hipStream_t s) {
   const int64_t n = C.Aglob.nr;
   SpmvArgs<double> a;
   a.x = x;
+  a.ldx = ldx;
   a.y = C.r.p;
+  a.ldy = n;
   a.b = b;
+  a.ldb = ldb;
+  a.nrhs = nrhs;
   spmv<double>(SPMV_RESID, C.Aglob, a, s);
-  dot_dev(C.r.p, C.r.p, n, C.partial.p, C.scal.p, s);
-  return std::sqrt(read_scalar(C, C.scal.p, s));
+  dotm(C.r.p, n, C.r.p, n, n, nrhs, C.partial.p, C.scal.p, s);
+  NF_HIP(hipMemcpyAsync(C.pinned, C.scal.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nrhs; ++k) res[k] = std::sqrt(C.pinned[k]);
 }
 
-__global__ void k_init_g(double* g, int m, double beta) {
-  const int i = threadIdx.x + blockIdx.x * blockDim.x;
-  if (i <= m) g[i] = i == 0 ? beta : 0.0;
-}
-__global__ void k_scale(const double* x, double a, double* y, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) y[i] = a * x[i];
+static void upload_ints(nfield_ctx& C, const std::vector<int>& v, int* dev, hipStream_t s) {
+  for (size_t k = 0; k < v.size(); ++k) C.pinned_i[k] = v[k];
+  NF_HIP(hipMemcpyAsync(dev, C.pinned_i, sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
+  NF_HIP(hipStreamSynchronize(s));   // the staging buffer is reused right away
 }
 
-static nfield_stats gmres(nfield_ctx& C, const double* b, double* x, const nfield_solve_opts& so, hipStream_t s) {
+__global__ void k_init_gm(double* g, int m, const double* beta, const int* mask) {
+  const int k = blockIdx.x, i = threadIdx.x;
+  if (mask && !mask[k]) return;
+  if (i <= m) g[(int64_t)k * (m + 1) + i] = i == 0 ? beta[k] : 0.0;
+}
+
+// Restarted GMRES(m) with right preconditioning (Sec. 3.2), plain or
+// flexible, on nrhs independent columns at once.  Each column runs its own
+// Arnoldi process (CGS2, Givens rotations on the device, its own
+// convergence test and restarts); the columns share only the kernel
+// launches, so a column's iterates do not depend on the other columns.
+static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                  const nfield_solve_opts& so, nfield_stats* st, hipStream_t s) {
   const int64_t n = C.Aglob.nr;
   const int m = so.restart;
-  nfield_stats st;
-  std::memset(&st, 0, sizeof(st));
   const bool flex = so.flexible != 0;
   ensure_workspace(C, m, flex);
-  const double beta0 = true_residual(C, b, x, s);
-  if (!std::isfinite(beta0)) { st.status = NFIELD_ENAN; return st; }
-  if (beta0 == 0.0) { st.status = NFIELD_OK; return st; }
-  int total = 0;
+  GmresLayout L;
+  L.n = n;
+  L.vs = (int64_t)(m + 1) * n;
+  L.hs = m + 1;
+  L.ps = (int64_t)(m + 1) * RED_BLOCKS;
+  L.m = m;
+  L.nrhs = nrhs;
+  GmresLayout LZ = L;
+  LZ.vs = (int64_t)m * n;
+  int* mask = C.imask.p;            // columns in the current Arnoldi cycle
+  int* part = C.imask.p + NRMAX;    // columns that took part in the cycle
+  int* jend = C.imask.p + 2 * NRMAX;
+  std::vector<double> beta0(nrhs), beta(nrhs);
+  std::vector<int> total(nrhs, 0), done(nrhs, 0), cyc(nrhs, 0), je(nrhs, 0);
+  for (int k = 0; k < nrhs; ++k) std::memset(&st[k], 0, sizeof(nfield_stats));
+  true_residuals(C, b, ldb, x, ldx, nrhs, beta0.data(), s);
+  for (int k = 0; k < nrhs; ++k) {
+    if (!std::isfinite(beta0[k])) { st[k].status = NFIELD_ENAN; done[k] = 1; }
+    else if (beta0[k] == 0.0) { st[k].status = NFIELD_OK; done[k] = 1; }
+  }
   bool first = true;
-  const int nb = (int)((n + 255) / 256);
   while (true) {
-    const double beta = first ? beta0 : true_residual(C, b, x, s);
+    if (first) beta = beta0;
+    else true_residuals(C, b, ldb, x, ldx, nrhs, beta.data(), s);
     first = false;
-    st.relres = beta / beta0;
-    if (!std::isfinite(beta)) { st.status = NFIELD_ENAN; break; }
-    if (beta / beta0 < so.rtol) { st.status = NFIELD_OK; break; }
-    if (total >= so.maxit) { st.status = NFIELD_NOT_CONVERGED; break; }
-    if (total > 0) st.restarts++;
-    hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, C.r.p, 1.0 / beta, C.V.p, n);
-    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(64), 0, s, C.g.p, m, beta);
-    int jend = 0;
+    int nact = 0;
+    for (int k = 0; k < nrhs; ++k) {
+      cyc[k] = 0;
+      if (done[k]) continue;
+      st[k].relres = beta[k] / beta0[k];
+      if (!std::isfinite(beta[k])) { st[k].status = NFIELD_ENAN; done[k] = 1; continue; }
+      if (beta[k] / beta0[k] < so.rtol) { st[k].status = NFIELD_OK; done[k] = 1; continue; }
+      if (total[k] >= so.maxit) { st[k].status = NFIELD_NOT_CONVERGED; done[k] = 1; continue; }
+      if (total[k] > 0) st[k].restarts++;
+      cyc[k] = 1;
+      ++nact;
+    }
+    if (nact == 0) break;
+    upload_ints(C, cyc, mask, s);
+    for (int k = 0; k < nrhs; ++k) C.pinned[k] = beta[k];
+    NF_HIP(hipMemcpyAsync(C.scal.p + 2 * NRMAX, C.pinned, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+    // v_0 = r / beta (r holds the residuals of the last true_residuals call)
+    scale_inv_devm(C.r.p, n, C.V.p, L.vs, C.scal.p + 2 * NRMAX, 1, n, nrhs, mask, s);
+    hipLaunchKernelGGL(k_init_gm, dim3(nrhs), dim3(64), 0, s, C.g.p, m, C.scal.p + 2 * NRMAX, mask);
+    NF_HIP(hipStreamSynchronize(s));   // the beta staging buffer is reused below
+    std::vector<int> in_cycle = cyc;
+    std::fill(je.begin(), je.end(), 0);
     for (int j = 0; j < m; ++j) {
       double* vj = C.V.p + (int64_t)j * n;
       double* zj = flex ? C.Z.p + (int64_t)j * n : C.z.p;
-      precond(C, vj, zj, s);
+      const int64_t ldz = flex ? LZ.vs : n;
+      precond(C, vj, L.vs, zj, ldz, nrhs, s);
       SpmvArgs<double> a;
       a.x = zj;
+      a.ldx = ldz;
       a.y = C.w.p;
+      a.ldy = n;
+      a.nrhs = nrhs;
       spmv<double>(SPMV_STORE, C.Aglob, a, s);
       // classical Gram-Schmidt, twice
-      mdot_partial(C.V.p, n, j + 1, C.w.p, n, C.partial.p, s);
-      mreduce(C.partial.p, j + 1, C.h1.p, 0, s);
-      mupdate_dot(C.V.p, n, j + 1, C.h1.p, C.w.p, n, C.partial.p, s);
-      mreduce(C.partial.p, j + 1, C.h2.p, 0, s);
-      mupdate_norm(C.V.p, n, j + 1, C.h2.p, C.w.p, n, C.partial.p, s);
-      givens_step(j, m, C.h1.p, C.h2.p, C.partial.p, C.H.p, C.cs.p, C.sn.p, C.g.p, C.scal.p + 1, C.scal.p + 2, s);
-      scale_inv_dev(C.w.p, C.V.p + (int64_t)(j + 1) * n, C.scal.p + 1, n, s);
-      NF_HIP(hipMemcpyAsync(C.pinned + 1, C.scal.p + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      mdot_partial(L, C.V.p, j + 1, C.w.p, n, C.partial.p, mask, s);
+      mreduce(L, C.partial.p, j + 1, C.h1.p, 0, mask, s);
+      mupdate_dot(L, C.V.p, j + 1, C.h1.p, C.w.p, n, C.partial.p, mask, s);
+      mreduce(L, C.partial.p, j + 1, C.h2.p, 0, mask, s);
+      mupdate_norm(L, C.V.p, j + 1, C.h2.p, C.w.p, n, C.partial.p, mask, s);
+      givens_step(L, j, C.h1.p, C.h2.p, C.partial.p, C.H.p, C.cs.p, C.sn.p, C.g.p, C.scal.p, mask, s);
+      scale_inv_devm(C.w.p, n, C.V.p + (int64_t)(j + 1) * n, L.vs, C.scal.p, 2, n, nrhs, mask, s);
+      NF_HIP(hipMemcpyAsync(C.pinned, C.scal.p, 2 * sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
       NF_HIP(hipStreamSynchronize(s));
-      ++total;
-      jend = j + 1;
-      const double hn = C.pinned[1], res = C.pinned[2];
-      if (!std::isfinite(res)) break;
-      if (hn <= 1e-300 || res / beta0 < so.rtol || total >= so.maxit) break;
+      bool changed = false;
+      int left = 0;
+      for (int k = 0; k < nrhs; ++k) {
+        if (!cyc[k]) continue;
+        ++total[k];
+        je[k] = j + 1;
+        const double hn = C.pinned[2 * k], res = C.pinned[2 * k + 1];
+        if (!std::isfinite(res) || hn <= 1e-300 || res / beta0[k] < so.rtol || total[k] >= so.maxit) {
+          cyc[k] = 0;
+          changed = true;
+        } else {
+          ++left;
+        }
+      }
+      if (left == 0) break;
+      if (changed) upload_ints(C, cyc, mask, s);
     }
-    backsolve(jend, m, C.H.p, C.g.p, C.y.p, s);
+    // end of the cycle: y = H^-1 g and the solution update for every column
+    // that took part
+    upload_ints(C, in_cycle, part, s);
+    upload_ints(C, je, jend, s);
+    int maxj = 0;
+    for (int k = 0; k < nrhs; ++k) maxj = std::max(maxj, je[k]);
+    backsolve(L, jend, C.H.p, C.g.p, C.y.p, part, s);
     if (flex) {
-      mcombine(C.Z.p, n, jend, C.y.p, x, n, 1, s);
+      mcombine(LZ, C.Z.p, jend, maxj, C.y.p, x, ldx, 1, part, s);
     } else {
-      mcombine(C.V.p, n, jend, C.y.p, C.u.p, n, 0, s);
-      precond(C, C.u.p, C.z.p, s);
-      axpy(1.0, C.z.p, x, n, s);
+      mcombine(L, C.V.p, jend, maxj, C.y.p, C.u.p, n, 0, part, s);
+      precond(C, C.u.p, n, C.z.p, n, nrhs, s);
+      add_intom<double>(C.z.p, n, x, ldx, n, nrhs, part, s);
     }
   }
-  st.iters = total;
-  return st;
+  for (int k = 0; k < nrhs; ++k) st[k].iters = total[k];
 }
 
 // host-side checks of one input block (before any device work)
@@ -885,8 +1019,8 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
       if (b) make_fp32(*b, s);
     C.root32 = build<float>(C, C.spec, C.A, C.F, 0, C.N, s);
     if (!C.r32.p) {
-      C.r32.alloc(C.Aglob.nr);
-      C.z32.alloc(C.Aglob.nr);
+      C.r32.alloc((size_t)C.Aglob.nr * NRMAX);
+      C.z32.alloc((size_t)C.Aglob.nr * NRMAX);
     }
   } else {
     C.root64 = build<double>(C, C.spec, C.A, C.F, 0, C.N, s);
@@ -1056,7 +1190,10 @@ nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, 
   g_acct = &ctx->bytes;
   try {
     const int64_t n = ctx->Aglob.nr;
-    for (int k = 0; k < nrhs; ++k) precond(*ctx, r + k * n, z + k * n, s);
+    for (int k = 0; k < nrhs; k += NRMAX) {
+      const int nb = std::min(NRMAX, nrhs - k);
+      precond(*ctx, r + k * n, n, z + k * n, n, nb, s);
+    }
     NF_HIP(hipGetLastError());
     g_acct = prev;
     return NFIELD_OK;
@@ -1071,10 +1208,13 @@ nfield_status nfield_matvec(nfield_ctx* ctx, const double* x, double* y, int32_t
   hipStream_t s = (hipStream_t)hip_stream;
   try {
     const int64_t n = ctx->Aglob.nr;
-    for (int k = 0; k < nrhs; ++k) {
+    for (int k = 0; k < nrhs; k += NRMAX) {
       SpmvArgs<double> a;
       a.x = x + k * n;
+      a.ldx = n;
       a.y = y + k * n;
+      a.ldy = n;
+      a.nrhs = std::min(NRMAX, nrhs - k);
       spmv<double>(SPMV_STORE, ctx->Aglob, a, s);
     }
     NF_HIP(hipGetLastError());
@@ -1100,21 +1240,23 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
   try {
     const int64_t n = ctx->Aglob.nr;
     int worst = NFIELD_OK;
-    for (int k = 0; k < nrhs; ++k) {
+    std::vector<nfield_stats> st(NRMAX);
+    for (int k = 0; k < nrhs; k += NRMAX) {
+      const int nb = std::min(NRMAX, nrhs - k);
       const auto t0 = std::chrono::steady_clock::now();
-      nfield_stats st = gmres(*ctx, b + k * n, x + k * n, so, s);
+      gmres(*ctx, b + k * n, n, x + k * n, n, nb, so, st.data(), s);
       NF_HIP(hipStreamSynchronize(s));
-      st.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      st.setup_s = ctx->setup_s;
-      if (stats) stats[k] = st;
-      if (st.status < 0) {
-        g_err = "nfield_gmres_solve: non-finite value in the iteration";
-        g_acct = prev;
-        return (nfield_status)st.status;
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int q = 0; q < nb; ++q) {
+        st[q].solve_s = dt;
+        st[q].setup_s = ctx->setup_s;
+        if (stats) stats[k + q] = st[q];
+        if (st[q].status < 0) worst = std::min(worst, st[q].status);
+        else if (worst >= 0 && st[q].status > worst) worst = st[q].status;
       }
-      if (st.status > worst) worst = st.status;
     }
     g_acct = prev;
+    if (worst < 0) g_err = "nfield_gmres_solve: non-finite value in the right-hand side or the iteration";
     return (nfield_status)worst;
   } catch (NfError& e) {
     g_acct = prev;
