@@ -317,8 +317,155 @@ def request_rhs(req, n):
     return uniform_rhs(n, req["nrhs"], req["rhs_seed"])
 
 
-def _not_yet(*a, **k):
-    raise NotImplementedError
+# --------------------------------------------------------------------------
+# Lung-like system: tissue (T), airway tree (W), volume constraints (L)
+# --------------------------------------------------------------------------
+def _acinus_constraint_rows(n, nacini, m, seed, free_map):
+    """B_k u = volume change of acinus k (an m^3 element sub-block of the n^3
+    box), written as the surface integral of u.n over the sub-block's
+    faces: for a face node, +-h^2 times its trapezoid weight on that face
+    (1 inside the face, 1/2 on a face edge, 1/4 at a face corner) in the
+    component normal to the face.  Origins are drawn without replacement."""
+    h = 1.0 / n
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xAC1]))
+    span = n - m + 1
+    flat = rng.choice(span ** 3, size=nacini, replace=False)
+    org = np.stack([flat % span, (flat // span) % span, flat // (span * span)], axis=1)
+    ln = np.arange(m + 1)
+    wts = np.where((ln == 0) | (ln == m), 0.5, 1.0)
+    rows, cols, vals = [], [], []
+    n1 = n + 1
+    for k, (ox, oy, oz) in enumerate(org):
+        entries = {}
+        for c in range(3):                       # faces normal to axis c
+            a1, a2 = [d for d in range(3) if d != c]
+            for side, sign in ((0, -1.0), (m, 1.0)):
+                g1, g2 = np.meshgrid(ln, ln, indexing="ij")
+                idx = np.zeros((3,) + g1.shape, int)
+                idx[c] = side
+                idx[a1] = g1
+                idx[a2] = g2
+                gi = idx[0] + ox
+                gj = idx[1] + oy
+                gk = idx[2] + oz
+                node = (gk * n1 + gj) * n1 + gi
+                w = sign * h * h * wts[g1] * wts[g2]
+                for nd, ww in zip(node.ravel(), w.ravel()):
+                    dof = free_map[nd * 3 + c]
+                    if dof >= 0:
+                        entries[dof] = entries.get(dof, 0.0) + ww
+        ks = sorted(entries)
+        rows += [k] * len(ks)
+        cols += ks
+        vals += [entries[q] for q in ks]
+    return rows, cols, vals
 
 
-lung3d = _not_yet
+def lung3d(n=64, depth=12, acinus=8, E=1.0, nu=0.45, dt=1.0, seed=0, nrhs=1, rt_scale=None):
+    """Tissue: Q1 linear elasticity (the Neo-Hookean model linearised at the
+    reference state) on an n^3 box, clamped at z = 0, K u - B^T lambda = f.
+
+    Airway: a binary tree of the given depth (2^(depth+1) - 1 segments in heap
+    order, root 0, children 2s+1 and 2s+2), 2 dofs per segment: the pressure
+    p_s at its distal node and its flow q_s (towards the acini).  Segment
+    resistances R_s are log-uniform in [1e-2, 1]; the pressure upstream of the
+    root (the mouth) is 0.  Terminal segment k feeds acinus k through an
+    acinar resistance Rt_k = rt_scale * (log-uniform in [1e-2, 1]); the default
+    rt_scale = 2^depth makes the 2^depth acini in parallel as resistive as one
+    segment.  The multiplier lambda_k is the pressure in acinus k.
+
+    The airway block is the Hessian of the convex quadratic
+        Phi(p, q) = 1/2 sum_s R_s (q_s - dp_s / R_s)^2 + 1/2 p^T L p,
+    dp_s = pressure drop along the segment (or along segment + acinus), L the
+    weighted tree Laplacian grounded at the mouth and (through Rt_k) at the
+    acini, so it is symmetric positive definite.  Its stationarity conditions
+    are exactly the physics: Poiseuille on every segment,
+        R_s q_s - (p_parent - p_s) = 0                  (internal flow rows)
+        (R_s + Rt_k) q_s - (p_parent - lambda_k) = 0    (terminal flow rows)
+    and mass conservation at every node, which the pressure rows state as
+        2 (L p)_s + q_s - sum_c q_c = 0                 (internal)
+        2 (L p)_s = 0                                   (terminal)
+    (on a solution q_s - sum_c q_c = -(L p)_s, so both read (L p)_s = 0).
+
+    Constraints: one per acinus, B_k u - dt q_k = 0 (volume change of the
+    acinus equals its inflow over the step), B_k the analytic surface form of
+    the acinus' volume change.  The multiplier block is zero (a saddle point).
+    """
+    h = 1.0 / n
+    nterm = 2 ** depth
+    nseg = 2 ** (depth + 1) - 1
+    if rt_scale is None:
+        rt_scale = float(nterm)
+    dims = (n + 1, n + 1, n + 1)
+    ijk = fem.grid_nodes(dims)
+    free = ijk[:, 2] > 0
+    free_dof = np.repeat(free, 3)
+    tmap = fem.renumber(free_dof)
+    nT = int(free_dof.sum())
+    Ke = fem.ke_elastic(fem.q1_3d(h, h, h), E, nu).reshape(8, 3, 8, 3)
+    conn = fem.grid_conn_3d(n, n, n)
+    st, _ = fem.stencil_assemble((n, n, n), 3, lambda ia, ib: np.broadcast_to(Ke[ia, :, ib, :], (conn.shape[0], 3, 3)))
+    ATT = fem.stencil_to_csr(st, dims, tmap, tmap, nT, nT)
+    del st
+    # airway tree
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xA1B]))
+    R = np.exp(rng.uniform(np.log(1e-2), np.log(1.0), nseg))
+    Rt = rt_scale * np.exp(rng.uniform(np.log(1e-2), np.log(1.0), nterm))
+    nW = 2 * nseg
+    first_term = nseg - nterm
+    g = 1.0 / R
+    wr, wc, wv = [], [], []
+    lr, lc, lv = [], [], []          # airway -> multiplier coupling
+    for sgm in range(nseg):
+        p, q = 2 * sgm, 2 * sgm + 1
+        par = (sgm - 1) // 2 if sgm > 0 else -1
+        # pressure rows: twice the weighted tree Laplacian plus the flow
+        # balance q_s - sum_c q_c (internal nodes only)
+        wr.append(p); wc.append(p); wv.append(2.0 * g[sgm])
+        if par >= 0:
+            # Laplacian couplings and the segment's share of the parent's diagonal
+            wr += [p, 2 * par, 2 * par]
+            wc += [2 * par, p, 2 * par]
+            wv += [-2.0 * g[sgm], -2.0 * g[sgm], 2.0 * g[sgm]]
+        if sgm < first_term:
+            wr.append(p); wc.append(q); wv.append(1.0)
+            for c in (2 * sgm + 1, 2 * sgm + 2):
+                wr.append(p); wc.append(2 * c + 1); wv.append(-1.0)
+            # flow row: Poiseuille, R_s q_s - (p_parent - p_s) = 0
+            wr += [q, q]; wc += [q, p]; wv += [R[sgm], 1.0]
+            if par >= 0:
+                wr.append(q); wc.append(2 * par); wv.append(-1.0)
+        else:
+            k = sgm - first_term
+            wr.append(p); wc.append(p); wv.append(2.0 / Rt[k])
+            lr.append(p); lc.append(k); lv.append(-2.0 / Rt[k])
+            # flow row: segment and acinus in series, (R_s + Rt_k) q_s - p_parent + lambda_k = 0
+            wr.append(q); wc.append(q); wv.append(R[sgm] + Rt[k])
+            if par >= 0:
+                wr.append(q); wc.append(2 * par); wv.append(-1.0)
+            lr.append(q); lc.append(k); lv.append(1.0)
+    AWW = sp.csr_matrix((wv, (wr, wc)), shape=(nW, nW))
+    AWW.sum_duplicates()
+    AWW.sort_indices()
+    AWL = sp.csr_matrix((lv, (lr, lc)), shape=(nW, nterm))
+    AWL.sort_indices()
+    # constraints
+    br, bc, bv = _acinus_constraint_rows(n, nterm, acinus, seed, tmap)
+    B = sp.csr_matrix((bv, (br, bc)), shape=(nterm, nT))
+    B.sort_indices()
+    ALT = B
+    ATL = sp.csr_matrix(-B.T)
+    ATL.sort_indices()
+    ALW = sp.csr_matrix((-dt * np.ones(nterm), (np.arange(nterm), 2 * (first_term + np.arange(nterm)) + 1)),
+                        shape=(nterm, nW))
+    ALW.sort_indices()
+    xyz = ijk[free] * h
+    nsT = rigid_modes_3d(xyz, xyz.mean(axis=0))
+    nsW = np.zeros((2, nW))
+    nsW[0, 0::2] = 1.0
+    nsW[1, 1::2] = 1.0
+    nsL = np.ones((1, nterm))
+    fields = [Field("tissue", nT, 3, nsT), Field("airway", nW, 2, nsW), Field("multiplier", nterm, 1, nsL)]
+    blocks = [[ATT, None, ATL], [None, AWW, AWL], [ALT, ALW, None]]
+    return BlockSystem(fields, blocks, uniform_rhs(nT + nW + nterm, nrhs, seed),
+                       meta=dict(kind="lung3d", n=n, depth=depth, seed=seed, split=[0, 0, 1]))

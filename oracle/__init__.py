@@ -137,6 +137,9 @@ class Oracle:
 
     def __init__(self, fields, blocks, spec, **opts):
         L = lib()
+        bad = set(opts) - set(DEFAULT_OPTS)
+        if bad:
+            raise TypeError(f"unknown oracle options: {sorted(bad)}")
         o = dict(DEFAULT_OPTS)
         o.update(opts)
         self.sizes = [f.ndof for f in fields]

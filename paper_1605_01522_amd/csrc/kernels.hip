@@ -1561,79 +1561,195 @@ void csr_to_dense(const DCsr& A, double* M, int64_t ld, int r0, int c0, hipStrea
     hipLaunchKernelGGL(k_csr_to_dense, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, M, ld, r0, c0);
 }
 
-// Gauss-Jordan on the augmented matrix W = [M | I] (n x 2n, row-major) with
-// partial pivoting (first row of largest magnitude); one workgroup.
-__global__ __launch_bounds__(1024) void k_gauss_jordan(double* W, int n, int* singular) {
-  extern __shared__ double fac[];            // n multipliers
-  __shared__ double bv[1024];
-  __shared__ int bi[1024];
-  __shared__ double pivval;
-  const int t = threadIdx.x, nt = blockDim.x, w = 2 * n;
-  for (int k = 0; k < n; ++k) {
+// In-place Gauss-Jordan inverse of a row-major n x n matrix with partial
+// pivoting (largest magnitude, lowest row on ties), blocked by column panels
+// of GJ_NB.  Per panel K = [k0, k0 + kb):
+//  1. one workgroup runs the kb pivot steps, each restricted to the panel's
+//     columns but applied to every row (row swaps cover whole rows); the
+//     panel then holds the columns K of the elimination matrix T;
+//  2. Y = rows K of the other columns, which are zeroed;
+//  3. every column outside K gets += T[:, K] Y (a rank-kb update), which
+//     applies the deferred eliminations to them.
+// Afterwards the matrix holds (P M)^-1 for the row permutation P of the
+// pivots, and the column swaps in reverse order turn it into M^-1.
+constexpr int GJ_NB = 32;
+constexpr int DENSE_MAX = 12000;
+
+__global__ __launch_bounds__(1024) void k_gj_panel(double* __restrict__ M, int n, int k0, int kb, int* __restrict__ piv,
+                                                   int* __restrict__ singular) {
+  __shared__ double rowk[GJ_NB];
+  __shared__ double redv[32];
+  __shared__ int redi[32];
+  __shared__ int pivrow;
+  __shared__ double pivabs, piva;
+  if (*singular) return;                       // an earlier panel failed
+  const int t = threadIdx.x;
+  const int lane = t & 31, grp = t >> 5;       // 32 groups of 32 lanes; lane = panel column
+  // pivot candidate for the first column of the panel
+  {
     double best = -1.0;
-    int bidx = n;
-    for (int i = k + t; i < n; i += nt) {
-      const double v = fabs(W[(int64_t)i * w + k]);
-      if (v > best) { best = v; bidx = i; }
+    int bi = n;
+    for (int r = k0 + t; r < n; r += 1024) {
+      const double v = fabs(M[(int64_t)r * n + k0]);
+      if (v > best) { best = v; bi = r; }
     }
-    bv[t] = best;
-    bi[t] = bidx;
-    __syncthreads();
-    for (int off = nt / 2; off > 0; off >>= 1) {
-      if (t < off) {
-        const double a = bv[t], b = bv[t + off];
-        const int ia = bi[t], ib = bi[t + off];
-        if (b > a || (b == a && ib < ia)) { bv[t] = b; bi[t] = ib; }
+    for (int off = 16; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 32);
+      const int oi = __shfl_xor(bi, off, 32);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { redv[grp] = best; redi[grp] = bi; }
+  }
+  __syncthreads();
+  for (int k = k0; k < k0 + kb; ++k) {
+    if (t < 32) {
+      double best = redv[t];
+      int bi = redi[t];
+      for (int off = 16; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, 32);
+        const int oi = __shfl_xor(bi, off, 32);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
       }
-      __syncthreads();
+      if (t == 0) { pivrow = bi; pivabs = best; }
     }
-    const int p = bi[0];
-    if (bv[0] <= 0.0) {
+    __syncthreads();
+    const int p = pivrow;
+    if (!(pivabs > 0.0)) {            // zero (or NaN) column below the diagonal
       if (t == 0) *singular = 1;
       return;
     }
+    if (t == 0) piv[k] = p;
     if (p != k)
-      for (int j = t; j < w; j += nt) {
-        const double a = W[(int64_t)k * w + j];
-        W[(int64_t)k * w + j] = W[(int64_t)p * w + j];
-        W[(int64_t)p * w + j] = a;
+      for (int c = t; c < n; c += 1024) {
+        const double a = M[(int64_t)k * n + c];
+        M[(int64_t)k * n + c] = M[(int64_t)p * n + c];
+        M[(int64_t)p * n + c] = a;
       }
     __syncthreads();
-    if (t == 0) pivval = W[(int64_t)k * w + k];
+    if (t == 0) piva = M[(int64_t)k * n + k];
     __syncthreads();
-    const double inv = 1.0 / pivval;
-    for (int j = t; j < w; j += nt) W[(int64_t)k * w + j] *= inv;
-    for (int i = t; i < n; i += nt) fac[i] = i == k ? 0.0 : W[(int64_t)i * w + k];
+    const double a = piva;           // read before the pivot row is overwritten
+    if (t < kb) {
+      const int j = k0 + t;
+      const double v = j == k ? 1.0 / a : M[(int64_t)k * n + j] / a;
+      rowk[t] = v;
+      M[(int64_t)k * n + j] = v;
+    }
     __syncthreads();
-    for (int64_t e = t; e < (int64_t)n * w; e += nt) {
-      const int i = (int)(e / w), j = (int)(e % w);
-      if (i != k) W[e] -= fac[i] * W[(int64_t)k * w + j];
+    // eliminate column k from every other row (panel columns only) and
+    // track the next pivot candidate among rows > k
+    const int nxt = k + 1 - k0;          // panel column of the next pivot
+    double best = -1.0;
+    int bi = n;
+    for (int i = grp; i < n; i += 32) {
+      if (i == k) continue;
+      const double f = M[(int64_t)i * n + k];
+      if (lane < kb) {
+        const int j = k0 + lane;
+        const double v = j == k ? -f / a : M[(int64_t)i * n + j] - f * rowk[lane];
+        M[(int64_t)i * n + j] = v;
+        if (lane == nxt && i > k && fabs(v) > best) { best = fabs(v); bi = i; }
+      }
+    }
+    if (nxt < kb) {
+      // lane nxt of each group holds that group's candidate
+      best = __shfl(best, nxt, 32);
+      bi = __shfl(bi, nxt, 32);
+      if (lane == 0) { redv[grp] = best; redi[grp] = bi; }
     }
     __syncthreads();
   }
 }
-__global__ void k_augment(const double* M, double* W, int n) {
+
+// Y (GJ_NB x n) = rows K of the columns outside K, which are then zeroed.
+__global__ void k_gj_save(double* __restrict__ M, double* __restrict__ Y, int n, int k0, int kb) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)n * 2 * n) return;
-  const int i = (int)(e / (2 * n)), j = (int)(e % (2 * n));
-  W[e] = j < n ? M[(int64_t)i * n + j] : (j - n == i ? 1.0 : 0.0);
+  if (e >= (int64_t)kb * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  if (c >= k0 && c < k0 + kb) {
+    Y[e] = 0.0;
+    return;
+  }
+  const int64_t m = (int64_t)(k0 + r) * n + c;
+  Y[e] = M[m];
+  M[m] = 0.0;
 }
-__global__ void k_extract_inverse(const double* W, double* M, int n) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)n * n) return;
-  const int i = (int)(e / n), j = (int)(e % n);
-  M[e] = W[(int64_t)i * 2 * n + n + j];
+
+// M[:, j] += M[:, K] Y[:, j] for every column j outside K.  64 x 64 tiles,
+// 256 threads, 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ M, const double* __restrict__ Y, int n, int k0, int kb) {
+  __shared__ double Ts[64][GJ_NB + 1];
+  __shared__ double Ys[GJ_NB][64 + 1];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * GJ_NB; e += 256) {
+    const int r = e / GJ_NB, q = e % GJ_NB;
+    Ts[r][q] = (r0 + r < n && q < kb) ? M[(int64_t)(r0 + r) * n + k0 + q] : 0.0;
+  }
+  for (int e = t; e < GJ_NB * 64; e += 256) {
+    const int q = e / 64, c = e % 64;
+    Ys[q][c] = (q < kb && c0 + c < n) ? Y[(int64_t)q * n + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tr = (t / 16) * 4, tc = (t % 16) * 4;
+  double acc[4][4] = {};
+  for (int q = 0; q < kb; ++q) {
+    double a[4], b[4];
+    for (int i = 0; i < 4; ++i) a[i] = Ts[tr + i][q];
+    for (int j = 0; j < 4; ++j) b[j] = Ys[q][tc + j];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+  }
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + tr + i;
+    if (r >= n) continue;
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tc + j;
+      if (c >= n || (c >= k0 && c < k0 + kb)) continue;
+      M[(int64_t)r * n + c] += acc[i][j];
+    }
+  }
 }
+
+__global__ void k_iota(int* v, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+// Column swaps of the pivots in reverse order; one thread per row.
+__global__ void k_gj_colswap(double* __restrict__ M, int n, const int* __restrict__ piv) {
+  extern __shared__ int sp[];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) sp[k] = piv[k];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* row = M + (int64_t)i * n;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = sp[k];
+    if (p != k) {
+      const double a = row[k];
+      row[k] = row[p];
+      row[p] = a;
+    }
+  }
+}
+
 int dense_inverse(double* M, int n, hipStream_t s) {
   if (n == 0) return 0;
-  NF_CHECK(n <= 6000, NFIELD_ENOMEM, "dense coarse solve larger than 6000 unknowns");
-  DBuf<double> W((size_t)n * 2 * n);
-  DBuf<int> sing(1);
+  NF_CHECK(n <= DENSE_MAX, NFIELD_ENOMEM, "dense solve larger than " + std::to_string(DENSE_MAX) + " unknowns");
+  DBuf<double> Y((size_t)GJ_NB * n);
+  DBuf<int> piv(n), sing(1);
   fill<int>(sing.p, 0, 1, s);
-  hipLaunchKernelGGL(k_augment, dim3(cdiv((int64_t)n * 2 * n, 256)), dim3(256), 0, s, M, W.p, n);
-  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), n * sizeof(double), s, W.p, n, sing.p);
+  hipLaunchKernelGGL(k_iota, dim3(cdiv(n, 256)), dim3(256), 0, s, piv.p, n);
+  const dim3 tiles(cdiv(n, 64), cdiv(n, 64));
+  for (int k0 = 0; k0 < n; k0 += GJ_NB) {
+    const int kb = std::min(GJ_NB, n - k0);
+    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(1024), 0, s, M, n, k0, kb, piv.p, sing.p);
+    hipLaunchKernelGGL(k_gj_save, dim3(cdiv((int64_t)kb * n, 256)), dim3(256), 0, s, M, Y.p, n, k0, kb);
+    hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, M, Y.p, n, k0, kb);
+  }
+  hipLaunchKernelGGL(k_gj_colswap, dim3(cdiv(n, 256)), dim3(256), sizeof(int) * n, s, M, n, piv.p);
   NF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_extract_inverse, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, W.p, M, n);
   int h = 0;
   NF_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));

@@ -260,15 +260,21 @@ static void bgs_sweep(const BlockMat& A, int f0, int f1, int order, const T* res
   }
 }
 
-// Level smoother of a (monolithic) hierarchy: one BGS sweep over the level's
-// blocks with each field's smoother in place of the block solve (a single
-// field: the field smoother itself).
+// Level smoother of a (monolithic) hierarchy (Sec. 4.3, last paragraph):
+// one BGS sweep over the level's blocks, or one SIMPLE step with the last
+// field as the Schur field, each with the fields' own smoothers in place of
+// the block solves (a single field: the field smoother itself).
 template <class T>
 struct LevelSmootherD {
   const BlockMat* A = nullptr;
   int order = 1;
+  int kind = 0;                     // 0 BGS, 1 SIMPLE
   std::vector<std::unique_ptr<FieldSmootherD<T>>> cheb;
   MBuf<T> r, d, t;
+  // SIMPLE: fields [0, N-1) predictor, field N-1 Schur
+  DBuf<T> dtinv;                    // SIMPLEC diagonal of the predictor block, inverted
+  std::unique_ptr<Solver<T>> schur; // dense inverse or Chebyshev on S~
+  MBuf<T> ts, u;
   void smooth(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) {
     const int N = A->N;
     if (N == 1) {
@@ -285,10 +291,43 @@ struct LevelSmootherD {
     T* dd = zero_guess ? x : d.p();
     const int64_t lddd = zero_guess ? ldx : d.ld;
     const int ord = order == 2 ? (zero_guess ? 0 : 1) : order;
-    bgs_sweep<T>(*A, 0, N, ord, res, ldres, dd, lddd, t.p(), t.ld, nrhs,
-                 [&](int i, const T* rhs, int64_t ldrhs, T* out, int64_t ldout) {
-                   cheb[i]->apply(rhs, ldrhs, out, ldout, nrhs, true, s);
-                 }, s);
+    auto inner = [&](int i, const T* rhs, int64_t ldrhs, T* out, int64_t ldout) {
+      cheb[i]->apply(rhs, ldrhs, out, ldout, nrhs, true, s);
+    };
+    if (kind == 0) {
+      bgs_sweep<T>(*A, 0, N, ord, res, ldres, dd, lddd, t.p(), t.ld, nrhs, inner, s);
+    } else {
+      const int g = N - 1;
+      std::vector<int> o = A->offsets();
+      bgs_sweep<T>(*A, 0, g, ord, res, ldres, dd, lddd, t.p(), t.ld, nrhs, inner, s);   // predictor
+      bool first = true;
+      for (int j = 0; j < g; ++j) {
+        if (!A->at(g, j)) continue;
+        SpmvArgs<T> a;
+        a.x = dd + o[j];
+        a.ldx = lddd;
+        a.y = ts.p();
+        a.ldy = ts.ld;
+        a.b = res + o[g];
+        a.ldb = ldres;
+        a.nrhs = nrhs;
+        spmv<T>(first ? SPMV_RESID : SPMV_SUB, *A->at(g, j), a, s);
+        first = false;
+      }
+      if (first) schur->apply(res + o[g], ldres, dd + o[g], lddd, nrhs, s);
+      else schur->apply(ts.p(), ts.ld, dd + o[g], lddd, nrhs, s);
+      for (int j = 0; j < g; ++j) {
+        if (!A->at(j, g)) continue;
+        SpmvArgs<T> a;
+        a.x = dd + o[g];
+        a.ldx = lddd;
+        a.y = u.p();
+        a.ldy = u.ld;
+        a.nrhs = nrhs;
+        spmv<T>(SPMV_STORE, *A->at(j, g), a, s);
+        sub_scaledm<T>(dtinv.p + o[j], u.p(), u.ld, dd + o[j], lddd, A->size[j], nrhs, s);
+      }
+    }
     if (!zero_guess) add_intom<T>(d.p(), d.ld, x, ldx, A->total(), nrhs, nullptr, s);
   }
 };
@@ -556,6 +595,51 @@ template <class T>
 static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const BlockMat& A, const std::vector<FieldDev>& F,
                                         int f0, int f1, hipStream_t s);
 
+// SIMPLE pieces over fields [f0, g) (predictor) and g (Schur), Sec. 3.2:
+// dt = inverse of the SIMPLEC-type diagonal of the merged predictor block
+// (mode 0: sum_j |a_ij|, 1: |sum_j a_ij|, 2: a_ii, over the predictor
+// columns), and S~ = A_gg - sum_i A_gi diag(dt_i) A_ig.
+static void simple_parts(const BlockMat& A, int f0, int g, int mode, DBuf<double>& dt, DCsr& Sm, hipStream_t s) {
+  std::vector<int> o = A.offsets();
+  const int n1 = o[g] - o[f0], n2 = A.size[g];
+  dt.alloc(n1 > 0 ? n1 : 1);
+  DBuf<int> zf(1);
+  fill<double>(dt.p, 0.0, n1, s);
+  fill<int>(zf.p, 0, 1, s);
+  for (int i = f0; i < g; ++i)
+    for (int j = f0; j < g; ++j)
+      if (A.at(i, j)) row_accumulate(*A.at(i, j), mode, i == j, dt.p + (o[i] - o[f0]), s);
+  finish_simplec(dt.p, n1, mode, zf.p, s);
+  int z = 0;
+  NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(z == 0, NFIELD_ESINGULAR, "SIMPLE: zero entry in the approximate predictor diagonal");
+  if (A.at(g, g)) csr_copy(*A.at(g, g), Sm, s);
+  else { Sm.nr = Sm.nc = n2; Sm.nnz = 0; }
+  for (int i = f0; i < g; ++i) {
+    if (!A.at(g, i) || !A.at(i, g)) continue;
+    DCsr Tm, prod, sum;
+    csr_copy(*A.at(i, g), Tm, s);
+    scale_rows(Tm, dt.p + (o[i] - o[f0]), s);
+    spgemm(*A.at(g, i), Tm, prod, s);
+    csr_add(1.0, Sm, -1.0, prod, sum, s);
+    Sm = std::move(sum);
+  }
+  NF_HIP(hipStreamSynchronize(s));
+  NF_CHECK(Sm.nnz > 0, NFIELD_ESINGULAR, "SIMPLE: approximate Schur complement is zero");
+}
+
+// Chebyshev on S~ used as the Schur solve of a SIMPLE level smoother when S~
+// is too large for a dense inverse.
+template <class T>
+struct ChebSolverD : Solver<T> {
+  std::shared_ptr<DCsr> S;
+  ChebD<T> cheb;
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
+    cheb.apply(r, ldr, z, ldz, nrhs, true, s);
+  }
+};
+
 template <class T>
 static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, const std::vector<FieldDev>& F, int f0, int f1,
                                             const Spec* smoother, const Spec& amg, hipStream_t s) {
@@ -566,8 +650,10 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
   const int steps = amg.steps > 0 ? amg.steps : 1;
   BlockMat sub = A.sub(f0, f1);
   std::vector<FieldDev> Fs(F.begin() + f0, F.begin() + f1);
-  NF_CHECK(!smoother || smoother->name == "BGS", NFIELD_EINVAL, "spec: only BGS level smoothers are available");
-  for (int i = 0; i < sub.N; ++i) NF_CHECK(sub.at(i, i) != nullptr, NFIELD_ESINGULAR, "AMG: zero diagonal block");
+  const bool simple = smoother && smoother->name == "SIMPLE";
+  NF_CHECK(!simple || sub.N >= 2, NFIELD_EINVAL, "AMG(SIMPLE) needs at least two fields");
+  for (int i = 0; i < sub.N; ++i)
+    NF_CHECK(sub.at(i, i) != nullptr || (simple && i == sub.N - 1), NFIELD_ESINGULAR, "AMG: zero diagonal block");
   auto H = std::make_unique<Hierarchy>();
   build_hierarchy(*H, sub, Fs, C.o, s);
   auto S = std::make_unique<AmgSolverD<T>>();
@@ -596,7 +682,9 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     LevelSmootherD<T>& M = S->sm[l];
     M.A = &L.A;
     M.order = smoother && smoother->order >= 0 ? smoother->order : C.o.order;
-    for (int i = 0; i < sub.N; ++i) {
+    M.kind = simple ? 1 : 0;
+    const int nsm = simple ? sub.N - 1 : sub.N;   // fields with their own smoother
+    for (int i = 0; i < nsm; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
       if (sgs) {
         auto g = std::make_unique<SgsD<T>>();
@@ -614,6 +702,49 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
       int mx = 0;
       for (int v : L.A.size) mx = std::max(mx, v);
       M.t.alloc(mx);
+    }
+    if (simple) {
+      const int g = sub.N - 1, n2 = L.A.size[g];
+      DBuf<double> dt;
+      auto Sm = std::make_shared<DCsr>();
+      simple_parts(L.A, 0, g, C.o.simplec_mode, dt, *Sm, s);
+      const int n1 = L.A.offsets()[g];
+      M.dtinv.alloc(n1 > 0 ? n1 : 1);
+      if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(M.dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
+      else cast_copy<double, float>(dt.p, (float*)M.dtinv.p, n1, s);
+      if (n2 <= C.o.schur_direct_max) {
+        auto lu = std::make_unique<LuSolverD<T>>();
+        BlockMat one;
+        one.N = 1;
+        one.size = {n2};
+        one.blk = {Sm};
+        dense_block_inverse(one, lu->inv, &lu->nn, s);
+        lu->n = n2;
+        M.schur = std::move(lu);
+      } else {
+        auto ch = std::make_unique<ChebSolverD<T>>();
+        DBuf<double> dg(n2), dinv(n2);
+        DBuf<int> zf(1);
+        fill<int>(zf.p, 0, 1, s);
+        csr_diag(*Sm, dg.p, zf.p, s);
+        invert(dg.p, dinv.p, n2, s);
+        int z = 0;
+        NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        NF_HIP(hipStreamSynchronize(s));
+        NF_CHECK(z == 0, NFIELD_ESINGULAR, "SIMPLE: zero diagonal entry in the approximate Schur complement");
+        const double lam = power_lambda(*Sm, dinv.p, C.o.seed, C.o.power_its, s);
+        if (sizeof(T) == sizeof(float)) make_fp32(*Sm, s);
+        ch->cheb.setup(Sm.get(), dinv.p, lam, lo, s);
+        NF_HIP(hipStreamSynchronize(s));
+        ch->S = Sm;
+        ch->n = n2;
+        M.schur = std::move(ch);
+      }
+      NF_HIP(hipStreamSynchronize(s));   // dt is released on return
+      M.ts.alloc(n2);
+      int mp = 0;
+      for (int i = 0; i < g; ++i) mp = std::max(mp, L.A.size[i]);
+      M.u.alloc(mp > 0 ? mp : 1);
     }
   }
   C.hiers.push_back(std::move(H));
@@ -679,33 +810,9 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->g = g;
     S->sweeps = sp.sweeps > 0 ? sp.sweeps : 1;
     const int n1 = o[g] - o[f0], n2 = A.size[g];
-    // SIMPLEC-type diagonal of the merged predictor block
-    DBuf<double> dt(n1 > 0 ? n1 : 1);
-    DBuf<int> zf(1);
-    fill<double>(dt.p, 0.0, n1, s);
-    fill<int>(zf.p, 0, 1, s);
-    for (int i = f0; i < g; ++i)
-      for (int j = f0; j < g; ++j)
-        if (A.at(i, j)) row_accumulate(*A.at(i, j), C.o.simplec_mode, i == j, dt.p + (o[i] - o[f0]), s);
-    finish_simplec(dt.p, n1, C.o.simplec_mode, zf.p, s);
-    int z = 0;
-    NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    NF_HIP(hipStreamSynchronize(s));
-    NF_CHECK(z == 0, NFIELD_ESINGULAR, "SIMPLE: zero entry in the approximate predictor diagonal");
-    // S~ = A_gg - sum_i A_gi D~_i^-1 A_ig
+    DBuf<double> dt;
     auto Sm = std::make_shared<DCsr>();
-    if (A.at(g, g)) csr_copy(*A.at(g, g), *Sm, s);
-    else { Sm->nr = Sm->nc = n2; Sm->nnz = 0; }
-    for (int i = f0; i < g; ++i) {
-      if (!A.at(g, i) || !A.at(i, g)) continue;
-      DCsr Tm, prod, sum;
-      csr_copy(*A.at(i, g), Tm, s);
-      scale_rows(Tm, dt.p + (o[i] - o[f0]), s);
-      spgemm(*A.at(g, i), Tm, prod, s);
-      csr_add(1.0, *Sm, -1.0, prod, sum, s);
-      *Sm = std::move(sum);
-    }
-    NF_CHECK(Sm->nnz > 0, NFIELD_ESINGULAR, "SIMPLE: approximate Schur complement is zero");
+    simple_parts(A, f0, g, C.o.simplec_mode, dt, *Sm, s);
     S->dtinv.alloc(n1 > 0 ? n1 : 1);
     if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(S->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
     else cast_copy<double, float>(dt.p, (float*)S->dtinv.p, n1, s);
