@@ -7,8 +7,13 @@ complement, smoothers, coarse inverses) and solve with GMRES(50) to
 rtol 1e-8.  value = steps per second (solves/s, setup included, as the
 paper's times include the preconditioner setup).
 
+Besides the main workload the line carries a "lung" record (the lung-like
+saddle system, SIMPLE(AMG(BGS);LU)) and a "serving" record (continuous
+batching of 512 TSI-like requests against sequential plain FP64 solves).
+
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
-[--workload fsi3d|tsi2d] [--no-cpu-baseline]
+[--workload fsi3d|tsi2d|lung3d] [--no-cpu-baseline] [--no-precision-form]
+[--no-lung] [--no-serving]
 """
 import argparse
 import json
@@ -29,7 +34,15 @@ WORKLOADS = {
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
                   spec="BGS(AMG)", opts=dict(sweeps=2, order="bwd")),
+    # lung-like saddle system: Q1 tissue on a 64^3 box, airway tree of depth
+    # 12, 4096 acinus volume constraints; outer SIMPLE with the monolithic
+    # AMG(BGS) on tissue + airway (damped Gauss-Seidel smoothers, omega 0.79)
+    # and a dense inverse of the 4096 x 4096 S~
+    "lung3d": dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=12, acinus=8, seed=seed),
+                   spec="SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)", opts=dict(split=[0, 0, 1])),
 }
+SERVE_SPEC = "BGS(AMG)"
+SERVE_OPTS = dict(sweeps=2, order="bwd")
 
 
 def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
@@ -52,31 +65,20 @@ def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
                 setup_s=t_setup, s_per_iter=per_it)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fsi3d", choices=sorted(WORKLOADS))
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-precision-form", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md and not measured.", file=sys.stderr)
-        sys.exit(2)
-
+def run_workload(name, steps, warmup, seed, precision_form):
+    """Generate the workload, build its solver once (upload included), then
+    time `steps` full steps (rebuild + GMRES(50) to rtol 1e-8) after `warmup`
+    untimed ones; a separate profiled pass gives per-kernel HIP-event times."""
     import numpy as np
     import torch
     from paper_1605_01522_amd import nfield
     from paper_1605_01522_amd.nfield import NField
 
-    W = WORKLOADS[args.workload]
+    W = WORKLOADS[name]
     t0 = time.perf_counter()
-    s = W["make"](args.seed)
+    s = W["make"](seed)
     t_gen = time.perf_counter() - t0
-    print(f"# generated {args.workload}: n={s.n} nnz={s.nnz()} in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    print(f"# generated {name}: n={s.n} nnz={s.nnz()} in {t_gen:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -92,7 +94,7 @@ def main():
         _, st = solver.gmres_solve(b, x, restart=50, rtol=1e-8)
         return st[0]
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         st = step()
         print(f"# warmup {w}: iters {st['iters']} setup {1e3 * st['setup_s']:.1f} ms "
               f"solve {1e3 * st['solve_s']:.1f} ms", file=sys.stderr, flush=True)
@@ -100,7 +102,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
-    for k in range(args.steps):
+    for k in range(steps):
         stats.append(step())
         print(f"# step {k}: iters {stats[-1]['iters']} setup {1e3 * stats[-1]['setup_s']:.1f} ms "
               f"solve {1e3 * stats[-1]['solve_s']:.1f} ms", file=sys.stderr, flush=True)
@@ -111,7 +113,7 @@ def main():
     # launch stream around every SpMV launch and every Gauss-Seidel sweep
     # (kept out of the timed steps above so that they do not slow them)
     nfield.nfield_prof_enable(1)
-    for k in range(max(1, min(args.steps, 2))):
+    for k in range(max(1, min(steps, 2))):
         step()
     torch.cuda.synchronize()
     prof = nfield.nfield_prof_read()
@@ -123,7 +125,7 @@ def main():
 
     # precision form: FP32 hierarchy and smoothers inside FP64 flexible GMRES
     prec = None
-    if not args.no_precision_form:
+    if precision_form:
         solver32 = NField(s.fields, s.blocks, W["spec"], hier_fp32=1, **W["opts"])
         x32 = torch.zeros_like(b)
 
@@ -136,11 +138,11 @@ def main():
         step32()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st32 = [step32() for _ in range(args.steps)]
+        st32 = [step32() for _ in range(steps)]
         torch.cuda.synchronize()
         el32 = time.perf_counter() - t0
         x32h = x32.cpu().numpy()
-        prec = dict(value=round(args.steps / el32, 4), unit="solves/s",
+        prec = dict(value=round(steps / el32, 4), unit="solves/s",
                     setup_ms=round(1e3 * float(np.median([t["setup_s"] for t in st32])), 3),
                     solve_ms=round(1e3 * float(np.median([t["solve_s"] for t in st32])), 3),
                     gmres_iters=st32[-1]["iters"],
@@ -149,7 +151,7 @@ def main():
                     footprint_mb=round(solver32.footprint_bytes() / 2**20, 1),
                     fp64_footprint_mb=round(solver.footprint_bytes() / 2**20, 1))
         solver32.close()
-    ms_per_step = 1e3 * elapsed / args.steps
+    ms_per_step = 1e3 * elapsed / steps
     dom = max(prof, key=lambda p: p["ms"]) if prof else None
     roofline = None
     if dom:
@@ -159,6 +161,126 @@ def main():
                         kernel=nfield.kernel_name(dom),
                         launches=dom["launches"], avg_us=round(1e3 * dom["ms"] / dom["launches"], 2),
                         bytes_per_launch=round(dom["bytes"] / dom["launches"]))
+    footprint_mb = round(solver.footprint_bytes() / 2**20, 1)
+    solver.close()
+    return dict(system=s, stats=stats, elapsed=elapsed, roofline=roofline, prec=prec, prof=prof,
+                relres=relres, t_first_setup=t_first_setup, spec=W["spec"], opts=W["opts"],
+                footprint_mb=footprint_mb)
+
+
+def summary(name, r, steps, seed):
+    """Compact record of a secondary workload run."""
+    import numpy as np
+    s, stats = r["system"], r["stats"]
+    return dict(workload=f"{name}: n={s.n} dofs, nnz={s.nnz()}, spec {r['spec']}, GMRES(50) rtol 1e-8, "
+                         f"seed {seed}",
+                fields=[f.ndof for f in s.fields], value=round(steps / r["elapsed"], 4), unit="solves/s",
+                setup_ms=round(1e3 * float(np.median([t["setup_s"] for t in stats])), 3),
+                solve_ms=round(1e3 * float(np.median([t["solve_s"] for t in stats])), 3),
+                gmres_iters=stats[-1]["iters"], relres=r["relres"], footprint_mb=r["footprint_mb"],
+                roofline=r["roofline"], precision_form=r["prec"],
+                spmv_profile=[dict(p, gbps=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1)) for p in
+                              sorted(r["prof"], key=lambda p: -p["ms"])[:4]])
+
+
+def serving(n_requests=512, seed=0, workers=4, load=0.8):
+    """Continuous-batching leg: 512 requests of 2-field TSI-like systems on
+    grids {16..128}^2 with 1-8 right-hand sides each.  (1) capacity: every
+    request queued at once, contexts already cached; (2) the same requests
+    with Poisson arrivals at `load` x capacity, replayed in real time, for
+    p50/p99 latency; (3) the baseline: the same requests served one
+    right-hand side at a time with plain FP64 GMRES, contexts cached."""
+    import numpy as np
+    import torch
+    import nfgen
+    from paper_1605_01522_amd.nfield import NField
+    from paper_1605_01522_amd.serve import Server, summarize
+
+    systems = {g: nfgen.tsi2d(nel=g) for g in nfgen.SERVE_GRIDS}
+
+    def rhs_for(req):
+        return nfgen.request_rhs(req, systems[req["grid"]].n)
+
+    def trace(rate):
+        t = nfgen.request_trace(n_requests, rate=rate, seed=seed)
+        for q in t:
+            q["key"] = q["grid"]
+        return t
+
+    srv = Server(lambda g: systems[g], SERVE_SPEC, SERVE_OPTS, workers=workers, max_cols=8, hier_fp32=True)
+    t0 = time.perf_counter()
+    srv.run(trace(1e9), rhs_for, time_scale=0.0)          # builds the cached contexts
+    t_warm = time.perf_counter() - t0
+    cap = summarize(srv.run(trace(1e9), rhs_for, time_scale=0.0))
+    print(f"# serving capacity: {cap['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+    items = srv.run(trace(load * cap["requests_per_s"]), rhs_for, time_scale=1.0)
+    live = summarize(items)
+    print(f"# serving at {load}x capacity: p50 {live['p50_ms']:.2f} ms p99 {live['p99_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
+    # accuracy of the served solutions
+    worst = 0.0
+    assembled = {g: systems[g].assembled() for g in systems}
+    for it in items:
+        A = assembled[it.req["grid"]]
+        B = rhs_for(it.req)
+        for k in range(B.shape[0]):
+            worst = max(worst, float(np.linalg.norm(B[k] - A @ it.x[k]) / np.linalg.norm(B[k])))
+    srv.close()
+    # baseline: sequential plain FP64, one column per solve, contexts cached
+    ctx = {g: NField(systems[g].fields, systems[g].blocks, SERVE_SPEC, **SERVE_OPTS) for g in systems}
+    tr = trace(1e9)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in tr:
+        tq = time.perf_counter()
+        B = torch.tensor(rhs_for(q), device="cuda")
+        for k in range(B.shape[0]):
+            ctx[q["grid"]].gmres_solve(B[k].contiguous(), rtol=1e-8)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - tq)
+    el = time.perf_counter() - t0
+    for c in ctx.values():
+        c.close()
+    cols = sum(q["nrhs"] for q in tr)
+    seq = dict(solves_per_s=round(cols / el, 2), requests_per_s=round(len(tr) / el, 2),
+               service_p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3),
+               service_p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3))
+    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    return dict(workload=f"{n_requests} requests, tsi2d grids {list(nfgen.SERVE_GRIDS)}^2, 1-8 rhs each, "
+                         f"spec {SERVE_SPEC}, FP32 hierarchy in FP64 flexible GMRES(50) rtol 1e-8, "
+                         f"{workers} streams, <= 8 columns per batch",
+                capacity=rnd(cap), at_load=dict(rnd(live), load=load), max_relres=worst,
+                context_build_s=round(t_warm, 3), sequential_plain_fp64=seq,
+                speedup_solves_per_s=round(cap["solves_per_s"] / seq["solves_per_s"], 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fsi3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true")
+    ap.add_argument("--no-lung", action="store_true", help="skip the lung-like saddle system leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "layout is described in DESIGN.md and not measured.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1605_01522_amd import nfield
+    from paper_1605_01522_amd.nfield import NField
+
+    W = WORKLOADS[args.workload]
+    r = run_workload(args.workload, args.steps, args.warmup, args.seed, not args.no_precision_form)
+    s, stats, elapsed, roofline, prec, prof = r["system"], r["stats"], r["elapsed"], r["roofline"], r["prec"], r["prof"]
+    relres, ms_per_step = r["relres"], 1e3 * r["elapsed"] / args.steps
     iters = stats[-1]["iters"]
     out = {
         "metric": "time-to-solve + HBM GB/s of GMRES/BGS-AMG; solves/s, p50/p99 latency",
@@ -178,7 +300,7 @@ def main():
                    "fields": [f.ndof for f in s.fields]},
         "setup_ms": round(1e3 * float(np.median([t["setup_s"] for t in stats])), 3),
         "solve_ms": round(1e3 * float(np.median([t["solve_s"] for t in stats])), 3),
-        "first_setup_with_upload_ms": round(1e3 * t_first_setup, 3),
+        "first_setup_with_upload_ms": round(1e3 * r["t_first_setup"], 3),
         "gmres_iters": iters,
         "relres": relres,
         "roofline": roofline,
@@ -188,6 +310,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, W["spec"], W["opts"], iters)
+    del r, s
+    if not args.no_lung and args.workload != "lung3d":
+        out["lung"] = summary("lung3d", run_workload("lung3d", 2, 1, args.seed, not args.no_precision_form),
+                              2, args.seed)
+    if not args.no_serving:
+        out["serving"] = serving(seed=args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -1254,16 +1254,106 @@ __global__ __launch_bounds__(64 * WAVES) void k_spgemm_count(const int* __restri
   }
 }
 
-// upper bound of each product row's length; rows split into two lists
+// upper bound of each product row's length; rows split into three lists
+// (LDS tables of 512 and 4096 slots, dense accumulator beyond)
 __global__ void k_spgemm_bin_ub(int nr, const int* __restrict__ Ap, const int* __restrict__ Ac, const int* __restrict__ Bp,
-                                int small_max, int* small, int* nsmall, int* big, int* nbig, int* cnt) {
+                                int small_max, int big_max, int* small, int* nsmall, int* big, int* nbig, int* huge, int* nhuge,
+                                int* cnt) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= nr) return;
-  int ub = 0;
+  int64_t ub = 0;
   for (int p = Ap[r]; p < Ap[r + 1]; ++p) ub += Bp[Ac[p] + 1] - Bp[Ac[p]];
   if (ub == 0) cnt[r] = 0;
   else if (ub <= small_max) small[atomicAdd(nsmall, 1)] = r;
-  else big[atomicAdd(nbig, 1)] = r;
+  else if (ub <= big_max) big[atomicAdd(nbig, 1)] = r;
+  else huge[atomicAdd(nhuge, 1)] = r;
+}
+
+// Dense-accumulator product rows (rows too long for the LDS tables): one
+// workgroup per row with a private flag array and accumulator over all
+// columns of B (batch slot = blockIdx.x).  Count: mark, then clear while
+// counting first clears, which leaves the flags zero for the next row.
+__global__ __launch_bounds__(256) void k_spa_count(const int* __restrict__ rows, const int* __restrict__ Ap,
+                                                   const int* __restrict__ Ac, const int* __restrict__ Bp,
+                                                   const int* __restrict__ Bc, int ncols, int* flags, int* cnt) {
+  __shared__ int part[4];
+  const int row = rows[blockIdx.x], t = threadIdx.x;
+  int* f = flags + (int64_t)blockIdx.x * ncols;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256) f[Bc[q]] = 1;
+  }
+  __syncthreads();
+  int mine = 0;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256)
+      if (atomicExch(&f[Bc[q]], 0) == 1) ++mine;
+  }
+  mine = wave_sum_int(mine);
+  if ((t & 63) == 0) part[t >> 6] = mine;
+  __syncthreads();
+  if (t == 0) cnt[row] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Fill: accumulate a_ik b_kj into acc[j] in ascending k (a barrier after
+// each k; the lanes of one step hold distinct columns), collect the touched
+// columns, sort them (bitonic in the slot's key scratch of ts entries), then
+// write the row in column order and clear what was touched.
+__global__ __launch_bounds__(256) void k_spa_fill(const int* __restrict__ rows, const int* __restrict__ Ap,
+                                                  const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                  const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                  const double* __restrict__ Bv, const int* __restrict__ Cp, int* __restrict__ Ccol,
+                                                  double* __restrict__ Cval, int ncols, int* flags, double* accs, int* kscr, int ts) {
+  __shared__ int pos;
+  const int row = rows[blockIdx.x], t = threadIdx.x;
+  int* f = flags + (int64_t)blockIdx.x * ncols;
+  double* acc = accs + (int64_t)blockIdx.x * ncols;
+  int* ks = kscr + (int64_t)blockIdx.x * ts;
+  const int c0 = Cp[row], cnt = Cp[row + 1] - c0;
+  if (t == 0) pos = 0;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    const double a = Av[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256) {
+      const int j = Bc[q];
+      acc[j] += a * Bv[q];
+      f[j] = 1;
+    }
+    __syncthreads();
+  }
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256) {
+      const int j = Bc[q];
+      if (atomicExch(&f[j], 0) == 1) {
+        const int at = atomicAdd(&pos, 1);
+        if (at < ts) ks[at] = j;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = pos + t; i < ts; i += 256) ks[i] = EMPTY_KEY;
+  __syncthreads();
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < ts; i += 256) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = ks[i], y = ks[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { ks[i] = y; ks[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = t; i < cnt; i += 256) {
+    const int j = ks[i];
+    const bool ok = j >= 0 && j < ncols;   // always true when the count pass matched
+    Ccol[c0 + i] = ok ? j : 0;
+    Cval[c0 + i] = ok ? acc[j] : 0.0;
+    if (ok) acc[j] = 0.0;
+  }
 }
 
 template <int CAP>
@@ -1323,16 +1413,27 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int* __restrict__ rows
   }
 }
 
-// split rows by their distinct count into the two LDS table sizes
+// split rows by their distinct count into the two LDS table sizes and the
+// dense-accumulator list
 __global__ void k_bin_rows(int nr, const int* __restrict__ Cp, int small_max, int big_max, int* small, int* nsmall, int* big,
-                           int* nbig, int* overflow) {
+                           int* nbig, int* huge, int* nhuge, int* maxlen) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= nr) return;
   const int c = Cp[r + 1] - Cp[r];
   if (c == 0) return;
   if (c <= small_max) small[atomicAdd(nsmall, 1)] = r;
   else if (c <= big_max) big[atomicAdd(nbig, 1)] = r;
-  else atomicOr(overflow, 1);
+  else {
+    huge[atomicAdd(nhuge, 1)] = r;
+    atomicMax(maxlen, c);
+  }
+}
+
+// rows of the dense-accumulator path run in batches of concurrent slots,
+// each slot holding a flag and an accumulator entry per column of B
+static int spa_slots(int ncols, int nrows, int extra_per_slot) {
+  const int64_t per = (int64_t)ncols * 12 + (int64_t)extra_per_slot * 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nrows, ((int64_t)1 << 29) / std::max<int64_t>(per, 1)));
 }
 
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
@@ -1340,44 +1441,66 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   C.nr = A.nr;
   C.nc = B.nc;
   C.ptr.alloc(A.nr + 1);
-  DBuf<int> cnt(A.nr + 1), flags(4);
-  DBuf<int> small(A.nr > 0 ? A.nr : 1), big(A.nr > 0 ? A.nr : 1);
-  fill<int>(flags.p, 0, 4, s);
+  const int nr1 = A.nr > 0 ? A.nr : 1;
+  DBuf<int> cnt(A.nr + 1), flags(8);
+  DBuf<int> small(nr1), big(nr1), huge(nr1);
+  fill<int>(flags.p, 0, 8, s);
   fill<int>(cnt.p, 0, A.nr + 1, s);
-  int h_flags[4];
+  int h_flags[8];
   if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
-    hipLaunchKernelGGL(k_spgemm_bin_ub, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, 256, small.p,
-                       flags.p, big.p, flags.p + 1, cnt.p);
+    hipLaunchKernelGGL(k_spgemm_bin_ub, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, 256,
+                       SPG_COUNT_CAP, small.p, flags.p, big.p, flags.p + 1, huge.p, flags.p + 2, cnt.p);
     NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
-    const int ns = h_flags[0], nb = h_flags[1];
-    fill<int>(flags.p + 2, 0, 1, s);
+    const int ns = h_flags[0], nb = h_flags[1], nh = h_flags[2];
     if (ns > 0)
       hipLaunchKernelGGL((k_spgemm_count<512, 4>), dim3(cdiv(ns, 4)), dim3(256), 0, s, small.p, ns, A.ptr.p, A.col.p, B.ptr.p,
-                         B.col.p, cnt.p, flags.p + 2);
+                         B.col.p, cnt.p, flags.p + 3);
     if (nb > 0)
       hipLaunchKernelGGL((k_spgemm_count<SPG_COUNT_CAP, 1>), dim3(nb), dim3(64), 0, s, big.p, nb, A.ptr.p, A.col.p, B.ptr.p,
-                         B.col.p, cnt.p, flags.p + 2);
+                         B.col.p, cnt.p, flags.p + 3);
+    if (nh > 0) {
+      const int slots = spa_slots(B.nc, nh, 0);
+      DBuf<int> f((size_t)slots * B.nc);
+      fill<int>(f.p, 0, (int64_t)slots * B.nc, s);
+      for (int r0 = 0; r0 < nh; r0 += slots)
+        hipLaunchKernelGGL(k_spa_count, dim3(std::min(slots, nh - r0)), dim3(256), 0, s, huge.p + r0, A.ptr.p, A.col.p,
+                           B.ptr.p, B.col.p, B.nc, f.p, cnt.p);
+      NF_HIP(hipStreamSynchronize(s));
+    }
     NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
-    NF_CHECK(h_flags[2] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 4096 distinct columns");
+    NF_CHECK(h_flags[3] == 0, NFIELD_ENOMEM, "spgemm: LDS hash table overflow");
   }
   C.nnz = exclusive_scan(cnt.p, C.ptr.p, A.nr, s);
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val.alloc(C.nnz > 0 ? C.nnz : 1);
   if (C.nnz == 0) return;
-  fill<int>(flags.p, 0, 4, s);
+  fill<int>(flags.p, 0, 8, s);
   hipLaunchKernelGGL(k_bin_rows, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, C.ptr.p, 256, 2048, small.p, flags.p, big.p,
-                     flags.p + 1, flags.p + 2);
+                     flags.p + 1, huge.p, flags.p + 2, flags.p + 3);
   NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
-  NF_CHECK(h_flags[2] == 0, NFIELD_ENOMEM, "spgemm: a product row has more than 2048 entries");
   if (h_flags[0] > 0)
     hipLaunchKernelGGL(k_spgemm_fill<512>, dim3(h_flags[0]), dim3(64), 0, s, small.p, h_flags[0], A.ptr.p, A.col.p, A.val.p,
                        B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
   if (h_flags[1] > 0)
     hipLaunchKernelGGL(k_spgemm_fill<4096>, dim3(h_flags[1]), dim3(64), 0, s, big.p, h_flags[1], A.ptr.p, A.col.p, A.val.p,
                        B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+  if (h_flags[2] > 0) {
+    const int nh = h_flags[2];
+    int ts = 1;
+    while (ts < h_flags[3]) ts <<= 1;
+    const int slots = spa_slots(B.nc, nh, ts);
+    DBuf<int> f((size_t)slots * B.nc), ks((size_t)slots * ts);
+    DBuf<double> acc((size_t)slots * B.nc);
+    fill<int>(f.p, 0, (int64_t)slots * B.nc, s);
+    fill<double>(acc.p, 0.0, (int64_t)slots * B.nc, s);
+    for (int r0 = 0; r0 < nh; r0 += slots)
+      hipLaunchKernelGGL(k_spa_fill, dim3(std::min(slots, nh - r0)), dim3(256), 0, s, huge.p + r0, A.ptr.p, A.col.p, A.val.p,
+                         B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p, B.nc, f.p, acc.p, ks.p, ts);
+  }
+  NF_HIP(hipGetLastError());
   NF_HIP(hipStreamSynchronize(s));
 }
 
@@ -1398,14 +1521,23 @@ __global__ void k_transpose_place(int nr, const int* __restrict__ ptr, const int
   }
 }
 // sort each row of (col, val) pairs by column: one wavefront per row,
-// bitonic sort in LDS (rows up to 4096 entries)
-__global__ __launch_bounds__(64) void k_sort_rows(int nr, const int* __restrict__ ptr, int* col, double* val, int* overflow) {
+// bitonic sort in LDS (rows up to 4096 entries); longer rows are listed in
+// longrows (count in longinfo[0], largest length in longinfo[1]) for
+// k_sort_long_rows
+__global__ __launch_bounds__(64) void k_sort_rows(int nr, const int* __restrict__ ptr, int* col, double* val, int* longrows,
+                                                  int* longinfo) {
   __shared__ int ks[4096];
   __shared__ double vs[4096];
   const int row = blockIdx.x, lane = threadIdx.x;
   const int p0 = ptr[row], len = ptr[row + 1] - p0;
   if (len <= 1) return;
-  if (len > 4096) { if (lane == 0) atomicOr(overflow, 1); return; }
+  if (len > 4096) {
+    if (lane == 0) {
+      longrows[atomicAdd(&longinfo[0], 1)] = row;
+      atomicMax(&longinfo[1], len);
+    }
+    return;
+  }
   int ts = 1;
   while (ts < len) ts <<= 1;
   for (int i = lane; i < ts; i += 64) {
@@ -1436,13 +1568,49 @@ __global__ __launch_bounds__(64) void k_sort_rows(int nr, const int* __restrict_
     val[p0 + i] = vs[i];
   }
 }
+// the same bitonic sort for rows longer than 4096 entries: one workgroup per
+// listed row, in a power-of-two scratch of ts pairs per row
+__global__ __launch_bounds__(1024) void k_sort_long_rows(const int* __restrict__ rows, const int* __restrict__ ptr, int* col,
+                                                         double* val, int* kscr, double* vscr, int ts) {
+  const int row = rows[blockIdx.x], t = threadIdx.x;
+  const int p0 = ptr[row], len = ptr[row + 1] - p0;
+  int* ks = kscr + (int64_t)blockIdx.x * ts;
+  double* vs = vscr + (int64_t)blockIdx.x * ts;
+  for (int i = t; i < ts; i += 1024) {
+    ks[i] = i < len ? col[p0 + i] : EMPTY_KEY;
+    vs[i] = i < len ? val[p0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < ts; i += 1024) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = ks[i], y = ks[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) {
+            ks[i] = y;
+            ks[ixj] = x;
+            const double v = vs[i];
+            vs[i] = vs[ixj];
+            vs[ixj] = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = t; i < len; i += 1024) {
+    col[p0 + i] = ks[i];
+    val[p0 + i] = vs[i];
+  }
+}
 void transpose(const DCsr& A, DCsr& T, hipStream_t s) {
   T.nr = A.nc;
   T.nc = A.nr;
-  DBuf<int> cnt(A.nc + 1), cursor(A.nc + 1), flag(1);
+  DBuf<int> cnt(A.nc + 1), cursor(A.nc + 1), longrows(A.nc > 0 ? A.nc : 1), longinfo(2);
   fill<int>(cnt.p, 0, A.nc + 1, s);
   fill<int>(cursor.p, 0, A.nc + 1, s);
-  fill<int>(flag.p, 0, 1, s);
+  fill<int>(longinfo.p, 0, 2, s);
   if (A.nnz > 0) hipLaunchKernelGGL(k_col_count, dim3(cdiv(A.nnz, 256)), dim3(256), 0, s, A.nnz, A.col.p, cnt.p);
   T.ptr.alloc(A.nc + 1);
   T.nnz = exclusive_scan(cnt.p, T.ptr.p, A.nc, s);
@@ -1451,11 +1619,23 @@ void transpose(const DCsr& A, DCsr& T, hipStream_t s) {
   if (A.nr > 0)
     hipLaunchKernelGGL(k_transpose_place, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, A.val.p, T.ptr.p,
                        cursor.p, T.col.p, T.val.p);
-  if (T.nr > 0) hipLaunchKernelGGL(k_sort_rows, dim3(T.nr), dim3(64), 0, s, T.nr, T.ptr.p, T.col.p, T.val.p, flag.p);
-  int f = 0;
-  NF_HIP(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (T.nr > 0)
+    hipLaunchKernelGGL(k_sort_rows, dim3(T.nr), dim3(64), 0, s, T.nr, T.ptr.p, T.col.p, T.val.p, longrows.p, longinfo.p);
+  int info[2] = {0, 0};
+  NF_HIP(hipMemcpyAsync(info, longinfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
-  NF_CHECK(f == 0, NFIELD_ENOMEM, "transpose: a column has more than 4096 entries");
+  if (info[0] > 0) {
+    int ts = 1;
+    while (ts < info[1]) ts <<= 1;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(info[0], ((int64_t)1 << 28) / ((int64_t)ts * 12)));
+    DBuf<int> kscr((size_t)chunk * ts);
+    DBuf<double> vscr((size_t)chunk * ts);
+    for (int c0 = 0; c0 < info[0]; c0 += chunk)
+      hipLaunchKernelGGL(k_sort_long_rows, dim3(std::min(chunk, info[0] - c0)), dim3(1024), 0, s, longrows.p + c0, T.ptr.p,
+                         T.col.p, T.val.p, kscr.p, vscr.p, ts);
+    NF_HIP(hipGetLastError());
+    NF_HIP(hipStreamSynchronize(s));
+  }
 }
 
 // ================================================================ sparse add
@@ -1573,6 +1753,7 @@ void csr_to_dense(const DCsr& A, double* M, int64_t ld, int r0, int c0, hipStrea
 // Afterwards the matrix holds (P M)^-1 for the row permutation P of the
 // pivots, and the column swaps in reverse order turn it into M^-1.
 constexpr int GJ_NB = 32;
+constexpr int GJ_UNROLL = 8;
 constexpr int DENSE_MAX = 12000;
 
 __global__ __launch_bounds__(1024) void k_gj_panel(double* __restrict__ M, int n, int k0, int kb, int* __restrict__ piv,
@@ -1639,16 +1820,26 @@ __global__ __launch_bounds__(1024) void k_gj_panel(double* __restrict__ M, int n
     // eliminate column k from every other row (panel columns only) and
     // track the next pivot candidate among rows > k
     const int nxt = k + 1 - k0;          // panel column of the next pivot
+    const int j = k0 + lane;
+    const bool active = lane < kb;
     double best = -1.0;
     int bi = n;
-    for (int i = grp; i < n; i += 32) {
-      if (i == k) continue;
-      const double f = M[(int64_t)i * n + k];
-      if (lane < kb) {
-        const int j = k0 + lane;
-        const double v = j == k ? -f / a : M[(int64_t)i * n + j] - f * rowk[lane];
-        M[(int64_t)i * n + j] = v;
-        if (lane == nxt && i > k && fabs(v) > best) { best = fabs(v); bi = i; }
+    // rows in batches of GJ_UNROLL per group so that their loads overlap
+    for (int base = grp; base < n; base += 32 * GJ_UNROLL) {
+      double f[GJ_UNROLL], v[GJ_UNROLL];
+#pragma unroll
+      for (int u = 0; u < GJ_UNROLL; ++u) {
+        const int i = base + 32 * u;
+        f[u] = i < n ? M[(int64_t)i * n + k] : 0.0;
+        v[u] = (i < n && active) ? M[(int64_t)i * n + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < GJ_UNROLL; ++u) {
+        const int i = base + 32 * u;
+        if (i >= n || i == k || !active) continue;
+        const double w = j == k ? -f[u] / a : v[u] - f[u] * rowk[lane];
+        M[(int64_t)i * n + j] = w;
+        if (lane == nxt && i > k && fabs(w) > best) { best = fabs(w); bi = i; }
       }
     }
     if (nxt < kb) {

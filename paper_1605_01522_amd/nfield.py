@@ -355,6 +355,9 @@ class NField:
     def nlevels(self, h=0):
         return lib().nfield_hier_nlevels(self.ctx, h)
 
+    def nfields(self, h=0):
+        return lib().nfield_hier_nfields(self.ctx, h)
+
     def level_size(self, h, l, f=0):
         return lib().nfield_hier_size(self.ctx, h, l, f)
 
