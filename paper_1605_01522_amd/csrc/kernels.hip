@@ -936,17 +936,10 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
 // written after all of the group's loads have completed, so the node's dofs
 // are relaxed together from their old values.
 template <int G, int B2, int NR, class T>
-__global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
-                                                   const int* __restrict__ ptr, const int* __restrict__ col,
-                                                   const T* __restrict__ val, const T* __restrict__ dinv, T omega,
-                                                   const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
-                                                   int nrhs) {
-  constexpr int NG = G * B2;
-  const int gid = blockIdx.x * 256 + threadIdx.x;
-  const int t = gid / NG, sub = gid % NG;
+__device__ __forceinline__ void sgs_node(int u, int sub, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                                         const T* __restrict__ val, const T* __restrict__ dinv, T omega,
+                                         const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
   const int q = sub / G, lane = sub % G;
-  if (t >= nnodes) return;
-  const int u = nodes[t];
   const int r = u * b + q;
   T acc[NR];
 #pragma unroll
@@ -971,6 +964,75 @@ __global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __rest
   }
 }
 
+template <int G, int B2, int NR, class T>
+__global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
+                                                   const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinv, T omega,
+                                                   const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
+                                                   int nrhs) {
+  constexpr int NG = G * B2;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int t = gid / NG;
+  if (t >= nnodes) return;
+  sgs_node<G, B2, NR, T>(nodes[t], gid % NG, b, ptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+}
+
+// A whole sweep over every colour of a small level in one workgroup: the
+// colours run in turn with a barrier between them (the same per-node update
+// as k_sgs_color, so the results are the same bits).
+template <int G, int B2, int NR, class T>
+__global__ __launch_bounds__(1024) void k_sgs_sweep1(const int* __restrict__ nodes, const int* __restrict__ off, int ncolors,
+                                                     int forward, int b, const int* __restrict__ ptr,
+                                                     const int* __restrict__ col, const T* __restrict__ val,
+                                                     const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
+                                                     int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
+  constexpr int NG = G * B2, PER = 1024 / NG;
+  const int grp = threadIdx.x / NG, sub = threadIdx.x % NG;
+  for (int ci = 0; ci < ncolors; ++ci) {
+    const int c = forward ? ci : ncolors - 1 - ci;
+    const int n1 = off[c + 1];
+    for (int t = off[c] + grp; t < n1; t += PER)
+      sgs_node<G, B2, NR, T>(nodes[t], sub, b, ptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+    __syncthreads();
+  }
+}
+
+// One workgroup per node for long rows: 256 / B2 lanes per row (rows in
+// separate wavefronts when B2 <= 4), all loads of the node before a barrier,
+// then the writes.
+template <int G, int B2, int NR, class T>
+__global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+                                                  const int* __restrict__ col, const T* __restrict__ val,
+                                                  const T* __restrict__ dinv, T omega, const T* __restrict__ rhs, int64_t ldr,
+                                                  T* __restrict__ x, int64_t ldx, int nrhs) {
+  static_assert(G * B2 == 256 && G <= 64, "one node per 256-thread workgroup");
+  const int u = nodes[blockIdx.x];
+  const int q = threadIdx.x / G, lane = threadIdx.x % G;
+  const int r = u * b + q;
+  T acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  if (q < b)
+    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) {
+      const T v = val[p];
+      const int c = col[p];
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nrhs) acc[k] += v * x[k * ldx + c];
+    }
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
+  __syncthreads();
+  if (q < b && lane == 0) {
+    const T w = omega * dinv[r];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) x[k * ldx + r] += w * (rhs[k * ldr + r] - acc[k]);
+  }
+}
+
 template <int G, int B2, class T>
 static void sgs_launch(const DCsr& A, int b, const int* nodes, int nnodes, const T* val, const T* dinv, T omega,
                        const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
@@ -983,12 +1045,77 @@ static void sgs_launch(const DCsr& A, int b, const int* nodes, int nnodes, const
                        val, dinv, omega, rhs, ldr, x, ldx, nrhs);
 }
 
+template <int G, int B2, class T>
+static void sgs_sweep1_launch(const int* nodes, const int* off, int nc, bool forward, const DCsr& A, int b, const T* val,
+                              const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, 1, T>), dim3(1), dim3(1024), 0, s, nodes, off, nc, forward ? 1 : 0, b, A.ptr.p,
+                       A.col.p, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+  else
+    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, NRMAX, T>), dim3(1), dim3(1024), 0, s, nodes, off, nc, forward ? 1 : 0, b,
+                       A.ptr.p, A.col.p, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+}
+
+template <int B2, class T>
+static void sgs_node_launch(const int* nodes, int nnodes, const DCsr& A, int b, const T* val, const T* dinv, T omega,
+                            const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+  constexpr int G = 256 / B2;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_sgs_node<G, B2, 1, T>), dim3(nnodes), dim3(256), 0, s, nodes, b, A.ptr.p, A.col.p, val, dinv, omega,
+                       rhs, ldr, x, ldx, nrhs);
+  else
+    hipLaunchKernelGGL((k_sgs_node<G, B2, NRMAX, T>), dim3(nnodes), dim3(256), 0, s, nodes, b, A.ptr.p, A.col.p, val, dinv,
+                       omega, rhs, ldr, x, ldx, nrhs);
+}
+
 int sgs_lanes(const DCsr& A, int b) {
   int b2 = 1;
   while (b2 < b) b2 <<= 1;
   int g = spmv_group(A.nr, A.nnz);
   while (g * b2 > 64) g >>= 1;
   return g < 2 ? 2 : g;
+}
+
+int sgs_kind(const DCsr& A, int b, int nnodes_total) {
+  const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+  if (A.nnz <= SGS_SWEEP1_MAX_NNZ && A.nr > 0 && A.nnz / A.nr <= SGS_SWEEP1_MAX_ROW && nnodes_total <= SGS_SWEEP1_MAX_NODES)
+    return SGS_SWEEP1;
+  if (B2 >= 4 && A.nr > 0 && A.nnz / A.nr >= SGS_NODE_MIN_ROW) return SGS_NODE;
+  return SGS_COLOR;
+}
+
+template <class T>
+void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off, bool forward,
+               const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+  const int nc = (int)off.size() - 1;
+  if (nc <= 0) return;
+  NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
+  NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
+  const T* val = csr_values<T>(A);
+  const int kind = sgs_kind(A, b, off[nc]);
+  const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+  if (kind == SGS_SWEEP1) {
+    const int G = sgs_lanes(A, b);
+#define NF_SGS1(GG, BB) \
+  if (G == GG && B2 == BB) return sgs_sweep1_launch<GG, BB, T>(nodes, off_dev, nc, forward, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+    NF_SGS1(2, 1) NF_SGS1(4, 1) NF_SGS1(8, 1) NF_SGS1(16, 1) NF_SGS1(32, 1) NF_SGS1(64, 1)
+    NF_SGS1(2, 2) NF_SGS1(4, 2) NF_SGS1(8, 2) NF_SGS1(16, 2) NF_SGS1(32, 2)
+    NF_SGS1(2, 4) NF_SGS1(4, 4) NF_SGS1(8, 4) NF_SGS1(16, 4)
+    NF_SGS1(2, 8) NF_SGS1(4, 8) NF_SGS1(8, 8)
+#undef NF_SGS1
+    throw NfError(NFIELD_EINVAL, "Gauss-Seidel: no kernel for this lane layout");
+  }
+  for (int i = 0; i < nc; ++i) {
+    const int c = forward ? i : nc - 1 - i;
+    const int m = off[c + 1] - off[c];
+    if (m <= 0) continue;
+    if (kind == SGS_NODE) {
+      if (B2 == 4) sgs_node_launch<4, T>(nodes + off[c], m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+      else sgs_node_launch<8, T>(nodes + off[c], m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+    } else {
+      sgs_color<T>(A, b, nodes + off[c], m, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+    }
+  }
 }
 
 template <class T>
@@ -1048,6 +1175,10 @@ void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int
   }
 }
 
+template void sgs_sweep<double>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const double*,
+                                double, const double*, int64_t, double*, int64_t, int, hipStream_t);
+template void sgs_sweep<float>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const float*, float,
+                               const float*, int64_t, float*, int64_t, int, hipStream_t);
 template void sgs_color<double>(const DCsr&, int, const int*, int, const double*, double, const double*, int64_t, double*,
                                 int64_t, int, hipStream_t);
 template void sgs_color<float>(const DCsr&, int, const int*, int, const float*, float, const float*, int64_t, float*,

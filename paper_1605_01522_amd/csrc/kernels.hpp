@@ -109,6 +109,21 @@ int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int*
 template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega,
                                   const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
 int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kernel
+// kernel layout of a sweep: SGS_SWEEP1 = every colour in one workgroup (small
+// levels), SGS_NODE = one workgroup per node (long rows), SGS_COLOR = one
+// lane group per node, a launch per colour
+enum { SGS_COLOR = 0, SGS_SWEEP1 = 1, SGS_NODE = 2 };
+constexpr int64_t SGS_SWEEP1_MAX_NNZ = 200000;
+constexpr int64_t SGS_SWEEP1_MAX_ROW = 48;
+constexpr int SGS_SWEEP1_MAX_NODES = 65536;
+constexpr int64_t SGS_NODE_MIN_ROW = 192;
+int sgs_kind(const DCsr& A, int b, int nnodes_total);
+// one sweep over all colours (forward: ascending colour order), nodes grouped
+// by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
+// device as off_dev)
+template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off,
+                                  bool forward, const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx,
+                                  int nrhs, hipStream_t s);
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)
 void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,

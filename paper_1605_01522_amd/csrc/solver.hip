@@ -164,6 +164,8 @@ struct SgsD : FieldSmootherD<T> {
   DBuf<T> dinv;
   DBuf<int> nodes;                 // nodes grouped by colour
   std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
+  DBuf<int> off_dev;
+  int kind = SGS_COLOR;
   void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s) {
     A = A_;
     b = b_;
@@ -189,7 +191,10 @@ struct SgsD : FieldSmootherD<T> {
     for (int u = 0; u < nn; ++u) list[cur[hc[u]]++] = u;
     nodes.alloc(list.size());
     NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
+    off_dev.alloc(off.size());
+    NF_HIP(hipMemcpyAsync(off_dev.p, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
     NF_HIP(hipStreamSynchronize(s));
+    kind = sgs_kind(*A, b, nn);
     // bytes of a sweep are counted only while launch timing is recording
     sweep_bytes = 0.0;
     sweep_bytes_x = 0.0;
@@ -211,13 +216,15 @@ struct SgsD : FieldSmootherD<T> {
   void sweep(bool forward, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const int nc = (int)off.size() - 1;
     const int slot = prof_begin(s);
-    for (int i = 0; i < nc; ++i) {
-      const int c = forward ? i : nc - 1 - i;
-      sgs_color<T>(*A, b, nodes.p + off[c], off[c + 1] - off[c], dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
-    }
+    sgs_sweep<T>(*A, b, nodes.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-    prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 10 + 6) * 10 + (sizeof(T) == 4 ? 1 : 0),
-             sweep_bytes + nrhs * sweep_bytes_x, nc);
+    const int lanes = kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
+    const int mode = kind == SGS_SWEEP1 ? 7 : kind == SGS_NODE ? 8 : 6;
+    int launches = kind == SGS_SWEEP1 ? 1 : 0;
+    if (kind != SGS_SWEEP1)
+      for (int c = 0; c < nc; ++c) launches += off[c + 1] > off[c] ? 1 : 0;
+    prof_end(slot, s, ((lanes * 16 + b2) * 10 + mode) * 10 + (sizeof(T) == 4 ? 1 : 0),
+             sweep_bytes + nrhs * sweep_bytes_x, launches);
   }
   void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
     if (zero_guess) fillm<T>(x, ldx, (T)0, n, nrhs, s);
