@@ -1875,111 +1875,115 @@ void csr_to_dense(const DCsr& A, double* M, int64_t ld, int r0, int c0, hipStrea
 // In-place Gauss-Jordan inverse of a row-major n x n matrix with partial
 // pivoting (largest magnitude, lowest row on ties), blocked by column panels
 // of GJ_NB.  Per panel K = [k0, k0 + kb):
-//  1. one workgroup runs the kb pivot steps, each restricted to the panel's
-//     columns but applied to every row (row swaps cover whole rows); the
-//     panel then holds the columns K of the elimination matrix T;
-//  2. Y = rows K of the other columns, which are zeroed;
-//  3. every column outside K gets += T[:, K] Y (a rank-kb update), which
-//     applies the deferred eliminations to them.
+//  1. the panel's columns are packed into a compact n x GJ_NB buffer and the
+//     kb pivot steps run on it, one launch per step over all rows (the step
+//     reads one buffer and writes the other, so rows never race); a step
+//     swaps rows k and p in the panel, scales the pivot row and eliminates
+//     column k from every other row, leaving the panel holding columns K of
+//     the elimination matrix T; each workgroup also offers its best
+//     candidate for the next pivot;
+//  2. the pivots' row swaps are applied to the other columns, Y = rows K of
+//     those columns is saved and zeroed, and every column outside K gets
+//     += T[:, K] Y (a rank-kb update), the deferred eliminations.
 // Afterwards the matrix holds (P M)^-1 for the row permutation P of the
-// pivots, and the column swaps in reverse order turn it into M^-1.
+// pivots; permuting its columns (the swaps in reverse order) gives M^-1.
 constexpr int GJ_NB = 32;
-constexpr int GJ_UNROLL = 8;
+constexpr int GJ_RPW = 8;          // panel rows per 256-thread workgroup
 constexpr int DENSE_MAX = 12000;
 
-__global__ __launch_bounds__(1024) void k_gj_panel(double* __restrict__ M, int n, int k0, int kb, int* __restrict__ piv,
-                                                   int* __restrict__ singular) {
-  __shared__ double rowk[GJ_NB];
-  __shared__ double redv[32];
-  __shared__ int redi[32];
-  __shared__ int pivrow;
-  __shared__ double pivabs, piva;
-  if (*singular) return;                       // an earlier panel failed
+__device__ __forceinline__ void gj_better(double& bv, int& bi, double ov, int oi) {
+  if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+}
+// workgroup-wide best (value, index) of 256 threads; result in every thread
+__device__ __forceinline__ void gj_block_best(double& bv, int& bi, double* sv, int* si) {
+  for (int off = 32; off > 0; off >>= 1) gj_better(bv, bi, __shfl_xor(bv, off), __shfl_xor(bi, off));
   const int t = threadIdx.x;
-  const int lane = t & 31, grp = t >> 5;       // 32 groups of 32 lanes; lane = panel column
-  // pivot candidate for the first column of the panel
-  {
-    double best = -1.0;
-    int bi = n;
-    for (int r = k0 + t; r < n; r += 1024) {
-      const double v = fabs(M[(int64_t)r * n + k0]);
-      if (v > best) { best = v; bi = r; }
-    }
-    for (int off = 16; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 32);
-      const int oi = __shfl_xor(bi, off, 32);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if (lane == 0) { redv[grp] = best; redi[grp] = bi; }
-  }
   __syncthreads();
+  if ((t & 63) == 0) { sv[t >> 6] = bv; si[t >> 6] = bi; }
+  __syncthreads();
+  bv = sv[0];
+  bi = si[0];
+  for (int w = 1; w < 4; ++w) gj_better(bv, bi, sv[w], si[w]);
+}
+
+// pack columns K into PB and offer the candidates of column k0 (rows >= k0)
+__global__ __launch_bounds__(256) void k_gj_pack(const double* __restrict__ M, double* __restrict__ PB, int n, int k0, int kb,
+                                                 double* __restrict__ cv, int* __restrict__ ci) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int t = threadIdx.x, lane = t & 31;
+  const int i = blockIdx.x * GJ_RPW + (t >> 5);
+  double bv = -1.0;
+  int bi = n;
+  if (i < n) {
+    const double v = lane < kb ? M[(int64_t)i * n + k0 + lane] : 0.0;
+    PB[(int64_t)i * GJ_NB + lane] = v;
+    if (lane == 0 && i >= k0) { bv = fabs(v); bi = i; }
+  }
+  gj_block_best(bv, bi, sv, si);
+  if (t == 0) { cv[blockIdx.x] = bv; ci[blockIdx.x] = bi; }
+}
+
+// one pivot step k on the packed panel: PBin -> PBout
+__global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ PBin, double* __restrict__ PBout, int n, int k0,
+                                                 int kb, int k, int nwg, const double* __restrict__ cv_in,
+                                                 const int* __restrict__ ci_in, double* __restrict__ cv_out,
+                                                 int* __restrict__ ci_out, int* __restrict__ piv, int* __restrict__ singular) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  if (*singular) return;
+  const int t = threadIdx.x, lane = t & 31;
+  double bv = -1.0;
+  int bi = n;
+  for (int w = t; w < nwg; w += 256) gj_better(bv, bi, cv_in[w], ci_in[w]);
+  gj_block_best(bv, bi, sv, si);
+  const int p = bi;
+  if (!(bv > 0.0)) {                   // zero (or NaN) column below the diagonal
+    if (blockIdx.x == 0 && t == 0) *singular = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && t == 0) piv[k] = p;
+  const int jj = k - k0;
+  const double a = PBin[(int64_t)p * GJ_NB + jj];
+  const double pr = PBin[(int64_t)p * GJ_NB + lane];
+  const double scaled = lane == jj ? 1.0 / a : pr / a;
+  const int i = blockIdx.x * GJ_RPW + (t >> 5);
+  double cb = -1.0;
+  int cbi = n;
+  if (i < n) {
+    double v;
+    if (i == k) {
+      v = scaled;
+    } else {
+      const int src = i == p ? k : i;
+      const double f = PBin[(int64_t)src * GJ_NB + jj];
+      v = lane == jj ? -f / a : PBin[(int64_t)src * GJ_NB + lane] - f * scaled;
+    }
+    if (lane < kb) PBout[(int64_t)i * GJ_NB + lane] = v;
+    if (lane == jj + 1 && i > k) { cb = fabs(v); cbi = i; }
+  }
+  gj_block_best(cb, cbi, sv, si);
+  if (t == 0) { cv_out[blockIdx.x] = cb; ci_out[blockIdx.x] = cbi; }
+}
+
+__global__ void k_gj_unpack(double* __restrict__ M, const double* __restrict__ PB, int n, int k0, int kb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * GJ_NB) return;
+  const int i = (int)(e / GJ_NB), lane = (int)(e % GJ_NB);
+  if (lane < kb) M[(int64_t)i * n + k0 + lane] = PB[e];
+}
+
+// the panel's row swaps on every column outside the panel (one thread per column)
+__global__ void k_gj_swaprows(double* __restrict__ M, int n, int k0, int kb, const int* __restrict__ piv) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + kb)) return;
   for (int k = k0; k < k0 + kb; ++k) {
-    if (t < 32) {
-      double best = redv[t];
-      int bi = redi[t];
-      for (int off = 16; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off, 32);
-        const int oi = __shfl_xor(bi, off, 32);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (t == 0) { pivrow = bi; pivabs = best; }
+    const int p = piv[k];
+    if (p != k) {
+      const double a = M[(int64_t)k * n + j];
+      M[(int64_t)k * n + j] = M[(int64_t)p * n + j];
+      M[(int64_t)p * n + j] = a;
     }
-    __syncthreads();
-    const int p = pivrow;
-    if (!(pivabs > 0.0)) {            // zero (or NaN) column below the diagonal
-      if (t == 0) *singular = 1;
-      return;
-    }
-    if (t == 0) piv[k] = p;
-    if (p != k)
-      for (int c = t; c < n; c += 1024) {
-        const double a = M[(int64_t)k * n + c];
-        M[(int64_t)k * n + c] = M[(int64_t)p * n + c];
-        M[(int64_t)p * n + c] = a;
-      }
-    __syncthreads();
-    if (t == 0) piva = M[(int64_t)k * n + k];
-    __syncthreads();
-    const double a = piva;           // read before the pivot row is overwritten
-    if (t < kb) {
-      const int j = k0 + t;
-      const double v = j == k ? 1.0 / a : M[(int64_t)k * n + j] / a;
-      rowk[t] = v;
-      M[(int64_t)k * n + j] = v;
-    }
-    __syncthreads();
-    // eliminate column k from every other row (panel columns only) and
-    // track the next pivot candidate among rows > k
-    const int nxt = k + 1 - k0;          // panel column of the next pivot
-    const int j = k0 + lane;
-    const bool active = lane < kb;
-    double best = -1.0;
-    int bi = n;
-    // rows in batches of GJ_UNROLL per group so that their loads overlap
-    for (int base = grp; base < n; base += 32 * GJ_UNROLL) {
-      double f[GJ_UNROLL], v[GJ_UNROLL];
-#pragma unroll
-      for (int u = 0; u < GJ_UNROLL; ++u) {
-        const int i = base + 32 * u;
-        f[u] = i < n ? M[(int64_t)i * n + k] : 0.0;
-        v[u] = (i < n && active) ? M[(int64_t)i * n + j] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < GJ_UNROLL; ++u) {
-        const int i = base + 32 * u;
-        if (i >= n || i == k || !active) continue;
-        const double w = j == k ? -f[u] / a : v[u] - f[u] * rowk[lane];
-        M[(int64_t)i * n + j] = w;
-        if (lane == nxt && i > k && fabs(w) > best) { best = fabs(w); bi = i; }
-      }
-    }
-    if (nxt < kb) {
-      // lane nxt of each group holds that group's candidate
-      best = __shfl(best, nxt, 32);
-      bi = __shfl(bi, nxt, 32);
-      if (lane == 0) { redv[grp] = best; redi[grp] = bi; }
-    }
-    __syncthreads();
   }
 }
 
@@ -2033,49 +2037,64 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ M, const
   }
 }
 
+// out[i][j] = W[i][src[j]]
+__global__ void k_gj_gather_cols(const double* __restrict__ W, double* __restrict__ out, int n, const int* __restrict__ src) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  out[e] = W[(int64_t)i * n + src[j]];
+}
+
 __global__ void k_iota(int* v, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) v[i] = i;
 }
 
-// Column swaps of the pivots in reverse order; one thread per row.
-__global__ void k_gj_colswap(double* __restrict__ M, int n, const int* __restrict__ piv) {
-  extern __shared__ int sp[];
-  for (int k = threadIdx.x; k < n; k += blockDim.x) sp[k] = piv[k];
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double* row = M + (int64_t)i * n;
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = sp[k];
-    if (p != k) {
-      const double a = row[k];
-      row[k] = row[p];
-      row[p] = a;
-    }
-  }
-}
-
 int dense_inverse(double* M, int n, hipStream_t s) {
   if (n == 0) return 0;
   NF_CHECK(n <= DENSE_MAX, NFIELD_ENOMEM, "dense solve larger than " + std::to_string(DENSE_MAX) + " unknowns");
-  DBuf<double> Y((size_t)GJ_NB * n);
-  DBuf<int> piv(n), sing(1);
+  const int nwg = cdiv(n, GJ_RPW);
+  DBuf<double> Y((size_t)GJ_NB * n), PB0((size_t)GJ_NB * n), PB1((size_t)GJ_NB * n), cv(2 * (size_t)nwg);
+  DBuf<int> piv(n), sing(1), ci(2 * (size_t)nwg);
   fill<int>(sing.p, 0, 1, s);
   hipLaunchKernelGGL(k_iota, dim3(cdiv(n, 256)), dim3(256), 0, s, piv.p, n);
   const dim3 tiles(cdiv(n, 64), cdiv(n, 64));
   for (int k0 = 0; k0 < n; k0 += GJ_NB) {
     const int kb = std::min(GJ_NB, n - k0);
-    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(1024), 0, s, M, n, k0, kb, piv.p, sing.p);
+    hipLaunchKernelGGL(k_gj_pack, dim3(nwg), dim3(256), 0, s, M, PB0.p, n, k0, kb, cv.p, ci.p);
+    for (int k = k0; k < k0 + kb; ++k) {
+      const int c = (k - k0) & 1;        // step parity: which buffers are read
+      double* in = c ? PB1.p : PB0.p;
+      double* out = c ? PB0.p : PB1.p;
+      hipLaunchKernelGGL(k_gj_step, dim3(nwg), dim3(256), 0, s, in, out, n, k0, kb, k, nwg, cv.p + (size_t)c * nwg,
+                         ci.p + (size_t)c * nwg, cv.p + (size_t)(1 - c) * nwg, ci.p + (size_t)(1 - c) * nwg, piv.p, sing.p);
+    }
+    const double* fin = (kb & 1) ? PB1.p : PB0.p;
+    hipLaunchKernelGGL(k_gj_unpack, dim3(cdiv((int64_t)n * GJ_NB, 256)), dim3(256), 0, s, M, fin, n, k0, kb);
+    hipLaunchKernelGGL(k_gj_swaprows, dim3(cdiv(n, 256)), dim3(256), 0, s, M, n, k0, kb, piv.p);
     hipLaunchKernelGGL(k_gj_save, dim3(cdiv((int64_t)kb * n, 256)), dim3(256), 0, s, M, Y.p, n, k0, kb);
     hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, M, Y.p, n, k0, kb);
   }
-  hipLaunchKernelGGL(k_gj_colswap, dim3(cdiv(n, 256)), dim3(256), sizeof(int) * n, s, M, n, piv.p);
   NF_HIP(hipGetLastError());
   int h = 0;
+  std::vector<int> hp(n);
   NF_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipMemcpyAsync(hp.data(), piv.p, sizeof(int) * n, hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
-  return h ? -1 : 0;
+  if (h) return -1;
+  // column j of M^-1 is column src[j] of (P M)^-1: the swaps applied to the
+  // columns in reverse order
+  std::vector<int> src(n);
+  for (int j = 0; j < n; ++j) src[j] = j;
+  for (int k = n - 1; k >= 0; --k) std::swap(src[k], src[hp[k]]);
+  DBuf<int> dsrc(n);
+  DBuf<double> W((size_t)n * n);
+  NF_HIP(hipMemcpyAsync(dsrc.p, src.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  NF_HIP(hipMemcpyAsync(W.p, M, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_gj_gather_cols, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, W.p, M, n, dsrc.p);
+  NF_HIP(hipGetLastError());
+  NF_HIP(hipStreamSynchronize(s));
+  return 0;
 }
 
 // ===================================================================== SIMPLE
