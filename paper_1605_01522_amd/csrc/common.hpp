@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -32,23 +33,87 @@ struct NfError : std::runtime_error {
     if (!(cond)) throw ::nf::NfError((code), (msg));    \
   } while (0)
 
-// Device bytes currently owned through DBuf objects created while a counter
-// is installed (one counter per context; setup installs it).
-extern thread_local size_t* g_acct;
+// Per-context cache of device blocks.  Buffers created while a context's
+// pool is installed (g_pool, set by every entry point for the call) come from
+// and return to that pool instead of hipMalloc / hipFree (hipFree waits for
+// the whole device).  Blocks are kept by size class; a block freed during a
+// call is reused only by later work of the same context, and a call on a
+// different stream than the previous one first waits for that stream, so a
+// reused block is never still in use by an earlier kernel.
+struct DevPool {
+  size_t live = 0;                 // bytes in buffers handed out
+  size_t cached = 0;               // bytes held for reuse
+  hipStream_t last = nullptr;
+  bool used = false;
+  std::multimap<size_t, void*> blocks;
+  static size_t size_class(size_t b) {
+    if (b <= 4096) return (b + 255) & ~(size_t)255;
+    const int lg = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t g = (size_t)1 << (lg - 3);
+    return (b + g - 1) & ~(g - 1);
+  }
+  void* get(size_t cls) {
+    auto it = blocks.find(cls);
+    if (it != blocks.end()) {
+      void* p = it->second;
+      blocks.erase(it);
+      cached -= cls;
+      live += cls;
+      return p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e != hipSuccess && !blocks.empty()) {          // give the cache back and retry once
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, cls);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    live += cls;
+    return p;
+  }
+  void put(void* p, size_t cls) {
+    blocks.emplace(cls, p);
+    live -= cls;
+    cached += cls;
+  }
+  void trim() {
+    if (blocks.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& b : blocks) (void)hipFree(b.second);
+    blocks.clear();
+    cached = 0;
+  }
+  void enter(hipStream_t s) {
+    if (used && s != last) (void)hipStreamSynchronize(last);
+    used = true;
+    last = s;
+  }
+  ~DevPool() { trim(); }
+};
+extern thread_local DevPool* g_pool;
 
 // Owned device buffer (move-only).
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
-  size_t* acct = nullptr;
+  DevPool* pool = nullptr;
+  size_t cls = 0;
   DBuf() = default;
   explicit DBuf(size_t n_) { alloc(n_); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), acct(o.acct) { o.p = nullptr; o.n = 0; o.acct = nullptr; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), pool(o.pool), cls(o.cls) { o.p = nullptr; o.n = 0; o.pool = nullptr; o.cls = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; acct = o.acct; o.p = nullptr; o.n = 0; o.acct = nullptr; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; pool = o.pool; cls = o.cls;
+      o.p = nullptr; o.n = 0; o.pool = nullptr; o.cls = 0;
+    }
     return *this;
   }
   ~DBuf() { release(); }
@@ -56,25 +121,32 @@ struct DBuf {
     release();
     n = n_;
     if (n) {
-      hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
-      if (e != hipSuccess) {
-        p = nullptr;
+      if (g_pool) {
+        pool = g_pool;
+        cls = DevPool::size_class(n * sizeof(T));
+        p = (T*)pool->get(cls);
+      } else {
+        if (hipMalloc((void**)&p, n * sizeof(T)) != hipSuccess) {
+          (void)hipGetLastError();
+          p = nullptr;
+        }
+      }
+      if (!p) {
+        pool = nullptr;
         n = 0;
-        (void)hipGetLastError();
         throw NfError(NFIELD_ENOMEM, "device allocation of " + std::to_string(n_ * sizeof(T)) + " bytes failed");
       }
-      acct = g_acct;
-      if (acct) *acct += n * sizeof(T);
     }
   }
   void release() {
     if (p) {
-      (void)hipFree(p);
-      if (acct) *acct -= n * sizeof(T);
+      if (pool) pool->put(p, cls);
+      else (void)hipFree(p);
     }
     p = nullptr;
     n = 0;
-    acct = nullptr;
+    pool = nullptr;
+    cls = 0;
   }
   T* get() const { return p; }
   size_t bytes() const { return n * sizeof(T); }

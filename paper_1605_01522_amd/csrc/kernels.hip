@@ -1353,10 +1353,13 @@ __device__ __forceinline__ int hash_insert(int* table, int ts, int logts, int ke
 
 // distinct-column count of listed rows: WAVES rows per block, one wavefront
 // and one LDS hash table of CAP slots per row
+// (rows whose table fills up are appended to ovf, count in ovf_n, and are
+// counted again by the dense-accumulator path)
 template <int CAP, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_spgemm_count(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
                                                              const int* __restrict__ Ac, const int* __restrict__ Bp,
-                                                             const int* __restrict__ Bc, int* __restrict__ cnt, int* overflow) {
+                                                             const int* __restrict__ Bc, int* __restrict__ cnt, int* ovf,
+                                                             int* ovf_n) {
   __shared__ int tables[WAVES][CAP];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int idx = blockIdx.x * WAVES + w;
@@ -1380,8 +1383,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_spgemm_count(const int* __restri
   const int tot = wave_sum_int(mine);
   const int anyfull = wave_sum_int(full);
   if (lane == 0) {
-    cnt[row] = tot;
-    if (anyfull) atomicOr(overflow, 1);
+    if (anyfull) ovf[atomicAdd(ovf_n, 1)] = row;
+    else cnt[row] = tot;
   }
 }
 
@@ -1487,28 +1490,39 @@ __global__ __launch_bounds__(256) void k_spa_fill(const int* __restrict__ rows, 
   }
 }
 
-template <int CAP>
-__global__ __launch_bounds__(64) void k_spgemm_fill(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
-                                                    const int* __restrict__ Ac, const double* __restrict__ Av,
-                                                    const int* __restrict__ Bp, const int* __restrict__ Bc,
-                                                    const double* __restrict__ Bv, const int* __restrict__ Cp,
-                                                    int* __restrict__ Ccol, double* __restrict__ Cval) {
-  __shared__ int keys[CAP];
-  __shared__ double acc[CAP];
-  if ((int)blockIdx.x >= nrows) return;
-  const int row = rows[blockIdx.x], lane = threadIdx.x;
+// WAVES rows per workgroup, one wavefront and one LDS table of CAP slots per
+// row (wavefront-level barriers only)
+template <int CAP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_spgemm_fill(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
+                                                            const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                            const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                            const double* __restrict__ Bv, const int* __restrict__ Cp,
+                                                            int* __restrict__ Ccol, double* __restrict__ Cval) {
+  __shared__ int keys_all[WAVES][CAP];
+  __shared__ double acc_all[WAVES][CAP];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * WAVES + w;
+  if (idx >= nrows) return;            // whole wavefront leaves; only wavefront barriers below
+  int* keys = keys_all[w];
+  double* acc = acc_all[w];
+  const int row = rows[idx];
   const int c0 = Cp[row], cnt = Cp[row + 1] - c0;
   if (cnt == 0) return;
   int ts = 1, logts = 0;
   while (ts < 2 * cnt) { ts <<= 1; ++logts; }
   if (ts > CAP) { ts = CAP; logts = 0; for (int t = CAP; t > 1; t >>= 1) ++logts; }
+  auto wave_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   for (int i = lane; i < ts; i += 64) keys[i] = EMPTY_KEY;
-  __syncthreads();
+  wave_sync();
   for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
     const int k = Ac[p];
     for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) hash_insert(keys, ts, logts, Bc[q]);
   }
-  __syncthreads();
+  wave_sync();
   // bitonic sort of the table (ascending; empty slots sort last)
   for (int kk = 2; kk <= ts; kk <<= 1)
     for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -1520,10 +1534,10 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int* __restrict__ rows
           if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
         }
       }
-      __syncthreads();
+      wave_sync();
     }
   for (int i = lane; i < cnt; i += 64) acc[i] = 0.0;
-  __syncthreads();
+  wave_sync();
   for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
     const int k = Ac[p];
     const double a = Av[p];
@@ -1536,7 +1550,7 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int* __restrict__ rows
       }
       acc[lo] += a * Bv[q];
     }
-    __syncthreads();
+    wave_sync();
   }
   for (int i = lane; i < cnt; i += 64) {
     Ccol[c0 + i] = keys[i];
@@ -1579,17 +1593,22 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   fill<int>(cnt.p, 0, A.nr + 1, s);
   int h_flags[8];
   if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
+    // rows with an upper bound above 256 go to the 4096-slot table; rows it
+    // cannot hold (more than 4096 distinct columns) to the dense accumulator
     hipLaunchKernelGGL(k_spgemm_bin_ub, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, 256,
-                       SPG_COUNT_CAP, small.p, flags.p, big.p, flags.p + 1, huge.p, flags.p + 2, cnt.p);
+                       INT_MAX, small.p, flags.p, big.p, flags.p + 1, huge.p, flags.p + 2, cnt.p);
     NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
-    const int ns = h_flags[0], nb = h_flags[1], nh = h_flags[2];
+    const int ns = h_flags[0], nb = h_flags[1];
     if (ns > 0)
       hipLaunchKernelGGL((k_spgemm_count<512, 4>), dim3(cdiv(ns, 4)), dim3(256), 0, s, small.p, ns, A.ptr.p, A.col.p, B.ptr.p,
-                         B.col.p, cnt.p, flags.p + 3);
+                         B.col.p, cnt.p, huge.p, flags.p + 2);
     if (nb > 0)
       hipLaunchKernelGGL((k_spgemm_count<SPG_COUNT_CAP, 1>), dim3(nb), dim3(64), 0, s, big.p, nb, A.ptr.p, A.col.p, B.ptr.p,
-                         B.col.p, cnt.p, flags.p + 3);
+                         B.col.p, cnt.p, huge.p, flags.p + 2);
+    NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    const int nh = h_flags[2];
     if (nh > 0) {
       const int slots = spa_slots(B.nc, nh, 0);
       DBuf<int> f((size_t)slots * B.nc);
@@ -1599,9 +1618,6 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
                            B.ptr.p, B.col.p, B.nc, f.p, cnt.p);
       NF_HIP(hipStreamSynchronize(s));
     }
-    NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
-    NF_HIP(hipStreamSynchronize(s));
-    NF_CHECK(h_flags[3] == 0, NFIELD_ENOMEM, "spgemm: LDS hash table overflow");
   }
   C.nnz = exclusive_scan(cnt.p, C.ptr.p, A.nr, s);
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
@@ -1613,11 +1629,11 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
   if (h_flags[0] > 0)
-    hipLaunchKernelGGL(k_spgemm_fill<512>, dim3(h_flags[0]), dim3(64), 0, s, small.p, h_flags[0], A.ptr.p, A.col.p, A.val.p,
-                       B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+    hipLaunchKernelGGL((k_spgemm_fill<512, 4>), dim3(cdiv(h_flags[0], 4)), dim3(256), 0, s, small.p, h_flags[0], A.ptr.p,
+                       A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
   if (h_flags[1] > 0)
-    hipLaunchKernelGGL(k_spgemm_fill<4096>, dim3(h_flags[1]), dim3(64), 0, s, big.p, h_flags[1], A.ptr.p, A.col.p, A.val.p,
-                       B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+    hipLaunchKernelGGL((k_spgemm_fill<4096, 1>), dim3(h_flags[1]), dim3(64), 0, s, big.p, h_flags[1], A.ptr.p, A.col.p,
+                       A.val.p, B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
   if (h_flags[2] > 0) {
     const int nh = h_flags[2];
     int ts = 1;

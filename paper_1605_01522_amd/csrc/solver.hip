@@ -18,7 +18,7 @@
 
 namespace nf {
 
-thread_local size_t* g_acct = nullptr;
+thread_local DevPool* g_pool = nullptr;
 static thread_local std::string g_err;
 
 // ================================================================ helpers
@@ -570,6 +570,7 @@ static void check_spec(const Spec& sp) {
 
 // ============================================================== context
 struct nfield_ctx {
+  nf::DevPool pool;   // first member: destroyed after every buffer it backs
   int N = 0;
   std::vector<nf::FieldDev> F;
   nf::BlockMat A;
@@ -582,7 +583,6 @@ struct nfield_ctx {
   nf::Spec spec;
   std::vector<std::shared_ptr<nf::DBuf<int>>> gpos;   // per block: entry -> position in Aglob
   nf::DBuf<float> r32, z32;
-  size_t bytes = 0;
   double setup_s = 0.0;
   // GMRES workspace
   int ws_m = 0;
@@ -1207,8 +1207,9 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
   *out = nullptr;
   hipStream_t s = (hipStream_t)hip_stream;
   auto C = std::make_unique<nfield_ctx>();
-  size_t* prev = g_acct;
-  g_acct = &C->bytes;
+  DevPool* prev = g_pool;
+  g_pool = &C->pool;
+  C->pool.enter(s);
   try {
     const auto t0 = std::chrono::steady_clock::now();
     nfield_opts od;
@@ -1275,14 +1276,14 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
     NF_HIP(hipStreamSynchronize(s));
     NF_HIP(hipGetLastError());
     C->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    g_acct = prev;
+    g_pool = prev;
     *out = C.release();
     return NFIELD_OK;
   } catch (NfError& e) {
-    g_acct = prev;
+    g_pool = prev;
     return fail(e);
   } catch (std::exception& e) {
-    g_acct = prev;
+    g_pool = prev;
     g_err = e.what();
     return NFIELD_ENOMEM;
   }
@@ -1294,14 +1295,15 @@ void nfield_destroy(nfield_ctx* ctx) {
   delete ctx;
 }
 
-size_t nfield_footprint_bytes(const nfield_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+size_t nfield_footprint_bytes(const nfield_ctx* ctx) { return ctx ? ctx->pool.live + ctx->pool.cached : 0; }
 int64_t nfield_size(const nfield_ctx* ctx) { return ctx ? ctx->Aglob.nr : 0; }
 
 nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, int32_t nrhs, void* hip_stream) {
   if (!ctx || !r || !z || nrhs < 0) { g_err = "nfield_precond_apply: bad argument"; return NFIELD_EINVAL; }
   hipStream_t s = (hipStream_t)hip_stream;
-  size_t* prev = g_acct;
-  g_acct = &ctx->bytes;
+  DevPool* prev = g_pool;
+  g_pool = &ctx->pool;
+  ctx->pool.enter(s);
   try {
     const int64_t n = ctx->Aglob.nr;
     for (int k = 0; k < nrhs; k += NRMAX) {
@@ -1309,10 +1311,10 @@ nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, 
       precond(*ctx, r + k * n, n, z + k * n, n, nb, s);
     }
     NF_HIP(hipGetLastError());
-    g_acct = prev;
+    g_pool = prev;
     return NFIELD_OK;
   } catch (NfError& e) {
-    g_acct = prev;
+    g_pool = prev;
     return fail(e);
   }
 }
@@ -1349,8 +1351,9 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
     return NFIELD_EINVAL;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  size_t* prev = g_acct;
-  g_acct = &ctx->bytes;
+  DevPool* prev = g_pool;
+  g_pool = &ctx->pool;
+  ctx->pool.enter(s);
   try {
     const int64_t n = ctx->Aglob.nr;
     int worst = NFIELD_OK;
@@ -1369,11 +1372,11 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
         else if (worst >= 0 && st[q].status > worst) worst = st[q].status;
       }
     }
-    g_acct = prev;
+    g_pool = prev;
     if (worst < 0) g_err = "nfield_gmres_solve: non-finite value in the right-hand side or the iteration";
     return (nfield_status)worst;
   } catch (NfError& e) {
-    g_acct = prev;
+    g_pool = prev;
     return fail(e);
   }
 }
@@ -1403,18 +1406,19 @@ nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const 
 nfield_status nfield_rebuild(nfield_ctx* ctx, void* hip_stream) {
   if (!ctx) { g_err = "nfield_rebuild: null context"; return NFIELD_EINVAL; }
   hipStream_t s = (hipStream_t)hip_stream;
-  size_t* prev = g_acct;
-  g_acct = &ctx->bytes;
+  DevPool* prev = g_pool;
+  g_pool = &ctx->pool;
+  ctx->pool.enter(s);
   try {
     const auto t0 = std::chrono::steady_clock::now();
     build_tree(*ctx, s);
     NF_HIP(hipStreamSynchronize(s));
     NF_HIP(hipGetLastError());
     ctx->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    g_acct = prev;
+    g_pool = prev;
     return NFIELD_OK;
   } catch (NfError& e) {
-    g_acct = prev;
+    g_pool = prev;
     return fail(e);
   }
 }
