@@ -210,6 +210,41 @@ template void dense_gemvm<float>(const double*, int, const float*, int64_t, floa
 // columns at most per launch (the matrix row is read once for all columns).
 // Row sums are reduced with xor-shuffles inside the group; lane 0 of the
 // group applies the epilogue to every column.
+// sum over p = p0, p0 + G, ... < p1 of val[p] x[k ldx + col[p]] into s[k]
+// (k < nrhs), in ascending p; loads of four entries are issued before their
+// products so that their latencies overlap
+template <int G, int NR, class T>
+__device__ __forceinline__ void row_dot(int p0, int p1, const int* __restrict__ col, const T* __restrict__ val,
+                                        const T* __restrict__ x, int64_t ldx, int nrhs, T* s) {
+  int p = p0;
+  for (; p + 3 * G < p1; p += 4 * G) {
+    T v[4];
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[u] = val[p + u * G];
+      c[u] = col[p + u * G];
+    }
+    T xv[4][NR];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) xv[u][k] = k < nrhs ? x[k * ldx + c[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nrhs) s[k] += v[u] * xv[u][k];
+  }
+  for (; p < p1; p += G) {
+    const T v = val[p];
+    const int c = col[p];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) s[k] += v * x[k * ldx + c];
+  }
+}
+
 template <int G, int MODE, int NR, class T>
 __global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ ptr, const int* __restrict__ col,
                                               const T* __restrict__ val, SpmvArgs<T> a) {
@@ -222,13 +257,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ pt
   T s[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) s[k] = 0;
-  for (int p = p0 + lane; p < p1; p += G) {
-    const T v = val[p];
-    const int c = col[p];
-#pragma unroll
-    for (int k = 0; k < NR; ++k)
-      if (k < nrhs) s[k] += v * x[k * a.ldx + c];
-  }
+  row_dot<G, NR, T>(p0 + lane, p1, col, val, x, a.ldx, nrhs, s);
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
@@ -944,14 +973,7 @@ __device__ __forceinline__ void sgs_node(int u, int sub, int b, const int* __res
   T acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = 0;
-  if (q < b)
-    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) {
-      const T v = val[p];
-      const int c = col[p];
-#pragma unroll
-      for (int k = 0; k < NR; ++k)
-        if (k < nrhs) acc[k] += v * x[k * ldx + c];
-    }
+  if (q < b) row_dot<G, NR, T>(ptr[r] + lane, ptr[r + 1], col, val, x, ldx, nrhs, acc);
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
@@ -1012,14 +1034,7 @@ __global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes,
   T acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = 0;
-  if (q < b)
-    for (int p = ptr[r] + lane; p < ptr[r + 1]; p += G) {
-      const T v = val[p];
-      const int c = col[p];
-#pragma unroll
-      for (int k = 0; k < NR; ++k)
-        if (k < nrhs) acc[k] += v * x[k * ldx + c];
-    }
+  if (q < b) row_dot<G, NR, T>(ptr[r] + lane, ptr[r + 1], col, val, x, ldx, nrhs, acc);
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
@@ -1076,9 +1091,11 @@ int sgs_lanes(const DCsr& A, int b) {
   return g < 2 ? 2 : g;
 }
 
-int sgs_kind(const DCsr& A, int b, int nnodes_total) {
+int sgs_kind(const DCsr& A, int b, int nnodes_total, int ncolors) {
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-  if (A.nnz <= SGS_SWEEP1_MAX_NNZ && A.nr > 0 && A.nnz / A.nr <= SGS_SWEEP1_MAX_ROW && nnodes_total <= SGS_SWEEP1_MAX_NODES)
+  // one workgroup costs about as much as 8 per-colour launches on these levels
+  if (ncolors >= SGS_SWEEP1_MIN_COLORS && A.nnz <= SGS_SWEEP1_MAX_NNZ && A.nr > 0 && A.nnz / A.nr <= SGS_SWEEP1_MAX_ROW &&
+      nnodes_total <= SGS_SWEEP1_MAX_NODES)
     return SGS_SWEEP1;
   if (B2 >= 4 && A.nr > 0 && A.nnz / A.nr >= SGS_NODE_MIN_ROW) return SGS_NODE;
   return SGS_COLOR;
@@ -1092,7 +1109,7 @@ void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
   NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
   const T* val = csr_values<T>(A);
-  const int kind = sgs_kind(A, b, off[nc]);
+  const int kind = sgs_kind(A, b, off[nc], nc);
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
   if (kind == SGS_SWEEP1) {
     const int G = sgs_lanes(A, b);

@@ -113,11 +113,12 @@ int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kern
 // levels), SGS_NODE = one workgroup per node (long rows), SGS_COLOR = one
 // lane group per node, a launch per colour
 enum { SGS_COLOR = 0, SGS_SWEEP1 = 1, SGS_NODE = 2 };
-constexpr int64_t SGS_SWEEP1_MAX_NNZ = 200000;
-constexpr int64_t SGS_SWEEP1_MAX_ROW = 48;
+constexpr int64_t SGS_SWEEP1_MAX_NNZ = 65536;
+constexpr int64_t SGS_SWEEP1_MAX_ROW = 128;
 constexpr int SGS_SWEEP1_MAX_NODES = 65536;
-constexpr int64_t SGS_NODE_MIN_ROW = 192;
-int sgs_kind(const DCsr& A, int b, int nnodes_total);
+constexpr int SGS_SWEEP1_MIN_COLORS = 8;
+constexpr int64_t SGS_NODE_MIN_ROW = 128;
+int sgs_kind(const DCsr& A, int b, int nnodes_total, int ncolors);
 // one sweep over all colours (forward: ascending colour order), nodes grouped
 // by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
 // device as off_dev)

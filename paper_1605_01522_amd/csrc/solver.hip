@@ -194,7 +194,7 @@ struct SgsD : FieldSmootherD<T> {
     off_dev.alloc(off.size());
     NF_HIP(hipMemcpyAsync(off_dev.p, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
     NF_HIP(hipStreamSynchronize(s));
-    kind = sgs_kind(*A, b, nn);
+    kind = sgs_kind(*A, b, nn, nc);
     // bytes of a sweep are counted only while launch timing is recording
     sweep_bytes = 0.0;
     sweep_bytes_x = 0.0;
