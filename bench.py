@@ -45,6 +45,38 @@ SERVE_SPEC = "BGS(AMG)"
 SERVE_OPTS = dict(sweeps=2, order="bwd")
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sgs_color_fsi3d_traffic.md")
+
+
+def kernel_source_digest():
+    """sha256 (first 16 hex digits) of the source of the Gauss-Seidel colour
+    kernel and the helpers it inlines."""
+    import hashlib
+    s = open(os.path.join(ROOT, "paper_1605_01522_amd", "csrc", "kernels.hip")).read()
+
+    def seg(a, b):
+        i = s.index(a)
+        return s[i:s.index(b, i)]
+    text = seg("template <int G, int NR, class T>\n__device__ __forceinline__ void row_dot(",
+               "template <int G, int MODE, int NR, class T>") + \
+        seg("template <int G, int B2, int NR, class T>\n__device__ __forceinline__ void sgs_node(",
+            "// A whole sweep over every colour of a small level")
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    if it is for this kernel and the kernel's source has not changed since."""
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_PROFILE).read().splitlines()
+                      if line.startswith(("kernel: ", "source_sha256_16: ", "traffic_bytes_per_launch: ")))
+        if fields.get("kernel") != kernel or fields.get("source_sha256_16") != kernel_source_digest():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
     """The CPU oracle on a bounded sample of the same workload: its full setup
     plus the first `budget_its` GMRES iterations, scaled to the GPU's
@@ -156,9 +188,12 @@ def run_workload(name, steps, warmup, seed, precision_form):
     roofline = None
     if dom:
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        kname = nfield.kernel_name(dom)
+        traffic = measured_traffic(kname) if name == "fsi3d" else None
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                        frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
-                        kernel=nfield.kernel_name(dom),
+                        frac=round(achieved / PEAK_HBM_GBS, 4),
+                        traffic=None if traffic is None else round(traffic),
+                        kernel=kname,
                         launches=dom["launches"], avg_us=round(1e3 * dom["ms"] / dom["launches"], 2),
                         bytes_per_launch=round(dom["bytes"] / dom["launches"]))
     footprint_mb = round(solver.footprint_bytes() / 2**20, 1)

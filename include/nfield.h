@@ -21,8 +21,12 @@
  *                           approximate Schur complement;
  *   "AMG(BGS)", "AMG(SIMPLE)"  monolithic AMG (Sec. 4.3): block-diagonal
  *                           transfers, coarse blocks R_i A_ij P_j, BGS or
- *                           SIMPLE level smoothers;
- *   "LU"                    dense direct solve (small blocks only).
+ *                           SIMPLE level smoothers (SIMPLE: the last field is
+ *                           the Schur field and is not coarsened, P = I; its
+ *                           S~ on every level is inverted densely up to
+ *                           schur_direct_max, else smoothed by Chebyshev);
+ *   "LU"                    dense direct solve (Gauss-Jordan inverse with
+ *                           partial pivoting, up to 12000 unknowns).
  * Optional per-method parameters: "BGS[sweeps=2,order=bwd](AMG)" (sweeps and
  * order of one BGS / SIMPLE node), "AMG[degree=1]" (Chebyshev smoother degree
  * of one hierarchy; degree 1 is damped Jacobi), "AMG[smoother=sgs,omega=0.69,
@@ -96,7 +100,7 @@ typedef struct {
   double cheb_boost;       /* 1.1 */
   int32_t simplec_mode;    /* SIMPLE diagonal: 0 sum_j|a_ij|, 1 |sum_j a_ij|, 2 a_ii; 0 */
   const int32_t *split;    /* field -> SIMPLE group (0 predictor, 1 Schur); NULL: last field */
-  int32_t schur_direct_max;/* Schur complements up to this size are solved by dense LU; 5000 */
+  int32_t schur_direct_max;/* Schur complements up to this size are inverted densely; 5000 */
   int32_t hier_fp32;       /* 1: store and run the AMG hierarchies in FP32 (precision form) */
   uint64_t seed;           /* MIS-2 keys and power-iteration start vectors */
 } nfield_opts;
@@ -164,13 +168,18 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
  * returns the number of kernel variants and fills up to max entries: key =
  * ((16*lanes_per_row + rows_per_node_group)*10 + kind)*10 + (1 if FP32),
  * kind 0-5 = SpMV epilogue (store, residual, add, subtract, Chebyshev step,
- * diagonal scaling), 6 = Gauss-Seidel colour sweep (timed per sweep, counted
- * per colour launch); launches, total milliseconds, total algorithmic bytes
- * (matrix once, operand once, epilogue streams). */
+ * diagonal scaling); Gauss-Seidel sweeps (timed per sweep): 6 = a launch per
+ * colour, one lane group per node; 7 = every colour in one single-workgroup
+ * launch (tiny levels with many colours); 8 = a launch per colour, one
+ * workgroup per node (long rows); launches, total milliseconds, total
+ * algorithmic bytes (matrix once, operand once, epilogue streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);
 
-size_t nfield_footprint_bytes(const nfield_ctx *ctx);   /* device bytes the context holds */
+/* Device bytes the context holds: its buffers plus the blocks it keeps
+ * cached for reuse by later calls (temporaries of a rebuild return there
+ * instead of being freed). */
+size_t nfield_footprint_bytes(const nfield_ctx *ctx);
 int64_t nfield_size(const nfield_ctx *ctx);             /* n = sum of field sizes */
 void nfield_destroy(nfield_ctx *ctx);
 const char *nfield_strerror(nfield_status s);

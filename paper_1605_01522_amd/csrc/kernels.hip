@@ -1646,8 +1646,8 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
   if (h_flags[0] > 0)
-    hipLaunchKernelGGL((k_spgemm_fill<512, 4>), dim3(cdiv(h_flags[0], 4)), dim3(256), 0, s, small.p, h_flags[0], A.ptr.p,
-                       A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+    hipLaunchKernelGGL((k_spgemm_fill<512, 1>), dim3(h_flags[0]), dim3(64), 0, s, small.p, h_flags[0], A.ptr.p, A.col.p,
+                       A.val.p, B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
   if (h_flags[1] > 0)
     hipLaunchKernelGGL((k_spgemm_fill<4096, 1>), dim3(h_flags[1]), dim3(64), 0, s, big.p, h_flags[1], A.ptr.p, A.col.p,
                        A.val.p, B.ptr.p, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
