@@ -103,6 +103,10 @@ typedef struct {
   int32_t schur_direct_max;/* Schur complements up to this size are inverted densely; 5000 */
   int32_t hier_fp32;       /* 1: store and run the AMG hierarchies in FP32 (precision form) */
   uint64_t seed;           /* MIS-2 keys and power-iteration start vectors */
+  int32_t graphs;          /* 1: the preconditioner's kernels are captured once (per column
+                              count, after every rebuild) into a HIP graph and replayed;
+                              0 (default): launched one by one.  Same bits either way; on
+                              gfx950 / ROCm 7.2 replay did not shorten the solve. */
 } nfield_opts;
 
 typedef struct {

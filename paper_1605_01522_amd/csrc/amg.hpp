@@ -16,6 +16,7 @@ struct Opts {
   int schur_direct_max = 5000;
   int hier_fp32 = 0;
   uint64_t seed = 0;
+  int graphs = 0;
 };
 
 // N x N grid of device blocks over fields [0, N); a null block is zero.

@@ -590,7 +590,21 @@ struct nfield_ctx {
   nf::DBuf<int> imask;
   double* pinned = nullptr;
   int* pinned_i = nullptr;
+  // preconditioner replay: graph per column count, captured on a private
+  // stream into fixed input / output buffers
+  hipGraphExec_t gexec[nf::NRMAX + 1] = {};
+  hipStream_t cap_stream = nullptr;
+  nf::DBuf<double> g_in, g_out;
+  void drop_graphs() {
+    for (auto& g : gexec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
   ~nfield_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (pinned) (void)hipHostFree(pinned);
     if (pinned_i) (void)hipHostFree(pinned_i);
   }
@@ -876,7 +890,7 @@ static void ensure_workspace(nfield_ctx& C, int m, int flexible) {
   if (!C.pinned_i) NF_HIP(hipHostMalloc((void**)&C.pinned_i, 64 * sizeof(int), hipHostMallocDefault));
 }
 
-static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
+static void precond_direct(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
   if (C.root64) {
     C.root64->apply(r, ldr, z, ldz, nrhs, s);
   } else {
@@ -885,6 +899,39 @@ static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int6
     C.root32->apply(C.r32.p, n, C.z32.p, n, nrhs, s);
     castm<float, double>(C.z32.p, n, z, ldz, n, nrhs, s);
   }
+}
+
+// z = M^-1 r.  With graphs on (and launch timing off) the preconditioner's
+// kernels are recorded once per column count on a private stream, reading
+// g_in and writing g_out, and replayed on s between two copies; the kernels
+// and their order are those of precond_direct.
+static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
+  if (!C.o.graphs || prof_recording()) return precond_direct(C, r, ldr, z, ldz, nrhs, s);
+  const int64_t n = C.Aglob.nr;
+  if (!C.g_in.p) {
+    C.g_in.alloc((size_t)n * NRMAX);
+    C.g_out.alloc((size_t)n * NRMAX);
+  }
+  if (!C.gexec[nrhs]) {
+    if (!C.cap_stream) NF_HIP(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking));
+    NF_HIP(hipStreamSynchronize(s));   // buffers the capture may allocate are then idle
+    hipGraph_t g = nullptr;
+    NF_HIP(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+      precond_direct(C, C.g_in.p, n, C.g_out.p, n, nrhs, C.cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(C.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    NF_HIP(hipStreamEndCapture(C.cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&C.gexec[nrhs], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NF_HIP(e);
+  }
+  copym<double>(r, ldr, C.g_in.p, n, n, nrhs, s);
+  NF_HIP(hipGraphLaunch(C.gexec[nrhs], s));
+  copym<double>(C.g_out.p, n, z, ldz, n, nrhs, s);
 }
 
 // ||b_k - A x_k|| for nrhs columns, read back to host res[k]
@@ -1124,6 +1171,7 @@ static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>
 
 // (re)build the preconditioner tree from the device-resident blocks
 static void build_tree(nfield_ctx& C, hipStream_t s) {
+  C.drop_graphs();
   C.root64.reset();
   C.root32.reset();
   C.hiers.clear();
@@ -1173,6 +1221,7 @@ void nfield_default_opts(nfield_opts* o) {
   o->schur_direct_max = 5000;
   o->hier_fp32 = 0;
   o->seed = 0;
+  o->graphs = 0;
 }
 
 void nfield_default_solve_opts(nfield_solve_opts* so) {
@@ -1228,6 +1277,7 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
     C->o.schur_direct_max = o.schur_direct_max;
     C->o.hier_fp32 = o.hier_fp32;
     C->o.seed = o.seed;
+    C->o.graphs = o.graphs;
     NF_CHECK(o.sweeps >= 1 && o.order >= 0 && o.order <= 2 && o.cheb_degree >= 1 && o.max_levels >= 1 &&
                  o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2,
              NFIELD_EINVAL, "options out of range");

@@ -33,7 +33,8 @@ class nfield_opts(C.Structure):
                 ("max_levels", C.c_int32), ("cheb_degree", C.c_int32), ("power_its", C.c_int32),
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double),
                 ("simplec_mode", C.c_int32), ("split", C.c_void_p),
-                ("schur_direct_max", C.c_int32), ("hier_fp32", C.c_int32), ("seed", C.c_uint64)]
+                ("schur_direct_max", C.c_int32), ("hier_fp32", C.c_int32), ("seed", C.c_uint64),
+                ("graphs", C.c_int32)]
 
 
 class nfield_solve_opts(C.Structure):
