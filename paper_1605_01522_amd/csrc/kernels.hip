@@ -685,12 +685,10 @@ static void scan_rec(const int* in, int* out, int64_t n, hipStream_t s) {
   DBuf<int> bs(nb + 1);
   hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(256), 0, s, in, out, n, bs.p);
   if (nb > 1) {
+    // (temporaries go back to the context's block cache, reused in stream order)
     DBuf<int> bss(nb + 1);
     scan_rec(bs.p, bss.p, nb, s);
     hipLaunchKernelGGL(k_scan_add, dim3(cdiv(n, 256)), dim3(256), 0, s, out, n, bss.p);
-    NF_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
-  } else {
-    NF_HIP(hipStreamSynchronize(s));
   }
 }
 
@@ -1409,11 +1407,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_spgemm_count(const int* __restri
 // (LDS tables of 512 and 4096 slots, dense accumulator beyond)
 __global__ void k_spgemm_bin_ub(int nr, const int* __restrict__ Ap, const int* __restrict__ Ac, const int* __restrict__ Bp,
                                 int small_max, int big_max, int* small, int* nsmall, int* big, int* nbig, int* huge, int* nhuge,
-                                int* cnt) {
+                                int* cnt, int* ubrow, unsigned long long* ubtotal) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= nr) return;
   int64_t ub = 0;
   for (int p = Ap[r]; p < Ap[r + 1]; ++p) ub += Bp[Ac[p] + 1] - Bp[Ac[p]];
+  ubrow[r] = (int)std::min<int64_t>(ub, INT_MAX);
+  atomicAdd(ubtotal, (unsigned long long)ub);
   if (ub == 0) cnt[r] = 0;
   else if (ub <= small_max) small[atomicAdd(nsmall, 1)] = r;
   else if (ub <= big_max) big[atomicAdd(nbig, 1)] = r;
@@ -1575,6 +1575,164 @@ __global__ __launch_bounds__(64 * WAVES) void k_spgemm_fill(const int* __restric
   }
 }
 
+// Single-pass product rows: the LDS hash set of the row is built, counted,
+// sorted and accumulated as in k_spgemm_fill, and the row is written to a
+// scratch at the row's upper-bound offset (its count in cnt); rows the table
+// cannot hold are listed in ovf for the dense accumulator.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_spgemm_fill_ub(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
+                                                       const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                       const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                       const double* __restrict__ Bv, const int* __restrict__ toff,
+                                                       const int* __restrict__ ubrow, int* __restrict__ tcol,
+                                                       double* __restrict__ tval, int* __restrict__ cnt, int* ovf, int* ovf_n) {
+  __shared__ int keys[CAP];
+  __shared__ double acc[CAP];
+  if ((int)blockIdx.x >= nrows) return;
+  const int row = rows[blockIdx.x], lane = threadIdx.x;
+  const int ub = ubrow[row];
+  int ts = 1, logts = 0;
+  while (ts < 2 * ub && ts < CAP) { ts <<= 1; ++logts; }
+  for (int i = lane; i < ts; i += 64) keys[i] = EMPTY_KEY;
+  __syncthreads();
+  int mine = 0, full = 0;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+      const int r = hash_insert(keys, ts, logts, Bc[q]);
+      if (r > 0) ++mine;
+      if (r < 0) full = 1;
+    }
+  }
+  const int c = wave_sum_int(mine);
+  if (wave_sum_int(full)) {
+    if (lane == 0) ovf[atomicAdd(ovf_n, 1)] = row;
+    return;
+  }
+  // gather the c keys to the front (through the accumulator's storage), pad
+  // to a power of two and sort only that
+  __shared__ int npos;
+  int* tmp = (int*)acc;
+  if (lane == 0) npos = 0;
+  __syncthreads();
+  for (int i = lane; i < ts; i += 64) {
+    const int k = keys[i];
+    if (k != EMPTY_KEY) tmp[atomicAdd(&npos, 1)] = k;
+  }
+  __syncthreads();
+  int ts2 = 1;
+  while (ts2 < c) ts2 <<= 1;
+  for (int i = lane; i < ts2; i += 64) keys[i] = i < c ? tmp[i] : EMPTY_KEY;
+  __syncthreads();
+  for (int kk = 2; kk <= ts2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < ts2; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = keys[i], y = keys[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = lane; i < c; i += 64) acc[i] = 0.0;
+  __syncthreads();
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    const double a = Av[p];
+    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+      const int key = Bc[q];
+      int lo = 0, hi = c;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      acc[lo] += a * Bv[q];
+    }
+    __syncthreads();
+  }
+  const int o = toff[row];
+  for (int i = lane; i < c; i += 64) {
+    tcol[o + i] = keys[i];
+    tval[o + i] = acc[i];
+  }
+  if (lane == 0) cnt[row] = c;
+}
+
+// the dense-accumulator row of k_spa_fill written to the scratch at the
+// row's upper-bound offset, its count in cnt (ts >= the row's distinct count)
+__global__ __launch_bounds__(256) void k_spa_fill_ub(const int* __restrict__ rows, const int* __restrict__ Ap,
+                                                     const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                     const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                     const double* __restrict__ Bv, const int* __restrict__ toff,
+                                                     int* __restrict__ tcol, double* __restrict__ tval, int* __restrict__ cnt,
+                                                     int ncols, int* flags, double* accs, int* kscr, int ts) {
+  __shared__ int pos;
+  const int row = rows[blockIdx.x], t = threadIdx.x;
+  int* f = flags + (int64_t)blockIdx.x * ncols;
+  double* acc = accs + (int64_t)blockIdx.x * ncols;
+  int* ks = kscr + (int64_t)blockIdx.x * ts;
+  if (t == 0) pos = 0;
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    const double a = Av[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256) {
+      const int j = Bc[q];
+      acc[j] += a * Bv[q];
+      f[j] = 1;
+    }
+    __syncthreads();
+  }
+  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+    const int k = Ac[p];
+    for (int q = Bp[k] + t; q < Bp[k + 1]; q += 256) {
+      const int j = Bc[q];
+      if (atomicExch(&f[j], 0) == 1) {
+        const int at = atomicAdd(&pos, 1);
+        if (at < ts) ks[at] = j;
+      }
+    }
+  }
+  __syncthreads();
+  const int c = pos < ts ? pos : ts;
+  for (int i = c + t; i < ts; i += 256) ks[i] = EMPTY_KEY;
+  __syncthreads();
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < ts; i += 256) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = ks[i], y = ks[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { ks[i] = y; ks[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  const int o = toff[row];
+  for (int i = t; i < c; i += 256) {
+    const int j = ks[i];
+    tcol[o + i] = j;
+    tval[o + i] = acc[j];
+    acc[j] = 0.0;
+  }
+  if (t == 0) cnt[row] = c;
+}
+
+// C row r = scratch[toff[r], toff[r] + cnt[r]) (one wavefront per row)
+__global__ __launch_bounds__(256) void k_spgemm_compact(int nr, const int* __restrict__ toff, const int* __restrict__ Cp,
+                                                        const int* __restrict__ tcol, const double* __restrict__ tval,
+                                                        int* __restrict__ Ccol, double* __restrict__ Cval) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= nr) return;
+  const int o = toff[r], c0 = Cp[r], n = Cp[r + 1] - c0;
+  for (int i = lane; i < n; i += 64) {
+    Ccol[c0 + i] = tcol[o + i];
+    Cval[c0 + i] = tval[o + i];
+  }
+}
+
 // split rows by their distinct count into the two LDS table sizes and the
 // dense-accumulator list
 __global__ void k_bin_rows(int nr, const int* __restrict__ Cp, int small_max, int big_max, int* small, int* nsmall, int* big,
@@ -1598,25 +1756,89 @@ static int spa_slots(int ncols, int nrows, int extra_per_slot) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(nrows, ((int64_t)1 << 29) / std::max<int64_t>(per, 1)));
 }
 
+// scratch of the single-pass product (upper-bound slots) above which the
+// two-pass product (count, then fill in place) is used
+constexpr int64_t SPG_ONEPASS_MAX_SLOTS = (int64_t)1 << 27;
+
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   NF_CHECK(A.nc == B.nr, NFIELD_EINVAL, "spgemm: inner dimensions differ");
   C.nr = A.nr;
   C.nc = B.nc;
   C.ptr.alloc(A.nr + 1);
   const int nr1 = A.nr > 0 ? A.nr : 1;
-  DBuf<int> cnt(A.nr + 1), flags(8);
+  DBuf<int> cnt(A.nr + 1), flags(8), ubrow(A.nr + 1);
+  DBuf<unsigned long long> ubtot(1);
   DBuf<int> small(nr1), big(nr1), huge(nr1);
   fill<int>(flags.p, 0, 8, s);
   fill<int>(cnt.p, 0, A.nr + 1, s);
+  fill<unsigned long long>(ubtot.p, 0ull, 1, s);
   int h_flags[8];
   if (A.nr > 0 && A.nnz > 0 && B.nnz > 0) {
     // rows with an upper bound above 256 go to the 4096-slot table; rows it
     // cannot hold (more than 4096 distinct columns) to the dense accumulator
     hipLaunchKernelGGL(k_spgemm_bin_ub, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr.p, A.col.p, B.ptr.p, 256,
-                       INT_MAX, small.p, flags.p, big.p, flags.p + 1, huge.p, flags.p + 2, cnt.p);
+                       INT_MAX, small.p, flags.p, big.p, flags.p + 1, huge.p, flags.p + 2, cnt.p, ubrow.p, ubtot.p);
+    unsigned long long h_ub = 0;
     NF_HIP(hipMemcpyAsync(h_flags, flags.p, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipMemcpyAsync(&h_ub, ubtot.p, sizeof(h_ub), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
     const int ns = h_flags[0], nb = h_flags[1];
+    if (h_ub <= (unsigned long long)SPG_ONEPASS_MAX_SLOTS) {
+      // single pass: rows into upper-bound slots of a scratch, then compacted
+      DBuf<int> toff(A.nr + 1), tcol(h_ub > 0 ? h_ub : 1);
+      DBuf<double> tval(h_ub > 0 ? h_ub : 1);
+      exclusive_scan(ubrow.p, toff.p, A.nr, s);
+      fill<int>(flags.p + 3, 0, 1, s);
+      // rows with an upper bound above 256 try a 1024-slot table (small LDS,
+      // many workgroups per CU); rows with more distinct columns retry with
+      // 4096 slots, and beyond that the dense accumulator
+      DBuf<int> big2(nr1);
+      fill<int>(flags.p + 4, 0, 1, s);
+      if (ns > 0)
+        hipLaunchKernelGGL(k_spgemm_fill_ub<512>, dim3(ns), dim3(64), 0, s, small.p, ns, A.ptr.p, A.col.p, A.val.p, B.ptr.p,
+                           B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p, flags.p + 3);
+      if (nb > 0)
+        hipLaunchKernelGGL(k_spgemm_fill_ub<1024>, dim3(nb), dim3(64), 0, s, big.p, nb, A.ptr.p, A.col.p, A.val.p, B.ptr.p,
+                           B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, big2.p, flags.p + 4);
+      int nb2 = 0;
+      if (nb > 0) {
+        NF_HIP(hipMemcpyAsync(&nb2, flags.p + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+        NF_HIP(hipStreamSynchronize(s));
+      }
+      if (nb2 > 0)
+        hipLaunchKernelGGL(k_spgemm_fill_ub<4096>, dim3(nb2), dim3(64), 0, s, big2.p, nb2, A.ptr.p, A.col.p, A.val.p,
+                           B.ptr.p, B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p, flags.p + 3);
+      int nh = 0;
+      NF_HIP(hipMemcpyAsync(&nh, flags.p + 3, sizeof(int), hipMemcpyDeviceToHost, s));
+      NF_HIP(hipStreamSynchronize(s));
+      if (nh > 0) {
+        // longest overflow row bounds its distinct count by min(upper bound, columns)
+        std::vector<int> hrows(nh), hub(A.nr);
+        NF_HIP(hipMemcpyAsync(hrows.data(), huge.p, sizeof(int) * nh, hipMemcpyDeviceToHost, s));
+        NF_HIP(hipMemcpyAsync(hub.data(), ubrow.p, sizeof(int) * A.nr, hipMemcpyDeviceToHost, s));
+        NF_HIP(hipStreamSynchronize(s));
+        int mx = 1;
+        for (int r : hrows) mx = std::max(mx, std::min(hub[r], B.nc));
+        int ts = 1;
+        while (ts < mx) ts <<= 1;
+        const int slots = spa_slots(B.nc, nh, ts);
+        DBuf<int> f((size_t)slots * B.nc), ks((size_t)slots * ts);
+        DBuf<double> acc((size_t)slots * B.nc);
+        fill<int>(f.p, 0, (int64_t)slots * B.nc, s);
+        fill<double>(acc.p, 0.0, (int64_t)slots * B.nc, s);
+        for (int r0 = 0; r0 < nh; r0 += slots)
+          hipLaunchKernelGGL(k_spa_fill_ub, dim3(std::min(slots, nh - r0)), dim3(256), 0, s, huge.p + r0, A.ptr.p, A.col.p,
+                             A.val.p, B.ptr.p, B.col.p, B.val.p, toff.p, tcol.p, tval.p, cnt.p, B.nc, f.p, acc.p, ks.p, ts);
+      }
+      C.nnz = exclusive_scan(cnt.p, C.ptr.p, A.nr, s);
+      C.col.alloc(C.nnz > 0 ? C.nnz : 1);
+      C.val.alloc(C.nnz > 0 ? C.nnz : 1);
+      if (C.nnz > 0)
+        hipLaunchKernelGGL(k_spgemm_compact, dim3(cdiv(A.nr, 4)), dim3(256), 0, s, A.nr, toff.p, C.ptr.p, tcol.p, tval.p,
+                           C.col.p, C.val.p);
+      NF_HIP(hipGetLastError());
+      return;
+    }
     if (ns > 0)
       hipLaunchKernelGGL((k_spgemm_count<512, 4>), dim3(cdiv(ns, 4)), dim3(256), 0, s, small.p, ns, A.ptr.p, A.col.p, B.ptr.p,
                          B.col.p, cnt.p, huge.p, flags.p + 2);

@@ -761,7 +761,6 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
         ch->n = n2;
         M.schur = std::move(ch);
       }
-      NF_HIP(hipStreamSynchronize(s));   // dt is released on return
       M.ts.alloc(n2);
       int mp = 0;
       for (int i = 0; i < g; ++i) mp = std::max(mp, L.A.size[i]);
@@ -837,7 +836,6 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->dtinv.alloc(n1 > 0 ? n1 : 1);
     if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(S->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
     else cast_copy<double, float>(dt.p, (float*)S->dtinv.p, n1, s);
-    NF_HIP(hipStreamSynchronize(s));   // dt is released on return
     S->pred = build<T>(C, sp.kids[0], A, F, f0, g, s);
     auto Bm = std::make_unique<BlockMat>();
     Bm->N = 1;
