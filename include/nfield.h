@@ -175,8 +175,10 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
  * diagonal scaling); Gauss-Seidel sweeps (timed per sweep): 6 = a launch per
  * colour, one lane group per node; 7 = every colour in one single-workgroup
  * launch (tiny levels with many colours); 8 = a launch per colour, one
- * workgroup per node (long rows); launches, total milliseconds, total
- * algorithmic bytes (matrix once, operand once, epilogue streams). */
+ * workgroup per node (long rows); 9 = the whole symmetric sweep of a small
+ * many-colour level as one dense affine map x <- S x + Q b; launches, total
+ * milliseconds, total algorithmic bytes (matrix once, operand once, epilogue
+ * streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);
 

@@ -1190,6 +1190,100 @@ void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int
   }
 }
 
+// Dense form of one symmetric Gauss-Seidel sweep on a small level: the
+// sweep is affine, x_new = S x + Q b, so it is run once on X = [I | 0] with
+// right-hand sides [0 | I] (2n columns), giving X = [S | Q].  One launch per
+// colour (forward then backward); a thread owns one column for all b rows of
+// one node and writes them after reading, as the colour kernels do.
+__global__ __launch_bounds__(256) void k_dense_sgs_colour(double* __restrict__ X, int n, const int* __restrict__ nodes, int b,
+                                                          const int* __restrict__ ptr, const int* __restrict__ col,
+                                                          const double* __restrict__ val, const double* __restrict__ dinv,
+                                                          double omega) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int64_t ld = 2 * (int64_t)n;
+  if (j >= 2 * n) return;
+  const int u = nodes[blockIdx.y];
+  double sum[MAXB];
+  for (int q = 0; q < b; ++q) {
+    const int r = u * b + q;
+    double acc = 0.0;
+    for (int p = ptr[r]; p < ptr[r + 1]; ++p) acc += val[p] * X[(int64_t)col[p] * ld + j];
+    sum[q] = acc;
+  }
+  for (int q = 0; q < b; ++q) {
+    const int r = u * b + q;
+    const double rhs = j == n + r ? 1.0 : 0.0;
+    X[(int64_t)r * ld + j] += omega * dinv[r] * (rhs - sum[q]);
+  }
+}
+__global__ void k_identity_left(double* X, int n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= 2 * (int64_t)n * n) return;
+  const int64_t r = e / (2 * n), c = e % (2 * n);
+  X[e] = c == r ? 1.0 : 0.0;
+}
+void dense_sgs_build(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, const double* dinv, double omega,
+                     double* X, hipStream_t s) {
+  const int n = A.nr, nc = (int)off.size() - 1;
+  hipLaunchKernelGGL(k_identity_left, dim3(cdiv(2 * (int64_t)n * n, 256)), dim3(256), 0, s, X, n);
+  for (int i = 0; i < 2 * nc; ++i) {
+    const int c = i < nc ? i : 2 * nc - 1 - i;
+    const int m = off[c + 1] - off[c];
+    if (m > 0)
+      hipLaunchKernelGGL(k_dense_sgs_colour, dim3(cdiv(2 * n, 256), m), dim3(256), 0, s, X, n, nodes + off[c], b, A.ptr.p,
+                         A.col.p, A.val.p, dinv, omega);
+  }
+  NF_HIP(hipGetLastError());
+}
+
+// y = S x + Q b (or Q b alone) for the dense sweep X = [S | Q] (n x 2n,
+// row-major, stored in T): one wavefront per row, columns lane-strided
+template <int NR, class T>
+__global__ __launch_bounds__(256) void k_dense_sweep_apply(const T* __restrict__ X, int n, const T* __restrict__ x, int64_t ldx,
+                                                           const T* __restrict__ rb, int64_t ldb, T* __restrict__ y, int64_t ldy,
+                                                           int nrhs, int with_x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  const T* m = X + (int64_t)row * 2 * n;
+  if (with_x)
+    for (int j = lane; j < n; j += 64) {
+      const double mj = m[j];
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nrhs) acc[k] += mj * (double)x[k * ldx + j];
+    }
+  for (int j = lane; j < n; j += 64) {
+    const double mj = m[n + j];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k < nrhs) acc[k] += mj * (double)rb[k * ldb + j];
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= nrhs) break;
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) y[k * ldy + row] = (T)v;
+  }
+}
+template <class T>
+void dense_sweep_apply(const T* X, int n, const T* x, int64_t ldx, const T* rb, int64_t ldb, T* y, int64_t ldy, int nrhs,
+                       bool with_x, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_dense_sweep_apply<1, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, x, ldx, rb, ldb, y, ldy, nrhs,
+                       with_x ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_dense_sweep_apply<NRMAX, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, x, ldx, rb, ldb, y, ldy, nrhs,
+                       with_x ? 1 : 0);
+}
+template void dense_sweep_apply<double>(const double*, int, const double*, int64_t, const double*, int64_t, double*, int64_t,
+                                        int, bool, hipStream_t);
+template void dense_sweep_apply<float>(const float*, int, const float*, int64_t, const float*, int64_t, float*, int64_t, int,
+                                       bool, hipStream_t);
+
 template void sgs_sweep<double>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const double*,
                                 double, const double*, int64_t, double*, int64_t, int, hipStream_t);
 template void sgs_sweep<float>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const float*, float,

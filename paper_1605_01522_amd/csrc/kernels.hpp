@@ -119,6 +119,14 @@ constexpr int SGS_SWEEP1_MAX_NODES = 65536;
 constexpr int SGS_SWEEP1_MIN_COLORS = 8;
 constexpr int64_t SGS_NODE_MIN_ROW = 128;
 int sgs_kind(const DCsr& A, int b, int nnodes_total, int ncolors);
+// levels up to SGS_DENSE_MAX dofs with at least SGS_DENSE_MIN_COLORS colours
+// apply their symmetric sweep as a dense affine map X = [S | Q]
+constexpr int SGS_DENSE_MAX = 2048;
+constexpr int SGS_DENSE_MIN_COLORS = 16;
+void dense_sgs_build(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, const double* dinv, double omega,
+                     double* X, hipStream_t s);
+template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t ldx, const T* rb, int64_t ldb, T* y,
+                                          int64_t ldy, int nrhs, bool with_x, hipStream_t s);
 // one sweep over all colours (forward: ascending colour order), nodes grouped
 // by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
 // device as off_dev)

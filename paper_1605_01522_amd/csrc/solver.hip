@@ -235,6 +235,43 @@ struct SgsD : FieldSmootherD<T> {
   }
 };
 
+// Symmetric Gauss-Seidel of a small many-colour level as its dense affine
+// map: the colouring, ordering and damping of SgsD, with the whole symmetric
+// sweep x <- S x + Q b precomputed (X = [S | Q], n x 2n) and applied as one
+// GEMV per sweep instead of one launch per colour and direction.
+template <class T>
+struct DenseSgsD : FieldSmootherD<T> {
+  int n = 0, steps = 1, b2 = 1;
+  DBuf<T> X;
+  MBuf<T> y;
+  void setup(const SgsD<T>& g, const DCsr* A, int b, const double* dinv64, double omega, int st, hipStream_t s) {
+    n = A->nr;
+    steps = st;
+    b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+    const size_t m = 2 * (size_t)n * n;
+    if (sizeof(T) == sizeof(double)) {
+      X.alloc(m);
+      dense_sgs_build(*A, b, g.nodes.p, g.off, dinv64, omega, (double*)X.p, s);
+    } else {
+      DBuf<double> X64(m);
+      dense_sgs_build(*A, b, g.nodes.p, g.off, dinv64, omega, X64.p, s);
+      X.alloc(m);
+      cast_copy<double, float>(X64.p, (float*)X.p, (int64_t)m, s);
+    }
+    y.alloc(n);
+  }
+  void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
+    for (int st = 0; st < steps; ++st) {
+      const bool with_x = !(zero_guess && st == 0);
+      const int slot = prof_begin(s);
+      dense_sweep_apply<T>(X.p, n, x, ldx, rhs, ldr, y.p(), y.ld, nrhs, with_x, s);
+      prof_end(slot, s, ((64 * 16 + b2) * 10 + 9) * 10 + (sizeof(T) == 4 ? 1 : 0),
+               (double)sizeof(T) * n * (with_x ? 2.0 * n : (double)n) + (double)nrhs * sizeof(T) * n * (with_x ? 3 : 2));
+      copym<T>(y.p(), y.ld, x, ldx, n, nrhs, s);
+    }
+  }
+};
+
 // One BGS sweep over fields [f0, f1) of a block matrix with per-field inner
 // solves: dd_i = S_i(res_i - sum_{j done} A_ij dd_j).
 template <class T, class Inner>
@@ -710,7 +747,14 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
       if (sgs) {
         auto g = std::make_unique<SgsD<T>>();
         g->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s);
-        M.cheb.push_back(std::move(g));
+        const int ncol = (int)g->off.size() - 1;
+        if (L.A.size[i] <= SGS_DENSE_MAX && ncol >= SGS_DENSE_MIN_COLORS) {
+          auto d = std::make_unique<DenseSgsD<T>>();
+          d->setup(*g, L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, s);
+          M.cheb.push_back(std::move(d));
+        } else {
+          M.cheb.push_back(std::move(g));
+        }
       } else {
         auto ch = std::make_unique<ChebD<T>>();
         ch->setup(L.A.at(i, i), L.dinv[i]->p, L.lambda[i], lo, s);

@@ -262,12 +262,13 @@ def nfield_prof_enable(on):
 
 
 SPMV_MODES = {0: "store", 1: "resid", 2: "add", 3: "sub", 4: "cheb", 5: "dscale", 6: "sgs",
-              7: "sgs_sweep1", 8: "sgs_node"}
+              7: "sgs_sweep1", 8: "sgs_node", 9: "sgs_dense"}
 # kernel names as the profiler prints them (single right-hand side)
 KERNEL_NAMES = {m: f"k_spmv<{{lanes}}, {m}, {{t}}>" for m in range(6)}
 KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[7] = "k_sgs_sweep1<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[8] = "k_sgs_node<{lanes}, {rows}, 1, {t}>"
+KERNEL_NAMES[9] = "k_dense_sweep_apply<1, {t}>"
 
 
 def kernel_name(p):
