@@ -930,6 +930,49 @@ __global__ void k_max_int(const int* x, int n, int* out) {
   if (i < n) atomicMax(out, x[i] + 1);
 }
 
+// The same rounds inside one workgroup with a barrier between rounds, for
+// graphs small enough that a launch per round would cost more than the scan:
+// a round visits every still uncoloured node; it stops when a round leaves
+// none (left[0] = 0) or after max_rounds (left[0] > 0: continue on the host).
+__global__ __launch_bounds__(1024) void k_color_rounds_1wg(int n, const int* __restrict__ gp, const int* __restrict__ ga,
+                                                           int* color, int max_rounds, int* left, int* err) {
+  __shared__ int nleft;
+  for (int round = 0; round < max_rounds; ++round) {
+    if (threadIdx.x == 0) nleft = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int u = threadIdx.x; u < n; u += 1024) {
+      if (__hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= 0) continue;
+      uint64_t m[4] = {0, 0, 0, 0};
+      bool ready = true;
+      for (int p = gp[u]; p < gp[u + 1]; ++p) {
+        const int v = ga[p];
+        if (v >= u) continue;
+        const int c = __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c < 0) { ready = false; break; }
+        if (c < 256) m[c >> 6] |= 1ull << (c & 63);
+      }
+      if (!ready) { ++mine; continue; }
+      int c = -1;
+      for (int w = 0; w < 4 && c < 0; ++w)
+        if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+      if (c < 0) { atomicOr(err, 1); c = 0; }
+      __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (mine) atomicAdd(&nleft, mine);
+    __syncthreads();
+    const int l = nleft;
+    __syncthreads();
+    if (l == 0) {
+      if (threadIdx.x == 0) *left = 0;
+      return;
+    }
+  }
+  if (threadIdx.x == 0) *left = 1;
+}
+
+constexpr int COLOR_1WG_MAX_NODES = 4096;   // larger graphs: a launch per round
+
 int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* color, hipStream_t s) {
   if (n == 0) return 0;
   constexpr int K = 16;                 // rounds per host check
@@ -937,17 +980,33 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
   const int g = cdiv(n, 256);
   fill<int>(color, -1, n, s);
   int rounds = 0;
-  while (true) {
+  if (n <= COLOR_1WG_MAX_NODES) {
+    // single-workgroup rounds, 256 per launch, until a launch reports none left
     fill<int>(cnt.p, 0, K + 2, s);
-    for (int r = 0; r < K; ++r)
-      hipLaunchKernelGGL(k_color_round, dim3(g), dim3(256), 0, s, n, gp, ga, color, cnt.p + r, cnt.p + K);
-    rounds += K;
-    int h[K + 2];
-    NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
-    NF_HIP(hipStreamSynchronize(s));
-    NF_CHECK(h[K] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
-    if (h[K - 1] == 0) break;
-    NF_CHECK(rounds <= n + K, NFIELD_EINVAL, "colouring did not terminate");
+    while (true) {
+      hipLaunchKernelGGL(k_color_rounds_1wg, dim3(1), dim3(1024), 0, s, n, gp, ga, color, 256, cnt.p, cnt.p + K);
+      rounds += 256;
+      int h[2];
+      NF_HIP(hipMemcpyAsync(&h[0], cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      NF_HIP(hipMemcpyAsync(&h[1], cnt.p + K, sizeof(int), hipMemcpyDeviceToHost, s));
+      NF_HIP(hipStreamSynchronize(s));
+      NF_CHECK(h[1] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+      if (h[0] == 0) break;
+      NF_CHECK(rounds <= n + 256, NFIELD_EINVAL, "colouring did not terminate");
+    }
+  } else {
+    while (true) {
+      fill<int>(cnt.p, 0, K + 2, s);
+      for (int r = 0; r < K; ++r)
+        hipLaunchKernelGGL(k_color_round, dim3(g), dim3(256), 0, s, n, gp, ga, color, cnt.p + r, cnt.p + K);
+      rounds += K;
+      int h[K + 2];
+      NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
+      NF_HIP(hipStreamSynchronize(s));
+      NF_CHECK(h[K] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+      if (h[K - 1] == 0) break;
+      NF_CHECK(rounds <= n + K, NFIELD_EINVAL, "colouring did not terminate");
+    }
   }
   fill<int>(cnt.p, 0, 1, s);
   hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p);
