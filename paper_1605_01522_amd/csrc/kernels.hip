@@ -898,122 +898,108 @@ int mis2_aggregate(int n, const int* gp, const int* ga, uint64_t seed, int* agg,
 }
 
 // ================================================== multicolour Gauss-Seidel
-// One round of greedy colouring in node order: an uncoloured node whose
-// smaller-index neighbours are all coloured takes the smallest colour they do
-// not use.  The result equals the sequential greedy colouring in node order
-// (a node's colour depends only on its smaller neighbours' final colours); a
-// node that sees a neighbour coloured earlier in the same round merely
-// finishes a round sooner.
-__global__ void k_color_round(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* color, int* left,
-                              int* err) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= n || __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
-  uint64_t m[4] = {0, 0, 0, 0};
-  for (int p = gp[u]; p < gp[u + 1]; ++p) {
-    const int v = ga[p];
-    if (v >= u) continue;
-    const int c = __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (c < 0) {
-      atomicAdd(left, 1);
-      return;
-    }
-    if (c < 256) m[c >> 6] |= 1ull << (c & 63);
-  }
-  int c = -1;
-  for (int w = 0; w < 4 && c < 0; ++w)
-    if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
-  if (c < 0) { atomicOr(err, 1); c = 0; }
-  __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Greedy colouring in node order: every node takes the smallest colour not
+// used by its smaller-index neighbours.  Each node's colour depends only on
+// its smaller neighbours' final colours, so any schedule that colours a node
+// after all of them gives the sequential result.
 __global__ void k_max_int(const int* x, int n, int* out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) atomicMax(out, x[i] + 1);
 }
 
-// The same rounds inside one workgroup with a barrier between rounds, for
-// graphs small enough that a launch per round would cost more than the scan:
-// a round visits every still uncoloured node; it stops when a round leaves
-// none (left[0] = 0) or after max_rounds (left[0] > 0: continue on the host).
-__global__ __launch_bounds__(1024) void k_color_rounds_1wg(int n, const int* __restrict__ gp, const int* __restrict__ ga,
-                                                           int* color, int max_rounds, int* left, int* err) {
-  __shared__ int nleft;
-  for (int round = 0; round < max_rounds; ++round) {
-    if (threadIdx.x == 0) nleft = 0;
-    __syncthreads();
-    int mine = 0;
-    for (int u = threadIdx.x; u < n; u += 1024) {
-      if (__hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= 0) continue;
-      uint64_t m[4] = {0, 0, 0, 0};
-      bool ready = true;
+// Schedule: wait[w] counts the smaller neighbours of w (in w's own list) not
+// yet coloured; a node is coloured as soon as that count is zero and then
+// releases the nodes waiting on it (the reverse of the smaller-neighbour
+// relation, built first: the node graph need not be symmetric).  One
+// workgroup runs every round of frontiers, kept in two global lists.
+__global__ void k_color_wait(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* wait, int* rcnt, int* front,
+                             int* nfront) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= n) return;
+  int c = 0;
+  for (int p = gp[w]; p < gp[w + 1]; ++p) {
+    const int v = ga[p];
+    if (v < w) {
+      ++c;
+      atomicAdd(&rcnt[v], 1);
+    }
+  }
+  wait[w] = c;
+  if (c == 0) front[atomicAdd(nfront, 1)] = w;
+}
+__global__ void k_color_rev(int n, const int* __restrict__ gp, const int* __restrict__ ga, const int* __restrict__ rptr,
+                            int* rcur, int* radj) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= n) return;
+  for (int p = gp[w]; p < gp[w + 1]; ++p) {
+    const int v = ga[p];
+    if (v < w) radj[rptr[v] + atomicAdd(&rcur[v], 1)] = w;
+  }
+}
+__global__ __launch_bounds__(1024) void k_color_frontier(const int* __restrict__ gp, const int* __restrict__ ga,
+                                                         const int* __restrict__ rptr, const int* __restrict__ radj, int* color,
+                                                         int* wait, int* fa, int* fb, const int* nfront0, int* err,
+                                                         int* done) {
+  __shared__ int nf_cur, nf_next;
+  if (threadIdx.x == 0) { nf_cur = *nfront0; nf_next = 0; }
+  __syncthreads();
+  int* cur = fa;
+  int* nxt = fb;
+  int coloured = 0;
+  while (true) {
+    const int m = nf_cur;
+    if (m == 0) break;
+    for (int i = threadIdx.x; i < m; i += 1024) {
+      const int u = cur[i];
+      uint64_t mask[4] = {0, 0, 0, 0};
       for (int p = gp[u]; p < gp[u + 1]; ++p) {
         const int v = ga[p];
         if (v >= u) continue;
         const int c = __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (c < 0) { ready = false; break; }
-        if (c < 256) m[c >> 6] |= 1ull << (c & 63);
+        if (c >= 0 && c < 256) mask[c >> 6] |= 1ull << (c & 63);
       }
-      if (!ready) { ++mine; continue; }
       int c = -1;
       for (int w = 0; w < 4 && c < 0; ++w)
-        if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+        if (~mask[w]) c = w * 64 + __builtin_ctzll(~mask[w]);
       if (c < 0) { atomicOr(err, 1); c = 0; }
       __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (int p = rptr[u]; p < rptr[u + 1]; ++p) {
+        const int w = radj[p];
+        if (atomicSub(&wait[w], 1) == 1) nxt[atomicAdd(&nf_next, 1)] = w;
+      }
     }
-    if (mine) atomicAdd(&nleft, mine);
+    coloured += m;
     __syncthreads();
-    const int l = nleft;
+    if (threadIdx.x == 0) { nf_cur = nf_next; nf_next = 0; }
     __syncthreads();
-    if (l == 0) {
-      if (threadIdx.x == 0) *left = 0;
-      return;
-    }
+    int* t = cur;
+    cur = nxt;
+    nxt = t;
   }
-  if (threadIdx.x == 0) *left = 1;
+  if (threadIdx.x == 0) *done = coloured;
 }
-
-constexpr int COLOR_1WG_MAX_NODES = 4096;   // larger graphs: a launch per round
 
 int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* color, hipStream_t s) {
   if (n == 0) return 0;
-  constexpr int K = 16;                 // rounds per host check
-  DBuf<int> cnt(K + 2);
   const int g = cdiv(n, 256);
+  DBuf<int> wait(n), fa(n), fb(n), cnt(4), rcnt(n + 1), rptr(n + 1), rcur(n + 1);
   fill<int>(color, -1, n, s);
-  int rounds = 0;
-  if (n <= COLOR_1WG_MAX_NODES) {
-    // single-workgroup rounds, 256 per launch, until a launch reports none left
-    fill<int>(cnt.p, 0, K + 2, s);
-    while (true) {
-      hipLaunchKernelGGL(k_color_rounds_1wg, dim3(1), dim3(1024), 0, s, n, gp, ga, color, 256, cnt.p, cnt.p + K);
-      rounds += 256;
-      int h[2];
-      NF_HIP(hipMemcpyAsync(&h[0], cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
-      NF_HIP(hipMemcpyAsync(&h[1], cnt.p + K, sizeof(int), hipMemcpyDeviceToHost, s));
-      NF_HIP(hipStreamSynchronize(s));
-      NF_CHECK(h[1] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
-      if (h[0] == 0) break;
-      NF_CHECK(rounds <= n + 256, NFIELD_EINVAL, "colouring did not terminate");
-    }
-  } else {
-    while (true) {
-      fill<int>(cnt.p, 0, K + 2, s);
-      for (int r = 0; r < K; ++r)
-        hipLaunchKernelGGL(k_color_round, dim3(g), dim3(256), 0, s, n, gp, ga, color, cnt.p + r, cnt.p + K);
-      rounds += K;
-      int h[K + 2];
-      NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
-      NF_HIP(hipStreamSynchronize(s));
-      NF_CHECK(h[K] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
-      if (h[K - 1] == 0) break;
-      NF_CHECK(rounds <= n + K, NFIELD_EINVAL, "colouring did not terminate");
-    }
-  }
-  fill<int>(cnt.p, 0, 1, s);
-  hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p);
-  int nc = 0;
-  NF_HIP(hipMemcpyAsync(&nc, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  fill<int>(cnt.p, 0, 4, s);
+  fill<int>(rcnt.p, 0, n + 1, s);
+  fill<int>(rcur.p, 0, n + 1, s);
+  hipLaunchKernelGGL(k_color_wait, dim3(g), dim3(256), 0, s, n, gp, ga, wait.p, rcnt.p, fa.p, cnt.p);
+  const int64_t nr = exclusive_scan(rcnt.p, rptr.p, n, s);
+  DBuf<int> radj(nr > 0 ? nr : 1);
+  hipLaunchKernelGGL(k_color_rev, dim3(g), dim3(256), 0, s, n, gp, ga, rptr.p, rcur.p, radj.p);
+  hipLaunchKernelGGL(k_color_frontier, dim3(1), dim3(1024), 0, s, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p, cnt.p,
+                     cnt.p + 1, cnt.p + 2);
+  hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p + 3);
+  int h[4];
+  NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
-  return nc;
+  NF_CHECK(h[1] == 0, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+  NF_CHECK(h[2] == n, NFIELD_EINVAL, "colouring left nodes uncoloured");
+  return h[3];
 }
 
 // One group of B2*G lanes per node (B2 = b rounded up to a power of two,
