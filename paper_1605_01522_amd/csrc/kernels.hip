@@ -288,6 +288,15 @@ int spmv_group(int nr, int64_t nnz) {
   while (g * 2 <= avg && g < 64) g *= 2;
   return g < 2 ? 2 : g;
 }
+// SpMV rows: about two entries per lane, so that the unrolled loads of a
+// row are spread over fewer lanes and more rows share a wavefront
+int spmv_lanes(int nr, int64_t nnz) {
+  if (nr <= 0) return 2;
+  const double avg = (double)nnz / nr;
+  int g = 1;
+  while (g * 4 <= avg && g < 64) g *= 2;
+  return g < 2 ? 2 : g;
+}
 
 template <int MODE, int NR, class T>
 static void spmv_mode(int G, const DCsr& A, const SpmvArgs<T>& a, const T* val, hipStream_t s) {
@@ -393,7 +402,7 @@ static double spmv_bytes(SpmvMode mode, const DCsr& A, int nrhs) {
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
   if (A.nr <= 0) return;
   const T* val = csr_values<T>(A);
-  const int G = spmv_group(A.nr, A.nnz);
+  const int G = spmv_lanes(A.nr, A.nnz);
   const bool timed = g_prof.on && g_prof.used < g_prof.ev.size() / 2;
   if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   switch (mode) {

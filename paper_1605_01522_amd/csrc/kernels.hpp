@@ -44,8 +44,9 @@ struct SpmvArgs {
   int64_t ldx = 0, ldy = 0, ldb = 0, ldd = 0, ldxo = 0;   // column strides
   int nrhs = 1;
 };
-// lanes per row chosen from the mean row length
+// lanes per row chosen from the mean row length (Gauss-Seidel; SpMV)
 int spmv_group(int nr, int64_t nnz);
+int spmv_lanes(int nr, int64_t nnz);
 
 // Optional per-launch timing of the SpMV kernels with HIP events on the
 // launch stream, keyed by (lanes per row, mode, FP32?), with the algorithmic
