@@ -288,7 +288,7 @@ int spmv_group(int nr, int64_t nnz) {
   while (g * 2 <= avg && g < 64) g *= 2;
   return g < 2 ? 2 : g;
 }
-// SpMV rows: about two entries per lane, so that the unrolled loads of a
+// SpMV rows: two to four entries per lane, so that the unrolled loads of a
 // row are spread over fewer lanes and more rows share a wavefront
 int spmv_lanes(int nr, int64_t nnz) {
   if (nr <= 0) return 2;
@@ -1138,7 +1138,7 @@ static void sgs_node_launch(const int* nodes, int nnodes, const DCsr& A, int b, 
 int sgs_lanes(const DCsr& A, int b) {
   int b2 = 1;
   while (b2 < b) b2 <<= 1;
-  int g = spmv_group(A.nr, A.nnz);
+  int g = spmv_lanes(A.nr, A.nnz);
   while (g * b2 > 64) g >>= 1;
   return g < 2 ? 2 : g;
 }
@@ -1245,48 +1245,70 @@ void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int
 }
 
 // Dense form of one symmetric Gauss-Seidel sweep on a small level: the
-// sweep is affine, x_new = S x + Q b, so it is run once on X = [I | 0] with
-// right-hand sides [0 | I] (2n columns), giving X = [S | Q].  One launch per
-// colour (forward then backward); a thread owns one column for all b rows of
-// one node and writes them after reading, as the colour kernels do.
-__global__ __launch_bounds__(256) void k_dense_sgs_colour(double* __restrict__ X, int n, const int* __restrict__ nodes, int b,
-                                                          const int* __restrict__ ptr, const int* __restrict__ col,
-                                                          const double* __restrict__ val, const double* __restrict__ dinv,
-                                                          double omega) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const int64_t ld = 2 * (int64_t)n;
-  if (j >= 2 * n) return;
-  const int u = nodes[blockIdx.y];
-  double sum[MAXB];
-  for (int q = 0; q < b; ++q) {
-    const int r = u * b + q;
-    double acc = 0.0;
-    for (int p = ptr[r]; p < ptr[r + 1]; ++p) acc += val[p] * X[(int64_t)col[p] * ld + j];
-    sum[q] = acc;
+// sweep is affine, x_new = S x + Q b, so it is run on X = [I | 0] with
+// right-hand sides [0 | I] (2n columns), giving X = [S | Q].  The columns
+// are independent sweeps: one workgroup takes `tile` of them through every
+// colour (forward then backward) with the tile held in LDS, a barrier between
+// colours; within a colour each thread owns one (node, row), and all rows of
+// the colour are summed before any is written, so a node's dofs are relaxed
+// together from their old values, as in the colour kernels.
+constexpr int DSGS_LDS_DOUBLES = 19456;   // 152 KiB of the 160 KiB LDS
+constexpr int DSGS_MAX_TILE = 4;
+__global__ __launch_bounds__(256) void k_dense_sgs_tile(double* __restrict__ X, int n, int tile, const int* __restrict__ nodes,
+                                                        const int* __restrict__ off, int nc, int b, const int* __restrict__ ptr,
+                                                        const int* __restrict__ col, const double* __restrict__ val,
+                                                        const double* __restrict__ dinv, double omega) {
+  __shared__ double xs[DSGS_LDS_DOUBLES];     // xs[r * tile + t] = X[r][j0 + t]
+  const int j0 = blockIdx.x * tile;
+  const int nt = min(tile, 2 * n - j0);
+  for (int e = threadIdx.x; e < n * tile; e += 256) {
+    const int r = e / tile, t = e % tile;
+    xs[e] = (t < nt && j0 + t < n && r == j0 + t) ? 1.0 : 0.0;
   }
-  for (int q = 0; q < b; ++q) {
-    const int r = u * b + q;
-    const double rhs = j == n + r ? 1.0 : 0.0;
-    X[(int64_t)r * ld + j] += omega * dinv[r] * (rhs - sum[q]);
-  }
-}
-__global__ void k_identity_left(double* X, int n) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= 2 * (int64_t)n * n) return;
-  const int64_t r = e / (2 * n), c = e % (2 * n);
-  X[e] = c == r ? 1.0 : 0.0;
-}
-void dense_sgs_build(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, const double* dinv, double omega,
-                     double* X, hipStream_t s) {
-  const int n = A.nr, nc = (int)off.size() - 1;
-  hipLaunchKernelGGL(k_identity_left, dim3(cdiv(2 * (int64_t)n * n, 256)), dim3(256), 0, s, X, n);
+  __syncthreads();
   for (int i = 0; i < 2 * nc; ++i) {
     const int c = i < nc ? i : 2 * nc - 1 - i;
-    const int m = off[c + 1] - off[c];
-    if (m > 0)
-      hipLaunchKernelGGL(k_dense_sgs_colour, dim3(cdiv(2 * n, 256), m), dim3(256), 0, s, X, n, nodes + off[c], b, A.ptr.p,
-                         A.col.p, A.val.p, dinv, omega);
+    const int m = (off[c + 1] - off[c]) * b;
+    for (int e0 = 0; e0 < m; e0 += 256) {
+      const int e = e0 + threadIdx.x;
+      int r = -1;
+      double acc[DSGS_MAX_TILE] = {0.0, 0.0, 0.0, 0.0};
+      if (e < m) {
+        r = nodes[off[c] + e / b] * b + e % b;
+        for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+          const double v = val[p];
+          const double* xr = xs + (int64_t)col[p] * tile;
+#pragma unroll
+          for (int t = 0; t < DSGS_MAX_TILE; ++t)
+            if (t < nt) acc[t] += v * xr[t];
+        }
+      }
+      __syncthreads();
+      if (r >= 0) {
+        const double w = omega * dinv[r];
+#pragma unroll
+        for (int t = 0; t < DSGS_MAX_TILE; ++t)
+          if (t < nt) {
+            const double rhs = (j0 + t >= n && r == j0 + t - n) ? 1.0 : 0.0;
+            xs[r * tile + t] += w * (rhs - acc[t]);
+          }
+      }
+      __syncthreads();
+    }
   }
+  const int64_t ld = 2 * (int64_t)n;
+  for (int e = threadIdx.x; e < n * tile; e += 256) {
+    const int r = e / tile, t = e % tile;
+    if (t < nt) X[r * ld + j0 + t] = xs[e];
+  }
+}
+void dense_sgs_build(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off,
+                     const double* dinv, double omega, double* X, hipStream_t s) {
+  const int n = A.nr, nc = (int)off.size() - 1;
+  const int tile = std::min(DSGS_MAX_TILE, DSGS_LDS_DOUBLES / std::max(n, 1));
+  NF_CHECK(tile >= 1, NFIELD_EINVAL, "dense Gauss-Seidel sweep: level too large");
+  hipLaunchKernelGGL(k_dense_sgs_tile, dim3(cdiv(2 * n, tile)), dim3(256), 0, s, X, n, tile, nodes, off_dev, nc, b, A.ptr.p,
+                     A.col.p, A.val.p, dinv, omega);
   NF_HIP(hipGetLastError());
 }
 

@@ -124,8 +124,8 @@ int sgs_kind(const DCsr& A, int b, int nnodes_total, int ncolors);
 // apply their symmetric sweep as a dense affine map X = [S | Q]
 constexpr int SGS_DENSE_MAX = 2048;
 constexpr int SGS_DENSE_MIN_COLORS = 16;
-void dense_sgs_build(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, const double* dinv, double omega,
-                     double* X, hipStream_t s);
+void dense_sgs_build(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off,
+                     const double* dinv, double omega, double* X, hipStream_t s);
 template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t ldx, const T* rb, int64_t ldb, T* y,
                                           int64_t ldy, int nrhs, bool with_x, hipStream_t s);
 // one sweep over all colours (forward: ascending colour order), nodes grouped

@@ -251,10 +251,10 @@ struct DenseSgsD : FieldSmootherD<T> {
     const size_t m = 2 * (size_t)n * n;
     if (sizeof(T) == sizeof(double)) {
       X.alloc(m);
-      dense_sgs_build(*A, b, g.nodes.p, g.off, dinv64, omega, (double*)X.p, s);
+      dense_sgs_build(*A, b, g.nodes.p, g.off_dev.p, g.off, dinv64, omega, (double*)X.p, s);
     } else {
       DBuf<double> X64(m);
-      dense_sgs_build(*A, b, g.nodes.p, g.off, dinv64, omega, X64.p, s);
+      dense_sgs_build(*A, b, g.nodes.p, g.off_dev.p, g.off, dinv64, omega, X64.p, s);
       X.alloc(m);
       cast_copy<double, float>(X64.p, (float*)X.p, (int64_t)m, s);
     }
