@@ -1928,7 +1928,7 @@ static int spa_slots(int ncols, int nrows, int extra_per_slot) {
 
 // scratch of the single-pass product (upper-bound slots) above which the
 // two-pass product (count, then fill in place) is used
-constexpr int64_t SPG_ONEPASS_MAX_SLOTS = (int64_t)1 << 27;
+constexpr int64_t SPG_ONEPASS_MAX_SLOTS = (int64_t)1 << 28;
 
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
   NF_CHECK(A.nc == B.nr, NFIELD_EINVAL, "spgemm: inner dimensions differ");
