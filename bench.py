@@ -91,10 +91,31 @@ def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
     t_its = time.perf_counter() - t0
     per_it = t_its / max(st["iters"], 1)
     t_solve = t_setup + per_it * gpu_iters
+    host = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                host = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
                 sample=f"oracle setup ({t_setup:.2f} s) + first {st['iters']} GMRES iterations "
                        f"({t_its:.2f} s) of the same system, scaled to {gpu_iters} iterations",
-                setup_s=t_setup, s_per_iter=per_it)
+                setup_s=t_setup, s_per_iter=per_it, host_cpu=host, host_threads=os.cpu_count())
+
+
+# the paper's own figures (other problems, other hardware): context only
+PAPER_CONTEXT = {
+    "note": "different problems, meshes and hardware (Leibniz Supercomputing Centre processors; CPU model, "
+            "clock and node layout not stated); Trilinos MueLu/ML with DD(GS) smoothers and KLU; times "
+            "include preconditioner setup; context, not a target",
+    "lung": "patient-specific lung, 2,197,952 dofs incl. 5 constraints, 64 processors, GMRES rtol 1e-6: "
+            "SIMPLE(BGS(AMG)) about 20 iterations, 14.9 s per linear solve; SIMPLE(AMG(BGS)) 16.6 s",
+    "tsi": "thermo-structure (second Danilovskaya problem), GMRES rtol 1e-8: BGS(AMG) 85,184 dofs on 2 "
+           "processors 33 iterations / 7.7 s; 1,331,000 dofs on 32 processors 56 iterations / 25.7 s",
+    "fsi": "pressure-wave FSI: results only in figures, no numbers recoverable",
+}
 
 
 def run_workload(name, steps, warmup, seed, precision_form):
@@ -345,6 +366,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, W["spec"], W["opts"], iters)
+    out["paper_context"] = PAPER_CONTEXT
     del r, s
     if not args.no_lung and args.workload != "lung3d":
         out["lung"] = summary("lung3d", run_workload("lung3d", 2, 1, args.seed, not args.no_precision_form),
