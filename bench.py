@@ -324,8 +324,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md and not measured.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this solver is built and "
+              "measured on a single GPU; no multi-GPU figure is produced.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
