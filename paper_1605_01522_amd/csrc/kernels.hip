@@ -1525,12 +1525,18 @@ __device__ __forceinline__ int hash_slot(int key, int logts) {
   return (int)(((uint32_t)key * 2654435761u) >> (32 - logts));
 }
 // returns 1 if the key was new, 0 if present, -1 if the table is full
+// (a plain read first: most inserts of a product row are repeats, which then
+// need no atomic; an empty slot is claimed by compare-and-swap)
 __device__ __forceinline__ int hash_insert(int* table, int ts, int logts, int key) {
   int h = logts > 0 ? hash_slot(key, logts) : 0;
   for (int probe = 0; probe < ts; ++probe) {
-    const int old = atomicCAS(&table[h], EMPTY_KEY, key);
-    if (old == EMPTY_KEY) return 1;
-    if (old == key) return 0;
+    int cur = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == key) return 0;
+    if (cur == EMPTY_KEY) {
+      cur = atomicCAS(&table[h], EMPTY_KEY, key);
+      if (cur == EMPTY_KEY) return 1;
+      if (cur == key) return 0;
+    }
     h = (h + 1) & (ts - 1);
   }
   return -1;
