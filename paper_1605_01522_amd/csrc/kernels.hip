@@ -211,37 +211,33 @@ template void dense_gemvm<float>(const double*, int, const float*, int64_t, floa
 // Row sums are reduced with xor-shuffles inside the group; lane 0 of the
 // group applies the epilogue to every column.
 // sum over p = p0, p0 + G, ... < p1 of val[p] x[k ldx + col[p]] into s[k]
-// (k < nrhs), in ascending p; loads of four entries are issued before their
-// products so that their latencies overlap
+// (k < nrhs), in ascending p.  The entries are taken U per lane at a time with
+// the loads past p1 masked off, so a lane's share of a typical row (at most 8
+// entries with one right-hand side) costs one round trip for the matrix and
+// one for the gathered x, instead of a chain of single-entry iterations.
 template <int G, int NR, class T>
 __device__ __forceinline__ void row_dot(int p0, int p1, const int* __restrict__ col, const T* __restrict__ val,
                                         const T* __restrict__ x, int64_t ldx, int nrhs, T* s) {
-  int p = p0;
-  for (; p + 3 * G < p1; p += 4 * G) {
-    T v[4];
-    int c[4];
+  constexpr int U = NR == 1 ? 8 : 4;
+  for (int p = p0; p < p1; p += U * G) {
+    T v[U];
+    int c[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v[u] = val[p + u * G];
-      c[u] = col[p + u * G];
+    for (int u = 0; u < U; ++u) {
+      const int q = p + u * G;
+      v[u] = q < p1 ? val[q] : (T)0;
+      c[u] = q < p1 ? col[q] : -1;
     }
-    T xv[4][NR];
+    T xv[U][NR];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) xv[u][k] = k < nrhs ? x[k * ldx + c[u]] : (T)0;
+      for (int k = 0; k < NR; ++k) xv[u][k] = (c[u] >= 0 && k < nrhs) ? x[k * ldx + c[u]] : (T)0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < NR; ++k)
-        if (k < nrhs) s[k] += v[u] * xv[u][k];
-  }
-  for (; p < p1; p += G) {
-    const T v = val[p];
-    const int c = col[p];
-#pragma unroll
-    for (int k = 0; k < NR; ++k)
-      if (k < nrhs) s[k] += v * x[k * ldx + c];
+        if (c[u] >= 0 && k < nrhs) s[k] += v[u] * xv[u][k];
   }
 }
 
