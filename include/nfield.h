@@ -107,6 +107,9 @@ typedef struct {
                               count, after every rebuild) into a HIP graph and replayed;
                               0 (default): launched one by one.  Same bits either way; on
                               gfx950 / ROCm 7.2 replay did not shorten the solve. */
+  int32_t block_products;  /* 1 (default): Galerkin products of node-blocked fields are
+                              formed block by block (one hash insert per block pair);
+                              0: entry by entry.  Same pattern and bits either way. */
 } nfield_opts;
 
 typedef struct {

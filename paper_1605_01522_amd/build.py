@@ -20,7 +20,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", SRC, "-Wall", "-Wno-unused-result"]
 
-SOURCES = ["kernels.hip", "amg.hip", "solver.hip"]
+SOURCES = ["kernels.hip", "bspgemm.hip", "amg.hip", "solver.hip"]
 
 
 def _compile(src):

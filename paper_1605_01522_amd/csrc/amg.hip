@@ -66,6 +66,36 @@ static std::shared_ptr<DBuf<double>> copy_dev(const DBuf<double>& x, hipStream_t
   return y;
 }
 
+// Node blocks pay in a product when the inner block and the output block hold
+// more than one entry.
+static bool use_blocks(const Opts& o, int br, int bk, int bc) { return o.block_products && bk >= 2 && br * bc >= 2; }
+
+// C = A B, A with br x bk node blocks, B with bk x bc
+static void product(const Opts& o, const DCsr& A, int br, int bk, const DCsr& B, int bc, DCsr& C, hipStream_t s) {
+  if (use_blocks(o, br, bk, bc)) spgemm_blocked(A, br, bk, B, bc, C, s);
+  else spgemm(A, B, C, s);
+}
+
+// Galerkin block R_i A_ij P_j (Sec. 3.3): A P first, then R (A P); node
+// blocks: R ci x bi, A bi x bj, P bj x cj.  With blocks on both products the
+// intermediate A P stays blocked.
+static void galerkin(const Opts& o, const DCsr& R, const DCsr& A, const DCsr& P, int ci, int bi, int bj, int cj, DCsr& Ac,
+                     hipStream_t s) {
+  if (use_blocks(o, bi, bj, cj) && use_blocks(o, ci, bi, cj)) {
+    DBsr Ab, Pb, APb, Rb, Cb;
+    csr_to_bsr(A, bi, bj, Ab, s);
+    csr_to_bsr(P, bj, cj, Pb, s);
+    bspgemm(Ab, Pb, APb, s);
+    csr_to_bsr(R, ci, bi, Rb, s);
+    bspgemm(Rb, APb, Cb, s);
+    bsr_to_csr(Cb, Ac, s);
+    return;
+  }
+  DCsr AP;
+  product(o, A, bi, bj, P, cj, AP, s);
+  product(o, R, ci, bi, AP, cj, Ac, s);
+}
+
 void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDev>& F, const Opts& o, hipStream_t s) {
   const int N = A0.N;
   H.N = N;
@@ -148,7 +178,7 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         auto dead = std::make_shared<DBuf<int>>();
         const int ndead = tentative(nnode, L.bs[i], k, agg->p, na, L.B[i]->p, Pt, *Bc, *dead, s);
         DCsr AP;
-        spgemm(Aii, Pt, AP, s);
+        product(o, Aii, L.bs[i], L.bs[i], Pt, k, AP, s);
         DBuf<double> srow(n);
         const double omega = 4.0 / (3.0 * L.lambda[i]);
         if (n > 0) hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, s, L.dinv[i]->p, -omega, srow.p, (int64_t)n);
@@ -173,10 +203,8 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
       for (int j = 0; j < N; ++j) {
         const DCsr* Aij = L.A.at(i, j);
         if (!Aij) continue;
-        DCsr AP;
-        spgemm(*Aij, *L.P[j], AP, s);
         auto Ac = std::make_shared<DCsr>();
-        spgemm(*L.R[i], AP, *Ac, s);
+        galerkin(o, *L.R[i], *Aij, *L.P[j], C.bs[i], L.bs[i], L.bs[j], C.bs[j], *Ac, s);
         if (i == j && C.ndead[i] > 0) set_diag_one(*Ac, C.dead[i]->p, C.ndead[i], s);
         C.A.blk[(size_t)i * N + j] = Ac;
       }

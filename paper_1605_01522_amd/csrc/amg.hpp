@@ -17,6 +17,7 @@ struct Opts {
   int hier_fp32 = 0;
   uint64_t seed = 0;
   int graphs = 0;
+  int block_products = 1;
 };
 
 // N x N grid of device blocks over fields [0, N); a null block is zero.

@@ -1,0 +1,405 @@
+// Block-structured sparse products for the Galerkin triple products of the
+// AMG setup (R A P, A P) on node-blocked matrices.
+//
+// A field's matrices are node-blocked: rows and columns come in groups of the
+// field's dofs per node (fine level) or near-nullspace vectors per aggregate
+// (coarse levels), and their sparsity is a pattern of small dense blocks.
+// Hashing scalar columns (one insert per scalar product, most of them repeats)
+// then costs far more than the arithmetic.  Here both operands are regrouped
+// into blocks of br x bc values with a bitmask of the stored entries, the
+// block pattern of the product comes from the scalar product machinery run on
+// the (much smaller) block patterns, and every output value is summed by the
+// lane that owns it.  Each output entry exists exactly when some inner index
+// pairs two stored entries, and its value adds a_ik b_kj over exactly those
+// pairs in ascending k (block by block, then within the block), which is the
+// pattern and the order of the scalar product: the results are the same bits.
+
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace nf {
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------ CSR -> blocks
+// The br scalar rows of block row i are adjacent in CSR, so its entries are
+// the range [ptr[i br], ptr[(i + 1) br]).
+constexpr int BSR_CAP = 2048;
+
+// ascending bitonic sort of keys[0, ts) (ts a power of two) by one wavefront
+__device__ void wave_bitonic(int* keys, int ts, int lane) {
+  for (int kk = 2; kk <= ts; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < ts; t += 64) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int x = keys[t], y = keys[u];
+          if ((x > y) == ((t & kk) == 0)) {
+            keys[t] = y;
+            keys[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// one wavefront per block row: its distinct block columns, ascending, into
+// the scratch at the row's first entry offset (it has room: one slot per
+// entry), their number into cnt[i].  Up to BSR_CAP entries are sorted in
+// LDS; longer block rows merge their BR sorted rows serially.
+template <int BR>
+__global__ __launch_bounds__(64) void k_bsr_keys(int bc, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                 int* __restrict__ ucol, int* __restrict__ cnt) {
+  __shared__ int keys[BSR_CAP];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int e0 = ptr[i * BR], e1 = ptr[(i + 1) * BR], E = e1 - e0;
+  if (E <= BSR_CAP) {
+    int ts = 1;
+    while (ts < E) ts <<= 1;
+    for (int t = lane; t < ts; t += 64) keys[t] = t < E ? col[e0 + t] / bc : INT_MAX;
+    __syncthreads();
+    wave_bitonic(keys, ts, lane);
+    int n = 0;
+    for (int t0 = 0; t0 < E; t0 += 64) {
+      const int t = t0 + lane;
+      const bool first = t < E && (t == 0 || keys[t - 1] != keys[t]);
+      const unsigned long long bal = __ballot(first);
+      if (first) ucol[e0 + n + __popcll(bal & ((1ull << lane) - 1ull))] = keys[t];
+      n += __popcll(bal);
+    }
+    if (lane == 0) cnt[i] = n;
+    return;
+  }
+  if (lane != 0) return;
+  int pos[BR], end[BR];
+#pragma unroll
+  for (int q = 0; q < BR; ++q) {
+    pos[q] = ptr[i * BR + q];
+    end[q] = ptr[i * BR + q + 1];
+  }
+  int n = 0;
+  while (true) {
+    int mn = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < BR; ++q)
+      if (pos[q] < end[q]) mn = min(mn, col[pos[q]] / bc);
+    if (mn == INT_MAX) break;
+#pragma unroll
+    for (int q = 0; q < BR; ++q)
+      while (pos[q] < end[q] && col[pos[q]] / bc == mn) ++pos[q];
+    ucol[e0 + n++] = mn;
+  }
+  cnt[i] = n;
+}
+
+// one wavefront per block row: copy its block columns, then every entry finds
+// its block (binary search) and lands at row q, column c inside it, with its
+// bit (q bc + c) or-ed into the block's mask (masks start at zero)
+__global__ __launch_bounds__(64) void k_bsr_place(int br, int bc, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                  const double* __restrict__ val, const int* __restrict__ ucol,
+                                                  const int* __restrict__ bptr, int* __restrict__ bcol,
+                                                  double* __restrict__ bval, unsigned long long* bmask) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int e0 = ptr[i * br], e1 = ptr[(i + 1) * br];
+  const int o = bptr[i], n = bptr[i + 1] - o, bb = br * bc;
+  const int* __restrict__ u = ucol + e0;
+  for (int t = lane; t < n; t += 64) bcol[o + t] = u[t];
+  for (int t = e0 + lane; t < e1; t += 64) {
+    int q = 0;
+    while (ptr[i * br + q + 1] <= t) ++q;
+    const int c = col[t], jb = c / bc;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (u[mid] < jb) lo = mid + 1; else hi = mid;
+    }
+    const int cc = c - jb * bc;
+    bval[(int64_t)(o + lo) * bb + q * bc + cc] = val[t];
+    atomicOr(&bmask[o + lo], 1ull << (q * bc + cc));
+  }
+}
+
+void csr_to_bsr(const DCsr& A, int br, int bc, DBsr& B, hipStream_t s) {
+  NF_CHECK(br >= 1 && br <= 8 && bc >= 1 && bc <= 8, NFIELD_EINVAL, "block product: block size above 8");
+  NF_CHECK(A.nr % br == 0 && A.nc % bc == 0, NFIELD_EINVAL, "block product: size not a multiple of the block size");
+  B.br = br;
+  B.bc = bc;
+  B.pat.nr = A.nr / br;
+  B.pat.nc = A.nc / bc;
+  const int nbr = B.pat.nr;
+  B.pat.ptr.alloc(nbr + 1);
+  DBuf<int> cnt(nbr + 1), ucol(A.nnz > 0 ? A.nnz : 1);
+  if (nbr > 0) {
+    switch (br) {
+#define NF_BK(R) \
+  case R: hipLaunchKernelGGL(k_bsr_keys<R>, dim3(nbr), dim3(64), 0, s, bc, A.ptr.p, A.col.p, ucol.p, cnt.p); break;
+      NF_BK(1) NF_BK(2) NF_BK(3) NF_BK(4) NF_BK(5) NF_BK(6) NF_BK(7) NF_BK(8)
+#undef NF_BK
+    }
+  }
+  B.pat.nnz = exclusive_scan(cnt.p, B.pat.ptr.p, nbr, s);
+  const int64_t nb = B.pat.nnz > 0 ? B.pat.nnz : 1;
+  B.pat.col.alloc(nb);
+  B.pat.val.alloc(nb);
+  B.val.alloc(nb * br * bc);
+  B.mask.alloc(nb);
+  fill<double>(B.pat.val.p, 1.0, nb, s);
+  fill<double>(B.val.p, 0.0, nb * br * bc, s);
+  fill<unsigned long long>(B.mask.p, 0ull, nb, s);
+  if (nbr > 0)
+    hipLaunchKernelGGL(k_bsr_place, dim3(nbr), dim3(64), 0, s, br, bc, A.ptr.p, A.col.p, A.val.p, ucol.p, B.pat.ptr.p,
+                       B.pat.col.p, B.val.p, B.mask.p);
+}
+
+// ------------------------------------------------------------ blocks -> CSR
+// one thread per scalar row: pass 0 counts its stored entries, pass 1 writes
+// them in ascending column (blocks ascending, then columns inside the block)
+template <int PASS>
+__global__ void k_bsr_rows(int nr, int br, int bc, const int* __restrict__ bptr, const int* __restrict__ bcol,
+                           const double* __restrict__ bval, const unsigned long long* __restrict__ bmask,
+                           int* __restrict__ cnt, const int* __restrict__ ptr, int* __restrict__ col,
+                           double* __restrict__ val) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const int i = r / br, q = r - i * br, bb = br * bc;
+  const unsigned long long rowbits = ((bc == 64 ? 0ull : (1ull << bc)) - 1ull) << (q * bc);
+  int n = 0;
+  const int o = PASS ? ptr[r] : 0;
+  for (int p = bptr[i]; p < bptr[i + 1]; ++p) {
+    const unsigned long long m = bmask[p] & rowbits;
+    if (!m) continue;
+    if (!PASS) {
+      n += __popcll(m);
+      continue;
+    }
+    for (int c = 0; c < bc; ++c)
+      if ((m >> (q * bc + c)) & 1ull) {
+        col[o + n] = bcol[p] * bc + c;
+        val[o + n] = bval[(int64_t)p * bb + q * bc + c];
+        ++n;
+      }
+  }
+  if (!PASS) cnt[r] = n;
+}
+
+void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s) {
+  A.nr = B.pat.nr * B.br;
+  A.nc = B.pat.nc * B.bc;
+  A.ptr.alloc(A.nr + 1);
+  DBuf<int> cnt(A.nr + 1);
+  if (A.nr > 0)
+    hipLaunchKernelGGL(k_bsr_rows<0>, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
+                       B.val.p, B.mask.p, cnt.p, (const int*)nullptr, (int*)nullptr, (double*)nullptr);
+  A.nnz = exclusive_scan(cnt.p, A.ptr.p, A.nr, s);
+  A.col.alloc(A.nnz > 0 ? A.nnz : 1);
+  A.val.alloc(A.nnz > 0 ? A.nnz : 1);
+  if (A.nr > 0 && A.nnz > 0)
+    hipLaunchKernelGGL(k_bsr_rows<1>, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
+                       B.val.p, B.mask.p, (int*)nullptr, A.ptr.p, A.col.p, A.val.p);
+}
+
+// ------------------------------------------------------------ numeric product
+// One wavefront per block row i of C, its output values and stored flags in
+// LDS (block by block, br bc values each).  For every block (i, kb) of A in
+// ascending kb the lanes take the entries (block (kb, j) of B, r, c) of B's
+// block row kb, one each: the lane finds block j in C's row (binary search
+// over the row's block columns) and adds a_rk b_kc for k ascending inside the
+// block where both entries are stored.  Within one A block no two lanes share
+// an output entry; the blocks follow one another with a barrier, so every
+// output entry sums its terms in ascending k.
+constexpr int BSP_CAPV = 2048;
+
+__global__ __launch_bounds__(64) void k_bspgemm_lds(int br, int bk, int bc, const int* __restrict__ Ap,
+                                                    const int* __restrict__ Ac, const double* __restrict__ Av,
+                                                    const unsigned long long* __restrict__ Am, const int* __restrict__ Bp,
+                                                    const int* __restrict__ Bc, const double* __restrict__ Bv,
+                                                    const unsigned long long* __restrict__ Bm, const int* __restrict__ Cp,
+                                                    const int* __restrict__ Cc, double* __restrict__ Cv,
+                                                    unsigned long long* __restrict__ Cm, int* __restrict__ ovf,
+                                                    int* __restrict__ novf) {
+  __shared__ double acc[BSP_CAPV];
+  __shared__ unsigned char st[BSP_CAPV];
+  __shared__ int ccol[BSP_CAPV / 2];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int c0 = Cp[i], ncb = Cp[i + 1] - c0, bb = br * bc, nel = ncb * bb;
+  if (nel > BSP_CAPV || ncb > BSP_CAPV / 2) {
+    if (lane == 0) ovf[atomicAdd(novf, 1)] = i;
+    return;
+  }
+  for (int t = lane; t < ncb; t += 64) ccol[t] = Cc[c0 + t];
+  for (int t = lane; t < nel; t += 64) {
+    acc[t] = 0.0;
+    st[t] = 0;
+  }
+  __syncthreads();
+  const int a0 = Ap[i], a1 = Ap[i + 1];
+  for (int p0 = a0; p0 < a1; p0 += 64) {
+    // block column, B row range and mask of the next 64 blocks of A's row
+    int mq0 = 0, mq1 = 0;
+    unsigned long long mam = 0;
+    if (p0 + lane < a1) {
+      const int kb = Ac[p0 + lane];
+      mq0 = Bp[kb];
+      mq1 = Bp[kb + 1];
+      mam = Am[p0 + lane];
+    }
+    const int np = min(64, a1 - p0);
+    for (int t = 0; t < np; ++t) {
+      const int q0 = __shfl(mq0, t), q1 = __shfl(mq1, t);
+      const unsigned long long am = __shfl(mam, t);
+      const double* __restrict__ av = Av + (int64_t)(p0 + t) * br * bk;
+      const int items = (q1 - q0) * bb;
+      for (int it = lane; it < items; it += 64) {
+        const int qo = it / bb, rc = it - qo * bb, r = rc / bc, c = rc - r * bc;
+        const int qq = q0 + qo;
+        const int jb = Bc[qq];
+        const unsigned long long bm = Bm[qq];
+        int lo = 0, hi = ncb;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (ccol[mid] < jb) lo = mid + 1; else hi = mid;
+        }
+        const double* __restrict__ bv = Bv + (int64_t)qq * bk * bc;
+        const int e = lo * bb + rc;
+        double a = acc[e];
+        bool any = false;
+        for (int k = 0; k < bk; ++k)
+          if (((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
+            a += av[r * bk + k] * bv[k * bc + c];
+            any = true;
+          }
+        if (any) {
+          acc[e] = a;
+          st[e] = 1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = lane; t < nel; t += 64) Cv[(int64_t)c0 * bb + t] = acc[t];
+  for (int pb = lane; pb < ncb; pb += 64) {
+    unsigned long long m = 0;
+    for (int rc = 0; rc < bb; ++rc)
+      if (st[pb * bb + rc]) m |= 1ull << rc;
+    Cm[c0 + pb] = m;
+  }
+}
+
+// Block rows too long for LDS: the listed rows, one wavefront each, every
+// lane owning output entries (each block padded to BBP = the next power of
+// two >= br bc, so a block never straddles a 64-lane window) of up to EPL
+// windows at a time and summing their terms over the A blocks in ascending
+// kb, k; the block's stored-entry mask is the ballot of its lanes.
+constexpr int BSP_EPL = 4;
+
+__global__ __launch_bounds__(64) void k_bspgemm_wide(const int* __restrict__ rows, int br, int bk, int bc, int bbp,
+                                                     const int* __restrict__ Ap, const int* __restrict__ Ac,
+                                                     const double* __restrict__ Av, const unsigned long long* __restrict__ Am,
+                                                     const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                     const double* __restrict__ Bv, const unsigned long long* __restrict__ Bm,
+                                                     const int* __restrict__ Cp, const int* __restrict__ Cc,
+                                                     double* __restrict__ Cv, unsigned long long* __restrict__ Cm) {
+  const int i = rows[blockIdx.x], lane = threadIdx.x;
+  const int c0 = Cp[i], ncb = Cp[i + 1] - c0;
+  const int bb = br * bc, nel = ncb * bbp;
+  const int a0 = Ap[i], a1 = Ap[i + 1];
+  for (int base = 0; base < nel; base += 64 * BSP_EPL) {
+    double acc[BSP_EPL];
+    bool st[BSP_EPL];
+    int jb[BSP_EPL], rr[BSP_EPL], cc[BSP_EPL];
+#pragma unroll
+    for (int u = 0; u < BSP_EPL; ++u) {
+      acc[u] = 0.0;
+      st[u] = false;
+      jb[u] = -1;
+      rr[u] = cc[u] = 0;
+      const int e = base + u * 64 + lane;
+      if (e < nel) {
+        const int pb = e / bbp, rc = e - pb * bbp;
+        if (rc < bb) {
+          jb[u] = Cc[c0 + pb];
+          rr[u] = rc / bc;
+          cc[u] = rc - rr[u] * bc;
+        }
+      }
+    }
+    for (int p = a0; p < a1; ++p) {
+      const int kb = Ac[p];
+      const unsigned long long am = Am[p];
+      const double* av = Av + (int64_t)p * br * bk;
+      const int q0 = Bp[kb], q1 = Bp[kb + 1];
+#pragma unroll
+      for (int u = 0; u < BSP_EPL; ++u) {
+        if (jb[u] < 0) continue;
+        int lo = q0, hi = q1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (Bc[mid] < jb[u]) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= q1 || Bc[lo] != jb[u]) continue;
+        const unsigned long long bm = Bm[lo];
+        const double* bv = Bv + (int64_t)lo * bk * bc;
+        for (int k = 0; k < bk; ++k)
+          if (((am >> (rr[u] * bk + k)) & 1ull) && ((bm >> (k * bc + cc[u])) & 1ull)) {
+            acc[u] += av[rr[u] * bk + k] * bv[k * bc + cc[u]];
+            st[u] = true;
+          }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BSP_EPL; ++u) {
+      const int e = base + u * 64 + lane;
+      const unsigned long long bal = __ballot(st[u]);
+      if (e < nel) {
+        const int pb = e / bbp, rc = e - pb * bbp;
+        if (rc < bb) Cv[(int64_t)(c0 + pb) * bb + rc] = acc[u];
+        if (rc == 0) {
+          // this block's bits sit at lanes [lane, lane + bbp) of the window
+          const unsigned long long w = bal >> lane;
+          Cm[c0 + pb] = bbp == 64 ? w : (w & ((1ull << bbp) - 1ull));
+        }
+      }
+    }
+  }
+}
+
+void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
+  NF_CHECK(A.pat.nc == B.pat.nr && A.bc == B.br, NFIELD_EINVAL, "block product: inner dimensions differ");
+  C.br = A.br;
+  C.bc = B.bc;
+  // block pattern of the product (the pattern values are counts, unused)
+  spgemm(A.pat, B.pat, C.pat, s);
+  const int64_t nb = C.pat.nnz > 0 ? C.pat.nnz : 1;
+  const int bb = C.br * C.bc;
+  C.val.alloc(nb * bb);
+  C.mask.alloc(nb);
+  const int nbr = C.pat.nr;
+  if (nbr <= 0 || C.pat.nnz <= 0) return;
+  DBuf<int> ovf(nbr), novf(1);
+  fill<int>(novf.p, 0, 1, s);
+  hipLaunchKernelGGL(k_bspgemm_lds, dim3(nbr), dim3(64), 0, s, A.br, A.bc, B.bc, A.pat.ptr.p, A.pat.col.p, A.val.p,
+                     A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p, C.val.p, C.mask.p,
+                     ovf.p, novf.p);
+  int n = 0;
+  NF_HIP(hipMemcpyAsync(&n, novf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  if (n > 0) {
+    int bbp = 1;
+    while (bbp < bb) bbp <<= 1;
+    hipLaunchKernelGGL(k_bspgemm_wide, dim3(n), dim3(64), 0, s, ovf.p, A.br, A.bc, B.bc, bbp, A.pat.ptr.p, A.pat.col.p,
+                       A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p, C.val.p,
+                       C.mask.p);
+  }
+}
+
+void spgemm_blocked(const DCsr& A, int br, int bk, const DCsr& B, int bc, DCsr& C, hipStream_t s) {
+  DBsr Ab, Bb, Cb;
+  csr_to_bsr(A, br, bk, Ab, s);
+  csr_to_bsr(B, bk, bc, Bb, s);
+  bspgemm(Ab, Bb, Cb, s);
+  bsr_to_csr(Cb, C, s);
+}
+
+}  // namespace nf

@@ -186,6 +186,7 @@ template <class T> void dense_gemvm(const double* M, int n, const T* b, int64_t 
 template void fill<double>(double*, double, int64_t, hipStream_t);
 template void fill<float>(float*, float, int64_t, hipStream_t);
 template void fill<int>(int*, int, int64_t, hipStream_t);
+template void fill<unsigned long long>(unsigned long long*, unsigned long long, int64_t, hipStream_t);
 template void cast_copy<double, float>(const double*, float*, int64_t, hipStream_t);
 template void cast_copy<float, double>(const float*, double*, int64_t, hipStream_t);
 template void fillm<double>(double*, int64_t, double, int64_t, int, hipStream_t);
@@ -1007,52 +1008,78 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
   return h[3];
 }
 
+// D^-1 scaling, rhs and old x of row r (loaded before the row sum with one
+// right-hand side; after it with several, where the registers are scarcer)
+template <int NR, class T>
+__device__ __forceinline__ void sgs_row_load(int r, const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
+                                             int64_t ldr, const T* __restrict__ x, int64_t ldx, int nrhs, T& w, T* rv,
+                                             T* xo) {
+  w = omega * dinv[r];
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+    if (k < nrhs) {
+      rv[k] = rhs[k * ldr + r];
+      xo[k] = x[k * ldx + r];
+    }
+}
+
 // One group of B2*G lanes per node (B2 = b rounded up to a power of two,
 // G lanes per row, B2*G <= 64 so the group lies inside one wavefront): every
 // row of the node is summed at once for all columns, and the updates are
 // written after all of the group's loads have completed, so the node's dofs
-// are relaxed together from their old values.
+// are relaxed together from their old values.  t indexes the colour-ordered
+// node list; cptr holds, per listed node, the b + 1 row bounds of its rows, so
+// the row loads need no lookup through the node id; with one right-hand side
+// the row's D^-1, rhs and old x (written by this group alone) are fetched
+// beside them.
 template <int G, int B2, int NR, class T>
-__device__ __forceinline__ void sgs_node(int u, int sub, int b, const int* __restrict__ ptr, const int* __restrict__ col,
-                                         const T* __restrict__ val, const T* __restrict__ dinv, T omega,
-                                         const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
+__device__ __forceinline__ void sgs_node(int t, int sub, int b, const int* __restrict__ nodes, const int* __restrict__ cptr,
+                                         const int* __restrict__ col, const T* __restrict__ val, const T* __restrict__ dinv,
+                                         T omega, const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
+                                         int nrhs) {
   const int q = sub / G, lane = sub % G;
-  const int r = u * b + q;
-  T acc[NR];
+  T acc[NR], rv[NR], xo[NR];
+  T w = 0;
+  int r = 0;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0;
-  if (q < b) row_dot<G, NR, T>(ptr[r] + lane, ptr[r + 1], col, val, x, ldx, nrhs, acc);
+  for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xo[k] = 0;
+  if (q < b) {
+    const int* cp = cptr + (int64_t)t * (b + 1) + q;
+    const int p0 = cp[0], p1 = cp[1];
+    r = nodes[t] * b + q;
+    if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
+    row_dot<G, NR, T>(p0 + lane, p1, col, val, x, ldx, nrhs, acc);
+  }
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
   if (q < b && lane == 0) {
-    const T w = omega * dinv[r];
+    if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
 #pragma unroll
     for (int k = 0; k < NR; ++k)
-      if (k < nrhs) x[k * ldx + r] += w * (rhs[k * ldr + r] - acc[k]);
+      if (k < nrhs) x[k * ldx + r] = xo[k] + w * (rv[k] - acc[k]);
   }
 }
 
 template <int G, int B2, int NR, class T>
-__global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, int b,
-                                                   const int* __restrict__ ptr, const int* __restrict__ col,
-                                                   const T* __restrict__ val, const T* __restrict__ dinv, T omega,
-                                                   const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
-                                                   int nrhs) {
+__global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, const int* __restrict__ cptr,
+                                                   int b, const int* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
+                                                   int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
   constexpr int NG = G * B2;
   const int gid = blockIdx.x * 256 + threadIdx.x;
   const int t = gid / NG;
   if (t >= nnodes) return;
-  sgs_node<G, B2, NR, T>(nodes[t], gid % NG, b, ptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+  sgs_node<G, B2, NR, T>(t, gid % NG, b, nodes, cptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
 }
 
 // A whole sweep over every colour of a small level in one workgroup: the
 // colours run in turn with a barrier between them (the same per-node update
 // as k_sgs_color, so the results are the same bits).
 template <int G, int B2, int NR, class T>
-__global__ __launch_bounds__(1024) void k_sgs_sweep1(const int* __restrict__ nodes, const int* __restrict__ off, int ncolors,
-                                                     int forward, int b, const int* __restrict__ ptr,
+__global__ __launch_bounds__(1024) void k_sgs_sweep1(const int* __restrict__ nodes, const int* __restrict__ cptr,
+                                                     const int* __restrict__ off, int ncolors, int forward, int b,
                                                      const int* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
                                                      int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
@@ -1062,7 +1089,7 @@ __global__ __launch_bounds__(1024) void k_sgs_sweep1(const int* __restrict__ nod
     const int c = forward ? ci : ncolors - 1 - ci;
     const int n1 = off[c + 1];
     for (int t = off[c] + grp; t < n1; t += PER)
-      sgs_node<G, B2, NR, T>(nodes[t], sub, b, ptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+      sgs_node<G, B2, NR, T>(t, sub, b, nodes, cptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
     __syncthreads();
   }
 }
@@ -1071,63 +1098,87 @@ __global__ __launch_bounds__(1024) void k_sgs_sweep1(const int* __restrict__ nod
 // separate wavefronts when B2 <= 4), all loads of the node before a barrier,
 // then the writes.
 template <int G, int B2, int NR, class T>
-__global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+__global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes, const int* __restrict__ cptr, int b,
                                                   const int* __restrict__ col, const T* __restrict__ val,
                                                   const T* __restrict__ dinv, T omega, const T* __restrict__ rhs, int64_t ldr,
                                                   T* __restrict__ x, int64_t ldx, int nrhs) {
   static_assert(G * B2 == 256 && G <= 64, "one node per 256-thread workgroup");
-  const int u = nodes[blockIdx.x];
+  const int t = blockIdx.x;
   const int q = threadIdx.x / G, lane = threadIdx.x % G;
-  const int r = u * b + q;
-  T acc[NR];
+  T acc[NR], rv[NR], xo[NR];
+  T w = 0;
+  int r = 0;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0;
-  if (q < b) row_dot<G, NR, T>(ptr[r] + lane, ptr[r + 1], col, val, x, ldx, nrhs, acc);
+  for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xo[k] = 0;
+  if (q < b) {
+    const int* cp = cptr + (int64_t)t * (b + 1) + q;
+    const int p0 = cp[0], p1 = cp[1];
+    r = nodes[t] * b + q;
+    if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
+    row_dot<G, NR, T>(p0 + lane, p1, col, val, x, ldx, nrhs, acc);
+  }
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
   __syncthreads();
   if (q < b && lane == 0) {
-    const T w = omega * dinv[r];
+    if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
 #pragma unroll
     for (int k = 0; k < NR; ++k)
-      if (k < nrhs) x[k * ldx + r] += w * (rhs[k * ldr + r] - acc[k]);
+      if (k < nrhs) x[k * ldx + r] = xo[k] + w * (rv[k] - acc[k]);
   }
 }
 
+// row bounds of every listed node's rows, in list order: cptr[t (b+1) + q] =
+// ptr[nodes[t] b + q], q = 0..b
+__global__ void k_sgs_cptr(int nnodes, const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+                           int* __restrict__ cptr) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)nnodes * (b + 1)) return;
+  const int t = (int)(i / (b + 1)), q = (int)(i % (b + 1));
+  cptr[i] = ptr[nodes[t] * b + q];
+}
+
+void sgs_node_ptrs(const DCsr& A, int b, const int* nodes, int nnodes, int* cptr, hipStream_t s) {
+  const int64_t m = (int64_t)nnodes * (b + 1);
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_sgs_cptr, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, cptr);
+}
+
 template <int G, int B2, class T>
-static void sgs_launch(const DCsr& A, int b, const int* nodes, int nnodes, const T* val, const T* dinv, T omega,
-                       const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+static void sgs_launch(const DCsr& A, int b, const int* nodes, const int* cptr, int nnodes, const T* val, const T* dinv,
+                       T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
   const int blocks = cdiv((int64_t)nnodes * G * B2, 256);
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_sgs_color<G, B2, 1, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p, val,
+    hipLaunchKernelGGL((k_sgs_color<G, B2, 1, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, cptr, b, A.col.p, val,
                        dinv, omega, rhs, ldr, x, ldx, nrhs);
   else
-    hipLaunchKernelGGL((k_sgs_color<G, B2, NRMAX, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, A.col.p,
+    hipLaunchKernelGGL((k_sgs_color<G, B2, NRMAX, T>), dim3(blocks), dim3(256), 0, s, nnodes, nodes, cptr, b, A.col.p,
                        val, dinv, omega, rhs, ldr, x, ldx, nrhs);
 }
 
 template <int G, int B2, class T>
-static void sgs_sweep1_launch(const int* nodes, const int* off, int nc, bool forward, const DCsr& A, int b, const T* val,
-                              const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+static void sgs_sweep1_launch(const int* nodes, const int* cptr, const int* off, int nc, bool forward, const DCsr& A,
+                              int b, const T* val, const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx,
+                              int nrhs, hipStream_t s) {
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, 1, T>), dim3(1), dim3(1024), 0, s, nodes, off, nc, forward ? 1 : 0, b, A.ptr.p,
+    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, 1, T>), dim3(1), dim3(1024), 0, s, nodes, cptr, off, nc, forward ? 1 : 0, b,
                        A.col.p, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
   else
-    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, NRMAX, T>), dim3(1), dim3(1024), 0, s, nodes, off, nc, forward ? 1 : 0, b,
-                       A.ptr.p, A.col.p, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
+    hipLaunchKernelGGL((k_sgs_sweep1<G, B2, NRMAX, T>), dim3(1), dim3(1024), 0, s, nodes, cptr, off, nc, forward ? 1 : 0,
+                       b, A.col.p, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
 }
 
 template <int B2, class T>
-static void sgs_node_launch(const int* nodes, int nnodes, const DCsr& A, int b, const T* val, const T* dinv, T omega,
-                            const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+static void sgs_node_launch(const int* nodes, const int* cptr, int nnodes, const DCsr& A, int b, const T* val,
+                            const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
   constexpr int G = 256 / B2;
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_sgs_node<G, B2, 1, T>), dim3(nnodes), dim3(256), 0, s, nodes, b, A.ptr.p, A.col.p, val, dinv, omega,
-                       rhs, ldr, x, ldx, nrhs);
+    hipLaunchKernelGGL((k_sgs_node<G, B2, 1, T>), dim3(nnodes), dim3(256), 0, s, nodes, cptr, b, A.col.p, val, dinv,
+                       omega, rhs, ldr, x, ldx, nrhs);
   else
-    hipLaunchKernelGGL((k_sgs_node<G, B2, NRMAX, T>), dim3(nnodes), dim3(256), 0, s, nodes, b, A.ptr.p, A.col.p, val, dinv,
+    hipLaunchKernelGGL((k_sgs_node<G, B2, NRMAX, T>), dim3(nnodes), dim3(256), 0, s, nodes, cptr, b, A.col.p, val, dinv,
                        omega, rhs, ldr, x, ldx, nrhs);
 }
 
@@ -1150,8 +1201,8 @@ int sgs_kind(const DCsr& A, int b, int nnodes_total, int ncolors) {
 }
 
 template <class T>
-void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off, bool forward,
-               const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* cptr, const int* off_dev, const std::vector<int>& off,
+               bool forward, const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
   const int nc = (int)off.size() - 1;
   if (nc <= 0) return;
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
@@ -1162,7 +1213,7 @@ void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const
   if (kind == SGS_SWEEP1) {
     const int G = sgs_lanes(A, b);
 #define NF_SGS1(GG, BB) \
-  if (G == GG && B2 == BB) return sgs_sweep1_launch<GG, BB, T>(nodes, off_dev, nc, forward, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+  if (G == GG && B2 == BB) return sgs_sweep1_launch<GG, BB, T>(nodes, cptr, off_dev, nc, forward, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
     NF_SGS1(2, 1) NF_SGS1(4, 1) NF_SGS1(8, 1) NF_SGS1(16, 1) NF_SGS1(32, 1) NF_SGS1(64, 1)
     NF_SGS1(2, 2) NF_SGS1(4, 2) NF_SGS1(8, 2) NF_SGS1(16, 2) NF_SGS1(32, 2)
     NF_SGS1(2, 4) NF_SGS1(4, 4) NF_SGS1(8, 4) NF_SGS1(16, 4)
@@ -1175,17 +1226,18 @@ void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const
     const int m = off[c + 1] - off[c];
     if (m <= 0) continue;
     if (kind == SGS_NODE) {
-      if (B2 == 4) sgs_node_launch<4, T>(nodes + off[c], m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
-      else sgs_node_launch<8, T>(nodes + off[c], m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+      const int* cp = cptr + (int64_t)off[c] * (b + 1);
+      if (B2 == 4) sgs_node_launch<4, T>(nodes + off[c], cp, m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+      else sgs_node_launch<8, T>(nodes + off[c], cp, m, A, b, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
     } else {
-      sgs_color<T>(A, b, nodes + off[c], m, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+      sgs_color<T>(A, b, nodes + off[c], cptr + (int64_t)off[c] * (b + 1), m, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
     }
   }
 }
 
 template <class T>
-void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega, const T* rhs, int64_t ldr,
-               T* x, int64_t ldx, int nrhs, hipStream_t s) {
+void sgs_color(const DCsr& A, int b, const int* nodes, const int* cptr, int nnodes, const T* dinv, T omega, const T* rhs,
+               int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
   if (nnodes <= 0) return;
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "Gauss-Seidel: block size above 8");
   NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
@@ -1193,7 +1245,7 @@ void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv
   const int G = sgs_lanes(A, b);
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
 #define NF_SGS(GG, BB) \
-  if (G == GG && B2 == BB) return sgs_launch<GG, BB, T>(A, b, nodes, nnodes, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
+  if (G == GG && B2 == BB) return sgs_launch<GG, BB, T>(A, b, nodes, cptr, nnodes, val, dinv, omega, rhs, ldr, x, ldx, nrhs, s);
   NF_SGS(2, 1) NF_SGS(4, 1) NF_SGS(8, 1) NF_SGS(16, 1) NF_SGS(32, 1) NF_SGS(64, 1)
   NF_SGS(2, 2) NF_SGS(4, 2) NF_SGS(8, 2) NF_SGS(16, 2) NF_SGS(32, 2)
   NF_SGS(2, 4) NF_SGS(4, 4) NF_SGS(8, 4) NF_SGS(16, 4)
@@ -1356,14 +1408,14 @@ template void dense_sweep_apply<double>(const double*, int, const double*, int64
 template void dense_sweep_apply<float>(const float*, int, const float*, int64_t, const float*, int64_t, float*, int64_t, int,
                                        bool, hipStream_t);
 
-template void sgs_sweep<double>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const double*,
-                                double, const double*, int64_t, double*, int64_t, int, hipStream_t);
-template void sgs_sweep<float>(const DCsr&, int, const int*, const int*, const std::vector<int>&, bool, const float*, float,
-                               const float*, int64_t, float*, int64_t, int, hipStream_t);
-template void sgs_color<double>(const DCsr&, int, const int*, int, const double*, double, const double*, int64_t, double*,
-                                int64_t, int, hipStream_t);
-template void sgs_color<float>(const DCsr&, int, const int*, int, const float*, float, const float*, int64_t, float*,
-                               int64_t, int, hipStream_t);
+template void sgs_sweep<double>(const DCsr&, int, const int*, const int*, const int*, const std::vector<int>&, bool,
+                                const double*, double, const double*, int64_t, double*, int64_t, int, hipStream_t);
+template void sgs_sweep<float>(const DCsr&, int, const int*, const int*, const int*, const std::vector<int>&, bool,
+                               const float*, float, const float*, int64_t, float*, int64_t, int, hipStream_t);
+template void sgs_color<double>(const DCsr&, int, const int*, const int*, int, const double*, double, const double*, int64_t,
+                                double*, int64_t, int, hipStream_t);
+template void sgs_color<float>(const DCsr&, int, const int*, const int*, int, const float*, float, const float*, int64_t,
+                               float*, int64_t, int, hipStream_t);
 
 // ======================================================= tentative prolongator
 __global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {

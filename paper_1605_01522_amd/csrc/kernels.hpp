@@ -105,10 +105,14 @@ void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const 
 // greedy colouring of a node graph in node order; returns the number of
 // colours and fills color[node]
 int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int* color, hipStream_t s);
+// row bounds of the listed nodes' rows in list order: cptr[t (b+1) + q] =
+// ptr[nodes[t] b + q] for q = 0..b (cptr holds nnodes (b+1) ints)
+void sgs_node_ptrs(const DCsr& A, int b, const int* nodes, int nnodes, int* cptr, hipStream_t s);
 // relax all nodes of one colour: x_r += omega dinv_r (b_r - A_r x) for the b
 // dofs of each listed node, all from the values before the node's update
-template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, int nnodes, const T* dinv, T omega,
-                                  const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
+// (cptr: the listed nodes' row bounds as sgs_node_ptrs writes them)
+template <class T> void sgs_color(const DCsr& A, int b, const int* nodes, const int* cptr, int nnodes, const T* dinv,
+                                  T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
 int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kernel
 // kernel layout of a sweep: SGS_SWEEP1 = every colour in one workgroup (small
 // levels), SGS_NODE = one workgroup per node (long rows), SGS_COLOR = one
@@ -130,10 +134,10 @@ template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t
                                           int64_t ldy, int nrhs, bool with_x, hipStream_t s);
 // one sweep over all colours (forward: ascending colour order), nodes grouped
 // by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
-// device as off_dev)
-template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* off_dev, const std::vector<int>& off,
-                                  bool forward, const T* dinv, T omega, const T* rhs, int64_t ldr, T* x, int64_t ldx,
-                                  int nrhs, hipStream_t s);
+// device as off_dev; cptr from sgs_node_ptrs over the whole list)
+template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* cptr, const int* off_dev,
+                                  const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs,
+                                  int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)
 void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,
@@ -153,6 +157,22 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
 // smoothed prolongator in place on AP = A * P_tent: AP <- P_tent + s .* AP
 void smooth_prolongator(DCsr& AP, const double* srow, const DCsr& Pt, int b, int k, const int* agg, hipStream_t s);
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
+// node-blocked matrix: block pattern (pat.val unused), br x bc values per
+// block (row-major, zero where nothing is stored) and a mask of the stored
+// entries (bit r bc + c)
+struct DBsr {
+  DCsr pat;
+  int br = 1, bc = 1;
+  DBuf<double> val;
+  DBuf<unsigned long long> mask;
+};
+void csr_to_bsr(const DCsr& A, int br, int bc, DBsr& B, hipStream_t s);
+void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s);
+// C = A B block by block (A.bc == B.br); same pattern and bits as spgemm on
+// the scalar matrices
+void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s);
+// C = A B for A with br x bk blocks and B with bk x bc blocks
+void spgemm_blocked(const DCsr& A, int br, int bk, const DCsr& B, int bc, DCsr& C, hipStream_t s);
 void transpose(const DCsr& A, DCsr& T, hipStream_t s);
 void csr_add(double alpha, const DCsr& A, double beta, const DCsr& B, DCsr& C, hipStream_t s);
 void csr_copy(const DCsr& A, DCsr& C, hipStream_t s);

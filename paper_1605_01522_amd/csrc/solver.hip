@@ -163,6 +163,7 @@ struct SgsD : FieldSmootherD<T> {
   T omega = 1;
   DBuf<T> dinv;
   DBuf<int> nodes;                 // nodes grouped by colour
+  DBuf<int> cptr;                  // row bounds of the listed nodes' rows, b + 1 each
   std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
   DBuf<int> off_dev;
   int kind = SGS_COLOR;
@@ -193,6 +194,8 @@ struct SgsD : FieldSmootherD<T> {
     NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
     off_dev.alloc(off.size());
     NF_HIP(hipMemcpyAsync(off_dev.p, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+    cptr.alloc((size_t)(nn > 0 ? nn : 1) * (b + 1));
+    sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
     NF_HIP(hipStreamSynchronize(s));
     kind = sgs_kind(*A, b, nn, nc);
     // bytes of a sweep are counted only while launch timing is recording
@@ -204,7 +207,7 @@ struct SgsD : FieldSmootherD<T> {
       const double sz = sizeof(T);
       for (int c = 0; c < nc; ++c) {
         const double rows = (double)(off[c + 1] - off[c]) * b;
-        sweep_bytes += cnnz[c] * (sz + 4) + rows * 4 + 4.0 * (off[c + 1] - off[c]) + rows * sz;
+        sweep_bytes += cnnz[c] * (sz + 4) + 4.0 * (b + 2) * (off[c + 1] - off[c]) + rows * sz;
         sweep_bytes_x += rows * 3 * sz + sz * ccols[c];
       }
     }
@@ -216,7 +219,7 @@ struct SgsD : FieldSmootherD<T> {
   void sweep(bool forward, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const int nc = (int)off.size() - 1;
     const int slot = prof_begin(s);
-    sgs_sweep<T>(*A, b, nodes.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
+    sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
     const int lanes = kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
     const int mode = kind == SGS_SWEEP1 ? 7 : kind == SGS_NODE ? 8 : 6;
@@ -1264,6 +1267,7 @@ void nfield_default_opts(nfield_opts* o) {
   o->hier_fp32 = 0;
   o->seed = 0;
   o->graphs = 0;
+  o->block_products = 1;
 }
 
 void nfield_default_solve_opts(nfield_solve_opts* so) {
@@ -1320,6 +1324,7 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
     C->o.hier_fp32 = o.hier_fp32;
     C->o.seed = o.seed;
     C->o.graphs = o.graphs;
+    C->o.block_products = o.block_products;
     NF_CHECK(o.sweeps >= 1 && o.order >= 0 && o.order <= 2 && o.cheb_degree >= 1 && o.max_levels >= 1 &&
                  o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2,
              NFIELD_EINVAL, "options out of range");
