@@ -70,30 +70,41 @@ static std::shared_ptr<DBuf<double>> copy_dev(const DBuf<double>& x, hipStream_t
 // more than one entry.
 static bool use_blocks(const Opts& o, int br, int bk, int bc) { return o.block_products && bk >= 2 && br * bc >= 2; }
 
-// C = A B, A with br x bk node blocks, B with bk x bc
-static void product(const Opts& o, const DCsr& A, int br, int bk, const DCsr& B, int bc, DCsr& C, hipStream_t s) {
-  if (use_blocks(o, br, bk, bc)) spgemm_blocked(A, br, bk, B, bc, C, s);
-  else spgemm(A, B, C, s);
-}
+// A field's matrices of one level in block form, converted once and shared by
+// the products that need them (A_ii for A P_tent and the Galerkin product,
+// P and R = P^T for every Galerkin product of the field's row and column).
+struct LevelBlocks {
+  std::vector<DBsr> A, P, R;
+  std::vector<char> hasA, hasP;
+  explicit LevelBlocks(int N) : A(N), P(N), R(N), hasA(N, 0), hasP(N, 0) {}
+};
 
 // Galerkin block R_i A_ij P_j (Sec. 3.3): A P first, then R (A P); node
 // blocks: R ci x bi, A bi x bj, P bj x cj.  With blocks on both products the
 // intermediate A P stays blocked.
-static void galerkin(const Opts& o, const DCsr& R, const DCsr& A, const DCsr& P, int ci, int bi, int bj, int cj, DCsr& Ac,
-                     hipStream_t s) {
+static void galerkin(const Opts& o, LevelBlocks& LB, int i, int j, const DCsr& R, const DCsr& A, const DCsr& P, int ci,
+                     int bi, int bj, int cj, DCsr& Ac, hipStream_t s) {
   if (use_blocks(o, bi, bj, cj) && use_blocks(o, ci, bi, cj)) {
-    DBsr Ab, Pb, APb, Rb, Cb;
-    csr_to_bsr(A, bi, bj, Ab, s);
-    csr_to_bsr(P, bj, cj, Pb, s);
-    bspgemm(Ab, Pb, APb, s);
-    csr_to_bsr(R, ci, bi, Rb, s);
-    bspgemm(Rb, APb, Cb, s);
+    DBsr Ab, Pb, Rb, APb, Cb;
+    const DBsr* pa = &Ab;
+    const DBsr* pp = &Pb;
+    const DBsr* pr = &Rb;
+    if (i == j && LB.hasA[i]) pa = &LB.A[i];
+    else csr_to_bsr(A, bi, bj, Ab, s);
+    if (LB.hasP[j]) pp = &LB.P[j];
+    else csr_to_bsr(P, bj, cj, Pb, s);
+    if (LB.hasP[i]) pr = &LB.R[i];
+    else csr_to_bsr(R, ci, bi, Rb, s);
+    bspgemm(*pa, *pp, APb, s);
+    bspgemm(*pr, APb, Cb, s);
     bsr_to_csr(Cb, Ac, s);
     return;
   }
   DCsr AP;
-  product(o, A, bi, bj, P, cj, AP, s);
-  product(o, R, ci, bi, AP, cj, Ac, s);
+  if (use_blocks(o, bi, bj, cj)) spgemm_blocked(A, bi, bj, P, cj, AP, s);
+  else spgemm(A, P, AP, s);
+  if (use_blocks(o, ci, bi, cj)) spgemm_blocked(R, ci, bi, AP, cj, Ac, s);
+  else spgemm(R, AP, Ac, s);
 }
 
 void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDev>& F, const Opts& o, hipStream_t s) {
@@ -154,8 +165,10 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
     L.P.resize(N);
     L.R.resize(N);
     L.agg.resize(N);
+    LevelBlocks LB(N);
     for (int i = 0; i < N; ++i) {
       const int n = L.A.size[i];
+      const bool coarsened = active[i];
       L.P[i] = std::make_unique<DCsr>();
       if (!active[i]) {
         identity(n, *L.P[i], s);
@@ -178,7 +191,16 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         auto dead = std::make_shared<DBuf<int>>();
         const int ndead = tentative(nnode, L.bs[i], k, agg->p, na, L.B[i]->p, Pt, *Bc, *dead, s);
         DCsr AP;
-        product(o, Aii, L.bs[i], L.bs[i], Pt, k, AP, s);
+        if (use_blocks(o, L.bs[i], L.bs[i], k)) {
+          DBsr Ptb, APb;
+          csr_to_bsr(Aii, L.bs[i], L.bs[i], LB.A[i], s);
+          LB.hasA[i] = 1;
+          csr_to_bsr(Pt, L.bs[i], k, Ptb, s);
+          bspgemm(LB.A[i], Ptb, APb, s);
+          bsr_to_csr(APb, AP, s);
+        } else {
+          spgemm(Aii, Pt, AP, s);
+        }
         DBuf<double> srow(n);
         const double omega = 4.0 / (3.0 * L.lambda[i]);
         if (n > 0) hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, s, L.dinv[i]->p, -omega, srow.p, (int64_t)n);
@@ -193,7 +215,15 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         if (na * k > 0.83 * n) active[i] = 0;
       }
       L.R[i] = std::make_unique<DCsr>();
-      transpose(*L.P[i], *L.R[i], s);
+      if (o.block_products && coarsened && L.bs[i] * C.bs[i] >= 2) {
+        // R = P^T through the block form, which the Galerkin products reuse
+        csr_to_bsr(*L.P[i], L.bs[i], C.bs[i], LB.P[i], s);
+        bsr_transpose(LB.P[i], LB.R[i], s);
+        bsr_to_csr(LB.R[i], *L.R[i], s);
+        LB.hasP[i] = 1;
+      } else {
+        transpose(*L.P[i], *L.R[i], s);
+      }
     }
     C.A.N = N;
     C.A.size.resize(N);
@@ -204,7 +234,7 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         const DCsr* Aij = L.A.at(i, j);
         if (!Aij) continue;
         auto Ac = std::make_shared<DCsr>();
-        galerkin(o, *L.R[i], *Aij, *L.P[j], C.bs[i], L.bs[i], L.bs[j], C.bs[j], *Ac, s);
+        galerkin(o, LB, i, j, *L.R[i], *Aij, *L.P[j], C.bs[i], L.bs[i], L.bs[j], C.bs[j], *Ac, s);
         if (i == j && C.ndead[i] > 0) set_diag_one(*Ac, C.dead[i]->p, C.ndead[i], s);
         C.A.blk[(size_t)i * N + j] = Ac;
       }

@@ -22,6 +22,15 @@ namespace nf {
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// v[t] = t (the pattern values of a converted matrix: its block indices)
+__global__ void k_iota(double* v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) v[t] = (double)t;
+}
+static void iota(double* v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, dim3(cdiv(n, 256)), dim3(256), 0, s, v, n);
+}
+
 // ------------------------------------------------------------ CSR -> blocks
 // The br scalar rows of block row i are adjacent in CSR, so its entries are
 // the range [ptr[i br], ptr[(i + 1) br]).
@@ -145,7 +154,7 @@ void csr_to_bsr(const DCsr& A, int br, int bc, DBsr& B, hipStream_t s) {
   B.pat.val.alloc(nb);
   B.val.alloc(nb * br * bc);
   B.mask.alloc(nb);
-  fill<double>(B.pat.val.p, 1.0, nb, s);
+  iota(B.pat.val.p, nb, s);
   fill<double>(B.val.p, 0.0, nb * br * bc, s);
   fill<unsigned long long>(B.mask.p, 0ull, nb, s);
   if (nbr > 0)
@@ -201,73 +210,115 @@ void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ numeric product
-// One wavefront per block row i of C, its output values and stored flags in
-// LDS (block by block, br bc values each).  For every block (i, kb) of A in
-// ascending kb the lanes take the entries (block (kb, j) of B, r, c) of B's
-// block row kb, one each: the lane finds block j in C's row (binary search
-// over the row's block columns) and adds a_rk b_kc for k ascending inside the
-// block where both entries are stored.  Within one A block no two lanes share
-// an output entry; the blocks follow one another with a barrier, so every
-// output entry sums its terms in ascending k.
-constexpr int BSP_CAPV = 2048;
+// One workgroup of NT threads per block row i of C, its output values and
+// stored flags in LDS (block by block, br bc values each).  For every block
+// (i, kb) of A in ascending kb the threads take the entries (block (kb, j) of
+// B, r, c) of B's block row kb, one each: the thread finds block j in C's row
+// (binary search over the row's block columns) and adds a_rk b_kc for k
+// ascending inside the block where both entries are stored.  Within one A
+// block no two threads share an output entry; the blocks follow one another
+// with a barrier, so every output entry sums its terms in ascending k.  The
+// block columns and B row ranges of the next NT blocks of A's row are read
+// at once.  With STAGE, B's block row and A's block are staged in LDS one
+// block ahead (double buffer), so the loads of the next A block overlap the
+// work on the current one (a B block row too long for the stage is read from
+// global memory); this suits few long rows (R (A P)), while many short rows
+// (A P) want the small footprint and the occupancy it brings.
+constexpr int BSP_STG = 512;     // staged values of one B block row
+constexpr int BSP_STGB = 64;     // staged blocks of one B block row
 
-__global__ __launch_bounds__(64) void k_bspgemm_lds(int br, int bk, int bc, const int* __restrict__ Ap,
-                                                    const int* __restrict__ Ac, const double* __restrict__ Av,
-                                                    const unsigned long long* __restrict__ Am, const int* __restrict__ Bp,
-                                                    const int* __restrict__ Bc, const double* __restrict__ Bv,
-                                                    const unsigned long long* __restrict__ Bm, const int* __restrict__ Cp,
-                                                    const int* __restrict__ Cc, double* __restrict__ Cv,
-                                                    unsigned long long* __restrict__ Cm, int* __restrict__ ovf,
-                                                    int* __restrict__ novf) {
-  __shared__ double acc[BSP_CAPV];
-  __shared__ unsigned char st[BSP_CAPV];
-  __shared__ int ccol[BSP_CAPV / 2];
-  const int i = blockIdx.x, lane = threadIdx.x;
+template <int NT>
+__device__ __forceinline__ void bsp_stage(int tid, int nq, int kbc, int na, const int* __restrict__ Bc,
+                                          const double* __restrict__ Bv, const unsigned long long* __restrict__ Bm,
+                                          const double* __restrict__ av, int q0, double* sv, int* sc,
+                                          unsigned long long* sm, double* sa) {
+  const int nv = nq * kbc;
+  for (int t = tid; t < nv; t += NT) sv[t] = Bv[(int64_t)q0 * kbc + t];
+  if (tid < nq) {
+    sc[tid] = Bc[q0 + tid];
+    sm[tid] = Bm[q0 + tid];
+  }
+  if (tid < na) sa[tid] = av[tid];
+}
+
+template <int NT, int CAPV, bool STAGE>
+__global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows, int br, int bk, int bc,
+                                                    const int* __restrict__ Ap, const int* __restrict__ Ac,
+                                                    const double* __restrict__ Av, const unsigned long long* __restrict__ Am,
+                                                    const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                    const double* __restrict__ Bv, const unsigned long long* __restrict__ Bm,
+                                                    const int* __restrict__ Cp, const int* __restrict__ Cc,
+                                                    double* __restrict__ Cv, unsigned long long* __restrict__ Cm,
+                                                    int* __restrict__ ovf, int* __restrict__ novf) {
+  __shared__ double acc[CAPV];
+  __shared__ unsigned char st[CAPV];
+  __shared__ int ccol[CAPV / 2];
+  __shared__ int mq0[NT], mq1[NT];
+  __shared__ unsigned long long mam[NT];
+  __shared__ double sv[STAGE ? 2 : 1][STAGE ? BSP_STG : 1];
+  __shared__ int sc[STAGE ? 2 : 1][STAGE ? BSP_STGB : 1];
+  __shared__ unsigned long long sm[STAGE ? 2 : 1][STAGE ? BSP_STGB : 1];
+  __shared__ double sa[STAGE ? 2 : 1][STAGE ? 64 : 1];
+  const int i = rows ? rows[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const int c0 = Cp[i], ncb = Cp[i + 1] - c0, bb = br * bc, nel = ncb * bb;
-  if (nel > BSP_CAPV || ncb > BSP_CAPV / 2) {
-    if (lane == 0) ovf[atomicAdd(novf, 1)] = i;
+  if (nel > CAPV || ncb > CAPV / 2) {
+    if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
     return;
   }
-  for (int t = lane; t < ncb; t += 64) ccol[t] = Cc[c0 + t];
-  for (int t = lane; t < nel; t += 64) {
+  const int kbc = bk * bc, na = br * bk;
+  for (int t = tid; t < ncb; t += NT) ccol[t] = Cc[c0 + t];
+  for (int t = tid; t < nel; t += NT) {
     acc[t] = 0.0;
     st[t] = 0;
   }
-  __syncthreads();
   const int a0 = Ap[i], a1 = Ap[i + 1];
-  for (int p0 = a0; p0 < a1; p0 += 64) {
-    // block column, B row range and mask of the next 64 blocks of A's row
-    int mq0 = 0, mq1 = 0;
-    unsigned long long mam = 0;
-    if (p0 + lane < a1) {
-      const int kb = Ac[p0 + lane];
-      mq0 = Bp[kb];
-      mq1 = Bp[kb + 1];
-      mam = Am[p0 + lane];
+  for (int p0 = a0; p0 < a1; p0 += NT) {
+    __syncthreads();
+    if (p0 + tid < a1) {
+      const int kb = Ac[p0 + tid];
+      mq0[tid] = Bp[kb];
+      mq1[tid] = Bp[kb + 1];
+      mam[tid] = Am[p0 + tid];
     }
-    const int np = min(64, a1 - p0);
+    __syncthreads();
+    const int np = min(NT, a1 - p0);
+    if (STAGE) {
+      const int nq = mq1[0] - mq0[0];
+      if (nq <= BSP_STGB && nq * kbc <= BSP_STG)
+        bsp_stage<NT>(tid, nq, kbc, na, Bc, Bv, Bm, Av + (int64_t)p0 * na, mq0[0], sv[0], sc[0], sm[0], sa[0]);
+      __syncthreads();
+    }
     for (int t = 0; t < np; ++t) {
-      const int q0 = __shfl(mq0, t), q1 = __shfl(mq1, t);
-      const unsigned long long am = __shfl(mam, t);
-      const double* __restrict__ av = Av + (int64_t)(p0 + t) * br * bk;
-      const int items = (q1 - q0) * bb;
-      for (int it = lane; it < items; it += 64) {
+      const int b = STAGE ? (t & 1) : 0;
+      const int q0 = mq0[t], nq = mq1[t] - q0;
+      const unsigned long long am = mam[t];
+      const bool staged = STAGE && nq <= BSP_STGB && nq * kbc <= BSP_STG;
+      const double* __restrict__ avp = Av + (int64_t)(p0 + t) * na;
+      const int items = nq * bb;
+      for (int it = tid; it < items; it += NT) {
         const int qo = it / bb, rc = it - qo * bb, r = rc / bc, c = rc - r * bc;
-        const int qq = q0 + qo;
-        const int jb = Bc[qq];
-        const unsigned long long bm = Bm[qq];
+        int jb;
+        unsigned long long bm;
+        if (staged) {
+          jb = sc[b][qo];
+          bm = sm[b][qo];
+        } else {
+          jb = Bc[q0 + qo];
+          bm = Bm[q0 + qo];
+        }
         int lo = 0, hi = ncb;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (ccol[mid] < jb) lo = mid + 1; else hi = mid;
         }
-        const double* __restrict__ bv = Bv + (int64_t)qq * bk * bc;
         const int e = lo * bb + rc;
         double a = acc[e];
         bool any = false;
         for (int k = 0; k < bk; ++k)
           if (((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
-            a += av[r * bk + k] * bv[k * bc + c];
+            const double x = staged ? sa[b][r * bk + k] : avp[r * bk + k];
+            const double y = staged ? sv[b][qo * kbc + k * bc + c] : Bv[(int64_t)(q0 + qo) * kbc + k * bc + c];
+            a += x * y;
             any = true;
           }
         if (any) {
@@ -275,11 +326,18 @@ __global__ __launch_bounds__(64) void k_bspgemm_lds(int br, int bk, int bc, cons
           st[e] = 1;
         }
       }
+      if (STAGE && t + 1 < np) {
+        const int nq1 = mq1[t + 1] - mq0[t + 1];
+        if (nq1 <= BSP_STGB && nq1 * kbc <= BSP_STG)
+          bsp_stage<NT>(tid, nq1, kbc, na, Bc, Bv, Bm, Av + (int64_t)(p0 + t + 1) * na, mq0[t + 1], sv[b ^ 1], sc[b ^ 1],
+                        sm[b ^ 1], sa[b ^ 1]);
+      }
       __syncthreads();
     }
   }
-  for (int t = lane; t < nel; t += 64) Cv[(int64_t)c0 * bb + t] = acc[t];
-  for (int pb = lane; pb < ncb; pb += 64) {
+  __syncthreads();
+  for (int t = tid; t < nel; t += NT) Cv[(int64_t)c0 * bb + t] = acc[t];
+  for (int pb = tid; pb < ncb; pb += NT) {
     unsigned long long m = 0;
     for (int rc = 0; rc < bb; ++rc)
       if (st[pb * bb + rc]) m |= 1ull << rc;
@@ -365,6 +423,21 @@ __global__ __launch_bounds__(64) void k_bspgemm_wide(const int* __restrict__ row
   }
 }
 
+template <int NT, int CAPV, bool STAGE>
+static int bsp_pass(const int* rows, int nrows, const DBsr& A, const DBsr& B, DBsr& C, int* ovf, int* novf, hipStream_t s) {
+  fill<int>(novf, 0, 1, s);
+  hipLaunchKernelGGL((k_bspgemm_lds<NT, CAPV, STAGE>), dim3(nrows), dim3(NT), 0, s, rows, A.br, A.bc, B.bc, A.pat.ptr.p,
+                     A.pat.col.p, A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p,
+                     C.val.p, C.mask.p, ovf, novf);
+  int n = 0;
+  NF_HIP(hipMemcpyAsync(&n, novf, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  return n;
+}
+
+// block rows of C above which a product counts as many short rows
+constexpr int BSP_MANY_ROWS = 8192;
+
 void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
   NF_CHECK(A.pat.nc == B.pat.nr && A.bc == B.br, NFIELD_EINVAL, "block product: inner dimensions differ");
   C.br = A.br;
@@ -377,21 +450,58 @@ void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
   C.mask.alloc(nb);
   const int nbr = C.pat.nr;
   if (nbr <= 0 || C.pat.nnz <= 0) return;
-  DBuf<int> ovf(nbr), novf(1);
-  fill<int>(novf.p, 0, 1, s);
-  hipLaunchKernelGGL(k_bspgemm_lds, dim3(nbr), dim3(64), 0, s, A.br, A.bc, B.bc, A.pat.ptr.p, A.pat.col.p, A.val.p,
-                     A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p, C.val.p, C.mask.p,
-                     ovf.p, novf.p);
-  int n = 0;
-  NF_HIP(hipMemcpyAsync(&n, novf.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  NF_HIP(hipStreamSynchronize(s));
+  DBuf<int> ovf1(nbr), ovf2(nbr), novf(1);
+  int n;
+  const int* left;
+  if (nbr >= BSP_MANY_ROWS) {
+    // small LDS first (many workgroups per CU), the longer rows again with more
+    const int n1 = bsp_pass<64, 512, false>(nullptr, nbr, A, B, C, ovf1.p, novf.p, s);
+    n = n1 > 0 ? bsp_pass<256, 2048, true>(ovf1.p, n1, A, B, C, ovf2.p, novf.p, s) : 0;
+    left = ovf2.p;
+  } else {
+    n = bsp_pass<256, 2048, true>(nullptr, nbr, A, B, C, ovf1.p, novf.p, s);
+    left = ovf1.p;
+  }
   if (n > 0) {
     int bbp = 1;
     while (bbp < bb) bbp <<= 1;
-    hipLaunchKernelGGL(k_bspgemm_wide, dim3(n), dim3(64), 0, s, ovf.p, A.br, A.bc, B.bc, bbp, A.pat.ptr.p, A.pat.col.p,
+    hipLaunchKernelGGL(k_bspgemm_wide, dim3(n), dim3(64), 0, s, left, A.br, A.bc, B.bc, bbp, A.pat.ptr.p, A.pat.col.p,
                        A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p, C.val.p,
                        C.mask.p);
   }
+}
+
+// R = P^T block by block: the block pattern transposed (pattern values carry
+// the source block's index), each block's values and mask transposed
+__global__ void k_bsr_tblocks(int64_t nb, int pr, int pc, const double* __restrict__ src, const double* __restrict__ Pv,
+                              const unsigned long long* __restrict__ Pm, double* __restrict__ Rv,
+                              unsigned long long* __restrict__ Rm) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nb) return;
+  const int64_t q = (int64_t)src[t];
+  const int bb = pr * pc;
+  const unsigned long long m = Pm[q];
+  unsigned long long rm = 0;
+  for (int r = 0; r < pr; ++r)
+    for (int c = 0; c < pc; ++c) {
+      Rv[t * bb + c * pr + r] = Pv[q * bb + r * pc + c];
+      if ((m >> (r * pc + c)) & 1ull) rm |= 1ull << (c * pr + r);
+    }
+  Rm[t] = rm;
+}
+
+void bsr_transpose(const DBsr& P, DBsr& R, hipStream_t s) {
+  R.br = P.bc;
+  R.bc = P.br;
+  transpose(P.pat, R.pat, s);
+  const int64_t nb = R.pat.nnz > 0 ? R.pat.nnz : 1;
+  R.val.alloc(nb * R.br * R.bc);
+  R.mask.alloc(nb);
+  if (R.pat.nnz > 0)
+    hipLaunchKernelGGL(k_bsr_tblocks, dim3(cdiv(R.pat.nnz, 256)), dim3(256), 0, s, R.pat.nnz, P.br, P.bc, R.pat.val.p,
+                       P.val.p, P.mask.p, R.val.p, R.mask.p);
+  // the pattern values of a converted matrix are block indices
+  if (R.pat.nnz > 0) iota(R.pat.val.p, R.pat.nnz, s);
 }
 
 void spgemm_blocked(const DCsr& A, int br, int bk, const DCsr& B, int bc, DCsr& C, hipStream_t s) {

@@ -985,20 +985,92 @@ __global__ __launch_bounds__(1024) void k_color_frontier(const int* __restrict__
   if (threadIdx.x == 0) *done = coloured;
 }
 
+// The same schedule with the wait counters (one byte each, packed four to a
+// word for LDS atomics) and the colours (one byte each) of every node in LDS,
+// for graphs of up to COLOR_LDS_NODES nodes with at most 255 smaller
+// neighbours per node.
+constexpr int COLOR_LDS_NODES = 73728;
+
+__global__ __launch_bounds__(1024) void k_color_frontier_lds(int n, const int* __restrict__ gp, const int* __restrict__ ga,
+                                                             const int* __restrict__ rptr, const int* __restrict__ radj,
+                                                             int* color, const int* __restrict__ wait, int* fa, int* fb,
+                                                             const int* nfront0, int* err, int* done) {
+  __shared__ unsigned int wt[COLOR_LDS_NODES / 4];
+  __shared__ unsigned char cl[COLOR_LDS_NODES];
+  __shared__ int nf_cur, nf_next;
+  for (int w = threadIdx.x; w < (n + 3) / 4; w += 1024) {
+    unsigned int x = 0;
+    for (int k = 0; k < 4; ++k)
+      if (4 * w + k < n) x |= (unsigned int)wait[4 * w + k] << (8 * k);
+    wt[w] = x;
+  }
+  if (threadIdx.x == 0) { nf_cur = *nfront0; nf_next = 0; }
+  __syncthreads();
+  int* cur = fa;
+  int* nxt = fb;
+  int coloured = 0;
+  while (true) {
+    const int m = nf_cur;
+    if (m == 0) break;
+    for (int i = threadIdx.x; i < m; i += 1024) {
+      const int u = cur[i];
+      uint64_t mask[4] = {0, 0, 0, 0};
+      for (int p = gp[u]; p < gp[u + 1]; ++p) {
+        const int v = ga[p];
+        if (v >= u) continue;
+        const int c = cl[v];
+        mask[c >> 6] |= 1ull << (c & 63);
+      }
+      int c = -1;
+      for (int w = 0; w < 4 && c < 0; ++w)
+        if (~mask[w]) c = w * 64 + __builtin_ctzll(~mask[w]);
+      if (c < 0) { atomicOr(err, 1); c = 0; }
+      cl[u] = (unsigned char)c;
+      for (int p = rptr[u]; p < rptr[u + 1]; ++p) {
+        const int w = radj[p];
+        const int sh = 8 * (w & 3);
+        const unsigned int old = atomicSub(&wt[w >> 2], 1u << sh);
+        if (((old >> sh) & 0xffu) == 1u) nxt[atomicAdd(&nf_next, 1)] = w;
+      }
+    }
+    coloured += m;
+    __syncthreads();
+    if (threadIdx.x == 0) { nf_cur = nf_next; nf_next = 0; }
+    __syncthreads();
+    int* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (int v = threadIdx.x; v < n; v += 1024) color[v] = cl[v];
+  if (threadIdx.x == 0) *done = coloured;
+}
+
+__global__ void k_max_wait(int n, const int* __restrict__ wait, int* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) atomicMax(out, wait[i]);
+}
+
 int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* color, hipStream_t s) {
   if (n == 0) return 0;
   const int g = cdiv(n, 256);
-  DBuf<int> wait(n), fa(n), fb(n), cnt(4), rcnt(n + 1), rptr(n + 1), rcur(n + 1);
+  DBuf<int> wait(n), fa(n), fb(n), cnt(5), rcnt(n + 1), rptr(n + 1), rcur(n + 1);
   fill<int>(color, -1, n, s);
-  fill<int>(cnt.p, 0, 4, s);
+  fill<int>(cnt.p, 0, 5, s);
   fill<int>(rcnt.p, 0, n + 1, s);
   fill<int>(rcur.p, 0, n + 1, s);
   hipLaunchKernelGGL(k_color_wait, dim3(g), dim3(256), 0, s, n, gp, ga, wait.p, rcnt.p, fa.p, cnt.p);
-  const int64_t nr = exclusive_scan(rcnt.p, rptr.p, n, s);
+  hipLaunchKernelGGL(k_max_wait, dim3(g), dim3(256), 0, s, n, wait.p, cnt.p + 4);
+  int maxwait = 0;
+  NF_HIP(hipMemcpyAsync(&maxwait, cnt.p + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+  const int64_t nr = exclusive_scan(rcnt.p, rptr.p, n, s);   // synchronises: maxwait is on the host
   DBuf<int> radj(nr > 0 ? nr : 1);
   hipLaunchKernelGGL(k_color_rev, dim3(g), dim3(256), 0, s, n, gp, ga, rptr.p, rcur.p, radj.p);
-  hipLaunchKernelGGL(k_color_frontier, dim3(1), dim3(1024), 0, s, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p, cnt.p,
-                     cnt.p + 1, cnt.p + 2);
+  if (n <= COLOR_LDS_NODES && maxwait <= 255)
+    hipLaunchKernelGGL(k_color_frontier_lds, dim3(1), dim3(1024), 0, s, n, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p,
+                       cnt.p, cnt.p + 1, cnt.p + 2);
+  else
+    hipLaunchKernelGGL(k_color_frontier, dim3(1), dim3(1024), 0, s, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p,
+                       cnt.p, cnt.p + 1, cnt.p + 2);
   hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p + 3);
   int h[4];
   NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -157,7 +157,8 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
 // smoothed prolongator in place on AP = A * P_tent: AP <- P_tent + s .* AP
 void smooth_prolongator(DCsr& AP, const double* srow, const DCsr& Pt, int b, int k, const int* agg, hipStream_t s);
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
-// node-blocked matrix: block pattern (pat.val unused), br x bc values per
+// node-blocked matrix: block pattern (pat.val: block indices for a converted
+// or transposed matrix, unused otherwise), br x bc values per
 // block (row-major, zero where nothing is stored) and a mask of the stored
 // entries (bit r bc + c)
 struct DBsr {
@@ -168,6 +169,8 @@ struct DBsr {
 };
 void csr_to_bsr(const DCsr& A, int br, int bc, DBsr& B, hipStream_t s);
 void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s);
+// R = P^T (P converted by csr_to_bsr)
+void bsr_transpose(const DBsr& P, DBsr& R, hipStream_t s);
 // C = A B block by block (A.bc == B.br); same pattern and bits as spgemm on
 // the scalar matrices
 void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s);
