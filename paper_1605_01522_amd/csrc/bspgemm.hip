@@ -163,34 +163,57 @@ void csr_to_bsr(const DCsr& A, int br, int bc, DBsr& B, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ blocks -> CSR
-// one thread per scalar row: pass 0 counts its stored entries, pass 1 writes
-// them in ascending column (blocks ascending, then columns inside the block)
-template <int PASS>
+// G lanes per scalar row (G divides 64): the lanes take G blocks of the block
+// row at a time, count their stored entries in this row, and (pass 1) write
+// them at offsets from a scan across the lanes, so the row comes out in
+// ascending column (blocks ascending, then columns inside the block); pass 0
+// writes the row's count
+template <int G, int PASS>
 __global__ void k_bsr_rows(int nr, int br, int bc, const int* __restrict__ bptr, const int* __restrict__ bcol,
                            const double* __restrict__ bval, const unsigned long long* __restrict__ bmask,
                            int* __restrict__ cnt, const int* __restrict__ ptr, int* __restrict__ col,
                            double* __restrict__ val) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = (int)(gid / G), lane = (int)(gid % G);
   if (r >= nr) return;
   const int i = r / br, q = r - i * br, bb = br * bc;
-  const unsigned long long rowbits = ((bc == 64 ? 0ull : (1ull << bc)) - 1ull) << (q * bc);
+  const unsigned long long rowbits = ((1ull << bc) - 1ull) << (q * bc);
   int n = 0;
   const int o = PASS ? ptr[r] : 0;
-  for (int p = bptr[i]; p < bptr[i + 1]; ++p) {
-    const unsigned long long m = bmask[p] & rowbits;
-    if (!m) continue;
-    if (!PASS) {
-      n += __popcll(m);
-      continue;
+  const int p1 = bptr[i + 1];
+  for (int p0 = bptr[i]; p0 < p1; p0 += G) {
+    const int p = p0 + lane;
+    const unsigned long long m = p < p1 ? (bmask[p] & rowbits) : 0ull;
+    const int k = __popcll(m);
+    int incl = k;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const int t = __shfl_up(incl, d, G);
+      if (lane >= d) incl += t;
     }
-    for (int c = 0; c < bc; ++c)
-      if ((m >> (q * bc + c)) & 1ull) {
-        col[o + n] = bcol[p] * bc + c;
-        val[o + n] = bval[(int64_t)p * bb + q * bc + c];
-        ++n;
-      }
+    if (PASS && m) {
+      int w = o + n + incl - k;
+      for (int c = 0; c < bc; ++c)
+        if ((m >> (q * bc + c)) & 1ull) {
+          col[w] = bcol[p] * bc + c;
+          val[w] = bval[(int64_t)p * bb + q * bc + c];
+          ++w;
+        }
+    }
+    n += __shfl(incl, G - 1, G);
   }
-  if (!PASS) cnt[r] = n;
+  if (!PASS && lane == 0) cnt[r] = n;
+}
+
+template <int G>
+static void bsr_rows(const DBsr& B, DCsr& A, int pass, const int* cnt_or_ptr, hipStream_t s) {
+  const int blocks = cdiv((int64_t)A.nr * G, 256);
+  if (pass == 0)
+    hipLaunchKernelGGL((k_bsr_rows<G, 0>), dim3(blocks), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
+                       B.val.p, B.mask.p, (int*)cnt_or_ptr, (const int*)nullptr, (int*)nullptr, (double*)nullptr);
+  else
+    hipLaunchKernelGGL((k_bsr_rows<G, 1>), dim3(blocks), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
+                       B.val.p, B.mask.p, (int*)nullptr, cnt_or_ptr, A.col.p, A.val.p);
 }
 
 void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s) {
@@ -198,15 +221,26 @@ void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s) {
   A.nc = B.pat.nc * B.bc;
   A.ptr.alloc(A.nr + 1);
   DBuf<int> cnt(A.nr + 1);
-  if (A.nr > 0)
-    hipLaunchKernelGGL(k_bsr_rows<0>, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
-                       B.val.p, B.mask.p, cnt.p, (const int*)nullptr, (int*)nullptr, (double*)nullptr);
-  A.nnz = exclusive_scan(cnt.p, A.ptr.p, A.nr, s);
-  A.col.alloc(A.nnz > 0 ? A.nnz : 1);
-  A.val.alloc(A.nnz > 0 ? A.nnz : 1);
-  if (A.nr > 0 && A.nnz > 0)
-    hipLaunchKernelGGL(k_bsr_rows<1>, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, B.br, B.bc, B.pat.ptr.p, B.pat.col.p,
-                       B.val.p, B.mask.p, (int*)nullptr, A.ptr.p, A.col.p, A.val.p);
+  // lanes per row: the average blocks per block row, a power of two in [4, 64]
+  const int64_t avg = B.pat.nr > 0 ? B.pat.nnz / B.pat.nr : 0;
+  const int G = avg > 32 ? 64 : avg > 16 ? 32 : avg > 8 ? 16 : avg > 4 ? 8 : 4;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      A.nnz = exclusive_scan(cnt.p, A.ptr.p, A.nr, s);
+      A.col.alloc(A.nnz > 0 ? A.nnz : 1);
+      A.val.alloc(A.nnz > 0 ? A.nnz : 1);
+      if (A.nnz == 0) break;
+    }
+    if (A.nr == 0) continue;
+    const int* arg = pass == 0 ? cnt.p : A.ptr.p;
+    switch (G) {
+      case 4: bsr_rows<4>(B, A, pass, arg, s); break;
+      case 8: bsr_rows<8>(B, A, pass, arg, s); break;
+      case 16: bsr_rows<16>(B, A, pass, arg, s); break;
+      case 32: bsr_rows<32>(B, A, pass, arg, s); break;
+      default: bsr_rows<64>(B, A, pass, arg, s); break;
+    }
+  }
 }
 
 // ------------------------------------------------------------ numeric product

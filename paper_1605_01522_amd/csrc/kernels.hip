@@ -942,95 +942,82 @@ __global__ void k_color_rev(int n, const int* __restrict__ gp, const int* __rest
     if (v < w) radj[rptr[v] + atomicAdd(&rcur[v], 1)] = w;
   }
 }
-__global__ __launch_bounds__(1024) void k_color_frontier(const int* __restrict__ gp, const int* __restrict__ ga,
-                                                         const int* __restrict__ rptr, const int* __restrict__ radj, int* color,
-                                                         int* wait, int* fa, int* fb, const int* nfront0, int* err,
-                                                         int* done) {
-  __shared__ int nf_cur, nf_next;
-  if (threadIdx.x == 0) { nf_cur = *nfront0; nf_next = 0; }
-  __syncthreads();
-  int* cur = fa;
-  int* nxt = fb;
-  int coloured = 0;
-  while (true) {
-    const int m = nf_cur;
-    if (m == 0) break;
-    for (int i = threadIdx.x; i < m; i += 1024) {
-      const int u = cur[i];
-      uint64_t mask[4] = {0, 0, 0, 0};
-      for (int p = gp[u]; p < gp[u + 1]; ++p) {
-        const int v = ga[p];
-        if (v >= u) continue;
-        const int c = __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (c >= 0 && c < 256) mask[c >> 6] |= 1ull << (c & 63);
-      }
-      int c = -1;
-      for (int w = 0; w < 4 && c < 0; ++w)
-        if (~mask[w]) c = w * 64 + __builtin_ctzll(~mask[w]);
-      if (c < 0) { atomicOr(err, 1); c = 0; }
-      __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      for (int p = rptr[u]; p < rptr[u + 1]; ++p) {
-        const int w = radj[p];
-        if (atomicSub(&wait[w], 1) == 1) nxt[atomicAdd(&nf_next, 1)] = w;
-      }
-    }
-    coloured += m;
-    __syncthreads();
-    if (threadIdx.x == 0) { nf_cur = nf_next; nf_next = 0; }
-    __syncthreads();
-    int* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  if (threadIdx.x == 0) *done = coloured;
-}
-
-// The same schedule with the wait counters (one byte each, packed four to a
-// word for LDS atomics) and the colours (one byte each) of every node in LDS,
-// for graphs of up to COLOR_LDS_NODES nodes with at most 255 smaller
-// neighbours per node.
+// Eight lanes per frontier node: the lanes split the node's neighbour list
+// (its smaller neighbours' colours are or-ed into one mask across the eight)
+// and the list of nodes waiting on it (their counters are released in
+// parallel).  With LDS, the wait counters (one byte each, packed four to a
+// word for LDS atomics) and the colours (one byte each) of every node live in
+// LDS, for graphs of up to COLOR_LDS_NODES nodes with at most 255 smaller
+// neighbours per node; otherwise both stay in global memory.
 constexpr int COLOR_LDS_NODES = 73728;
+constexpr int COLOR_LPN = 8;
 
-__global__ __launch_bounds__(1024) void k_color_frontier_lds(int n, const int* __restrict__ gp, const int* __restrict__ ga,
-                                                             const int* __restrict__ rptr, const int* __restrict__ radj,
-                                                             int* color, const int* __restrict__ wait, int* fa, int* fb,
-                                                             const int* nfront0, int* err, int* done) {
-  __shared__ unsigned int wt[COLOR_LDS_NODES / 4];
-  __shared__ unsigned char cl[COLOR_LDS_NODES];
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_color_frontier(int n, const int* __restrict__ gp, const int* __restrict__ ga,
+                                                         const int* __restrict__ rptr, const int* __restrict__ radj,
+                                                         int* color, int* wait, int* fa, int* fb, const int* nfront0,
+                                                         int* err, int* done) {
+  __shared__ unsigned int wt[LDS ? COLOR_LDS_NODES / 4 : 1];
+  __shared__ unsigned char cl[LDS ? COLOR_LDS_NODES : 1];
   __shared__ int nf_cur, nf_next;
-  for (int w = threadIdx.x; w < (n + 3) / 4; w += 1024) {
-    unsigned int x = 0;
-    for (int k = 0; k < 4; ++k)
-      if (4 * w + k < n) x |= (unsigned int)wait[4 * w + k] << (8 * k);
-    wt[w] = x;
-  }
+  if (LDS)
+    for (int w = threadIdx.x; w < (n + 3) / 4; w += 1024) {
+      unsigned int x = 0;
+      for (int k = 0; k < 4; ++k)
+        if (4 * w + k < n) x |= (unsigned int)wait[4 * w + k] << (8 * k);
+      wt[w] = x;
+    }
   if (threadIdx.x == 0) { nf_cur = *nfront0; nf_next = 0; }
   __syncthreads();
+  const int grp = threadIdx.x / COLOR_LPN, sub = threadIdx.x % COLOR_LPN;
+  constexpr int NGRP = 1024 / COLOR_LPN;
   int* cur = fa;
   int* nxt = fb;
   int coloured = 0;
   while (true) {
     const int m = nf_cur;
     if (m == 0) break;
-    for (int i = threadIdx.x; i < m; i += 1024) {
-      const int u = cur[i];
+    // every group runs the same number of passes (the shuffles need all lanes)
+    for (int i0 = 0; i0 < m; i0 += NGRP) {
+      const int i = i0 + grp;
+      const int u = i < m ? cur[i] : -1;
       uint64_t mask[4] = {0, 0, 0, 0};
-      for (int p = gp[u]; p < gp[u + 1]; ++p) {
-        const int v = ga[p];
-        if (v >= u) continue;
-        const int c = cl[v];
-        mask[c >> 6] |= 1ull << (c & 63);
-      }
+      if (u >= 0)
+        for (int p = gp[u] + sub; p < gp[u + 1]; p += COLOR_LPN) {
+          const int v = ga[p];
+          if (v >= u) continue;
+          const int c = LDS ? (int)cl[v] : __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (c >= 0 && c < 256) mask[c >> 6] |= 1ull << (c & 63);
+        }
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int o = COLOR_LPN / 2; o > 0; o >>= 1) mask[w] |= __shfl_xor(mask[w], o, COLOR_LPN);
+      if (u < 0) continue;
       int c = -1;
       for (int w = 0; w < 4 && c < 0; ++w)
         if (~mask[w]) c = w * 64 + __builtin_ctzll(~mask[w]);
-      if (c < 0) { atomicOr(err, 1); c = 0; }
-      cl[u] = (unsigned char)c;
-      for (int p = rptr[u]; p < rptr[u + 1]; ++p) {
+      if (c < 0) {
+        if (sub == 0) atomicOr(err, 1);
+        c = 0;
+      }
+      if (sub == 0) {
+        if (LDS) cl[u] = (unsigned char)c;
+        else __hip_atomic_store(&color[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      // the colour is stored before any waiting node can be released
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      for (int p = rptr[u] + sub; p < rptr[u + 1]; p += COLOR_LPN) {
         const int w = radj[p];
-        const int sh = 8 * (w & 3);
-        const unsigned int old = atomicSub(&wt[w >> 2], 1u << sh);
-        if (((old >> sh) & 0xffu) == 1u) nxt[atomicAdd(&nf_next, 1)] = w;
+        bool last;
+        if (LDS) {
+          const int sh = 8 * (w & 3);
+          last = ((atomicSub(&wt[w >> 2], 1u << sh) >> sh) & 0xffu) == 1u;
+        } else {
+          last = atomicSub(&wait[w], 1) == 1;
+        }
+        if (last) nxt[atomicAdd(&nf_next, 1)] = w;
       }
     }
     coloured += m;
@@ -1041,7 +1028,8 @@ __global__ __launch_bounds__(1024) void k_color_frontier_lds(int n, const int* _
     cur = nxt;
     nxt = t;
   }
-  for (int v = threadIdx.x; v < n; v += 1024) color[v] = cl[v];
+  if (LDS)
+    for (int v = threadIdx.x; v < n; v += 1024) color[v] = cl[v];
   if (threadIdx.x == 0) *done = coloured;
 }
 
@@ -1066,11 +1054,11 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
   DBuf<int> radj(nr > 0 ? nr : 1);
   hipLaunchKernelGGL(k_color_rev, dim3(g), dim3(256), 0, s, n, gp, ga, rptr.p, rcur.p, radj.p);
   if (n <= COLOR_LDS_NODES && maxwait <= 255)
-    hipLaunchKernelGGL(k_color_frontier_lds, dim3(1), dim3(1024), 0, s, n, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p,
-                       cnt.p, cnt.p + 1, cnt.p + 2);
+    hipLaunchKernelGGL(k_color_frontier<true>, dim3(1), dim3(1024), 0, s, n, gp, ga, rptr.p, radj.p, color, wait.p, fa.p,
+                       fb.p, cnt.p, cnt.p + 1, cnt.p + 2);
   else
-    hipLaunchKernelGGL(k_color_frontier, dim3(1), dim3(1024), 0, s, gp, ga, rptr.p, radj.p, color, wait.p, fa.p, fb.p,
-                       cnt.p, cnt.p + 1, cnt.p + 2);
+    hipLaunchKernelGGL(k_color_frontier<false>, dim3(1), dim3(1024), 0, s, n, gp, ga, rptr.p, radj.p, color, wait.p, fa.p,
+                       fb.p, cnt.p, cnt.p + 1, cnt.p + 2);
   hipLaunchKernelGGL(k_max_int, dim3(g), dim3(256), 0, s, color, n, cnt.p + 3);
   int h[4];
   NF_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
