@@ -59,7 +59,7 @@ def kernel_source_digest():
         return s[i:s.index(b, i)]
     text = seg("template <int G, int NR, class T>\n__device__ __forceinline__ void row_dot(",
                "template <int G, int MODE, int NR, class T>") + \
-        seg("template <int G, int B2, int NR, class T>\n__device__ __forceinline__ void sgs_node(",
+        seg("template <int NR, class T>\n__device__ __forceinline__ void sgs_row_load(",
             "// A whole sweep over every colour of a small level")
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 

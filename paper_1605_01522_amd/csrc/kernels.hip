@@ -285,13 +285,16 @@ int spmv_group(int nr, int64_t nnz) {
   while (g * 2 <= avg && g < 64) g *= 2;
   return g < 2 ? 2 : g;
 }
-// SpMV rows: two to four entries per lane, so that the unrolled loads of a
-// row are spread over fewer lanes and more rows share a wavefront
+// SpMV rows: two to four entries per lane; four to eight on rows of 64 or
+// more entries when that still leaves at least 16,384 wavefronts (measured:
+// large matrices with long rows gain from the fewer wavefronts, short rows
+// and small matrices lose)
 int spmv_lanes(int nr, int64_t nnz) {
   if (nr <= 0) return 2;
   const double avg = (double)nnz / nr;
   int g = 1;
   while (g * 4 <= avg && g < 64) g *= 2;
+  if (avg >= 64 && g > 2 && (int64_t)nr * (g / 2) >= (int64_t)64 * 16384) g /= 2;
   return g < 2 ? 2 : g;
 }
 
