@@ -333,12 +333,27 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
         const int qo = it / bb, rc = it - qo * bb, r = rc / bc, c = rc - r * bc;
         int jb;
         unsigned long long bm;
+        double x[8], y[8];
+        // every operand is fetched at once (stored or not), then used where
+        // both entries are stored
         if (staged) {
           jb = sc[b][qo];
           bm = sm[b][qo];
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k < bk) {
+              x[k] = sa[b][r * bk + k];
+              y[k] = sv[b][qo * kbc + k * bc + c];
+            }
         } else {
           jb = Bc[q0 + qo];
           bm = Bm[q0 + qo];
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k < bk) {
+              x[k] = avp[r * bk + k];
+              y[k] = Bv[(int64_t)(q0 + qo) * kbc + k * bc + c];
+            }
         }
         int lo = 0, hi = ncb;
         while (lo < hi) {
@@ -348,11 +363,10 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
         const int e = lo * bb + rc;
         double a = acc[e];
         bool any = false;
-        for (int k = 0; k < bk; ++k)
-          if (((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
-            const double x = staged ? sa[b][r * bk + k] : avp[r * bk + k];
-            const double y = staged ? sv[b][qo * kbc + k * bc + c] : Bv[(int64_t)(q0 + qo) * kbc + k * bc + c];
-            a += x * y;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < bk && ((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
+            a += x[k] * y[k];
             any = true;
           }
         if (any) {
