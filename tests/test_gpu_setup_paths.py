@@ -1,0 +1,133 @@
+"""Setup paths that the physics workloads at test size do not reach, against
+the oracle: block products whose output rows overflow the LDS passes (and the
+register-owned fallback beyond them), and the greedy colouring with its
+counters in global memory (more nodes than the LDS variant holds, or a node
+with more than 255 smaller neighbours)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import nfgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _grid_plus_random(n, b, extra, seed):
+    """Node graph: 27-point stencil on an n^3 grid plus `extra` random
+    long-range neighbours per node (symmetrised); b dofs per node with dense
+    blocks, symmetric and strictly diagonally dominant (SPD)."""
+    rng = np.random.default_rng(seed)
+    N = n ** 3
+    ijk = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    rows, cols = [], []
+    for d in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1], indexing="ij")).reshape(3, -1).T:
+        if not d.any():
+            continue
+        nb = ijk + d
+        ok = np.all((nb >= 0) & (nb < n), axis=1)
+        rows.append(np.nonzero(ok)[0])
+        cols.append(np.ravel_multi_index(nb[ok].T, (n, n, n)))
+    r = np.repeat(np.arange(N), extra)
+    c = rng.integers(0, N, N * extra)
+    keep = r != c
+    rows.append(r[keep])
+    cols.append(c[keep])
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    G = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(N, N)).tocsr()
+    G = ((G + G.T) > 0).astype(np.float64).tocoo()
+    # dense b x b blocks with small random entries on every edge
+    bi = np.repeat(G.row * b, b * b) + np.tile(np.repeat(np.arange(b), b), G.nnz)
+    bj = np.repeat(G.col * b, b * b) + np.tile(np.tile(np.arange(b), b), G.nnz)
+    v = -rng.uniform(0.0, 1.0, bi.size)
+    A = sp.coo_matrix((v, (bi, bj)), shape=(N * b, N * b)).tocsr()
+    A = (A + A.T) * 0.5
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = A.tocsr()
+    A.sort_indices()
+    ns = np.zeros((b, N * b))
+    for c_ in range(b):
+        ns[c_, c_::b] = 1.0
+    return A, ns
+
+
+def _lap2d(m):
+    T = sp.diags([-1.0, 2.0, -1.0], [-1, 0, 1], shape=(m, m))
+    I = sp.identity(m)
+    A = (sp.kron(T, I) + sp.kron(I, T)).tocsr()
+    A.sort_indices()
+    return A
+
+
+def _system(A, b, ns):
+    f = nfgen.Field("f", A.shape[0], b, ns)
+    rhs = np.random.default_rng(1).uniform(-1, 1, (1, A.shape[0]))
+    return nfgen.BlockSystem([f], [[A]], rhs)
+
+
+def _compare(s, spec, tol=1e-10, **opts):
+    from paper_1605_01522_amd import NField
+    dev = torch.device("cuda:0")
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = NField(s.fields, s.blocks, spec, **opts)
+    assert g.nlevels(0) == o.nlevels(0)
+    for l in range(o.nlevels(0)):
+        assert g.level_size(0, l, 0) == o.level_size(0, l, 0)
+    r = np.random.default_rng(7).standard_normal((2, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= tol * np.linalg.norm(zo[k]), k
+    return g
+
+
+@pytest.mark.parametrize("n,b", [(21, 4), (15, 8)])
+def test_block_products_long_rows(n, b):
+    """n^3 nodes of b dofs with random long-range couplings.  b = 4: 9,261
+    fine A P rows, all beyond the 512-value pass, within the 2,048-value one;
+    b = 8: almost every A P and every R (A P) row beyond 2,048 values (the
+    register-owned fallback)."""
+    _say(f"case block products, long rows, n={n} b={b}")
+    from paper_1605_01522_amd import NField
+    A, ns = _grid_plus_random(n, b, 3, seed=5)
+    s = _system(A, b, ns)
+    g = _compare(s, "AMG", coarse_max=64)
+    sca = NField(s.fields, s.blocks, "AMG", coarse_max=64, block_products=0)
+    r = torch.tensor(np.random.default_rng(9).standard_normal((1, s.n)), device=torch.device("cuda:0"))
+    assert np.array_equal(g.precond_apply(r).cpu().numpy(), sca.precond_apply(r).cpu().numpy())
+    g.close()
+    sca.close()
+
+
+def test_coloring_many_nodes():
+    """84,100 nodes: the colouring keeps its counters in global memory."""
+    _say("case colouring, 84,100 nodes")
+    A = _lap2d(290)
+    s = _system(A, 1, np.ones((1, A.shape[0])))
+    _compare(s, "AMG[smoother=sgs]").close()
+
+
+def test_coloring_wide_node():
+    """A node coupled to 300 smaller nodes: more than a byte counter holds."""
+    _say("case colouring, node with 300 smaller neighbours")
+    m = 40
+    L = _lap2d(m).tolil()
+    n = m * m + 1
+    A = sp.lil_matrix((n, n))
+    A[: n - 1, : n - 1] = L
+    idx = np.random.default_rng(3).choice(n - 1, 300, replace=False)
+    for i in idx:
+        A[n - 1, i] = A[i, n - 1] = -0.01
+        A[i, i] += 0.01
+    A[n - 1, n - 1] = 300 * 0.01 + 1.0
+    A = A.tocsr()
+    A.sort_indices()
+    s = _system(A, 1, np.ones((1, n)))
+    _compare(s, "AMG[smoother=sgs]", coarse_max=50).close()
