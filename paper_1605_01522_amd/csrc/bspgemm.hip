@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
   }
 }
 
-// Block rows too long for LDS: the listed rows, one wavefront each, every
+// Block rows too long for LDS (more than 8,192 values): the listed rows, one wavefront each, every
 // lane owning output entries (each block padded to BBP = the next power of
 // two >= br bc, so a block never straddles a 64-lane window) of up to EPL
 // windows at a time and summing their terms over the A blocks in ascending
@@ -509,6 +509,12 @@ void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
   } else {
     n = bsp_pass<256, 2048, true>(nullptr, nbr, A, B, C, ovf1.p, novf.p, s);
     left = ovf1.p;
+  }
+  if (n > 0) {
+    // rows up to 8,192 values: one workgroup per CU (104 KB of LDS)
+    int* out = left == ovf1.p ? ovf2.p : ovf1.p;
+    n = bsp_pass<256, 8192, true>(left, n, A, B, C, out, novf.p, s);
+    left = out;
   }
   if (n > 0) {
     int bbp = 1;

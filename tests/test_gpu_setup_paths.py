@@ -1,6 +1,6 @@
 """Setup paths that the physics workloads at test size do not reach, against
-the oracle: block products whose output rows overflow the LDS passes (and the
-register-owned fallback beyond them), and the greedy colouring with its
+the oracle: block products whose output rows overflow the LDS passes (up to
+the register-owned fallback beyond all of them), and the greedy colouring with its
 counters in global memory (more nodes than the LDS variant holds, or a node
 with more than 255 smaller neighbours)."""
 import numpy as np
@@ -92,8 +92,7 @@ def _compare(s, spec, tol=1e-10, **opts):
 def test_block_products_long_rows(n, b):
     """n^3 nodes of b dofs with random long-range couplings.  b = 4: 9,261
     fine A P rows, all beyond the 512-value pass, within the 2,048-value one;
-    b = 8: almost every A P and every R (A P) row beyond 2,048 values (the
-    register-owned fallback)."""
+    b = 8: almost every A P and every R (A P) row beyond 2,048 values."""
     _say(f"case block products, long rows, n={n} b={b}")
     from paper_1605_01522_amd import NField
     A, ns = _grid_plus_random(n, b, 3, seed=5)
@@ -102,6 +101,48 @@ def test_block_products_long_rows(n, b):
     sca = NField(s.fields, s.blocks, "AMG", coarse_max=64, block_products=0)
     r = torch.tensor(np.random.default_rng(9).standard_normal((1, s.n)), device=torch.device("cuda:0"))
     assert np.array_equal(g.precond_apply(r).cpu().numpy(), sca.precond_apply(r).cpu().numpy())
+    g.close()
+    sca.close()
+
+
+def test_block_products_beyond_lds():
+    """Monolithic AMG over a coarsened scalar field and a dense field of 150
+    nodes x 8 dofs that is not coarsened (P = I): its Galerkin block keeps
+    rows of 150 blocks of 8 x 8 (9,600 values), beyond every LDS pass."""
+    _say("case block products beyond LDS (dense uncoarsened field)")
+    from paper_1605_01522_amd import NField
+    rng = np.random.default_rng(11)
+    m = 20
+    T = sp.diags([-1.0, 2.0, -1.0], [-1, 0, 1], shape=(m, m))
+    I = sp.identity(m)
+    A0 = (sp.kron(sp.kron(T, I), I) + sp.kron(sp.kron(I, T), I) + sp.kron(sp.kron(I, I), T)).tocsr()
+    A0.sort_indices()
+    n1 = 150 * 8
+    M = rng.uniform(-1.0, 1.0, (n1, n1))
+    M = (M + M.T) * 0.5
+    M += np.diag(np.abs(M).sum(axis=1) + 1.0)
+    A1 = sp.csr_matrix(M)
+    A1.sort_indices()
+    ns1 = np.zeros((8, n1))
+    for c in range(8):
+        ns1[c, c::8] = 1.0
+    f0 = nfgen.Field("a", A0.shape[0], 1, np.ones((1, A0.shape[0])))
+    f1 = nfgen.Field("b", n1, 8, ns1)
+    rhs = rng.uniform(-1, 1, (1, A0.shape[0] + n1))
+    s = nfgen.BlockSystem([f0, f1], [[A0, None], [None, A1]], rhs)
+    opts = dict(coarse_max=1500)
+    dev = torch.device("cuda:0")
+    o = oracle.Oracle(s.fields, s.blocks, "AMG(BGS)", **opts)
+    g = NField(s.fields, s.blocks, "AMG(BGS)", **opts)
+    sca = NField(s.fields, s.blocks, "AMG(BGS)", block_products=0, **opts)
+    assert g.nlevels(0) == o.nlevels(0) >= 2
+    r = np.random.default_rng(7).standard_normal((2, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    zs = sca.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.array_equal(zg, zs)
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k]), k
     g.close()
     sca.close()
 
