@@ -130,6 +130,9 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
   while (true) {
     const int l = (int)H.lev.size() - 1;
     Level& L = H.lev[l];
+    L.gptr.assign(N, nullptr);
+    L.gadj.assign(N, nullptr);
+    L.nnode.assign(N, 0);
     L.lambda.assign(N, 0.0);
     L.dinv.resize(N);
     for (int i = 0; i < N; ++i) {
@@ -181,11 +184,15 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         NF_CHECK(L.lambda[i] > 0.0, NFIELD_ESINGULAR, "AMG: diagonal block has a zero diagonal entry");
         const int k = L.B[i] ? (int)(L.B[i]->n / n) : 0;
         NF_CHECK(k >= 1, NFIELD_EINVAL, "AMG: field has no near-nullspace vectors");
-        DBuf<int> gptr, gadj;
+        auto gptr = std::make_shared<DBuf<int>>(), gadj = std::make_shared<DBuf<int>>();
         int nnode = 0;
-        node_graph(Aii, L.bs[i], gptr, gadj, &nnode, s);
+        node_graph(Aii, L.bs[i], *gptr, *gadj, &nnode, s);
         auto agg = std::make_shared<DBuf<int>>(nnode > 0 ? nnode : 1);
-        const int na = mis2_aggregate(nnode, gptr.p, gadj.p, o.seed, agg->p, s);
+        const int na = mis2_aggregate(nnode, gptr->p, gadj->p, o.seed, agg->p, s);
+        // kept for the level's Gauss-Seidel colouring
+        L.gptr[i] = gptr;
+        L.gadj[i] = gadj;
+        L.nnode[i] = nnode;
         DCsr Pt;
         auto Bc = std::make_shared<DBuf<double>>();
         auto dead = std::make_shared<DBuf<int>>();

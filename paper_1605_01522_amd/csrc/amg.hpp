@@ -62,6 +62,9 @@ struct Level {
   std::vector<std::shared_ptr<DBuf<double>>> dinv;  // per field D^-1 (null if no diagonal)
   std::vector<std::shared_ptr<DBuf<int>>> dead;
   std::vector<int> ndead;
+  // per field node graph of A_ii (from aggregation; null where not built)
+  std::vector<std::shared_ptr<DBuf<int>>> gptr, gadj;
+  std::vector<int> nnode;
 };
 
 struct Hierarchy {

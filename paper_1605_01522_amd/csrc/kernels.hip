@@ -945,15 +945,15 @@ __global__ void k_color_rev(int n, const int* __restrict__ gp, const int* __rest
     if (v < w) radj[rptr[v] + atomicAdd(&rcur[v], 1)] = w;
   }
 }
-// Eight lanes per frontier node: the lanes split the node's neighbour list
-// (its smaller neighbours' colours are or-ed into one mask across the eight)
+// Four lanes per frontier node: the lanes split the node's neighbour list
+// (its smaller neighbours' colours are or-ed into one mask across the four)
 // and the list of nodes waiting on it (their counters are released in
 // parallel).  With LDS, the wait counters (one byte each, packed four to a
 // word for LDS atomics) and the colours (one byte each) of every node live in
 // LDS, for graphs of up to COLOR_LDS_NODES nodes with at most 255 smaller
 // neighbours per node; otherwise both stay in global memory.
 constexpr int COLOR_LDS_NODES = 73728;
-constexpr int COLOR_LPN = 8;
+constexpr int COLOR_LPN = 4;
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_color_frontier(int n, const int* __restrict__ gp, const int* __restrict__ ga,

@@ -167,7 +167,9 @@ struct SgsD : FieldSmootherD<T> {
   std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
   DBuf<int> off_dev;
   int kind = SGS_COLOR;
-  void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s) {
+  // gp / ga / nn: the node graph of A when the caller already has it
+  void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s,
+             const DBuf<int>* gp = nullptr, const DBuf<int>* ga = nullptr, int nn_given = 0) {
     A = A_;
     b = b_;
     n = A->nr;
@@ -178,9 +180,19 @@ struct SgsD : FieldSmootherD<T> {
     else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
     DBuf<int> gptr, gadj;
     int nn = 0;
-    node_graph(*A, b, gptr, gadj, &nn, s);
+    const int* gpp;
+    const int* gap;
+    if (gp && ga) {
+      nn = nn_given;
+      gpp = gp->p;
+      gap = ga->p;
+    } else {
+      node_graph(*A, b, gptr, gadj, &nn, s);
+      gpp = gptr.p;
+      gap = gadj.p;
+    }
     DBuf<int> color(nn > 0 ? nn : 1);
-    const int nc = color_nodes(nn, gptr.p, gadj.p, seed, color.p, s);
+    const int nc = color_nodes(nn, gpp, gap, seed, color.p, s);
     std::vector<int> hc(nn);
     NF_HIP(hipMemcpyAsync(hc.data(), color.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
@@ -749,7 +761,9 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
       if (sgs) {
         auto g = std::make_unique<SgsD<T>>();
-        g->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s);
+        const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
+        g->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s, have ? L.gptr[i].get() : nullptr,
+                 have ? L.gadj[i].get() : nullptr, have ? L.nnode[i] : 0);
         const int ncol = (int)g->off.size() - 1;
         if (L.A.size[i] <= SGS_DENSE_MAX && ncol >= SGS_DENSE_MIN_COLORS) {
           auto d = std::make_unique<DenseSgsD<T>>();
