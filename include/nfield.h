@@ -110,6 +110,12 @@ typedef struct {
   int32_t block_products;  /* 1 (default): Galerkin products of node-blocked fields are
                               formed block by block (one hash insert per block pair);
                               0: entry by entry.  Same pattern and bits either way. */
+  int32_t parallel_setup;  /* 1 (default): independent parts of the preconditioner (the
+                              fields of BGS, the predictor and Schur parts of SIMPLE)
+                              are set up concurrently, each on a host thread and HIP
+                              stream of the library's own that first waits for the
+                              caller's stream (which then waits for them); 0: one after
+                              another on the caller's stream.  Same bits either way. */
 } nfield_opts;
 
 typedef struct {

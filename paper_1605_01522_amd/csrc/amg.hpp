@@ -18,6 +18,7 @@ struct Opts {
   uint64_t seed = 0;
   int graphs = 0;
   int block_products = 1;
+  int parallel_setup = 1;
 };
 
 // N x N grid of device blocks over fields [0, N); a null block is zero.

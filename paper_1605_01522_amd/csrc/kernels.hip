@@ -350,6 +350,10 @@ void prof_enable(int on) {
 }
 
 bool prof_recording() { return g_prof.on; }
+// launches of a thread set quiet are not timed (threads that set up parts of
+// the preconditioner concurrently)
+static thread_local bool g_prof_quiet = false;
+void prof_quiet(bool q) { g_prof_quiet = q; }
 
 int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes) {
   std::vector<int> keys;
@@ -377,7 +381,7 @@ int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes) {
 }
 
 int prof_begin(hipStream_t s) {
-  if (!g_prof.on || g_prof.used >= g_prof.ev.size() / 2) return -1;
+  if (!g_prof.on || g_prof_quiet || g_prof.used >= g_prof.ev.size() / 2) return -1;
   NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   return (int)g_prof.used;
 }
@@ -403,7 +407,7 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
   if (A.nr <= 0) return;
   const T* val = csr_values<T>(A);
   const int G = spmv_lanes(A.nr, A.nnz);
-  const bool timed = g_prof.on && g_prof.used < g_prof.ev.size() / 2;
+  const bool timed = g_prof.on && !g_prof_quiet && g_prof.used < g_prof.ev.size() / 2;
   if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   switch (mode) {
     case SPMV_STORE: spmv_nr<SPMV_STORE, T>(G, A, a, val, s); break;

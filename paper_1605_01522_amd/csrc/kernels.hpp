@@ -58,6 +58,7 @@ int prof_read(int max, int* key, int64_t* count, double* ms, double* bytes);
 int prof_begin(hipStream_t s);
 void prof_end(int slot, hipStream_t s, int key, double bytes, int count = 1);
 bool prof_recording();
+void prof_quiet(bool q);   // this thread's launches untimed
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s);
 
 // ------------------------------------------------------------ reductions (FP64, deterministic)

@@ -13,12 +13,18 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
+#include <mutex>
+#include <exception>
 
 #include "amg.hpp"
 
 namespace nf {
 
 thread_local DevPool* g_pool = nullptr;
+// where this thread's builds leave the hierarchies and blocks they own
+thread_local std::vector<std::unique_ptr<Hierarchy>>* g_hsink = nullptr;
+thread_local std::vector<std::unique_ptr<BlockMat>>* g_osink = nullptr;
 static thread_local std::string g_err;
 
 // ================================================================ helpers
@@ -621,8 +627,25 @@ static void check_spec(const Spec& sp) {
 }  // namespace nf
 
 // ============================================================== context
+// A subtree of the solver built concurrently with its siblings: its own host
+// thread, stream and block cache (kept across rebuilds, so the cache serves
+// the next build of the same subtree).
+struct SideBuild {
+  nf::DevPool pool;
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  ~SideBuild() {
+    pool.trim();
+    if (done) (void)hipEventDestroy(done);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
 struct nfield_ctx {
   nf::DevPool pool;   // first member: destroyed after every buffer it backs
+  std::vector<std::unique_ptr<SideBuild>> side;   // second: after every buffer they back
+  size_t side_next = 0;
+  std::mutex side_mu;   // nested concurrent builds take their side slots under it
   int N = 0;
   std::vector<nf::FieldDev> F;
   nf::BlockMat A;
@@ -663,6 +686,81 @@ struct nfield_ctx {
 };
 
 namespace nf {
+
+// Independent children of a solver node (the fields of BGS, the predictor and
+// Schur parts of SIMPLE) are set up concurrently: one host thread each, on a
+// stream of its own that first waits for everything already queued on s,
+// allocating from the subtree's own block cache; s then waits for every
+// child's stream.  Hierarchies and owned blocks are handed back in child
+// order, so the tree, and every result, is the same as built one by one.
+template <class T>
+using BuildTask = std::function<std::unique_ptr<Solver<T>>(hipStream_t)>;
+
+template <class T>
+static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, const std::vector<BuildTask<T>>& tasks,
+                                                              hipStream_t s) {
+  const size_t n = tasks.size();
+  std::vector<std::unique_ptr<Solver<T>>> out(n);
+  if (n < 2 || !C.o.parallel_setup) {
+    for (size_t k = 0; k < n; ++k) out[k] = tasks[k](s);
+    return out;
+  }
+  int dev = 0;
+  NF_HIP(hipGetDevice(&dev));
+  std::vector<SideBuild*> sb(n);
+  {
+    std::lock_guard<std::mutex> lock(C.side_mu);
+    for (size_t k = 0; k < n; ++k) {
+      if (C.side_next == C.side.size()) {
+        auto b = std::make_unique<SideBuild>();
+        NF_HIP(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+        NF_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        C.side.push_back(std::move(b));
+      }
+      sb[k] = C.side[C.side_next++].get();
+    }
+  }
+  hipEvent_t start;
+  NF_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  NF_HIP(hipEventRecord(start, s));
+  std::vector<std::vector<std::unique_ptr<Hierarchy>>> hs(n);
+  std::vector<std::vector<std::unique_ptr<BlockMat>>> os(n);
+  std::vector<std::exception_ptr> err(n);
+  std::vector<char> ok(n, 0);
+  std::vector<std::thread> th;
+  for (size_t k = 0; k < n; ++k)
+    th.emplace_back([&, k] {
+      try {
+        NF_HIP(hipSetDevice(dev));
+        g_pool = &sb[k]->pool;
+        g_hsink = &hs[k];
+        g_osink = &os[k];
+        prof_quiet(true);
+        sb[k]->pool.enter(sb[k]->st);
+        NF_HIP(hipStreamWaitEvent(sb[k]->st, start, 0));
+        out[k] = tasks[k](sb[k]->st);
+        NF_HIP(hipEventRecord(sb[k]->done, sb[k]->st));
+        ok[k] = 1;
+      } catch (...) {
+        err[k] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(start);
+  for (size_t k = 0; k < n; ++k)
+    if (ok[k]) NF_HIP(hipStreamWaitEvent(s, sb[k]->done, 0));
+  for (size_t k = 0; k < n; ++k) {
+    for (auto& h : hs[k]) g_hsink->push_back(std::move(h));
+    for (auto& o : os[k]) g_osink->push_back(std::move(o));
+  }
+  for (size_t k = 0; k < n; ++k)
+    if (err[k]) {
+      // the other children may still have work queued on their streams
+      for (size_t j = 0; j < n; ++j) (void)hipStreamSynchronize(sb[j]->st);
+      std::rethrow_exception(err[k]);
+    }
+  return out;
+}
 
 template <class T>
 static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const BlockMat& A, const std::vector<FieldDev>& F,
@@ -828,7 +926,7 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
       M.u.alloc(mp > 0 ? mp : 1);
     }
   }
-  C.hiers.push_back(std::move(H));
+  g_hsink->push_back(std::move(H));
   return S;
 }
 
@@ -863,11 +961,13 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->sweeps = sp.sweeps > 0 ? sp.sweeps : C.o.sweeps;
     S->order = sp.order >= 0 ? sp.order : C.o.order;
     int mx = 0;
+    std::vector<BuildTask<T>> tasks;
     for (int i = f0; i < f1; ++i) {
       NF_CHECK(A.at(i, i) != nullptr, NFIELD_ESINGULAR, "BGS: zero diagonal block");
-      S->child.push_back(build<T>(C, sp.kids[0], A, F, i, i + 1, s));
+      tasks.push_back([&C, &sp, &A, &F, i](hipStream_t st) { return build<T>(C, sp.kids[0], A, F, i, i + 1, st); });
       mx = std::max(mx, A.size[i]);
     }
+    S->child = build_children<T>(C, tasks, s);
     S->n = n;
     S->res.alloc(n);
     S->d.alloc(n);
@@ -897,7 +997,6 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->dtinv.alloc(n1 > 0 ? n1 : 1);
     if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(S->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
     else cast_copy<double, float>(dt.p, (float*)S->dtinv.p, n1, s);
-    S->pred = build<T>(C, sp.kids[0], A, F, f0, g, s);
     auto Bm = std::make_unique<BlockMat>();
     Bm->N = 1;
     Bm->size = {n2};
@@ -906,8 +1005,15 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     std::vector<FieldDev> Fs = {F[g]};
     Spec def;
     def.name = n2 <= C.o.schur_direct_max ? "LU" : "AMG";
-    S->schur = build<T>(C, sp.kids.size() == 2 ? sp.kids[1] : def, *Bm, Fs, 0, 1, s);
-    C.owned.push_back(std::move(Bm));
+    const Spec& ssp = sp.kids.size() == 2 ? sp.kids[1] : def;
+    const BlockMat& B1 = *Bm;
+    std::vector<BuildTask<T>> tasks;
+    tasks.push_back([&C, &sp, &A, &F, f0, g](hipStream_t st) { return build<T>(C, sp.kids[0], A, F, f0, g, st); });
+    tasks.push_back([&C, &ssp, &B1, &Fs](hipStream_t st) { return build<T>(C, ssp, B1, Fs, 0, 1, st); });
+    auto kids = build_children<T>(C, tasks, s);
+    S->pred = std::move(kids[0]);
+    S->schur = std::move(kids[1]);
+    g_osink->push_back(std::move(Bm));
     S->n = n;
     S->res.alloc(n);
     S->d.alloc(n);
@@ -1235,6 +1341,9 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
   C.root32.reset();
   C.hiers.clear();
   C.owned.clear();
+  C.side_next = 0;
+  g_hsink = &C.hiers;
+  g_osink = &C.owned;
   if (C.o.hier_fp32) {
     for (auto& b : C.A.blk)
       if (b) make_fp32(*b, s);
@@ -1282,6 +1391,7 @@ void nfield_default_opts(nfield_opts* o) {
   o->seed = 0;
   o->graphs = 0;
   o->block_products = 1;
+  o->parallel_setup = 1;
 }
 
 void nfield_default_solve_opts(nfield_solve_opts* so) {
@@ -1339,6 +1449,7 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
     C->o.seed = o.seed;
     C->o.graphs = o.graphs;
     C->o.block_products = o.block_products;
+    C->o.parallel_setup = o.parallel_setup;
     NF_CHECK(o.sweeps >= 1 && o.order >= 0 && o.order <= 2 && o.cheb_degree >= 1 && o.max_levels >= 1 &&
                  o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2,
              NFIELD_EINVAL, "options out of range");
@@ -1406,7 +1517,12 @@ void nfield_destroy(nfield_ctx* ctx) {
   delete ctx;
 }
 
-size_t nfield_footprint_bytes(const nfield_ctx* ctx) { return ctx ? ctx->pool.live + ctx->pool.cached : 0; }
+size_t nfield_footprint_bytes(const nfield_ctx* ctx) {
+  if (!ctx) return 0;
+  size_t b = ctx->pool.live + ctx->pool.cached;
+  for (auto& sb : ctx->side) b += sb->pool.live + sb->pool.cached;
+  return b;
+}
 int64_t nfield_size(const nfield_ctx* ctx) { return ctx ? ctx->Aglob.nr : 0; }
 
 nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, int32_t nrhs, void* hip_stream) {

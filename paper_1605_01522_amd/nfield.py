@@ -34,7 +34,7 @@ class nfield_opts(C.Structure):
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double),
                 ("simplec_mode", C.c_int32), ("split", C.c_void_p),
                 ("schur_direct_max", C.c_int32), ("hier_fp32", C.c_int32), ("seed", C.c_uint64),
-                ("graphs", C.c_int32), ("block_products", C.c_int32)]
+                ("graphs", C.c_int32), ("block_products", C.c_int32), ("parallel_setup", C.c_int32)]
 
 
 class nfield_solve_opts(C.Structure):
