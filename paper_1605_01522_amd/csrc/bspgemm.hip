@@ -276,7 +276,8 @@ __device__ __forceinline__ void bsp_stage(int tid, int nq, int kbc, int na, cons
 }
 
 template <int NT, int CAPV, bool STAGE>
-__global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows, int br, int bk, int bc,
+__global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows, int nrows, const int* __restrict__ nrows_dev,
+                                                    int br, int bk, int bc,
                                                     const int* __restrict__ Ap, const int* __restrict__ Ac,
                                                     const double* __restrict__ Av, const unsigned long long* __restrict__ Am,
                                                     const int* __restrict__ Bp, const int* __restrict__ Bc,
@@ -293,103 +294,110 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
   __shared__ int sc[STAGE ? 2 : 1][STAGE ? BSP_STGB : 1];
   __shared__ unsigned long long sm[STAGE ? 2 : 1][STAGE ? BSP_STGB : 1];
   __shared__ double sa[STAGE ? 2 : 1][STAGE ? 64 : 1];
-  const int i = rows ? rows[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
-  const int c0 = Cp[i], ncb = Cp[i + 1] - c0, bb = br * bc, nel = ncb * bb;
-  if (nel > CAPV || ncb > CAPV / 2) {
-    if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
-    return;
-  }
-  const int kbc = bk * bc, na = br * bk;
-  for (int t = tid; t < ncb; t += NT) ccol[t] = Cc[c0 + t];
-  for (int t = tid; t < nel; t += NT) {
-    acc[t] = 0.0;
-    st[t] = 0;
-  }
-  const int a0 = Ap[i], a1 = Ap[i + 1];
-  for (int p0 = a0; p0 < a1; p0 += NT) {
+  const int tid = threadIdx.x;
+  // rows: all of C's (no list) or a list whose length may be on the device;
+  // workgroups stride over them
+  const int nlist = nrows_dev ? *nrows_dev : nrows;
+  for (int bi = blockIdx.x; bi < nlist; bi += gridDim.x) {
     __syncthreads();
-    if (p0 + tid < a1) {
-      const int kb = Ac[p0 + tid];
-      mq0[tid] = Bp[kb];
-      mq1[tid] = Bp[kb + 1];
-      mam[tid] = Am[p0 + tid];
+    const int i = rows ? rows[bi] : bi;
+    const int c0 = Cp[i], ncb = Cp[i + 1] - c0, bb = br * bc, nel = ncb * bb;
+    if (nel > CAPV || ncb > CAPV / 2) {
+      if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
+      continue;
     }
-    __syncthreads();
-    const int np = min(NT, a1 - p0);
-    if (STAGE) {
-      const int nq = mq1[0] - mq0[0];
-      if (nq <= BSP_STGB && nq * kbc <= BSP_STG)
-        bsp_stage<NT>(tid, nq, kbc, na, Bc, Bv, Bm, Av + (int64_t)p0 * na, mq0[0], sv[0], sc[0], sm[0], sa[0]);
+    const int kbc = bk * bc, na = br * bk;
+    for (int t = tid; t < ncb; t += NT) ccol[t] = Cc[c0 + t];
+    for (int t = tid; t < nel; t += NT) {
+      acc[t] = 0.0;
+      st[t] = 0;
+    }
+    const int a0 = Ap[i], a1 = Ap[i + 1];
+    for (int p0 = a0; p0 < a1; p0 += NT) {
       __syncthreads();
-    }
-    for (int t = 0; t < np; ++t) {
-      const int b = STAGE ? (t & 1) : 0;
-      const int q0 = mq0[t], nq = mq1[t] - q0;
-      const unsigned long long am = mam[t];
-      const bool staged = STAGE && nq <= BSP_STGB && nq * kbc <= BSP_STG;
-      const double* __restrict__ avp = Av + (int64_t)(p0 + t) * na;
-      const int items = nq * bb;
-      for (int it = tid; it < items; it += NT) {
-        const int qo = it / bb, rc = it - qo * bb, r = rc / bc, c = rc - r * bc;
-        int jb;
-        unsigned long long bm;
-        double x[8], y[8];
-        // every operand is fetched at once (stored or not), then used where
-        // both entries are stored
-        if (staged) {
-          jb = sc[b][qo];
-          bm = sm[b][qo];
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (k < bk) {
-              x[k] = sa[b][r * bk + k];
-              y[k] = sv[b][qo * kbc + k * bc + c];
-            }
-        } else {
-          jb = Bc[q0 + qo];
-          bm = Bm[q0 + qo];
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (k < bk) {
-              x[k] = avp[r * bk + k];
-              y[k] = Bv[(int64_t)(q0 + qo) * kbc + k * bc + c];
-            }
-        }
-        int lo = 0, hi = ncb;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (ccol[mid] < jb) lo = mid + 1; else hi = mid;
-        }
-        const int e = lo * bb + rc;
-        double a = acc[e];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (k < bk && ((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
-            a += x[k] * y[k];
-            any = true;
+      if (p0 + tid < a1) {
+        const int kb = Ac[p0 + tid];
+        mq0[tid] = Bp[kb];
+        mq1[tid] = Bp[kb + 1];
+        mam[tid] = Am[p0 + tid];
+      }
+      __syncthreads();
+      const int np = min(NT, a1 - p0);
+      if (STAGE) {
+        const int nq = mq1[0] - mq0[0];
+        if (nq <= BSP_STGB && nq * kbc <= BSP_STG)
+          bsp_stage<NT>(tid, nq, kbc, na, Bc, Bv, Bm, Av + (int64_t)p0 * na, mq0[0], sv[0], sc[0], sm[0], sa[0]);
+        __syncthreads();
+      }
+      for (int t = 0; t < np; ++t) {
+        const int b = STAGE ? (t & 1) : 0;
+        const int q0 = mq0[t], nq = mq1[t] - q0;
+        const unsigned long long am = mam[t];
+        const bool staged = STAGE && nq <= BSP_STGB && nq * kbc <= BSP_STG;
+        const double* __restrict__ avp = Av + (int64_t)(p0 + t) * na;
+        const int items = nq * bb;
+        for (int it = tid; it < items; it += NT) {
+          const int qo = it / bb, rc = it - qo * bb, r = rc / bc, c = rc - r * bc;
+          int jb;
+          unsigned long long bm;
+          double x[8], y[8];
+          // every operand is fetched at once (stored or not), then used where
+          // both entries are stored
+          if (staged) {
+            jb = sc[b][qo];
+            bm = sm[b][qo];
+  #pragma unroll
+            for (int k = 0; k < 8; ++k)
+              if (k < bk) {
+                x[k] = sa[b][r * bk + k];
+                y[k] = sv[b][qo * kbc + k * bc + c];
+              }
+          } else {
+            jb = Bc[q0 + qo];
+            bm = Bm[q0 + qo];
+  #pragma unroll
+            for (int k = 0; k < 8; ++k)
+              if (k < bk) {
+                x[k] = avp[r * bk + k];
+                y[k] = Bv[(int64_t)(q0 + qo) * kbc + k * bc + c];
+              }
           }
-        if (any) {
-          acc[e] = a;
-          st[e] = 1;
+          int lo = 0, hi = ncb;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ccol[mid] < jb) lo = mid + 1; else hi = mid;
+          }
+          const int e = lo * bb + rc;
+          double a = acc[e];
+          bool any = false;
+  #pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k < bk && ((am >> (r * bk + k)) & 1ull) && ((bm >> (k * bc + c)) & 1ull)) {
+              a += x[k] * y[k];
+              any = true;
+            }
+          if (any) {
+            acc[e] = a;
+            st[e] = 1;
+          }
         }
+        if (STAGE && t + 1 < np) {
+          const int nq1 = mq1[t + 1] - mq0[t + 1];
+          if (nq1 <= BSP_STGB && nq1 * kbc <= BSP_STG)
+            bsp_stage<NT>(tid, nq1, kbc, na, Bc, Bv, Bm, Av + (int64_t)(p0 + t + 1) * na, mq0[t + 1], sv[b ^ 1], sc[b ^ 1],
+                          sm[b ^ 1], sa[b ^ 1]);
+        }
+        __syncthreads();
       }
-      if (STAGE && t + 1 < np) {
-        const int nq1 = mq1[t + 1] - mq0[t + 1];
-        if (nq1 <= BSP_STGB && nq1 * kbc <= BSP_STG)
-          bsp_stage<NT>(tid, nq1, kbc, na, Bc, Bv, Bm, Av + (int64_t)(p0 + t + 1) * na, mq0[t + 1], sv[b ^ 1], sc[b ^ 1],
-                        sm[b ^ 1], sa[b ^ 1]);
-      }
-      __syncthreads();
     }
-  }
-  __syncthreads();
-  for (int t = tid; t < nel; t += NT) Cv[(int64_t)c0 * bb + t] = acc[t];
-  for (int pb = tid; pb < ncb; pb += NT) {
-    unsigned long long m = 0;
-    for (int rc = 0; rc < bb; ++rc)
-      if (st[pb * bb + rc]) m |= 1ull << rc;
-    Cm[c0 + pb] = m;
+    __syncthreads();
+    for (int t = tid; t < nel; t += NT) Cv[(int64_t)c0 * bb + t] = acc[t];
+    for (int pb = tid; pb < ncb; pb += NT) {
+      unsigned long long m = 0;
+      for (int rc = 0; rc < bb; ++rc)
+        if (st[pb * bb + rc]) m |= 1ull << rc;
+      Cm[c0 + pb] = m;
+    }
   }
 }
 
@@ -400,87 +408,92 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
 // kb, k; the block's stored-entry mask is the ballot of its lanes.
 constexpr int BSP_EPL = 4;
 
-__global__ __launch_bounds__(64) void k_bspgemm_wide(const int* __restrict__ rows, int br, int bk, int bc, int bbp,
+__global__ __launch_bounds__(64) void k_bspgemm_wide(const int* __restrict__ rows, int nrows, const int* __restrict__ nrows_dev,
+                                                     int br, int bk, int bc, int bbp,
                                                      const int* __restrict__ Ap, const int* __restrict__ Ac,
                                                      const double* __restrict__ Av, const unsigned long long* __restrict__ Am,
                                                      const int* __restrict__ Bp, const int* __restrict__ Bc,
                                                      const double* __restrict__ Bv, const unsigned long long* __restrict__ Bm,
                                                      const int* __restrict__ Cp, const int* __restrict__ Cc,
                                                      double* __restrict__ Cv, unsigned long long* __restrict__ Cm) {
-  const int i = rows[blockIdx.x], lane = threadIdx.x;
-  const int c0 = Cp[i], ncb = Cp[i + 1] - c0;
-  const int bb = br * bc, nel = ncb * bbp;
-  const int a0 = Ap[i], a1 = Ap[i + 1];
-  for (int base = 0; base < nel; base += 64 * BSP_EPL) {
-    double acc[BSP_EPL];
-    bool st[BSP_EPL];
-    int jb[BSP_EPL], rr[BSP_EPL], cc[BSP_EPL];
-#pragma unroll
-    for (int u = 0; u < BSP_EPL; ++u) {
-      acc[u] = 0.0;
-      st[u] = false;
-      jb[u] = -1;
-      rr[u] = cc[u] = 0;
-      const int e = base + u * 64 + lane;
-      if (e < nel) {
-        const int pb = e / bbp, rc = e - pb * bbp;
-        if (rc < bb) {
-          jb[u] = Cc[c0 + pb];
-          rr[u] = rc / bc;
-          cc[u] = rc - rr[u] * bc;
-        }
-      }
-    }
-    for (int p = a0; p < a1; ++p) {
-      const int kb = Ac[p];
-      const unsigned long long am = Am[p];
-      const double* av = Av + (int64_t)p * br * bk;
-      const int q0 = Bp[kb], q1 = Bp[kb + 1];
-#pragma unroll
+  const int lane = threadIdx.x;
+  const int nlist = nrows_dev ? *nrows_dev : nrows;
+  for (int bi = blockIdx.x; bi < nlist; bi += gridDim.x) {
+    const int i = rows[bi];
+    const int c0 = Cp[i], ncb = Cp[i + 1] - c0;
+    const int bb = br * bc, nel = ncb * bbp;
+    const int a0 = Ap[i], a1 = Ap[i + 1];
+    for (int base = 0; base < nel; base += 64 * BSP_EPL) {
+      double acc[BSP_EPL];
+      bool st[BSP_EPL];
+      int jb[BSP_EPL], rr[BSP_EPL], cc[BSP_EPL];
+  #pragma unroll
       for (int u = 0; u < BSP_EPL; ++u) {
-        if (jb[u] < 0) continue;
-        int lo = q0, hi = q1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (Bc[mid] < jb[u]) lo = mid + 1; else hi = mid;
-        }
-        if (lo >= q1 || Bc[lo] != jb[u]) continue;
-        const unsigned long long bm = Bm[lo];
-        const double* bv = Bv + (int64_t)lo * bk * bc;
-        for (int k = 0; k < bk; ++k)
-          if (((am >> (rr[u] * bk + k)) & 1ull) && ((bm >> (k * bc + cc[u])) & 1ull)) {
-            acc[u] += av[rr[u] * bk + k] * bv[k * bc + cc[u]];
-            st[u] = true;
+        acc[u] = 0.0;
+        st[u] = false;
+        jb[u] = -1;
+        rr[u] = cc[u] = 0;
+        const int e = base + u * 64 + lane;
+        if (e < nel) {
+          const int pb = e / bbp, rc = e - pb * bbp;
+          if (rc < bb) {
+            jb[u] = Cc[c0 + pb];
+            rr[u] = rc / bc;
+            cc[u] = rc - rr[u] * bc;
           }
+        }
       }
-    }
-#pragma unroll
-    for (int u = 0; u < BSP_EPL; ++u) {
-      const int e = base + u * 64 + lane;
-      const unsigned long long bal = __ballot(st[u]);
-      if (e < nel) {
-        const int pb = e / bbp, rc = e - pb * bbp;
-        if (rc < bb) Cv[(int64_t)(c0 + pb) * bb + rc] = acc[u];
-        if (rc == 0) {
-          // this block's bits sit at lanes [lane, lane + bbp) of the window
-          const unsigned long long w = bal >> lane;
-          Cm[c0 + pb] = bbp == 64 ? w : (w & ((1ull << bbp) - 1ull));
+      for (int p = a0; p < a1; ++p) {
+        const int kb = Ac[p];
+        const unsigned long long am = Am[p];
+        const double* av = Av + (int64_t)p * br * bk;
+        const int q0 = Bp[kb], q1 = Bp[kb + 1];
+  #pragma unroll
+        for (int u = 0; u < BSP_EPL; ++u) {
+          if (jb[u] < 0) continue;
+          int lo = q0, hi = q1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (Bc[mid] < jb[u]) lo = mid + 1; else hi = mid;
+          }
+          if (lo >= q1 || Bc[lo] != jb[u]) continue;
+          const unsigned long long bm = Bm[lo];
+          const double* bv = Bv + (int64_t)lo * bk * bc;
+          for (int k = 0; k < bk; ++k)
+            if (((am >> (rr[u] * bk + k)) & 1ull) && ((bm >> (k * bc + cc[u])) & 1ull)) {
+              acc[u] += av[rr[u] * bk + k] * bv[k * bc + cc[u]];
+              st[u] = true;
+            }
+        }
+      }
+  #pragma unroll
+      for (int u = 0; u < BSP_EPL; ++u) {
+        const int e = base + u * 64 + lane;
+        const unsigned long long bal = __ballot(st[u]);
+        if (e < nel) {
+          const int pb = e / bbp, rc = e - pb * bbp;
+          if (rc < bb) Cv[(int64_t)(c0 + pb) * bb + rc] = acc[u];
+          if (rc == 0) {
+            // this block's bits sit at lanes [lane, lane + bbp) of the window
+            const unsigned long long w = bal >> lane;
+            Cm[c0 + pb] = bbp == 64 ? w : (w & ((1ull << bbp) - 1ull));
+          }
         }
       }
     }
   }
 }
 
+// One pass over a row list (or all rows), with the list's length read on the
+// device: rows too long for the pass are appended to ovf (count novf, which
+// starts at zero).  Nothing is read back, so the passes queue one behind the
+// other without the host waiting.
 template <int NT, int CAPV, bool STAGE>
-static int bsp_pass(const int* rows, int nrows, const DBsr& A, const DBsr& B, DBsr& C, int* ovf, int* novf, hipStream_t s) {
-  fill<int>(novf, 0, 1, s);
-  hipLaunchKernelGGL((k_bspgemm_lds<NT, CAPV, STAGE>), dim3(nrows), dim3(NT), 0, s, rows, A.br, A.bc, B.bc, A.pat.ptr.p,
-                     A.pat.col.p, A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p,
-                     C.val.p, C.mask.p, ovf, novf);
-  int n = 0;
-  NF_HIP(hipMemcpyAsync(&n, novf, sizeof(int), hipMemcpyDeviceToHost, s));
-  NF_HIP(hipStreamSynchronize(s));
-  return n;
+static void bsp_pass(const int* rows, int nrows, const int* nrows_dev, int grid, const DBsr& A, const DBsr& B, DBsr& C,
+                     int* ovf, int* novf, hipStream_t s) {
+  hipLaunchKernelGGL((k_bspgemm_lds<NT, CAPV, STAGE>), dim3(grid), dim3(NT), 0, s, rows, nrows, nrows_dev, A.br, A.bc, B.bc,
+                     A.pat.ptr.p, A.pat.col.p, A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p,
+                     C.pat.col.p, C.val.p, C.mask.p, ovf, novf);
 }
 
 // block rows of C above which a product counts as many short rows
@@ -498,31 +511,30 @@ void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
   C.mask.alloc(nb);
   const int nbr = C.pat.nr;
   if (nbr <= 0 || C.pat.nnz <= 0) return;
-  DBuf<int> ovf1(nbr), ovf2(nbr), novf(1);
-  int n;
-  const int* left;
+  // every pass takes the rows the previous one could not hold: 512 values in
+  // 6.5 KB of LDS (many workgroups per CU, for many short rows), 2,048 values
+  // with a staged B row, 8,192 values (one workgroup per CU), then register-
+  // owned entries; later passes stride over their lists with bounded grids
+  DBuf<int> l1(nbr), l2(nbr), l3(nbr), cnt(3);
+  fill<int>(cnt.p, 0, 3, s);
+  const int* list2;
+  const int* n2;
   if (nbr >= BSP_MANY_ROWS) {
-    // small LDS first (many workgroups per CU), the longer rows again with more
-    const int n1 = bsp_pass<64, 512, false>(nullptr, nbr, A, B, C, ovf1.p, novf.p, s);
-    n = n1 > 0 ? bsp_pass<256, 2048, true>(ovf1.p, n1, A, B, C, ovf2.p, novf.p, s) : 0;
-    left = ovf2.p;
+    bsp_pass<64, 512, false>(nullptr, nbr, nullptr, nbr, A, B, C, l1.p, cnt.p, s);
+    bsp_pass<256, 2048, true>(l1.p, nbr, cnt.p, std::min(nbr, 4096), A, B, C, l2.p, cnt.p + 1, s);
+    list2 = l2.p;
+    n2 = cnt.p + 1;
   } else {
-    n = bsp_pass<256, 2048, true>(nullptr, nbr, A, B, C, ovf1.p, novf.p, s);
-    left = ovf1.p;
+    bsp_pass<256, 2048, true>(nullptr, nbr, nullptr, nbr, A, B, C, l2.p, cnt.p + 1, s);
+    list2 = l2.p;
+    n2 = cnt.p + 1;
   }
-  if (n > 0) {
-    // rows up to 8,192 values: one workgroup per CU (104 KB of LDS)
-    int* out = left == ovf1.p ? ovf2.p : ovf1.p;
-    n = bsp_pass<256, 8192, true>(left, n, A, B, C, out, novf.p, s);
-    left = out;
-  }
-  if (n > 0) {
-    int bbp = 1;
-    while (bbp < bb) bbp <<= 1;
-    hipLaunchKernelGGL(k_bspgemm_wide, dim3(n), dim3(64), 0, s, left, A.br, A.bc, B.bc, bbp, A.pat.ptr.p, A.pat.col.p,
-                       A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p, C.pat.col.p, C.val.p,
-                       C.mask.p);
-  }
+  bsp_pass<256, 8192, true>(list2, nbr, n2, std::min(nbr, 512), A, B, C, l3.p, cnt.p + 2, s);
+  int bbp = 1;
+  while (bbp < bb) bbp <<= 1;
+  hipLaunchKernelGGL(k_bspgemm_wide, dim3(std::min(nbr, 1024)), dim3(64), 0, s, l3.p, nbr, cnt.p + 2, A.br, A.bc, B.bc, bbp,
+                     A.pat.ptr.p, A.pat.col.p, A.val.p, A.mask.p, B.pat.ptr.p, B.pat.col.p, B.val.p, B.mask.p, C.pat.ptr.p,
+                     C.pat.col.p, C.val.p, C.mask.p);
 }
 
 // R = P^T block by block: the block pattern transposed (pattern values carry

@@ -1871,7 +1871,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_spgemm_fill(const int* __restric
 // scratch at the row's upper-bound offset (its count in cnt); rows the table
 // cannot hold are listed in ovf for the dense accumulator.
 template <int CAP>
-__global__ __launch_bounds__(64) void k_spgemm_fill_ub(const int* __restrict__ rows, int nrows, const int* __restrict__ Ap,
+__global__ __launch_bounds__(64) void k_spgemm_fill_ub(const int* __restrict__ rows, int nrows, const int* __restrict__ nrows_dev,
+                                                       const int* __restrict__ Ap,
                                                        const int* __restrict__ Ac, const double* __restrict__ Av,
                                                        const int* __restrict__ Bp, const int* __restrict__ Bc,
                                                        const double* __restrict__ Bv, const int* __restrict__ toff,
@@ -1879,76 +1880,81 @@ __global__ __launch_bounds__(64) void k_spgemm_fill_ub(const int* __restrict__ r
                                                        double* __restrict__ tval, int* __restrict__ cnt, int* ovf, int* ovf_n) {
   __shared__ int keys[CAP];
   __shared__ double acc[CAP];
-  if ((int)blockIdx.x >= nrows) return;
-  const int row = rows[blockIdx.x], lane = threadIdx.x;
-  const int ub = ubrow[row];
-  int ts = 1, logts = 0;
-  while (ts < 2 * ub && ts < CAP) { ts <<= 1; ++logts; }
-  for (int i = lane; i < ts; i += 64) keys[i] = EMPTY_KEY;
-  __syncthreads();
-  int mine = 0, full = 0;
-  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
-    const int k = Ac[p];
-    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
-      const int r = hash_insert(keys, ts, logts, Bc[q]);
-      if (r > 0) ++mine;
-      if (r < 0) full = 1;
-    }
-  }
-  const int c = wave_sum_int(mine);
-  if (wave_sum_int(full)) {
-    if (lane == 0) ovf[atomicAdd(ovf_n, 1)] = row;
-    return;
-  }
-  // gather the c keys to the front (through the accumulator's storage), pad
-  // to a power of two and sort only that
   __shared__ int npos;
-  int* tmp = (int*)acc;
-  if (lane == 0) npos = 0;
-  __syncthreads();
-  for (int i = lane; i < ts; i += 64) {
-    const int k = keys[i];
-    if (k != EMPTY_KEY) tmp[atomicAdd(&npos, 1)] = k;
-  }
-  __syncthreads();
-  int ts2 = 1;
-  while (ts2 < c) ts2 <<= 1;
-  for (int i = lane; i < ts2; i += 64) keys[i] = i < c ? tmp[i] : EMPTY_KEY;
-  __syncthreads();
-  for (int kk = 2; kk <= ts2; kk <<= 1)
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < ts2; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const int x = keys[i], y = keys[ixj];
-          const bool up = (i & kk) == 0;
-          if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
+  // the list's length on the device (a list another pass wrote) when given;
+  // workgroups stride over the list
+  const int nlist = nrows_dev ? *nrows_dev : nrows;
+  for (int bi = blockIdx.x; bi < nlist; bi += gridDim.x) {
+    __syncthreads();
+    const int row = rows[bi], lane = threadIdx.x;
+    const int ub = ubrow[row];
+    int ts = 1, logts = 0;
+    while (ts < 2 * ub && ts < CAP) { ts <<= 1; ++logts; }
+    for (int i = lane; i < ts; i += 64) keys[i] = EMPTY_KEY;
+    __syncthreads();
+    int mine = 0, full = 0;
+    for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+      const int k = Ac[p];
+      for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+        const int r = hash_insert(keys, ts, logts, Bc[q]);
+        if (r > 0) ++mine;
+        if (r < 0) full = 1;
+      }
+    }
+    const int c = wave_sum_int(mine);
+    if (wave_sum_int(full)) {
+      if (lane == 0) ovf[atomicAdd(ovf_n, 1)] = row;
+      continue;
+    }
+    // gather the c keys to the front (through the accumulator's storage), pad
+    // to a power of two and sort only that
+    int* tmp = (int*)acc;
+    if (lane == 0) npos = 0;
+    __syncthreads();
+    for (int i = lane; i < ts; i += 64) {
+      const int k = keys[i];
+      if (k != EMPTY_KEY) tmp[atomicAdd(&npos, 1)] = k;
+    }
+    __syncthreads();
+    int ts2 = 1;
+    while (ts2 < c) ts2 <<= 1;
+    for (int i = lane; i < ts2; i += 64) keys[i] = i < c ? tmp[i] : EMPTY_KEY;
+    __syncthreads();
+    for (int kk = 2; kk <= ts2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < ts2; i += 64) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const int x = keys[i], y = keys[ixj];
+            const bool up = (i & kk) == 0;
+            if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
+          }
         }
+        __syncthreads();
+      }
+    for (int i = lane; i < c; i += 64) acc[i] = 0.0;
+    __syncthreads();
+    for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
+      const int k = Ac[p];
+      const double a = Av[p];
+      for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
+        const int key = Bc[q];
+        int lo = 0, hi = c;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (keys[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        acc[lo] += a * Bv[q];
       }
       __syncthreads();
     }
-  for (int i = lane; i < c; i += 64) acc[i] = 0.0;
-  __syncthreads();
-  for (int p = Ap[row]; p < Ap[row + 1]; ++p) {
-    const int k = Ac[p];
-    const double a = Av[p];
-    for (int q = Bp[k] + lane; q < Bp[k + 1]; q += 64) {
-      const int key = Bc[q];
-      int lo = 0, hi = c;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (keys[mid] < key) lo = mid + 1; else hi = mid;
-      }
-      acc[lo] += a * Bv[q];
+    const int o = toff[row];
+    for (int i = lane; i < c; i += 64) {
+      tcol[o + i] = keys[i];
+      tval[o + i] = acc[i];
     }
-    __syncthreads();
+    if (lane == 0) cnt[row] = c;
   }
-  const int o = toff[row];
-  for (int i = lane; i < c; i += 64) {
-    tcol[o + i] = keys[i];
-    tval[o + i] = acc[i];
-  }
-  if (lane == 0) cnt[row] = c;
 }
 
 // the dense-accumulator row of k_spa_fill written to the scratch at the
@@ -2086,19 +2092,18 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
       DBuf<int> big2(nr1);
       fill<int>(flags.p + 4, 0, 1, s);
       if (ns > 0)
-        hipLaunchKernelGGL(k_spgemm_fill_ub<512>, dim3(ns), dim3(64), 0, s, small.p, ns, A.ptr.p, A.col.p, A.val.p, B.ptr.p,
-                           B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p, flags.p + 3);
-      if (nb > 0)
-        hipLaunchKernelGGL(k_spgemm_fill_ub<1024>, dim3(nb), dim3(64), 0, s, big.p, nb, A.ptr.p, A.col.p, A.val.p, B.ptr.p,
-                           B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, big2.p, flags.p + 4);
-      int nb2 = 0;
+        hipLaunchKernelGGL(k_spgemm_fill_ub<512>, dim3(ns), dim3(64), 0, s, small.p, ns, (const int*)nullptr, A.ptr.p,
+                           A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p,
+                           flags.p + 3);
       if (nb > 0) {
-        NF_HIP(hipMemcpyAsync(&nb2, flags.p + 4, sizeof(int), hipMemcpyDeviceToHost, s));
-        NF_HIP(hipStreamSynchronize(s));
+        hipLaunchKernelGGL(k_spgemm_fill_ub<1024>, dim3(nb), dim3(64), 0, s, big.p, nb, (const int*)nullptr, A.ptr.p,
+                           A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, big2.p,
+                           flags.p + 4);
+        // the retries: the list's length stays on the device, a bounded grid
+        // strides over it
+        hipLaunchKernelGGL(k_spgemm_fill_ub<4096>, dim3(std::min(nb, 2048)), dim3(64), 0, s, big2.p, nb, flags.p + 4, A.ptr.p, A.col.p,
+                           A.val.p, B.ptr.p, B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p, flags.p + 3);
       }
-      if (nb2 > 0)
-        hipLaunchKernelGGL(k_spgemm_fill_ub<4096>, dim3(nb2), dim3(64), 0, s, big2.p, nb2, A.ptr.p, A.col.p, A.val.p,
-                           B.ptr.p, B.col.p, B.val.p, toff.p, ubrow.p, tcol.p, tval.p, cnt.p, huge.p, flags.p + 3);
       int nh = 0;
       NF_HIP(hipMemcpyAsync(&nh, flags.p + 3, sizeof(int), hipMemcpyDeviceToHost, s));
       NF_HIP(hipStreamSynchronize(s));
@@ -2316,14 +2321,37 @@ void transpose(const DCsr& A, DCsr& T, hipStream_t s) {
 }
 
 // ================================================================ sparse add
-template <bool FILL>
+// G lanes per row: a row present in only one operand is copied (scaled) by
+// the lanes together; a row present in both is merged by the group's first
+// lane (both cases give every entry the expression of the serial merge)
+template <bool FILL, int G>
 __global__ void k_csr_add(int nr, double alpha, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
                           double beta, const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
                           int* cnt_or_ptr, int* cc, double* cv) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = (int)(gid / G), lane = (int)(gid % G);
   if (r >= nr) return;
   int p = ap ? ap[r] : 0, pe = ap ? ap[r + 1] : 0, q = bp ? bp[r] : 0, qe = bp ? bp[r + 1] : 0;
-  int o = FILL ? cnt_or_ptr[r] : 0, n = 0;
+  const int o = FILL ? cnt_or_ptr[r] : 0;
+  if (q == qe || p == pe) {
+    const int n = (pe - p) + (qe - q);
+    if (!FILL) {
+      if (lane == 0) cnt_or_ptr[r] = n;
+      return;
+    }
+    for (int t = lane; t < n; t += G) {
+      if (p < pe) {
+        cc[o + t] = ac[p + t];
+        cv[o + t] = alpha * av[p + t];
+      } else {
+        cc[o + t] = bc[q + t];
+        cv[o + t] = beta * bv[q + t];
+      }
+    }
+    return;
+  }
+  if (lane != 0) return;
+  int n = 0;
   while (p < pe || q < qe) {
     const int ca = p < pe ? ac[p] : INT_MAX, cb = q < qe ? bc[q] : INT_MAX;
     int c;
@@ -2343,16 +2371,17 @@ void csr_add(double alpha, const DCsr& A, double beta, const DCsr& B, DCsr& C, h
   C.nc = ha ? A.nc : B.nc;
   DBuf<int> cnt(nr + 1);
   C.ptr.alloc(nr + 1);
-  const int g = cdiv(nr, 256);
+  constexpr int G = 8;
+  const int g = cdiv((int64_t)nr * G, 256);
   if (nr > 0)
-    hipLaunchKernelGGL(k_csr_add<false>, dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p, beta,
-                       hb ? B.ptr.p : nullptr, B.col.p, B.val.p, cnt.p, nullptr, nullptr);
+    hipLaunchKernelGGL((k_csr_add<false, G>), dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p,
+                       beta, hb ? B.ptr.p : nullptr, B.col.p, B.val.p, cnt.p, nullptr, nullptr);
   C.nnz = exclusive_scan(cnt.p, C.ptr.p, nr, s);
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val.alloc(C.nnz > 0 ? C.nnz : 1);
   if (nr > 0)
-    hipLaunchKernelGGL(k_csr_add<true>, dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p, beta,
-                       hb ? B.ptr.p : nullptr, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
+    hipLaunchKernelGGL((k_csr_add<true, G>), dim3(g), dim3(256), 0, s, nr, alpha, ha ? A.ptr.p : nullptr, A.col.p, A.val.p,
+                       beta, hb ? B.ptr.p : nullptr, B.col.p, B.val.p, C.ptr.p, C.col.p, C.val.p);
   NF_HIP(hipStreamSynchronize(s));
 }
 void csr_copy(const DCsr& A, DCsr& C, hipStream_t s) {
