@@ -8,11 +8,12 @@
 // then costs far more than the arithmetic.  Here both operands are regrouped
 // into blocks of br x bc values with a bitmask of the stored entries, the
 // block pattern of the product comes from the scalar product machinery run on
-// the (much smaller) block patterns, and every output value is summed by the
-// lane that owns it.  Each output entry exists exactly when some inner index
-// pairs two stored entries, and its value adds a_ik b_kj over exactly those
-// pairs in ascending k (block by block, then within the block), which is the
-// pattern and the order of the scalar product: the results are the same bits.
+// the (much smaller) block patterns, and every output value is accumulated
+// term by term, one A block after another.  Each output entry exists exactly
+// when some inner index pairs two stored entries, and its value adds a_ik b_kj
+// over exactly those pairs in ascending k (block by block, then within the
+// block), which is the pattern and the order of the scalar product: the
+// results are the same bits.
 
 #include <climits>
 
