@@ -119,6 +119,30 @@ def test_lung_amg_simple_schur_chebyshev_parity(dev):
     assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
 
 
+def test_lung_benchmarked_configuration_parity(dev):
+    """The lung workload's preconditioner (SIMPLE with D~ = diag(A11) around
+    the monolithic AMG(BGS) with damped Gauss-Seidel, dense S~ inverse)."""
+    _say("case lung benchmarked configuration n=16")
+    s = nfgen.lung3d(n=16, depth=7, acinus=4, seed=2)
+    spec = "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)"
+    opts = dict(simplec_mode=2, **SPLIT)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(6).standard_normal(s.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8, maxit=1000)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=1000)
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    _say(f"lung benchmarked configuration: gpu iters {st[0]['iters']} oracle {so['iters']} relres {res:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert abs(st[0]["iters"] - so["iters"]) <= 2
+
+
 def test_lung_mid_size_solution_parity(dev):
     """Several levels on every field and a 512-multiplier dense Schur inverse."""
     _say("case lung n=24 SIMPLE(AMG(BGS);LU)")
