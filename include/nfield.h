@@ -34,7 +34,9 @@
  * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7).
  *
  * All device work runs in the library's own HIP kernels for gfx950, enqueued
- * on the caller's stream.  Every vector argument named *_dev is a device
+ * on the caller's stream (setup and rebuild may also use streams of the
+ * library's own for independent parts, ordered after the caller's stream and
+ * before its later work; see parallel_setup).  Every vector argument named *_dev is a device
  * pointer owned by the caller (for instance a torch tensor), FP64, holding
  * nrhs columns of length n = sum_i ndof_i one after the other (column-major
  * n x nrhs), each column in global field order [x_1; ...; x_N].
@@ -138,7 +140,8 @@ void nfield_default_solve_opts(nfield_solve_opts *sopts);
 /* Build the preconditioner for the system: upload every block, parse spec,
  * build the AMG hierarchies (node graph, MIS-2 aggregation, tentative and
  * smoothed prolongators, Galerkin products, smoothers, coarse LU) on the
- * device.  hip_stream may be NULL (default stream).  Errors: EINVAL for
+ * device.  hip_stream may be NULL (default stream).  Returns after the device
+ * work has finished.  Errors: EINVAL for
  * malformed CSR, block shapes that disagree with fields[i].ndof, or a bad
  * spec; ESINGULAR for BGS / AMG on a zero diagonal block or entry, or a
  * zero coarse pivot; ENOMEM; EHIP. */
