@@ -688,11 +688,13 @@ struct nfield_ctx {
 namespace nf {
 
 // Independent children of a solver node (the fields of BGS, the predictor and
-// Schur parts of SIMPLE) are set up concurrently: one host thread each, on a
-// stream of its own that first waits for everything already queued on s,
-// allocating from the subtree's own block cache; s then waits for every
-// child's stream.  Hierarchies and owned blocks are handed back in child
-// order, so the tree, and every result, is the same as built one by one.
+// Schur parts of SIMPLE) are set up concurrently: the first on the calling
+// thread and stream, every other one on a host thread and a stream of its own
+// that first waits for everything already queued on s, allocating from the
+// subtree's own block cache; s then waits for every child's stream.  (Keeping
+// the first child on s keeps the number of streams, which share a few
+// hardware queues, low.)  Hierarchies and owned blocks are handed back in
+// child order, so the tree, and every result, is the same as built one by one.
 template <class T>
 using BuildTask = std::function<std::unique_ptr<Solver<T>>(hipStream_t)>;
 
@@ -707,10 +709,10 @@ static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, con
   }
   int dev = 0;
   NF_HIP(hipGetDevice(&dev));
-  std::vector<SideBuild*> sb(n);
+  std::vector<SideBuild*> sb(n, nullptr);
   {
     std::lock_guard<std::mutex> lock(C.side_mu);
-    for (size_t k = 0; k < n; ++k) {
+    for (size_t k = 1; k < n; ++k) {
       if (C.side_next == C.side.size()) {
         auto b = std::make_unique<SideBuild>();
         NF_HIP(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
@@ -728,7 +730,7 @@ static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, con
   std::vector<std::exception_ptr> err(n);
   std::vector<char> ok(n, 0);
   std::vector<std::thread> th;
-  for (size_t k = 0; k < n; ++k)
+  for (size_t k = 1; k < n; ++k)
     th.emplace_back([&, k] {
       try {
         NF_HIP(hipSetDevice(dev));
@@ -745,18 +747,24 @@ static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, con
         err[k] = std::current_exception();
       }
     });
+  // the first child here, straight into this thread's sinks (it comes first)
+  try {
+    out[0] = tasks[0](s);
+  } catch (...) {
+    err[0] = std::current_exception();
+  }
   for (auto& t : th) t.join();
   (void)hipEventDestroy(start);
-  for (size_t k = 0; k < n; ++k)
+  for (size_t k = 1; k < n; ++k)
     if (ok[k]) NF_HIP(hipStreamWaitEvent(s, sb[k]->done, 0));
-  for (size_t k = 0; k < n; ++k) {
+  for (size_t k = 1; k < n; ++k) {
     for (auto& h : hs[k]) g_hsink->push_back(std::move(h));
     for (auto& o : os[k]) g_osink->push_back(std::move(o));
   }
   for (size_t k = 0; k < n; ++k)
     if (err[k]) {
       // the other children may still have work queued on their streams
-      for (size_t j = 0; j < n; ++j) (void)hipStreamSynchronize(sb[j]->st);
+      for (size_t j = 1; j < n; ++j) (void)hipStreamSynchronize(sb[j]->st);
       std::rethrow_exception(err[k]);
     }
   return out;
