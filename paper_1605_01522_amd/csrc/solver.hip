@@ -687,25 +687,20 @@ struct nfield_ctx {
 
 namespace nf {
 
-// Independent children of a solver node (the fields of BGS, the predictor and
-// Schur parts of SIMPLE) are set up concurrently: the first on the calling
+// Independent parts of the setup (the children of a solver node: the fields
+// of BGS, the predictor and Schur parts of SIMPLE; a hierarchy and its finest
+// level's Gauss-Seidel set-up) run concurrently: the first on the calling
 // thread and stream, every other one on a host thread and a stream of its own
 // that first waits for everything already queued on s, allocating from the
-// subtree's own block cache; s then waits for every child's stream.  (Keeping
-// the first child on s keeps the number of streams, which share a few
+// part's own block cache; s then waits for every part's stream.  (Keeping
+// the first part on s keeps the number of streams, which share a few
 // hardware queues, low.)  Hierarchies and owned blocks are handed back in
-// child order, so the tree, and every result, is the same as built one by one.
-template <class T>
-using BuildTask = std::function<std::unique_ptr<Solver<T>>(hipStream_t)>;
-
-template <class T>
-static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, const std::vector<BuildTask<T>>& tasks,
-                                                              hipStream_t s) {
+// task order, so the tree, and every result, is the same as built one by one.
+static void run_concurrently(nfield_ctx& C, const std::vector<std::function<void(hipStream_t)>>& tasks, hipStream_t s) {
   const size_t n = tasks.size();
-  std::vector<std::unique_ptr<Solver<T>>> out(n);
   if (n < 2 || !C.o.parallel_setup) {
-    for (size_t k = 0; k < n; ++k) out[k] = tasks[k](s);
-    return out;
+    for (size_t k = 0; k < n; ++k) tasks[k](s);
+    return;
   }
   int dev = 0;
   NF_HIP(hipGetDevice(&dev));
@@ -740,16 +735,16 @@ static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, con
         prof_quiet(true);
         sb[k]->pool.enter(sb[k]->st);
         NF_HIP(hipStreamWaitEvent(sb[k]->st, start, 0));
-        out[k] = tasks[k](sb[k]->st);
+        tasks[k](sb[k]->st);
         NF_HIP(hipEventRecord(sb[k]->done, sb[k]->st));
         ok[k] = 1;
       } catch (...) {
         err[k] = std::current_exception();
       }
     });
-  // the first child here, straight into this thread's sinks (it comes first)
+  // the first task here, straight into this thread's sinks (it comes first)
   try {
-    out[0] = tasks[0](s);
+    tasks[0](s);
   } catch (...) {
     err[0] = std::current_exception();
   }
@@ -763,10 +758,22 @@ static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, con
   }
   for (size_t k = 0; k < n; ++k)
     if (err[k]) {
-      // the other children may still have work queued on their streams
+      // the other tasks may still have work queued on their streams
       for (size_t j = 1; j < n; ++j) (void)hipStreamSynchronize(sb[j]->st);
       std::rethrow_exception(err[k]);
     }
+}
+
+template <class T>
+using BuildTask = std::function<std::unique_ptr<Solver<T>>(hipStream_t)>;
+
+template <class T>
+static std::vector<std::unique_ptr<Solver<T>>> build_children(nfield_ctx& C, const std::vector<BuildTask<T>>& tasks,
+                                                              hipStream_t s) {
+  std::vector<std::unique_ptr<Solver<T>>> out(tasks.size());
+  std::vector<std::function<void(hipStream_t)>> run;
+  for (size_t k = 0; k < tasks.size(); ++k) run.push_back([&out, &tasks, k](hipStream_t st) { out[k] = tasks[k](st); });
+  run_concurrently(C, run, s);
   return out;
 }
 
@@ -819,6 +826,23 @@ struct ChebSolverD : Solver<T> {
   }
 };
 
+// Multicolour Gauss-Seidel of one field on one level (the node graph of A is
+// computed here unless given); small many-colour levels as the dense map.
+template <class T>
+static std::unique_ptr<FieldSmootherD<T>> make_sgs(const DCsr* A, int b, const double* dinv64, double omega, int steps,
+                                                   uint64_t seed, hipStream_t s, const DBuf<int>* gp, const DBuf<int>* ga,
+                                                   int nn) {
+  auto g = std::make_unique<SgsD<T>>();
+  g->setup(A, b, dinv64, omega, steps, seed, s, gp, ga, nn);
+  const int ncol = (int)g->off.size() - 1;
+  if (A->nr <= SGS_DENSE_MAX && ncol >= SGS_DENSE_MIN_COLORS) {
+    auto d = std::make_unique<DenseSgsD<T>>();
+    d->setup(*g, A, b, dinv64, omega, steps, s);
+    return d;
+  }
+  return g;
+}
+
 template <class T>
 static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, const std::vector<FieldDev>& F, int f0, int f1,
                                             const Spec* smoother, const Spec& amg, hipStream_t s) {
@@ -834,7 +858,34 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
   for (int i = 0; i < sub.N; ++i)
     NF_CHECK(sub.at(i, i) != nullptr || (simple && i == sub.N - 1), NFIELD_ESINGULAR, "AMG: zero diagonal block");
   auto H = std::make_unique<Hierarchy>();
-  build_hierarchy(*H, sub, Fs, C.o, s);
+  // the finest level's Gauss-Seidel needs only A_ii: set up beside the
+  // hierarchy (its own D^-1 and node graph, the same values as the
+  // hierarchy's), unless the level smoother is SIMPLE
+  std::vector<std::unique_ptr<FieldSmootherD<T>>> sgs0(sub.N);
+  if (sgs && !simple && C.o.parallel_setup) {
+    std::vector<std::function<void(hipStream_t)>> tasks;
+    tasks.push_back([&](hipStream_t st) { build_hierarchy(*H, sub, Fs, C.o, st); });
+    tasks.push_back([&](hipStream_t st) {
+      for (int i = 0; i < sub.N; ++i) {
+        const DCsr* Aii = sub.at(i, i);
+        if (!Aii || Aii->nr <= 0) continue;
+        DBuf<double> d(Aii->nr), dinv(Aii->nr);
+        DBuf<int> zf(1);
+        fill<int>(zf.p, 0, 1, st);
+        csr_diag(*Aii, d.p, zf.p, st);
+        invert(d.p, dinv.p, Aii->nr, st);
+        int z = 0;
+        NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        NF_HIP(hipStreamSynchronize(st));
+        if (z) continue;   // a zero diagonal entry: the hierarchy's check reports it
+        sgs0[i] = make_sgs<T>(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0);
+        NF_HIP(hipStreamSynchronize(st));
+      }
+    });
+    run_concurrently(C, tasks, s);
+  } else {
+    build_hierarchy(*H, sub, Fs, C.o, s);
+  }
   auto S = std::make_unique<AmgSolverD<T>>();
   S->H = H.get();
   S->n = sub.total();
@@ -866,17 +917,13 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     for (int i = 0; i < nsm; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
       if (sgs) {
-        auto g = std::make_unique<SgsD<T>>();
-        const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
-        g->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s, have ? L.gptr[i].get() : nullptr,
-                 have ? L.gadj[i].get() : nullptr, have ? L.nnode[i] : 0);
-        const int ncol = (int)g->off.size() - 1;
-        if (L.A.size[i] <= SGS_DENSE_MAX && ncol >= SGS_DENSE_MIN_COLORS) {
-          auto d = std::make_unique<DenseSgsD<T>>();
-          d->setup(*g, L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, s);
-          M.cheb.push_back(std::move(d));
+        if (l == 0 && sgs0[i]) {
+          M.cheb.push_back(std::move(sgs0[i]));
         } else {
-          M.cheb.push_back(std::move(g));
+          const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
+          M.cheb.push_back(make_sgs<T>(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s,
+                                       have ? L.gptr[i].get() : nullptr, have ? L.gadj[i].get() : nullptr,
+                                       have ? L.nnode[i] : 0));
         }
       } else {
         auto ch = std::make_unique<ChebD<T>>();
