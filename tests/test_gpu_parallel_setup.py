@@ -53,3 +53,26 @@ def test_parallel_setup_same_bits(name, make, spec, opts):
     assert par.footprint_bytes() > 0
     par.close()
     seq.close()
+
+
+@pytest.mark.parametrize("parallel", [1, 0])
+def test_error_in_a_concurrent_part(parallel):
+    """A singular diagonal entry in the second BGS field (set up on a side
+    thread): the setup fails with ESINGULAR like the sequential one, and the
+    library stays usable."""
+    from paper_1605_01522_amd import NField, nfield
+    print(f"case parallel setup error path parallel={parallel}", flush=True)
+    s = nfgen.tsi2d(nel=20, seed=1)     # both fields above the coarse size
+    B = s.blocks[1][1].tolil()
+    B[3, 3] = 0.0
+    B = B.tocsr()
+    B.eliminate_zeros()
+    B.sort_indices()
+    bad = [[s.blocks[0][0], s.blocks[0][1]], [s.blocks[1][0], B]]
+    with pytest.raises(nfield.NFieldError) as e:
+        NField(s.fields, bad, "BGS(AMG)", parallel_setup=parallel, sweeps=2, order="bwd")
+    assert e.value.code == -3
+    g = NField(s.fields, s.blocks, "BGS(AMG)", parallel_setup=parallel, sweeps=2, order="bwd")
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=torch.device("cuda:0")), rtol=1e-8)
+    assert st[0]["status"] == 0
+    g.close()
