@@ -230,12 +230,24 @@ def run_workload(name, steps, warmup, seed, precision_form):
                 footprint_mb=footprint_mb)
 
 
+def opts_text(opts):
+    """The setup options of a workload other than the field split, as text."""
+    names = {"simplec_mode": {0: "SIMPLE D~ = abs row sums", 1: "SIMPLE D~ = |row sums|", 2: "SIMPLE D~ = diag(A11)"}}
+    parts = []
+    for k, v in opts.items():
+        if k == "split":
+            continue
+        parts.append(names[k][v] if k in names else f"{k}={v}")
+    return ", ".join(parts)
+
+
 def summary(name, r, steps, seed):
     """Compact record of a secondary workload run."""
     import numpy as np
     s, stats = r["system"], r["stats"]
-    return dict(workload=f"{name}: n={s.n} dofs, nnz={s.nnz()}, spec {r['spec']}, GMRES(50) rtol 1e-8, "
-                         f"seed {seed}",
+    extra = opts_text(WORKLOADS[name]["opts"])
+    return dict(workload=f"{name}: n={s.n} dofs, nnz={s.nnz()}, spec {r['spec']}"
+                         f"{', ' + extra if extra else ''}, GMRES(50) rtol 1e-8, seed {seed}",
                 fields=[f.ndof for f in s.fields], value=round(steps / r["elapsed"], 4), unit="solves/s",
                 setup_ms=round(1e3 * float(np.median([t["setup_s"] for t in stats])), 3),
                 solve_ms=round(1e3 * float(np.median([t["solve_s"] for t in stats])), 3),
@@ -357,7 +369,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={s.n} dofs, nnz={s.nnz()}, spec {W['spec']}, "
+        "config": {"workload": f"{args.workload}: n={s.n} dofs, nnz={s.nnz()}, spec {W['spec']}"
+                               f"{', ' + opts_text(W['opts']) if opts_text(W['opts']) else ''}, "
                                f"GMRES(50) rtol 1e-8, seed {args.seed}",
                    "fields": [f.ndof for f in s.fields]},
         "setup_ms": round(1e3 * float(np.median([t["setup_s"] for t in stats])), 3),
