@@ -29,12 +29,13 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     # 3-field FSI-like system: Q1 elastic slab 40x40x8 (S), ALE vector
     # Laplacian (G) and PSPG Q1-Q1 Oseen flow (F) on a 40^3 hex box; degree-1
-    # Chebyshev on S and G, damped SGS (omega 0.65) on F and the SIMPLE
-    # diagonal D~ = diag(A11): the fastest of the settings measured (61
-    # iterations; with the absolute row sums as D~ 78, and then Chebyshev
-    # degree 2 with omega 0.69 94, degree 3 86, omega 0.8 135)
+    # Chebyshev on S and G, damped multicolour Gauss-Seidel on F (omega 0.9,
+    # forward sweeps before the coarse correction, backward after) and the
+    # SIMPLE diagonal D~ = diag(A11): the fastest of the settings measured
+    # (78 iterations at half the sweeps; full symmetric sweeps with omega 0.65
+    # take 61 and more time; with the absolute row sums as D~ 78 more)
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
-                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])",
+                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.9,half=1])",
                   opts=dict(split=[0, 0, 1], simplec_mode=2)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),

@@ -31,7 +31,9 @@
  * order of one BGS / SIMPLE node), "AMG[degree=1]" (Chebyshev smoother degree
  * of one hierarchy; degree 1 is damped Jacobi), "AMG[smoother=sgs,omega=0.69,
  * steps=1]" (symmetric multicolour Gauss-Seidel with damping omega instead of
- * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7).
+ * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7;
+ * "half=1": pre-smoothing sweeps the colours forward only, post-smoothing
+ * backward only, instead of both sweeping forward then backward).
  *
  * All device work runs in the library's own HIP kernels for gfx950, enqueued
  * on the caller's stream (setup and rebuild may also use streams of the

@@ -532,13 +532,16 @@ struct BlockMat {
 //    family of smoothers the paper runs inside its AMG): nodes of one colour
 //    are relaxed together, colours forward then backward; the dofs of one
 //    node are updated together from the values before the node's update.
+//    With half, pre-smoothing (before the coarse correction) sweeps forward
+//    only and post-smoothing backward only; the level smoother tells the
+//    field smoother which of the two it is doing.
 struct Cheb {
   const Csr* A = nullptr;
   std::vector<double> dinv;
   double lambda = 0.0, lo = 0.0, hi = 0.0;
   int degree = 2;
   int kind = 0;                       // 0 Chebyshev, 1 multicolour SGS
-  int bs = 1, steps = 1;
+  int bs = 1, steps = 1, half = 0;
   double omega = 1.0;
   std::vector<std::vector<int>> color_nodes;   // nodes of each colour, ascending
   void setup_sgs(const Csr* A_, int b, double om, int st, uint64_t seed) {
@@ -571,12 +574,15 @@ struct Cheb {
       for (int q = 0; q < bs; ++q) x[u * bs + q] += upd[q];
     }
   }
-  void apply_sgs(const double* b, double* x, bool zero_guess) const {
+  // pre: this application is pre-smoothing (only matters with half)
+  void apply_sgs(const double* b, double* x, bool zero_guess, bool pre) const {
     if (zero_guess) std::fill(x, x + A->nr, 0.0);
     const int nc = (int)color_nodes.size();
     for (int st = 0; st < steps; ++st) {
-      for (int c = 0; c < nc; ++c) relax_color(c, b, x);
-      for (int c = nc - 1; c >= 0; --c) relax_color(c, b, x);
+      if (!half || pre)
+        for (int c = 0; c < nc; ++c) relax_color(c, b, x);
+      if (!half || !pre)
+        for (int c = nc - 1; c >= 0; --c) relax_color(c, b, x);
     }
   }
   void setup(const Csr* A_, double lam, const Opts& o) {
@@ -592,8 +598,8 @@ struct Cheb {
     lo = lam / o.cheb_ratio;
     degree = o.cheb_degree;
   }
-  void apply(const double* b, double* x, bool zero_guess) const {
-    if (kind == 1) { apply_sgs(b, x, zero_guess); return; }
+  void apply(const double* b, double* x, bool zero_guess, bool pre = true) const {
+    if (kind == 1) { apply_sgs(b, x, zero_guess, pre); return; }
     const int n = A->nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     std::vector<double> r(n), d(n);
@@ -765,7 +771,7 @@ struct LevelSmoother {
   DenseLU schur_lu;
   bool schur_direct = true;
   Cheb schur_cheb;
-  void bgs_sweep(int f0, int f1, const double* r, double* d, int ord) const {
+  void bgs_sweep(int f0, int f1, const double* r, double* d, int ord, bool pre) const {
     std::vector<int> o = A->offsets();
     std::vector<int> seq;
     for (int i = f0; i < f1; ++i) seq.push_back(i);
@@ -780,7 +786,7 @@ struct LevelSmoother {
           spmv(*A->at(i, j), d + (o[j] - o[f0]), y.data());
           for (int q = 0; q < A->size[i]; ++q) t[q] -= y[q];
         }
-      cheb[i].apply(t.data(), d + (o[i] - o[f0]), true);
+      cheb[i].apply(t.data(), d + (o[i] - o[f0]), true, pre);
       done[i] = 1;
     }
   }
@@ -795,12 +801,13 @@ struct LevelSmoother {
     }
     // symmetric order: forward before the coarse correction, backward after
     const int ord = order == 2 ? (zero_guess ? 0 : 1) : order;
+    // pre-smoothing starts from zero, post-smoothing does not
     if (kind == 0) {
-      bgs_sweep(0, N, r.data(), d.data(), ord);
+      bgs_sweep(0, N, r.data(), d.data(), ord, zero_guess);
     } else {
       std::vector<int> o = A->offsets();
       const int n1 = o[ngroup1], n2 = n - n1;
-      bgs_sweep(0, ngroup1, r.data(), d.data(), ord);              // predictor
+      bgs_sweep(0, ngroup1, r.data(), d.data(), ord, zero_guess);  // predictor
       std::vector<double> t(r.begin() + n1, r.end()), y(n2);
       for (int j = 0; j < ngroup1; ++j)
         if (A->at(ngroup1, j)) {
@@ -976,7 +983,7 @@ struct SimpleSolver : Solver {
 // in brackets: "BGS[sweeps=2,order=bwd](AMG)".
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -1009,6 +1016,10 @@ struct Parser {
         else if (k == "smoother") sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : -9;
         else if (k == "omega") sp.omega = atof(v.c_str());
         else if (k == "steps") sp.steps = atoi(v.c_str());
+        else if (k == "half") {
+          sp.half = atoi(v.c_str());
+          if (sp.half != 0 && sp.half != 1) throw Error(EINVAL_, "spec: bad value " + v);
+        }
         else throw Error(EINVAL_, "spec: unknown parameter " + k);
         if (sp.smoother == -9 || (k == "omega" && !(sp.omega > 0.0 && sp.omega < 2.0)) ||
             (k == "steps" && sp.steps < 1))
@@ -1085,8 +1096,12 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
     M.cheb.resize(sub.N);
     const int nchb = M.kind == 1 ? sub.N - 1 : sub.N;
     for (int i = 0; i < nchb; ++i) {
-      if (sgs) M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
-      else M.cheb[i].setup(L.A.at(i, i), L.lambda[i], lo);
+      if (sgs) {
+        M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
+        M.cheb[i].half = amg.half;
+      } else {
+        M.cheb[i].setup(L.A.at(i, i), L.lambda[i], lo);
+      }
     }
     if (M.kind == 1) {
       if (sub.N < 2) throw Error(EINVAL_, "AMG(SIMPLE) needs at least two fields");
@@ -1561,7 +1576,7 @@ int orc_color_nodes(int32_t nnode, const int64_t* gptr, const int32_t* gadj, uin
 
 // one application of the multicolour SGS smoother (for splitting-form tests)
 int orc_sgs(int32_t n, const int64_t* rowptr, const int32_t* col, const double* val, int32_t b, double omega,
-            int32_t steps, uint64_t seed, const double* rhs, double* x, int32_t zero_guess) {
+            int32_t steps, uint64_t seed, const double* rhs, double* x, int32_t zero_guess, int32_t half) {
   try {
     orc::Csr A;
     A.nr = A.nc = n;
@@ -1570,7 +1585,8 @@ int orc_sgs(int32_t n, const int64_t* rowptr, const int32_t* col, const double* 
     A.val.assign(val, val + rowptr[n]);
     orc::Cheb c;
     c.setup_sgs(&A, b, omega, steps, seed);
-    c.apply(rhs, x, zero_guess != 0);
+    c.half = half;
+    c.apply(rhs, x, zero_guess != 0, zero_guess != 0);
     return 0;
   } catch (orc::Error& e) { g_err = e.what(); return e.code; }
 }

@@ -83,6 +83,9 @@ template <class T>
 struct FieldSmootherD {
   virtual ~FieldSmootherD() {}
   virtual void apply(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) = 0;
+  // the level smoother's phase for the next applications: pre-smoothing
+  // (before the coarse correction) or post-smoothing
+  virtual void set_phase(bool pre) { (void)pre; }
 };
 
 // Chebyshev smoother on D^-1 A over [lambda/ratio, boost*lambda]: three-term
@@ -247,11 +250,15 @@ struct SgsD : FieldSmootherD<T> {
     prof_end(slot, s, ((lanes * 16 + b2) * 10 + mode) * 10 + (sizeof(T) == 4 ? 1 : 0),
              sweep_bytes + nrhs * sweep_bytes_x, launches);
   }
+  // half: pre-smoothing sweeps forward only, post-smoothing backward only
+  int half = 0;
+  bool pre = true;
+  void set_phase(bool p) override { pre = p; }
   void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
     if (zero_guess) fillm<T>(x, ldx, (T)0, n, nrhs, s);
     for (int st = 0; st < steps; ++st) {
-      sweep(true, rhs, ldr, x, ldx, nrhs, s);
-      sweep(false, rhs, ldr, x, ldx, nrhs, s);
+      if (!half || pre) sweep(true, rhs, ldr, x, ldx, nrhs, s);
+      if (!half || !pre) sweep(false, rhs, ldr, x, ldx, nrhs, s);
     }
   }
 };
@@ -342,6 +349,8 @@ struct LevelSmootherD {
   MBuf<T> ts, u;
   void smooth(const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) {
     const int N = A->N;
+    // pre-smoothing starts from zero, post-smoothing does not
+    for (auto& c : cheb) c->set_phase(zero_guess);
     if (N == 1) {
       cheb[0]->apply(b, ldb, x, ldx, nrhs, zero_guess, s);
       return;
@@ -533,7 +542,7 @@ struct SimpleSolverD : Solver<T> {
 // ================================================================== spec
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -577,6 +586,9 @@ static Spec parse_spec(const std::string& str) {
         } else if (k == "steps") {
           sp.steps = atoi(v.c_str());
           NF_CHECK(sp.steps >= 1, NFIELD_EINVAL, "spec: steps must be >= 1");
+        } else if (k == "half") {
+          sp.half = atoi(v.c_str());
+          NF_CHECK(sp.half == 0 || sp.half == 1, NFIELD_EINVAL, "spec: half must be 0 or 1");
         } else {
           throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
         }
@@ -827,13 +839,16 @@ struct ChebSolverD : Solver<T> {
 };
 
 // Multicolour Gauss-Seidel of one field on one level (the node graph of A is
-// computed here unless given); small many-colour levels as the dense map.
+// computed here unless given); small many-colour levels as the dense map of
+// the full symmetric sweep (not with half sweeps).
 template <class T>
 static std::unique_ptr<FieldSmootherD<T>> make_sgs(const DCsr* A, int b, const double* dinv64, double omega, int steps,
                                                    uint64_t seed, hipStream_t s, const DBuf<int>* gp, const DBuf<int>* ga,
-                                                   int nn) {
+                                                   int nn, int half = 0) {
   auto g = std::make_unique<SgsD<T>>();
   g->setup(A, b, dinv64, omega, steps, seed, s, gp, ga, nn);
+  g->half = half;
+  if (half) return g;
   const int ncol = (int)g->off.size() - 1;
   if (A->nr <= SGS_DENSE_MAX && ncol >= SGS_DENSE_MIN_COLORS) {
     auto d = std::make_unique<DenseSgsD<T>>();
@@ -878,7 +893,7 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
         NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, st));
         NF_HIP(hipStreamSynchronize(st));
         if (z) continue;   // a zero diagonal entry: the hierarchy's check reports it
-        sgs0[i] = make_sgs<T>(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0);
+        sgs0[i] = make_sgs<T>(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0, amg.half);
         NF_HIP(hipStreamSynchronize(st));
       }
     });
@@ -923,7 +938,7 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
           const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
           M.cheb.push_back(make_sgs<T>(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s,
                                        have ? L.gptr[i].get() : nullptr, have ? L.gadj[i].get() : nullptr,
-                                       have ? L.nnode[i] : 0));
+                                       have ? L.nnode[i] : 0, amg.half));
         }
       } else {
         auto ch = std::make_unique<ChebD<T>>();

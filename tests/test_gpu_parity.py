@@ -107,7 +107,9 @@ def test_mono_amg_hierarchy_parity(dev):
 SPECS = ["BGS(AMG)", "BGS[order=fwd](AMG)", "BGS[sweeps=3,order=sym](AMG)", "BGS(LU)",
          "SIMPLE(AMG;AMG)", "SIMPLE(AMG;LU)", "AMG(BGS)", "AMG(BGS[order=fwd])",
          "BGS(AMG[smoother=sgs,omega=0.8])", "BGS(AMG[smoother=sgs,omega=1.1,steps=2])",
-         "AMG[smoother=sgs,omega=0.9](BGS)", "BGS(AMG[degree=3])"]
+         "AMG[smoother=sgs,omega=0.9](BGS)", "BGS(AMG[degree=3])",
+         "BGS(AMG[smoother=sgs,omega=0.9,half=1])", "AMG[smoother=sgs,omega=0.9,half=1](BGS)",
+         "BGS(AMG[smoother=sgs,omega=0.8,half=1,steps=2])"]
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -214,15 +216,16 @@ def test_singular_inputs(dev):
 
 
 # ------------------------------------------------- 3-field FSI-like system
-# the benchmarked configuration, and the one it was tuned from
-FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])"
+# the benchmarked configuration, and the ones it was tuned from
+FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.9,half=1])"
+FSI_SPEC_FULL = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])"
 FSI_SPEC_D2 = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 FSI_OPTS = dict(split=[0, 0, 1], simplec_mode=2)
 FSI_OPTS_ABS = dict(split=[0, 0, 1])
 
 
-@pytest.mark.parametrize("n,layers,spec,opts", [(6, 2, FSI_SPEC, FSI_OPTS), (6, 2, FSI_SPEC_D2, FSI_OPTS_ABS),
-                                                (12, 3, FSI_SPEC, FSI_OPTS)])
+@pytest.mark.parametrize("n,layers,spec,opts", [(6, 2, FSI_SPEC, FSI_OPTS), (6, 2, FSI_SPEC_FULL, FSI_OPTS),
+                                                (6, 2, FSI_SPEC_D2, FSI_OPTS_ABS), (12, 3, FSI_SPEC, FSI_OPTS)])
 def test_fsi_hierarchy_precond_and_solution_parity(dev, n, layers, spec, opts):
     _say(f"case fsi3d n={n} layers={layers} {spec} {opts}")
     s = nfgen.fsi3d(n=n, layers=layers, seed=n)

@@ -265,11 +265,17 @@ def test_chebyshev_closed_form(degree):
 
 
 # ---------------------------------------------------------------- V-cycle
-def test_vcycle_symmetric_contraction():
+@pytest.mark.parametrize("spec", ["AMG", "AMG[smoother=sgs,omega=0.9]", "AMG[smoother=sgs,omega=0.9,half=1]",
+                                  "AMG[smoother=sgs,omega=1.1,half=1,steps=2]"])
+def test_vcycle_symmetric_contraction(spec):
+    """With R = P^T, an exact coarse solve and a post-smoother that is the
+    adjoint of the pre-smoother (the same Chebyshev polynomial, or the
+    backward colour sweep after the forward one), the V-cycle is a symmetric
+    operator and an A-norm contraction (Sec. 3.1)."""
     s = nfgen.tsi2d(nel=10)
     sub = [s.fields[1]]
     blocks = [[s.blocks[1][1]]]
-    o = Oracle(sub, blocks, "AMG", coarse_max=20)
+    o = Oracle(sub, blocks, spec, coarse_max=20)
     assert o.nlevels(0) >= 2
     n = s.fields[1].ndof
     M = o.precond_apply(np.eye(n))          # row i = M e_i  (M symmetric)
@@ -277,6 +283,20 @@ def test_vcycle_symmetric_contraction():
     assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
     ev = sla.eigvals(np.eye(n) - M.T @ A).real
     assert ev.min() > -1e-10 and ev.max() < 1.0
+
+
+def test_vcycle_half_sweeps_differ_by_phase():
+    """Half sweeps taken in the same direction before and after the coarse
+    correction would make the V-cycle non-symmetric: the symmetric result
+    above depends on the post-smoother sweeping backward."""
+    s = nfgen.tsi2d(nel=10)
+    A = s.blocks[1][1]
+    n = A.shape[0]
+    E = np.eye(n)
+    fwd = np.array([oracle.sgs(A, 1, E[i], omega=0.9, half=1) for i in range(n)])       # forward only
+    bwd = np.array([oracle.sgs(A, 1, E[i], omega=0.9, x0=np.zeros(n), half=1) for i in range(n)])
+    assert np.abs(fwd - bwd.T).max() < 1e-12 * np.abs(fwd).max()   # adjoint pair
+    assert np.abs(fwd - fwd.T).max() > 1e-3 * np.abs(fwd).max()    # not symmetric alone
 
 
 # -------------------------------------------------------------------- BGS
@@ -520,3 +540,8 @@ def test_sgs_equals_colour_splitting(field, b, omega):
     y1 = np.linalg.solve(D / omega + Lf, rhs)
     y2 = np.linalg.solve(D / omega + Lb, rhs + (D / omega - D - Ub) @ y1)
     assert np.abs(oracle.sgs(A, b, rhs, omega=omega) - y2).max() < 1e-11 * np.abs(y2).max()
+    # half sweeps: forward only from a zero guess, backward only otherwise
+    assert np.abs(oracle.sgs(A, b, rhs, omega=omega, half=1) - y1).max() < 1e-11 * np.abs(y1).max()
+    z1 = np.linalg.solve(D / omega + Lb, rhs + (D / omega - D - Ub) @ x0)
+    got = oracle.sgs(A, b, rhs, omega=omega, x0=x0, half=1)
+    assert np.abs(got - z1).max() < 1e-11 * np.abs(z1).max()
