@@ -18,6 +18,7 @@
 #include <climits>
 
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace nf {
 
@@ -65,6 +66,14 @@ __global__ __launch_bounds__(64) void k_bsr_keys(int bc, const int* __restrict__
   __shared__ int keys[BSR_CAP];
   const int i = blockIdx.x, lane = threadIdx.x;
   const int e0 = ptr[i * BR], e1 = ptr[(i + 1) * BR], E = e1 - e0;
+  {  // rows with the block columns of the first row: those, ascending
+    const int n0 = group_runs(e0, ptr[i * BR + 1], bc, col, -1, nullptr);
+    if (rows_share_groups(ptr, i * BR, BR, bc, col, n0)) {
+      group_runs(e0, ptr[i * BR + 1], bc, col, -1, ucol + e0);
+      if (lane == 0) cnt[i] = n0;
+      return;
+    }
+  }
   if (E <= BSR_CAP) {
     int ts = 1;
     while (ts < E) ts <<= 1;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace nf {
 
@@ -751,13 +752,11 @@ void power_start(double* v, int64_t n, uint64_t seed, hipStream_t s) {
 
 // ================================================================ node graph
 constexpr int MAXB = 8;
-// node u ~ v (u != v) iff some stored entry couples their dofs; one thread
-// per node merges the b sorted rows of the node by node index.
-template <bool FILL>
-__global__ void k_node_graph(int nnode, int b, const int* __restrict__ ptr, const int* __restrict__ col, int* cnt_or_off,
-                             int* adj) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= nnode) return;
+// node u ~ v (u != v) iff some stored entry couples their dofs.  The
+// neighbours come out in ascending order.
+//
+// Serial form (one lane): merge the b sorted rows of the node by node index.
+__device__ int node_merge(int u, int b, const int* __restrict__ ptr, const int* __restrict__ col, int* adj) {
   int p[MAXB], e[MAXB];
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
@@ -765,7 +764,6 @@ __global__ void k_node_graph(int nnode, int b, const int* __restrict__ ptr, cons
     e[c] = c < b ? ptr[u * b + c + 1] : 0;
   }
   int cnt = 0;
-  const int out = FILL ? cnt_or_off[u] : 0;
   while (true) {
     int mn = INT_MAX;
 #pragma unroll
@@ -776,11 +774,35 @@ __global__ void k_node_graph(int nnode, int b, const int* __restrict__ ptr, cons
     for (int c = 0; c < MAXB; ++c)
       while (p[c] < e[c] && col[p[c]] / b == mn) ++p[c];
     if (mn != u) {
-      if (FILL) adj[out + cnt] = mn;
+      if (adj) adj[cnt] = mn;
       ++cnt;
     }
   }
-  if (!FILL) cnt_or_off[u] = cnt;
+  return cnt;
+}
+// Wavefront form: when every row of the node couples to the same set of
+// nodes (the usual case for node-blocked operators), that set is the first
+// row's, found with one pass over each row: each row has as many distinct
+// nodes as the first and each of its nodes occurs in the first (binary
+// search).  Otherwise lane 0 merges.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_node_graph(int nnode, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                    int* cnt_or_off, int* adj) {
+  const int u = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (u >= nnode) return;
+  const int p0 = ptr[u * b], e0 = ptr[u * b + 1];
+  const int n0 = group_runs(p0, e0, b, col, -1, nullptr);
+  const bool same = rows_share_groups(ptr, u * b, b, b, col, n0);
+  if (same) {
+    if (FILL) group_runs(p0, e0, b, col, u, adj + cnt_or_off[u]);
+    else {
+      const int c = group_runs(p0, e0, b, col, u, nullptr);
+      if (lane == 0) cnt_or_off[u] = c;
+    }
+  } else if (lane == 0) {
+    const int c = node_merge(u, b, ptr, col, FILL ? adj + cnt_or_off[u] : nullptr);
+    if (!FILL) cnt_or_off[u] = c;
+  }
 }
 void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nnode_out, hipStream_t s) {
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "block size must be between 1 and 8");
@@ -789,10 +811,10 @@ void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nno
   *nnode_out = nn;
   DBuf<int> cnt(nn + 1);
   gptr.alloc(nn + 1);
-  if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(cdiv(nn, 4)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
   const int64_t tot = exclusive_scan(cnt.p, gptr.p, nn, s);
   gadj.alloc(tot > 0 ? tot : 1);
-  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(cdiv(nn, 4)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
   NF_HIP(hipStreamSynchronize(s));
 }
 
@@ -1575,29 +1597,42 @@ __global__ void k_ptent_pattern(int ndof, int b, int k, const int* __restrict__ 
   const int a = agg[r / b];
   for (int j = 0; j < k; ++j) col[r * k + j] = a * k + j;
 }
-// One wavefront per aggregate: order its nodes (lane 0), copy the
+// One wavefront per aggregate: order its nodes (each lane ranks some of the
+// members against all of them; the members are distinct node ids), copy the
 // near-nullspace rows, then modified Gram-Schmidt with positive R diagonal
 // (each lane owns a strided set of the aggregate's rows; inner products are
 // wavefront sums); a column whose remaining norm is <= 1e-12 ||B_a||_F is
-// dead: zero in Q, zero row in R, flagged.
+// dead: zero in Q, zero row in R, flagged.  Aggregates of up to
+// TQR_LDS_MEMBERS nodes are ranked and kept in LDS, larger ones in `sorted`.
+constexpr int TQR_LDS_MEMBERS = 1024;
 __global__ __launch_bounds__(64) void k_tentative_qr(int nagg, int b, int k, int ndof, const int* __restrict__ aoff,
-                                                     int* members, const double* __restrict__ B, double* __restrict__ Q,
+                                                     const int* __restrict__ members, int* __restrict__ sorted,
+                                                     const double* __restrict__ B, double* __restrict__ Q,
                                                      double* __restrict__ Bc, int* __restrict__ dead) {
+  __shared__ int raw[TQR_LDS_MEMBERS], ord[TQR_LDS_MEMBERS];
   const int a = blockIdx.x, lane = threadIdx.x;
   if (a >= nagg) return;
-  const int m0 = aoff[a], m1 = aoff[a + 1];
-  if (lane == 0)
-    for (int i = m0 + 1; i < m1; ++i) {   // insertion sort of the member nodes
-      const int v = members[i];
-      int j = i - 1;
-      while (j >= m0 && members[j] > v) { members[j + 1] = members[j]; --j; }
-      members[j + 1] = v;
-    }
+  const int m0 = aoff[a], m1 = aoff[a + 1], m = m1 - m0;
+  const bool in_lds = m <= TQR_LDS_MEMBERS;
+  const int* src = members + m0;
+  if (in_lds) {
+    for (int t = lane; t < m; t += 64) raw[t] = members[m0 + t];
+    __syncthreads();
+    src = raw;
+  }
+  for (int t = lane; t < m; t += 64) {
+    const int v = src[t];
+    int rk = 0;
+    for (int i = 0; i < m; ++i) rk += src[i] < v ? 1 : 0;
+    if (in_lds) ord[rk] = v;
+    else sorted[m0 + rk] = v;
+  }
   __syncthreads();
+  const int* mem = in_lds ? ord : sorted + m0;
   const int rows = (m1 - m0) * b, nc = nagg * k;
   double fro = 0.0;
   for (int t = lane; t < rows; t += 64) {
-    const int r = members[m0 + t / b] * b + t % b;
+    const int r = mem[t / b] * b + t % b;
     for (int j = 0; j < k; ++j) {
       const double v = B[(int64_t)j * ndof + r];
       Q[(int64_t)r * k + j] = v;
@@ -1611,25 +1646,25 @@ __global__ __launch_bounds__(64) void k_tentative_qr(int nagg, int b, int k, int
     for (int l = 0; l < j; ++l) {
       double rr = 0.0;
       for (int t = lane; t < rows; t += 64) {
-        const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+        const int64_t r = (int64_t)(mem[t / b] * b + t % b) * k;
         rr += Q[r + l] * Q[r + j];
       }
       rr = wave_sum(rr);
       R[l * MAXB + j] = rr;
       for (int t = lane; t < rows; t += 64) {
-        const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+        const int64_t r = (int64_t)(mem[t / b] * b + t % b) * k;
         Q[r + j] -= rr * Q[r + l];
       }
     }
     double nr = 0.0;
     for (int t = lane; t < rows; t += 64) {
-      const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+      const int64_t r = (int64_t)(mem[t / b] * b + t % b) * k;
       nr += Q[r + j] * Q[r + j];
     }
     nr = sqrt(wave_sum(nr));
     const bool is_dead = nr <= 1e-12 * fro;
     for (int t = lane; t < rows; t += 64) {
-      const int64_t r = (int64_t)(members[m0 + t / b] * b + t % b) * k;
+      const int64_t r = (int64_t)(mem[t / b] * b + t % b) * k;
       Q[r + j] = is_dead ? 0.0 : Q[r + j] / nr;
     }
     if (is_dead) {
@@ -1653,7 +1688,8 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
   NF_CHECK(k >= 1 && k <= MAXB, NFIELD_EINVAL, "near-nullspace dimension must be between 1 and 8");
   const int ndof = nnode * b, nc = nagg * k;
   NF_CHECK((int64_t)ndof * k < INT_MAX, NFIELD_ENOMEM, "tentative prolongator too large");
-  DBuf<int> cnt(nagg + 1), aoff(nagg + 1), cursor(nagg + 1), members(nnode > 0 ? nnode : 1), dflag(nc + 1), doff(nc + 1);
+  DBuf<int> cnt(nagg + 1), aoff(nagg + 1), cursor(nagg + 1), members(nnode > 0 ? nnode : 1), sorted(nnode > 0 ? nnode : 1),
+      dflag(nc + 1), doff(nc + 1);
   fill<int>(cnt.p, 0, nagg + 1, s);
   fill<int>(cursor.p, 0, nagg + 1, s);
   const int g = cdiv(nnode, 256);
@@ -1669,7 +1705,7 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
   Bc.alloc((size_t)k * nc);
   hipLaunchKernelGGL(k_ptent_pattern, dim3(cdiv(ndof + 1, 256)), dim3(256), 0, s, ndof, b, k, agg, P.ptr.p, P.col.p);
   if (nagg > 0)
-    hipLaunchKernelGGL(k_tentative_qr, dim3(nagg), dim3(64), 0, s, nagg, b, k, ndof, aoff.p, members.p, B, P.val.p, Bc.p,
+    hipLaunchKernelGGL(k_tentative_qr, dim3(nagg), dim3(64), 0, s, nagg, b, k, ndof, aoff.p, members.p, sorted.p, B, P.val.p, Bc.p,
                        dflag.p);
   const int ndead = (int)exclusive_scan(dflag.p, doff.p, nc, s);
   dead.alloc(ndead > 0 ? ndead : 1);
