@@ -38,24 +38,6 @@ static void iota(double* v, int64_t n, hipStream_t s) {
 // the range [ptr[i br], ptr[(i + 1) br]).
 constexpr int BSR_CAP = 2048;
 
-// ascending bitonic sort of keys[0, ts) (ts a power of two) by one wavefront
-__device__ void wave_bitonic(int* keys, int ts, int lane) {
-  for (int kk = 2; kk <= ts; kk <<= 1)
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int t = lane; t < ts; t += 64) {
-        const int u = t ^ j;
-        if (u > t) {
-          const int x = keys[t], y = keys[u];
-          if ((x > y) == ((t & kk) == 0)) {
-            keys[t] = y;
-            keys[u] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-}
-
 // one wavefront per block row: its distinct block columns, ascending, into
 // the scratch at the row's first entry offset (it has room: one slot per
 // entry), their number into cnt[i].  Up to BSR_CAP entries are sorted in
@@ -67,12 +49,17 @@ __global__ __launch_bounds__(64) void k_bsr_keys(int bc, const int* __restrict__
   const int i = blockIdx.x, lane = threadIdx.x;
   const int e0 = ptr[i * BR], e1 = ptr[(i + 1) * BR], E = e1 - e0;
   {  // rows with the block columns of the first row: those, ascending
-    const int n0 = group_runs(e0, ptr[i * BR + 1], bc, col, -1, nullptr);
-    if (rows_share_groups(ptr, i * BR, BR, bc, col, n0)) {
-      group_runs(e0, ptr[i * BR + 1], bc, col, -1, ucol + e0);
+    int n0;
+    if (rows_share_groups(ptr, i * BR, BR, bc, col, keys, BSR_CAP, n0)) {
+      __syncthreads();
+      if (n0 <= BSR_CAP)
+        for (int t = lane; t < n0; t += 64) ucol[e0 + t] = keys[t];
+      else   // one row (BR = 1) with more block columns than keys holds
+        group_runs(e0, ptr[i * BR + 1], bc, col, -1, ucol + e0);
       if (lane == 0) cnt[i] = n0;
       return;
     }
+    __syncthreads();   // keys held the first row's block columns
   }
   if (E <= BSR_CAP) {
     int ts = 1;

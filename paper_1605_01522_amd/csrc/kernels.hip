@@ -780,29 +780,46 @@ __device__ int node_merge(int u, int b, const int* __restrict__ ptr, const int* 
   }
   return cnt;
 }
-// Wavefront form: when every row of the node couples to the same set of
-// nodes (the usual case for node-blocked operators), that set is the first
-// row's, found with one pass over each row: each row has as many distinct
-// nodes as the first and each of its nodes occurs in the first (binary
-// search).  Otherwise lane 0 merges.
+// One wavefront per node.  When every row of the node couples to the same
+// set of nodes (the usual case for node-blocked operators), that set is the
+// first row's, found with one pass over each row: each row's distinct nodes
+// in order are the first row's.  Otherwise (rows of a constrained dof, say) the node
+// indices of all its rows are sorted in LDS and the runs counted, or, beyond
+// NG_CAP entries, lane 0 merges.
+constexpr int NG_CAP = 2048;
 template <bool FILL>
-__global__ __launch_bounds__(256) void k_node_graph(int nnode, int b, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                    int* cnt_or_off, int* adj) {
-  const int u = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+__global__ __launch_bounds__(64) void k_node_graph(int nnode, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   int* cnt_or_off, int* adj) {
+  __shared__ int keys[NG_CAP];
+  const int u = blockIdx.x, lane = threadIdx.x;
   if (u >= nnode) return;
   const int p0 = ptr[u * b], e0 = ptr[u * b + 1];
-  const int n0 = group_runs(p0, e0, b, col, -1, nullptr);
-  const bool same = rows_share_groups(ptr, u * b, b, b, col, n0);
-  if (same) {
-    if (FILL) group_runs(p0, e0, b, col, u, adj + cnt_or_off[u]);
-    else {
-      const int c = group_runs(p0, e0, b, col, u, nullptr);
-      if (lane == 0) cnt_or_off[u] = c;
+  int* out = FILL ? adj + cnt_or_off[u] : nullptr;
+  int c, n0;
+  if (rows_share_groups(ptr, u * b, b, b, col, keys, NG_CAP, n0)) {
+    c = group_runs(p0, e0, b, col, u, out);
+  } else {
+    __syncthreads();   // keys held the first row's nodes
+    const int E = ptr[u * b + b] - p0;
+    if (E <= NG_CAP) {
+      int ts = 1;
+      while (ts < E) ts <<= 1;
+      for (int t = lane; t < ts; t += 64) keys[t] = t < E ? col[p0 + t] / b : INT_MAX;
+      __syncthreads();
+      wave_bitonic(keys, ts, lane);
+      c = 0;
+      for (int t0 = 0; t0 < E; t0 += 64) {
+        const int t = t0 + lane;
+        const bool first = t < E && (t == 0 || keys[t - 1] != keys[t]) && keys[t] != u;
+        const unsigned long long bal = __ballot(first);
+        if (out && first) out[c + __popcll(bal & ((1ull << lane) - 1ull))] = keys[t];
+        c += __popcll(bal);
+      }
+    } else {
+      c = lane == 0 ? node_merge(u, b, ptr, col, out) : 0;
     }
-  } else if (lane == 0) {
-    const int c = node_merge(u, b, ptr, col, FILL ? adj + cnt_or_off[u] : nullptr);
-    if (!FILL) cnt_or_off[u] = c;
   }
+  if (!FILL && lane == 0) cnt_or_off[u] = c;
 }
 void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nnode_out, hipStream_t s) {
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "block size must be between 1 and 8");
@@ -811,10 +828,10 @@ void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nno
   *nnode_out = nn;
   DBuf<int> cnt(nn + 1);
   gptr.alloc(nn + 1);
-  if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(cdiv(nn, 4)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
   const int64_t tot = exclusive_scan(cnt.p, gptr.p, nn, s);
   gadj.alloc(tot > 0 ? tot : 1);
-  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(cdiv(nn, 4)), dim3(256), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
+  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
   NF_HIP(hipStreamSynchronize(s));
 }
 
@@ -980,6 +997,8 @@ __global__ void k_color_rev(int n, const int* __restrict__ gp, const int* __rest
 // neighbours per node; otherwise both stay in global memory.
 constexpr int COLOR_LDS_NODES = 73728;
 constexpr int COLOR_LPN = 4;
+// neighbour loads a lane issues together before using them
+constexpr int COLOR_BATCH = 8;
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_color_frontier(int n, const int* __restrict__ gp, const int* __restrict__ ga,
@@ -1010,14 +1029,26 @@ __global__ __launch_bounds__(1024) void k_color_frontier(int n, const int* __res
     for (int i0 = 0; i0 < m; i0 += NGRP) {
       const int i = i0 + grp;
       const int u = i < m ? cur[i] : -1;
+      int g0 = 0, g1 = 0, r0 = 0, r1 = 0;
+      if (u >= 0) {
+        g0 = gp[u];
+        g1 = gp[u + 1];
+        r0 = rptr[u];
+        r1 = rptr[u + 1];
+      }
       uint64_t mask[4] = {0, 0, 0, 0};
-      if (u >= 0)
-        for (int p = gp[u] + sub; p < gp[u + 1]; p += COLOR_LPN) {
-          const int v = ga[p];
+      for (int pb = g0 + sub; pb < g1; pb += COLOR_BATCH * COLOR_LPN) {
+        int vv[COLOR_BATCH];   // the batch's loads issued together
+#pragma unroll
+        for (int q = 0; q < COLOR_BATCH; ++q) vv[q] = pb + q * COLOR_LPN < g1 ? ga[pb + q * COLOR_LPN] : INT_MAX;
+#pragma unroll
+        for (int q = 0; q < COLOR_BATCH; ++q) {
+          const int v = vv[q];
           if (v >= u) continue;
           const int c = LDS ? (int)cl[v] : __hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           if (c >= 0 && c < 256) mask[c >> 6] |= 1ull << (c & 63);
         }
+      }
 #pragma unroll
       for (int w = 0; w < 4; ++w)
 #pragma unroll
@@ -1037,16 +1068,23 @@ __global__ __launch_bounds__(1024) void k_color_frontier(int n, const int* __res
       // the colour is stored before any waiting node can be released
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
-      for (int p = rptr[u] + sub; p < rptr[u + 1]; p += COLOR_LPN) {
-        const int w = radj[p];
-        bool last;
-        if (LDS) {
-          const int sh = 8 * (w & 3);
-          last = ((atomicSub(&wt[w >> 2], 1u << sh) >> sh) & 0xffu) == 1u;
-        } else {
-          last = atomicSub(&wait[w], 1) == 1;
+      for (int pb = r0 + sub; pb < r1; pb += COLOR_BATCH * COLOR_LPN) {
+        int ww[COLOR_BATCH];
+#pragma unroll
+        for (int q = 0; q < COLOR_BATCH; ++q) ww[q] = pb + q * COLOR_LPN < r1 ? radj[pb + q * COLOR_LPN] : -1;
+#pragma unroll
+        for (int q = 0; q < COLOR_BATCH; ++q) {
+          const int w = ww[q];
+          if (w < 0) continue;
+          bool last;
+          if (LDS) {
+            const int sh = 8 * (w & 3);
+            last = ((atomicSub(&wt[w >> 2], 1u << sh) >> sh) & 0xffu) == 1u;
+          } else {
+            last = atomicSub(&wait[w], 1) == 1;
+          }
+          if (last) nxt[atomicAdd(&nf_next, 1)] = w;
         }
-        if (last) nxt[atomicAdd(&nf_next, 1)] = w;
       }
     }
     coloured += m;
@@ -1085,14 +1123,26 @@ __global__ __launch_bounds__(256) void k_color_round(const int* __restrict__ gp,
   for (int i0 = 0; i0 < m; i0 += ngrp) {
     const int i = i0 + grp;
     const int u = i < m ? cur[i] : -1;
+    int g0 = 0, g1 = 0, r0 = 0, r1 = 0;
+    if (u >= 0) {
+      g0 = gp[u];
+      g1 = gp[u + 1];
+      r0 = rptr[u];
+      r1 = rptr[u + 1];
+    }
     uint64_t mask[4] = {0, 0, 0, 0};
-    if (u >= 0)
-      for (int p = gp[u] + sub; p < gp[u + 1]; p += COLOR_LPN) {
-        const int v = ga[p];
+    for (int pb = g0 + sub; pb < g1; pb += COLOR_BATCH * COLOR_LPN) {
+      int vv[COLOR_BATCH];
+#pragma unroll
+      for (int q = 0; q < COLOR_BATCH; ++q) vv[q] = pb + q * COLOR_LPN < g1 ? ga[pb + q * COLOR_LPN] : INT_MAX;
+#pragma unroll
+      for (int q = 0; q < COLOR_BATCH; ++q) {
+        const int v = vv[q];
         if (v >= u) continue;
         const int c = color[v];
         if (c >= 0 && c < 256) mask[c >> 6] |= 1ull << (c & 63);
       }
+    }
 #pragma unroll
     for (int w = 0; w < 4; ++w)
 #pragma unroll
@@ -1106,9 +1156,13 @@ __global__ __launch_bounds__(256) void k_color_round(const int* __restrict__ gp,
       c = 0;
     }
     if (sub == 0) color[u] = c;
-    for (int p = rptr[u] + sub; p < rptr[u + 1]; p += COLOR_LPN) {
-      const int w = radj[p];
-      if (atomicSub(&wait[w], 1) == 1) nxt[atomicAdd(nnxt, 1)] = w;
+    for (int pb = r0 + sub; pb < r1; pb += COLOR_BATCH * COLOR_LPN) {
+      int ww[COLOR_BATCH];
+#pragma unroll
+      for (int q = 0; q < COLOR_BATCH; ++q) ww[q] = pb + q * COLOR_LPN < r1 ? radj[pb + q * COLOR_LPN] : -1;
+#pragma unroll
+      for (int q = 0; q < COLOR_BATCH; ++q)
+        if (ww[q] >= 0 && atomicSub(&wait[ww[q]], 1) == 1) nxt[atomicAdd(nnxt, 1)] = ww[q];
     }
   }
 }

@@ -172,3 +172,27 @@ def test_coloring_wide_node():
     A.sort_indices()
     s = _system(A, 1, np.ones((1, n)))
     _compare(s, "AMG[smoother=sgs]", coarse_max=50).close()
+
+
+@pytest.mark.parametrize("n", [600, 2100])
+def test_node_graph_rows_differ(n):
+    """Two dofs per node on a chain; dof 0 of node 0 is coupled to dof 0 of
+    every node.  The two rows of each node then reach different nodes, so
+    the node graph and the block columns cannot take the first row's set:
+    they sort the node's entries (n = 600), and for node 0 at n = 2,100 its
+    2,100-entry row is beyond the sort's capacity and is merged serially."""
+    _say(f"case node graph with differing rows, n={n}")
+    T = sp.diags([-1.0, 2.0, -1.0], [-1, 0, 1], shape=(n, n))
+    A = sp.kron(T, sp.identity(2)).tolil()
+    for j in range(1, n):
+        A[0, 2 * j] = A[2 * j, 0] = -0.01
+        A[2 * j, 2 * j] += 0.01
+    A[0, 0] += 0.01 * (n - 1) + 1.0
+    A = A.tocsr()
+    A.sort_indices()
+    ns = np.zeros((2, 2 * n))
+    ns[0, 0::2] = 1.0
+    ns[1, 1::2] = 1.0
+    s = _system(A, 2, ns)
+    _compare(s, "AMG[smoother=sgs]", coarse_max=40).close()
+    _compare(s, "AMG", coarse_max=40).close()
