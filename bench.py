@@ -31,12 +31,14 @@ WORKLOADS = {
     # Laplacian (G) and PSPG Q1-Q1 Oseen flow (F) on a 40^3 hex box; degree-1
     # Chebyshev on S and G, damped multicolour Gauss-Seidel on F (omega 0.9,
     # forward sweeps before the coarse correction, backward after) and the
-    # SIMPLE diagonal D~ = diag(A11): the fastest of the settings measured
-    # (78 iterations at half the sweeps; full symmetric sweeps with omega 0.65
-    # take 61 and more time; with the absolute row sums as D~ 78 more)
+    # SIMPLE diagonal D~ = diag(A11), coarse direct solves up to 2,000 dofs
+    # (the slab's second level, 1,932 dofs): the fastest of the settings
+    # measured (72 iterations; 78 with coarse solves up to 200 dofs; full
+    # symmetric sweeps with omega 0.65 take fewer iterations and more time;
+    # the absolute row sums as D~ more iterations)
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
                   spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.9,half=1])",
-                  opts=dict(split=[0, 0, 1], simplec_mode=2)),
+                  opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
                   spec="BGS(AMG)", opts=dict(sweeps=2, order="bwd")),
@@ -44,9 +46,12 @@ WORKLOADS = {
     # 12, 4096 acinus volume constraints; outer SIMPLE (D~ = diag(A11): 156
     # iterations, against 210 with the absolute row sums) with the monolithic
     # AMG(BGS) on tissue + airway (damped Gauss-Seidel smoothers, omega 0.79)
-    # and a dense inverse of the 4096 x 4096 S~
+    # and a dense inverse of the 4096 x 4096 S~; coarse direct solves up to
+    # 1,000 dofs (three levels, 154 iterations; four levels with 200: 156
+    # and a longer setup)
     "lung3d": dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=12, acinus=8, seed=seed),
-                   spec="SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)", opts=dict(split=[0, 0, 1], simplec_mode=2)),
+                   spec="SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)",
+                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000)),
 }
 SERVE_SPEC = "BGS(AMG)"
 SERVE_OPTS = dict(sweeps=2, order="bwd")

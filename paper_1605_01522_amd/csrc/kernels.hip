@@ -2672,6 +2672,13 @@ __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ PBin
   __shared__ int si[4];
   if (*singular) return;
   const int t = threadIdx.x, lane = t & 31;
+  const int jj = k - k0;
+  const int i = blockIdx.x * GJ_RPW + (t >> 5);
+  // the row's own values and those of row k (which row p takes) do not
+  // depend on the pivot: loaded before its reduction
+  const int ii = i < n ? i : k;
+  const double fi = PBin[(int64_t)ii * GJ_NB + jj], vi = PBin[(int64_t)ii * GJ_NB + lane];
+  const double fk = PBin[(int64_t)k * GJ_NB + jj], vk = PBin[(int64_t)k * GJ_NB + lane];
   double bv = -1.0;
   int bi = n;
   for (int w = t; w < nwg; w += 256) gj_better(bv, bi, cv_in[w], ci_in[w]);
@@ -2682,11 +2689,9 @@ __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ PBin
     return;
   }
   if (blockIdx.x == 0 && t == 0) piv[k] = p;
-  const int jj = k - k0;
   const double a = PBin[(int64_t)p * GJ_NB + jj];
   const double pr = PBin[(int64_t)p * GJ_NB + lane];
   const double scaled = lane == jj ? 1.0 / a : pr / a;
-  const int i = blockIdx.x * GJ_RPW + (t >> 5);
   double cb = -1.0;
   int cbi = n;
   if (i < n) {
@@ -2694,9 +2699,8 @@ __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ PBin
     if (i == k) {
       v = scaled;
     } else {
-      const int src = i == p ? k : i;
-      const double f = PBin[(int64_t)src * GJ_NB + jj];
-      v = lane == jj ? -f / a : PBin[(int64_t)src * GJ_NB + lane] - f * scaled;
+      const double f = i == p ? fk : fi;
+      v = lane == jj ? -f / a : (i == p ? vk : vi) - f * scaled;
     }
     if (lane < kb) PBout[(int64_t)i * GJ_NB + lane] = v;
     if (lane == jj + 1 && i > k) { cb = fabs(v); cbi = i; }
@@ -2741,12 +2745,22 @@ __global__ void k_gj_save(double* __restrict__ M, double* __restrict__ Y, int n,
 }
 
 // M[:, j] += M[:, K] Y[:, j] for every column j outside K.  64 x 64 tiles,
-// 256 threads, 4 x 4 outputs per thread.
+// 256 threads, 4 x 4 outputs per thread; a thread's 16 outputs are loaded
+// first, so that their latency overlaps the staging and the products.
 __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ M, const double* __restrict__ Y, int n, int k0, int kb) {
   __shared__ double Ts[64][GJ_NB + 1];
   __shared__ double Ys[GJ_NB][64 + 1];
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
   const int t = threadIdx.x;
+  const int tr = (t / 16) * 4, tc = (t % 16) * 4;
+  double cv[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + tr + i, c = c0 + tc + j;
+      cv[i][j] = (r < n && c < n) ? M[(int64_t)r * n + c] : 0.0;
+    }
   for (int e = t; e < 64 * GJ_NB; e += 256) {
     const int r = e / GJ_NB, q = e % GJ_NB;
     Ts[r][q] = (r0 + r < n && q < kb) ? M[(int64_t)(r0 + r) * n + k0 + q] : 0.0;
@@ -2756,7 +2770,6 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ M, const
     Ys[q][c] = (q < kb && c0 + c < n) ? Y[(int64_t)q * n + c0 + c] : 0.0;
   }
   __syncthreads();
-  const int tr = (t / 16) * 4, tc = (t % 16) * 4;
   double acc[4][4] = {};
   for (int q = 0; q < kb; ++q) {
     double a[4], b[4];
@@ -2771,7 +2784,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ M, const
     for (int j = 0; j < 4; ++j) {
       const int c = c0 + tc + j;
       if (c >= n || (c >= k0 && c < k0 + kb)) continue;
-      M[(int64_t)r * n + c] += acc[i][j];
+      M[(int64_t)r * n + c] = cv[i][j] + acc[i][j];
     }
   }
 }

@@ -125,7 +125,7 @@ def test_lung_benchmarked_configuration_parity(dev):
     _say("case lung benchmarked configuration n=16")
     s = nfgen.lung3d(n=16, depth=7, acinus=4, seed=2)
     spec = "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)"
-    opts = dict(simplec_mode=2, **SPLIT)
+    opts = dict(simplec_mode=2, coarse_max=1000, **SPLIT)
     o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
     g = _gpu(s, spec, **opts)
     r = np.random.default_rng(6).standard_normal(s.n)
