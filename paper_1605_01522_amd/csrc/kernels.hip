@@ -8,6 +8,7 @@
 // taken in the same order on every run.
 
 #include <climits>
+#include <cstring>
 #include <vector>
 
 #include "kernels.hpp"
@@ -2802,9 +2803,124 @@ __global__ void k_iota(int* v, int n) {
   if (i < n) v[i] = i;
 }
 
+// ---- symmetric definite matrices: the same elimination without row
+// exchanges.  A symmetric matrix whose elimination pivots all have one sign
+// is definite, and Gauss-Jordan without pivoting is then stable; a panel
+// becomes one kb x kb inverse (one workgroup, LDS) and one pass over the
+// rows instead of kb pivot steps over all rows.
+
+// max |M_ij - M_ji| (out[0]) and max |M_ij| (out[1]) as the bit patterns of
+// nonnegative doubles, which order like the values; 32 x 32 tile pairs
+__global__ __launch_bounds__(256) void k_sym_check(const double* __restrict__ M, int n, unsigned long long* out) {
+  __shared__ double a[32][33], b[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    a[r][tx] = (bi + r < n && bj + tx < n) ? M[(int64_t)(bi + r) * n + bj + tx] : 0.0;
+    b[r][tx] = (bj + r < n && bi + tx < n) ? M[(int64_t)(bj + r) * n + bi + tx] : 0.0;
+  }
+  __syncthreads();
+  double asym = 0.0, mag = 0.0;
+  for (int r = ty; r < 32; r += 8) {      // partner of M[bi + r][bj + tx] is M[bj + tx][bi + r]
+    asym = fmax(asym, fabs(a[r][tx] - b[tx][r]));
+    mag = fmax(mag, fabs(a[r][tx]));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    asym = fmax(asym, __shfl_xor(asym, off));
+    mag = fmax(mag, __shfl_xor(mag, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(asym));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(mag));
+  }
+}
+
+// Dinv = inverse of the diagonal block M[K, K] by Gauss-Jordan in LDS (one
+// thread per entry); a pivot p with sign * p <= tiny flags the matrix as
+// not definite
+__global__ __launch_bounds__(1024) void k_gjnp_diag(const double* __restrict__ M, int n, int k0, int kb, double sign,
+                                                    double tiny, double* __restrict__ Dinv, int* fail) {
+  __shared__ double D[GJ_NB][GJ_NB + 1];
+  const int r = threadIdx.x / GJ_NB, c = threadIdx.x % GJ_NB;
+  D[r][c] = (r < kb && c < kb) ? M[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
+  __syncthreads();
+  for (int q = 0; q < kb; ++q) {
+    const double a = D[q][q];
+    if (threadIdx.x == 0 && !(sign * a > tiny)) *fail = 1;
+    const double sc = c == q ? 1.0 / a : D[q][c] / a;
+    double v;
+    if (r == q) v = sc;
+    else {
+      const double f = D[r][q];
+      v = c == q ? -f / a : D[r][c] - f * sc;
+    }
+    __syncthreads();
+    D[r][c] = v;
+    __syncthreads();
+  }
+  if (r < kb && c < kb) Dinv[r * GJ_NB + c] = D[r][c];
+}
+
+// columns K of the elimination matrix, in place: rows in K take Dinv, every
+// other row i takes -M[i, K] Dinv (32 lanes per row, ascending inner index)
+__global__ __launch_bounds__(256) void k_gjnp_panel(double* __restrict__ M, int n, int k0, int kb,
+                                                    const double* __restrict__ Dinv) {
+  __shared__ double Ds[GJ_NB * GJ_NB];
+  for (int e = threadIdx.x; e < GJ_NB * GJ_NB; e += 256) Ds[e] = (e / GJ_NB < kb && e % GJ_NB < kb) ? Dinv[e] : 0.0;
+  __syncthreads();
+  const int i = blockIdx.x * GJ_RPW + (threadIdx.x >> 5), c = threadIdx.x & 31;
+  const bool row = i < n;
+  const double m = row && c < kb ? M[(int64_t)(row ? i : 0) * n + k0 + c] : 0.0;
+  double v = 0.0;
+  for (int q = 0; q < kb; ++q) v = fma(__shfl(m, q, 32), Ds[q * GJ_NB + c], v);
+  if (!row || c >= kb) return;
+  M[(int64_t)i * n + k0 + c] = (i >= k0 && i < k0 + kb) ? Ds[(i - k0) * GJ_NB + c] : -v;
+}
+
+// Gauss-Jordan without row exchanges; false if a pivot breaks the sign test
+// (M is then partly eliminated: the caller restores it)
+static bool dense_inverse_definite(double* M, int n, double sign, double tiny, hipStream_t s) {
+  const int nwg = cdiv(n, GJ_RPW);
+  DBuf<double> Y((size_t)GJ_NB * n), Dinv(GJ_NB * GJ_NB);
+  DBuf<int> fail(1);
+  fill<int>(fail.p, 0, 1, s);
+  const dim3 tiles(cdiv(n, 64), cdiv(n, 64));
+  for (int k0 = 0; k0 < n; k0 += GJ_NB) {
+    const int kb = std::min(GJ_NB, n - k0);
+    hipLaunchKernelGGL(k_gjnp_diag, dim3(1), dim3(GJ_NB * GJ_NB), 0, s, M, n, k0, kb, sign, tiny, Dinv.p, fail.p);
+    hipLaunchKernelGGL(k_gjnp_panel, dim3(nwg), dim3(256), 0, s, M, n, k0, kb, Dinv.p);
+    hipLaunchKernelGGL(k_gj_save, dim3(cdiv((int64_t)kb * n, 256)), dim3(256), 0, s, M, Y.p, n, k0, kb);
+    hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, M, Y.p, n, k0, kb);
+  }
+  NF_HIP(hipGetLastError());
+  int h = 0;
+  NF_HIP(hipMemcpyAsync(&h, fail.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  return h == 0;
+}
+
 int dense_inverse(double* M, int n, hipStream_t s) {
   if (n == 0) return 0;
   NF_CHECK(n <= DENSE_MAX, NFIELD_ENOMEM, "dense solve larger than " + std::to_string(DENSE_MAX) + " unknowns");
+  {
+    DBuf<unsigned long long> chk(2);
+    fill<unsigned long long>(chk.p, 0ull, 2, s);
+    hipLaunchKernelGGL(k_sym_check, dim3(cdiv(n, 32), cdiv(n, 32)), dim3(256), 0, s, M, n, chk.p);
+    unsigned long long h[2];
+    double m00 = 0.0;
+    NF_HIP(hipMemcpyAsync(h, chk.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipMemcpyAsync(&m00, M, sizeof(double), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    double asym, mag;
+    std::memcpy(&asym, &h[0], sizeof(double));
+    std::memcpy(&mag, &h[1], sizeof(double));
+    if (mag > 0.0 && asym <= 1e-12 * mag && m00 != 0.0) {
+      DBuf<double> keep((size_t)n * n);
+      NF_HIP(hipMemcpyAsync(keep.p, M, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+      if (dense_inverse_definite(M, n, m00 > 0.0 ? 1.0 : -1.0, 1e-14 * mag, s)) return 0;
+      NF_HIP(hipMemcpyAsync(M, keep.p, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    }
+  }
   const int nwg = cdiv(n, GJ_RPW);
   DBuf<double> Y((size_t)GJ_NB * n), PB0((size_t)GJ_NB * n), PB1((size_t)GJ_NB * n), cv(2 * (size_t)nwg);
   DBuf<int> piv(n), sing(1), ci(2 * (size_t)nwg);

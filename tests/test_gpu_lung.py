@@ -63,6 +63,54 @@ def test_dense_inverse_parity(dev, n):
         assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
 
 
+def _symmetric(n, seed, kind):
+    """Symmetric, well conditioned: definite (positive or negative), or
+    indefinite with diagonal entries of both signs."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, n)) * (rng.random((n, n)) < min(1.0, 4.0 / n))
+    M = B + B.T
+    d = n + rng.random(n)
+    if kind == "indefinite":
+        d[1::2] *= -1.0
+    M += np.diag(d)
+    return -M if kind == "negative" else M
+
+
+@pytest.mark.parametrize("kind", ["positive", "negative", "indefinite"])
+@pytest.mark.parametrize("n", [1, 33, 200, 2100])
+def test_dense_inverse_symmetric(dev, n, kind):
+    """Symmetric definite matrices are inverted without row exchanges; an
+    indefinite one fails the pivot sign test and takes the pivoting path."""
+    _say(f"case dense inverse symmetric {kind} n={n}")
+    A = sp.csr_matrix(_symmetric(n, n + 7, kind))
+    A.sort_indices()
+    f = nfgen.Field("f", n, 1, np.ones((1, n)))
+    s = nfgen.BlockSystem([f], [[A]], np.zeros((1, n)))
+    o = oracle.Oracle(s.fields, s.blocks, "LU")
+    g = _gpu(s, "LU")
+    r = np.random.default_rng(n + 2).standard_normal((2, n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    Ad = A.toarray()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-12 * np.linalg.norm(zo[k]), k
+        assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
+
+
+def test_dense_inverse_symmetric_singular(dev):
+    _say("case dense inverse symmetric singular")
+    from paper_1605_01522_amd import nfield
+    n = 70
+    M = _symmetric(n, 3, "positive")
+    M[40, :] = 0.0
+    M[:, 40] = 0.0                     # a zero row and column
+    A = sp.csr_matrix(M)
+    f = nfgen.Field("f", n, 1, np.ones((1, n)))
+    with pytest.raises(nfield.NFieldError) as e:
+        _gpu(nfgen.BlockSystem([f], [[A]], np.zeros((1, n))), "LU")
+    assert e.value.code == -3
+
+
 def test_dense_inverse_singular(dev):
     _say("case dense inverse singular")
     from paper_1605_01522_amd import nfield
