@@ -463,31 +463,55 @@ void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
                      (const int*)nullptr);
 }
 
-// column k = blockIdx.y: partial dots of V_k[0..ncols) with w_k
-template <int MAXC>
+// column k = blockIdx.y: partial dots of V_k[k0, k0 + CH) (k0 = CH
+// blockIdx.z, below ncols) with w_k.  Splitting the columns over blockIdx.z
+// keeps the accumulators few and the workgroups many; each dot still sums
+// its terms per thread and per workgroup in the same order.
+template <int CH>
 __global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
                                               const double* __restrict__ w, int64_t ldw, double* __restrict__ partial,
                                               int64_t ps, const int* mask) {
   __shared__ double ws[4];
-  const int kc = blockIdx.y;
+  const int kc = blockIdx.y, k0 = blockIdx.z * CH;
   if (mask && !mask[kc]) return;
-  const double* Vk = V + kc * vs;
+  const int nk = min(CH, ncols - k0);
+  const double* Vk = V + kc * vs + (int64_t)k0 * n;
   const double* wk = w + kc * ldw;
-  double acc[MAXC];
+  double acc[CH];
 #pragma unroll
-  for (int k = 0; k < MAXC; ++k) acc[k] = 0.0;
+  for (int k = 0; k < CH; ++k) acc[k] = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double wi = wk[i];
 #pragma unroll
-    for (int k = 0; k < MAXC; ++k)
-      if (k < ncols) acc[k] += Vk[k * n + i] * wi;
+    for (int k = 0; k < CH; ++k)
+      if (k < nk) acc[k] += Vk[k * n + i] * wi;
   }
 #pragma unroll
-  for (int k = 0; k < MAXC; ++k)
-    if (k < ncols) {
+  for (int k = 0; k < CH; ++k)
+    if (k < nk) {
       double r = block_sum256(acc[k], ws);
-      if (threadIdx.x == 0) partial[kc * ps + (int64_t)k * RED_BLOCKS + blockIdx.x] = r;
+      if (threadIdx.x == 0) partial[kc * ps + (int64_t)(k0 + k) * RED_BLOCKS + blockIdx.x] = r;
     }
+}
+
+// w_k <- w_k - V_k h_k, one element per thread (terms in ascending k)
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_mupdate_only(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
+                                                      const double* __restrict__ h, int64_t hs, double* __restrict__ w,
+                                                      int64_t ldw, const int* mask) {
+  __shared__ double hsh[MAXC];
+  const int kc = blockIdx.y;
+  if (mask && !mask[kc]) return;
+  for (int k = threadIdx.x; k < MAXC; k += 256) hsh[k] = k < ncols ? h[kc * hs + k] : 0.0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double* Vk = V + kc * vs;
+  double wi = w[kc * ldw + i];
+#pragma unroll
+  for (int k = 0; k < MAXC; ++k)
+    if (k < ncols) wi -= Vk[k * n + i] * hsh[k];
+  w[kc * ldw + i] = wi;
 }
 
 // w_k <- w_k - V_k h_k, then partial dots V_k^T w_k (NORM=false) or ||w_k||^2 (NORM=true)
@@ -569,17 +593,27 @@ __global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, 
 
 void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double* w, int64_t ldw, double* partial,
                   const int* mask, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL(k_mdot<MC>, dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n, ncols, w,
-                                             ldw, partial, L.ps, mask));
+  if (ncols <= 0) return;
+  NF_CHECK(ncols <= 64, NFIELD_EINVAL, "GMRES restart length above 63 is not supported");
+  if (ncols <= 8)
+    hipLaunchKernelGGL(k_mdot<8>, dim3(RED_BLOCKS, L.nrhs, 1), dim3(256), 0, s, V, L.vs, L.n, ncols, w, ldw, partial, L.ps,
+                       mask);
+  else
+    hipLaunchKernelGGL(k_mdot<16>, dim3(RED_BLOCKS, L.nrhs, cdiv(ncols, 16)), dim3(256), 0, s, V, L.vs, L.n, ncols, w, ldw,
+                       partial, L.ps, mask);
 }
 void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out, int accumulate, const int* mask,
              hipStream_t s) {
   hipLaunchKernelGGL(k_mreduce, dim3(ncols, L.nrhs), dim3(256), 0, s, partial, L.ps, out, L.hs, accumulate, mask);
 }
+// the update with every element's thread, then the dots as mdot_partial
+// (the same sums as one fused pass, at the cost of a second read of V)
 void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
                  double* partial, const int* mask, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, false>), dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n,
-                                             ncols, h, L.hs, w, ldw, partial, L.ps, mask));
+  if (ncols <= 0 || L.n <= 0) return;
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
+                                             L.n, ncols, h, L.hs, w, ldw, mask));
+  mdot_partial(L, V, ncols, w, ldw, partial, mask, s);
 }
 void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
                   double* partial, const int* mask, hipStream_t s) {
