@@ -514,51 +514,20 @@ __global__ __launch_bounds__(256) void k_mupdate_only(const double* __restrict__
   w[kc * ldw + i] = wi;
 }
 
-// w_k <- w_k - V_k h_k, then partial dots V_k^T w_k (NORM=false) or ||w_k||^2 (NORM=true)
-template <int MAXC, bool NORM>
-__global__ __launch_bounds__(256) void k_mupdate(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
-                                                 const double* __restrict__ h, int64_t hs, double* __restrict__ w, int64_t ldw,
-                                                 double* __restrict__ partial, int64_t ps, const int* mask) {
+// partial sums of w_k^2 in the grid-stride order of the workgroups
+__global__ __launch_bounds__(256) void k_norm_partial(int64_t n, const double* __restrict__ w, int64_t ldw,
+                                                      double* __restrict__ partial, int64_t ps, const int* mask) {
   __shared__ double ws[4];
-  __shared__ double hsh[MAXC];
   const int kc = blockIdx.y;
   if (mask && !mask[kc]) return;
-  const double* Vk = V + kc * vs;
-  double* wk = w + kc * ldw;
-  for (int k = threadIdx.x; k < MAXC; k += 256) hsh[k] = k < ncols ? h[kc * hs + k] : 0.0;
-  __syncthreads();
-  double acc[NORM ? 1 : MAXC];
-#pragma unroll
-  for (int k = 0; k < (NORM ? 1 : MAXC); ++k) acc[k] = 0.0;
+  const double* wk = w + kc * ldw;
+  double acc = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    double vk[MAXC];
-    double wi = wk[i];
-#pragma unroll
-    for (int k = 0; k < MAXC; ++k)
-      if (k < ncols) {
-        vk[k] = Vk[k * n + i];
-        wi -= vk[k] * hsh[k];
-      }
-    wk[i] = wi;
-    if (NORM) {
-      acc[0] += wi * wi;
-    } else {
-#pragma unroll
-      for (int k = 0; k < MAXC; ++k)
-        if (k < ncols) acc[(NORM ? 0 : k)] += vk[k] * wi;
-    }
+    const double wi = wk[i];
+    acc += wi * wi;
   }
-  if (NORM) {
-    double r = block_sum256(acc[0], ws);
-    if (threadIdx.x == 0) partial[kc * ps + blockIdx.x] = r;
-  } else {
-#pragma unroll
-    for (int k = 0; k < (NORM ? 1 : MAXC); ++k)
-      if (k < ncols) {
-        double r = block_sum256(acc[k], ws);
-        if (threadIdx.x == 0) partial[kc * ps + (int64_t)k * RED_BLOCKS + blockIdx.x] = r;
-      }
-  }
+  const double r = block_sum256(acc, ws);
+  if (threadIdx.x == 0) partial[kc * ps + blockIdx.x] = r;
 }
 
 template <int MAXC>
@@ -617,8 +586,10 @@ void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double*
 }
 void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
                   double* partial, const int* mask, hipStream_t s) {
-  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate<MC, true>), dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, V, L.vs, L.n,
-                                             ncols, h, L.hs, w, ldw, partial, L.ps, mask));
+  if (ncols <= 0 || L.n <= 0) return;
+  NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
+                                             L.n, ncols, h, L.hs, w, ldw, mask));
+  hipLaunchKernelGGL(k_norm_partial, dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, L.n, w, ldw, partial, L.ps, mask);
 }
 void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
               int64_t ldu, int accumulate, const int* mask, hipStream_t s) {

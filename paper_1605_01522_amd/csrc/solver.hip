@@ -1258,11 +1258,15 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
     NF_HIP(hipStreamSynchronize(s));   // the beta staging buffer is reused below
     std::vector<int> in_cycle = cyc;
     std::fill(je.begin(), je.end(), 0);
+    const int64_t ldz = flex ? LZ.vs : n;
+    bool z_ready = false;             // z_j already enqueued by the step before
+    // the last two residual estimates of each column, to foresee the end
+    std::vector<double> res1(beta), res2(nrhs, 0.0);
     for (int j = 0; j < m; ++j) {
       double* vj = C.V.p + (int64_t)j * n;
       double* zj = flex ? C.Z.p + (int64_t)j * n : C.z.p;
-      const int64_t ldz = flex ? LZ.vs : n;
-      precond(C, vj, L.vs, zj, ldz, nrhs, s);
+      if (!z_ready) precond(C, vj, L.vs, zj, ldz, nrhs, s);
+      z_ready = false;
       SpmvArgs<double> a;
       a.x = zj;
       a.ldx = ldz;
@@ -1279,6 +1283,21 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
       givens_step(L, j, C.h1.p, C.h2.p, C.partial.p, C.H.p, C.cs.p, C.sn.p, C.g.p, C.scal.p, mask, s);
       scale_inv_devm(C.w.p, n, C.V.p + (int64_t)(j + 1) * n, L.vs, C.scal.p, 2, n, nrhs, mask, s);
       NF_HIP(hipMemcpyAsync(C.pinned, C.scal.p, 2 * sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      // the next step's preconditioner needs only v_{j+1}: enqueued before
+      // the wait for this step's residual estimates, so that the device has
+      // work while the host tests them; not when every column is expected
+      // to stop here (the estimate falling at its last rate to below twice
+      // the tolerance, or the iteration limit)
+      bool more = false;
+      for (int k = 0; k < nrhs && !more; ++k) {
+        if (!cyc[k]) continue;
+        const double rate = res2[k] > 0.0 ? std::min(1.0, res1[k] / res2[k]) : 1.0;
+        more = !(res1[k] * rate < 2.0 * so.rtol * beta0[k] || total[k] + 1 >= so.maxit);
+      }
+      if (j + 1 < m && more) {
+        precond(C, C.V.p + (int64_t)(j + 1) * n, L.vs, flex ? C.Z.p + (int64_t)(j + 1) * n : C.z.p, ldz, nrhs, s);
+        z_ready = true;
+      }
       NF_HIP(hipStreamSynchronize(s));
       bool changed = false;
       int left = 0;
@@ -1287,6 +1306,8 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
         ++total[k];
         je[k] = j + 1;
         const double hn = C.pinned[2 * k], res = C.pinned[2 * k + 1];
+        res2[k] = res1[k];
+        res1[k] = res;
         if (!std::isfinite(res) || hn <= 1e-300 || res / beta0[k] < so.rtol || total[k] >= so.maxit) {
           cyc[k] = 0;
           changed = true;
