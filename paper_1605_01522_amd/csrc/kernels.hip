@@ -604,36 +604,47 @@ __global__ __launch_bounds__(256) void k_givens(int j, int m, const double* __re
                                                 int64_t hs, const double* __restrict__ nrm_partial, int64_t ps, double* H,
                                                 double* cs, double* sn, double* g, double* scal, const int* mask) {
   __shared__ double ws[4];
+  __shared__ double hc[66], csl[64], snl[64];   // the new column and the rotations so far, staged by all threads
   const int kc = blockIdx.x;
   if (mask && !mask[kc]) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += nrm_partial[kc * ps + i];
-  s = block_sum256(s, ws);
-  if (threadIdx.x != 0) return;
   const int ld = m + 1;
   double* Hk = H + (int64_t)kc * ld * m;
   double* csk = cs + (int64_t)kc * m;
   double* snk = sn + (int64_t)kc * m;
   double* gk = g + (int64_t)kc * ld;
   double* Hj = Hk + (int64_t)j * ld;
-  for (int i = 0; i <= j; ++i) Hj[i] = h1[kc * hs + i] + h2[kc * hs + i];
-  const double hn = sqrt(s);
-  Hj[j + 1] = hn;
-  scal[2 * kc] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = Hj[i], c = Hj[i + 1];
-    Hj[i] = csk[i] * a + snk[i] * c;
-    Hj[i + 1] = -snk[i] * a + csk[i] * c;
+  for (int i = threadIdx.x; i <= j; i += 256) hc[i] = h1[kc * hs + i] + h2[kc * hs + i];
+  for (int i = threadIdx.x; i < j; i += 256) {
+    csl[i] = csk[i];
+    snl[i] = snk[i];
   }
-  const double a = Hj[j], c = Hj[j + 1];
-  const double den = hypot(a, c);
-  csk[j] = den == 0.0 ? 1.0 : a / den;
-  snk[j] = den == 0.0 ? 0.0 : c / den;
-  Hj[j] = den;
-  Hj[j + 1] = 0.0;
-  gk[j + 1] = -snk[j] * gk[j];
-  gk[j] = csk[j] * gk[j];
-  scal[2 * kc + 1] = fabs(gk[j + 1]);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += nrm_partial[kc * ps + i];
+  s = block_sum256(s, ws);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(s);
+    hc[j + 1] = hn;
+    scal[2 * kc] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = hc[i], c = hc[i + 1];
+      hc[i] = csl[i] * a + snl[i] * c;
+      hc[i + 1] = -snl[i] * a + csl[i] * c;
+    }
+    const double a = hc[j], c = hc[j + 1];
+    const double den = hypot(a, c);
+    const double cj = den == 0.0 ? 1.0 : a / den, sj = den == 0.0 ? 0.0 : c / den;
+    csk[j] = cj;
+    snk[j] = sj;
+    hc[j] = den;
+    hc[j + 1] = 0.0;
+    const double gj = gk[j];
+    gk[j + 1] = -sj * gj;
+    gk[j] = cj * gj;
+    scal[2 * kc + 1] = fabs(gk[j + 1]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 256) Hj[i] = hc[i];
 }
 __global__ void k_backsolve(const int* ncols, int m, const double* H, const double* g, double* y, const int* mask) {
   const int kc = blockIdx.x;
