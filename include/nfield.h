@@ -26,7 +26,9 @@
  *                           S~ on every level is inverted densely up to
  *                           schur_direct_max, else smoothed by Chebyshev);
  *   "LU"                    dense direct solve (Gauss-Jordan inverse with
- *                           partial pivoting, up to 12000 unknowns).
+ *                           partial pivoting, up to 12000 unknowns; a
+ *                           symmetric definite matrix is inverted without
+ *                           row exchanges).
  * Optional per-method parameters: "BGS[sweeps=2,order=bwd](AMG)" (sweeps and
  * order of one BGS / SIMPLE node), "AMG[degree=1]" (Chebyshev smoother degree
  * of one hierarchy; degree 1 is damped Jacobi), "AMG[smoother=sgs,omega=0.69,
