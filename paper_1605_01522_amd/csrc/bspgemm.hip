@@ -252,9 +252,11 @@ void bsr_to_csr(const DBsr& B, DCsr& A, hipStream_t s) {
 // block columns and B row ranges of the next NT blocks of A's row are read
 // at once.  With STAGE, B's block row and A's block are staged in LDS one
 // block ahead (double buffer), so the loads of the next A block overlap the
-// work on the current one (a B block row too long for the stage is read from
-// global memory); this suits few long rows (R (A P)), while many short rows
-// (A P) want the small footprint and the occupancy it brings.
+// work on the current one: they are issued into registers before the current
+// block's work and stored to LDS after it (a B block row too long for the
+// stage is read from global memory); this suits few long rows (R (A P)),
+// while many short rows (A P) want the small footprint and the occupancy it
+// brings.
 constexpr int BSP_STG = 512;     // staged values of one B block row
 constexpr int BSP_STGB = 64;     // staged blocks of one B block row
 
@@ -328,6 +330,29 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
       }
       for (int t = 0; t < np; ++t) {
         const int b = STAGE ? (t & 1) : 0;
+        // the next block's stage is loaded into registers before this
+        // block's work and written to the other buffer after it
+        constexpr int PVN = STAGE ? (BSP_STG + NT - 1) / NT : 1;
+        double pv[PVN], pa = 0.0;
+        int pc = 0, nv1 = 0;
+        unsigned long long pm = 0ull;
+        bool pf = false;
+        if (STAGE && t + 1 < np) {
+          const int nq1 = mq1[t + 1] - mq0[t + 1];
+          pf = nq1 <= BSP_STGB && nq1 * kbc <= BSP_STG;
+          if (pf) {
+            const int q1 = mq0[t + 1];
+            nv1 = nq1 * kbc;
+  #pragma unroll
+            for (int u = 0; u < PVN; ++u)
+              if (tid + u * NT < nv1) pv[u] = Bv[(int64_t)q1 * kbc + tid + u * NT];
+            if (tid < nq1) {
+              pc = Bc[q1 + tid];
+              pm = Bm[q1 + tid];
+            }
+            if (tid < na) pa = Av[(int64_t)(p0 + t + 1) * na + tid];
+          }
+        }
         const int q0 = mq0[t], nq = mq1[t] - q0;
         const unsigned long long am = mam[t];
         const bool staged = STAGE && nq <= BSP_STGB && nq * kbc <= BSP_STG;
@@ -378,11 +403,15 @@ __global__ __launch_bounds__(NT) void k_bspgemm_lds(const int* __restrict__ rows
             st[e] = 1;
           }
         }
-        if (STAGE && t + 1 < np) {
-          const int nq1 = mq1[t + 1] - mq0[t + 1];
-          if (nq1 <= BSP_STGB && nq1 * kbc <= BSP_STG)
-            bsp_stage<NT>(tid, nq1, kbc, na, Bc, Bv, Bm, Av + (int64_t)(p0 + t + 1) * na, mq0[t + 1], sv[b ^ 1], sc[b ^ 1],
-                          sm[b ^ 1], sa[b ^ 1]);
+        if (pf) {
+  #pragma unroll
+          for (int u = 0; u < PVN; ++u)
+            if (tid + u * NT < nv1) sv[b ^ 1][tid + u * NT] = pv[u];
+          if (tid < mq1[t + 1] - mq0[t + 1]) {
+            sc[b ^ 1][tid] = pc;
+            sm[b ^ 1][tid] = pm;
+          }
+          if (tid < na) sa[b ^ 1][tid] = pa;
         }
         __syncthreads();
       }
