@@ -97,6 +97,40 @@ def test_dense_inverse_symmetric(dev, n, kind):
         assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
 
 
+def _nonsymmetric(n, seed, trap):
+    """Nonsymmetric and diagonally dominant, or with a 1e-9 entry in the
+    leading 2 x 2 block ([[1e-9, 1], [1, 1]]) whose elimination without row
+    exchanges would grow by 1e9: the partial-pivoting path must exchange
+    the first two rows."""
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n)) * (rng.random((n, n)) < min(1.0, 6.0 / n))
+    M += np.diag(n + rng.random(n))
+    if trap:
+        M[:2, :] = 0.0
+        M[:, :2] = 0.0
+        M[0, 0], M[0, 1], M[1, 0], M[1, 1] = 1e-9, 1.0, 1.0, 1.0
+    return M
+
+
+@pytest.mark.parametrize("trap", [False, True])
+@pytest.mark.parametrize("n", [32, 84, 500])
+def test_dense_inverse_nonsymmetric(dev, n, trap):
+    _say(f"case dense inverse nonsymmetric n={n} trap={trap}")
+    A = sp.csr_matrix(_nonsymmetric(n, n + 11, trap))
+    A.sort_indices()
+    f = nfgen.Field("f", n, 1, np.ones((1, n)))
+    s = nfgen.BlockSystem([f], [[A]], np.zeros((1, n)))
+    o = oracle.Oracle(s.fields, s.blocks, "LU")
+    g = _gpu(s, "LU")
+    r = np.random.default_rng(n + 3).standard_normal((2, n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    Ad = A.toarray()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-12 * np.linalg.norm(zo[k]), k
+        assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
+
+
 def test_dense_inverse_symmetric_singular(dev):
     _say("case dense inverse symmetric singular")
     from paper_1605_01522_amd import nfield
