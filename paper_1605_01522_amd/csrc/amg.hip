@@ -212,7 +212,6 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         const double omega = 4.0 / (3.0 * L.lambda[i]);
         if (n > 0) hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, s, L.dinv[i]->p, -omega, srow.p, (int64_t)n);
         smooth_prolongator(AP, srow.p, Pt, L.bs[i], k, agg->p, s);
-        NF_HIP(hipStreamSynchronize(s));
         *L.P[i] = std::move(AP);
         L.agg[i] = agg;
         C.bs[i] = k;
@@ -245,7 +244,6 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         if (i == j && C.ndead[i] > 0) set_diag_one(*Ac, C.dead[i]->p, C.ndead[i], s);
         C.A.blk[(size_t)i * N + j] = Ac;
       }
-    NF_HIP(hipStreamSynchronize(s));
     H.lev.push_back(std::move(C));
   }
   dense_block_inverse(H.lev.back().A, H.coarse_inv, &H.ncoarse, s);

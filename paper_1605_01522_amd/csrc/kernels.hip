@@ -849,7 +849,6 @@ void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nno
   const int64_t tot = exclusive_scan(cnt.p, gptr.p, nn, s);
   gadj.alloc(tot > 0 ? tot : 1);
   if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
-  NF_HIP(hipStreamSynchronize(s));
 }
 
 // ===================================================================== MIS-2
@@ -1781,7 +1780,6 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
   const int ndead = (int)exclusive_scan(dflag.p, doff.p, nc, s);
   dead.alloc(ndead > 0 ? ndead : 1);
   if (ndead > 0) hipLaunchKernelGGL(k_compact_flags, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, dflag.p, doff.p, dead.p);
-  NF_HIP(hipStreamSynchronize(s));
   return ndead;
 }
 
