@@ -83,5 +83,6 @@ def test_host_validation_rejects_malformed_input():
     wrong = [[s.blocks[0][0], s.blocks[0][1][:, :-1]], [s.blocks[1][0], s.blocks[1][1]]]
     assert _setup_code(s.fields, wrong, "BGS(AMG)") == -1
     # malformed specifications
-    for spec in ["BGS(AMG", "FOO(AMG)", "BGS[sweeps=0](AMG)", "BGS(AMG))", "BGS[order=up](AMG)"]:
+    for spec in ["BGS(AMG", "FOO(AMG)", "BGS[sweeps=0](AMG)", "BGS(AMG))", "BGS[order=up](AMG)",
+                 "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])", "BGS(AMG[degree=0])"]:
         assert _setup_code(s.fields, s.blocks, spec) == -1, spec

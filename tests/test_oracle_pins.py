@@ -473,9 +473,10 @@ def test_end_to_end_tsi_full_size_vs_sparse_lu():
 # -------------------------------------------------------------- error paths
 def test_errors():
     s = nfgen.tsi2d(nel=4)
-    with pytest.raises(oracle.OracleError) as e:
-        Oracle(s.fields, s.blocks, "BGS(AMG", sweeps=2)
-    assert e.value.code == -1
+    for spec in ["BGS(AMG", "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])"]:
+        with pytest.raises(oracle.OracleError) as e:
+            Oracle(s.fields, s.blocks, spec, sweeps=2)
+        assert e.value.code == -1, spec
     bad = [[s.blocks[0][0], s.blocks[0][1]], [s.blocks[1][0], None]]
     with pytest.raises(oracle.OracleError) as e:
         Oracle(s.fields, bad, "BGS(AMG)")
