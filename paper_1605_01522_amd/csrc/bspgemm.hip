@@ -525,12 +525,78 @@ static void bsp_pass(const int* rows, int nrows, const int* nrows_dev, int grid,
 // block rows of C above which a product counts as many short rows
 constexpr int BSP_MANY_ROWS = 8192;
 
+// ------------------------------------------------------------ block pattern
+// Block pattern of A B when B has at most PAT_BITS block columns: one
+// wavefront per block row marks the block columns it reaches in an LDS
+// bitmap (lanes take A's entries, each walking its B row), then reads the
+// set bits in ascending order (pass 0 counts them, pass 1 writes them at the
+// row's offset).  The same pattern as the scalar product machinery, with no
+// hashing.
+constexpr int PAT_BITS = 16384;
+template <int PASS>
+__global__ __launch_bounds__(64) void k_pattern_bits(int nc, const int* __restrict__ Ap, const int* __restrict__ Ac,
+                                                     const int* __restrict__ Bp, const int* __restrict__ Bc,
+                                                     int* __restrict__ cnt_or_ptr, int* __restrict__ Cc) {
+  __shared__ unsigned int bits[PAT_BITS / 32];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int nw = (nc + 31) >> 5;
+  for (int w = lane; w < nw; w += 64) bits[w] = 0u;
+  __syncthreads();
+  for (int p = Ap[i] + lane; p < Ap[i + 1]; p += 64) {
+    const int k = Ac[p];
+    for (int q = Bp[k]; q < Bp[k + 1]; ++q) {
+      const int j = Bc[q];
+      atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+  }
+  __syncthreads();
+  int n = 0;
+  const int o = PASS ? cnt_or_ptr[i] : 0;
+  for (int w0 = 0; w0 < nw; w0 += 64) {
+    const int w = w0 + lane;
+    const unsigned int x = w < nw ? bits[w] : 0u;
+    const int c = __popc(x);
+    int incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    if (PASS) {
+      int pos = o + n + incl - c;
+      for (unsigned int y = x; y; y &= y - 1u) Cc[pos++] = (w << 5) + __ffs((int)y) - 1;
+    }
+    n += __shfl(incl, 63, 64);
+  }
+  if (!PASS && lane == 0) cnt_or_ptr[i] = n;
+}
+
+static void pattern_bits(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
+  C.nr = A.nr;
+  C.nc = B.nc;
+  C.ptr.alloc(C.nr + 1);
+  DBuf<int> cnt(C.nr + 1);
+  if (C.nr > 0)
+    hipLaunchKernelGGL(k_pattern_bits<0>, dim3(C.nr), dim3(64), 0, s, C.nc, A.ptr.p, A.col.p, B.ptr.p, B.col.p, cnt.p,
+                       (int*)nullptr);
+  C.nnz = exclusive_scan(cnt.p, C.ptr.p, C.nr, s);
+  const int64_t nb = C.nnz > 0 ? C.nnz : 1;
+  C.col.alloc(nb);
+  C.val.alloc(nb);
+  if (C.nnz > 0) {
+    hipLaunchKernelGGL(k_pattern_bits<1>, dim3(C.nr), dim3(64), 0, s, C.nc, A.ptr.p, A.col.p, B.ptr.p, B.col.p, C.ptr.p,
+                       C.col.p);
+    iota(C.val.p, C.nnz, s);
+  }
+}
+
 void bspgemm(const DBsr& A, const DBsr& B, DBsr& C, hipStream_t s) {
   NF_CHECK(A.pat.nc == B.pat.nr && A.bc == B.br, NFIELD_EINVAL, "block product: inner dimensions differ");
   C.br = A.br;
   C.bc = B.bc;
-  // block pattern of the product (the pattern values are counts, unused)
-  spgemm(A.pat, B.pat, C.pat, s);
+  // block pattern of the product (its values, unused, are block indices
+  // from the bitmap path and counts from the scalar product)
+  if (B.pat.nc <= PAT_BITS) pattern_bits(A.pat, B.pat, C.pat, s);
+  else spgemm(A.pat, B.pat, C.pat, s);
   const int64_t nb = C.pat.nnz > 0 ? C.pat.nnz : 1;
   const int bb = C.br * C.bc;
   C.val.alloc(nb * bb);
