@@ -102,16 +102,25 @@ __global__ __launch_bounds__(64) void k_bsr_keys(int bc, const int* __restrict__
 
 // one wavefront per block row: copy its block columns, then every entry finds
 // its block (binary search) and lands at row q, column c inside it, with its
-// bit (q bc + c) or-ed into the block's mask (masks start at zero)
+// bit (q bc + c) or-ed into the block's mask: in LDS for rows of up to
+// BSR_PLACE_LDS blocks (written out at the end), in global memory (zeroed
+// beforehand) beyond
+constexpr int BSR_PLACE_LDS = 512;
 __global__ __launch_bounds__(64) void k_bsr_place(int br, int bc, const int* __restrict__ ptr, const int* __restrict__ col,
                                                   const double* __restrict__ val, const int* __restrict__ ucol,
                                                   const int* __restrict__ bptr, int* __restrict__ bcol,
                                                   double* __restrict__ bval, unsigned long long* bmask) {
+  __shared__ unsigned long long lm[BSR_PLACE_LDS];
   const int i = blockIdx.x, lane = threadIdx.x;
   const int e0 = ptr[i * br], e1 = ptr[(i + 1) * br];
   const int o = bptr[i], n = bptr[i + 1] - o, bb = br * bc;
+  const bool in_lds = n <= BSR_PLACE_LDS;
   const int* __restrict__ u = ucol + e0;
-  for (int t = lane; t < n; t += 64) bcol[o + t] = u[t];
+  for (int t = lane; t < n; t += 64) {
+    bcol[o + t] = u[t];
+    if (in_lds) lm[t] = 0ull;
+  }
+  __syncthreads();
   for (int t = e0 + lane; t < e1; t += 64) {
     int q = 0;
     while (ptr[i * br + q + 1] <= t) ++q;
@@ -123,7 +132,13 @@ __global__ __launch_bounds__(64) void k_bsr_place(int br, int bc, const int* __r
     }
     const int cc = c - jb * bc;
     bval[(int64_t)(o + lo) * bb + q * bc + cc] = val[t];
-    atomicOr(&bmask[o + lo], 1ull << (q * bc + cc));
+    const unsigned long long bit = 1ull << (q * bc + cc);
+    if (in_lds) atomicOr(&lm[lo], bit);
+    else atomicOr(&bmask[o + lo], bit);
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int t = lane; t < n; t += 64) bmask[o + t] = lm[t];
   }
 }
 
