@@ -16,9 +16,6 @@
 
 namespace nf {
 
-__global__ void k_sqrt1(double* v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *v = sqrt(*v);
-}
 __global__ void k_scale_copy(const double* x, double a, double* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] = a * x[i];
@@ -28,9 +25,7 @@ double power_lambda(const DCsr& A, const double* dinv, uint64_t seed, int its, h
   const int n = A.nr;
   DBuf<double> v(n), w(n), partial(RED_BLOCKS), nrm(1);
   power_start(v.p, n, seed, s);
-  dotm(v.p, n, v.p, n, n, 1, partial.p, nrm.p, s);
-  hipLaunchKernelGGL(k_sqrt1, dim3(1), dim3(1), 0, s, nrm.p);
-  scale_inv_devm(v.p, n, v.p, n, nrm.p, 1, n, 1, nullptr, s);
+  normalize(v.p, v.p, n, partial.p, nrm.p, s);
   double lam = 0.0;
   for (int it = 0; it < its; ++it) {
     SpmvArgs<double> a;
@@ -39,9 +34,7 @@ double power_lambda(const DCsr& A, const double* dinv, uint64_t seed, int its, h
     a.dinv = dinv;
     a.ldx = a.ldy = n;
     spmv<double>(SPMV_DSCALE, A, a, s);
-    dotm(w.p, n, w.p, n, n, 1, partial.p, nrm.p, s);
-    hipLaunchKernelGGL(k_sqrt1, dim3(1), dim3(1), 0, s, nrm.p);
-    scale_inv_devm(w.p, n, v.p, n, nrm.p, 1, n, 1, nullptr, s);
+    normalize(w.p, v.p, n, partial.p, nrm.p, s);
   }
   NF_HIP(hipMemcpyAsync(&lam, nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));

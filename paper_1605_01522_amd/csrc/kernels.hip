@@ -463,6 +463,25 @@ void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
                      (const int*)nullptr);
 }
 
+// v = w / ||w||, ||w||^2 the sum of the RED_BLOCKS partials of one dot:
+// every workgroup sums them as k_mreduce does (same order, same bits) and
+// workgroup 0 stores ||w|| in nrm[0]; a zero norm leaves w unscaled
+__global__ __launch_bounds__(256) void k_normalize_partials(const double* __restrict__ partial, const double* __restrict__ w,
+                                                            double* __restrict__ v, int64_t n, double* __restrict__ nrm) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[i];
+  s = block_sum256(s, ws);
+  const double sv = sqrt(s);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nrm = sv;
+  const double inv = sv != 0.0 ? 1.0 / sv : 1.0;
+  NF_ROWS(n) v[i] = w[i] * inv;
+}
+void normalize(const double* w, double* v, int64_t n, double* partial, double* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partialm, dim3(RED_BLOCKS, 1), dim3(256), 0, s, w, n, w, n, n, partial);
+  if (n > 0) hipLaunchKernelGGL(k_normalize_partials, dim3(grid_cols(n, 1)), dim3(256), 0, s, partial, w, v, n, nrm);
+}
+
 // column k = blockIdx.y: partial dots of V_k[k0, k0 + CH) (k0 = CH
 // blockIdx.z, below ncols) with w_k.  Splitting the columns over blockIdx.z
 // keeps the accumulators few and the workgroups many; each dot still sums

@@ -65,6 +65,9 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
 constexpr int RED_BLOCKS = 480;
 constexpr int RED_THREADS = 256;
 // out[k] = x_k . y_k for nrhs columns (partial: RED_BLOCKS * nrhs doubles)
+// v = w / ||w|| (in place allowed), nrm[0] = ||w||: one partial-dot launch
+// and one launch that reduces the partials and scales
+void normalize(const double* w, double* v, int64_t n, double* partial, double* nrm, hipStream_t s);
 void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n, int nrhs, double* partial, double* out,
           hipStream_t s);
 // GMRES block operations, batched over nrhs independent columns.  Column k's
