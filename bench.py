@@ -29,17 +29,17 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     # 3-field FSI-like system: Q1 elastic slab 40x40x8 (S), ALE vector
     # Laplacian (G) and PSPG Q1-Q1 Oseen flow (F) on a 40^3 hex box; degree-1
-    # Chebyshev on S and G, damped multicolour Gauss-Seidel on F (omega 0.9,
+    # Chebyshev on S and G, damped multicolour Gauss-Seidel on F (omega 0.85,
     # forward sweeps before the coarse correction, backward after) and the
     # SIMPLE diagonal D~ = diag(A11), coarse direct solves up to 2,000 dofs
     # (the slab's second level, 1,932 dofs) and the degree-1 Chebyshev
     # interval [lambda/4, 1.1 lambda] on S and G: the fastest of the settings
-    # measured (69 iterations; 72 with [lambda/30, 1.1 lambda], 78 with
-    # coarse solves up to 200 dofs; full symmetric sweeps with omega 0.65
-    # take fewer iterations and more time; the absolute row sums as D~ more
-    # iterations)
+    # measured (68 iterations; 69 with omega 0.9, 72 with [lambda/30,
+    # 1.1 lambda], 78 with coarse solves up to 200 dofs; full symmetric
+    # sweeps with omega 0.65 take fewer iterations and more time; the
+    # absolute row sums as D~ more iterations)
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
-                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.9,half=1])",
+                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])",
                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),

@@ -217,7 +217,7 @@ def test_singular_inputs(dev):
 
 # ------------------------------------------------- 3-field FSI-like system
 # the benchmarked configuration, and the ones it was tuned from
-FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.9,half=1])"
+FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])"
 FSI_SPEC_FULL = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])"
 FSI_SPEC_D2 = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 FSI_OPTS = dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)
