@@ -246,20 +246,21 @@ def test_one_level_is_exact():
 
 
 # ---------------------------------------------------------------- Chebyshev
-@pytest.mark.parametrize("degree", [1, 2, 3])
-def test_chebyshev_closed_form(degree):
+@pytest.mark.parametrize("degree,ratio,boost", [(1, 30.0, 1.1), (2, 30.0, 1.1), (3, 30.0, 1.1), (1, 4.0, 1.1),
+                                                (2, 4.0, 1.0)])
+def test_chebyshev_closed_form(degree, ratio, boost):
     n, c = 40, 0.3
     A = sp.diags([np.full(n - 1, c), np.ones(n), np.full(n - 1, c)], [-1, 0, 1], format="csr")
     k = np.arange(1, n + 1)
     lam_k = 1 + 2 * c * np.cos(k * np.pi / (n + 1))
     V = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(np.arange(1, n + 1), k) * np.pi / (n + 1))
     lam = lam_k.max()
-    lo, hi = lam / 30.0, 1.1 * lam
+    lo, hi = lam / ratio, boost * lam
     th, de = (hi + lo) / 2, (hi - lo) / 2
     T = lambda m, t: np.cos(m * np.arccos(t)) if abs(t) <= 1 else np.cosh(m * np.arccosh(abs(t))) * (np.sign(t) ** m)
     for j in range(n):
         v = V[:, j]
-        x = oracle.chebyshev(A, lam, A @ v, degree=degree)
+        x = oracle.chebyshev(A, lam, A @ v, degree=degree, ratio=ratio, boost=boost)
         p = T(degree, (th - lam_k[j]) / de) / T(degree, th / de)
         assert np.abs(x - (1 - p) * v).max() < 1e-14
 
