@@ -56,7 +56,9 @@ WORKLOADS = {
                    opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000)),
 }
 SERVE_SPEC = "BGS(AMG)"
-SERVE_OPTS = dict(sweeps=2, order="bwd")
+# two backward BGS sweeps; Chebyshev interval [lambda/8, 1.1 lambda] (one
+# GMRES iteration fewer than [lambda/30, 1.1 lambda] on the 32^2-128^2 grids)
+SERVE_OPTS = dict(sweeps=2, order="bwd", cheb_ratio=8.0)
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sgs_color_fsi3d_traffic.md")
@@ -330,7 +332,8 @@ def serving(n_requests=512, seed=0, workers=4, load=0.8):
                service_p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3))
     rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
     return dict(workload=f"{n_requests} requests, tsi2d grids {list(nfgen.SERVE_GRIDS)}^2, 1-8 rhs each, "
-                         f"spec {SERVE_SPEC}, FP32 hierarchy in FP64 flexible GMRES(50) rtol 1e-8, "
+                         f"spec {SERVE_SPEC}, {opts_text(SERVE_OPTS)}, FP32 hierarchy in FP64 flexible GMRES(50) "
+                         f"rtol 1e-8, "
                          f"{workers} streams, <= 8 columns per batch",
                 capacity=rnd(cap), at_load=dict(rnd(live), load=load), max_relres=worst,
                 context_build_s=round(t_warm, 3), sequential_plain_fp64=seq,
