@@ -62,6 +62,27 @@ class BlockSystem:
         return M
 
 
+def permute_fields(sys_, order):
+    """The same system with its fields (and block rows / columns, right-hand
+    side slices) taken in the given order."""
+    o = sys_.offsets()
+    rhs = np.concatenate([sys_.rhs[:, o[i]:o[i + 1]] for i in order], axis=1)
+    blocks = [[sys_.blocks[i][j] for j in order] for i in order]
+    return BlockSystem([sys_.fields[i] for i in order], blocks, rhs, meta=dict(sys_.meta, field_order=list(order)))
+
+
+def one_sided_pattern(A, seed, frac=0.3):
+    """A copy of A with a seeded share `frac` of its strictly upper entries
+    removed: a nonsymmetric pattern in which row u couples to v while row v
+    no longer couples to u."""
+    A = sp.coo_matrix(A)
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x051DE]))
+    drop = (A.col > A.row) & (rng.random(A.nnz) < frac)
+    B = sp.csr_matrix((A.data[~drop], (A.row[~drop], A.col[~drop])), shape=A.shape)
+    B.sort_indices()
+    return B
+
+
 def uniform_rhs(n, nrhs, seed):
     """iid uniform[-1, 1] right-hand sides, (nrhs, n)."""
     rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x5EED]))

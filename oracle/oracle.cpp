@@ -188,7 +188,9 @@ static uint64_t splitmix64(uint64_t x) {
 
 // ---------------------------------------------------------- aggregation
 // Node graph of a field with block size b: node u owns dofs [b u, b u + b);
-// u ~ v (u != v) iff some stored entry couples a dof of u with a dof of v.
+// u ~ v (u != v) iff some stored entry couples a dof of u with a dof of v,
+// in either direction (entry (u, v) or (v, u)): the graph of the pattern of
+// A + A^T, so that the relation is symmetric even when the pattern is not.
 // Strength threshold 0: every stored connection counts (the paper is silent).
 struct Graph {
   int n = 0;
@@ -201,17 +203,19 @@ static Graph node_graph(const Csr& A, int b) {
   Graph G;
   G.n = A.nr / b;
   G.ptr.assign(G.n + 1, 0);
-  std::vector<int> nb;
-  for (int u = 0; u < G.n; ++u) {
-    nb.clear();
+  std::vector<std::vector<int>> nb(G.n);
+  for (int u = 0; u < G.n; ++u)
     for (int r = b * u; r < b * u + b; ++r)
       for (int64_t p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
-        int v = A.col[p] / b;
-        if (v != u) nb.push_back(v);
+        const int v = A.col[p] / b;
+        if (v == u) continue;
+        nb[u].push_back(v);
+        nb[v].push_back(u);
       }
-    std::sort(nb.begin(), nb.end());
-    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-    G.adj.insert(G.adj.end(), nb.begin(), nb.end());
+  for (int u = 0; u < G.n; ++u) {
+    std::sort(nb[u].begin(), nb[u].end());
+    nb[u].erase(std::unique(nb[u].begin(), nb[u].end()), nb[u].end());
+    G.adj.insert(G.adj.end(), nb[u].begin(), nb[u].end());
     G.ptr[u + 1] = (int64_t)G.adj.size();
   }
   return G;
@@ -310,7 +314,8 @@ static std::vector<int> aggregate(const Graph& G, const std::vector<int>& state,
 // Greedy colouring of the node graph in node order: node u takes the
 // smallest colour not used by its neighbours of smaller index.  (On a
 // structured 27-point stencil numbered lexicographically this gives 8
-// colours.)  No two neighbours share a colour.
+// colours.)  The node graph is symmetric, so every neighbour of smaller
+// index is seen from u and no two neighbours share a colour.
 static std::vector<int> color_nodes(const Graph& G, uint64_t /*seed*/, int* ncolors) {
   const int n = G.n;
   std::vector<int> color(n, -1);
@@ -1204,7 +1209,12 @@ static std::unique_ptr<Solver> build(Ctx& C, const Spec& sp, const BlockMat& A, 
 // Arnoldi on A M, modified Gram-Schmidt, Givens rotations.  Plain form:
 // x += M (V y) at the end of a cycle; flexible form keeps Z = [M v_j] and
 // does x += Z y.  Stop when |g_{j+1}| / ||r0|| < rtol, confirmed by the true
-// residual (a failed confirmation restarts).
+// residual (a failed confirmation restarts).  A breakdown (||w|| <= 1e-300
+// after the orthogonalisation: the Krylov space is invariant) ends the
+// cycle; if the true residual then still fails the test, a restart would
+// rebuild the same space, and the solve ends with EBREAKDOWN.  A zero on the
+// diagonal of the rotated Hessenberg matrix (A M singular on the space)
+// gives a zero coefficient in the back substitution.
 struct SolveOpts { int restart = 50, maxit = 1000, flexible = 0; double rtol = 1e-8; };
 struct Stats { int iters = 0, restarts = 0, status = 0; double relres = 0, setup_s = 0, solve_s = 0, bytes = 0, gbps = 0; };
 
@@ -1224,13 +1234,14 @@ static Stats gmres(const BlockMat& A, Solver& M, const double* b, double* x, con
   for (int i = 0; i < n; ++i) if (!std::isfinite(b[i])) { st.status = ENAN; return st; }
   if (beta0 == 0.0) { st.status = OK; return st; }
   int total = 0;
-  bool first = true;
+  bool first = true, broke = false;
   while (true) {
     const double beta = first ? beta0 : residual();
     first = false;
     st.relres = beta / beta0;
     if (!std::isfinite(beta)) { st.status = ENAN; break; }
     if (beta / beta0 < so.rtol) { st.status = OK; break; }
+    if (broke) { st.status = EBREAKDOWN; break; }
     if (total >= so.maxit) { st.status = NOT_CONVERGED; break; }
     if (total > 0) st.restarts++;
     for (int i = 0; i < n; ++i) V[0][i] = r[i] / beta;
@@ -1264,13 +1275,14 @@ static Stats gmres(const BlockMat& A, Solver& M, const double* b, double* x, con
       ++total;
       jend = j + 1;
       if (!std::isfinite(g[j + 1])) break;
-      if (hn <= 1e-300 || std::fabs(g[j + 1]) / beta0 < so.rtol || total >= so.maxit) break;
+      if (hn <= 1e-300) { broke = true; break; }
+      if (std::fabs(g[j + 1]) / beta0 < so.rtol || total >= so.maxit) break;
       for (int q = 0; q < n; ++q) V[j + 1][q] = w[q] / hn;
     }
     for (int i = jend - 1; i >= 0; --i) {   // back substitution H y = g
       double s = g[i];
       for (int k = i + 1; k < jend; ++k) s -= H[(size_t)i * m + k] * y[k];
-      y[i] = s / H[(size_t)i * m + i];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
     }
     if (so.flexible) {
       for (int k = 0; k < jend; ++k)

@@ -45,12 +45,18 @@ def test_block_matvec_matches_dense():
 
 
 # ------------------------------------------------------------ node graph
-@pytest.mark.parametrize("field,b", [(0, 2), (1, 1)])
-def test_node_graph_brute_force(field, b):
+@pytest.mark.parametrize("field,b,cut", [(0, 2, False), (1, 1, False), (0, 2, True), (1, 1, True)])
+def test_node_graph_brute_force(field, b, cut):
+    """u ~ v iff some dof of u and some dof of v are coupled by a stored entry
+    in either direction (the pattern of A + A^T), u != v."""
     s = small_tsi(5)
     A = s.blocks[field][field]
+    if cut:
+        A = nfgen.one_sided_pattern(A, 3)
+        assert (A != A.T).nnz > 0
     gp, ga = oracle.node_graph(A, b)
     D = A.toarray() != 0
+    D = D | D.T
     nn = A.shape[0] // b
     for u in range(nn):
         blk = D[b * u:b * u + b].reshape(b, nn, b).any(axis=(0, 2))
@@ -139,6 +145,62 @@ def test_mis2_matches_definition_bruteforce():
         st[und & near & (st == 0)] = 2
     got, _, _ = oracle.mis2_aggregate(gp, ga, seed)
     assert np.array_equal(got, st)
+
+
+def _aggregates_by_definition(gp, ga, st):
+    """Aggregates from the MIS-2 states, written out from the definition on a
+    dense adjacency: roots numbered in ascending node order; a non-root
+    adjacent to a root joins it (that root is unique); every other node joins
+    the adjacent phase-2 node's aggregate with the smallest number."""
+    n = len(gp) - 1
+    adj = np.zeros((n, n), bool)
+    for u in range(n):
+        adj[u, ga[gp[u]:gp[u + 1]]] = True
+    roots = np.nonzero(st == 1)[0]
+    agg = np.full(n, -1)
+    agg[roots] = np.arange(len(roots))
+    phase2 = np.zeros(n, bool)
+    for u in range(n):
+        if st[u] == 1:
+            continue
+        near = [r for r in roots if adj[u, r]]
+        assert len(near) <= 1                 # roots are at least 3 apart
+        if near:
+            agg[u] = agg[near[0]]
+            phase2[u] = True
+    ties = 0
+    for u in range(n):
+        if agg[u] >= 0:
+            continue
+        cand = sorted({agg[v] for v in np.nonzero(adj[u] & phase2)[0]})
+        assert cand, u
+        ties += len(cand) > 1
+        agg[u] = cand[0]
+    return agg, ties
+
+
+@pytest.mark.parametrize("name,make", GRAPHS + [("tsi-structure-13", lambda: oracle.node_graph(small_tsi(13).blocks[0][0], 2)),
+                                                ("fsi-grid", lambda: oracle.node_graph(nfgen.fsi3d(n=6, layers=2).blocks[1][1], 3))])
+@pytest.mark.parametrize("seed", [0, 7, 12])
+def test_aggregation_phase3_smallest_number(name, make, seed):
+    """The oracle's aggregates equal the definition; and the graphs used here
+    contain nodes whose phase-2 neighbours lie in different aggregates, so a
+    largest-number or first-found join would fail this test."""
+    gp, ga = make()
+    st, agg, na = oracle.mis2_aggregate(gp, ga, seed)
+    ref, ties = _aggregates_by_definition(gp, ga, st)
+    assert np.array_equal(agg, ref)
+
+
+def test_aggregation_phase3_ties_occur():
+    """The graphs of the phase-3 test include real ties (see above)."""
+    total = 0
+    for _, make in GRAPHS:
+        gp, ga = make()
+        for seed in (0, 7, 12):
+            st, _, _ = oracle.mis2_aggregate(gp, ga, seed)
+            total += _aggregates_by_definition(gp, ga, st)[1]
+    assert total >= 5, total
 
 
 # ------------------------------------------------------ tentative prolongator
@@ -346,24 +408,46 @@ def _simple_dense(A11, A12, A21, A22, dt):
     return L @ U
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
-def test_simple_matches_matrix_form(mode):
-    s = nfgen.tsi2d(nel=5, alpha=0.2, cba=0.1)
+def heat_first_tsi(nel, **kw):
+    """The TSI-like system with its fields swapped: the transient heat block
+    M/dt + K (row sums = the lumped mass / dt, all positive) is the SIMPLE
+    predictor and the elastic block the Schur field."""
+    return nfgen.permute_fields(nfgen.tsi2d(nel=nel, **kw), [1, 0])
+
+
+# the literal SIMPLEC diagonal |sum_j a_ij| needs a predictor whose row sums
+# do not vanish: it is pinned on the heat-first system, where it differs from
+# the other two choices (K has off-diagonal entries of both signs' effect)
+@pytest.mark.parametrize("heat_first,mode", [(False, 0), (False, 2), (True, 0), (True, 1), (True, 2)])
+def test_simple_matches_matrix_form(heat_first, mode):
+    s = heat_first_tsi(5, alpha=0.2, cba=0.1) if heat_first else nfgen.tsi2d(nel=5, alpha=0.2, cba=0.1)
     A = s.assembled().toarray()
     n0 = s.fields[0].ndof
     A11, A12, A21, A22 = A[:n0, :n0], A[:n0, n0:], A[n0:, :n0], A[n0:, n0:]
     B11 = s.blocks[0][0].toarray()
     dt = {0: np.abs(B11).sum(1), 1: np.abs(B11.sum(1)), 2: np.diag(B11)}[mode]
+    assert dt.min() > 1e-3 * dt.max()
     if mode == 1:
-        B = s.blocks[0][0]
-        if np.min(dt) < 1e-12:
-            pytest.skip("literal row sums vanish on this operator")
+        # the three diagonals are different here, so this pins mode 1 itself
+        assert np.abs(dt - np.abs(B11).sum(1)).max() > 0.1 * dt.max()
+        assert np.abs(dt - np.diag(B11)).max() > 0.1 * dt.max()
     o = Oracle(s.fields, s.blocks, "SIMPLE(LU;LU)", simplec_mode=mode)
     r = np.random.default_rng(3).standard_normal(s.n)
     z = o.precond_apply(r)
     M = _simple_dense(A11, A12, A21, A22, dt)
     ref = np.linalg.solve(M, r)
     assert np.abs(z - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_simplec_literal_gmres_reaches_dense_solution():
+    """GMRES with SIMPLE(AMG;AMG) and the literal SIMPLEC diagonal on the
+    heat-first system converges to the dense solution."""
+    s = heat_first_tsi(16)
+    o = Oracle(s.fields, s.blocks, "SIMPLE(AMG;AMG)", simplec_mode=1, coarse_max=40)
+    x, st = o.gmres(s.rhs[0], rtol=1e-10)
+    xd = np.linalg.solve(s.assembled().toarray(), s.rhs[0])
+    assert st["status"] == 0
+    assert np.linalg.norm(x - xd) < 1e-7 * np.linalg.norm(xd)
 
 
 def test_simple_exact_when_A11_diagonal():
@@ -508,6 +592,21 @@ def test_coloring_valid_and_greedy(name, make):
         assert all(c in lower for c in range(col[u])) and col[u] not in lower
 
 
+@pytest.mark.parametrize("b", [1, 2])
+def test_coloring_one_sided_coupling(b):
+    """A pattern in which row u couples to v but row v not to u: u and v still
+    get different colours (the colouring sees the coupling from both ends)."""
+    s = small_tsi(7)
+    A = nfgen.one_sided_pattern(s.blocks[2 - b][2 - b], 5, frac=0.5)
+    gp, ga = oracle.node_graph(A, b)
+    col, nc = oracle.color_nodes(gp, ga, 0)
+    coo = sp.coo_matrix(A)
+    nu, nv = coo.row // b, coo.col // b
+    off = nu != nv
+    assert off.sum() > 0
+    assert np.all(col[nu[off]] != col[nv[off]])
+
+
 def test_coloring_structured_stencil_uses_eight_colours():
     s = nfgen.fsi3d(n=6, layers=2)
     gp, ga = oracle.node_graph(s.blocks[1][1], 3)   # 27-point stencil on a 5^3 node grid
@@ -547,3 +646,24 @@ def test_sgs_equals_colour_splitting(field, b, omega):
     z1 = np.linalg.solve(D / omega + Lb, rhs + (D / omega - D - Ub) @ x0)
     got = oracle.sgs(A, b, rhs, omega=omega, x0=x0, half=1)
     assert np.abs(got - z1).max() < 1e-11 * np.abs(z1).max()
+
+
+# ------------------------------------------------------- Krylov breakdown
+def test_gmres_breakdown_statuses():
+    """Forward BGS with exact block solves on the singular A = [[I, I], [I, I]]
+    makes A M^-1 = [[0, I], [0, I]]: for b = [e_1; 0] the first Arnoldi
+    vector maps to zero and the iterate cannot improve (EBREAKDOWN, x = 0);
+    for b = [e_1; e_1] = A [e_1; 0] the breakdown gives the exact solution."""
+    n = 3
+    I = sp.identity(n, format="csr")
+    f = [nfgen.Field(f"f{k}", n, 1, np.ones((1, n))) for k in range(2)]
+    o = Oracle(f, [[I, I], [I, I]], "BGS[sweeps=1,order=fwd](LU)")
+    b = np.zeros(2 * n)
+    b[0] = 1.0
+    with pytest.raises(oracle.OracleError) as e:
+        o.gmres(b)
+    assert e.value.code == -4
+    b[n] = 1.0
+    x, st = o.gmres(b)
+    assert st["status"] == 0 and st["iters"] == 1
+    assert np.abs(sp.bmat([[I, I], [I, I]]) @ x - b).max() < 1e-14
