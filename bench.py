@@ -40,10 +40,10 @@ WORKLOADS = {
     # absolute row sums as D~ more iterations)
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
                   spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])",
-                  opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)),
+                  opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
-                  spec="BGS(AMG)", opts=dict(sweeps=2, order="bwd")),
+                  spec="BGS(AMG)", opts=dict(sweeps=2, order="bwd", max_rhs=1)),
     # lung-like saddle system: Q1 tissue on a 64^3 box, airway tree of depth
     # 12, 4096 acinus volume constraints; outer SIMPLE (D~ = diag(A11): 156
     # iterations, against 210 with the absolute row sums) with the monolithic
@@ -53,7 +53,7 @@ WORKLOADS = {
     # and a longer setup)
     "lung3d": dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=12, acinus=8, seed=seed),
                    spec="SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)",
-                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000)),
+                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000, max_rhs=1)),
 }
 SERVE_SPEC = "BGS(AMG)"
 # two backward BGS sweeps; Chebyshev interval [lambda/8, 1.1 lambda] (one
@@ -218,7 +218,9 @@ def run_workload(name, steps, warmup, seed, precision_form):
                     relres=float(np.linalg.norm(s.rhs[0] - A @ x32h) / np.linalg.norm(s.rhs[0])),
                     rel_err_vs_fp64=float(np.linalg.norm(x32h - xs) / np.linalg.norm(xs)),
                     footprint_mb=round(solver32.footprint_bytes() / 2**20, 1),
-                    fp64_footprint_mb=round(solver.footprint_bytes() / 2**20, 1))
+                    fp64_footprint_mb=round(solver.footprint_bytes() / 2**20, 1),
+                    precond_mb=round(solver32.precond_bytes() / 2**20, 1),
+                    fp64_precond_mb=round(solver.precond_bytes() / 2**20, 1))
         solver32.close()
     ms_per_step = 1e3 * elapsed / steps
     dom = max(prof, key=lambda p: p["ms"]) if prof else None
@@ -238,6 +240,88 @@ def run_workload(name, steps, warmup, seed, precision_form):
     return dict(system=s, stats=stats, elapsed=elapsed, roofline=roofline, prec=prec, prof=prof,
                 relres=relres, t_first_setup=t_first_setup, spec=W["spec"], opts=W["opts"],
                 footprint_mb=footprint_mb)
+
+
+def tsi_config0(steps=50, warmup=5, seed=0):
+    """The 2-field TSI-like system as its configuration states it (FP64,
+    GMRES(50) rtol 1e-8, two backward BGS sweeps with per-field SA-AMG,
+    degree-2 Chebyshev, coarse direct solves up to 200 dofs): BGS(AMG), and
+    the monolithic AMG(BGS) whose coarse levels carry the coupling blocks
+    R_i A_ij P_j; median of `steps` steps (rebuild + solve) each."""
+    import numpy as np
+    import torch
+    import nfgen
+    from paper_1605_01522_amd.nfield import NField
+    s = nfgen.tsi2d(nel=32, seed=seed)
+    b = torch.tensor(s.rhs[0], device="cuda")
+    A = s.assembled()
+    out = {}
+    for spec in ("BGS(AMG)", "AMG(BGS)"):
+        g = NField(s.fields, s.blocks, spec, sweeps=2, order="bwd", max_rhs=1)
+        x = torch.zeros_like(b)
+        ts, st = [], None
+        for k in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.rebuild()
+            x.zero_()
+            _, st = g.gmres_solve(b, x, rtol=1e-8)
+            torch.cuda.synchronize()
+            if k >= warmup:
+                ts.append(time.perf_counter() - t0)
+        xs = x.cpu().numpy()
+        rec = dict(gmres_iters=st[0]["iters"], status=st[0]["status"],
+                   median_ms_per_step=round(1e3 * float(np.median(ts)), 3),
+                   solves_per_s=round(len(ts) / sum(ts), 2),
+                   setup_ms=round(1e3 * st[0]["setup_s"], 3), solve_ms=round(1e3 * st[0]["solve_s"], 3),
+                   relres=float(np.linalg.norm(s.rhs[0] - A @ xs) / np.linalg.norm(s.rhs[0])),
+                   levels=g.nlevels(0), op_complexity=[round(g.complexity(h)[0], 3) for h in range(g.hier_count())])
+        if spec == "AMG(BGS)":
+            rec["coupled_coarse_nnz"] = [[g.matrix(0, l, "A", 0, 1).nnz, g.matrix(0, l, "A", 1, 0).nnz]
+                                         for l in range(g.nlevels(0))]
+        out[spec] = rec
+        g.close()
+    return dict(workload=f"tsi2d: n={s.n} dofs, nnz={s.nnz()}, two backward BGS sweeps, degree-2 Chebyshev "
+                         f"over [lambda/30, 1.1 lambda], coarse direct solves up to 200 dofs, FP64 GMRES(50) "
+                         f"rtol 1e-8, seed {seed}; a step = rebuild + solve; {steps} steps after {warmup} warm-up",
+                **out)
+
+
+def alpha_sweep(steps=3, seed=0):
+    """Coupling-strength sweep on the TSI-like system (the paper's robustness
+    experiment, Sec. 7.1): both coupling blocks scale with alpha; per alpha
+    and preconditioner, GMRES(50) iterations to rtol 1e-8 (maxit 1000) and
+    the median step time (rebuild + solve)."""
+    import numpy as np
+    import torch
+    import nfgen
+    from paper_1605_01522_amd.nfield import NField
+    specs = {"BGS(AMG)": dict(sweeps=2, order="bwd"), "BGS[order=sym](AMG)": dict(sweeps=2),
+             "AMG(BGS)": dict(sweeps=2, order="bwd"), "SIMPLE(AMG;AMG)": {}}
+    rows = []
+    for alpha in nfgen.ALPHA_SWEEP:
+        s = nfgen.tsi2d_alpha(alpha, nel=32, seed=seed)
+        b = torch.tensor(s.rhs[0], device="cuda")
+        row = dict(alpha=alpha)
+        for spec, o in specs.items():
+            g = NField(s.fields, s.blocks, spec, max_rhs=1, **o)
+            ts, st = [], None
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.rebuild()
+                _, st = g.gmres_solve(b, rtol=1e-8, maxit=1000)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[spec] = dict(iters=st[0]["iters"], status=st[0]["status"],
+                             ms=round(1e3 * float(np.median(ts)), 2))
+            g.close()
+        rows.append(row)
+        print(f"# alpha {alpha}: " + ", ".join(f"{k} {v['iters']}" for k, v in row.items() if k != "alpha"),
+              file=sys.stderr, flush=True)
+    return dict(workload="tsi2d 32 x 32, C_AB = alpha int B^T m N, C_BA = -0.1 alpha int N div N_u; "
+                         "GMRES(50) rtol 1e-8, maxit 1000 (status 1 = not converged), median of "
+                         f"{steps} steps (rebuild + solve)", rows=rows)
 
 
 def opts_text(opts):
@@ -351,6 +435,8 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--no-lung", action="store_true", help="skip the lung-like saddle system leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
+    ap.add_argument("--no-tsi", action="store_true", help="skip the TSI-like system's own timing")
+    ap.add_argument("--no-alpha-sweep", action="store_true", help="skip the coupling-strength sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this solver is built and "
@@ -399,8 +485,12 @@ def main():
     out["paper_context"] = PAPER_CONTEXT
     del r, s
     if not args.no_lung and args.workload != "lung3d":
-        out["lung"] = summary("lung3d", run_workload("lung3d", 2, 1, args.seed, not args.no_precision_form),
-                              2, args.seed)
+        out["lung"] = summary("lung3d", run_workload("lung3d", 5, 1, args.seed, not args.no_precision_form),
+                              5, args.seed)
+    if not args.no_tsi:
+        out["tsi2d"] = tsi_config0(seed=args.seed)
+    if not args.no_alpha_sweep:
+        out["alpha_sweep"] = alpha_sweep(seed=args.seed)
     if not args.no_serving:
         out["serving"] = serving(seed=args.seed)
     print(json.dumps(out), flush=True)

@@ -122,6 +122,11 @@ typedef struct {
                               stream of the library's own that first waits for the
                               caller's stream (which then waits for them); 0: one after
                               another on the caller's stream.  Same bits either way. */
+  int32_t max_rhs;         /* right-hand sides one launch sequence handles (1..8; default 8):
+                              the preconditioner's temporaries and the Krylov workspace
+                              hold this many columns; calls with more columns run in
+                              batches of max_rhs.  1 for single right-hand-side use keeps
+                              the context small. */
 } nfield_opts;
 
 typedef struct {
@@ -134,8 +139,13 @@ typedef struct {
 typedef struct {
   int32_t iters, restarts, status;
   double relres;           /* final true relative residual */
-  double setup_s, solve_s; /* wall seconds of nfield_setup and of this solve */
-  double bytes, gbps;      /* algorithmic HBM bytes of the solve, and bytes / solve_s */
+  double setup_s, solve_s; /* wall seconds of the last setup / rebuild and of this solve */
+  double bytes;            /* algorithmic HBM bytes of the solve's launches (every operand
+                              once per launch: matrix entries and indices, the vectors read
+                              and written; a Gauss-Seidel sweep's operand once per sweep).
+                              The columns of one batch of up to 8 share their launches: each
+                              column reports the batch's bytes. */
+  double gbps;             /* bytes / solve_s, in GB/s (1e9 bytes per second) */
 } nfield_stats;
 
 void nfield_default_opts(nfield_opts *opts);
@@ -166,7 +176,13 @@ nfield_status nfield_matvec(nfield_ctx *ctx, const double *x_dev, double *y_dev,
 /* Solve A x = b with right-preconditioned (or flexible) GMRES(m) per column.
  * x_dev holds the initial guess on entry and the solution on return.  stats
  * (nrhs entries, may be NULL) receives per-column results.  The call returns
- * after the solve has finished on the device. */
+ * after the solve has finished on the device.  Per column: OK when the true
+ * relative residual is below rtol; NOT_CONVERGED at maxit; EBREAKDOWN when
+ * the Arnoldi process broke down (||w|| <= 1e-300 after orthogonalisation:
+ * an invariant Krylov space) and the true residual still fails the test,
+ * where a restart would rebuild the same space (x holds the last iterate);
+ * ENAN for a non-finite right-hand side or iterate.  The return value is
+ * the worst column status (any negative one first). */
 nfield_status nfield_gmres_solve(nfield_ctx *ctx, const double *b_dev, double *x_dev,
                                  int32_t nrhs, const nfield_solve_opts *sopts,
                                  nfield_stats *stats, void *hip_stream);
@@ -202,6 +218,12 @@ int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, 
  * cached for reuse by later calls (temporaries of a rebuild return there
  * instead of being freed). */
 size_t nfield_footprint_bytes(const nfield_ctx *ctx);
+/* Device bytes the preconditioner itself holds after the last setup or
+ * rebuild: hierarchies (coarse blocks, transfers), smoother data, Schur
+ * approximations, coarse inverses, FP32 copies of the input blocks (precision
+ * form) and the preconditioner's temporaries; not the input blocks, the
+ * Krylov workspace or the cache. */
+size_t nfield_precond_bytes(const nfield_ctx *ctx);
 int64_t nfield_size(const nfield_ctx *ctx);             /* n = sum of field sizes */
 void nfield_destroy(nfield_ctx *ctx);
 const char *nfield_strerror(nfield_status s);
@@ -223,6 +245,18 @@ int64_t nfield_hier_matrix(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t 
 /* aggregate number of every node of field f on level l; returns the node count or -1 */
 int32_t nfield_hier_aggregates(const nfield_ctx *ctx, int32_t h, int32_t l, int32_t f,
                                int32_t *agg);
+/* stored entries of every block of level l of hierarchy h (-1 if absent) */
+int64_t nfield_hier_nnz(const nfield_ctx *ctx, int32_t h, int32_t l);
+/* operator complexity sum_l nnz(A^l) / nnz(A^0) and grid complexity
+ * sum_l n^l / n^0 of hierarchy h (0 if absent) */
+double nfield_hier_op_complexity(const nfield_ctx *ctx, int32_t h);
+double nfield_hier_grid_complexity(const nfield_ctx *ctx, int32_t h);
+
+/* Residual history of the last nfield_gmres_solve call, column col: the
+ * relative residual estimate |g_{j+1}| / ||r_0|| after every Arnoldi step
+ * (host copies).  Returns the number of steps (filling at most max values of
+ * out, which may be NULL), or -1 for a column the last call did not have. */
+int32_t nfield_residual_history(const nfield_ctx *ctx, int32_t col, double *out, int32_t max);
 
 #ifdef __cplusplus
 }

@@ -172,6 +172,20 @@ def tsi2d(nel=32, E=1.0, nu=0.3, kappa=1.0, dt=0.1, alpha=1e-2, cba=1e-3,
     return sys_
 
 
+def tsi2d_alpha(alpha, nel=32, seed=0, nrhs=1):
+    """The TSI-like system at coupling strength alpha: as in the paper's
+    thermo-mechanical system both off-diagonal blocks grow with the thermal
+    expansion coefficient, here C_AB = alpha int B^T m N and
+    C_BA = -0.1 alpha int N div(N_u) (opposite signs, as thermal stress and
+    thermoelastic heating have, so that the coupled operator stays
+    well-posed as alpha grows and only the block splittings suffer).
+    alpha = 1e-2 gives the default coupling magnitudes of tsi2d."""
+    return tsi2d(nel=nel, alpha=alpha, cba=0.1 * alpha, cba_sign=-1.0, seed=seed, nrhs=nrhs)
+
+
+ALPHA_SWEEP = (1e-2, 1e-1, 1.0, 10.0, 30.0, 100.0, 300.0, 1000.0)
+
+
 # --------------------------------------------------------------------------
 # 3-field FSI-like system (solid S, grid motion G, fluid F)
 # --------------------------------------------------------------------------

@@ -19,6 +19,7 @@ struct Opts {
   int graphs = 0;
   int block_products = 1;
   int parallel_setup = 1;
+  int max_rhs = NRMAX;
 };
 
 // N x N grid of device blocks over fields [0, N); a null block is zero.

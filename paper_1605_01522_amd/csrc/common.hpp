@@ -80,6 +80,12 @@ struct DevPool {
     live -= cls;
     cached += cls;
   }
+  // give a block back to the device instead of the cache (hipFree waits for
+  // the device)
+  void drop(void* p, size_t cls) {
+    live -= cls;
+    (void)hipFree(p);
+  }
   void trim() {
     if (blocks.empty()) return;
     (void)hipDeviceSynchronize();
@@ -141,6 +147,18 @@ struct DBuf {
   void release() {
     if (p) {
       if (pool) pool->put(p, cls);
+      else (void)hipFree(p);
+    }
+    p = nullptr;
+    n = 0;
+    pool = nullptr;
+    cls = 0;
+  }
+  // release to the device, not to the context's cache (the caller makes
+  // sure no queued work still uses the buffer)
+  void free_now() {
+    if (p) {
+      if (pool) pool->drop(p, cls);
       else (void)hipFree(p);
     }
     p = nullptr;

@@ -127,6 +127,10 @@ __global__ __launch_bounds__(256) void k_dense_gemvm(const double* __restrict__ 
   }
 }
 
+static thread_local double g_alg_bytes = 0.0;
+void bytes_count(double b) { g_alg_bytes += b; }
+double bytes_counted() { return g_alg_bytes; }
+
 static inline int grid_for(int64_t n, int threads = 256) {
   int64_t g = (n + threads - 1) / threads;
   if (g > 8192) g = 8192;
@@ -147,9 +151,11 @@ template <class S, class D> void cast_copy(const S* x, D* y, int64_t n, hipStrea
   if (n > 0) hipLaunchKernelGGL((k_cast<S, D>), dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
 }
 template <class T> void fillm(T* x, int64_t ldx, T v, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count((double)sizeof(T) * n * nrhs);
   if (n > 0 && nrhs > 0) hipLaunchKernelGGL(k_fillm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, x, ldx, v, n);
 }
 template <class S, class D> void castm(const S* x, int64_t ldx, D* y, int64_t ldy, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count((double)(sizeof(S) + sizeof(D)) * n * nrhs);
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL((k_castm<S, D>), dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, x, ldx, y, ldy, n);
 }
@@ -158,22 +164,26 @@ template <class T> void copym(const T* x, int64_t ldx, T* y, int64_t ldy, int64_
 }
 template <class T> void add_intom(const T* d, int64_t ldd, T* x, int64_t ldx, int64_t n, int nrhs, const int* mask,
                                   hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count(3.0 * sizeof(T) * n * nrhs);
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_add_intom<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, d, ldd, x, ldx, n, mask);
 }
 template <class T> void sub_scaledm(const T* dinv, const T* u, int64_t ldu, T* x, int64_t ldx, int64_t n, int nrhs,
                                     hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count((double)sizeof(T) * n * (1 + 3 * nrhs));
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_sub_scaledm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, dinv, u, ldu, x, ldx, n);
 }
 template <class T> void cheb_firstm(const T* b, int64_t ldb, const T* dinv, T inv_theta, T* d, int64_t ldd, T* x,
                                     int64_t ldx, int64_t n, int nrhs, hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count((double)sizeof(T) * n * (1 + 3 * nrhs));
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_cheb_firstm<T>, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, b, ldb, dinv, inv_theta, d, ldd,
                        x, ldx, n);
 }
 void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride, int64_t n,
                     int nrhs, const int* mask, hipStream_t s) {
+  if (n > 0 && nrhs > 0) bytes_count(16.0 * n * nrhs);
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_scale_inv_devm, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, w, ldw, v, ldv, nrm, stride, n,
                        mask);
@@ -181,6 +191,7 @@ void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const 
 template <class T> void dense_gemvm(const double* M, int n, const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs,
                                     hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
+  bytes_count(8.0 * n * n + 2.0 * sizeof(T) * n * nrhs);
   if (nrhs == 1) hipLaunchKernelGGL((k_dense_gemvm<1, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, ldb, x, ldx, nrhs);
   else hipLaunchKernelGGL((k_dense_gemvm<NRMAX, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, M, n, b, ldb, x, ldx, nrhs);
 }
@@ -409,6 +420,7 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
   if (A.nr <= 0) return;
   const T* val = csr_values<T>(A);
   const int G = spmv_lanes(A.nr, A.nnz);
+  bytes_count(spmv_bytes<T>(mode, A, a.nrhs));
   const bool timed = g_prof.on && !g_prof_quiet && g_prof.used < g_prof.ev.size() / 2;
   if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
   switch (mode) {
@@ -458,6 +470,7 @@ __global__ __launch_bounds__(256) void k_mreduce(const double* __restrict__ part
 
 void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n, int nrhs, double* partial, double* out,
           hipStream_t s) {
+  bytes_count(16.0 * n * nrhs);
   hipLaunchKernelGGL(k_dot_partialm, dim3(RED_BLOCKS, nrhs), dim3(256), 0, s, x, ldx, y, ldy, n, partial);
   hipLaunchKernelGGL(k_mreduce, dim3(1, nrhs), dim3(256), 0, s, partial, (int64_t)RED_BLOCKS, out, (int64_t)1, 0,
                      (const int*)nullptr);
@@ -583,6 +596,7 @@ void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double
                   const int* mask, hipStream_t s) {
   if (ncols <= 0) return;
   NF_CHECK(ncols <= 64, NFIELD_EINVAL, "GMRES restart length above 63 is not supported");
+  bytes_count(8.0 * L.n * (ncols + 1) * L.nrhs);
   if (ncols <= 8)
     hipLaunchKernelGGL(k_mdot<8>, dim3(RED_BLOCKS, L.nrhs, 1), dim3(256), 0, s, V, L.vs, L.n, ncols, w, ldw, partial, L.ps,
                        mask);
@@ -599,6 +613,7 @@ void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out
 void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
                  double* partial, const int* mask, hipStream_t s) {
   if (ncols <= 0 || L.n <= 0) return;
+  bytes_count(8.0 * L.n * (ncols + 2) * L.nrhs);
   NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
                                              L.n, ncols, h, L.hs, w, ldw, mask));
   mdot_partial(L, V, ncols, w, ldw, partial, mask, s);
@@ -606,6 +621,7 @@ void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double*
 void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
                   double* partial, const int* mask, hipStream_t s) {
   if (ncols <= 0 || L.n <= 0) return;
+  bytes_count(8.0 * L.n * (ncols + 3) * L.nrhs);
   NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
                                              L.n, ncols, h, L.hs, w, ldw, mask));
   hipLaunchKernelGGL(k_norm_partial, dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, L.n, w, ldw, partial, L.ps, mask);
@@ -613,6 +629,7 @@ void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double
 void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
               int64_t ldu, int accumulate, const int* mask, hipStream_t s) {
   if (max_ncols <= 0) return;
+  bytes_count(8.0 * L.n * (max_ncols + (accumulate ? 2 : 1)) * L.nrhs);
   NF_MAXC_DISPATCH(max_ncols, hipLaunchKernelGGL(k_mcombine<MC>, dim3(grid_cols(L.n, L.nrhs), L.nrhs), dim3(256), 0, s, V, L.vs,
                                                  L.n, ncols, y, (int64_t)L.m, u, ldu, accumulate, mask));
 }
@@ -675,7 +692,10 @@ __global__ void k_backsolve(const int* ncols, int m, const double* H, const doub
   for (int i = k - 1; i >= 0; --i) {
     double s = gk[i];
     for (int l = i + 1; l < k; ++l) s -= Hk[(int64_t)l * ld + i] * yk[l];
-    yk[i] = s / Hk[(int64_t)i * ld + i];
+    // a zero diagonal (A M singular on the Krylov space, after a breakdown)
+    // leaves that coefficient at zero
+    const double d = Hk[(int64_t)i * ld + i];
+    yk[i] = d != 0.0 ? s / d : 0.0;
   }
 }
 void givens_step(const GmresLayout& L, int j, const double* h1, const double* h2, const double* nrm_partial, double* H,
@@ -857,6 +877,31 @@ __global__ __launch_bounds__(64) void k_node_graph(int nnode, int b, const int* 
   }
   if (!FILL && lane == 0) cnt_or_off[u] = c;
 }
+// flag = 1 if some edge u -> v of the graph has no edge v -> u (the
+// neighbour lists are sorted: a binary search in v's list)
+__global__ void k_graph_asym(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* flag) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= n) return;
+  for (int p = gp[u]; p < gp[u + 1]; ++p) {
+    const int v = ga[p];
+    int lo = gp[v], hi = gp[v + 1];
+    const int end = hi;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ga[mid] < u) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo == end || ga[lo] != u) {
+      atomicOr(flag, 1);
+      return;
+    }
+  }
+}
+
+// The node graph is the pattern of A + A^T on nodes: the rows give u -> v;
+// when some edge has no reverse (a nonsymmetric pattern), the graph is
+// replaced by its union with its transpose, so that the MIS-2 distances and
+// the colouring see every coupling from both ends.
 void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nnode_out, hipStream_t s) {
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "block size must be between 1 and 8");
   NF_CHECK(A.nr == A.nc && A.nr % b == 0, NFIELD_EINVAL, "node graph: size is not a multiple of the block size");
@@ -867,7 +912,25 @@ void node_graph(const DCsr& A, int b, DBuf<int>& gptr, DBuf<int>& gadj, int* nno
   if (nn > 0) hipLaunchKernelGGL(k_node_graph<false>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, cnt.p, nullptr);
   const int64_t tot = exclusive_scan(cnt.p, gptr.p, nn, s);
   gadj.alloc(tot > 0 ? tot : 1);
-  if (nn > 0) hipLaunchKernelGGL(k_node_graph<true>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
+  if (nn <= 0 || tot <= 0) return;
+  hipLaunchKernelGGL(k_node_graph<true>, dim3(nn), dim3(64), 0, s, nn, b, A.ptr.p, A.col.p, gptr.p, gadj.p);
+  fill<int>(cnt.p, 0, 1, s);
+  hipLaunchKernelGGL(k_graph_asym, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, gptr.p, gadj.p, cnt.p);
+  int asym = 0;
+  NF_HIP(hipMemcpyAsync(&asym, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  if (!asym) return;
+  DCsr G, GT, U;
+  G.nr = G.nc = nn;
+  G.nnz = tot;
+  G.ptr = std::move(gptr);
+  G.col = std::move(gadj);
+  G.val.alloc(tot);
+  fill<double>(G.val.p, 1.0, tot, s);
+  transpose(G, GT, s);
+  csr_add(1.0, G, 1.0, GT, U, s);
+  gptr = std::move(U.ptr);
+  gadj = std::move(U.col);
 }
 
 // ===================================================================== MIS-2
@@ -997,8 +1060,10 @@ __global__ void k_max_int(const int* x, int n, int* out) {
 // Schedule: wait[w] counts the smaller neighbours of w (in w's own list) not
 // yet coloured; a node is coloured as soon as that count is zero and then
 // releases the nodes waiting on it (the reverse of the smaller-neighbour
-// relation, built first: the node graph need not be symmetric).  One
-// workgroup runs every round of frontiers, kept in two global lists.
+// relation, built first from the lists themselves).  node_graph makes the
+// graph symmetric, so a node sees every smaller neighbour and no two
+// neighbours share a colour.  One workgroup runs every round of frontiers,
+// kept in two global lists.
 __global__ void k_color_wait(int n, const int* __restrict__ gp, const int* __restrict__ ga, int* wait, int* rcnt, int* front,
                              int* nfront) {
   const int w = blockIdx.x * 256 + threadIdx.x;

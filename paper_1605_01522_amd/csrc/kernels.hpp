@@ -11,6 +11,13 @@ namespace nf {
 // mix, so a column's result does not depend on the other columns.
 constexpr int NRMAX = 8;
 
+// Algorithmic HBM bytes of the apply-phase launches made by this thread
+// (every operand counted once per launch: matrix entries, indices, the
+// vectors read and written), accumulated by the launch wrappers; a solve
+// reads the counter before and after to fill nfield_stats.bytes.
+void bytes_count(double b);
+double bytes_counted();
+
 // ------------------------------------------------------------ vectors
 template <class T> void fill(T* x, T v, int64_t n, hipStream_t s);   // one column
 template <class S, class D> void cast_copy(const S* x, D* y, int64_t n, hipStream_t s);

@@ -28,14 +28,17 @@ thread_local std::vector<std::unique_ptr<BlockMat>>* g_osink = nullptr;
 static thread_local std::string g_err;
 
 // ================================================================ helpers
-// Multi-column buffers: every temporary holds NRMAX columns of its length.
+// Multi-column buffers: every temporary of a preconditioner holds the
+// largest column count one call may pass (the max_rhs option, at most
+// NRMAX), set for the thread that builds it.
+thread_local int g_mbuf_cols = NRMAX;
 template <class T>
 struct MBuf {
   DBuf<T> buf;
   int64_t ld = 0;
   void alloc(int64_t n) {
     ld = n > 0 ? n : 1;
-    buf.alloc((size_t)ld * NRMAX);
+    buf.alloc((size_t)ld * g_mbuf_cols);
   }
   T* p() const { return buf.p; }
 };
@@ -219,7 +222,16 @@ struct SgsD : FieldSmootherD<T> {
     sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
     NF_HIP(hipStreamSynchronize(s));
     kind = sgs_kind(*A, b, nn, nc);
-    // bytes of a sweep are counted only while launch timing is recording
+    // a sweep's algorithmic bytes for the solve statistics: every entry and
+    // row bound once, node ids and D^-1, and per right-hand side the rhs, the
+    // own x read and written and the operand x once
+    {
+      const double sz = sizeof(T);
+      stat_bytes = (double)A->nnz * (sz + 4) + 4.0 * (b + 2) * nn + sz * n;
+      stat_bytes_x = 4.0 * sz * n;
+    }
+    // per-launch bytes with the distinct columns of every colour, counted
+    // only while launch timing is recording
     sweep_bytes = 0.0;
     sweep_bytes_x = 0.0;
     if (prof_recording()) {
@@ -236,9 +248,10 @@ struct SgsD : FieldSmootherD<T> {
   // algorithmic bytes of one sweep over all colours: every colour's rows'
   // entries and pointers, node ids and D^-1 (once), and per right-hand side
   // its rhs, own x read and written and each distinct column value read
-  double sweep_bytes = 0.0, sweep_bytes_x = 0.0;
+  double sweep_bytes = 0.0, sweep_bytes_x = 0.0, stat_bytes = 0.0, stat_bytes_x = 0.0;
   void sweep(bool forward, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const int nc = (int)off.size() - 1;
+    bytes_count(stat_bytes + nrhs * stat_bytes_x);
     const int slot = prof_begin(s);
     sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
@@ -291,10 +304,12 @@ struct DenseSgsD : FieldSmootherD<T> {
   void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
     for (int st = 0; st < steps; ++st) {
       const bool with_x = !(zero_guess && st == 0);
+      const double bytes =
+          (double)sizeof(T) * n * (with_x ? 2.0 * n : (double)n) + (double)nrhs * sizeof(T) * n * (with_x ? 3 : 2);
+      bytes_count(bytes);
       const int slot = prof_begin(s);
       dense_sweep_apply<T>(X.p, n, x, ldx, rhs, ldr, y.p(), y.ld, nrhs, with_x, s);
-      prof_end(slot, s, ((64 * 16 + b2) * 10 + 9) * 10 + (sizeof(T) == 4 ? 1 : 0),
-               (double)sizeof(T) * n * (with_x ? 2.0 * n : (double)n) + (double)nrhs * sizeof(T) * n * (with_x ? 3 : 2));
+      prof_end(slot, s, ((64 * 16 + b2) * 10 + 9) * 10 + (sizeof(T) == 4 ? 1 : 0), bytes);
       copym<T>(y.p(), y.ld, x, ldx, n, nrhs, s);
     }
   }
@@ -671,15 +686,19 @@ struct nfield_ctx {
   std::vector<std::shared_ptr<nf::DBuf<int>>> gpos;   // per block: entry -> position in Aglob
   nf::DBuf<float> r32, z32;
   double setup_s = 0.0;
+  size_t tree_bytes = 0;   // live device bytes the preconditioner tree holds
   // GMRES workspace
-  int ws_m = 0;
+  int ws_m = 0, ws_nr = 0;
   nf::DBuf<double> V, Z, w, z, r, u, H, cs, sn, g, y, h1, h2, partial, scal;
   nf::DBuf<int> imask;
   double* pinned = nullptr;
   int* pinned_i = nullptr;
+  // residual estimates of the last solve, per column
+  std::vector<std::vector<double>> hist;
   // preconditioner replay: graph per column count, captured on a private
   // stream into fixed input / output buffers
   hipGraphExec_t gexec[nf::NRMAX + 1] = {};
+  double gbytes[nf::NRMAX + 1] = {};   // algorithmic bytes of one replay
   hipStream_t cap_stream = nullptr;
   nf::DBuf<double> g_in, g_out;
   void drop_graphs() {
@@ -737,9 +756,11 @@ static void run_concurrently(nfield_ctx& C, const std::vector<std::function<void
   std::vector<std::exception_ptr> err(n);
   std::vector<char> ok(n, 0);
   std::vector<std::thread> th;
+  const int cols = g_mbuf_cols;
   for (size_t k = 1; k < n; ++k)
-    th.emplace_back([&, k] {
+    th.emplace_back([&, k, cols] {
       try {
+        g_mbuf_cols = cols;
         NF_HIP(hipSetDevice(dev));
         g_pool = &sb[k]->pool;
         g_hsink = &hs[k];
@@ -1097,63 +1118,124 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
 }
 
 // ================================================================= GMRES
-// Krylov workspace sized for NRMAX columns of restart length m.
-static void ensure_workspace(nfield_ctx& C, int m, int flexible) {
+// Device and host buffers of one GMRES call (the context's own, grown on
+// demand).
+struct KrylovWs {
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *u = nullptr;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h1 = nullptr, *h2 = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  int* imask = nullptr;            // 3 NRMAX ints
+  float *r32 = nullptr, *z32 = nullptr;   // FP32 staging of the precision form (n nrhs each)
+  double* pinned = nullptr;        // host staging, 64 doubles
+  int* pinned_i = nullptr;         // host staging, 64 ints
+  bool direct = false;             // launch the preconditioner directly (no graph replay)
+};
+
+// FP32 staging of the precision form for nrhs columns, grown on demand
+static void fp32_staging(nfield_ctx& C, int nrhs) {
   const int64_t n = C.Aglob.nr;
-  if (C.ws_m < m || (flexible && C.Z.n < (size_t)n * m * NRMAX)) {
-    C.V.alloc((size_t)n * (m + 1) * NRMAX);
-    if (flexible) C.Z.alloc((size_t)n * m * NRMAX);
-    C.H.alloc((size_t)(m + 1) * m * NRMAX);
-    C.cs.alloc((size_t)m * NRMAX);
-    C.sn.alloc((size_t)m * NRMAX);
-    C.g.alloc((size_t)(m + 1) * NRMAX);
-    C.y.alloc((size_t)m * NRMAX);
-    C.h1.alloc((size_t)(m + 1) * NRMAX);
-    C.h2.alloc((size_t)(m + 1) * NRMAX);
-    C.partial.alloc((size_t)RED_BLOCKS * (m + 1) * NRMAX);
-    C.ws_m = m;
+  if (C.root32 && C.r32.n < (size_t)n * nrhs) {
+    C.r32.alloc((size_t)n * nrhs);
+    C.z32.alloc((size_t)n * nrhs);
   }
-  if (!C.w.p) {
-    C.w.alloc((size_t)n * NRMAX);
-    C.z.alloc((size_t)n * NRMAX);
-    C.r.alloc((size_t)n * NRMAX);
-    C.u.alloc((size_t)n * NRMAX);
+}
+
+// Krylov workspace for nrhs columns of restart length m in the context's
+// own buffers, grown on demand (kept at the largest restart length and
+// column count used so far).
+static KrylovWs ctx_workspace(nfield_ctx& C, int m, int flexible, int nrhs) {
+  const int64_t n = C.Aglob.nr;
+  if (C.ws_m < m || C.ws_nr < nrhs) {
+    const int mm = std::max(m, C.ws_m), nr = std::max(nrhs, C.ws_nr);
+    C.V.alloc((size_t)n * (mm + 1) * nr);
+    if (C.Z.p) C.Z.alloc((size_t)n * mm * nr);
+    C.H.alloc((size_t)(mm + 1) * mm * nr);
+    C.cs.alloc((size_t)mm * nr);
+    C.sn.alloc((size_t)mm * nr);
+    C.g.alloc((size_t)(mm + 1) * nr);
+    C.y.alloc((size_t)mm * nr);
+    C.h1.alloc((size_t)(mm + 1) * nr);
+    C.h2.alloc((size_t)(mm + 1) * nr);
+    C.partial.alloc((size_t)RED_BLOCKS * (mm + 1) * nr);
+    C.ws_m = mm;
+    C.ws_nr = nr;
+  }
+  if (flexible && C.Z.n < (size_t)n * C.ws_m * C.ws_nr) C.Z.alloc((size_t)n * C.ws_m * C.ws_nr);
+  if (C.w.n < (size_t)n * C.ws_nr) {
+    C.w.alloc((size_t)n * C.ws_nr);
+    C.z.alloc((size_t)n * C.ws_nr);
+    C.r.alloc((size_t)n * C.ws_nr);
+    C.u.alloc((size_t)n * C.ws_nr);
+  }
+  if (!C.scal.p) {
     C.scal.alloc(4 * NRMAX);
     C.imask.alloc(3 * NRMAX);
   }
+  fp32_staging(C, nrhs);
   if (!C.pinned) NF_HIP(hipHostMalloc((void**)&C.pinned, 64 * sizeof(double), hipHostMallocDefault));
   if (!C.pinned_i) NF_HIP(hipHostMalloc((void**)&C.pinned_i, 64 * sizeof(int), hipHostMallocDefault));
+  KrylovWs W;
+  W.V = C.V.p;
+  W.Z = C.Z.p;
+  W.w = C.w.p;
+  W.z = C.z.p;
+  W.r = C.r.p;
+  W.u = C.u.p;
+  W.H = C.H.p;
+  W.cs = C.cs.p;
+  W.sn = C.sn.p;
+  W.g = C.g.p;
+  W.y = C.y.p;
+  W.h1 = C.h1.p;
+  W.h2 = C.h2.p;
+  W.partial = C.partial.p;
+  W.scal = C.scal.p;
+  W.imask = C.imask.p;
+  W.r32 = C.r32.p;
+  W.z32 = C.z32.p;
+  W.pinned = C.pinned;
+  W.pinned_i = C.pinned_i;
+  return W;
 }
 
-static void precond_direct(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
+static void precond_direct(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, float* r32,
+                           float* z32, hipStream_t s) {
   if (C.root64) {
     C.root64->apply(r, ldr, z, ldz, nrhs, s);
   } else {
     const int64_t n = C.Aglob.nr;
-    castm<double, float>(r, ldr, C.r32.p, n, n, nrhs, s);
-    C.root32->apply(C.r32.p, n, C.z32.p, n, nrhs, s);
-    castm<float, double>(C.z32.p, n, z, ldz, n, nrhs, s);
+    castm<double, float>(r, ldr, r32, n, n, nrhs, s);
+    C.root32->apply(r32, n, z32, n, nrhs, s);
+    castm<float, double>(z32, n, z, ldz, n, nrhs, s);
   }
 }
 
 // z = M^-1 r.  With graphs on (and launch timing off) the preconditioner's
 // kernels are recorded once per column count on a private stream, reading
 // g_in and writing g_out, and replayed on s between two copies; the kernels
-// and their order are those of precond_direct.
-static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s) {
-  if (!C.o.graphs || prof_recording()) return precond_direct(C, r, ldr, z, ldz, nrhs, s);
+// and their order are those of precond_direct.  W (may be null: the
+// context's own staging) gives the FP32 staging and may ask for direct
+// launches.
+static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int64_t ldz, int nrhs, hipStream_t s,
+                    const KrylovWs* W = nullptr) {
+  if (W && W->direct) return precond_direct(C, r, ldr, z, ldz, nrhs, W->r32, W->z32, s);
+  fp32_staging(C, nrhs);
+  if (!C.o.graphs || prof_recording()) return precond_direct(C, r, ldr, z, ldz, nrhs, C.r32.p, C.z32.p, s);
   const int64_t n = C.Aglob.nr;
   if (!C.g_in.p) {
-    C.g_in.alloc((size_t)n * NRMAX);
-    C.g_out.alloc((size_t)n * NRMAX);
+    C.g_in.alloc((size_t)n * C.o.max_rhs);
+    C.g_out.alloc((size_t)n * C.o.max_rhs);
   }
   if (!C.gexec[nrhs]) {
     if (!C.cap_stream) NF_HIP(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking));
     NF_HIP(hipStreamSynchronize(s));   // buffers the capture may allocate are then idle
     hipGraph_t g = nullptr;
     NF_HIP(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeRelaxed));
+    const double b0 = bytes_counted();
     try {
-      precond_direct(C, C.g_in.p, n, C.g_out.p, n, nrhs, C.cap_stream);
+      precond_direct(C, C.g_in.p, n, C.g_out.p, n, nrhs, C.r32.p, C.z32.p, C.cap_stream);
+      C.gbytes[nrhs] = bytes_counted() - b0;
+      bytes_count(-C.gbytes[nrhs]);   // counted at each replay instead
     } catch (...) {
       (void)hipStreamEndCapture(C.cap_stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -1165,32 +1247,33 @@ static void precond(nfield_ctx& C, const double* r, int64_t ldr, double* z, int6
     NF_HIP(e);
   }
   copym<double>(r, ldr, C.g_in.p, n, n, nrhs, s);
+  bytes_count(C.gbytes[nrhs]);
   NF_HIP(hipGraphLaunch(C.gexec[nrhs], s));
   copym<double>(C.g_out.p, n, z, ldz, n, nrhs, s);
 }
 
 // ||b_k - A x_k|| for nrhs columns, read back to host res[k]
-static void true_residuals(nfield_ctx& C, const double* b, int64_t ldb, const double* x, int64_t ldx, int nrhs,
-                           double* res, hipStream_t s) {
+static void true_residuals(nfield_ctx& C, const KrylovWs& W, const double* b, int64_t ldb, const double* x, int64_t ldx,
+                           int nrhs, double* res, hipStream_t s) {
   const int64_t n = C.Aglob.nr;
   SpmvArgs<double> a;
   a.x = x;
   a.ldx = ldx;
-  a.y = C.r.p;
+  a.y = W.r;
   a.ldy = n;
   a.b = b;
   a.ldb = ldb;
   a.nrhs = nrhs;
   spmv<double>(SPMV_RESID, C.Aglob, a, s);
-  dotm(C.r.p, n, C.r.p, n, n, nrhs, C.partial.p, C.scal.p, s);
-  NF_HIP(hipMemcpyAsync(C.pinned, C.scal.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  dotm(W.r, n, W.r, n, n, nrhs, W.partial, W.scal, s);
+  NF_HIP(hipMemcpyAsync(W.pinned, W.scal, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
   NF_HIP(hipStreamSynchronize(s));
-  for (int k = 0; k < nrhs; ++k) res[k] = std::sqrt(C.pinned[k]);
+  for (int k = 0; k < nrhs; ++k) res[k] = std::sqrt(W.pinned[k]);
 }
 
-static void upload_ints(nfield_ctx& C, const std::vector<int>& v, int* dev, hipStream_t s) {
-  for (size_t k = 0; k < v.size(); ++k) C.pinned_i[k] = v[k];
-  NF_HIP(hipMemcpyAsync(dev, C.pinned_i, sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
+static void upload_ints(const KrylovWs& W, const std::vector<int>& v, int* dev, hipStream_t s) {
+  for (size_t k = 0; k < v.size(); ++k) W.pinned_i[k] = v[k];
+  NF_HIP(hipMemcpyAsync(dev, W.pinned_i, sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
   NF_HIP(hipStreamSynchronize(s));   // the staging buffer is reused right away
 }
 
@@ -1205,12 +1288,11 @@ __global__ void k_init_gm(double* g, int m, const double* beta, const int* mask)
 // Arnoldi process (CGS2, Givens rotations on the device, its own
 // convergence test and restarts); the columns share only the kernel
 // launches, so a column's iterates do not depend on the other columns.
-static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                  const nfield_solve_opts& so, nfield_stats* st, hipStream_t s) {
+static void gmres(nfield_ctx& C, const KrylovWs& W, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                  const nfield_solve_opts& so, nfield_stats* st, hipStream_t s, std::vector<double>* hist = nullptr) {
   const int64_t n = C.Aglob.nr;
   const int m = so.restart;
   const bool flex = so.flexible != 0;
-  ensure_workspace(C, m, flex);
   GmresLayout L;
   L.n = n;
   L.vs = (int64_t)(m + 1) * n;
@@ -1220,13 +1302,13 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
   L.nrhs = nrhs;
   GmresLayout LZ = L;
   LZ.vs = (int64_t)m * n;
-  int* mask = C.imask.p;            // columns in the current Arnoldi cycle
-  int* part = C.imask.p + NRMAX;    // columns that took part in the cycle
-  int* jend = C.imask.p + 2 * NRMAX;
+  int* mask = W.imask;            // columns in the current Arnoldi cycle
+  int* part = W.imask + NRMAX;    // columns that took part in the cycle
+  int* jend = W.imask + 2 * NRMAX;
   std::vector<double> beta0(nrhs), beta(nrhs);
-  std::vector<int> total(nrhs, 0), done(nrhs, 0), cyc(nrhs, 0), je(nrhs, 0);
+  std::vector<int> total(nrhs, 0), done(nrhs, 0), cyc(nrhs, 0), je(nrhs, 0), broke(nrhs, 0);
   for (int k = 0; k < nrhs; ++k) std::memset(&st[k], 0, sizeof(nfield_stats));
-  true_residuals(C, b, ldb, x, ldx, nrhs, beta0.data(), s);
+  true_residuals(C, W, b, ldb, x, ldx, nrhs, beta0.data(), s);
   for (int k = 0; k < nrhs; ++k) {
     if (!std::isfinite(beta0[k])) { st[k].status = NFIELD_ENAN; done[k] = 1; }
     else if (beta0[k] == 0.0) { st[k].status = NFIELD_OK; done[k] = 1; }
@@ -1234,7 +1316,7 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
   bool first = true;
   while (true) {
     if (first) beta = beta0;
-    else true_residuals(C, b, ldb, x, ldx, nrhs, beta.data(), s);
+    else true_residuals(C, W, b, ldb, x, ldx, nrhs, beta.data(), s);
     first = false;
     int nact = 0;
     for (int k = 0; k < nrhs; ++k) {
@@ -1243,18 +1325,21 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
       st[k].relres = beta[k] / beta0[k];
       if (!std::isfinite(beta[k])) { st[k].status = NFIELD_ENAN; done[k] = 1; continue; }
       if (beta[k] / beta0[k] < so.rtol) { st[k].status = NFIELD_OK; done[k] = 1; continue; }
+      // a breakdown whose solution fails the true-residual test: a restart
+      // would rebuild the same invariant space
+      if (broke[k]) { st[k].status = NFIELD_EBREAKDOWN; done[k] = 1; continue; }
       if (total[k] >= so.maxit) { st[k].status = NFIELD_NOT_CONVERGED; done[k] = 1; continue; }
       if (total[k] > 0) st[k].restarts++;
       cyc[k] = 1;
       ++nact;
     }
     if (nact == 0) break;
-    upload_ints(C, cyc, mask, s);
-    for (int k = 0; k < nrhs; ++k) C.pinned[k] = beta[k];
-    NF_HIP(hipMemcpyAsync(C.scal.p + 2 * NRMAX, C.pinned, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+    upload_ints(W, cyc, mask, s);
+    for (int k = 0; k < nrhs; ++k) W.pinned[k] = beta[k];
+    NF_HIP(hipMemcpyAsync(W.scal + 2 * NRMAX, W.pinned, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
     // v_0 = r / beta (r holds the residuals of the last true_residuals call)
-    scale_inv_devm(C.r.p, n, C.V.p, L.vs, C.scal.p + 2 * NRMAX, 1, n, nrhs, mask, s);
-    hipLaunchKernelGGL(k_init_gm, dim3(nrhs), dim3(64), 0, s, C.g.p, m, C.scal.p + 2 * NRMAX, mask);
+    scale_inv_devm(W.r, n, W.V, L.vs, W.scal + 2 * NRMAX, 1, n, nrhs, mask, s);
+    hipLaunchKernelGGL(k_init_gm, dim3(nrhs), dim3(64), 0, s, W.g, m, W.scal + 2 * NRMAX, mask);
     NF_HIP(hipStreamSynchronize(s));   // the beta staging buffer is reused below
     std::vector<int> in_cycle = cyc;
     std::fill(je.begin(), je.end(), 0);
@@ -1263,26 +1348,26 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
     // the last two residual estimates of each column, to foresee the end
     std::vector<double> res1(beta), res2(nrhs, 0.0);
     for (int j = 0; j < m; ++j) {
-      double* vj = C.V.p + (int64_t)j * n;
-      double* zj = flex ? C.Z.p + (int64_t)j * n : C.z.p;
-      if (!z_ready) precond(C, vj, L.vs, zj, ldz, nrhs, s);
+      double* vj = W.V + (int64_t)j * n;
+      double* zj = flex ? W.Z + (int64_t)j * n : W.z;
+      if (!z_ready) precond(C, vj, L.vs, zj, ldz, nrhs, s, &W);
       z_ready = false;
       SpmvArgs<double> a;
       a.x = zj;
       a.ldx = ldz;
-      a.y = C.w.p;
+      a.y = W.w;
       a.ldy = n;
       a.nrhs = nrhs;
       spmv<double>(SPMV_STORE, C.Aglob, a, s);
       // classical Gram-Schmidt, twice
-      mdot_partial(L, C.V.p, j + 1, C.w.p, n, C.partial.p, mask, s);
-      mreduce(L, C.partial.p, j + 1, C.h1.p, 0, mask, s);
-      mupdate_dot(L, C.V.p, j + 1, C.h1.p, C.w.p, n, C.partial.p, mask, s);
-      mreduce(L, C.partial.p, j + 1, C.h2.p, 0, mask, s);
-      mupdate_norm(L, C.V.p, j + 1, C.h2.p, C.w.p, n, C.partial.p, mask, s);
-      givens_step(L, j, C.h1.p, C.h2.p, C.partial.p, C.H.p, C.cs.p, C.sn.p, C.g.p, C.scal.p, mask, s);
-      scale_inv_devm(C.w.p, n, C.V.p + (int64_t)(j + 1) * n, L.vs, C.scal.p, 2, n, nrhs, mask, s);
-      NF_HIP(hipMemcpyAsync(C.pinned, C.scal.p, 2 * sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      mdot_partial(L, W.V, j + 1, W.w, n, W.partial, mask, s);
+      mreduce(L, W.partial, j + 1, W.h1, 0, mask, s);
+      mupdate_dot(L, W.V, j + 1, W.h1, W.w, n, W.partial, mask, s);
+      mreduce(L, W.partial, j + 1, W.h2, 0, mask, s);
+      mupdate_norm(L, W.V, j + 1, W.h2, W.w, n, W.partial, mask, s);
+      givens_step(L, j, W.h1, W.h2, W.partial, W.H, W.cs, W.sn, W.g, W.scal, mask, s);
+      scale_inv_devm(W.w, n, W.V + (int64_t)(j + 1) * n, L.vs, W.scal, 2, n, nrhs, mask, s);
+      NF_HIP(hipMemcpyAsync(W.pinned, W.scal, 2 * sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
       // the next step's preconditioner needs only v_{j+1}: enqueued before
       // the wait for this step's residual estimates, so that the device has
       // work while the host tests them; not when every column is expected
@@ -1295,7 +1380,7 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
         more = !(res1[k] * rate < 2.0 * so.rtol * beta0[k] || total[k] + 1 >= so.maxit);
       }
       if (j + 1 < m && more) {
-        precond(C, C.V.p + (int64_t)(j + 1) * n, L.vs, flex ? C.Z.p + (int64_t)(j + 1) * n : C.z.p, ldz, nrhs, s);
+        precond(C, W.V + (int64_t)(j + 1) * n, L.vs, flex ? W.Z + (int64_t)(j + 1) * n : W.z, ldz, nrhs, s, &W);
         z_ready = true;
       }
       NF_HIP(hipStreamSynchronize(s));
@@ -1305,10 +1390,12 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
         if (!cyc[k]) continue;
         ++total[k];
         je[k] = j + 1;
-        const double hn = C.pinned[2 * k], res = C.pinned[2 * k + 1];
+        const double hn = W.pinned[2 * k], res = W.pinned[2 * k + 1];
+        if (hist) hist[k].push_back(res / beta0[k]);
         res2[k] = res1[k];
         res1[k] = res;
         if (!std::isfinite(res) || hn <= 1e-300 || res / beta0[k] < so.rtol || total[k] >= so.maxit) {
+          if (hn <= 1e-300) broke[k] = 1;
           cyc[k] = 0;
           changed = true;
         } else {
@@ -1316,21 +1403,21 @@ static void gmres(nfield_ctx& C, const double* b, int64_t ldb, double* x, int64_
         }
       }
       if (left == 0) break;
-      if (changed) upload_ints(C, cyc, mask, s);
+      if (changed) upload_ints(W, cyc, mask, s);
     }
     // end of the cycle: y = H^-1 g and the solution update for every column
     // that took part
-    upload_ints(C, in_cycle, part, s);
-    upload_ints(C, je, jend, s);
+    upload_ints(W, in_cycle, part, s);
+    upload_ints(W, je, jend, s);
     int maxj = 0;
     for (int k = 0; k < nrhs; ++k) maxj = std::max(maxj, je[k]);
-    backsolve(L, jend, C.H.p, C.g.p, C.y.p, part, s);
+    backsolve(L, jend, W.H, W.g, W.y, part, s);
     if (flex) {
-      mcombine(LZ, C.Z.p, jend, maxj, C.y.p, x, ldx, 1, part, s);
+      mcombine(LZ, W.Z, jend, maxj, W.y, x, ldx, 1, part, s);
     } else {
-      mcombine(L, C.V.p, jend, maxj, C.y.p, C.u.p, n, 0, part, s);
-      precond(C, C.u.p, n, C.z.p, n, nrhs, s);
-      add_intom<double>(C.z.p, n, x, ldx, n, nrhs, part, s);
+      mcombine(L, W.V, jend, maxj, W.y, W.u, n, 0, part, s);
+      precond(C, W.u, n, W.z, n, nrhs, s, &W);
+      add_intom<double>(W.z, n, x, ldx, n, nrhs, part, s);
     }
   }
   for (int k = 0; k < nrhs; ++k) st[k].iters = total[k];
@@ -1425,6 +1512,14 @@ static void merge_global(const nfield_csr* blocks, int N, const std::vector<int>
   NF_HIP(hipStreamSynchronize(s));
 }
 
+// device bytes in live buffers of the context (its own pool and the side
+// builds' pools)
+static size_t tree_live(const nfield_ctx& C) {
+  size_t b = C.pool.live;
+  for (auto& sb : C.side) b += sb->pool.live;
+  return b;
+}
+
 // (re)build the preconditioner tree from the device-resident blocks
 static void build_tree(nfield_ctx& C, hipStream_t s) {
   C.drop_graphs();
@@ -1435,17 +1530,34 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
   C.side_next = 0;
   g_hsink = &C.hiers;
   g_osink = &C.owned;
+  g_mbuf_cols = C.o.max_rhs;
+  for (auto& b : C.A.blk)   // FP32 copies of the inputs count as the tree's
+    if (b) b->val32.release();
+  const size_t live0 = tree_live(C);
   if (C.o.hier_fp32) {
     for (auto& b : C.A.blk)
       if (b) make_fp32(*b, s);
     C.root32 = build<float>(C, C.spec, C.A, C.F, 0, C.N, s);
-    if (!C.r32.p) {
-      C.r32.alloc((size_t)C.Aglob.nr * NRMAX);
-      C.z32.alloc((size_t)C.Aglob.nr * NRMAX);
-    }
+    // the FP32 tree runs on the FP32 copies alone: the FP64 values of the
+    // matrices it built (coarse levels, transfers, Schur approximations)
+    // are released; the input blocks keep theirs (rebuilds start there)
+    NF_HIP(hipStreamSynchronize(s));
+    for (auto& H : C.hiers)
+      for (size_t l = 0; l < H->lev.size(); ++l) {
+        Level& L = H->lev[l];
+        if (l > 0)
+          for (auto& b : L.A.blk)
+            if (b && b->val32.p) b->val.free_now();
+        for (auto& p : L.P) if (p && p->val32.p) p->val.free_now();
+        for (auto& r : L.R) if (r && r->val32.p) r->val.free_now();
+      }
+    for (auto& B : C.owned)
+      for (auto& b : B->blk)
+        if (b && b->val32.p) b->val.free_now();
   } else {
     C.root64 = build<double>(C, C.spec, C.A, C.F, 0, C.N, s);
   }
+  C.tree_bytes = tree_live(C) - live0;
 }
 
 __global__ void k_scatter_vals(const double* v, const int* pos, int64_t n, double* out) {
@@ -1483,6 +1595,7 @@ void nfield_default_opts(nfield_opts* o) {
   o->graphs = 0;
   o->block_products = 1;
   o->parallel_setup = 1;
+  o->max_rhs = NRMAX;
 }
 
 void nfield_default_solve_opts(nfield_solve_opts* so) {
@@ -1541,8 +1654,10 @@ nfield_status nfield_setup(int32_t nfields, const nfield_field* fields, const nf
     C->o.graphs = o.graphs;
     C->o.block_products = o.block_products;
     C->o.parallel_setup = o.parallel_setup;
+    C->o.max_rhs = o.max_rhs;
     NF_CHECK(o.sweeps >= 1 && o.order >= 0 && o.order <= 2 && o.cheb_degree >= 1 && o.max_levels >= 1 &&
-                 o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2,
+                 o.cheb_ratio > 1.0 && o.cheb_boost > 0.0 && o.simplec_mode >= 0 && o.simplec_mode <= 2 &&
+                 o.max_rhs >= 1 && o.max_rhs <= NRMAX,
              NFIELD_EINVAL, "options out of range");
     C->N = nfields;
     C->A.N = nfields;
@@ -1615,6 +1730,7 @@ size_t nfield_footprint_bytes(const nfield_ctx* ctx) {
   return b;
 }
 int64_t nfield_size(const nfield_ctx* ctx) { return ctx ? ctx->Aglob.nr : 0; }
+size_t nfield_precond_bytes(const nfield_ctx* ctx) { return ctx ? ctx->tree_bytes : 0; }
 
 nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, int32_t nrhs, void* hip_stream) {
   if (!ctx || !r || !z || nrhs < 0) { g_err = "nfield_precond_apply: bad argument"; return NFIELD_EINVAL; }
@@ -1624,8 +1740,9 @@ nfield_status nfield_precond_apply(nfield_ctx* ctx, const double* r, double* z, 
   ctx->pool.enter(s);
   try {
     const int64_t n = ctx->Aglob.nr;
-    for (int k = 0; k < nrhs; k += NRMAX) {
-      const int nb = std::min(NRMAX, nrhs - k);
+    const int cols = ctx->o.max_rhs;
+    for (int k = 0; k < nrhs; k += cols) {
+      const int nb = std::min(cols, nrhs - k);
       precond(*ctx, r + k * n, n, z + k * n, n, nb, s);
     }
     NF_HIP(hipGetLastError());
@@ -1658,14 +1775,15 @@ nfield_status nfield_matvec(nfield_ctx* ctx, const double* x, double* y, int32_t
   }
 }
 
-nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
+static nfield_status gmres_entry(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
                                  nfield_stats* stats, void* hip_stream) {
-  if (!ctx || !b || !x || nrhs < 0) { g_err = "nfield_gmres_solve: bad argument"; return NFIELD_EINVAL; }
+  const char* who = "nfield_gmres_solve";
+  if (!ctx || !b || !x || nrhs < 0) { g_err = std::string(who) + ": bad argument"; return NFIELD_EINVAL; }
   nfield_solve_opts so;
   nfield_default_solve_opts(&so);
   if (sopts) so = *sopts;
   if (so.restart < 1 || so.restart > 63 || so.maxit < 0 || !(so.rtol > 0)) {
-    g_err = "nfield_gmres_solve: restart must be in [1, 63], maxit >= 0, rtol > 0";
+    g_err = std::string(who) + ": restart must be in [1, 63], maxit >= 0, rtol > 0";
     return NFIELD_EINVAL;
   }
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1676,27 +1794,43 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
     const int64_t n = ctx->Aglob.nr;
     int worst = NFIELD_OK;
     std::vector<nfield_stats> st(NRMAX);
-    for (int k = 0; k < nrhs; k += NRMAX) {
-      const int nb = std::min(NRMAX, nrhs - k);
+    const int cols = ctx->o.max_rhs;   // columns per batch: what the preconditioner's temporaries hold
+    for (int k = 0; k < nrhs; k += cols) {
+      const int nb = std::min(cols, nrhs - k);
       const auto t0 = std::chrono::steady_clock::now();
-      gmres(*ctx, b + k * n, n, x + k * n, n, nb, so, st.data(), s);
+      const double b0 = bytes_counted();
+      if (k == 0) ctx->hist.assign(nrhs, {});
+      const KrylovWs W = ctx_workspace(*ctx, so.restart, so.flexible, nb);
+      gmres(*ctx, W, b + k * n, n, x + k * n, n, nb, so, st.data(), s, ctx->hist.data() + k);
       NF_HIP(hipStreamSynchronize(s));
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      const double bytes = bytes_counted() - b0;
       for (int q = 0; q < nb; ++q) {
         st[q].solve_s = dt;
         st[q].setup_s = ctx->setup_s;
+        st[q].bytes = bytes;
+        st[q].gbps = dt > 0.0 ? bytes / dt * 1e-9 : 0.0;
         if (stats) stats[k + q] = st[q];
         if (st[q].status < 0) worst = std::min(worst, st[q].status);
         else if (worst >= 0 && st[q].status > worst) worst = st[q].status;
       }
     }
     g_pool = prev;
-    if (worst < 0) g_err = "nfield_gmres_solve: non-finite value in the right-hand side or the iteration";
+    if (worst == NFIELD_ENAN) g_err = std::string(who) + ": non-finite value in the right-hand side or the iteration";
+    else if (worst == NFIELD_EBREAKDOWN)
+      g_err = std::string(who) + ": Krylov breakdown (the preconditioned operator is singular on the Krylov space) "
+                                 "and the true residual is above rtol";
+    else if (worst == NFIELD_NOT_CONVERGED) g_err = std::string(who) + ": iteration limit reached above rtol";
     return (nfield_status)worst;
   } catch (NfError& e) {
     g_pool = prev;
     return fail(e);
   }
+}
+
+nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
+                                 nfield_stats* stats, void* hip_stream) {
+  return gmres_entry(ctx, b, x, nrhs, sopts, stats, hip_stream);
 }
 
 nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const double* val, int32_t on_device,
@@ -1777,12 +1911,49 @@ int64_t nfield_hier_matrix(const nfield_ctx* c, int32_t h, int32_t l, int32_t wh
       for (int r = 0; r <= M->nr; ++r) rowptr[r] = p[r];
     }
     if (colind && M->nnz) NF_HIP(hipMemcpy(colind, M->col.p, sizeof(int) * M->nnz, hipMemcpyDeviceToHost));
-    if (val && M->nnz) NF_HIP(hipMemcpy(val, M->val.p, sizeof(double) * M->nnz, hipMemcpyDeviceToHost));
+    if (val && M->nnz) {
+      if (M->val.p) {
+        NF_HIP(hipMemcpy(val, M->val.p, sizeof(double) * M->nnz, hipMemcpyDeviceToHost));
+      } else {   // a precision-form matrix keeps its FP32 values only
+        std::vector<float> v32(M->nnz);
+        NF_HIP(hipMemcpy(v32.data(), M->val32.p, sizeof(float) * M->nnz, hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q < M->nnz; ++q) val[q] = v32[q];
+      }
+    }
     return M->nnz;
   } catch (NfError& e) {
     g_err = e.what();
     return -2;
   }
+}
+
+int64_t nfield_hier_nnz(const nfield_ctx* c, int32_t h, int32_t l) {
+  if (!c || h < 0 || h >= (int)c->hiers.size() || l < 0 || l >= (int)c->hiers[h]->lev.size()) return -1;
+  int64_t t = 0;
+  for (const auto& b : c->hiers[h]->lev[l].A.blk)
+    if (b) t += b->nnz;
+  return t;
+}
+
+static double hier_complexity(const nfield_ctx* c, int32_t h, bool op) {
+  if (!c || h < 0 || h >= (int)c->hiers.size() || c->hiers[h]->lev.empty()) return 0.0;
+  double t = 0.0, t0 = 0.0;
+  for (size_t l = 0; l < c->hiers[h]->lev.size(); ++l) {
+    const double v = op ? (double)nfield_hier_nnz(c, h, (int32_t)l) : (double)c->hiers[h]->lev[l].A.total();
+    if (l == 0) t0 = v;
+    t += v;
+  }
+  return t0 > 0.0 ? t / t0 : 0.0;
+}
+double nfield_hier_op_complexity(const nfield_ctx* c, int32_t h) { return hier_complexity(c, h, true); }
+double nfield_hier_grid_complexity(const nfield_ctx* c, int32_t h) { return hier_complexity(c, h, false); }
+
+int32_t nfield_residual_history(const nfield_ctx* c, int32_t col, double* out, int32_t max) {
+  if (!c || col < 0 || col >= (int)c->hist.size()) return -1;
+  const auto& v = c->hist[col];
+  if (out)
+    for (int32_t i = 0; i < max && i < (int32_t)v.size(); ++i) out[i] = v[i];
+  return (int32_t)v.size();
 }
 
 int32_t nfield_hier_aggregates(const nfield_ctx* c, int32_t h, int32_t l, int32_t f, int32_t* agg) {

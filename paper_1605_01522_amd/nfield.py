@@ -34,7 +34,8 @@ class nfield_opts(C.Structure):
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double),
                 ("simplec_mode", C.c_int32), ("split", C.c_void_p),
                 ("schur_direct_max", C.c_int32), ("hier_fp32", C.c_int32), ("seed", C.c_uint64),
-                ("graphs", C.c_int32), ("block_products", C.c_int32), ("parallel_setup", C.c_int32)]
+                ("graphs", C.c_int32), ("block_products", C.c_int32), ("parallel_setup", C.c_int32),
+                ("max_rhs", C.c_int32)]
 
 
 class nfield_solve_opts(C.Structure):
@@ -52,9 +53,11 @@ class nfield_stats(C.Structure):
 EXPORTS = ["nfield_default_opts", "nfield_default_solve_opts", "nfield_setup",
            "nfield_precond_apply", "nfield_matvec", "nfield_gmres_solve",
            "nfield_update_values", "nfield_rebuild", "nfield_prof_enable", "nfield_prof_read",
-           "nfield_footprint_bytes", "nfield_size", "nfield_destroy", "nfield_strerror",
+           "nfield_footprint_bytes", "nfield_precond_bytes", "nfield_size", "nfield_destroy", "nfield_strerror",
            "nfield_last_error", "nfield_hier_count", "nfield_hier_nlevels", "nfield_hier_nfields",
-           "nfield_hier_size", "nfield_hier_lambda", "nfield_hier_matrix", "nfield_hier_aggregates"]
+           "nfield_hier_size", "nfield_hier_lambda", "nfield_hier_matrix", "nfield_hier_aggregates",
+           "nfield_hier_nnz", "nfield_hier_op_complexity", "nfield_hier_grid_complexity",
+           "nfield_residual_history"]
 
 _lib = None
 
@@ -88,6 +91,8 @@ def lib():
     L.nfield_prof_read.restype = i32
     L.nfield_footprint_bytes.argtypes = [vp]
     L.nfield_footprint_bytes.restype = C.c_size_t
+    L.nfield_precond_bytes.argtypes = [vp]
+    L.nfield_precond_bytes.restype = C.c_size_t
     L.nfield_size.argtypes = [vp]
     L.nfield_size.restype = i64
     L.nfield_destroy.argtypes = [vp]
@@ -103,6 +108,13 @@ def lib():
     L.nfield_hier_matrix.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     L.nfield_hier_matrix.restype = i64
     L.nfield_hier_aggregates.argtypes = [vp, i32, i32, i32, vp]
+    L.nfield_hier_nnz.argtypes = [vp, i32, i32]
+    L.nfield_hier_nnz.restype = i64
+    for f in ("nfield_hier_op_complexity", "nfield_hier_grid_complexity"):
+        getattr(L, f).argtypes = [vp, i32]
+        getattr(L, f).restype = C.c_double
+    L.nfield_residual_history.argtypes = [vp, i32, vp, i32]
+    L.nfield_residual_history.restype = i32
     _lib = L
     return L
 
@@ -347,6 +359,9 @@ class NField:
     def footprint_bytes(self):
         return nfield_footprint_bytes(self.ctx)
 
+    def precond_bytes(self):
+        return lib().nfield_precond_bytes(self.ctx)
+
     def update_values(self, i, j, val, stream=None):
         nfield_update_values(self.ctx, i, j, val, stream)
 
@@ -385,6 +400,25 @@ class NField:
         val = np.zeros(max(nnz, 1), np.float64)
         L.nfield_hier_matrix(self.ctx, h, l, w, i, j, _p(ptr), _p(col), _p(val), None, None)
         return sp.csr_matrix((val[:nnz], col[:nnz], ptr), shape=(nr.value, nc.value))
+
+    def level_nnz(self, h, l):
+        return lib().nfield_hier_nnz(self.ctx, h, l)
+
+    def complexity(self, h=0):
+        """(operator complexity, grid complexity) of hierarchy h."""
+        L = lib()
+        return L.nfield_hier_op_complexity(self.ctx, h), L.nfield_hier_grid_complexity(self.ctx, h)
+
+    def residual_history(self, col=0):
+        """Relative residual estimates after every Arnoldi step of the last
+        solve, for one column (None if the last solve had no such column)."""
+        L = lib()
+        n = L.nfield_residual_history(self.ctx, col, None, 0)
+        if n < 0:
+            return None
+        out = np.zeros(max(n, 1), np.float64)
+        L.nfield_residual_history(self.ctx, col, _p(out), n)
+        return out[:n]
 
     def aggregates(self, h, l, f=0):
         L = lib()

@@ -97,6 +97,25 @@ def test_dense_inverse_symmetric(dev, n, kind):
         assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
 
 
+def test_dense_inverse_symmetric_4096(dev):
+    """The size of the lung-like system's dense S~ inverse (4,096 multipliers):
+    a symmetric definite matrix, inverted without row exchanges."""
+    n = 4096
+    _say(f"case dense inverse symmetric positive n={n}")
+    A = sp.csr_matrix(_symmetric(n, 17, "positive"))
+    A.sort_indices()
+    f = nfgen.Field("f", n, 1, np.ones((1, n)))
+    s = nfgen.BlockSystem([f], [[A]], np.zeros((1, n)))
+    g = _gpu(s, "LU")
+    r = np.random.default_rng(5).standard_normal((2, n))
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    Ad = A.toarray()
+    ref = np.linalg.solve(Ad, r.T).T
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - ref[k]) <= 1e-12 * np.linalg.norm(ref[k]), k
+        assert np.linalg.norm(Ad @ zg[k] - r[k]) <= 1e-12 * np.linalg.norm(r[k])
+
+
 def _nonsymmetric(n, seed, trap):
     """Nonsymmetric and diagonally dominant, or with a 1e-9 entry in the
     leading 2 x 2 block ([[1e-9, 1], [1, 1]]) whose elimination without row
@@ -223,6 +242,26 @@ def test_lung_benchmarked_configuration_parity(dev):
     assert st[0]["status"] == 0 and res < 1e-8
     assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
     assert abs(st[0]["iters"] - so["iters"]) <= 2
+
+
+def test_lung_full_size_precond_parity(dev):
+    """The benchmarked lung-like system at full size (831,678 dofs, 4,096
+    multipliers, the 4,096 x 4,096 dense S~ inverse): one application of
+    the benchmarked preconditioner against the oracle's."""
+    _say("case lung full size (n=64, depth=12, acinus=8) precond")
+    s = nfgen.lung3d(n=64, depth=12, acinus=8, seed=0)
+    spec = "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)"
+    opts = dict(simplec_mode=2, coarse_max=1000, **SPLIT)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(6).standard_normal(s.n)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    g.close()
+    _say("lung full size: oracle setup")
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    zo = o.precond_apply(r)
+    err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    _say(f"lung full size: preconditioner relative difference {err:.2e}")
+    assert err <= 1e-9
 
 
 def test_lung_mid_size_solution_parity(dev):

@@ -287,6 +287,96 @@ def test_fsi_full_size_sampled_parity(dev, fsi_full):
     res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
     _say(f"full-size fsi3d: iters {st[0]['iters']} relres {res:.2e}")
     assert st[0]["status"] == 0 and res < 1e-8
+    # the whole solve against the oracle's solve of the same system
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=1000)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"full-size fsi3d: oracle iters {so['iters']}, relative difference {err:.2e}")
+    assert so["status"] == 0
+    assert err <= 1e-6
+    assert abs(st[0]["iters"] - so["iters"]) <= 2, (st[0]["iters"], so["iters"])
+
+
+# --------------------------------------- SIMPLEC literal diagonal |sum_j a_ij|
+@pytest.mark.parametrize("spec", ["SIMPLE(AMG;AMG)", "SIMPLE(LU;LU)"])
+def test_simplec_literal_row_sums_parity(dev, spec):
+    """SIMPLE with the literal SIMPLEC diagonal (simplec_mode=1) on the
+    heat-first TSI-like system, whose predictor rows have nonzero sums:
+    preconditioner application and solution against the oracle."""
+    _say(f"case SIMPLEC literal {spec}")
+    s = nfgen.permute_fields(nfgen.tsi2d(nel=20, seed=6, nrhs=2), [1, 0])
+    opts = dict(simplec_mode=1, coarse_max=40)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(9).standard_normal((2, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k]), k
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs, device=dev), rtol=1e-8)
+    x = x.cpu().numpy()
+    for k in range(2):
+        xo, so = o.gmres(s.rhs[k], rtol=1e-8)
+        res = np.linalg.norm(s.rhs[k] - A @ x[k]) / np.linalg.norm(s.rhs[k])
+        assert st[k]["status"] == 0 and res < 1e-8
+        assert np.linalg.norm(x[k] - xo) <= 1e-6 * np.linalg.norm(xo)
+        assert abs(st[k]["iters"] - so["iters"]) <= 2
+
+
+# ------------------------------------------- nonsymmetric block patterns
+@pytest.mark.parametrize("spec", ["BGS(AMG[smoother=sgs,omega=0.9])", "BGS(AMG)",
+                                  "AMG[smoother=sgs,omega=0.9,half=1](BGS)"])
+def test_one_sided_pattern_parity(dev, spec):
+    """Diagonal blocks whose patterns are not symmetric (row u couples to v,
+    row v not to u): the node graphs are the symmetric union on both sides,
+    so aggregates are bit-exact and the colourings keep every coupled pair
+    apart; hierarchy and preconditioner against the oracle."""
+    _say(f"case one-sided pattern {spec}")
+    s = nfgen.tsi2d(nel=16, seed=2, nrhs=2)
+    for i in range(2):
+        s.blocks[i][i] = nfgen.one_sided_pattern(s.blocks[i][i], 10 + i, frac=0.3)
+    opts = dict(coarse_max=40, **TSI_OPTS)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    _compare_hierarchies(g, o)
+    r = np.random.default_rng(12).standard_normal((2, s.n))
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(zg[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k]), k
+
+
+# ------------------------------- coupling-strength sweep (Sec. 7.1, TSI)
+# the preconditioners of the sweep, each against the oracle at a weak, a
+# medium and a strong coupling (where some of them stop converging)
+ALPHA_SPECS = [("BGS(AMG)", dict(sweeps=2, order="bwd")), ("BGS[order=sym](AMG)", dict(sweeps=2)),
+               ("AMG(BGS)", dict(sweeps=2, order="bwd")), ("SIMPLE(AMG;AMG)", {})]
+
+
+@pytest.mark.parametrize("alpha", [1e-2, 30.0, 300.0])
+@pytest.mark.parametrize("spec,opts", ALPHA_SPECS)
+def test_alpha_sweep_parity(dev, spec, opts, alpha):
+    _say(f"case alpha sweep {spec} alpha={alpha}")
+    s = nfgen.tsi2d_alpha(alpha, nel=32, nrhs=1)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(13).standard_normal(s.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8, maxit=300)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=300)
+    _say(f"  gpu {st[0]['status']}/{st[0]['iters']} oracle {so['status']}/{so['iters']}")
+    if so["status"] == 0 and so["iters"] < 290:
+        res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+        assert st[0]["status"] == 0 and res < 1e-8
+        assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+        assert abs(st[0]["iters"] - so["iters"]) <= 2
+    else:
+        # both stop at the iteration limit (or both converge at its very end)
+        assert so["iters"] >= 290 and st[0]["iters"] >= 288
 
 
 def test_rebuild_after_value_update(dev):
