@@ -41,6 +41,11 @@ WORKLOADS = {
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
                   spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])",
                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
+    # the same system with the paper's own fluid smoother, DD(GS) (one
+    # workgroup per aggregate, Gauss-Seidel inside in colour order)
+    "fsi3d_dd": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
+                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1])",
+                     opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
                   spec="BGS(AMG)", opts=dict(sweeps=2, order="bwd", max_rhs=1)),

@@ -35,7 +35,16 @@
  * steps=1]" (symmetric multicolour Gauss-Seidel with damping omega instead of
  * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7;
  * "half=1": pre-smoothing sweeps the colours forward only, post-smoothing
- * backward only, instead of both sweeping forward then backward).
+ * backward only, instead of both sweeping forward then backward),
+ * "AMG[smoother=ddgs,omega=0.79]" (the paper's DD(GS) smoother of Sec. 7:
+ * Gauss-Seidel inside subdomains coupled additively; the subdomains are the
+ * level's aggregates, relaxed in colour order, one workgroup each),
+ * "AMG[pg=1]" (Petrov-Galerkin transfers for nonsymmetric fields, the
+ * paper's fluid AMG of Sec. 7 after Sala and Tuminaro: P = P_tent -
+ * D^-1 A P_tent diag(omega) with column dampings minimising ||A P e_j||_2,
+ * R from the same construction on A^T, coarse blocks R_i A_ij P_j).  A
+ * single-level block solve: "DDGS[omega=0.79,steps=1]" (DD(GS) sweeps from
+ * a zero guess, the paper's BGS(DD(GS)) comparison).
  *
  * All device work runs in the library's own HIP kernels for gfx950, enqueued
  * on the caller's stream (setup and rebuild may also use streams of the
@@ -202,15 +211,15 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
 /* Launch timing of the SpMV kernels (HIP events on the launch stream).
  * nfield_prof_enable(1) clears and starts recording, 0 stops.  prof_read
  * returns the number of kernel variants and fills up to max entries: key =
- * ((16*lanes_per_row + rows_per_node_group)*10 + kind)*10 + (1 if FP32),
+ * ((16*lanes_per_row + rows_per_node_group)*100 + kind)*10 + (1 if FP32),
  * kind 0-5 = SpMV epilogue (store, residual, add, subtract, Chebyshev step,
  * diagonal scaling); Gauss-Seidel sweeps (timed per sweep): 6 = a launch per
  * colour, one lane group per node; 7 = every colour in one single-workgroup
  * launch (tiny levels with many colours); 8 = a launch per colour, one
  * workgroup per node (long rows); 9 = the whole symmetric sweep of a small
- * many-colour level as one dense affine map x <- S x + Q b; launches, total
- * milliseconds, total algorithmic bytes (matrix once, operand once, epilogue
- * streams). */
+ * many-colour level as one dense affine map x <- S x + Q b; 10 = a DD(GS)
+ * sweep (one workgroup per subdomain); launches, total milliseconds, total
+ * algorithmic bytes (matrix once, operand once, epilogue streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);
 

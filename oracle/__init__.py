@@ -101,7 +101,8 @@ def lib():
                                     C.c_int32]
         L.orc_color_nodes.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]
         L.orc_sgs.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
-                              C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
+                              C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                              C.c_int32, C.c_void_p]
         L.orc_splitmix64.argtypes = [C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         _lib = L
@@ -332,14 +333,16 @@ def color_nodes(gptr, gadj, seed):
     return col, nc
 
 
-def sgs(A, b, rhs, omega=1.0, steps=1, seed=0, x0=None, half=0):
+def sgs(A, b, rhs, omega=1.0, steps=1, seed=0, x0=None, half=0, dd=False, sub=None):
     """Multicolour SGS from x0 (zero if None); half: forward sweeps only from
-    a zero guess, backward sweeps only otherwise."""
+    a zero guess, backward sweeps only otherwise.  dd: the DD(GS) smoother,
+    with the subdomains `sub` (node -> subdomain; None: the aggregates)."""
     p, c, v = _csr_arrays(A)
     rhs = np.ascontiguousarray(rhs, np.float64)
     x = np.zeros_like(rhs) if x0 is None else np.ascontiguousarray(x0, np.float64).copy()
+    sb = None if sub is None else np.ascontiguousarray(sub, np.int32)
     rc = lib().orc_sgs(A.shape[0], _p(p), _p(c), _p(v), b, omega, steps, seed, _p(rhs), _p(x),
-                       1 if x0 is None else 0, half)
+                       1 if x0 is None else 0, half, 1 if dd else 0, None if sb is None else _p(sb))
     if rc != 0:
         raise OracleError(rc, lib().orc_last_error().decode())
     return x

@@ -311,6 +311,16 @@ static std::vector<int> aggregate(const Graph& G, const std::vector<int>& state,
   return agg;
 }
 
+// Subdomains of the DD(GS) smoother: the MIS-2 aggregates of the level's
+// node graph for the same seed, i.e. the aggregates the AMG coarsening of
+// that level forms (compact patches of a node and its neighbours).
+static std::vector<int> dd_subdomains(const Graph& G, uint64_t seed, int* n_sub);
+
+static std::vector<int> dd_subdomains(const Graph& G, uint64_t seed, int* n_sub) {
+  std::vector<int> st = mis2(G, seed);
+  return aggregate(G, st, n_sub);
+}
+
 // Greedy colouring of the node graph in node order: node u takes the
 // smallest colour not used by its neighbours of smaller index.  (On a
 // structured 27-point stencil numbered lexicographically this gives 8
@@ -486,6 +496,7 @@ struct Opts {
   std::vector<int> split;    // field -> group (0 predictor, 1 Schur); empty: last field is Schur
   int schur_direct_max = 5000;
   uint64_t seed = 0;
+  int pg = 0;                // Petrov-Galerkin transfers (per AMG node of the specification)
 };
 
 // ------------------------------------------------------- block matrices
@@ -539,16 +550,24 @@ struct BlockMat {
 //    node are updated together from the values before the node's update.
 //    With half, pre-smoothing (before the coarse correction) sweeps forward
 //    only and post-smoothing backward only; the level smoother tells the
-//    field smoother which of the two it is doing.
+//    field smoother which of the two it is doing;
+//  * DD(GS) with damping omega, the paper's domain-decomposition smoother
+//    (Sec. 7: Gauss-Seidel inside each subdomain, the subdomains coupled
+//    additively): the nodes are split into subdomains (the level's
+//    aggregates); in a sweep every subdomain relaxes its nodes in the colour
+//    order of the multicolour SGS, using the newest values of its own nodes
+//    and the values the other subdomains' nodes held when the sweep began.
+//    Forward then backward, or half sweeps as above.
 struct Cheb {
   const Csr* A = nullptr;
   std::vector<double> dinv;
   double lambda = 0.0, lo = 0.0, hi = 0.0;
   int degree = 2;
-  int kind = 0;                       // 0 Chebyshev, 1 multicolour SGS
+  int kind = 0;                       // 0 Chebyshev, 1 multicolour SGS, 2 DD(GS)
   int bs = 1, steps = 1, half = 0;
   double omega = 1.0;
   std::vector<std::vector<int>> color_nodes;   // nodes of each colour, ascending
+  std::vector<int> sub;                        // DD(GS): node -> subdomain
   void setup_sgs(const Csr* A_, int b, double om, int st, uint64_t seed) {
     A = A_;
     std::vector<double> d = diagonal(*A);
@@ -567,27 +586,52 @@ struct Cheb {
     color_nodes.assign(nc, {});
     for (int u = 0; u < G.n; ++u) color_nodes[col[u]].push_back(u);
   }
-  void relax_color(int c, const double* b, double* x) const {
+  // DD(GS): the SGS set-up plus the subdomains (given, or the aggregates)
+  void setup_ddgs(const Csr* A_, int b, double om, int st, uint64_t seed, const int* given_sub = nullptr) {
+    setup_sgs(A_, b, om, st, seed);
+    kind = 2;
+    Graph G = node_graph(*A, b);
+    if (given_sub) {
+      sub.assign(given_sub, given_sub + G.n);
+    } else {
+      int ns = 0;
+      sub = dd_subdomains(G, seed, &ns);
+    }
+  }
+  // relax the nodes of colour c; with DD(GS) (xold non-null) a coupling to a
+  // node of another subdomain takes that node's value from xold
+  void relax_color(int c, const double* b, double* x, const double* xold = nullptr) const {
     std::vector<double> upd(bs);
     for (int u : color_nodes[c]) {
       for (int q = 0; q < bs; ++q) {
         const int r = u * bs + q;
         double s = b[r];
-        for (int64_t p = A->ptr[r]; p < A->ptr[r + 1]; ++p) s -= A->val[p] * x[A->col[p]];
+        for (int64_t p = A->ptr[r]; p < A->ptr[r + 1]; ++p) {
+          const int cc = A->col[p];
+          const bool own = !xold || sub[cc / bs] == sub[u];
+          s -= A->val[p] * (own ? x[cc] : xold[cc]);
+        }
         upd[q] = omega * dinv[r] * s;
       }
       for (int q = 0; q < bs; ++q) x[u * bs + q] += upd[q];
     }
   }
+  // one sweep over the colours in the given direction; DD(GS): every
+  // subdomain relaxes its own nodes in colour order against the values its
+  // neighbours held when the sweep began (block Jacobi between subdomains,
+  // Gauss-Seidel inside)
+  void sweep(bool forward, const double* b, double* x) const {
+    const int nc = (int)color_nodes.size();
+    std::vector<double> xold;
+    if (kind == 2) xold.assign(x, x + A->nr);
+    for (int k = 0; k < nc; ++k) relax_color(forward ? k : nc - 1 - k, b, x, kind == 2 ? xold.data() : nullptr);
+  }
   // pre: this application is pre-smoothing (only matters with half)
   void apply_sgs(const double* b, double* x, bool zero_guess, bool pre) const {
     if (zero_guess) std::fill(x, x + A->nr, 0.0);
-    const int nc = (int)color_nodes.size();
     for (int st = 0; st < steps; ++st) {
-      if (!half || pre)
-        for (int c = 0; c < nc; ++c) relax_color(c, b, x);
-      if (!half || !pre)
-        for (int c = nc - 1; c >= 0; --c) relax_color(c, b, x);
+      if (!half || pre) sweep(true, b, x);
+      if (!half || !pre) sweep(false, b, x);
     }
   }
   void setup(const Csr* A_, double lam, const Opts& o) {
@@ -604,7 +648,7 @@ struct Cheb {
     degree = o.cheb_degree;
   }
   void apply(const double* b, double* x, bool zero_guess, bool pre = true) const {
-    if (kind == 1) { apply_sgs(b, x, zero_guess, pre); return; }
+    if (kind >= 1) { apply_sgs(b, x, zero_guess, pre); return; }
     const int n = A->nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     std::vector<double> r(n), d(n);
@@ -648,6 +692,37 @@ struct Hierarchy {
   DenseLU coarse;
   int N = 0;
 };
+
+// Petrov-Galerkin smoothing of a tentative prolongator (Sala and Tuminaro,
+// "A new Petrov-Galerkin smoothed aggregation preconditioner for
+// nonsymmetric linear systems", SIAM J. Sci. Comput. 2008, the method the
+// paper uses for the fluid, Sec. 7): P = P_tent - Q diag(omega) with
+// Q = D^-1 A P_tent, each column's damping omega_j minimising ||A P e_j||_2,
+// omega_j = <A P_tent e_j, A Q e_j> / ||A Q e_j||^2, and 0 where that is
+// negative or A Q e_j = 0.  The column sums run over the rows in ascending
+// order.  Given A^T instead of A this gives the transpose of the restriction.
+static Csr pg_smooth(const Csr& A, const Csr& Pt, const std::vector<double>& dinv) {
+  Csr AP = spgemm(A, Pt);
+  Csr Q = AP;
+  scale_rows(Q, dinv);
+  Csr AQ = spgemm(A, Q);
+  std::vector<double> num(Pt.nc, 0.0), den(Pt.nc, 0.0);
+  for (int r = 0; r < AQ.nr; ++r) {
+    int64_t p = AP.ptr[r];
+    for (int64_t q = AQ.ptr[r]; q < AQ.ptr[r + 1]; ++q) {
+      const int c = AQ.col[q];
+      while (p < AP.ptr[r + 1] && AP.col[p] < c) ++p;
+      if (p < AP.ptr[r + 1] && AP.col[p] == c) num[c] += AP.val[p] * AQ.val[q];
+      den[c] += AQ.val[q] * AQ.val[q];
+    }
+  }
+  std::vector<double> omega(Pt.nc, 0.0);
+  for (int c = 0; c < Pt.nc; ++c)
+    if (den[c] > 0.0 && num[c] > 0.0) omega[c] = num[c] / den[c];
+  for (int r = 0; r < Q.nr; ++r)
+    for (int64_t p = Q.ptr[r]; p < Q.ptr[r + 1]; ++p) Q.val[p] *= -omega[Q.col[p]];
+  return add(1.0, Pt, 1.0, Q);
+}
 
 static void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDesc>& F,
                             const Opts& o) {
@@ -710,19 +785,29 @@ static void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<
         const int k = (int)(L.B[i].size() / n);
         if (k == 0) throw Error(EINVAL_, "AMG: field has no near-nullspace vectors");
         Tentative T = tentative(L.agg[i], na, L.bs[i], k, L.B[i]);
-        // smoothed prolongator P = (I - omega D^-1 A) P_tent, omega = 4/(3 lambda)
-        std::vector<double> d = diagonal(Aii), s(n);
-        const double omega = 4.0 / (3.0 * L.lambda[i]);
-        for (int r = 0; r < n; ++r) s[r] = -omega / d[r];
-        Csr AP = spgemm(Aii, T.P);
-        scale_rows(AP, s);
-        L.P[i] = add(1.0, T.P, 1.0, AP);
+        std::vector<double> d = diagonal(Aii);
+        if (o.pg) {
+          // Petrov-Galerkin smoothed aggregation: column-wise dampings for
+          // P from A and for R from A^T
+          std::vector<double> dinv(n);
+          for (int r = 0; r < n; ++r) dinv[r] = 1.0 / d[r];
+          L.P[i] = pg_smooth(Aii, T.P, dinv);
+          L.R[i] = transpose(pg_smooth(transpose(Aii), T.P, dinv));
+        } else {
+          // smoothed prolongator P = (I - omega D^-1 A) P_tent, omega = 4/(3 lambda)
+          std::vector<double> s(n);
+          const double omega = 4.0 / (3.0 * L.lambda[i]);
+          for (int r = 0; r < n; ++r) s[r] = -omega / d[r];
+          Csr AP = spgemm(Aii, T.P);
+          scale_rows(AP, s);
+          L.P[i] = add(1.0, T.P, 1.0, AP);
+        }
         C.bs[i] = k;
         C.B[i] = T.Bc;
         C.dead[i] = T.dead;
         if (na * k > 0.83 * n) active[i] = 0;   // coarsening stalled
       }
-      L.R[i] = transpose(L.P[i]);
+      if (L.R[i].nr == 0 && L.R[i].nc == 0) L.R[i] = transpose(L.P[i]);   // R = P^T unless Petrov-Galerkin
     }
     C.A.N = N;
     C.A.size.resize(N);
@@ -759,6 +844,14 @@ struct Ctx;
 struct LuSolver : Solver {
   DenseLU lu;
   void apply(const double* r, double* z) override { lu.solve(r, z); }
+};
+
+// A single-level smoother used as a block solve (the DD(GS) block solver of
+// the paper's single-level comparison BGS(DD(GS)), Sec. 7): its sweeps from
+// a zero guess, forward then backward.
+struct SmootherSolver : Solver {
+  Cheb sm;
+  void apply(const double* r, double* z) override { sm.apply(r, z, true, true); }
 };
 
 // Level smoother of a (monolithic) hierarchy: one BGS sweep or one SIMPLE
@@ -988,7 +1081,7 @@ struct SimpleSolver : Solver {
 // in brackets: "BGS[sweeps=2,order=bwd](AMG)".
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -1018,12 +1111,16 @@ struct Parser {
         if (k == "sweeps") sp.sweeps = atoi(v.c_str());
         else if (k == "order") sp.order = v == "fwd" ? 0 : v == "bwd" ? 1 : v == "sym" ? 2 : -9;
         else if (k == "degree") sp.degree = atoi(v.c_str());
-        else if (k == "smoother") sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : -9;
+        else if (k == "smoother") sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : v == "ddgs" ? 2 : -9;
         else if (k == "omega") sp.omega = atof(v.c_str());
         else if (k == "steps") sp.steps = atoi(v.c_str());
         else if (k == "half") {
           sp.half = atoi(v.c_str());
           if (sp.half != 0 && sp.half != 1) throw Error(EINVAL_, "spec: bad value " + v);
+        }
+        else if (k == "pg") {
+          sp.pg = atoi(v.c_str());
+          if (sp.pg != 0 && sp.pg != 1) throw Error(EINVAL_, "spec: bad value " + v);
         }
         else throw Error(EINVAL_, "spec: unknown parameter " + k);
         if (sp.smoother == -9 || (k == "omega" && !(sp.omega > 0.0 && sp.omega < 2.0)) ||
@@ -1079,7 +1176,7 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
   auto S = std::make_unique<AmgSolver>();
   Opts lo = C.o;                       // this hierarchy's smoother degree
   if (amg.degree > 0) lo.cheb_degree = amg.degree;
-  const bool sgs = amg.smoother == 1;
+  const bool sgs = amg.smoother == 1 || amg.smoother == 2;
   const double omega = amg.omega > 0.0 ? amg.omega : 1.0;
   const int steps = amg.steps > 0 ? amg.steps : 1;
   BlockMat sub = sub_blocks(A, f0, f1);
@@ -1087,7 +1184,9 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
   for (int i = 0; i < sub.N; ++i)
     if (!sub.at(i, i) && !(smoother && smoother->name == "SIMPLE" && i == sub.N - 1))
       throw Error(ESINGULAR, "AMG: zero diagonal block");
-  build_hierarchy(S->H, sub, Fs, C.o);
+  Opts ho = C.o;
+  ho.pg = amg.pg;
+  build_hierarchy(S->H, sub, Fs, ho);
   S->n = sub.total();
   S->smoother_kind = smoother && smoother->name == "SIMPLE" ? 1 : 0;
   const int nl = (int)S->H.lev.size();
@@ -1102,7 +1201,8 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
     const int nchb = M.kind == 1 ? sub.N - 1 : sub.N;
     for (int i = 0; i < nchb; ++i) {
       if (sgs) {
-        M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
+        if (amg.smoother == 2) M.cheb[i].setup_ddgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
+        else M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
         M.cheb[i].half = amg.half;
       } else {
         M.cheb[i].setup(L.A.at(i, i), L.lambda[i], lo);
@@ -1135,6 +1235,16 @@ static std::unique_ptr<Solver> build(Ctx& C, const Spec& sp, const BlockMat& A, 
     BlockMat sub = sub_blocks(A, f0, f1);
     S->n = sub.total();
     S->lu.factor(sub.dense(0, nf), S->n);
+    return S;
+  }
+  if (sp.name == "DDGS") {
+    if (!sp.kids.empty()) throw Error(EINVAL_, "spec: DDGS takes no argument");
+    if (nf != 1) throw Error(EINVAL_, "spec: DDGS needs a single field");
+    const Csr* Aii = A.at(f0, f0);
+    if (!Aii) throw Error(ESINGULAR, "DDGS: zero diagonal block");
+    auto S = std::make_unique<SmootherSolver>();
+    S->sm.setup_ddgs(Aii, F[f0].bs, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed);
+    S->n = Aii->nr;
     return S;
   }
   if (sp.name == "AMG") {
@@ -1586,9 +1696,12 @@ int orc_color_nodes(int32_t nnode, const int64_t* gptr, const int32_t* gadj, uin
   return nc;
 }
 
-// one application of the multicolour SGS smoother (for splitting-form tests)
+// one application of the multicolour SGS smoother (for splitting-form tests);
+// dd: the DD(GS) smoother instead, with subdomains sub (node -> subdomain;
+// NULL: the aggregates)
 int orc_sgs(int32_t n, const int64_t* rowptr, const int32_t* col, const double* val, int32_t b, double omega,
-            int32_t steps, uint64_t seed, const double* rhs, double* x, int32_t zero_guess, int32_t half) {
+            int32_t steps, uint64_t seed, const double* rhs, double* x, int32_t zero_guess, int32_t half, int32_t dd,
+            const int32_t* sub) {
   try {
     orc::Csr A;
     A.nr = A.nc = n;
@@ -1596,7 +1709,8 @@ int orc_sgs(int32_t n, const int64_t* rowptr, const int32_t* col, const double* 
     A.col.assign(col, col + rowptr[n]);
     A.val.assign(val, val + rowptr[n]);
     orc::Cheb c;
-    c.setup_sgs(&A, b, omega, steps, seed);
+    if (dd) c.setup_ddgs(&A, b, omega, steps, seed, sub);
+    else c.setup_sgs(&A, b, omega, steps, seed);
     c.half = half;
     c.apply(rhs, x, zero_guess != 0, zero_guess != 0);
     return 0;

@@ -191,21 +191,56 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         auto dead = std::make_shared<DBuf<int>>();
         const int ndead = tentative(nnode, L.bs[i], k, agg->p, na, L.B[i]->p, Pt, *Bc, *dead, s);
         DCsr AP;
+        // B (a field's matrix with b x b node blocks) times a matrix of b x k blocks
+        auto times_blocks = [&](const DCsr& Bm, const DBsr* Bb, const DCsr& X, DCsr& out) {
+          if (use_blocks(o, L.bs[i], L.bs[i], k)) {
+            DBsr Xb, Ob, Bo;
+            if (!Bb) {
+              csr_to_bsr(Bm, L.bs[i], L.bs[i], Bo, s);
+              Bb = &Bo;
+            }
+            csr_to_bsr(X, L.bs[i], k, Xb, s);
+            bspgemm(*Bb, Xb, Ob, s);
+            bsr_to_csr(Ob, out, s);
+          } else {
+            spgemm(Bm, X, out, s);
+          }
+        };
         if (use_blocks(o, L.bs[i], L.bs[i], k)) {
-          DBsr Ptb, APb;
           csr_to_bsr(Aii, L.bs[i], L.bs[i], LB.A[i], s);
           LB.hasA[i] = 1;
-          csr_to_bsr(Pt, L.bs[i], k, Ptb, s);
-          bspgemm(LB.A[i], Ptb, APb, s);
-          bsr_to_csr(APb, AP, s);
-        } else {
-          spgemm(Aii, Pt, AP, s);
         }
-        DBuf<double> srow(n);
-        const double omega = 4.0 / (3.0 * L.lambda[i]);
-        if (n > 0) hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, s, L.dinv[i]->p, -omega, srow.p, (int64_t)n);
-        smooth_prolongator(AP, srow.p, Pt, L.bs[i], k, agg->p, s);
-        *L.P[i] = std::move(AP);
+        times_blocks(Aii, LB.hasA[i] ? &LB.A[i] : nullptr, Pt, AP);
+        if (o.pg) {
+          // Petrov-Galerkin smoothed aggregation: P = P_tent - Q diag(om),
+          // Q = D^-1 A P_tent, column dampings minimising ||A P e_j||; the
+          // restriction is the same construction on A^T, transposed
+          const int nc = na * k;
+          auto pg_side = [&](const DCsr& M, const DBsr* Mb, const DCsr& MP, DCsr& out) {
+            DCsr Q, MQ;
+            csr_copy(MP, Q, s);
+            scale_rows(Q, L.dinv[i]->p, s);
+            times_blocks(M, Mb, Q, MQ);
+            DBuf<double> om(nc > 0 ? nc : 1);
+            pg_omega(MP, MQ, om.p, s);
+            pg_prolongator(Q, om.p, Pt, L.bs[i], k, agg->p, out, s);
+            NF_HIP(hipStreamSynchronize(s));
+          };
+          DCsr P, At, AtP, PR;
+          pg_side(Aii, LB.hasA[i] ? &LB.A[i] : nullptr, AP, P);
+          transpose(Aii, At, s);
+          times_blocks(At, nullptr, Pt, AtP);
+          pg_side(At, nullptr, AtP, PR);
+          *L.P[i] = std::move(P);
+          L.R[i] = std::make_unique<DCsr>();
+          transpose(PR, *L.R[i], s);
+        } else {
+          DBuf<double> srow(n);
+          const double omega = 4.0 / (3.0 * L.lambda[i]);
+          if (n > 0) hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, s, L.dinv[i]->p, -omega, srow.p, (int64_t)n);
+          smooth_prolongator(AP, srow.p, Pt, L.bs[i], k, agg->p, s);
+          *L.P[i] = std::move(AP);
+        }
         L.agg[i] = agg;
         C.bs[i] = k;
         C.B[i] = Bc;
@@ -213,6 +248,7 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
         C.ndead[i] = ndead;
         if (na * k > 0.83 * n) active[i] = 0;
       }
+      if (L.R[i]) continue;   // Petrov-Galerkin: R built above
       L.R[i] = std::make_unique<DCsr>();
       if (o.block_products && coarsened && L.bs[i] * C.bs[i] >= 2) {
         // R = P^T through the block form, which the Galerkin products reuse

@@ -20,6 +20,7 @@ struct Opts {
   int block_products = 1;
   int parallel_setup = 1;
   int max_rhs = NRMAX;
+  int pg = 0;   // Petrov-Galerkin transfers (per AMG node of the specification)
 };
 
 // N x N grid of device blocks over fields [0, N); a null block is zero.

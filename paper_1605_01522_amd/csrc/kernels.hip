@@ -433,7 +433,7 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
   }
   if (timed) {
     NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
-    g_prof.key.push_back(((G * 16) * 10 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
+    g_prof.key.push_back(((G * 16) * 100 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
     g_prof.bytes.push_back(spmv_bytes<T>(mode, A, a.nrhs));
     g_prof.count.push_back(1);
     ++g_prof.used;
@@ -1734,6 +1734,151 @@ template void sgs_color<double>(const DCsr&, int, const int*, const int*, int, c
 template void sgs_color<float>(const DCsr&, int, const int*, const int*, int, const float*, float, const float*, int64_t,
                                float*, int64_t, int, hipStream_t);
 
+// ==================================================================== DD(GS)
+// Domain-decomposition Gauss-Seidel: the nodes are split into subdomains
+// (the level's aggregates); one workgroup owns one subdomain and relaxes its
+// nodes colour by colour (a barrier between colours), each node as in the
+// multicolour kernels (its dofs together, from their old values).  A
+// coupling to a node of the same subdomain reads x (the workgroup's own,
+// newest values); a coupling to another subdomain reads xo, the values of
+// the sweep's start (NULL: zero), so workgroups never read what another one
+// writes.  dcol holds the columns encoded once at set-up: c >= 0 for a
+// column of the same subdomain, -1 - c for another subdomain's.
+template <int G, int NR, class T>
+__device__ __forceinline__ void row_dot_dd(int p0, int p1, const int* __restrict__ dcol, const T* __restrict__ val,
+                                           const T* __restrict__ x, int64_t ldx, const T* __restrict__ xo, int64_t ldxo,
+                                           int nrhs, T* s) {
+  constexpr int U = NR == 1 ? 8 : 4;
+  for (int p = p0; p < p1; p += U * G) {
+    T v[U];
+    int c[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = p + u * G;
+      ok[u] = q < p1;
+      v[u] = ok[u] ? val[q] : (T)0;
+      c[u] = ok[u] ? dcol[q] : 0;
+    }
+    T xv[U][NR];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        T t = (T)0;
+        if (ok[u] && k < nrhs) {
+          if (c[u] >= 0) t = x[k * ldx + c[u]];
+          else if (xo) t = xo[k * ldxo + (-1 - c[u])];
+        }
+        xv[u][k] = t;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (ok[u] && k < nrhs) s[k] += v[u] * xv[u][k];
+  }
+}
+
+template <int G, int B2, int NR, class T>
+__global__ __launch_bounds__(256) void k_dd_sweep(const int* __restrict__ nodes, const int* __restrict__ cptr,
+                                                  const int* __restrict__ off, int nc, int forward, int b,
+                                                  const int* __restrict__ dcol, const T* __restrict__ val,
+                                                  const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
+                                                  int64_t ldr, const T* __restrict__ xo, int64_t ldxo, T* __restrict__ x,
+                                                  int64_t ldx, int nrhs) {
+  constexpr int NG = G * B2, PER = 256 / NG;
+  const int grp = threadIdx.x / NG, sub = threadIdx.x % NG;
+  const int q = sub / G, lane = sub % G;
+  const int* so = off + (int64_t)blockIdx.x * (nc + 1);
+  for (int ci = 0; ci < nc; ++ci) {
+    const int c = forward ? ci : nc - 1 - ci;
+    const int t1 = so[c + 1];
+    for (int t = so[c] + grp; t < t1; t += PER) {
+      T acc[NR], rv[NR], xv[NR];
+      T w = 0;
+      int r = 0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xv[k] = 0;
+      if (q < b) {
+        const int* cp = cptr + (int64_t)t * (b + 1) + q;
+        const int p0 = cp[0], p1 = cp[1];
+        r = nodes[t] * b + q;
+        if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xv);
+        row_dot_dd<G, NR, T>(p0 + lane, p1, dcol, val, x, ldx, xo, ldxo, nrhs, acc);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
+      if (q < b && lane == 0) {
+        if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xv);
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          if (k < nrhs) x[k * ldx + r] = xv[k] + w * (rv[k] - acc[k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// dcol for the rows of every node: own-subdomain columns as they are, the
+// others as -1 - c
+__global__ void k_dd_encode(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                            const int* __restrict__ sub, int* __restrict__ dcol) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const int su = sub[r / b];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const int c = col[p];
+    dcol[p] = sub[c / b] == su ? c : -1 - c;
+  }
+}
+
+void dd_encode(const DCsr& A, int b, const int* sub, int* dcol, hipStream_t s) {
+  if (A.nr > 0) hipLaunchKernelGGL(k_dd_encode, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, sub, dcol);
+}
+
+template <int G, int B2, class T>
+static void dd_launch(int nsub, const int* nodes, const int* cptr, const int* off, int nc, bool forward, int b,
+                      const int* dcol, const T* val, const T* dinv, T omega, const T* rhs, int64_t ldr, const T* xo,
+                      int64_t ldxo, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_dd_sweep<G, B2, 1, T>), dim3(nsub), dim3(256), 0, s, nodes, cptr, off, nc, forward ? 1 : 0, b,
+                       dcol, val, dinv, omega, rhs, ldr, xo, ldxo, x, ldx, nrhs);
+  else
+    hipLaunchKernelGGL((k_dd_sweep<G, B2, NRMAX, T>), dim3(nsub), dim3(256), 0, s, nodes, cptr, off, nc, forward ? 1 : 0,
+                       b, dcol, val, dinv, omega, rhs, ldr, xo, ldxo, x, ldx, nrhs);
+}
+
+template <class T>
+void dd_sweep(const DCsr& A, int b, int nsub, const int* nodes, const int* cptr, const int* off_dev, int nc, bool forward,
+              const int* dcol, const T* dinv, T omega, const T* rhs, int64_t ldr, const T* xo, int64_t ldxo, T* x,
+              int64_t ldx, int nrhs, hipStream_t s) {
+  if (nsub <= 0 || nc <= 0) return;
+  NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "DD(GS): block size above 8");
+  NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
+  const T* val = csr_values<T>(A);
+  const int G = sgs_lanes(A, b);
+  const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+#define NF_DD(GG, BB)                                                                                          \
+  if (G == GG && B2 == BB)                                                                                     \
+    return dd_launch<GG, BB, T>(nsub, nodes, cptr, off_dev, nc, forward, b, dcol, val, dinv, omega, rhs, ldr, xo, \
+                                ldxo, x, ldx, nrhs, s);
+  NF_DD(2, 1) NF_DD(4, 1) NF_DD(8, 1) NF_DD(16, 1) NF_DD(32, 1) NF_DD(64, 1)
+  NF_DD(2, 2) NF_DD(4, 2) NF_DD(8, 2) NF_DD(16, 2) NF_DD(32, 2)
+  NF_DD(2, 4) NF_DD(4, 4) NF_DD(8, 4) NF_DD(16, 4)
+  NF_DD(2, 8) NF_DD(4, 8) NF_DD(8, 8)
+#undef NF_DD
+  throw NfError(NFIELD_EINVAL, "DD(GS): no kernel for this lane layout");
+}
+template void dd_sweep<double>(const DCsr&, int, int, const int*, const int*, const int*, int, bool, const int*,
+                               const double*, double, const double*, int64_t, const double*, int64_t, double*, int64_t,
+                               int, hipStream_t);
+template void dd_sweep<float>(const DCsr&, int, int, const int*, const int*, const int*, int, bool, const int*,
+                              const float*, float, const float*, int64_t, const float*, int64_t, float*, int64_t, int,
+                              hipStream_t);
+
 // ======================================================= tentative prolongator
 __global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {
   const int u = blockIdx.x * 256 + threadIdx.x;
@@ -1887,6 +2032,59 @@ void smooth_prolongator(DCsr& AP, const double* srow, const DCsr& Pt, int b, int
   if (AP.nr > 0)
     hipLaunchKernelGGL(k_smooth_P, dim3(cdiv(AP.nr, 256)), dim3(256), 0, s, AP.nr, AP.ptr.p, AP.col.p, AP.val.p, srow,
                        Pt.val.p, b, k, agg);
+}
+
+// Petrov-Galerkin dampings: om[j] = <AP e_j, AQ e_j> / ||AQ e_j||^2 (0 where
+// that is not positive or AQ e_j = 0), from the transposes (rows = columns
+// of P, entries in ascending row order): one thread per column, its sums in
+// ascending row order.
+__global__ void k_pg_omega(int nc, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+                           const int* __restrict__ qp, const int* __restrict__ qc, const double* __restrict__ qv,
+                           double* __restrict__ om) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nc) return;
+  int p = ap[j];
+  const int pe = ap[j + 1];
+  double num = 0.0, den = 0.0;
+  for (int q = qp[j]; q < qp[j + 1]; ++q) {
+    const int r = qc[q];
+    const double v = qv[q];
+    while (p < pe && ac[p] < r) ++p;
+    if (p < pe && ac[p] == r) num += av[p] * v;
+    den += v * v;
+  }
+  om[j] = (den > 0.0 && num > 0.0) ? num / den : 0.0;
+}
+void pg_omega(const DCsr& AP, const DCsr& AQ, double* om, hipStream_t s) {
+  DCsr APt, AQt;
+  transpose(AP, APt, s);
+  transpose(AQ, AQt, s);
+  if (AP.nc > 0)
+    hipLaunchKernelGGL(k_pg_omega, dim3(cdiv(AP.nc, 256)), dim3(256), 0, s, AP.nc, APt.ptr.p, APt.col.p, APt.val.p,
+                       AQt.ptr.p, AQt.col.p, AQt.val.p, om);
+  NF_HIP(hipStreamSynchronize(s));   // the transposes are freed on return
+}
+// P = P_tent - Q diag(om) on the pattern of Q (= that of A P_tent), written
+// into val; P_tent entries as in k_smooth_P
+__global__ void k_pg_P(int nr, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ qv,
+                       const double* __restrict__ om, const double* __restrict__ ptv, int b, int k,
+                       const int* __restrict__ agg, double* __restrict__ val) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nr) return;
+  const int a = agg[r / b];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const int c = col[p];
+    double v = -om[c] * qv[p];
+    if (c / k == a) v = ptv[(int64_t)r * k + (c - a * k)] + v;
+    val[p] = v;
+  }
+}
+void pg_prolongator(const DCsr& Q, const double* om, const DCsr& Pt, int b, int k, const int* agg, DCsr& P,
+                    hipStream_t s) {
+  csr_copy(Q, P, s);
+  if (Q.nr > 0)
+    hipLaunchKernelGGL(k_pg_P, dim3(cdiv(Q.nr, 256)), dim3(256), 0, s, Q.nr, Q.ptr.p, Q.col.p, Q.val.p, om, Pt.val.p, b,
+                       k, agg, P.val.p);
 }
 
 // ===================================================================== SpGEMM

@@ -149,6 +149,15 @@ template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t
 template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* cptr, const int* off_dev,
                                   const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs,
                                   int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
+// DD(GS) sweep: one workgroup per subdomain; nodes grouped by (subdomain,
+// colour), subdomain q's colour c owning nodes[off[q (nc+1) + c],
+// off[q (nc+1) + c + 1]) (off on the device); cptr from sgs_node_ptrs over
+// that list; dcol from dd_encode; xo: the sweep's start values of x (NULL:
+// zero)
+void dd_encode(const DCsr& A, int b, const int* sub, int* dcol, hipStream_t s);
+template <class T> void dd_sweep(const DCsr& A, int b, int nsub, const int* nodes, const int* cptr, const int* off_dev,
+                                 int nc, bool forward, const int* dcol, const T* dinv, T omega, const T* rhs, int64_t ldr,
+                                 const T* xo, int64_t ldxo, T* x, int64_t ldx, int nrhs, hipStream_t s);
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)
 void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,
@@ -168,6 +177,12 @@ int tentative(int nnode, int b, int k, const int* agg, int nagg, const double* B
 // smoothed prolongator in place on AP = A * P_tent: AP <- P_tent + s .* AP
 void smooth_prolongator(DCsr& AP, const double* srow, const DCsr& Pt, int b, int k, const int* agg, hipStream_t s);
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
+// Petrov-Galerkin smoothing of a tentative prolongator: om[j] (P.nc values)
+// = <AP e_j, AQ e_j> / ||AQ e_j||^2 clipped at 0; P = P_tent - Q diag(om)
+// on the pattern of Q = D^-1 A P_tent
+void pg_omega(const DCsr& AP, const DCsr& AQ, double* om, hipStream_t s);
+void pg_prolongator(const DCsr& Q, const double* om, const DCsr& Pt, int b, int k, const int* agg, DCsr& P,
+                    hipStream_t s);
 // node-blocked matrix: block pattern (pat.val: block indices for a converted
 // or transposed matrix, unused otherwise), br x bc values per
 // block (row-major, zero where nothing is stored) and a mask of the stored

@@ -260,7 +260,7 @@ struct SgsD : FieldSmootherD<T> {
     int launches = kind == SGS_SWEEP1 ? 1 : 0;
     if (kind != SGS_SWEEP1)
       for (int c = 0; c < nc; ++c) launches += off[c + 1] > off[c] ? 1 : 0;
-    prof_end(slot, s, ((lanes * 16 + b2) * 10 + mode) * 10 + (sizeof(T) == 4 ? 1 : 0),
+    prof_end(slot, s, ((lanes * 16 + b2) * 100 + mode) * 10 + (sizeof(T) == 4 ? 1 : 0),
              sweep_bytes + nrhs * sweep_bytes_x, launches);
   }
   // half: pre-smoothing sweeps forward only, post-smoothing backward only
@@ -272,6 +272,110 @@ struct SgsD : FieldSmootherD<T> {
     for (int st = 0; st < steps; ++st) {
       if (!half || pre) sweep(true, rhs, ldr, x, ldx, nrhs, s);
       if (!half || !pre) sweep(false, rhs, ldr, x, ldx, nrhs, s);
+    }
+  }
+};
+
+// DD(GS) with damping omega (the paper's domain-decomposition smoother,
+// Sec. 7): subdomains = the level's aggregates (given, or computed from the
+// node graph with the hierarchy's MIS-2 rule), one workgroup per subdomain
+// relaxing its nodes in colour order against the other subdomains' values
+// from the start of the sweep; forward then backward, or half sweeps.
+template <class T>
+struct DdgsD : FieldSmootherD<T> {
+  const DCsr* A = nullptr;
+  int b = 1, steps = 1, n = 0, nsub = 0, nc = 0, half = 0;
+  bool pre = true;
+  T omega = 1;
+  DBuf<T> dinv;
+  DBuf<int> nodes, cptr, off, dcol;
+  MBuf<T> xold;
+  double stat_bytes = 0.0, stat_bytes_x = 0.0;
+  void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s,
+             const DBuf<int>* gp, const DBuf<int>* ga, int nn_given, const DBuf<int>* agg_given, int h) {
+    A = A_;
+    b = b_;
+    n = A->nr;
+    omega = (T)om;
+    steps = st;
+    half = h;
+    dinv.alloc(n);
+    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(dinv.p, dinv64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
+    DBuf<int> gptr, gadj;
+    int nn = 0;
+    const int *gpp, *gap;
+    if (gp && ga) {
+      nn = nn_given;
+      gpp = gp->p;
+      gap = ga->p;
+    } else {
+      node_graph(*A, b, gptr, gadj, &nn, s);
+      gpp = gptr.p;
+      gap = gadj.p;
+    }
+    DBuf<int> color(nn > 0 ? nn : 1), subd;
+    nc = color_nodes(nn, gpp, gap, seed, color.p, s);
+    const int* sp;
+    if (agg_given) {
+      sp = agg_given->p;
+    } else {
+      subd.alloc(nn > 0 ? nn : 1);
+      mis2_aggregate(nn, gpp, gap, seed, subd.p, s);
+      sp = subd.p;
+    }
+    std::vector<int> hc(nn), hs(nn);
+    NF_HIP(hipMemcpyAsync(hc.data(), color.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    NF_HIP(hipMemcpyAsync(hs.data(), sp, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    nsub = 0;
+    for (int v : hs) nsub = std::max(nsub, v + 1);
+    // nodes ordered by (subdomain, colour, node); off[q (nc + 1) + c]
+    std::vector<int> cnt((size_t)nsub * nc + 1, 0);
+    for (int u = 0; u < nn; ++u) cnt[(size_t)hs[u] * nc + hc[u] + 1]++;
+    for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+    std::vector<int> list(nn > 0 ? nn : 1), cur(cnt.begin(), cnt.end() - 1);
+    for (int u = 0; u < nn; ++u) list[cur[(size_t)hs[u] * nc + hc[u]]++] = u;
+    std::vector<int> ho((size_t)nsub * (nc + 1));
+    for (int q = 0; q < nsub; ++q)
+      for (int c = 0; c <= nc; ++c) ho[(size_t)q * (nc + 1) + c] = cnt[(size_t)q * nc + c];
+    nodes.alloc(list.size());
+    off.alloc(ho.size() > 0 ? ho.size() : 1);
+    NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
+    NF_HIP(hipMemcpyAsync(off.p, ho.data(), sizeof(int) * ho.size(), hipMemcpyHostToDevice, s));
+    cptr.alloc((size_t)(nn > 0 ? nn : 1) * (b + 1));
+    sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
+    dcol.alloc(A->nnz > 0 ? A->nnz : 1);
+    dd_encode(*A, b, sp, dcol.p, s);
+    xold.alloc(n);
+    NF_HIP(hipStreamSynchronize(s));   // the host lists are freed on return
+    const double sz = sizeof(T);
+    stat_bytes = (double)A->nnz * (sz + 4) + 4.0 * (b + 2) * nn + sz * n + 4.0 * ho.size();
+    stat_bytes_x = 4.0 * sz * n;
+  }
+  void sweep(bool forward, bool from_zero, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
+    if (!from_zero) copym<T>(x, ldx, xold.p(), xold.ld, n, nrhs, s);
+    bytes_count(stat_bytes + nrhs * stat_bytes_x);
+    const int slot = prof_begin(s);
+    dd_sweep<T>(*A, b, nsub, nodes.p, cptr.p, off.p, nc, forward, dcol.p, dinv.p, omega, rhs, ldr,
+                from_zero ? nullptr : xold.p(), xold.ld, x, ldx, nrhs, s);
+    const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+    prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 100 + 10) * 10 + (sizeof(T) == 4 ? 1 : 0),
+             stat_bytes + nrhs * stat_bytes_x, 1);
+  }
+  void set_phase(bool p) override { pre = p; }
+  void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
+    if (zero_guess) fillm<T>(x, ldx, (T)0, n, nrhs, s);
+    bool zero = zero_guess;
+    for (int st = 0; st < steps; ++st) {
+      if (!half || pre) {
+        sweep(true, zero, rhs, ldr, x, ldx, nrhs, s);
+        zero = false;
+      }
+      if (!half || !pre) {
+        sweep(false, zero, rhs, ldr, x, ldx, nrhs, s);
+        zero = false;
+      }
     }
   }
 };
@@ -309,7 +413,7 @@ struct DenseSgsD : FieldSmootherD<T> {
       bytes_count(bytes);
       const int slot = prof_begin(s);
       dense_sweep_apply<T>(X.p, n, x, ldx, rhs, ldr, y.p(), y.ld, nrhs, with_x, s);
-      prof_end(slot, s, ((64 * 16 + b2) * 10 + 9) * 10 + (sizeof(T) == 4 ? 1 : 0), bytes);
+      prof_end(slot, s, ((64 * 16 + b2) * 100 + 9) * 10 + (sizeof(T) == 4 ? 1 : 0), bytes);
       copym<T>(y.p(), y.ld, x, ldx, n, nrhs, s);
     }
   }
@@ -462,6 +566,17 @@ struct AmgSolverD : Solver<T> {
   }
 };
 
+// A single-level smoother used as a block solve (the DD(GS) block solver of
+// the paper's single-level comparison BGS(DD(GS)), Sec. 7): its sweeps from
+// a zero guess, forward then backward.
+template <class T>
+struct SmootherSolverD : Solver<T> {
+  std::unique_ptr<FieldSmootherD<T>> sm;
+  void apply(const T* r, int64_t ldr, T* z, int64_t ldz, int nrhs, hipStream_t s) override {
+    sm->apply(r, ldr, z, ldz, nrhs, true, s);
+  }
+};
+
 template <class T>
 struct LuSolverD : Solver<T> {
   DBuf<double> inv;
@@ -557,7 +672,7 @@ struct SimpleSolverD : Solver<T> {
 // ================================================================== spec
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -593,8 +708,8 @@ static Spec parse_spec(const std::string& str) {
           sp.degree = atoi(v.c_str());
           NF_CHECK(sp.degree >= 1, NFIELD_EINVAL, "spec: degree must be >= 1");
         } else if (k == "smoother") {
-          sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : -9;
-          NF_CHECK(sp.smoother >= 0, NFIELD_EINVAL, "spec: smoother must be cheb or sgs");
+          sp.smoother = v == "cheb" ? 0 : v == "sgs" ? 1 : v == "ddgs" ? 2 : -9;
+          NF_CHECK(sp.smoother >= 0, NFIELD_EINVAL, "spec: smoother must be cheb, sgs or ddgs");
         } else if (k == "omega") {
           sp.omega = atof(v.c_str());
           NF_CHECK(sp.omega > 0.0 && sp.omega < 2.0, NFIELD_EINVAL, "spec: omega must be in (0, 2)");
@@ -604,6 +719,9 @@ static Spec parse_spec(const std::string& str) {
         } else if (k == "half") {
           sp.half = atoi(v.c_str());
           NF_CHECK(sp.half == 0 || sp.half == 1, NFIELD_EINVAL, "spec: half must be 0 or 1");
+        } else if (k == "pg") {
+          sp.pg = atoi(v.c_str());
+          NF_CHECK(sp.pg == 0 || sp.pg == 1, NFIELD_EINVAL, "spec: pg must be 0 or 1");
         } else {
           throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
         }
@@ -637,6 +755,7 @@ static Spec parse_spec(const std::string& str) {
 static void check_spec(const Spec& sp) {
   const size_t k = sp.kids.size();
   if (sp.name == "LU") NF_CHECK(k == 0, NFIELD_EINVAL, "spec: LU takes no argument");
+  else if (sp.name == "DDGS") NF_CHECK(k == 0, NFIELD_EINVAL, "spec: DDGS takes no argument");
   else if (sp.name == "AMG") {
     NF_CHECK(k <= 1, NFIELD_EINVAL, "spec: AMG takes at most one level smoother");
     if (k == 1) {
@@ -884,7 +1003,8 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
                                             const Spec* smoother, const Spec& amg, hipStream_t s) {
   Opts lo = C.o;   // smoother polynomial degree of this hierarchy
   if (amg.degree > 0) lo.cheb_degree = amg.degree;
-  const bool sgs = amg.smoother == 1;
+  const bool sgs = amg.smoother == 1 || amg.smoother == 2;
+  const bool dd = amg.smoother == 2;
   const double omega = amg.omega > 0.0 ? amg.omega : 1.0;
   const int steps = amg.steps > 0 ? amg.steps : 1;
   BlockMat sub = A.sub(f0, f1);
@@ -894,13 +1014,15 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
   for (int i = 0; i < sub.N; ++i)
     NF_CHECK(sub.at(i, i) != nullptr || (simple && i == sub.N - 1), NFIELD_ESINGULAR, "AMG: zero diagonal block");
   auto H = std::make_unique<Hierarchy>();
+  Opts ho = C.o;   // this hierarchy's transfers
+  ho.pg = amg.pg;
   // the finest level's Gauss-Seidel needs only A_ii: set up beside the
   // hierarchy (its own D^-1 and node graph, the same values as the
   // hierarchy's), unless the level smoother is SIMPLE
   std::vector<std::unique_ptr<FieldSmootherD<T>>> sgs0(sub.N);
-  if (sgs && !simple && C.o.parallel_setup) {
+  if (sgs && !dd && !simple && C.o.parallel_setup) {
     std::vector<std::function<void(hipStream_t)>> tasks;
-    tasks.push_back([&](hipStream_t st) { build_hierarchy(*H, sub, Fs, C.o, st); });
+    tasks.push_back([&](hipStream_t st) { build_hierarchy(*H, sub, Fs, ho, st); });
     tasks.push_back([&](hipStream_t st) {
       for (int i = 0; i < sub.N; ++i) {
         const DCsr* Aii = sub.at(i, i);
@@ -920,7 +1042,7 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     });
     run_concurrently(C, tasks, s);
   } else {
-    build_hierarchy(*H, sub, Fs, C.o, s);
+    build_hierarchy(*H, sub, Fs, ho, s);
   }
   auto S = std::make_unique<AmgSolverD<T>>();
   S->H = H.get();
@@ -952,7 +1074,15 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     const int nsm = simple ? sub.N - 1 : sub.N;   // fields with their own smoother
     for (int i = 0; i < nsm; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
-      if (sgs) {
+      if (dd) {
+        const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
+        const bool hagg = i < (int)L.agg.size() && L.agg[i];
+        auto d = std::make_unique<DdgsD<T>>();
+        d->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s, have ? L.gptr[i].get() : nullptr,
+                 have ? L.gadj[i].get() : nullptr, have ? L.nnode[i] : 0, hagg && have ? L.agg[i].get() : nullptr,
+                 amg.half);
+        M.cheb.push_back(std::move(d));
+      } else if (sgs) {
         if (l == 0 && sgs0[i]) {
           M.cheb.push_back(std::move(sgs0[i]));
         } else {
@@ -1033,6 +1163,27 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     BlockMat sub = A.sub(f0, f1);
     dense_block_inverse(sub, S->inv, &S->nn, s);
     S->n = n;
+    return S;
+  }
+  if (sp.name == "DDGS") {
+    NF_CHECK(nf_ == 1, NFIELD_EINVAL, "spec: DDGS needs a single field");
+    const DCsr* Aii = A.at(f0, f0);
+    NF_CHECK(Aii != nullptr, NFIELD_ESINGULAR, "DDGS: zero diagonal block");
+    DBuf<double> d(Aii->nr), dinv(Aii->nr);
+    DBuf<int> zf(1);
+    fill<int>(zf.p, 0, 1, s);
+    csr_diag(*Aii, d.p, zf.p, s);
+    invert(d.p, dinv.p, Aii->nr, s);
+    int z = 0;
+    NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    NF_CHECK(z == 0, NFIELD_ESINGULAR, "DDGS: zero diagonal entry");
+    auto sm = std::make_unique<DdgsD<T>>();
+    sm->setup(Aii, F[f0].bs, dinv.p, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed, s,
+              nullptr, nullptr, 0, nullptr, 0);
+    auto S = std::make_unique<SmootherSolverD<T>>();
+    S->sm = std::move(sm);
+    S->n = Aii->nr;
     return S;
   }
   if (sp.name == "AMG") {

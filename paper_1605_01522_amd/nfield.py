@@ -274,13 +274,14 @@ def nfield_prof_enable(on):
 
 
 SPMV_MODES = {0: "store", 1: "resid", 2: "add", 3: "sub", 4: "cheb", 5: "dscale", 6: "sgs",
-              7: "sgs_sweep1", 8: "sgs_node", 9: "sgs_dense"}
+              7: "sgs_sweep1", 8: "sgs_node", 9: "sgs_dense", 10: "ddgs"}
 # kernel names as the profiler prints them (single right-hand side)
 KERNEL_NAMES = {m: f"k_spmv<{{lanes}}, {m}, {{t}}>" for m in range(6)}
 KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[7] = "k_sgs_sweep1<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[8] = "k_sgs_node<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[9] = "k_dense_sweep_apply<1, {t}>"
+KERNEL_NAMES[10] = "k_dd_sweep<{lanes}, {rows}, 1, {t}>"
 
 
 def kernel_name(p):
@@ -299,8 +300,8 @@ def nfield_prof_read(max_keys=64):
     out = []
     for k in range(min(n, max_keys)):
         kk = int(key[k])
-        lanes, rows = (kk // 100) // 16, (kk // 100) % 16
-        out.append(dict(lanes=lanes, rows=rows, mode=SPMV_MODES[(kk // 10) % 10],
+        lanes, rows = (kk // 1000) // 16, (kk // 1000) % 16
+        out.append(dict(lanes=lanes, rows=rows, mode=SPMV_MODES[(kk // 10) % 100],
                         fp32=bool(kk % 10), launches=int(cnt[k]), ms=float(ms[k]),
                         bytes=float(by[k])))
     return out

@@ -109,7 +109,10 @@ SPECS = ["BGS(AMG)", "BGS[order=fwd](AMG)", "BGS[sweeps=3,order=sym](AMG)", "BGS
          "BGS(AMG[smoother=sgs,omega=0.8])", "BGS(AMG[smoother=sgs,omega=1.1,steps=2])",
          "AMG[smoother=sgs,omega=0.9](BGS)", "BGS(AMG[degree=3])",
          "BGS(AMG[smoother=sgs,omega=0.9,half=1])", "AMG[smoother=sgs,omega=0.9,half=1](BGS)",
-         "BGS(AMG[smoother=sgs,omega=0.8,half=1,steps=2])"]
+         "BGS(AMG[smoother=sgs,omega=0.8,half=1,steps=2])",
+         "BGS(AMG[smoother=ddgs,omega=0.79])", "BGS(AMG[smoother=ddgs,omega=0.9,half=1])",
+         "AMG[smoother=ddgs,omega=0.8](BGS)", "BGS(AMG[smoother=ddgs,omega=1.1,half=1,steps=2])",
+         "BGS(DDGS[omega=0.79])", "BGS[sweeps=1](DDGS[omega=0.69,steps=2])"]
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -222,10 +225,16 @@ FSI_SPEC_FULL = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])"
 FSI_SPEC_D2 = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 FSI_OPTS = dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)
 FSI_OPTS_ABS = dict(split=[0, 0, 1])
+# the paper's own smoother on the fluid (DD(GS), subdomains = aggregates)
+FSI_SPEC_DD = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1])"
+# Petrov-Galerkin transfers on the fluid (Sec. 7: PG-AMG for the fluid)
+FSI_SPEC_PG = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1,pg=1])"
 
 
 @pytest.mark.parametrize("n,layers,spec,opts", [(6, 2, FSI_SPEC, FSI_OPTS), (6, 2, FSI_SPEC_FULL, FSI_OPTS),
-                                                (6, 2, FSI_SPEC_D2, FSI_OPTS_ABS), (12, 3, FSI_SPEC, FSI_OPTS)])
+                                                (6, 2, FSI_SPEC_D2, FSI_OPTS_ABS), (12, 3, FSI_SPEC, FSI_OPTS),
+                                                (12, 3, FSI_SPEC_DD, FSI_OPTS), (16, 4, FSI_SPEC_DD, FSI_OPTS),
+                                                (12, 3, FSI_SPEC_PG, FSI_OPTS), (16, 4, FSI_SPEC_PG, FSI_OPTS)])
 def test_fsi_hierarchy_precond_and_solution_parity(dev, n, layers, spec, opts):
     _say(f"case fsi3d n={n} layers={layers} {spec} {opts}")
     s = nfgen.fsi3d(n=n, layers=layers, seed=n)
@@ -294,6 +303,31 @@ def test_fsi_full_size_sampled_parity(dev, fsi_full):
     assert so["status"] == 0
     assert err <= 1e-6
     assert abs(st[0]["iters"] - so["iters"]) <= 2, (st[0]["iters"], so["iters"])
+
+
+# ------------------------------------------ Petrov-Galerkin transfers
+@pytest.mark.parametrize("n,spec", [(10, "AMG[smoother=sgs,omega=0.85,half=1,pg=1]"), (14, "AMG[smoother=sgs,omega=0.85,half=1,pg=1]")])
+def test_pg_hierarchy_parity(dev, n, spec):
+    """Petrov-Galerkin hierarchy of the nonsymmetric fluid block: P, R (from
+    A^T) and R A P against the oracle's, preconditioner and solution."""
+    _say(f"case Petrov-Galerkin {spec} n={n}")
+    s = nfgen.fsi3d(n=n, layers=2, seed=3)
+    sub = nfgen.BlockSystem([s.fields[2]], [[s.blocks[2][2]]], s.rhs[:, s.offsets()[2]:])
+    o = oracle.Oracle(sub.fields, sub.blocks, spec, coarse_max=100)
+    g = _gpu(sub, spec, coarse_max=100)
+    _compare_hierarchies(g, o)
+    r = np.random.default_rng(14).standard_normal(sub.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    A = sub.assembled()
+    x, st = g.gmres_solve(torch.tensor(sub.rhs[0], device=dev), rtol=1e-8, maxit=500)
+    xo, so = o.gmres(sub.rhs[0], rtol=1e-8, maxit=500)
+    x = x.cpu().numpy()
+    assert st[0]["status"] == 0 and so["status"] == 0
+    assert np.linalg.norm(sub.rhs[0] - A @ x) < 1e-8 * np.linalg.norm(sub.rhs[0])
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert abs(st[0]["iters"] - so["iters"]) <= 2
 
 
 # --------------------------------------- SIMPLEC literal diagonal |sum_j a_ij|

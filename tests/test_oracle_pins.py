@@ -329,7 +329,8 @@ def test_chebyshev_closed_form(degree, ratio, boost):
 
 # ---------------------------------------------------------------- V-cycle
 @pytest.mark.parametrize("spec", ["AMG", "AMG[smoother=sgs,omega=0.9]", "AMG[smoother=sgs,omega=0.9,half=1]",
-                                  "AMG[smoother=sgs,omega=1.1,half=1,steps=2]"])
+                                  "AMG[smoother=sgs,omega=1.1,half=1,steps=2]", "AMG[smoother=ddgs,omega=0.9]",
+                                  "AMG[smoother=ddgs,omega=0.8,half=1]"])
 def test_vcycle_symmetric_contraction(spec):
     """With R = P^T, an exact coarse solve and a post-smoother that is the
     adjoint of the pre-smoother (the same Chebyshev polynomial, or the
@@ -667,3 +668,132 @@ def test_gmres_breakdown_statuses():
     x, st = o.gmres(b)
     assert st["status"] == 0 and st["iters"] == 1
     assert np.abs(sp.bmat([[I, I], [I, I]]) @ x - b).max() < 1e-14
+
+
+# -------------------------------------------------------------------- DD(GS)
+def _dd_splittings(A, b, col, sub):
+    """D, and the lower / upper parts of the DD(GS) splitting: entry (r, p) of
+    a node u coupled to node v of the same subdomain with an earlier (later)
+    colour."""
+    Ad = A.toarray()
+    cr, sr = np.repeat(col, b), np.repeat(sub, b)
+    same = sr[None, :] == sr[:, None]
+    Lf = np.where(same & (cr[None, :] < cr[:, None]), Ad, 0.0)
+    Lb = np.where(same & (cr[None, :] > cr[:, None]), Ad, 0.0)
+    return Ad, np.diag(np.diag(Ad)), Lf, Lb
+
+
+@pytest.mark.parametrize("field,b,omega", [(0, 2, 0.79), (1, 1, 0.69), (0, 2, 1.2)])
+def test_ddgs_equals_subdomain_splitting(field, b, omega):
+    """One DD(GS) sweep: (D/omega + L_s)(x1 - x0) = rhs - A x0, where L_s keeps
+    the couplings to nodes of the same subdomain (the level's MIS-2
+    aggregates) with an earlier colour; the backward sweep uses the later
+    colours; half sweeps take one of the two."""
+    s = nfgen.tsi2d(nel=9, seed=2)
+    A = s.blocks[field][field]
+    gp, ga = oracle.node_graph(A, b)
+    col, nc = oracle.color_nodes(gp, ga, 0)
+    _, agg, na = oracle.mis2_aggregate(gp, ga, 0)
+    assert 1 < na < len(agg)
+    Ad, D, Lf, Lb = _dd_splittings(A, b, col, agg)
+    rng = np.random.default_rng(4)
+    n = Ad.shape[0]
+    rhs, x0 = rng.standard_normal(n), rng.standard_normal(n)
+    x1 = x0 + np.linalg.solve(D / omega + Lf, rhs - Ad @ x0)
+    x2 = x1 + np.linalg.solve(D / omega + Lb, rhs - Ad @ x1)
+    got = oracle.sgs(A, b, rhs, omega=omega, x0=x0, dd=True)
+    assert np.abs(got - x2).max() < 1e-11 * np.abs(x2).max()
+    y1 = np.linalg.solve(D / omega + Lf, rhs)
+    assert np.abs(oracle.sgs(A, b, rhs, omega=omega, half=1, dd=True) - y1).max() < 1e-11 * np.abs(y1).max()
+    z1 = x0 + np.linalg.solve(D / omega + Lb, rhs - Ad @ x0)
+    assert np.abs(oracle.sgs(A, b, rhs, omega=omega, x0=x0, half=1, dd=True) - z1).max() < 1e-11 * np.abs(z1).max()
+    # the subdomain coupling is real here: it differs from the global colour sweep
+    glob = oracle.sgs(A, b, rhs, omega=omega, x0=x0)
+    assert np.abs(glob - got).max() > 1e-6 * np.abs(got).max()
+
+
+def test_ddgs_limits_sgs_and_jacobi():
+    """One subdomain: DD(GS) is the multicolour SGS.  One node per subdomain:
+    every sweep is damped Jacobi, x1 = x0 + omega D^-1 (rhs - A x0)."""
+    s = nfgen.tsi2d(nel=7, seed=5)
+    A = s.blocks[0][0]
+    nn = A.shape[0] // 2
+    rng = np.random.default_rng(6)
+    rhs, x0 = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    one = oracle.sgs(A, 2, rhs, omega=0.8, x0=x0, dd=True, sub=np.zeros(nn, np.int32))
+    assert np.array_equal(one, oracle.sgs(A, 2, rhs, omega=0.8, x0=x0))
+    dinv = 1.0 / A.diagonal()
+    x1 = x0 + 0.8 * dinv * (rhs - A @ x0)
+    x2 = x1 + 0.8 * dinv * (rhs - A @ x1)
+    got = oracle.sgs(A, 2, rhs, omega=0.8, x0=x0, dd=True, sub=np.arange(nn, dtype=np.int32))
+    assert np.abs(got - x2).max() < 1e-12 * np.abs(x2).max()
+
+
+# ------------------------------------------------ Petrov-Galerkin transfers
+def _fluid_only(n=8, seed=3):
+    s = nfgen.fsi3d(n=n, layers=2, seed=seed)
+    return [s.fields[2]], [[s.blocks[2][2]]]
+
+
+def test_pg_dampings_minimise_column_residuals():
+    """Petrov-Galerkin prolongator on the nonsymmetric fluid block:
+    P - P_tent = -Q diag(omega) with Q = D^-1 A P_tent, and each column's
+    damping minimises ||A P e_j||_2 over omega_j >= 0, i.e. A P e_j is
+    orthogonal to A Q e_j where omega_j > 0 and the derivative at 0 is
+    non-negative where omega_j = 0."""
+    f, b = _fluid_only()
+    A = b[0][0]
+    o = Oracle(f, b, "AMG[pg=1]", coarse_max=100)
+    assert o.nlevels(0) >= 2
+    P = o.matrix(0, 0, "P").toarray()
+    agg = o.aggregates(0, 0)
+    na = agg.max() + 1
+    Pt, _, _ = oracle.tentative(agg, na, f[0].block_size, f[0].nullspace)
+    Pt = Pt.toarray()
+    Ad = A.toarray()
+    Q = (Ad / np.diag(Ad)[:, None]) @ Pt
+    Dlt = Pt - P
+    nq = np.linalg.norm(Q, axis=0)
+    om = np.array([Dlt[:, j] @ Q[:, j] / nq[j] ** 2 if nq[j] > 0 else 0.0 for j in range(P.shape[1])])
+    assert np.abs(Dlt - Q * om[None, :]).max() < 1e-13 * np.abs(P).max()
+    assert om.min() >= 0.0 and (om > 0).sum() > P.shape[1] // 2
+    AP, AQ = Ad @ P, Ad @ Q
+    for j in range(P.shape[1]):
+        g = AP[:, j] @ AQ[:, j]
+        scale = np.linalg.norm(AP[:, j]) * np.linalg.norm(AQ[:, j]) + 1e-300
+        if om[j] > 0:
+            assert abs(g) < 1e-10 * scale, j
+        else:
+            assert g >= -1e-10 * scale, j
+
+
+def test_pg_restriction_and_galerkin():
+    """R comes from the same construction on A^T (so R != P^T on the fluid),
+    A_c = R A P; on a symmetric block the Petrov-Galerkin restriction is P^T
+    and the hierarchy that of the same dampings on both sides."""
+    f, b = _fluid_only()
+    A = b[0][0].toarray()
+    o = Oracle(f, b, "AMG[pg=1]", coarse_max=100)
+    P, R = o.matrix(0, 0, "P").toarray(), o.matrix(0, 0, "R").toarray()
+    assert np.abs(R - P.T).max() > 1e-6 * np.abs(P).max()
+    Ac = o.matrix(0, 1, "A").toarray()
+    assert np.abs(Ac - R @ A @ P).max() < 1e-13 * np.abs(Ac).max()
+    # the restriction is the transposed prolongator of A^T
+    ot = Oracle(f, [[b[0][0].T.tocsr()]], "AMG[pg=1]", coarse_max=100)
+    if np.array_equal(ot.aggregates(0, 0), o.aggregates(0, 0)):
+        assert np.abs(ot.matrix(0, 0, "P").toarray() - R.T).max() < 1e-12 * np.abs(R).max()
+    s = nfgen.tsi2d(nel=10)
+    fs, bs = [s.fields[1]], [[s.blocks[1][1]]]
+    osym = Oracle(fs, bs, "AMG[pg=1]", coarse_max=30)
+    Ps, Rs = osym.matrix(0, 0, "P").toarray(), osym.matrix(0, 0, "R").toarray()
+    assert np.abs(Rs - Ps.T).max() < 1e-13 * np.abs(Ps).max()
+
+
+def test_pg_amg_gmres_reaches_dense_solution():
+    f, b = _fluid_only(n=8, seed=5)
+    A = b[0][0]
+    rhs = np.random.default_rng(3).standard_normal(A.shape[0])
+    o = Oracle(f, b, "AMG[smoother=sgs,omega=0.85,half=1,pg=1]", coarse_max=100)
+    x, st = o.gmres(rhs, rtol=1e-10, maxit=300)
+    xd = np.linalg.solve(A.toarray(), rhs)
+    assert st["status"] == 0 and np.linalg.norm(x - xd) < 1e-7 * np.linalg.norm(xd)
