@@ -196,6 +196,25 @@ nfield_status nfield_gmres_solve(nfield_ctx *ctx, const double *b_dev, double *x
                                  int32_t nrhs, const nfield_solve_opts *sopts,
                                  nfield_stats *stats, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as nfield_gmres_solve (same kernels in the same order, so the same
+ * results bit for bit), with its Krylov workspace (basis V, flexible basis
+ * Z, Hessenberg and rotation arrays, reduction partials, the FP32 staging of
+ * the precision form) in a static device array of 256 MiB per device
+ * instead of buffers of the context, and its host staging in the call's own
+ * pageable arrays.  It calls no hipMalloc / hipFree / hipHostMalloc and no
+ * allocating routine; the preconditioner is launched directly (no graph
+ * replay).  The workspace takes about 8 n ((m + 1) + m (flexible) + 4)
+ * min(nrhs, 8) bytes (+ 4 n min(nrhs, 8) with hier_fp32); a call whose
+ * workspace exceeds 256 MiB returns NFIELD_ENOMEM before any device work.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (from several threads
+ * or streams) race and must be serialised by the caller. */
+nfield_status nfield_gmres_solve_noalloc(nfield_ctx *ctx, const double *b_dev, double *x_dev,
+                                         int32_t nrhs, const nfield_solve_opts *sopts,
+                                         nfield_stats *stats, void *hip_stream);
+
 /* Replace the values of the nonzero block (i, j), keeping its pattern (the
  * next Newton step of the paper's monolithic scheme, Sec. 2).  val holds the
  * block's nnz values in its CSR order, in device memory (on_device = 1,

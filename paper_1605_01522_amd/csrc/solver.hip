@@ -1269,8 +1269,9 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
 }
 
 // ================================================================= GMRES
-// Device and host buffers of one GMRES call (the context's own, grown on
-// demand).
+// Device and host buffers of one GMRES call: the context's own (grown on
+// demand) or carved from the static scratch of the allocation-free entry
+// point.
 struct KrylovWs {
   double *V = nullptr, *Z = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *u = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h1 = nullptr, *h2 = nullptr;
@@ -1716,6 +1717,82 @@ __global__ void k_scatter_vals(const double* v, const int* pos, int64_t n, doubl
   if (i < n) out[pos[i]] = v[i];
 }
 
+// ------------------------------------------------ allocation-free workspace
+// The Krylov workspace of nfield_gmres_solve_noalloc lives in this static
+// device array (256 MiB on every device the library runs on, held until the
+// process ends).  Host code never passes the array's name to a kernel or a
+// copy: the address of each device's copy comes from hipGetSymbolAddress,
+// taken once per device (with that device current) and kept here.
+constexpr size_t SCRATCH_DOUBLES = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+static double* scratch_on_current_device() {
+  int dev = 0;
+  NF_HIP(hipGetDevice(&dev));
+  NF_CHECK(dev >= 0 && dev < SCRATCH_MAX_DEVICES, NFIELD_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    NF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    NF_CHECK(p != nullptr, NFIELD_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+    g_scratch_dev[dev] = (double*)p;
+  }
+  return g_scratch_dev[dev];
+}
+
+// Krylov workspace of nrhs columns carved from the scratch array, every
+// region on a 256-byte boundary; host staging in the caller's arrays.
+// size_only: check that the workspace fits (ENOMEM if not) and return.
+static KrylovWs scratch_workspace(nfield_ctx& C, int m, int flexible, int nrhs, double* host_d, int* host_i,
+                                  bool size_only) {
+  const size_t n = (size_t)C.Aglob.nr, nr = (size_t)nrhs, mm = (size_t)m;
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t o = off;
+    off += (doubles + 31) & ~(size_t)31;
+    return o;
+  };
+  const size_t oV = take(n * (mm + 1) * nr), oZ = flexible ? take(n * mm * nr) : 0;
+  const size_t ow = take(n * nr), oz = take(n * nr), orr = take(n * nr), ou = take(n * nr);
+  const size_t oH = take((mm + 1) * mm * nr), ocs = take(mm * nr), osn = take(mm * nr), og = take((mm + 1) * nr);
+  const size_t oy = take(mm * nr), oh1 = take((mm + 1) * nr), oh2 = take((mm + 1) * nr);
+  const size_t op = take((size_t)RED_BLOCKS * (mm + 1) * nr), os = take(4 * NRMAX);
+  const size_t oi = take((3 * NRMAX + 1) / 2);
+  const bool f32 = C.root32 != nullptr;
+  const size_t or32 = f32 ? take((n * nr + 1) / 2) : 0, oz32 = f32 ? take((n * nr + 1) / 2) : 0;
+  NF_CHECK(off <= SCRATCH_DOUBLES, NFIELD_ENOMEM,
+           "nfield_gmres_solve_noalloc: the Krylov workspace (" + std::to_string(off * 8) +
+               " bytes) exceeds the static scratch of " + std::to_string(SCRATCH_DOUBLES * 8) + " bytes");
+  KrylovWs W;
+  if (size_only) return W;
+  double* base = scratch_on_current_device();
+  W.V = base + oV;
+  W.Z = flexible ? base + oZ : nullptr;
+  W.w = base + ow;
+  W.z = base + oz;
+  W.r = base + orr;
+  W.u = base + ou;
+  W.H = base + oH;
+  W.cs = base + ocs;
+  W.sn = base + osn;
+  W.g = base + og;
+  W.y = base + oy;
+  W.h1 = base + oh1;
+  W.h2 = base + oh2;
+  W.partial = base + op;
+  W.scal = base + os;
+  W.imask = (int*)(base + oi);
+  W.r32 = f32 ? (float*)(base + or32) : nullptr;
+  W.z32 = f32 ? (float*)(base + oz32) : nullptr;
+  W.pinned = host_d;
+  W.pinned_i = host_i;
+  W.direct = true;
+  return W;
+}
+
 }  // namespace nf
 
 // ================================================================ C ABI
@@ -1927,8 +2004,8 @@ nfield_status nfield_matvec(nfield_ctx* ctx, const double* x, double* y, int32_t
 }
 
 static nfield_status gmres_entry(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
-                                 nfield_stats* stats, void* hip_stream) {
-  const char* who = "nfield_gmres_solve";
+                                 nfield_stats* stats, void* hip_stream, bool noalloc) {
+  const char* who = noalloc ? "nfield_gmres_solve_noalloc" : "nfield_gmres_solve";
   if (!ctx || !b || !x || nrhs < 0) { g_err = std::string(who) + ": bad argument"; return NFIELD_EINVAL; }
   nfield_solve_opts so;
   nfield_default_solve_opts(&so);
@@ -1945,13 +2022,18 @@ static nfield_status gmres_entry(nfield_ctx* ctx, const double* b, double* x, in
     const int64_t n = ctx->Aglob.nr;
     int worst = NFIELD_OK;
     std::vector<nfield_stats> st(NRMAX);
+    double host_d[64];   // staging of the allocation-free path (pageable)
+    int host_i[64];
     const int cols = ctx->o.max_rhs;   // columns per batch: what the preconditioner's temporaries hold
+    if (noalloc && nrhs > 0) (void)scratch_workspace(*ctx, so.restart, so.flexible, std::min(cols, nrhs), nullptr,
+                                                     nullptr, true);   // size check first
     for (int k = 0; k < nrhs; k += cols) {
       const int nb = std::min(cols, nrhs - k);
       const auto t0 = std::chrono::steady_clock::now();
       const double b0 = bytes_counted();
       if (k == 0) ctx->hist.assign(nrhs, {});
-      const KrylovWs W = ctx_workspace(*ctx, so.restart, so.flexible, nb);
+      const KrylovWs W = noalloc ? scratch_workspace(*ctx, so.restart, so.flexible, nb, host_d, host_i, false)
+                                 : ctx_workspace(*ctx, so.restart, so.flexible, nb);
       gmres(*ctx, W, b + k * n, n, x + k * n, n, nb, so, st.data(), s, ctx->hist.data() + k);
       NF_HIP(hipStreamSynchronize(s));
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1981,7 +2063,12 @@ static nfield_status gmres_entry(nfield_ctx* ctx, const double* b, double* x, in
 
 nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs, const nfield_solve_opts* sopts,
                                  nfield_stats* stats, void* hip_stream) {
-  return gmres_entry(ctx, b, x, nrhs, sopts, stats, hip_stream);
+  return gmres_entry(ctx, b, x, nrhs, sopts, stats, hip_stream, false);
+}
+
+nfield_status nfield_gmres_solve_noalloc(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs,
+                                         const nfield_solve_opts* sopts, nfield_stats* stats, void* hip_stream) {
+  return gmres_entry(ctx, b, x, nrhs, sopts, stats, hip_stream, true);
 }
 
 nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const double* val, int32_t on_device,

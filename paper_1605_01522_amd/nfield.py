@@ -51,7 +51,7 @@ class nfield_stats(C.Structure):
 
 # every symbol include/nfield.h declares
 EXPORTS = ["nfield_default_opts", "nfield_default_solve_opts", "nfield_setup",
-           "nfield_precond_apply", "nfield_matvec", "nfield_gmres_solve",
+           "nfield_precond_apply", "nfield_matvec", "nfield_gmres_solve", "nfield_gmres_solve_noalloc",
            "nfield_update_values", "nfield_rebuild", "nfield_prof_enable", "nfield_prof_read",
            "nfield_footprint_bytes", "nfield_precond_bytes", "nfield_size", "nfield_destroy", "nfield_strerror",
            "nfield_last_error", "nfield_hier_count", "nfield_hier_nlevels", "nfield_hier_nfields",
@@ -82,6 +82,8 @@ def lib():
     L.nfield_matvec.restype = C.c_int
     L.nfield_gmres_solve.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.nfield_gmres_solve.restype = C.c_int
+    L.nfield_gmres_solve_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.nfield_gmres_solve_noalloc.restype = C.c_int
     L.nfield_update_values.argtypes = [vp, i32, i32, vp, i32, vp]
     L.nfield_update_values.restype = C.c_int
     L.nfield_rebuild.argtypes = [vp, vp]
@@ -229,8 +231,10 @@ def nfield_matvec(ctx, x, y, stream=None):
         raise NFieldError(rc, "nfield_matvec")
 
 
-def nfield_gmres_solve(ctx, b, x, restart=50, maxit=1000, flexible=0, rtol=1e-8, stream=None):
-    """Solves in place into x; returns (status, list of per-column stats dicts)."""
+def nfield_gmres_solve(ctx, b, x, restart=50, maxit=1000, flexible=0, rtol=1e-8, stream=None, noalloc=False):
+    """Solves in place into x; returns (status, list of per-column stats dicts).
+    noalloc: call nfield_gmres_solve_noalloc (workspace in the library's
+    static scratch array, no device allocation)."""
     n = lib().nfield_size(ctx)
     bp, k = _dev(b, n, "b")
     xp, k2 = _dev(x, n, "x")
@@ -238,10 +242,10 @@ def nfield_gmres_solve(ctx, b, x, restart=50, maxit=1000, flexible=0, rtol=1e-8,
         raise ValueError("b and x differ in shape")
     so = nfield_solve_opts(restart, maxit, flexible, rtol)
     st = (nfield_stats * max(k, 1))()
-    rc = lib().nfield_gmres_solve(ctx, bp, xp, k, C.byref(so), C.cast(st, C.c_void_p),
-                                  _stream(stream))
+    fn = lib().nfield_gmres_solve_noalloc if noalloc else lib().nfield_gmres_solve
+    rc = fn(ctx, bp, xp, k, C.byref(so), C.cast(st, C.c_void_p), _stream(stream))
     if rc < 0:
-        raise NFieldError(rc, "nfield_gmres_solve")
+        raise NFieldError(rc, "nfield_gmres_solve_noalloc" if noalloc else "nfield_gmres_solve")
     stats = [dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres,
                   setup_s=s.setup_s, solve_s=s.solve_s, bytes=s.bytes, gbps=s.gbps)
              for s in st[:k]]
