@@ -42,9 +42,15 @@ WORKLOADS = {
                   spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])",
                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # the same system with the paper's own fluid smoother, DD(GS) (one
-    # workgroup per aggregate, Gauss-Seidel inside in colour order)
+    # workgroup per aggregate, Gauss-Seidel inside in colour order; levels
+    # with fewer than 256 aggregates are one subdomain)
     "fsi3d_dd": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
                      spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1])",
+                     opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
+    # the same system with Petrov-Galerkin transfers on the fluid (the
+    # paper's fluid AMG, after Sala and Tuminaro)
+    "fsi3d_pg": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
+                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1,pg=1])",
                      opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
@@ -442,6 +448,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
     ap.add_argument("--no-tsi", action="store_true", help="skip the TSI-like system's own timing")
     ap.add_argument("--no-alpha-sweep", action="store_true", help="skip the coupling-strength sweep")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FSI-like variants (DD(GS) fluid smoother, Petrov-Galerkin fluid AMG)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this solver is built and "
@@ -492,6 +500,10 @@ def main():
     if not args.no_lung and args.workload != "lung3d":
         out["lung"] = summary("lung3d", run_workload("lung3d", 5, 1, args.seed, not args.no_precision_form),
                               5, args.seed)
+    if not args.no_variants and args.workload == "fsi3d":
+        # the paper's own fluid components on the same system, 5 steps each
+        out["variants"] = {v: summary(v, run_workload(v, 5, 1, args.seed, False), 5, args.seed)
+                           for v in ("fsi3d_dd", "fsi3d_pg")}
     if not args.no_tsi:
         out["tsi2d"] = tsi_config0(seed=args.seed)
     if not args.no_alpha_sweep:

@@ -557,7 +557,9 @@ struct BlockMat {
 //    aggregates); in a sweep every subdomain relaxes its nodes in the colour
 //    order of the multicolour SGS, using the newest values of its own nodes
 //    and the values the other subdomains' nodes held when the sweep began.
-//    Forward then backward, or half sweeps as above.
+//    Forward then backward, or half sweeps as above.  A level with fewer
+//    aggregates than the ddmin parameter (default 256: the workgroups a GPU
+//    runs side by side) is one subdomain: the multicolour SGS.
 struct Cheb {
   const Csr* A = nullptr;
   std::vector<double> dinv;
@@ -586,8 +588,10 @@ struct Cheb {
     color_nodes.assign(nc, {});
     for (int u = 0; u < G.n; ++u) color_nodes[col[u]].push_back(u);
   }
-  // DD(GS): the SGS set-up plus the subdomains (given, or the aggregates)
-  void setup_ddgs(const Csr* A_, int b, double om, int st, uint64_t seed, const int* given_sub = nullptr) {
+  // DD(GS): the SGS set-up plus the subdomains (given, or the aggregates;
+  // a level with fewer than ddmin aggregates is one subdomain)
+  void setup_ddgs(const Csr* A_, int b, double om, int st, uint64_t seed, const int* given_sub = nullptr,
+                  int ddmin = 1) {
     setup_sgs(A_, b, om, st, seed);
     kind = 2;
     Graph G = node_graph(*A, b);
@@ -596,6 +600,7 @@ struct Cheb {
     } else {
       int ns = 0;
       sub = dd_subdomains(G, seed, &ns);
+      if (ns < ddmin) sub.assign(G.n, 0);
     }
   }
   // relax the nodes of colour c; with DD(GS) (xold non-null) a coupling to a
@@ -1081,7 +1086,7 @@ struct SimpleSolver : Solver {
 // in brackets: "BGS[sweeps=2,order=bwd](AMG)".
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0, ddmin = 256;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -1121,6 +1126,10 @@ struct Parser {
         else if (k == "pg") {
           sp.pg = atoi(v.c_str());
           if (sp.pg != 0 && sp.pg != 1) throw Error(EINVAL_, "spec: bad value " + v);
+        }
+        else if (k == "ddmin") {
+          sp.ddmin = atoi(v.c_str());
+          if (sp.ddmin < 1) throw Error(EINVAL_, "spec: bad value " + v);
         }
         else throw Error(EINVAL_, "spec: unknown parameter " + k);
         if (sp.smoother == -9 || (k == "omega" && !(sp.omega > 0.0 && sp.omega < 2.0)) ||
@@ -1201,7 +1210,7 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
     const int nchb = M.kind == 1 ? sub.N - 1 : sub.N;
     for (int i = 0; i < nchb; ++i) {
       if (sgs) {
-        if (amg.smoother == 2) M.cheb[i].setup_ddgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
+        if (amg.smoother == 2) M.cheb[i].setup_ddgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed, nullptr, amg.ddmin);
         else M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
         M.cheb[i].half = amg.half;
       } else {
@@ -1243,7 +1252,8 @@ static std::unique_ptr<Solver> build(Ctx& C, const Spec& sp, const BlockMat& A, 
     const Csr* Aii = A.at(f0, f0);
     if (!Aii) throw Error(ESINGULAR, "DDGS: zero diagonal block");
     auto S = std::make_unique<SmootherSolver>();
-    S->sm.setup_ddgs(Aii, F[f0].bs, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed);
+    S->sm.setup_ddgs(Aii, F[f0].bs, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed, nullptr,
+                     sp.ddmin);
     S->n = Aii->nr;
     return S;
   }

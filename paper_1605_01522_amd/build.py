@@ -41,7 +41,8 @@ def build_library(verbose=False):
             if err.strip():
                 print(err, file=sys.stderr)
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [o for o, _ in results]
+    # -z defs: a symbol that no object defines fails the link, not the load
+    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", "-o", tmp] + [o for o, _ in results]
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
     return OUT

@@ -1736,148 +1736,264 @@ template void sgs_color<float>(const DCsr&, int, const int*, const int*, int, co
 
 // ==================================================================== DD(GS)
 // Domain-decomposition Gauss-Seidel: the nodes are split into subdomains
-// (the level's aggregates); one workgroup owns one subdomain and relaxes its
-// nodes colour by colour (a barrier between colours), each node as in the
-// multicolour kernels (its dofs together, from their old values).  A
-// coupling to a node of the same subdomain reads x (the workgroup's own,
-// newest values); a coupling to another subdomain reads xo, the values of
-// the sweep's start (NULL: zero), so workgroups never read what another one
-// writes.  dcol holds the columns encoded once at set-up: c >= 0 for a
-// column of the same subdomain, -1 - c for another subdomain's.
-template <int G, int NR, class T>
-__device__ __forceinline__ void row_dot_dd(int p0, int p1, const int* __restrict__ dcol, const T* __restrict__ val,
-                                           const T* __restrict__ x, int64_t ldx, const T* __restrict__ xo, int64_t ldxo,
-                                           int nrhs, T* s) {
-  constexpr int U = NR == 1 ? 8 : 4;
+// (the level's aggregates); one workgroup owns one subdomain, whose nodes are
+// listed by (subdomain, colour, node).  At set-up every row of the list is
+// split into its own part (couplings to nodes of the same subdomain, columns
+// as local dof indices: position in the subdomain's list times b plus the
+// component) and its other part (couplings to other subdomains, global
+// columns), both stored in list order.  A sweep:
+//  1. stage the subdomain's x in LDS and ext = rhs - (other part) xo, where
+//     xo holds every node's value at the sweep's start (NULL: zero) -- fully
+//     parallel over the subdomain's rows, the only gather of the sweep;
+//  2. colour by colour (a barrier between colours, colours without nodes in
+//     the subdomain skipped): each node's dofs together from their old
+//     values, x_r += omega dinv_r (ext_r - (own part) x), own values in LDS;
+//  3. write the subdomain's x back.
+// Workgroups never read what another one writes.
+template <int G, int U, int NR, class T>
+__device__ __forceinline__ void dd_row_sum(int p0, int p1, const int* __restrict__ col, const T* __restrict__ val,
+                                           const T* src, int64_t lds, int nrhs, T* s) {
   for (int p = p0; p < p1; p += U * G) {
     T v[U];
     int c[U];
-    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = p + u * G;
-      ok[u] = q < p1;
-      v[u] = ok[u] ? val[q] : (T)0;
-      c[u] = ok[u] ? dcol[q] : 0;
+      v[u] = q < p1 ? val[q] : (T)0;
+      c[u] = q < p1 ? col[q] : -1;
     }
     T xv[U][NR];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        T t = (T)0;
-        if (ok[u] && k < nrhs) {
-          if (c[u] >= 0) t = x[k * ldx + c[u]];
-          else if (xo) t = xo[k * ldxo + (-1 - c[u])];
-        }
-        xv[u][k] = t;
-      }
+      for (int k = 0; k < NR; ++k) xv[u][k] = (c[u] >= 0 && k < nrhs) ? src[k * lds + c[u]] : (T)0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < NR; ++k)
-        if (ok[u] && k < nrhs) s[k] += v[u] * xv[u][k];
+        if (c[u] >= 0 && k < nrhs) s[k] += v[u] * xv[u][k];
   }
 }
 
-template <int G, int B2, int NR, class T>
-__global__ __launch_bounds__(256) void k_dd_sweep(const int* __restrict__ nodes, const int* __restrict__ cptr,
-                                                  const int* __restrict__ off, int nc, int forward, int b,
-                                                  const int* __restrict__ dcol, const T* __restrict__ val,
-                                                  const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
-                                                  int64_t ldr, const T* __restrict__ xo, int64_t ldxo, T* __restrict__ x,
-                                                  int64_t ldx, int nrhs) {
-  constexpr int NG = G * B2, PER = 256 / NG;
-  const int grp = threadIdx.x / NG, sub = threadIdx.x % NG;
-  const int q = sub / G, lane = sub % G;
+// LDS of one workgroup (md = max_nodes * b dofs): xs and ext (NR columns of
+// md values each), the node ids, and the own and other row bounds of the
+// subdomain's rows (md + 1 each, relative to its first entry).
+template <int G1, int U1, int G2, int B2, int NR, class T>
+__global__ __launch_bounds__(256) void k_dd_sweep(const int* __restrict__ nodes, const int* __restrict__ off, int nc,
+                                                  int forward, int b, const int* __restrict__ optr,
+                                                  const int* __restrict__ ocol, const T* __restrict__ oval,
+                                                  const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                  const T* __restrict__ xval, const T* __restrict__ dinv, T omega,
+                                                  const T* __restrict__ rhs, int64_t ldr, const T* __restrict__ xo,
+                                                  int64_t ldxo, T* __restrict__ x, int64_t ldx, int nrhs, int max_nodes) {
+  extern __shared__ __align__(16) unsigned char dd_lds[];
   const int* so = off + (int64_t)blockIdx.x * (nc + 1);
-  for (int ci = 0; ci < nc; ++ci) {
-    const int c = forward ? ci : nc - 1 - ci;
-    const int t1 = so[c + 1];
-    for (int t = so[c] + grp; t < t1; t += PER) {
-      T acc[NR], rv[NR], xv[NR];
-      T w = 0;
-      int r = 0;
+  const int base = so[0], nn = so[nc] - base, nd = nn * b;
+  const int md = max_nodes * b;
+  T* xs = (T*)dd_lds;
+  T* ext = xs + (size_t)NR * md;
+  int* nid = (int*)(ext + (size_t)NR * md);
+  int* ob = nid + max_nodes;
+  int* xb = ob + md + 1;
+  const int rb = base * b;
+  // node ids and row bounds of the subdomain: one round trip
+  for (int e = threadIdx.x; e < nn; e += 256) nid[e] = nodes[base + e];
+  for (int e = threadIdx.x; e <= nd; e += 256) {
+    ob[e] = optr[rb + e];
+    xb[e] = xptr[rb + e];
+  }
+  __syncthreads();
+  // 1. own values, and ext = rhs - (other part) xo with G1 lanes per row,
+  // U1 entries per lane in flight
+  for (int e = threadIdx.x; e < nd * NR; e += 256) {
+    const int k = e / nd, d = e % nd;
+    const int64_t r = (int64_t)nid[d / b] * b + d % b;
+    xs[k * md + d] = k < nrhs ? x[k * ldx + r] : (T)0;
+  }
+  {
+    const int lane = threadIdx.x % G1;
+    for (int d0 = 0; d0 < nd; d0 += 256 / G1) {
+      const int d = d0 + threadIdx.x / G1;
+      T acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xv[k] = 0;
-      if (q < b) {
-        const int* cp = cptr + (int64_t)t * (b + 1) + q;
-        const int p0 = cp[0], p1 = cp[1];
-        r = nodes[t] * b + q;
-        if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xv);
-        row_dot_dd<G, NR, T>(p0 + lane, p1, dcol, val, x, ldx, xo, ldxo, nrhs, acc);
-      }
+      for (int k = 0; k < NR; ++k) acc[k] = 0;
+      if (d < nd && xo) dd_row_sum<G1, U1, NR, T>(xb[d] + lane, xb[d + 1], xcol, xval, xo, ldxo, nrhs, acc);
 #pragma unroll
       for (int k = 0; k < NR; ++k)
 #pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
-      if (q < b && lane == 0) {
-        if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xv);
+        for (int o = G1 / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G1);
+      if (d < nd && lane == 0) {
+        const int64_t r = (int64_t)nid[d / b] * b + d % b;
 #pragma unroll
         for (int k = 0; k < NR; ++k)
-          if (k < nrhs) x[k * ldx + r] = xv[k] + w * (rv[k] - acc[k]);
+          if (k < nrhs) ext[k * md + d] = rhs[k * ldr + r] - acc[k];
+      }
+    }
+  }
+  __syncthreads();
+  // 2. the colours
+  constexpr int NG = G2 * B2, PER = 256 / NG;
+  const int grp = threadIdx.x / NG, sub = threadIdx.x % NG;
+  const int q = sub / G2, lane = sub % G2;
+  for (int ci = 0; ci < nc; ++ci) {
+    const int c = forward ? ci : nc - 1 - ci;
+    const int t0 = so[c] - base, t1 = so[c + 1] - base;
+    if (t0 == t1) continue;   // no node of this colour here (uniform over the workgroup)
+    for (int t = t0 + grp; t < t1; t += PER) {
+      T acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = 0;
+      const int d = t * b + q;
+      if (q < b) dd_row_sum<G2, NR == 1 ? 8 : 4, NR, T>(ob[d] + lane, ob[d + 1], ocol, oval, xs, md, nrhs, acc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int o = G2 / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G2);
+      if (q < b && lane == 0) {
+        const T w = omega * dinv[(int64_t)nid[t] * b + q];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          if (k < nrhs) xs[k * md + d] = xs[k * md + d] + w * (ext[k * md + d] - acc[k]);
       }
     }
     __syncthreads();
   }
-}
-
-// dcol for the rows of every node: own-subdomain columns as they are, the
-// others as -1 - c
-__global__ void k_dd_encode(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
-                            const int* __restrict__ sub, int* __restrict__ dcol) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= nr) return;
-  const int su = sub[r / b];
-  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
-    const int c = col[p];
-    dcol[p] = sub[c / b] == su ? c : -1 - c;
+  // 3. write back
+  for (int e = threadIdx.x; e < nd * NR; e += 256) {
+    const int k = e / nd, d = e % nd;
+    if (k < nrhs) x[k * ldx + (int64_t)nid[d / b] * b + d % b] = xs[k * md + d];
   }
 }
 
-void dd_encode(const DCsr& A, int b, const int* sub, int* dcol, hipStream_t s) {
-  if (A.nr > 0) hipLaunchKernelGGL(k_dd_encode, dim3(cdiv(A.nr, 256)), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, sub, dcol);
+// own / other entry counts of every listed row (list order: row lr = t b + q)
+__global__ void k_dd_split_count(int nlist, int b, const int* __restrict__ nodes, const int* __restrict__ ptr,
+                                 const int* __restrict__ col, const int* __restrict__ sub, int* __restrict__ nown,
+                                 int* __restrict__ noth) {
+  const int lr = blockIdx.x * 256 + threadIdx.x;
+  if (lr >= nlist * b) return;
+  const int u = nodes[lr / b], r = u * b + lr % b, su = sub[u];
+  int o = 0, x = 0;
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    if (sub[col[p] / b] == su) ++o;
+    else ++x;
+  }
+  nown[lr] = o;
+  noth[lr] = x;
 }
-
-template <int G, int B2, class T>
-static void dd_launch(int nsub, const int* nodes, const int* cptr, const int* off, int nc, bool forward, int b,
-                      const int* dcol, const T* val, const T* dinv, T omega, const T* rhs, int64_t ldr, const T* xo,
-                      int64_t ldxo, T* x, int64_t ldx, int nrhs, hipStream_t s) {
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_dd_sweep<G, B2, 1, T>), dim3(nsub), dim3(256), 0, s, nodes, cptr, off, nc, forward ? 1 : 0, b,
-                       dcol, val, dinv, omega, rhs, ldr, xo, ldxo, x, ldx, nrhs);
-  else
-    hipLaunchKernelGGL((k_dd_sweep<G, B2, NRMAX, T>), dim3(nsub), dim3(256), 0, s, nodes, cptr, off, nc, forward ? 1 : 0,
-                       b, dcol, val, dinv, omega, rhs, ldr, xo, ldxo, x, ldx, nrhs);
+template <class T>
+__global__ void k_dd_split_fill(int nlist, int b, const int* __restrict__ nodes, const int* __restrict__ ptr,
+                                const int* __restrict__ col, const double* __restrict__ val, const int* __restrict__ sub,
+                                const int* __restrict__ pos, const int* __restrict__ optr, int* __restrict__ ocol,
+                                T* __restrict__ oval, const int* __restrict__ xptr, int* __restrict__ xcol,
+                                T* __restrict__ xval) {
+  const int lr = blockIdx.x * 256 + threadIdx.x;
+  if (lr >= nlist * b) return;
+  const int u = nodes[lr / b], r = u * b + lr % b, su = sub[u];
+  int o = optr[lr], x = xptr[lr];
+  for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const int c = col[p];
+    if (sub[c / b] == su) {
+      ocol[o] = pos[c / b] * b + c % b;
+      oval[o++] = (T)val[p];
+    } else {
+      xcol[x] = c;
+      xval[x++] = (T)val[p];
+    }
+  }
 }
 
 template <class T>
-void dd_sweep(const DCsr& A, int b, int nsub, const int* nodes, const int* cptr, const int* off_dev, int nc, bool forward,
-              const int* dcol, const T* dinv, T omega, const T* rhs, int64_t ldr, const T* xo, int64_t ldxo, T* x,
-              int64_t ldx, int nrhs, hipStream_t s) {
+void dd_split(const DCsr& A, int b, int nlist, const int* nodes, const int* sub, const int* pos, DBuf<int>& optr,
+              DBuf<int>& ocol, DBuf<T>& oval, DBuf<int>& xptr, DBuf<int>& xcol, DBuf<T>& xval, hipStream_t s) {
+  const int nr = nlist * b;
+  DBuf<int> no(nr + 1), nx(nr + 1);
+  optr.alloc(nr + 1);
+  xptr.alloc(nr + 1);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_dd_split_count, dim3(cdiv(nr, 256)), dim3(256), 0, s, nlist, b, nodes, A.ptr.p, A.col.p, sub,
+                       no.p, nx.p);
+  const int64_t to = exclusive_scan(no.p, optr.p, nr, s), tx = exclusive_scan(nx.p, xptr.p, nr, s);
+  ocol.alloc(to > 0 ? to : 1);
+  oval.alloc(to > 0 ? to : 1);
+  xcol.alloc(tx > 0 ? tx : 1);
+  xval.alloc(tx > 0 ? tx : 1);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_dd_split_fill<T>, dim3(cdiv(nr, 256)), dim3(256), 0, s, nlist, b, nodes, A.ptr.p, A.col.p,
+                       A.val.p, sub, pos, optr.p, ocol.p, oval.p, xptr.p, xcol.p, xval.p);
+}
+template void dd_split<double>(const DCsr&, int, int, const int*, const int*, const int*, DBuf<int>&, DBuf<int>&,
+                               DBuf<double>&, DBuf<int>&, DBuf<int>&, DBuf<double>&, hipStream_t);
+template void dd_split<float>(const DCsr&, int, int, const int*, const int*, const int*, DBuf<int>&, DBuf<int>&,
+                              DBuf<float>&, DBuf<int>&, DBuf<int>&, DBuf<float>&, hipStream_t);
+
+size_t dd_lds_bytes(int b, int max_nodes, int nrhs, size_t val_bytes) {
+  const int NR = nrhs == 1 ? 1 : NRMAX;
+  const size_t md = (size_t)max_nodes * b;
+  return 2 * val_bytes * (size_t)NR * md + sizeof(int) * ((size_t)max_nodes + 2 * (md + 1));
+}
+
+// lanes per row of the own part: two to four entries per lane, at most
+// 64 / B2 (a node's rows in one wavefront)
+static int dd_lanes(double avg, int cap) {
+  int g = 1;
+  while (g * 4 <= avg && g < 64) g *= 2;
+  if (g < 2) g = 2;
+  while (g > cap) g >>= 1;
+  return g;
+}
+
+template <int G1, int U1, int G2, int B2, class T>
+static void dd_launch(int nsub, const int* nodes, const int* off, int nc, bool forward, int b, const int* optr,
+                      const int* ocol, const T* oval, const int* xptr, const int* xcol, const T* xval, const T* dinv,
+                      T omega, const T* rhs, int64_t ldr, const T* xo, int64_t ldxo, T* x, int64_t ldx, int nrhs,
+                      int max_nodes, hipStream_t s) {
+  const size_t lds = dd_lds_bytes(b, max_nodes, nrhs, sizeof(T));
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_dd_sweep<G1, U1, G2, B2, 1, T>), dim3(nsub), dim3(256), lds, s, nodes, off, nc,
+                       forward ? 1 : 0, b, optr, ocol, oval, xptr, xcol, xval, dinv, omega, rhs, ldr, xo, ldxo, x, ldx,
+                       nrhs, max_nodes);
+  else
+    hipLaunchKernelGGL((k_dd_sweep<G1, 4, G2, B2, NRMAX, T>), dim3(nsub), dim3(256), lds, s, nodes, off, nc,
+                       forward ? 1 : 0, b, optr, ocol, oval, xptr, xcol, xval, dinv, omega, rhs, ldr, xo, ldxo, x, ldx,
+                       nrhs, max_nodes);
+}
+
+// Lanes per row: G1 for the other part, G2 for the own part, each from the
+// part's mean row length (two to four entries per lane).
+template <class T>
+void dd_sweep(int b, int nsub, const int* nodes, const int* off_dev, int nc, bool forward, double avg_own,
+              double avg_other, const int* optr, const int* ocol, const T* oval, const int* xptr, const int* xcol,
+              const T* xval, const T* dinv, T omega, const T* rhs, int64_t ldr, const T* xo, int64_t ldxo, T* x,
+              int64_t ldx, int nrhs, int max_nodes, hipStream_t s) {
   if (nsub <= 0 || nc <= 0) return;
   NF_CHECK(b >= 1 && b <= MAXB, NFIELD_EINVAL, "DD(GS): block size above 8");
   NF_CHECK(nrhs >= 1 && nrhs <= NRMAX, NFIELD_EINVAL, "more than 8 right-hand sides in one call");
-  const T* val = csr_values<T>(A);
-  const int G = sgs_lanes(A, b);
+  NF_CHECK(dd_lds_bytes(b, max_nodes, nrhs, sizeof(T)) <= DD_LDS_MAX, NFIELD_EINVAL,
+           "DD(GS): a subdomain is too large for the workgroup's LDS");
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-#define NF_DD(GG, BB)                                                                                          \
-  if (G == GG && B2 == BB)                                                                                     \
-    return dd_launch<GG, BB, T>(nsub, nodes, cptr, off_dev, nc, forward, b, dcol, val, dinv, omega, rhs, ldr, xo, \
-                                ldxo, x, ldx, nrhs, s);
-  NF_DD(2, 1) NF_DD(4, 1) NF_DD(8, 1) NF_DD(16, 1) NF_DD(32, 1) NF_DD(64, 1)
-  NF_DD(2, 2) NF_DD(4, 2) NF_DD(8, 2) NF_DD(16, 2) NF_DD(32, 2)
-  NF_DD(2, 4) NF_DD(4, 4) NF_DD(8, 4) NF_DD(16, 4)
-  NF_DD(2, 8) NF_DD(4, 8) NF_DD(8, 8)
+  const int G2 = dd_lanes(avg_own, 64 / B2), G1 = dd_lanes(avg_other, 16);
+  const int U1 = 8;
+#define NF_DD(A1, V1, A2, BB)                                                                                        \
+  if (G1 == A1 && U1 == V1 && G2 == A2 && B2 == BB)                                                                  \
+    return dd_launch<A1, V1, A2, BB, T>(nsub, nodes, off_dev, nc, forward, b, optr, ocol, oval, xptr, xcol, xval, dinv, \
+                                        omega, rhs, ldr, xo, ldxo, x, ldx, nrhs, max_nodes, s);
+#define NF_DD_G2(A1, V1) \
+  NF_DD(A1, V1, 2, 1) NF_DD(A1, V1, 4, 1) NF_DD(A1, V1, 8, 1) NF_DD(A1, V1, 16, 1) NF_DD(A1, V1, 32, 1)  \
+  NF_DD(A1, V1, 64, 1) NF_DD(A1, V1, 2, 2) NF_DD(A1, V1, 4, 2) NF_DD(A1, V1, 8, 2) NF_DD(A1, V1, 16, 2) \
+  NF_DD(A1, V1, 32, 2) NF_DD(A1, V1, 2, 4) NF_DD(A1, V1, 4, 4) NF_DD(A1, V1, 8, 4) NF_DD(A1, V1, 16, 4) \
+  NF_DD(A1, V1, 2, 8) NF_DD(A1, V1, 4, 8) NF_DD(A1, V1, 8, 8)
+  NF_DD_G2(1, 8) NF_DD_G2(2, 8) NF_DD_G2(4, 8) NF_DD_G2(8, 8) NF_DD_G2(16, 8)
+  NF_DD_G2(1, 16) NF_DD_G2(2, 16) NF_DD_G2(4, 16) NF_DD_G2(8, 16) NF_DD_G2(16, 16)
+#undef NF_DD_G2
 #undef NF_DD
   throw NfError(NFIELD_EINVAL, "DD(GS): no kernel for this lane layout");
 }
-template void dd_sweep<double>(const DCsr&, int, int, const int*, const int*, const int*, int, bool, const int*,
-                               const double*, double, const double*, int64_t, const double*, int64_t, double*, int64_t,
-                               int, hipStream_t);
-template void dd_sweep<float>(const DCsr&, int, int, const int*, const int*, const int*, int, bool, const int*,
-                              const float*, float, const float*, int64_t, const float*, int64_t, float*, int64_t, int,
-                              hipStream_t);
+template void dd_sweep<double>(int, int, const int*, const int*, int, bool, double, double, const int*, const int*,
+                               const double*, const int*, const int*, const double*, const double*, double,
+                               const double*, int64_t, const double*, int64_t, double*, int64_t, int, int, hipStream_t);
+template void dd_sweep<float>(int, int, const int*, const int*, int, bool, double, double, const int*, const int*,
+                              const float*, const int*, const int*, const float*, const float*, float, const float*,
+                              int64_t, const float*, int64_t, float*, int64_t, int, int, hipStream_t);
 
 // ======================================================= tentative prolongator
 __global__ void k_count_by(int n, const int* __restrict__ key, int* cnt) {

@@ -149,15 +149,23 @@ template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t
 template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* cptr, const int* off_dev,
                                   const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs,
                                   int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);
-// DD(GS) sweep: one workgroup per subdomain; nodes grouped by (subdomain,
-// colour), subdomain q's colour c owning nodes[off[q (nc+1) + c],
-// off[q (nc+1) + c + 1]) (off on the device); cptr from sgs_node_ptrs over
-// that list; dcol from dd_encode; xo: the sweep's start values of x (NULL:
-// zero)
-void dd_encode(const DCsr& A, int b, const int* sub, int* dcol, hipStream_t s);
-template <class T> void dd_sweep(const DCsr& A, int b, int nsub, const int* nodes, const int* cptr, const int* off_dev,
-                                 int nc, bool forward, const int* dcol, const T* dinv, T omega, const T* rhs, int64_t ldr,
-                                 const T* xo, int64_t ldxo, T* x, int64_t ldx, int nrhs, hipStream_t s);
+// DD(GS) sweep: one workgroup per subdomain; nodes listed by (subdomain,
+// colour, node), subdomain q's colour c owning nodes[off[q (nc+1) + c],
+// off[q (nc+1) + c + 1]) (off on the device).  dd_split stores every listed
+// row's own part (couplings inside its subdomain, local dof columns; pos: a
+// node's position in its subdomain's list) and other part (global columns),
+// in list order; xo: the sweep's start values of x (NULL: zero); max_nodes:
+// the largest subdomain (its values live in LDS).
+constexpr size_t DD_LDS_MAX = 65536;
+size_t dd_lds_bytes(int b, int max_nodes, int nrhs, size_t val_bytes);
+template <class T> void dd_split(const DCsr& A, int b, int nlist, const int* nodes, const int* sub, const int* pos,
+                                 DBuf<int>& optr, DBuf<int>& ocol, DBuf<T>& oval, DBuf<int>& xptr, DBuf<int>& xcol,
+                                 DBuf<T>& xval, hipStream_t s);
+template <class T> void dd_sweep(int b, int nsub, const int* nodes, const int* off_dev, int nc, bool forward,
+                                 double avg_own, double avg_other, const int* optr, const int* ocol, const T* oval,
+                                 const int* xptr, const int* xcol, const T* xval, const T* dinv, T omega, const T* rhs,
+                                 int64_t ldr, const T* xo, int64_t ldxo, T* x, int64_t ldx, int nrhs, int max_nodes,
+                                 hipStream_t s);
 // per colour: stored entries of its rows and distinct columns they touch
 // (algorithmic bytes of one colour sweep)
 void color_traffic(const DCsr& A, int b, const int* nodes, const std::vector<int>& off, std::vector<int64_t>& nnz,

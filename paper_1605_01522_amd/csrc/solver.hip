@@ -282,26 +282,31 @@ struct SgsD : FieldSmootherD<T> {
 // relaxing its nodes in colour order against the other subdomains' values
 // from the start of the sweep; forward then backward, or half sweeps.
 template <class T>
+static std::unique_ptr<FieldSmootherD<T>> make_sgs(const DCsr* A, int b, const double* dinv64, double omega, int steps,
+                                                   uint64_t seed, hipStream_t s, const DBuf<int>* gp, const DBuf<int>* ga,
+                                                   int nn, int half);
+
+template <class T>
 struct DdgsD : FieldSmootherD<T> {
   const DCsr* A = nullptr;
-  int b = 1, steps = 1, n = 0, nsub = 0, nc = 0, half = 0;
+  int b = 1, steps = 1, n = 0, nsub = 0, nc = 0, half = 0, max_nodes = 0;
+  std::unique_ptr<FieldSmootherD<T>> whole;   // a level with few subdomains: one subdomain (multicolour SGS)
   bool pre = true;
   T omega = 1;
   DBuf<T> dinv;
-  DBuf<int> nodes, cptr, off, dcol;
+  DBuf<int> nodes, off, optr, ocol, xptr, xcol;
+  DBuf<T> oval, xval;
+  double avg_own = 0.0, avg_other = 0.0;
   MBuf<T> xold;
   double stat_bytes = 0.0, stat_bytes_x = 0.0;
   void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s,
-             const DBuf<int>* gp, const DBuf<int>* ga, int nn_given, const DBuf<int>* agg_given, int h) {
+             const DBuf<int>* gp, const DBuf<int>* ga, int nn_given, const DBuf<int>* agg_given, int h, int ddmin) {
     A = A_;
     b = b_;
     n = A->nr;
     omega = (T)om;
     steps = st;
     half = h;
-    dinv.alloc(n);
-    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(dinv.p, dinv64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
     DBuf<int> gptr, gadj;
     int nn = 0;
     const int *gpp, *gap;
@@ -314,8 +319,7 @@ struct DdgsD : FieldSmootherD<T> {
       gpp = gptr.p;
       gap = gadj.p;
     }
-    DBuf<int> color(nn > 0 ? nn : 1), subd;
-    nc = color_nodes(nn, gpp, gap, seed, color.p, s);
+    DBuf<int> subd;
     const int* sp;
     if (agg_given) {
       sp = agg_given->p;
@@ -324,47 +328,73 @@ struct DdgsD : FieldSmootherD<T> {
       mis2_aggregate(nn, gpp, gap, seed, subd.p, s);
       sp = subd.p;
     }
-    std::vector<int> hc(nn), hs(nn);
-    NF_HIP(hipMemcpyAsync(hc.data(), color.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    std::vector<int> hs(nn);
     NF_HIP(hipMemcpyAsync(hs.data(), sp, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
     nsub = 0;
     for (int v : hs) nsub = std::max(nsub, v + 1);
+    if (nsub < ddmin) {   // one subdomain: the multicolour SGS
+      whole = make_sgs<T>(A, b, dinv64, om, st, seed, s, gp && ga ? gp : nullptr, gp && ga ? ga : nullptr,
+                          gp && ga ? nn_given : 0, h);
+      return;
+    }
+    dinv.alloc(n);
+    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(dinv.p, dinv64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else cast_copy<double, float>(dinv64, (float*)dinv.p, n, s);
+    DBuf<int> color(nn > 0 ? nn : 1);
+    nc = color_nodes(nn, gpp, gap, seed, color.p, s);
+    std::vector<int> hc(nn);
+    NF_HIP(hipMemcpyAsync(hc.data(), color.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
     // nodes ordered by (subdomain, colour, node); off[q (nc + 1) + c]
     std::vector<int> cnt((size_t)nsub * nc + 1, 0);
     for (int u = 0; u < nn; ++u) cnt[(size_t)hs[u] * nc + hc[u] + 1]++;
     for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
     std::vector<int> list(nn > 0 ? nn : 1), cur(cnt.begin(), cnt.end() - 1);
     for (int u = 0; u < nn; ++u) list[cur[(size_t)hs[u] * nc + hc[u]]++] = u;
-    std::vector<int> ho((size_t)nsub * (nc + 1));
-    for (int q = 0; q < nsub; ++q)
+    std::vector<int> ho((size_t)nsub * (nc + 1)), pos(nn > 0 ? nn : 1);
+    max_nodes = 0;
+    for (int q = 0; q < nsub; ++q) {
       for (int c = 0; c <= nc; ++c) ho[(size_t)q * (nc + 1) + c] = cnt[(size_t)q * nc + c];
+      const int q0 = ho[(size_t)q * (nc + 1)], q1 = ho[(size_t)q * (nc + 1) + nc];
+      max_nodes = std::max(max_nodes, q1 - q0);
+      for (int t = q0; t < q1; ++t) pos[list[t]] = t - q0;
+    }
+    NF_CHECK(dd_lds_bytes(b, max_nodes, g_mbuf_cols, sizeof(T)) <= DD_LDS_MAX, NFIELD_EINVAL,
+             "DD(GS): a subdomain is too large for the workgroup's LDS");
     nodes.alloc(list.size());
     off.alloc(ho.size() > 0 ? ho.size() : 1);
+    DBuf<int> pos_dev(pos.size());
     NF_HIP(hipMemcpyAsync(nodes.p, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
     NF_HIP(hipMemcpyAsync(off.p, ho.data(), sizeof(int) * ho.size(), hipMemcpyHostToDevice, s));
-    cptr.alloc((size_t)(nn > 0 ? nn : 1) * (b + 1));
-    sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
-    dcol.alloc(A->nnz > 0 ? A->nnz : 1);
-    dd_encode(*A, b, sp, dcol.p, s);
+    NF_HIP(hipMemcpyAsync(pos_dev.p, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice, s));
+    dd_split<T>(*A, b, nn, nodes.p, sp, pos_dev.p, optr, ocol, oval, xptr, xcol, xval, s);
     xold.alloc(n);
     NF_HIP(hipStreamSynchronize(s));   // the host lists are freed on return
+    avg_own = n > 0 ? (double)oval.n / n : 0.0;
+    avg_other = n > 0 ? (double)xval.n / n : 0.0;
     const double sz = sizeof(T);
-    stat_bytes = (double)A->nnz * (sz + 4) + 4.0 * (b + 2) * nn + sz * n + 4.0 * ho.size();
+    // entries and row bounds of both parts, node ids, subdomain offsets,
+    // D^-1; per right-hand side rhs, x read and written, xo once
+    stat_bytes = (double)A->nnz * (sz + 4) + 8.0 * (n + 1) + 4.0 * nn + 4.0 * ho.size() + sz * n;
     stat_bytes_x = 4.0 * sz * n;
   }
   void sweep(bool forward, bool from_zero, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     if (!from_zero) copym<T>(x, ldx, xold.p(), xold.ld, n, nrhs, s);
     bytes_count(stat_bytes + nrhs * stat_bytes_x);
     const int slot = prof_begin(s);
-    dd_sweep<T>(*A, b, nsub, nodes.p, cptr.p, off.p, nc, forward, dcol.p, dinv.p, omega, rhs, ldr,
-                from_zero ? nullptr : xold.p(), xold.ld, x, ldx, nrhs, s);
+    dd_sweep<T>(b, nsub, nodes.p, off.p, nc, forward, avg_own, avg_other, optr.p, ocol.p, oval.p, xptr.p, xcol.p,
+                xval.p, dinv.p, omega, rhs, ldr, from_zero ? nullptr : xold.p(), xold.ld, x, ldx, nrhs, max_nodes, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
     prof_end(slot, s, ((sgs_lanes(*A, b) * 16 + b2) * 100 + 10) * 10 + (sizeof(T) == 4 ? 1 : 0),
              stat_bytes + nrhs * stat_bytes_x, 1);
   }
-  void set_phase(bool p) override { pre = p; }
+  void set_phase(bool p) override {
+    pre = p;
+    if (whole) whole->set_phase(p);
+  }
   void apply(const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, bool zero_guess, hipStream_t s) override {
+    if (whole) return whole->apply(rhs, ldr, x, ldx, nrhs, zero_guess, s);
     if (zero_guess) fillm<T>(x, ldx, (T)0, n, nrhs, s);
     bool zero = zero_guess;
     for (int st = 0; st < steps; ++st) {
@@ -672,7 +702,7 @@ struct SimpleSolverD : Solver<T> {
 // ================================================================== spec
 struct Spec {
   std::string name;
-  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0;
+  int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0, ddmin = 256;
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -722,6 +752,9 @@ static Spec parse_spec(const std::string& str) {
         } else if (k == "pg") {
           sp.pg = atoi(v.c_str());
           NF_CHECK(sp.pg == 0 || sp.pg == 1, NFIELD_EINVAL, "spec: pg must be 0 or 1");
+        } else if (k == "ddmin") {
+          sp.ddmin = atoi(v.c_str());
+          NF_CHECK(sp.ddmin >= 1, NFIELD_EINVAL, "spec: ddmin must be >= 1");
         } else {
           throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
         }
@@ -984,7 +1017,7 @@ struct ChebSolverD : Solver<T> {
 template <class T>
 static std::unique_ptr<FieldSmootherD<T>> make_sgs(const DCsr* A, int b, const double* dinv64, double omega, int steps,
                                                    uint64_t seed, hipStream_t s, const DBuf<int>* gp, const DBuf<int>* ga,
-                                                   int nn, int half = 0) {
+                                                   int nn, int half) {
   auto g = std::make_unique<SgsD<T>>();
   g->setup(A, b, dinv64, omega, steps, seed, s, gp, ga, nn);
   g->half = half;
@@ -1016,11 +1049,11 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
   auto H = std::make_unique<Hierarchy>();
   Opts ho = C.o;   // this hierarchy's transfers
   ho.pg = amg.pg;
-  // the finest level's Gauss-Seidel needs only A_ii: set up beside the
-  // hierarchy (its own D^-1 and node graph, the same values as the
-  // hierarchy's), unless the level smoother is SIMPLE
+  // the finest level's Gauss-Seidel or DD(GS) needs only A_ii: set up beside
+  // the hierarchy (its own D^-1, node graph and, for DD(GS), aggregates: the
+  // same values as the hierarchy's), unless the level smoother is SIMPLE
   std::vector<std::unique_ptr<FieldSmootherD<T>>> sgs0(sub.N);
-  if (sgs && !dd && !simple && C.o.parallel_setup) {
+  if (sgs && !simple && C.o.parallel_setup) {
     std::vector<std::function<void(hipStream_t)>> tasks;
     tasks.push_back([&](hipStream_t st) { build_hierarchy(*H, sub, Fs, ho, st); });
     tasks.push_back([&](hipStream_t st) {
@@ -1036,7 +1069,13 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
         NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, st));
         NF_HIP(hipStreamSynchronize(st));
         if (z) continue;   // a zero diagonal entry: the hierarchy's check reports it
-        sgs0[i] = make_sgs<T>(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0, amg.half);
+        if (dd) {   // its own node graph and aggregates (the same as the hierarchy's level 0)
+          auto d = std::make_unique<DdgsD<T>>();
+          d->setup(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0, nullptr, amg.half, amg.ddmin);
+          sgs0[i] = std::move(d);
+        } else {
+          sgs0[i] = make_sgs<T>(Aii, Fs[i].bs, dinv.p, omega, steps, C.o.seed, st, nullptr, nullptr, 0, amg.half);
+        }
         NF_HIP(hipStreamSynchronize(st));
       }
     });
@@ -1074,13 +1113,15 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     const int nsm = simple ? sub.N - 1 : sub.N;   // fields with their own smoother
     for (int i = 0; i < nsm; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
-      if (dd) {
+      if (dd && l == 0 && sgs0[i]) {
+        M.cheb.push_back(std::move(sgs0[i]));
+      } else if (dd) {
         const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
         const bool hagg = i < (int)L.agg.size() && L.agg[i];
         auto d = std::make_unique<DdgsD<T>>();
         d->setup(L.A.at(i, i), L.bs[i], L.dinv[i]->p, omega, steps, C.o.seed, s, have ? L.gptr[i].get() : nullptr,
                  have ? L.gadj[i].get() : nullptr, have ? L.nnode[i] : 0, hagg && have ? L.agg[i].get() : nullptr,
-                 amg.half);
+                 amg.half, amg.ddmin);
         M.cheb.push_back(std::move(d));
       } else if (sgs) {
         if (l == 0 && sgs0[i]) {
@@ -1180,7 +1221,7 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     NF_CHECK(z == 0, NFIELD_ESINGULAR, "DDGS: zero diagonal entry");
     auto sm = std::make_unique<DdgsD<T>>();
     sm->setup(Aii, F[f0].bs, dinv.p, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed, s,
-              nullptr, nullptr, 0, nullptr, 0);
+              nullptr, nullptr, 0, nullptr, 0, sp.ddmin);
     auto S = std::make_unique<SmootherSolverD<T>>();
     S->sm = std::move(sm);
     S->n = Aii->nr;

@@ -110,9 +110,10 @@ SPECS = ["BGS(AMG)", "BGS[order=fwd](AMG)", "BGS[sweeps=3,order=sym](AMG)", "BGS
          "AMG[smoother=sgs,omega=0.9](BGS)", "BGS(AMG[degree=3])",
          "BGS(AMG[smoother=sgs,omega=0.9,half=1])", "AMG[smoother=sgs,omega=0.9,half=1](BGS)",
          "BGS(AMG[smoother=sgs,omega=0.8,half=1,steps=2])",
-         "BGS(AMG[smoother=ddgs,omega=0.79])", "BGS(AMG[smoother=ddgs,omega=0.9,half=1])",
-         "AMG[smoother=ddgs,omega=0.8](BGS)", "BGS(AMG[smoother=ddgs,omega=1.1,half=1,steps=2])",
-         "BGS(DDGS[omega=0.79])", "BGS[sweeps=1](DDGS[omega=0.69,steps=2])"]
+         "BGS(AMG[smoother=ddgs,omega=0.79,ddmin=1])", "BGS(AMG[smoother=ddgs,omega=0.9,half=1,ddmin=1])",
+         "AMG[smoother=ddgs,omega=0.8,ddmin=1](BGS)", "BGS(AMG[smoother=ddgs,omega=1.1,half=1,steps=2,ddmin=1])",
+         "BGS(AMG[smoother=ddgs,omega=0.9,half=1])", "BGS(DDGS[omega=0.79,ddmin=1])",
+         "BGS[sweeps=1](DDGS[omega=0.69,steps=2,ddmin=1])"]
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -226,7 +227,7 @@ FSI_SPEC_D2 = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 FSI_OPTS = dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)
 FSI_OPTS_ABS = dict(split=[0, 0, 1])
 # the paper's own smoother on the fluid (DD(GS), subdomains = aggregates)
-FSI_SPEC_DD = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1])"
+FSI_SPEC_DD = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1,ddmin=1])"
 # Petrov-Galerkin transfers on the fluid (Sec. 7: PG-AMG for the fluid)
 FSI_SPEC_PG = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1,pg=1])"
 

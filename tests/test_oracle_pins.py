@@ -329,8 +329,8 @@ def test_chebyshev_closed_form(degree, ratio, boost):
 
 # ---------------------------------------------------------------- V-cycle
 @pytest.mark.parametrize("spec", ["AMG", "AMG[smoother=sgs,omega=0.9]", "AMG[smoother=sgs,omega=0.9,half=1]",
-                                  "AMG[smoother=sgs,omega=1.1,half=1,steps=2]", "AMG[smoother=ddgs,omega=0.9]",
-                                  "AMG[smoother=ddgs,omega=0.8,half=1]"])
+                                  "AMG[smoother=sgs,omega=1.1,half=1,steps=2]", "AMG[smoother=ddgs,omega=0.9,ddmin=1]",
+                                  "AMG[smoother=ddgs,omega=0.8,half=1,ddmin=1]"])
 def test_vcycle_symmetric_contraction(spec):
     """With R = P^T, an exact coarse solve and a post-smoother that is the
     adjoint of the pre-smoother (the same Chebyshev polynomial, or the
@@ -797,3 +797,17 @@ def test_pg_amg_gmres_reaches_dense_solution():
     x, st = o.gmres(rhs, rtol=1e-10, maxit=300)
     xd = np.linalg.solve(A.toarray(), rhs)
     assert st["status"] == 0 and np.linalg.norm(x - xd) < 1e-7 * np.linalg.norm(xd)
+
+
+def test_ddgs_few_aggregates_is_one_subdomain():
+    """A level with fewer aggregates than ddmin (default 256) is one
+    subdomain: the DD(GS) hierarchy then applies exactly the multicolour SGS;
+    with ddmin = 1 the subdomains are the aggregates and the result differs."""
+    s = nfgen.tsi2d(nel=16)
+    f, b = [s.fields[1]], [[s.blocks[1][1]]]
+    r = np.random.default_rng(8).standard_normal(f[0].ndof)
+    z_sgs = Oracle(f, b, "AMG[smoother=sgs,omega=0.9,half=1]", coarse_max=30).precond_apply(r)
+    z_dd = Oracle(f, b, "AMG[smoother=ddgs,omega=0.9,half=1]", coarse_max=30).precond_apply(r)
+    z_dd1 = Oracle(f, b, "AMG[smoother=ddgs,omega=0.9,half=1,ddmin=1]", coarse_max=30).precond_apply(r)
+    assert np.array_equal(z_sgs, z_dd)
+    assert np.abs(z_dd1 - z_sgs).max() > 1e-8 * np.abs(z_sgs).max()
