@@ -215,6 +215,56 @@ nfield_status nfield_gmres_solve_noalloc(nfield_ctx *ctx, const double *b_dev, d
                                          int32_t nrhs, const nfield_solve_opts *sopts,
                                          nfield_stats *stats, void *hip_stream);
 
+/* ---- slot batches: iteration-level continuous batching of GMRES columns.
+ * A batch holds `slots` columns (1 <= slots <= the context's max_rhs), each
+ * running the restarted GMRES of nfield_gmres_solve (Sec. 3.2) on its own
+ * right-hand side: the same kernels act on each column, so a column's
+ * solution and statistics are those of nfield_gmres_solve of that column
+ * alone, bit for bit.  nfield_batch_step advances every running column by
+ * one Arnoldi step in shared launches; between steps the caller submits new
+ * right-hand sides into free slots and takes finished ones out, so columns
+ * join and leave a running batch at its Arnoldi step boundaries.  A
+ * column's Krylov cycle ends as in nfield_gmres_solve (estimate below rtol,
+ * breakdown, maxit or m steps); the step after, its solution is updated and
+ * its true residual tested, and it finishes (stats as nfield_gmres_solve's,
+ * with solve_s the wall time from submission, bytes and gbps 0) or starts
+ * the next cycle in the same step.  The batch owns about 8 n slots
+ * ((m + 1) + 6 + (m if flexible, else 1)) bytes of device memory, taken
+ * from its context's cache (and counted in nfield_footprint_bytes);
+ * it uses the context's preconditioner and must be destroyed before it.
+ * Calls on one batch, and solves on its context, must not overlap (one
+ * stream or host thread at a time); every call is enqueued on hip_stream. */
+typedef struct nfield_batch nfield_batch;   /* opaque */
+
+/* Create a batch of `slots` free slots with the solve options sopts (NULL:
+ * defaults).  EINVAL for slots outside [1, max_rhs] or bad options. */
+nfield_status nfield_batch_create(nfield_ctx *ctx, int32_t slots, const nfield_solve_opts *sopts,
+                                  nfield_batch **out);
+/* Put a right-hand side (device, n doubles, copied) into a free slot, with
+ * the initial guess x0_dev (device, n doubles, copied; NULL: zero).  The
+ * column joins at the next step.  EINVAL if the slot is not free. */
+nfield_status nfield_batch_submit(nfield_batch *batch, int32_t slot, const double *b_dev,
+                                  const double *x0_dev, void *hip_stream);
+/* One step: cycle ends, true-residual tests and cycle starts of the columns
+ * that need them, then one Arnoldi step of every running column.  The
+ * slots that finished in this step are written to done (up to `slots`
+ * entries, may be NULL) and counted in *ndone; *nactive receives the
+ * number of slots still working.  Returns after the step has finished on
+ * the device. */
+nfield_status nfield_batch_step(nfield_batch *batch, int32_t *done, int32_t *ndone,
+                                int32_t *nactive, void *hip_stream);
+/* Copy a finished slot's solution to x_dev (device, n doubles, may be
+ * NULL), its statistics to *stats (may be NULL), and free the slot.  EINVAL
+ * if the slot has not finished. */
+nfield_status nfield_batch_take(nfield_batch *batch, int32_t slot, double *x_dev,
+                                nfield_stats *stats, void *hip_stream);
+/* 0 free, 1 waiting for its true residual, 2 in an Arnoldi cycle, 3 cycle
+ * ended, 4 finished (take it); -1 for a bad argument. */
+int32_t nfield_batch_state(const nfield_batch *batch, int32_t slot);
+/* Device bytes the batch holds. */
+size_t nfield_batch_bytes(const nfield_batch *batch);
+void nfield_batch_destroy(nfield_batch *batch);
+
 /* Replace the values of the nonzero block (i, j), keeping its pattern (the
  * next Newton step of the paper's monolithic scheme, Sec. 2).  val holds the
  * block's nnz values in its CSR order, in device memory (on_device = 1,

@@ -94,13 +94,13 @@ __global__ void k_cheb_firstm(const T* b, int64_t ldb, const T* dinv, T inv_thet
   }
 }
 __global__ void k_scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride,
-                                 int64_t n, const int* mask) {
+                                 int64_t n, const int* mask, const int* vcol, int64_t vstep) {
   const int k = blockIdx.y;
   if (mask && !mask[k]) return;
   const double sv = nrm[k * stride];
   const double inv = sv != 0.0 ? 1.0 / sv : 1.0;
   const double* wk = w + k * ldw;
-  double* vk = v + k * ldv;
+  double* vk = v + k * ldv + (vcol ? (int64_t)vcol[k] * vstep : 0);
   NF_ROWS(n) vk[i] = wk[i] * inv;
 }
 // one wavefront per row of a dense row-major matrix, all columns at once
@@ -182,11 +182,11 @@ template <class T> void cheb_firstm(const T* b, int64_t ldb, const T* dinv, T in
                        x, ldx, n);
 }
 void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride, int64_t n,
-                    int nrhs, const int* mask, hipStream_t s) {
+                    int nrhs, const int* mask, hipStream_t s, const int* vcol, int64_t vstep) {
   if (n > 0 && nrhs > 0) bytes_count(16.0 * n * nrhs);
   if (n > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_scale_inv_devm, dim3(grid_cols(n, nrhs), nrhs), dim3(256), 0, s, w, ldw, v, ldv, nrm, stride, n,
-                       mask);
+                       mask, vcol, vstep);
 }
 template <class T> void dense_gemvm(const double* M, int n, const T* b, int64_t ldb, T* x, int64_t ldx, int nrhs,
                                     hipStream_t s) {
@@ -457,10 +457,11 @@ __global__ __launch_bounds__(256) void k_dot_partialm(const double* __restrict__
 }
 // grid (ncols, nrhs): out[k*os + j] (+)= sum of partial[k*ps + j*RED_BLOCKS + 0..RED_BLOCKS)
 __global__ __launch_bounds__(256) void k_mreduce(const double* __restrict__ partial, int64_t ps, double* __restrict__ out,
-                                                 int64_t os, int accumulate, const int* mask) {
+                                                 int64_t os, int accumulate, const int* mask, const int* ncv) {
   __shared__ double ws[4];
   const int j = blockIdx.x, k = blockIdx.y;
   if (mask && !mask[k]) return;
+  if (ncv && j >= ncv[k]) return;
   const double* pk = partial + k * ps + (int64_t)j * RED_BLOCKS;
   double s = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += pk[i];
@@ -473,7 +474,7 @@ void dotm(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
   bytes_count(16.0 * n * nrhs);
   hipLaunchKernelGGL(k_dot_partialm, dim3(RED_BLOCKS, nrhs), dim3(256), 0, s, x, ldx, y, ldy, n, partial);
   hipLaunchKernelGGL(k_mreduce, dim3(1, nrhs), dim3(256), 0, s, partial, (int64_t)RED_BLOCKS, out, (int64_t)1, 0,
-                     (const int*)nullptr);
+                     (const int*)nullptr, (const int*)nullptr);
 }
 
 // v = w / ||w||, ||w||^2 the sum of the RED_BLOCKS partials of one dot:
@@ -502,11 +503,13 @@ void normalize(const double* w, double* v, int64_t n, double* partial, double* n
 template <int CH>
 __global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
                                               const double* __restrict__ w, int64_t ldw, double* __restrict__ partial,
-                                              int64_t ps, const int* mask) {
+                                              int64_t ps, const int* mask, const int* ncv) {
   __shared__ double ws[4];
   const int kc = blockIdx.y, k0 = blockIdx.z * CH;
   if (mask && !mask[kc]) return;
+  if (ncv) ncols = ncv[kc];
   const int nk = min(CH, ncols - k0);
+  if (nk <= 0) return;   // uniform over the workgroup
   const double* Vk = V + kc * vs + (int64_t)k0 * n;
   const double* wk = w + kc * ldw;
   double acc[CH];
@@ -530,10 +533,11 @@ __global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int6
 template <int MAXC>
 __global__ __launch_bounds__(256) void k_mupdate_only(const double* __restrict__ V, int64_t vs, int64_t n, int ncols,
                                                       const double* __restrict__ h, int64_t hs, double* __restrict__ w,
-                                                      int64_t ldw, const int* mask) {
+                                                      int64_t ldw, const int* mask, const int* ncv) {
   __shared__ double hsh[MAXC];
   const int kc = blockIdx.y;
   if (mask && !mask[kc]) return;
+  if (ncv) ncols = ncv[kc];
   for (int k = threadIdx.x; k < MAXC; k += 256) hsh[k] = k < ncols ? h[kc * hs + k] : 0.0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -593,37 +597,37 @@ __global__ __launch_bounds__(256) void k_mcombine(const double* __restrict__ V, 
   } while (0)
 
 void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double* w, int64_t ldw, double* partial,
-                  const int* mask, hipStream_t s) {
+                  const int* mask, hipStream_t s, const int* ncv) {
   if (ncols <= 0) return;
   NF_CHECK(ncols <= 64, NFIELD_EINVAL, "GMRES restart length above 63 is not supported");
   bytes_count(8.0 * L.n * (ncols + 1) * L.nrhs);
   if (ncols <= 8)
     hipLaunchKernelGGL(k_mdot<8>, dim3(RED_BLOCKS, L.nrhs, 1), dim3(256), 0, s, V, L.vs, L.n, ncols, w, ldw, partial, L.ps,
-                       mask);
+                       mask, ncv);
   else
     hipLaunchKernelGGL(k_mdot<16>, dim3(RED_BLOCKS, L.nrhs, cdiv(ncols, 16)), dim3(256), 0, s, V, L.vs, L.n, ncols, w, ldw,
-                       partial, L.ps, mask);
+                       partial, L.ps, mask, ncv);
 }
 void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out, int accumulate, const int* mask,
-             hipStream_t s) {
-  hipLaunchKernelGGL(k_mreduce, dim3(ncols, L.nrhs), dim3(256), 0, s, partial, L.ps, out, L.hs, accumulate, mask);
+             hipStream_t s, const int* ncv) {
+  hipLaunchKernelGGL(k_mreduce, dim3(ncols, L.nrhs), dim3(256), 0, s, partial, L.ps, out, L.hs, accumulate, mask, ncv);
 }
 // the update with every element's thread, then the dots as mdot_partial
 // (the same sums as one fused pass, at the cost of a second read of V)
 void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
-                 double* partial, const int* mask, hipStream_t s) {
+                 double* partial, const int* mask, hipStream_t s, const int* ncv) {
   if (ncols <= 0 || L.n <= 0) return;
   bytes_count(8.0 * L.n * (ncols + 2) * L.nrhs);
   NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
-                                             L.n, ncols, h, L.hs, w, ldw, mask));
-  mdot_partial(L, V, ncols, w, ldw, partial, mask, s);
+                                             L.n, ncols, h, L.hs, w, ldw, mask, ncv));
+  mdot_partial(L, V, ncols, w, ldw, partial, mask, s, ncv);
 }
 void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
-                  double* partial, const int* mask, hipStream_t s) {
+                  double* partial, const int* mask, hipStream_t s, const int* ncv) {
   if (ncols <= 0 || L.n <= 0) return;
   bytes_count(8.0 * L.n * (ncols + 3) * L.nrhs);
   NF_MAXC_DISPATCH(ncols, hipLaunchKernelGGL((k_mupdate_only<MC>), dim3(cdiv(L.n, 256), L.nrhs), dim3(256), 0, s, V, L.vs,
-                                             L.n, ncols, h, L.hs, w, ldw, mask));
+                                             L.n, ncols, h, L.hs, w, ldw, mask, ncv));
   hipLaunchKernelGGL(k_norm_partial, dim3(RED_BLOCKS, L.nrhs), dim3(256), 0, s, L.n, w, ldw, partial, L.ps, mask);
 }
 void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
@@ -638,11 +642,13 @@ void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_n
 // (m+1) x m column-major.
 __global__ __launch_bounds__(256) void k_givens(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
                                                 int64_t hs, const double* __restrict__ nrm_partial, int64_t ps, double* H,
-                                                double* cs, double* sn, double* g, double* scal, const int* mask) {
+                                                double* cs, double* sn, double* g, double* scal, const int* mask,
+                                                const int* jv) {
   __shared__ double ws[4];
   __shared__ double hc[66], csl[64], snl[64];   // the new column and the rotations so far, staged by all threads
   const int kc = blockIdx.x;
   if (mask && !mask[kc]) return;
+  if (jv) j = jv[kc];
   const int ld = m + 1;
   double* Hk = H + (int64_t)kc * ld * m;
   double* csk = cs + (int64_t)kc * m;
@@ -699,13 +705,42 @@ __global__ void k_backsolve(const int* ncols, int m, const double* H, const doub
   }
 }
 void givens_step(const GmresLayout& L, int j, const double* h1, const double* h2, const double* nrm_partial, double* H,
-                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s) {
+                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s, const int* jv) {
   hipLaunchKernelGGL(k_givens, dim3(L.nrhs), dim3(256), 0, s, j, L.m, h1, h2, L.hs, nrm_partial, L.ps, H, cs, sn, g, scal,
-                     mask);
+                     mask, jv);
 }
 void backsolve(const GmresLayout& L, const int* ncols, const double* H, const double* g, double* y, const int* mask,
                hipStream_t s) {
   hipLaunchKernelGGL(k_backsolve, dim3(L.nrhs), dim3(64), 0, s, ncols, L.m, H, g, y, mask);
+}
+
+// Columns of per-column Krylov sets: out column c = V_{act[c]}[jv[act[c]]]
+// (jv NULL: vector 0), and the reverse scatter.
+__global__ void k_slot_gather(const double* __restrict__ V, int64_t vs, int64_t n, const int* __restrict__ act,
+                              const int* __restrict__ jv, double* __restrict__ out) {
+  const int c = blockIdx.y, k = act[c];
+  const double* src = V + k * vs + (jv ? (int64_t)jv[k] * n : 0);
+  double* dst = out + (int64_t)c * n;
+  NF_ROWS(n) dst[i] = src[i];
+}
+__global__ void k_slot_scatter(const double* __restrict__ in, int64_t n, const int* __restrict__ act,
+                               const int* __restrict__ jv, double* __restrict__ V, int64_t vs) {
+  const int c = blockIdx.y, k = act[c];
+  const double* src = in + (int64_t)c * n;
+  double* dst = V + k * vs + (jv ? (int64_t)jv[k] * n : 0);
+  NF_ROWS(n) dst[i] = src[i];
+}
+void slot_gather(const double* V, int64_t vs, int64_t n, const int* act, const int* jv, int nact, double* out,
+                 hipStream_t s) {
+  if (n <= 0 || nact <= 0) return;
+  bytes_count(16.0 * n * nact);
+  hipLaunchKernelGGL(k_slot_gather, dim3(grid_cols(n, nact), nact), dim3(256), 0, s, V, vs, n, act, jv, out);
+}
+void slot_scatter(const double* in, int64_t n, const int* act, const int* jv, int nact, double* V, int64_t vs,
+                  hipStream_t s) {
+  if (n <= 0 || nact <= 0) return;
+  bytes_count(16.0 * n * nact);
+  hipLaunchKernelGGL(k_slot_scatter, dim3(grid_cols(n, nact), nact), dim3(256), 0, s, in, n, act, jv, V, vs);
 }
 
 // ====================================================================== scan

@@ -89,28 +89,38 @@ struct GmresLayout {
   int m = 0;            // restart length
   int nrhs = 1;
 };
+// ncv (device, may be null): per-column counts of basis vectors, at most
+// ncols (the grid's count); columns then proceed at their own Arnoldi steps
 void mdot_partial(const GmresLayout& L, const double* V, int ncols, const double* w, int64_t ldw, double* partial,
-                  const int* mask, hipStream_t s);
+                  const int* mask, hipStream_t s, const int* ncv = nullptr);
 void mreduce(const GmresLayout& L, const double* partial, int ncols, double* out, int accumulate, const int* mask,
-             hipStream_t s);
+             hipStream_t s, const int* ncv = nullptr);
 void mupdate_dot(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
-                 double* partial, const int* mask, hipStream_t s);
+                 double* partial, const int* mask, hipStream_t s, const int* ncv = nullptr);
 void mupdate_norm(const GmresLayout& L, const double* V, int ncols, const double* h, double* w, int64_t ldw,
-                  double* partial, const int* mask, hipStream_t s);
+                  double* partial, const int* mask, hipStream_t s, const int* ncv = nullptr);
 // u_k (+)= sum_{j < ncols_k} V_k[j] y_k[j]; ncols per column on the device, max_ncols on the host
 void mcombine(const GmresLayout& L, const double* V, const int* ncols, int max_ncols, const double* y, double* u,
               int64_t ldu, int accumulate, const int* mask, hipStream_t s);
 // Arnoldi step j bookkeeping per column: reduce ||w||^2 partials into
 // H(j+1,j), h1 + h2 into H(:,j), apply the stored rotations and a new one,
 // update g, write ||w|| and |g_{j+1}| to scal[2k], scal[2k+1].
+// (jv, device, may be null: per-column step numbers in place of j)
 void givens_step(const GmresLayout& L, int j, const double* h1, const double* h2, const double* nrm_partial, double* H,
-                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s);
+                 double* cs, double* sn, double* g, double* scal, const int* mask, hipStream_t s,
+                 const int* jv = nullptr);
 // y_k = H_k(0:k,0:k)^-1 g_k with k = ncols[col]
 void backsolve(const GmresLayout& L, const int* ncols, const double* H, const double* g, double* y, const int* mask,
                hipStream_t s);
-// v_k = w_k / nrm[k * stride] (v_k = w_k if the norm is zero)
+// v_k = w_k / nrm[k * stride] (v_k = w_k if the norm is zero); vcol (device,
+// may be null): column k's destination moved by vcol[k] * vstep elements
 void scale_inv_devm(const double* w, int64_t ldw, double* v, int64_t ldv, const double* nrm, int stride, int64_t n,
-                    int nrhs, const int* mask, hipStream_t s);
+                    int nrhs, const int* mask, hipStream_t s, const int* vcol = nullptr, int64_t vstep = 0);
+// out column c = V + act[c] vs + jv[act[c]] n (jv may be null: + 0), and back
+void slot_gather(const double* V, int64_t vs, int64_t n, const int* act, const int* jv, int nact, double* out,
+                 hipStream_t s);
+void slot_scatter(const double* in, int64_t n, const int* act, const int* jv, int nact, double* V, int64_t vs,
+                  hipStream_t s);
 
 // ------------------------------------------------------------ multicolour Gauss-Seidel
 // greedy colouring of a node graph in node order; returns the number of

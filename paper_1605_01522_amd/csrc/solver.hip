@@ -1836,6 +1836,224 @@ static KrylovWs scratch_workspace(nfield_ctx& C, int m, int flexible, int nrhs, 
 
 }  // namespace nf
 
+// ============================================================ slot batches
+// Iteration-level continuous batching.  A batch holds a fixed number of
+// column slots, each running its own restarted GMRES process with the
+// arithmetic of gmres() above (the same kernels per column, so a column's
+// iterates are those of a solve of that column alone).  One step advances
+// every running slot by one Arnoldi step in shared launches; at the step
+// boundaries finished slots leave (their Krylov cycle ends, the solution is
+// updated and the true residual decides) and new right-hand sides join.
+// The preconditioner and the operator act on the running slots gathered into
+// contiguous columns; the basis, Hessenberg and rotation state stay per slot,
+// each slot at its own Arnoldi index.
+enum SlotState { SLOT_FREE = 0, SLOT_START, SLOT_RUN, SLOT_END, SLOT_DONE };
+
+struct nfield_batch {
+  nfield_ctx* C = nullptr;
+  int slots = 0, m = 0;
+  bool flex = false;
+  nfield_solve_opts so{};
+  nf::GmresLayout L, LZ;
+  // per slot: basis (m + 1 vectors), flexible basis (m), solution, rhs,
+  // one work vector, the cycle-end combination; compact columns rc, zc, wc
+  nf::DBuf<double> V, Z, X, Bv, Wsl, U, rc, zc, wc;
+  nf::DBuf<double> H, cs, sn, g, y, h1, h2, partial, scal;
+  nf::DBuf<int> ibuf;          // 3 phases x 5 slots ints
+  double* pinned = nullptr;    // 4 slots doubles
+  int* pinned_i = nullptr;     // 3 phases x 5 slots ints
+  std::vector<int> state, j, total, fresh;
+  std::vector<char> broke;
+  std::vector<double> beta0;
+  std::vector<nfield_stats> st;
+  std::vector<std::chrono::steady_clock::time_point> t_submit;
+  ~nfield_batch() {
+    if (pinned) (void)hipHostFree(pinned);
+    if (pinned_i) (void)hipHostFree(pinned_i);
+  }
+  // device and host int regions of one phase: [act | mask | jv | ncv | aux]
+  int* dev_i(int phase) { return ibuf.p + (size_t)phase * 5 * slots; }
+  int* host_i(int phase) { return pinned_i + (size_t)phase * 5 * slots; }
+};
+
+namespace nf {
+
+static void batch_upload(nfield_batch& B, int phase, int regions, hipStream_t s) {
+  NF_HIP(hipMemcpyAsync(B.dev_i(phase), B.host_i(phase), sizeof(int) * regions * B.slots, hipMemcpyHostToDevice, s));
+}
+
+// Cycle ends of the slots in SLOT_END: y = H^-1 g, x += Z y (flexible) or
+// x += M^-1 (V y); the slots then wait for their true residual.
+static void batch_cycle_ends(nfield_batch& B, hipStream_t s) {
+  nfield_ctx& C = *B.C;
+  const int64_t n = C.Aglob.nr;
+  int* hi = B.host_i(0);
+  int* act = hi;
+  int* part = hi + B.slots;
+  int* jend = hi + 2 * B.slots;
+  int ne = 0, maxj = 0;
+  for (int k = 0; k < B.slots; ++k) {
+    const bool e = B.state[k] == SLOT_END;
+    part[k] = e;
+    jend[k] = e ? B.j[k] : 0;
+    if (e) {
+      act[ne++] = k;
+      maxj = std::max(maxj, B.j[k]);
+    }
+  }
+  if (ne == 0) return;
+  batch_upload(B, 0, 3, s);
+  int* dact = B.dev_i(0);
+  int* dpart = dact + B.slots;
+  int* djend = dact + 2 * B.slots;
+  backsolve(B.L, djend, B.H.p, B.g.p, B.y.p, dpart, s);
+  if (B.flex) {
+    mcombine(B.LZ, B.Z.p, djend, maxj, B.y.p, B.X.p, n, 1, dpart, s);
+  } else {
+    mcombine(B.L, B.V.p, djend, maxj, B.y.p, B.U.p, n, 0, dpart, s);
+    slot_gather(B.U.p, n, n, dact, nullptr, ne, B.rc.p, s);
+    precond(C, B.rc.p, n, B.zc.p, n, ne, s);
+    slot_scatter(B.zc.p, n, dact, nullptr, ne, B.U.p, n, s);
+    add_intom<double>(B.U.p, n, B.X.p, n, n, B.slots, dpart, s);
+  }
+  for (int c = 0; c < ne; ++c) B.state[act[c]] = SLOT_START;
+}
+
+// True residuals of the slots in SLOT_START and the restart test; a slot
+// that goes on starts a cycle: v_0 = r / beta, g = beta e_1.
+static void batch_cycle_starts(nfield_batch& B, std::vector<int>& finished, hipStream_t s) {
+  nfield_ctx& C = *B.C;
+  const int64_t n = C.Aglob.nr;
+  const nfield_solve_opts& so = B.so;
+  int* act = B.host_i(1);
+  int* mask = act + B.slots;
+  int ns = 0;
+  for (int k = 0; k < B.slots; ++k) {
+    mask[k] = 0;
+    if (B.state[k] == SLOT_START) act[ns++] = k;
+  }
+  if (ns == 0) return;
+  batch_upload(B, 1, 1, s);
+  int* dact = B.dev_i(1);
+  int* dmask = dact + B.slots;
+  slot_gather(B.X.p, n, n, dact, nullptr, ns, B.zc.p, s);
+  slot_gather(B.Bv.p, n, n, dact, nullptr, ns, B.wc.p, s);
+  SpmvArgs<double> a;
+  a.x = B.zc.p;
+  a.ldx = n;
+  a.y = B.rc.p;
+  a.ldy = n;
+  a.b = B.wc.p;
+  a.ldb = n;
+  a.nrhs = ns;
+  spmv<double>(SPMV_RESID, C.Aglob, a, s);
+  dotm(B.rc.p, n, B.rc.p, n, n, ns, B.partial.p, B.scal.p, s);
+  double* res = B.pinned;
+  double* beta = B.pinned + B.slots;
+  NF_HIP(hipMemcpyAsync(res, B.scal.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  int nbegin = 0;
+  for (int c = 0; c < ns; ++c) {
+    const int k = act[c];
+    const double bk = std::sqrt(res[c]);
+    nfield_stats& st = B.st[k];
+    auto finish = [&](int status) {
+      st.status = status;
+      B.state[k] = SLOT_DONE;
+      finished.push_back(k);
+    };
+    if (B.fresh[k]) {
+      B.fresh[k] = 0;
+      B.beta0[k] = bk;
+      if (!std::isfinite(bk)) { finish(NFIELD_ENAN); continue; }
+      if (bk == 0.0) { finish(NFIELD_OK); continue; }
+    }
+    st.relres = bk / B.beta0[k];
+    if (!std::isfinite(bk)) { finish(NFIELD_ENAN); continue; }
+    if (bk / B.beta0[k] < so.rtol) { finish(NFIELD_OK); continue; }
+    if (B.broke[k]) { finish(NFIELD_EBREAKDOWN); continue; }
+    if (B.total[k] >= so.maxit) { finish(NFIELD_NOT_CONVERGED); continue; }
+    if (B.total[k] > 0) st.restarts++;
+    mask[k] = 1;
+    beta[k] = bk;
+    B.j[k] = 0;
+    B.state[k] = SLOT_RUN;
+    ++nbegin;
+  }
+  if (nbegin == 0) return;
+  batch_upload(B, 1, 2, s);   // the mask (and the same act list)
+  double* dbeta = B.scal.p + 2 * B.slots;
+  NF_HIP(hipMemcpyAsync(dbeta, beta, sizeof(double) * B.slots, hipMemcpyHostToDevice, s));
+  slot_scatter(B.rc.p, n, dact, nullptr, ns, B.Wsl.p, n, s);
+  scale_inv_devm(B.Wsl.p, n, B.V.p, B.L.vs, dbeta, 1, n, B.slots, dmask, s);
+  hipLaunchKernelGGL(k_init_gm, dim3(B.slots), dim3(64), 0, s, B.g.p, B.m, dbeta, dmask);
+}
+
+// One Arnoldi step of every slot in SLOT_RUN, each at its own index j:
+// z = M^-1 v_j, w = A z, two classical Gram-Schmidt passes over v_0..v_j,
+// the Givens update and v_{j+1} = w / ||w||.
+static void batch_arnoldi(nfield_batch& B, hipStream_t s) {
+  nfield_ctx& C = *B.C;
+  const int64_t n = C.Aglob.nr;
+  const nfield_solve_opts& so = B.so;
+  int* act = B.host_i(2);
+  int* mask = act + B.slots;
+  int* jv = act + 2 * B.slots;
+  int* ncv = act + 3 * B.slots;
+  int nr = 0, maxj = 0;
+  for (int k = 0; k < B.slots; ++k) {
+    const bool r = B.state[k] == SLOT_RUN;
+    mask[k] = r;
+    jv[k] = r ? B.j[k] : 0;
+    ncv[k] = jv[k] + 1;
+    if (r) {
+      act[nr++] = k;
+      maxj = std::max(maxj, B.j[k]);
+    }
+  }
+  if (nr == 0) return;
+  batch_upload(B, 2, 4, s);
+  int* dact = B.dev_i(2);
+  int* dmask = dact + B.slots;
+  int* djv = dact + 2 * B.slots;
+  int* dncv = dact + 3 * B.slots;
+  slot_gather(B.V.p, B.L.vs, n, dact, djv, nr, B.rc.p, s);
+  precond(C, B.rc.p, n, B.zc.p, n, nr, s);
+  if (B.flex) slot_scatter(B.zc.p, n, dact, djv, nr, B.Z.p, B.LZ.vs, s);
+  SpmvArgs<double> a;
+  a.x = B.zc.p;
+  a.ldx = n;
+  a.y = B.wc.p;
+  a.ldy = n;
+  a.nrhs = nr;
+  spmv<double>(SPMV_STORE, C.Aglob, a, s);
+  slot_scatter(B.wc.p, n, dact, nullptr, nr, B.Wsl.p, n, s);
+  const GmresLayout& L = B.L;
+  const int nc = maxj + 1;
+  mdot_partial(L, B.V.p, nc, B.Wsl.p, n, B.partial.p, dmask, s, dncv);
+  mreduce(L, B.partial.p, nc, B.h1.p, 0, dmask, s, dncv);
+  mupdate_dot(L, B.V.p, nc, B.h1.p, B.Wsl.p, n, B.partial.p, dmask, s, dncv);
+  mreduce(L, B.partial.p, nc, B.h2.p, 0, dmask, s, dncv);
+  mupdate_norm(L, B.V.p, nc, B.h2.p, B.Wsl.p, n, B.partial.p, dmask, s, dncv);
+  givens_step(L, 0, B.h1.p, B.h2.p, B.partial.p, B.H.p, B.cs.p, B.sn.p, B.g.p, B.scal.p, dmask, s, djv);
+  scale_inv_devm(B.Wsl.p, n, B.V.p + n, L.vs, B.scal.p, 2, n, B.slots, dmask, s, djv, n);
+  double* hr = B.pinned + 2 * B.slots;
+  NF_HIP(hipMemcpyAsync(hr, B.scal.p, 2 * sizeof(double) * B.slots, hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < nr; ++c) {
+    const int k = act[c];
+    ++B.total[k];
+    ++B.j[k];
+    const double hn = hr[2 * k], res = hr[2 * k + 1];
+    if (!std::isfinite(res) || hn <= 1e-300 || res / B.beta0[k] < so.rtol || B.total[k] >= so.maxit || B.j[k] == B.m) {
+      if (hn <= 1e-300) B.broke[k] = 1;
+      B.state[k] = SLOT_END;
+    }
+  }
+}
+
+}  // namespace nf
+
 // ================================================================ C ABI
 using namespace nf;
 
@@ -2110,6 +2328,169 @@ nfield_status nfield_gmres_solve(nfield_ctx* ctx, const double* b, double* x, in
 nfield_status nfield_gmres_solve_noalloc(nfield_ctx* ctx, const double* b, double* x, int32_t nrhs,
                                          const nfield_solve_opts* sopts, nfield_stats* stats, void* hip_stream) {
   return gmres_entry(ctx, b, x, nrhs, sopts, stats, hip_stream, true);
+}
+
+nfield_status nfield_batch_create(nfield_ctx* ctx, int32_t slots, const nfield_solve_opts* sopts, nfield_batch** out) {
+  if (!ctx || !out || slots < 1 || slots > NRMAX || slots > ctx->o.max_rhs) {
+    g_err = "nfield_batch_create: bad argument (slots must be in [1, max_rhs])";
+    return NFIELD_EINVAL;
+  }
+  *out = nullptr;
+  nfield_solve_opts so;
+  nfield_default_solve_opts(&so);
+  if (sopts) so = *sopts;
+  if (so.restart < 1 || so.restart > 63 || so.maxit < 0 || !(so.rtol > 0)) {
+    g_err = "nfield_batch_create: restart must be in [1, 63], maxit >= 0, rtol > 0";
+    return NFIELD_EINVAL;
+  }
+  DevPool* prev = g_pool;
+  g_pool = &ctx->pool;
+  try {
+    auto B = std::make_unique<nfield_batch>();
+    const int64_t n = ctx->Aglob.nr;
+    const int m = so.restart;
+    const size_t sl = (size_t)slots;
+    B->C = ctx;
+    B->slots = slots;
+    B->m = m;
+    B->flex = so.flexible != 0;
+    B->so = so;
+    B->L.n = n;
+    B->L.vs = (int64_t)(m + 1) * n;
+    B->L.hs = m + 1;
+    B->L.ps = (int64_t)(m + 1) * RED_BLOCKS;
+    B->L.m = m;
+    B->L.nrhs = slots;
+    B->LZ = B->L;
+    B->LZ.vs = (int64_t)m * n;
+    B->V.alloc((size_t)n * (m + 1) * sl);
+    if (B->flex) B->Z.alloc((size_t)n * m * sl);
+    else B->U.alloc((size_t)n * sl);
+    for (DBuf<double>* d : {&B->X, &B->Bv, &B->Wsl, &B->rc, &B->zc, &B->wc}) d->alloc((size_t)n * sl);
+    B->H.alloc((size_t)(m + 1) * m * sl);
+    B->cs.alloc((size_t)m * sl);
+    B->sn.alloc((size_t)m * sl);
+    B->g.alloc((size_t)(m + 1) * sl);
+    B->y.alloc((size_t)m * sl);
+    B->h1.alloc((size_t)(m + 1) * sl);
+    B->h2.alloc((size_t)(m + 1) * sl);
+    B->partial.alloc((size_t)RED_BLOCKS * (m + 1) * sl);
+    B->scal.alloc(4 * sl);
+    B->ibuf.alloc(15 * sl);
+    NF_HIP(hipHostMalloc((void**)&B->pinned, 4 * sl * sizeof(double), hipHostMallocDefault));
+    NF_HIP(hipHostMalloc((void**)&B->pinned_i, 15 * sl * sizeof(int), hipHostMallocDefault));
+    B->state.assign(sl, SLOT_FREE);
+    B->j.assign(sl, 0);
+    B->total.assign(sl, 0);
+    B->fresh.assign(sl, 0);
+    B->broke.assign(sl, 0);
+    B->beta0.assign(sl, 0.0);
+    B->st.assign(sl, nfield_stats{});
+    B->t_submit.assign(sl, {});
+    g_pool = prev;
+    *out = B.release();
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    g_pool = prev;
+    return fail(e);
+  }
+}
+
+nfield_status nfield_batch_submit(nfield_batch* B, int32_t slot, const double* b, const double* x0, void* hip_stream) {
+  if (!B || !b || slot < 0 || slot >= B->slots || B->state[slot] != SLOT_FREE) {
+    g_err = "nfield_batch_submit: bad argument or the slot is not free";
+    return NFIELD_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    const int64_t n = B->C->Aglob.nr;
+    double* xs = B->X.p + (int64_t)slot * n;
+    NF_HIP(hipMemcpyAsync(B->Bv.p + (int64_t)slot * n, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (x0) NF_HIP(hipMemcpyAsync(xs, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else NF_HIP(hipMemsetAsync(xs, 0, sizeof(double) * n, s));
+    B->state[slot] = SLOT_START;
+    B->fresh[slot] = 1;
+    B->j[slot] = 0;
+    B->total[slot] = 0;
+    B->broke[slot] = 0;
+    B->beta0[slot] = 0.0;
+    std::memset(&B->st[slot], 0, sizeof(nfield_stats));
+    B->t_submit[slot] = std::chrono::steady_clock::now();
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    return fail(e);
+  }
+}
+
+nfield_status nfield_batch_step(nfield_batch* B, int32_t* done, int32_t* ndone, int32_t* nactive, void* hip_stream) {
+  if (!B) { g_err = "nfield_batch_step: null batch"; return NFIELD_EINVAL; }
+  hipStream_t s = (hipStream_t)hip_stream;
+  nfield_ctx& C = *B->C;
+  DevPool* prev = g_pool;
+  g_pool = &C.pool;
+  C.pool.enter(s);
+  try {
+    std::vector<int> finished;
+    batch_cycle_ends(*B, s);
+    batch_cycle_starts(*B, finished, s);
+    batch_arnoldi(*B, s);
+    // the host staging of this step is rewritten by the next one
+    NF_HIP(hipStreamSynchronize(s));
+    NF_HIP(hipGetLastError());
+    const auto now = std::chrono::steady_clock::now();
+    for (int k : finished) {
+      B->st[k].iters = B->total[k];
+      B->st[k].setup_s = C.setup_s;
+      B->st[k].solve_s = std::chrono::duration<double>(now - B->t_submit[k]).count();
+    }
+    if (done)
+      for (size_t q = 0; q < finished.size(); ++q) done[q] = finished[q];
+    if (ndone) *ndone = (int32_t)finished.size();
+    int live = 0;
+    for (int k = 0; k < B->slots; ++k) live += B->state[k] == SLOT_START || B->state[k] == SLOT_RUN ||
+                                             B->state[k] == SLOT_END;
+    if (nactive) *nactive = live;
+    g_pool = prev;
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    g_pool = prev;
+    return fail(e);
+  }
+}
+
+nfield_status nfield_batch_take(nfield_batch* B, int32_t slot, double* x, nfield_stats* stats, void* hip_stream) {
+  if (!B || slot < 0 || slot >= B->slots || B->state[slot] != SLOT_DONE) {
+    g_err = "nfield_batch_take: bad argument or the slot has not finished";
+    return NFIELD_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    const int64_t n = B->C->Aglob.nr;
+    if (x) NF_HIP(hipMemcpyAsync(x, B->X.p + (int64_t)slot * n, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (stats) *stats = B->st[slot];
+    B->state[slot] = SLOT_FREE;
+    return NFIELD_OK;
+  } catch (NfError& e) {
+    return fail(e);
+  }
+}
+
+int32_t nfield_batch_state(const nfield_batch* B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->slots) return -1;
+  return B->state[slot];
+}
+
+size_t nfield_batch_bytes(const nfield_batch* B) {
+  if (!B) return 0;
+  size_t b = 0;
+  for (const DBuf<double>* d : {&B->V, &B->Z, &B->X, &B->Bv, &B->Wsl, &B->U, &B->rc, &B->zc, &B->wc, &B->H, &B->cs,
+                                &B->sn, &B->g, &B->y, &B->h1, &B->h2, &B->partial, &B->scal})
+    b += d->n * sizeof(double);
+  return b + B->ibuf.n * sizeof(int);
+}
+
+void nfield_batch_destroy(nfield_batch* B) {
+  delete B;
 }
 
 nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const double* val, int32_t on_device,

@@ -57,7 +57,8 @@ EXPORTS = ["nfield_default_opts", "nfield_default_solve_opts", "nfield_setup",
            "nfield_last_error", "nfield_hier_count", "nfield_hier_nlevels", "nfield_hier_nfields",
            "nfield_hier_size", "nfield_hier_lambda", "nfield_hier_matrix", "nfield_hier_aggregates",
            "nfield_hier_nnz", "nfield_hier_op_complexity", "nfield_hier_grid_complexity",
-           "nfield_residual_history"]
+           "nfield_residual_history", "nfield_batch_create", "nfield_batch_submit", "nfield_batch_step",
+           "nfield_batch_take", "nfield_batch_state", "nfield_batch_bytes", "nfield_batch_destroy"]
 
 _lib = None
 
@@ -117,6 +118,19 @@ def lib():
         getattr(L, f).restype = C.c_double
     L.nfield_residual_history.argtypes = [vp, i32, vp, i32]
     L.nfield_residual_history.restype = i32
+    L.nfield_batch_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
+    L.nfield_batch_create.restype = C.c_int
+    L.nfield_batch_submit.argtypes = [vp, i32, vp, vp, vp]
+    L.nfield_batch_submit.restype = C.c_int
+    L.nfield_batch_step.argtypes = [vp, vp, vp, vp, vp]
+    L.nfield_batch_step.restype = C.c_int
+    L.nfield_batch_take.argtypes = [vp, i32, vp, vp, vp]
+    L.nfield_batch_take.restype = C.c_int
+    L.nfield_batch_state.argtypes = [vp, i32]
+    L.nfield_batch_state.restype = i32
+    L.nfield_batch_bytes.argtypes = [vp]
+    L.nfield_batch_bytes.restype = C.c_size_t
+    L.nfield_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -246,10 +260,82 @@ def nfield_gmres_solve(ctx, b, x, restart=50, maxit=1000, flexible=0, rtol=1e-8,
     rc = fn(ctx, bp, xp, k, C.byref(so), C.cast(st, C.c_void_p), _stream(stream))
     if rc < 0:
         raise NFieldError(rc, "nfield_gmres_solve_noalloc" if noalloc else "nfield_gmres_solve")
-    stats = [dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres,
-                  setup_s=s.setup_s, solve_s=s.solve_s, bytes=s.bytes, gbps=s.gbps)
-             for s in st[:k]]
+    stats = [_stats_dict(s) for s in st[:k]]
     return rc, stats
+
+
+def _stats_dict(s):
+    return dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres,
+                setup_s=s.setup_s, solve_s=s.solve_s, bytes=s.bytes, gbps=s.gbps)
+
+
+class Batch:
+    """Iteration-level continuous batching over a context (nfield_batch_*):
+    `slots` GMRES columns advanced one Arnoldi step per step(); right-hand
+    sides join free slots and finished ones are taken between steps.  Holds
+    a reference to its NField, and is destroyed before it."""
+
+    def __init__(self, nf, slots, restart=50, maxit=1000, flexible=0, rtol=1e-8):
+        self.nf = nf
+        self.slots = slots
+        so = nfield_solve_opts(restart, maxit, flexible, rtol)
+        out = C.c_void_p()
+        rc = lib().nfield_batch_create(nf.ctx, slots, C.byref(so), C.byref(out))
+        if rc != 0:
+            raise NFieldError(rc, "nfield_batch_create")
+        self.b = out
+        self._done = (C.c_int32 * slots)()
+
+    def submit(self, slot, b, x0=None, stream=None):
+        """b, x0: float64 CUDA tensors of n elements (copied on the stream)."""
+        n = self.nf.n
+        bp, k = _dev(b, n, "b")
+        if k != 1:
+            raise ValueError("one right-hand side per slot")
+        xp = None
+        if x0 is not None:
+            xp, _ = _dev(x0, n, "x0")
+        rc = lib().nfield_batch_submit(self.b, slot, bp, xp, _stream(stream))
+        if rc != 0:
+            raise NFieldError(rc, "nfield_batch_submit")
+
+    def step(self, stream=None):
+        """One step; returns (slots finished in it, slots still working)."""
+        nd, na = C.c_int32(), C.c_int32()
+        rc = lib().nfield_batch_step(self.b, C.cast(self._done, C.c_void_p), C.byref(nd), C.byref(na),
+                                     _stream(stream))
+        if rc != 0:
+            raise NFieldError(rc, "nfield_batch_step")
+        return [int(self._done[q]) for q in range(nd.value)], na.value
+
+    def take(self, slot, x=None, stream=None):
+        """Copy the finished slot's solution into x (float64 CUDA tensor of n
+        elements, or None) and free the slot; returns its stats dict."""
+        xp = None
+        if x is not None:
+            xp, _ = _dev(x, self.nf.n, "x")
+        st = nfield_stats()
+        rc = lib().nfield_batch_take(self.b, slot, xp, C.byref(st), _stream(stream))
+        if rc != 0:
+            raise NFieldError(rc, "nfield_batch_take")
+        return _stats_dict(st)
+
+    def state(self, slot):
+        return lib().nfield_batch_state(self.b, slot)
+
+    def nbytes(self):
+        return lib().nfield_batch_bytes(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().nfield_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def nfield_update_values(ctx, i, j, val, stream=None):

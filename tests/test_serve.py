@@ -1,10 +1,12 @@
-"""Serving loop: batch formation and admission (CPU, fake contexts), and on
+"""Serving loop: column admission at step boundaries, key choice and memory
+admission (CPU, fake contexts), and on
 the GPU a replayed trace whose every request gives the same bits as a solo
 solve."""
 import numpy as np
 import pytest
 
 import nfgen
+from bench import SERVE_OPTS, SERVE_SPEC
 from paper_1605_01522_amd import serve
 
 
@@ -30,45 +32,94 @@ def _server(budget):
     srv.workers = 2
     srv.max_cols = 8
     srv.budget = budget
-    srv.ctx = [serve.OrderedDict() for _ in range(2)]
-    srv.busy_keys = [set(), set()]
-    srv.bytes_est = {}
-    srv.systems = {}
+    srv.max_wait_s = 0.02
+    srv.max_keys = 2
+    srv._init_state()
     srv.system_for_key = lambda key: _Sys(100 * key)
     return srv
 
 
-def _items(reqs):
-    return [serve.Served(dict(id=i, key=k, nrhs=c, arrival_s=0.0)) for i, (k, c) in enumerate(reqs)]
+def _items(reqs, t=0.0):
+    out = [serve.Served(dict(id=i, key=k, nrhs=c, arrival_s=t)) for i, (k, c) in enumerate(reqs)]
+    for it in out:
+        it.t_arrive = t
+    return out
 
 
-def test_batch_joins_same_key_up_to_max_columns():
+def _cached(srv, w, key, nbytes):
+    c = (_FakeCtx(nbytes), _FakeCtx(0))
+    srv.ctx[w][key] = c
+    return c
+
+
+def test_admission_fills_free_slots_in_arrival_order_by_column():
     srv = _server(1 << 40)
     items = _items([(16, 3), (32, 2), (16, 4), (16, 2), (32, 8)])
     waiting = list(range(5))
-    b = srv._take_batch(waiting, items, 0)
-    assert b == [0, 2]                       # 3 + 4 columns; the next (2) would exceed 8
-    assert waiting == [1, 3, 4]
-    b = srv._take_batch(waiting, items, 0)
-    assert b == [1]                          # 2 + 8 > 8
-    assert srv._take_batch(waiting, items, 0) == [3]
+    # 8 free slots: request 0's 3 columns, request 2's 4, one of request 3's
+    adm = srv._admit(waiting, items, 16, 8, 0)
+    assert adm == [(0, 0), (0, 1), (0, 2), (2, 0), (2, 1), (2, 2), (2, 3), (3, 0)]
+    assert waiting == [1, 3, 4] and items[3].next_col == 1
+    # a slot frees at a step boundary: request 3's second column joins
+    assert srv._admit(waiting, items, 16, 1, 0) == [(3, 1)]
+    assert waiting == [1, 4]
+    # a request partly admitted by worker 0 is not split to worker 1
+    items[1].worker = 0
+    items[1].next_col = 1
+    waiting = [1, 4]
+    assert srv._admit(waiting, items, 32, 8, 1) == [(4, c) for c in range(8)]
+    assert srv._pick_key([1], items, 1) is None
 
 
-def test_admission_evicts_idle_contexts_and_waits_when_full():
+def test_pick_key_takes_the_oldest_request_and_reserves_its_bytes():
+    srv = _server(1000)
+    srv.bytes_est = {16: 600, 32: 300}
+    items = _items([(32, 1), (16, 1)])
+    assert srv._pick_key([0, 1], items, 0) == (32, [])
+    assert srv.pending == {(0, 32): 300}
+    # the reservation counts: 300 reserved + 600 fits 1000, a second 300 would not
+    assert srv._pick_key([1], items, 1) == (16, [])
+    assert srv._cached_bytes() == 900
+    assert srv._pick_key([0], items, 1) is None
+
+
+def test_admission_evicts_idle_contexts_outside_the_lock_and_waits_when_full():
     srv = _server(1000)
     srv.bytes_est = {16: 600, 32: 600}
-    srv.ctx[0][16] = _FakeCtx(600)
+    c16 = _cached(srv, 0, 16, 600)
     items = _items([(32, 1)])
-    waiting = [0]
-    # an idle context is evicted to make room
-    assert srv._take_batch(waiting, items, 1) == [0]
-    assert 16 not in srv.ctx[0]
+    # an idle context is handed back for eviction (closed by the caller)
+    key, victims = srv._pick_key([0], items, 1)
+    assert key == 32 and victims == [c16] and 16 not in srv.ctx[0] and not c16[0].closed
     # a busy context is not evicted: the request waits
-    srv.ctx[0][16] = _FakeCtx(600)
+    srv = _server(1000)
+    srv.bytes_est = {16: 600, 32: 600}
+    _cached(srv, 0, 16, 600)
     srv.busy_keys[0].add(16)
-    items = _items([(32, 1)])
-    waiting = [0]
-    assert srv._take_batch(waiting, items, 1) is None and waiting == [0]
+    assert srv._pick_key([0], _items([(32, 1)]), 1) is None and 16 in srv.ctx[0]
+
+
+def test_a_context_larger_than_the_budget_is_an_error():
+    srv = _server(1000)
+    srv.bytes_est = {16: 5000}
+    with pytest.raises(MemoryError):
+        srv._pick_key([0], _items([(16, 1)]), 0)
+
+
+def test_starving_counts_keys_the_worker_does_not_serve():
+    srv = _server(1 << 40)
+    items = _items([(16, 1), (32, 1)], t=0.0)
+    assert not srv._starving([1], items, {16}, now=0.01)
+    assert srv._starving([1], items, {16}, now=0.03)
+    assert not srv._starving([1], items, {16, 32}, now=0.03)
+
+
+def test_pick_key_skips_keys_the_worker_serves():
+    srv = _server(1 << 40)
+    items = _items([(16, 1), (32, 1)])
+    _cached(srv, 0, 16, 10)
+    assert srv._pick_key([0, 1], items, 0) == (16, [])
+    assert srv._pick_key([0, 1], items, 0, held={16}) == (32, [])
 
 
 @pytest.mark.gpu
@@ -80,14 +131,14 @@ def test_served_trace_matches_solo_bitwise():
     for r in trace:
         r["key"] = r["grid"]
     systems = {g: nfgen.tsi2d(nel=g) for g in grids}
-    opts = dict(sweeps=2, order="bwd")
-    srv = serve.Server(lambda g: systems[g], "BGS(AMG)", opts, workers=3, max_cols=8)
+    srv = serve.Server(lambda g: systems[g], SERVE_SPEC, SERVE_OPTS, workers=3, max_cols=8)
     items = srv.run(trace, lambda req: nfgen.request_rhs(req, systems[req["grid"]].n), time_scale=1.0)
     summ = serve.summarize(items)
     print(summ, flush=True)
     assert summ["all_converged"]
     assert max(it.batch_cols for it in items) > 1        # some requests shared a launch
-    solo = {g: NField(systems[g].fields, systems[g].blocks, "BGS(AMG)", hier_fp32=1, **opts) for g in grids}
+    assert any(it.joined_running for it in items)       # some joined a running batch
+    solo = {g: NField(systems[g].fields, systems[g].blocks, SERVE_SPEC, hier_fp32=1, **SERVE_OPTS) for g in grids}
     for it in items:
         g = it.req["grid"]
         B = torch.tensor(nfgen.request_rhs(it.req, systems[g].n), device="cuda")
