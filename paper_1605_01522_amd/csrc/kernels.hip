@@ -1414,13 +1414,25 @@ __device__ __forceinline__ void sgs_node(int t, int sub, int b, const int* __res
   }
 }
 
+// Workgroups go to the 8 XCDs, each with its own L2, round-robin by
+// workgroup index.  xcd_block maps the hardware index b (of nb) to a logical
+// one under which XCD k takes the k-th contiguous eighth of the logical
+// range (a bijection: XCD k holds the b = k (mod 8)).  A colour's node list
+// is in node order, so an XCD then relaxes one slab of nodes, whose gathered
+// x entries share its L2 (measured on the FSI-like fine fluid level: 7.9 ->
+// 7.5 us per colour launch; plain SpMV rows got slower with it).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, k = b & 7, i = b >> 3;
+  return k * q + min(k, r) + i;
+}
+
 template <int G, int B2, int NR, class T>
 __global__ __launch_bounds__(256) void k_sgs_color(int nnodes, const int* __restrict__ nodes, const int* __restrict__ cptr,
                                                    int b, const int* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
                                                    int64_t ldr, T* __restrict__ x, int64_t ldx, int nrhs) {
   constexpr int NG = G * B2;
-  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   const int t = gid / NG;
   if (t >= nnodes) return;
   sgs_node<G, B2, NR, T>(t, gid % NG, b, nodes, cptr, col, val, dinv, omega, rhs, ldr, x, ldx, nrhs);
