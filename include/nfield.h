@@ -116,7 +116,12 @@ typedef struct {
   int32_t simplec_mode;    /* SIMPLE diagonal: 0 sum_j|a_ij|, 1 |sum_j a_ij|, 2 a_ii; 0 */
   const int32_t *split;    /* field -> SIMPLE group (0 predictor, 1 Schur); NULL: last field */
   int32_t schur_direct_max;/* Schur complements up to this size are inverted densely; 5000 */
-  int32_t hier_fp32;       /* 1: store and run the AMG hierarchies in FP32 (precision form) */
+  int32_t hier_fp32;       /* 1: store and run the AMG hierarchies in FP32 (precision form).
+                              The FP32 tree keeps FP32 copies of the input blocks it reads;
+                              the input blocks' FP64 values are then released (the merged
+                              FP64 operator of GMRES holds the same values) and gathered
+                              back from it at each rebuild, so a rebuild briefly holds
+                              them again. */
   uint64_t seed;           /* MIS-2 keys and power-iteration start vectors */
   int32_t graphs;          /* 1: the preconditioner's kernels are captured once (per column
                               count, after every rebuild) into a HIP graph and replayed;
@@ -298,9 +303,10 @@ int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, 
 size_t nfield_footprint_bytes(const nfield_ctx *ctx);
 /* Device bytes the preconditioner itself holds after the last setup or
  * rebuild: hierarchies (coarse blocks, transfers), smoother data, Schur
- * approximations, coarse inverses, FP32 copies of the input blocks (precision
- * form) and the preconditioner's temporaries; not the input blocks, the
- * Krylov workspace or the cache. */
+ * approximations, coarse inverses, FP32 copies of the input blocks that an
+ * FP32 solver reads (precision form) and the preconditioner's temporaries;
+ * not the input blocks (nor the FP64 input values the precision form
+ * releases), the Krylov workspace or the cache. */
 size_t nfield_precond_bytes(const nfield_ctx *ctx);
 int64_t nfield_size(const nfield_ctx *ctx);             /* n = sum of field sizes */
 void nfield_destroy(nfield_ctx *ctx);

@@ -331,7 +331,10 @@ static void spmv_nr(int G, const DCsr& A, const SpmvArgs<T>& a, const T* val, hi
 }
 
 template <class T> static const T* csr_values(const DCsr& A);
-template <> const double* csr_values<double>(const DCsr& A) { return A.val.p; }
+template <> const double* csr_values<double>(const DCsr& A) {
+  if (!A.val.p && A.nnz > 0) throw NfError(NFIELD_EINVAL, "FP64 values of a matrix were released (FP32 hierarchy)");
+  return A.val.p;
+}
 template <> const float* csr_values<float>(const DCsr& A) {
   if (!A.val32.p && A.nnz > 0) throw NfError(NFIELD_EINVAL, "FP32 values of a matrix were not prepared");
   return A.val32.p;

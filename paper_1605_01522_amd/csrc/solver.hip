@@ -72,6 +72,14 @@ static void prepare_fp32(BlockMat& A, hipStream_t s) {
   for (auto& b : A.blk)
     if (b && !b->val32.p) make_fp32(*b, s);
 }
+// FP32 copy of block (i, j) for a solver of precision T that reads it
+// (input blocks get one only when some FP32 solver uses them)
+template <class T>
+static void need_fp32(const BlockMat& A, int i, int j, hipStream_t s) {
+  if (sizeof(T) != sizeof(float)) return;
+  DCsr* b = const_cast<DCsr*>(A.at(i, j));
+  if (b && !b->val32.p) make_fp32(*b, s);
+}
 
 // ================================================================ solvers
 template <class T>
@@ -836,6 +844,7 @@ struct nfield_ctx {
   std::unique_ptr<nf::Solver<float>> root32;
   nf::Spec spec;
   std::vector<std::shared_ptr<nf::DBuf<int>>> gpos;   // per block: entry -> position in Aglob
+  bool inputs_dropped = false;   // FP32 tree built: input blocks hold no FP64 values
   nf::DBuf<float> r32, z32;
   double setup_s = 0.0;
   size_t tree_bytes = 0;   // live device bytes the preconditioner tree holds
@@ -1219,6 +1228,7 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     NF_HIP(hipMemcpyAsync(&z, zf.p, sizeof(int), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
     NF_CHECK(z == 0, NFIELD_ESINGULAR, "DDGS: zero diagonal entry");
+    need_fp32<T>(A, f0, f0, s);
     auto sm = std::make_unique<DdgsD<T>>();
     sm->setup(Aii, F[f0].bs, dinv.p, sp.omega > 0.0 ? sp.omega : 1.0, sp.steps > 0 ? sp.steps : 1, C.o.seed, s,
               nullptr, nullptr, 0, nullptr, 0, sp.ddmin);
@@ -1243,6 +1253,11 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->f1 = f1;
     S->sweeps = sp.sweeps > 0 ? sp.sweeps : C.o.sweeps;
     S->order = sp.order >= 0 ? sp.order : C.o.order;
+    // the sweep reads the coupling blocks; the residual of later sweeps all
+    // blocks (before the children, which may be built concurrently)
+    for (int i = f0; i < f1; ++i)
+      for (int j = f0; j < f1; ++j)
+        if (i != j || S->sweeps > 1) need_fp32<T>(A, i, j, s);
     int mx = 0;
     std::vector<BuildTask<T>> tasks;
     for (int i = f0; i < f1; ++i) {
@@ -1273,6 +1288,10 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
     S->f1 = f1;
     S->g = g;
     S->sweeps = sp.sweeps > 0 ? sp.sweeps : 1;
+    // the step reads A_gj and A_jg; the residual of later sweeps all blocks
+    for (int i = f0; i < f1; ++i)
+      for (int j = f0; j < f1; ++j)
+        if (S->sweeps > 1 || (i == g) != (j == g)) need_fp32<T>(A, i, j, s);
     const int n1 = o[g] - o[f0], n2 = A.size[g];
     DBuf<double> dt;
     auto Sm = std::make_shared<DCsr>();
@@ -1714,6 +1733,15 @@ static size_t tree_live(const nfield_ctx& C) {
 }
 
 // (re)build the preconditioner tree from the device-resident blocks
+__global__ void k_scatter_vals(const double* v, const int* pos, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[pos[i]] = v[i];
+}
+__global__ void k_gather_vals(const double* g, const int* pos, int64_t n, double* v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = g[pos[i]];
+}
+
 static void build_tree(nfield_ctx& C, hipStream_t s) {
   C.drop_graphs();
   C.root64.reset();
@@ -1724,12 +1752,23 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
   g_hsink = &C.hiers;
   g_osink = &C.owned;
   g_mbuf_cols = C.o.max_rhs;
+  if (C.inputs_dropped) {   // the input blocks' FP64 values, from the merged operator
+    for (size_t k = 0; k < C.A.blk.size(); ++k) {
+      DCsr* b = C.A.blk[k].get();
+      if (!b || b->nnz == 0) continue;
+      NF_CHECK(C.gpos[k] != nullptr, NFIELD_EINVAL, "rebuild: a block without its merged positions");
+      b->val.alloc(b->nnz);
+      hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)((b->nnz + 255) / 256)), dim3(256), 0, s, C.Aglob.val.p,
+                         C.gpos[k]->p, b->nnz, b->val.p);
+    }
+    NF_HIP(hipGetLastError());
+    C.inputs_dropped = false;
+  }
   for (auto& b : C.A.blk)   // FP32 copies of the inputs count as the tree's
     if (b) b->val32.release();
   const size_t live0 = tree_live(C);
   if (C.o.hier_fp32) {
-    for (auto& b : C.A.blk)
-      if (b) make_fp32(*b, s);
+    // FP32 copies of the input blocks are made where an FP32 solver reads them
     C.root32 = build<float>(C, C.spec, C.A, C.F, 0, C.N, s);
     // the FP32 tree runs on the FP32 copies alone: the FP64 values of the
     // matrices it built (coarse levels, transfers, Schur approximations)
@@ -1747,16 +1786,18 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
     for (auto& B : C.owned)
       for (auto& b : B->blk)
         if (b && b->val32.p) b->val.free_now();
+    C.tree_bytes = tree_live(C) - live0;
+    // the input blocks' FP64 values are the merged operator's (which FP64
+    // GMRES keeps): released, and gathered back from it at the next rebuild
+    for (auto& b : C.A.blk)
+      if (b && b->nnz > 0) b->val.free_now();
+    C.inputs_dropped = true;
   } else {
     C.root64 = build<double>(C, C.spec, C.A, C.F, 0, C.N, s);
+    C.tree_bytes = tree_live(C) - live0;
   }
-  C.tree_bytes = tree_live(C) - live0;
 }
 
-__global__ void k_scatter_vals(const double* v, const int* pos, int64_t n, double* out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[pos[i]] = v[i];
-}
 
 // ------------------------------------------------ allocation-free workspace
 // The Krylov workspace of nfield_gmres_solve_noalloc lives in this static
@@ -2502,13 +2543,22 @@ nfield_status nfield_update_values(nfield_ctx* ctx, int32_t i, int32_t j, const 
   hipStream_t s = (hipStream_t)hip_stream;
   try {
     DCsr& B = *ctx->A.blk[(size_t)i * ctx->N + j];
-    NF_HIP(hipMemcpyAsync(B.val.p, val, sizeof(double) * B.nnz, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    // with the FP32 tree the block holds no FP64 values: the new ones go
+    // through a buffer of their own into the merged operator alone
+    DevPool* prev = g_pool;
+    g_pool = &ctx->pool;
+    DBuf<double> tmp;
+    if (ctx->inputs_dropped && B.nnz > 0) tmp.alloc(B.nnz);
+    g_pool = prev;
+    double* dst = ctx->inputs_dropped ? tmp.p : B.val.p;
+    NF_HIP(hipMemcpyAsync(dst, val, sizeof(double) * B.nnz, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     const auto& pos = ctx->gpos[(size_t)i * ctx->N + j];
     if (B.nnz > 0)
-      hipLaunchKernelGGL(k_scatter_vals, dim3((unsigned)((B.nnz + 255) / 256)), dim3(256), 0, s, B.val.p, pos->p, B.nnz,
+      hipLaunchKernelGGL(k_scatter_vals, dim3((unsigned)((B.nnz + 255) / 256)), dim3(256), 0, s, dst, pos->p, B.nnz,
                          ctx->Aglob.val.p);
     NF_HIP(hipGetLastError());
-    if (!on_device) NF_HIP(hipStreamSynchronize(s));
+    if (!on_device || tmp.p) NF_HIP(hipStreamSynchronize(s));
+    if (tmp.p) tmp.free_now();
     return NFIELD_OK;
   } catch (NfError& e) {
     return fail(e);
