@@ -179,6 +179,31 @@ def test_precision_form_fp32_hierarchy(dev):
     assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
 
 
+@pytest.mark.parametrize("nel", [16, 64])
+def test_serving_configuration_parity(dev, nel):
+    """The configuration the serving form runs (BGS(AMG), two backward
+    sweeps, Chebyshev over [lambda/8, 1.1 lambda]) against the oracle: the
+    FP64 preconditioner application, and the FP32-hierarchy flexible solve
+    the server uses against the FP64 oracle solution."""
+    from bench import SERVE_OPTS, SERVE_SPEC
+    _say(f"case serving configuration nel={nel}")
+    s = nfgen.tsi2d(nel=nel, seed=0)
+    o = oracle.Oracle(s.fields, s.blocks, SERVE_SPEC, **SERVE_OPTS)
+    g = _gpu(s, SERVE_SPEC, **SERVE_OPTS)
+    r = np.random.default_rng(5).standard_normal(s.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    g32 = _gpu(s, SERVE_SPEC, hier_fp32=1, **SERVE_OPTS)
+    x, st = g32.gmres_solve(torch.tensor(s.rhs[0], device=dev), flexible=1, rtol=1e-8)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8)
+    res = np.linalg.norm(s.rhs[0] - s.assembled() @ x) / np.linalg.norm(s.rhs[0])
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"  fp32 hierarchy iters {st[0]['iters']} (fp64 oracle {so['iters']}), relres {res:.2e}, err {err:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
+
+
 # ------------------------------------------------------------ edge cases
 def test_single_level_is_exact(dev):
     _say("case single level")
