@@ -321,20 +321,19 @@ static std::vector<int> dd_subdomains(const Graph& G, uint64_t seed, int* n_sub)
   return aggregate(G, st, n_sub);
 }
 
-// Greedy colouring of the node graph in node order: node u takes the
-// smallest colour not used by its neighbours of smaller index.  (On a
+// Greedy colouring: the nodes in the given order each take the smallest
+// colour that none of their already coloured neighbours has.  The node graph
+// is symmetric, so no two neighbours share a colour.  (In node order on a
 // structured 27-point stencil numbered lexicographically this gives 8
-// colours.)  The node graph is symmetric, so every neighbour of smaller
-// index is seen from u and no two neighbours share a colour.
-static std::vector<int> color_nodes(const Graph& G, uint64_t /*seed*/, int* ncolors) {
-  const int n = G.n;
-  std::vector<int> color(n, -1);
+// colours.)
+static std::vector<int> greedy_colors(const Graph& G, const std::vector<int>& order, int* ncolors) {
+  std::vector<int> color(G.n, -1);
   int nc = 0;
-  for (int u = 0; u < n; ++u) {
+  for (int u : order) {
     std::vector<char> used(G.ptr[u + 1] - G.ptr[u] + 1, 0);
     for (int64_t p = G.ptr[u]; p < G.ptr[u + 1]; ++p) {
-      const int v = G.adj[p];
-      if (v < u && color[v] < (int)used.size()) used[color[v]] = 1;
+      const int c = color[G.adj[p]];
+      if (c >= 0 && c < (int)used.size()) used[c] = 1;
     }
     int c = 0;
     while (used[c]) ++c;
@@ -342,6 +341,67 @@ static std::vector<int> color_nodes(const Graph& G, uint64_t /*seed*/, int* ncol
     nc = std::max(nc, c + 1);
   }
   *ncolors = nc;
+  return color;
+}
+
+// Smallest-last order (Matula and Beck): repeatedly remove a node of least
+// degree in the graph that remains, and colour in the reverse of the removal
+// order.  Ties: the nodes of one degree form a stack; at the start every
+// node is pushed in ascending number onto the stack of its degree, a node
+// whose degree drops (a neighbour was removed; neighbours visited in
+// adjacency order) is pushed onto its new degree's stack, and the node
+// removed is the top of the least non-empty stack (entries of nodes removed
+// or moved since are skipped).
+static std::vector<int> smallest_last_order(const Graph& G) {
+  const int n = G.n;
+  std::vector<int> deg(n, 0);
+  int maxd = 0;
+  for (int u = 0; u < n; ++u) {
+    for (int64_t p = G.ptr[u]; p < G.ptr[u + 1]; ++p) deg[u] += G.adj[p] != u;
+    maxd = std::max(maxd, deg[u]);
+  }
+  std::vector<std::vector<int>> stack(maxd + 1);
+  for (int u = 0; u < n; ++u) stack[deg[u]].push_back(u);
+  std::vector<char> gone(n, 0);
+  std::vector<int> removal;
+  int d = 0;
+  while ((int)removal.size() < n) {
+    int u = -1;
+    while (u < 0) {
+      while (stack[d].empty()) ++d;
+      const int t = stack[d].back();
+      stack[d].pop_back();
+      if (!gone[t] && deg[t] == d) u = t;
+    }
+    gone[u] = 1;
+    removal.push_back(u);
+    for (int64_t p = G.ptr[u]; p < G.ptr[u + 1]; ++p) {
+      const int v = G.adj[p];
+      if (v == u || gone[v]) continue;
+      --deg[v];
+      stack[deg[v]].push_back(v);
+      d = std::min(d, deg[v]);
+    }
+  }
+  return std::vector<int>(removal.rbegin(), removal.rend());
+}
+
+// Colouring of a node graph for the multicolour smoothers: greedy in node
+// order; graphs of at most COLOR_SL_MAX nodes are also coloured greedily in
+// smallest-last order and keep that colouring when it has fewer colours.
+constexpr int COLOR_SL_MAX = 32768;
+static std::vector<int> color_nodes(const Graph& G, uint64_t /*seed*/, int* ncolors) {
+  std::vector<int> natural(G.n);
+  for (int u = 0; u < G.n; ++u) natural[u] = u;
+  std::vector<int> color = greedy_colors(G, natural, ncolors);
+  if (G.n > 0 && G.n <= COLOR_SL_MAX) {
+    int nsl = 0;
+    std::vector<int> c2 = greedy_colors(G, smallest_last_order(G), &nsl);
+    if (nsl < *ncolors) {
+      color = c2;
+      *ncolors = nsl;
+    }
+  }
   return color;
 }
 

@@ -1315,8 +1315,101 @@ __global__ void k_max_wait(int n, const int* __restrict__ wait, int* out) {
   if (i < n) atomicMax(out, wait[i]);
 }
 
+// ---- small graphs on the host: coarse levels have few nodes with many
+// neighbours, where the order of a greedy colouring matters.  The colouring
+// is greedy in node order (as on the device) and greedy in smallest-last
+// order, and the one with fewer colours is kept (node order on ties).
+// Smallest-last (Matula-Beck): nodes leave the graph one at a time, always
+// one of least remaining degree, and are coloured in the reverse order.
+// Ties follow stacks per degree: all nodes pushed in ascending number onto
+// the stack of their degree at the start; a node whose degree drops (its
+// neighbour left; neighbours in adjacency order) pushed onto its new
+// degree's stack; the next node to leave is the top of the least non-empty
+// stack, skipping entries of nodes that have left or moved on.
+constexpr int COLOR_HOST_MAX = 32768;
+
+static int host_greedy(int n, const std::vector<int>& gp, const std::vector<int>& ga, const std::vector<int>& order,
+                       int maxdeg, std::vector<int>& col) {
+  col.assign(n, -1);
+  std::vector<int> stamp(maxdeg + 2, -1);
+  int nc = 0;
+  for (int i = 0; i < n; ++i) {
+    const int u = order[i];
+    for (int p = gp[u]; p < gp[u + 1]; ++p)
+      if (col[ga[p]] >= 0) stamp[col[ga[p]]] = i;
+    int c = 0;
+    while (stamp[c] == i) ++c;
+    col[u] = c;
+    nc = std::max(nc, c + 1);
+  }
+  return nc;
+}
+
+static void host_smallest_last(int n, const std::vector<int>& gp, const std::vector<int>& ga, int maxdeg,
+                               std::vector<int>& deg, std::vector<int>& order) {
+  std::vector<int> head(maxdeg + 1, -1), ent_node, ent_next;
+  ent_node.reserve((size_t)n + ga.size());
+  ent_next.reserve((size_t)n + ga.size());
+  auto push = [&](int d, int v) {
+    ent_node.push_back(v);
+    ent_next.push_back(head[d]);
+    head[d] = (int)ent_node.size() - 1;
+  };
+  for (int u = 0; u < n; ++u) push(deg[u], u);
+  std::vector<char> gone(n, 0);
+  order.assign(n, -1);
+  int d = 0;
+  for (int k = 0; k < n; ++k) {
+    int u = -1;
+    while (u < 0) {
+      while (head[d] < 0) ++d;
+      const int e = head[d];
+      head[d] = ent_next[e];
+      const int t = ent_node[e];
+      if (!gone[t] && deg[t] == d) u = t;
+    }
+    gone[u] = 1;
+    order[n - 1 - k] = u;   // colouring order = reverse removal order
+    for (int p = gp[u]; p < gp[u + 1]; ++p) {
+      const int v = ga[p];
+      if (v == u || gone[v]) continue;
+      push(--deg[v], v);
+      d = std::min(d, deg[v]);
+    }
+  }
+}
+
+static int color_nodes_host(int n, const int* gp_dev, const int* ga_dev, int* color, hipStream_t s) {
+  std::vector<int> gp(n + 1);
+  NF_HIP(hipMemcpyAsync(gp.data(), gp_dev, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  std::vector<int> ga(gp[n]);
+  if (gp[n] > 0) NF_HIP(hipMemcpyAsync(ga.data(), ga_dev, sizeof(int) * gp[n], hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  std::vector<int> deg(n, 0), order(n);
+  int maxdeg = 0;
+  for (int u = 0; u < n; ++u) {
+    for (int p = gp[u]; p < gp[u + 1]; ++p) deg[u] += ga[p] != u;
+    maxdeg = std::max(maxdeg, deg[u]);
+  }
+  for (int u = 0; u < n; ++u) order[u] = u;
+  std::vector<int> col, col2;
+  int nc = host_greedy(n, gp, ga, order, maxdeg, col);
+  host_smallest_last(n, gp, ga, maxdeg, deg, order);
+  const int nc2 = host_greedy(n, gp, ga, order, maxdeg, col2);
+  if (nc2 < nc) {
+    nc = nc2;
+    col.swap(col2);
+  }
+  NF_CHECK(nc <= 256, NFIELD_ENOMEM, "colouring needs more than 256 colours");
+  NF_HIP(hipMemcpyAsync(color, col.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  NF_HIP(hipStreamSynchronize(s));   // the host array is freed on return
+  return nc;
+}
+
 int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* color, hipStream_t s) {
   if (n == 0) return 0;
+  if (n <= COLOR_HOST_MAX) return color_nodes_host(n, gp, ga, color, s);
   const int g = cdiv(n, 256);
   DBuf<int> wait(n), fa(n), fb(n), cnt(5), rcnt(n + 1), rptr(n + 1), rcur(n + 1);
   fill<int>(color, -1, n, s);

@@ -123,8 +123,9 @@ void slot_scatter(const double* in, int64_t n, const int* act, const int* jv, in
                   hipStream_t s);
 
 // ------------------------------------------------------------ multicolour Gauss-Seidel
-// greedy colouring of a node graph in node order; returns the number of
-// colours and fills color[node]
+// greedy colouring of a node graph in node order (graphs of at most 32,768
+// nodes: also in smallest-last order, keeping the one with fewer colours);
+// returns the number of colours and fills color[node]
 int color_nodes(int nnode, const int* gptr, const int* gadj, uint64_t seed, int* color, hipStream_t s);
 // row bounds of the listed nodes' rows in list order: cptr[t (b+1) + q] =
 // ptr[nodes[t] b + q] for q = 0..b (cptr holds nnodes (b+1) ints)

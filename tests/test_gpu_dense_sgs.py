@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 SPEC = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 
 
-@pytest.mark.parametrize("n,layers,steps", [(16, 4, 1), (16, 4, 2)])
+@pytest.mark.parametrize("n,layers,steps", [(20, 4, 1), (20, 4, 2)])
 def test_dense_sweep_matches_oracle(n, layers, steps):
     assert torch.cuda.is_available()
     from paper_1605_01522_amd import NField, nfield

@@ -578,19 +578,68 @@ def test_errors():
 
 
 # --------------------------------------------------- multicolour Gauss-Seidel
-@pytest.mark.parametrize("name,make", GRAPHS)
+def _crown_graph(k):
+    """K_{k,k} minus a perfect matching, numbered u_0 v_0 u_1 v_1 ...: greedy
+    in node order needs k colours, the graph is 2-colourable."""
+    n = 2 * k
+    M = np.zeros((n, n), bool)
+    for i in range(k):
+        for j in range(k):
+            if i != j:
+                M[2 * i, 2 * j + 1] = M[2 * j + 1, 2 * i] = True
+    gp = np.concatenate([[0], np.cumsum(M.sum(1))]).astype(np.int64)
+    ga = np.concatenate([np.nonzero(M[u])[0] for u in range(n)]).astype(np.int32)
+    return gp, ga
+
+
+def _natural_greedy(adj):
+    n = adj.shape[0]
+    col = -np.ones(n, int)
+    for u in range(n):
+        used = {col[v] for v in np.nonzero(adj[u])[0] if v < u}
+        col[u] = next(c for c in range(n + 1) if c not in used)
+    return col
+
+
+def _degeneracy(adj):
+    """max over the removal sequence of the least remaining degree (the same
+    for every tie-breaking)"""
+    alive = np.ones(adj.shape[0], bool)
+    deg = adj.sum(1).astype(int)
+    worst = 0
+    while alive.any():
+        cand = np.nonzero(alive)[0]
+        u = cand[np.argmin(deg[cand])]
+        worst = max(worst, deg[u])
+        alive[u] = False
+        deg -= adj[u].astype(int)
+    return worst
+
+
+@pytest.mark.parametrize("name,make", GRAPHS + [("crown-40", lambda: _crown_graph(20))])
 def test_coloring_valid_and_greedy(name, make):
+    """Valid (no coupled pair shares a colour); greedy in some order (every
+    node sees every smaller colour among its neighbours); at most as many
+    colours as the node-order greedy colouring and at most degeneracy + 1
+    (the smallest-last bound); the node-order colouring itself when that is
+    not beaten."""
     gp, ga = make()
     n = len(gp) - 1
     col, nc = oracle.color_nodes(gp, ga, 3)
     adj, _ = _dist2(gp, ga, n)
+    np.fill_diagonal(adj, False)
     assert col.min() == 0 and col.max() == nc - 1
     i, j = np.nonzero(adj)
     assert np.all(col[i] != col[j])
-    # greedy: every colour below a node's own is taken by a smaller-index neighbour
     for u in range(n):
-        lower = {col[v] for v in np.nonzero(adj[u])[0] if v < u}
-        assert all(c in lower for c in range(col[u])) and col[u] not in lower
+        seen = {col[v] for v in np.nonzero(adj[u])[0]}
+        assert all(c in seen for c in range(col[u]))
+    nat = _natural_greedy(adj)
+    assert nc <= min(nat.max() + 1, _degeneracy(adj) + 1)
+    if nc == nat.max() + 1:
+        assert np.array_equal(col, nat)
+    if name == "crown-40":
+        assert nat.max() + 1 == 20 and nc == 2
 
 
 @pytest.mark.parametrize("b", [1, 2])
