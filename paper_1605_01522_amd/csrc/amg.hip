@@ -228,12 +228,30 @@ void build_hierarchy(Hierarchy& H, const BlockMat& A0, const std::vector<FieldDe
           };
           DCsr P, At, AtP, PR;
           pg_side(Aii, LB.hasA[i] ? &LB.A[i] : nullptr, AP, P);
-          transpose(Aii, At, s);
-          times_blocks(At, nullptr, Pt, AtP);
-          pg_side(At, nullptr, AtP, PR);
+          // A^T (and below R) through the block forms where the products
+          // run on blocks: the same entries as the scalar transposes
+          DBsr Atb;
+          const DBsr* atb = nullptr;
+          if (LB.hasA[i]) {
+            bsr_transpose(LB.A[i], Atb, s);
+            atb = &Atb;
+          } else {
+            transpose(Aii, At, s);
+          }
+          times_blocks(At, atb, Pt, AtP);
+          pg_side(At, atb, AtP, PR);
           *L.P[i] = std::move(P);
           L.R[i] = std::make_unique<DCsr>();
-          transpose(PR, *L.R[i], s);
+          if (o.block_products && L.bs[i] * k >= 2) {
+            DBsr PRb;
+            csr_to_bsr(PR, L.bs[i], k, PRb, s);
+            bsr_transpose(PRb, LB.R[i], s);
+            bsr_to_csr(LB.R[i], *L.R[i], s);
+            csr_to_bsr(*L.P[i], L.bs[i], k, LB.P[i], s);
+            LB.hasP[i] = 1;
+          } else {
+            transpose(PR, *L.R[i], s);
+          }
         } else {
           DBuf<double> srow(n);
           const double omega = 4.0 / (3.0 * L.lambda[i]);
