@@ -261,7 +261,9 @@ def tsi_config0(steps=50, warmup=5, seed=0):
     GMRES(50) rtol 1e-8, two backward BGS sweeps with per-field SA-AMG,
     degree-2 Chebyshev, coarse direct solves up to 200 dofs): BGS(AMG), and
     the monolithic AMG(BGS) whose coarse levels carry the coupling blocks
-    R_i A_ij P_j; median of `steps` steps (rebuild + solve) each."""
+    R_i A_ij P_j, and the paper's single-level comparator BGS(DD(GS))
+    (omega 0.79, the level's aggregates as subdomains); median of `steps`
+    steps (rebuild + solve) each."""
     import numpy as np
     import torch
     import nfgen
@@ -270,7 +272,7 @@ def tsi_config0(steps=50, warmup=5, seed=0):
     b = torch.tensor(s.rhs[0], device="cuda")
     A = s.assembled()
     out = {}
-    for spec in ("BGS(AMG)", "AMG(BGS)"):
+    for spec in ("BGS(AMG)", "AMG(BGS)", "BGS(DDGS[omega=0.79,ddmin=1])"):
         g = NField(s.fields, s.blocks, spec, sweeps=2, order="bwd", max_rhs=1)
         x = torch.zeros_like(b)
         ts, st = [], None
@@ -289,7 +291,8 @@ def tsi_config0(steps=50, warmup=5, seed=0):
                    solves_per_s=round(len(ts) / sum(ts), 2),
                    setup_ms=round(1e3 * st[0]["setup_s"], 3), solve_ms=round(1e3 * st[0]["solve_s"], 3),
                    relres=float(np.linalg.norm(s.rhs[0] - A @ xs) / np.linalg.norm(s.rhs[0])),
-                   levels=g.nlevels(0), op_complexity=[round(g.complexity(h)[0], 3) for h in range(g.hier_count())])
+                   levels=g.nlevels(0) if g.hier_count() else 0,
+                   op_complexity=[round(g.complexity(h)[0], 3) for h in range(g.hier_count())])
         if spec == "AMG(BGS)":
             rec["coupled_coarse_nnz"] = [[g.matrix(0, l, "A", 0, 1).nnz, g.matrix(0, l, "A", 1, 0).nnz]
                                          for l in range(g.nlevels(0))]

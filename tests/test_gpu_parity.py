@@ -133,7 +133,8 @@ def test_precond_apply_parity(dev, spec):
 
 # ------------------------------------------------------------ end to end
 @pytest.mark.parametrize("nel,seed,spec", [(32, 0, "BGS(AMG)"), (32, 1, "BGS(AMG)"), (13, 2, "BGS(AMG)"),
-                                           (32, 0, "AMG(BGS)"), (32, 0, "SIMPLE(AMG;AMG)")])
+                                           (32, 0, "AMG(BGS)"), (32, 0, "SIMPLE(AMG;AMG)"),
+                                           (32, 0, "BGS(DDGS[omega=0.79,ddmin=1])")])
 def test_gmres_solution_parity(dev, nel, seed, spec):
     _say(f"case gmres {spec} nel={nel} seed={seed}")
     s = nfgen.tsi2d(nel=nel, seed=seed, nrhs=2)
