@@ -292,7 +292,9 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
  * launch (tiny levels with many colours); 8 = a launch per colour, one
  * workgroup per node (long rows); 9 = the whole symmetric sweep of a small
  * many-colour level as one dense affine map x <- S x + Q b; 10 = a DD(GS)
- * sweep (one workgroup per subdomain); launches, total milliseconds, total
+ * sweep (one workgroup per subdomain); 11 = a launch per colour from the
+ * block copy of a level made of dense 2 x 2 or 3 x 3 node blocks; launches,
+ * total milliseconds, total
  * algorithmic bytes (matrix once, operand once, epilogue streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);

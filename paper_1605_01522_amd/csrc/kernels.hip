@@ -1863,6 +1863,172 @@ void dense_sweep_apply(const T* X, int n, const T* x, int64_t ldx, const T* rb, 
     hipLaunchKernelGGL((k_dense_sweep_apply<NRMAX, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, x, ldx, rb, ldb, y, ldy, nrhs,
                        with_x ? 1 : 0);
 }
+// ---- levels made of dense B x B node blocks (elasticity, B = 2 or 3): a
+// block copy for the colour kernel, one column node per block and its B*B
+// values stored entry-major (value e of every block, then value e + 1), so
+// that the lanes of a node, which take consecutive blocks, read consecutive
+// addresses; the block row bounds of each node in colour order.
+// A matrix is made of dense b x b blocks when every row of a node holds the
+// same block columns in full: row r of node u has the length of the node's
+// first row, and its entries are, block by block, the b consecutive columns
+// of the block column that the first row has there.  Then the entries before
+// node u number b^2 times the blocks before it.
+constexpr int BSR_COPY_LANES = 16;   // lanes per row of the check and the copy
+__global__ void k_bsr_dense_check(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                                  int* __restrict__ bad) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = (int)(gid / BSR_COPY_LANES), lane = (int)(gid % BSR_COPY_LANES);
+  if (r >= nr) return;
+  const int u = r / b;
+  const int f0 = ptr[u * b], len = ptr[u * b + 1] - f0, p0 = ptr[r];
+  bool ok = len % b == 0 && ptr[r + 1] - p0 == len && f0 % (b * b) == 0;
+  for (int k = lane * b; ok && k < len; k += BSR_COPY_LANES * b) {
+    const int c0 = col[f0 + k];
+    ok = c0 % b == 0;
+    for (int c = 0; ok && c < b; ++c) ok = col[p0 + k + c] == c0 + c;
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+// the block copy of a matrix that passed the check: block (u, k) is number
+// ptr[u b] / b^2 + k; value (q, c) of it goes to bval[(q b + c) nblk + blk]
+template <class T>
+__global__ void k_bsr_dense_copy(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
+                                 const double* __restrict__ val, int64_t nblk, int* __restrict__ bcol, T* __restrict__ bval) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = (int)(gid / BSR_COPY_LANES), lane = (int)(gid % BSR_COPY_LANES);
+  if (r >= nr) return;
+  const int u = r / b, q = r % b;
+  const int64_t blk0 = ptr[u * b] / (b * b);
+  const int p0 = ptr[r], len = ptr[r + 1] - p0;
+  for (int i = lane; i < len; i += BSR_COPY_LANES) {
+    const int64_t blk = blk0 + i / b;
+    const int c = i % b;
+    bval[(int64_t)(q * b + c) * nblk + blk] = (T)val[p0 + i];
+    if (q == 0 && c == 0) bcol[blk] = col[p0 + i] / b;
+  }
+}
+__global__ void k_bsr_node_bounds(int nnodes, const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+                                  int* __restrict__ bcp) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nnodes) return;
+  const int u = nodes[t];
+  bcp[2 * t] = ptr[u * b] / (b * b);
+  bcp[2 * t + 1] = ptr[(u + 1) * b] / (b * b);
+}
+
+// One colour of the Gauss-Seidel sweep from the block copy: G lanes per node,
+// each lane taking whole blocks (two at a time in flight), the node's B row
+// sums reduced across its G lanes; lanes 0..B-1 write the node's B values
+// (x_r += omega D^-1_r (b_r - A_r x), A_r x with the node's own old values,
+// as k_sgs_color).  Colours are independent sets, so only the own node's x
+// is both read and written, by lanes of one wavefront, reads first.
+template <int B, int G, class T>
+__global__ __launch_bounds__(256) void k_sgs_color_bsr(int nnodes, const int* __restrict__ nodes,
+                                                       const int* __restrict__ bcp, const int* __restrict__ bcol,
+                                                       const T* __restrict__ bval, int64_t nblk,
+                                                       const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
+                                                       T* __restrict__ x) {
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int t = gid / G, lane = gid % G;
+  if (t >= nnodes) return;   // whole groups of G lanes together
+  const int node = nodes[t];
+  const int k0 = bcp[2 * t], k1 = bcp[2 * t + 1];
+  T w = 0, rv = 0, xo = 0;
+  if (lane < B) {
+    const int64_t r = (int64_t)node * B + lane;
+    w = omega * dinv[r];
+    rv = rhs[r];
+    xo = x[r];
+  }
+  T acc[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) acc[q] = 0;
+  for (int k = k0 + lane; k < k1; k += 2 * G) {
+    const int kb = k + G;
+    const bool hb = kb < k1;
+    const int ca = bcol[k], cb = hb ? bcol[kb] : ca;
+    T va[B * B], vb[B * B], xa[B], xb[B];
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) {
+      va[e] = bval[(int64_t)e * nblk + k];
+      vb[e] = hb ? bval[(int64_t)e * nblk + kb] : (T)0;
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      xa[c] = x[(int64_t)ca * B + c];
+      xb[c] = hb ? x[(int64_t)cb * B + c] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        acc[q] += va[q * B + c] * xa[c];
+        acc[q] += vb[q * B + c] * xb[c];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < B; ++q)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, G);
+  T a = acc[0];
+#pragma unroll
+  for (int q = 1; q < B; ++q)
+    if (lane == q) a = acc[q];
+  if (lane < B) x[(int64_t)node * B + lane] = xo + w * (rv - a);
+}
+
+template <class T>
+bool sgs_bsr_setup(const DCsr& A, int b, const int* nodes, int nnodes, DBuf<int>& bcp, DBuf<int>& bcol, DBuf<T>& bval,
+                   int64_t& nblk, hipStream_t s) {
+  if ((b != 2 && b != 3) || nnodes <= 0 || A.nnz <= 0 || A.nr != nnodes * b || A.nc != A.nr) return false;
+  if (A.nnz % (b * b) != 0) return false;
+  DBuf<int> bad(1);
+  fill<int>(bad.p, 0, 1, s);
+  const unsigned rows_grid = (unsigned)cdiv((int64_t)A.nr * BSR_COPY_LANES, 256);
+  hipLaunchKernelGGL(k_bsr_dense_check, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, bad.p);
+  int h = 1;
+  NF_HIP(hipMemcpyAsync(&h, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  NF_HIP(hipStreamSynchronize(s));
+  if (h) return false;   // some block not full
+  nblk = A.nnz / (b * b);
+  bcp.alloc((size_t)2 * nnodes);
+  hipLaunchKernelGGL(k_bsr_node_bounds, dim3(cdiv(nnodes, 256)), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, bcp.p);
+  bcol.alloc(nblk);
+  bval.alloc((size_t)nblk * b * b);
+  hipLaunchKernelGGL(k_bsr_dense_copy<T>, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, A.val.p, nblk,
+                     bcol.p, bval.p);
+  NF_HIP(hipGetLastError());
+  return true;
+}
+
+template <class T>
+void sgs_sweep_bsr(int b, const int* nodes, const int* bcp, const int* bcol, const T* bval, int64_t nblk,
+                   const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs, T* x, hipStream_t s) {
+  const int nc = (int)off.size() - 1;
+  constexpr int G = 16;
+  for (int i = 0; i < nc; ++i) {
+    const int c = forward ? i : nc - 1 - i;
+    const int m = off[c + 1] - off[c];
+    if (m <= 0) continue;
+    const unsigned blocks = (unsigned)cdiv((int64_t)m * G, 256);
+    if (b == 3)
+      hipLaunchKernelGGL((k_sgs_color_bsr<3, G, T>), dim3(blocks), dim3(256), 0, s, m, nodes + off[c],
+                         bcp + (int64_t)2 * off[c], bcol, bval, nblk, dinv, omega, rhs, x);
+    else
+      hipLaunchKernelGGL((k_sgs_color_bsr<2, G, T>), dim3(blocks), dim3(256), 0, s, m, nodes + off[c],
+                         bcp + (int64_t)2 * off[c], bcol, bval, nblk, dinv, omega, rhs, x);
+  }
+}
+template bool sgs_bsr_setup<double>(const DCsr&, int, const int*, int, DBuf<int>&, DBuf<int>&, DBuf<double>&, int64_t&,
+                                    hipStream_t);
+template bool sgs_bsr_setup<float>(const DCsr&, int, const int*, int, DBuf<int>&, DBuf<int>&, DBuf<float>&, int64_t&,
+                                   hipStream_t);
+template void sgs_sweep_bsr<double>(int, const int*, const int*, const int*, const double*, int64_t,
+                                    const std::vector<int>&, bool, const double*, double, const double*, double*,
+                                    hipStream_t);
+template void sgs_sweep_bsr<float>(int, const int*, const int*, const int*, const float*, int64_t,
+                                   const std::vector<int>&, bool, const float*, float, const float*, float*, hipStream_t);
+
 template void dense_sweep_apply<double>(const double*, int, const double*, int64_t, const double*, int64_t, double*, int64_t,
                                         int, bool, hipStream_t);
 template void dense_sweep_apply<float>(const float*, int, const float*, int64_t, const float*, int64_t, float*, int64_t, int,

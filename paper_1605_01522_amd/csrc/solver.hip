@@ -187,6 +187,12 @@ struct SgsD : FieldSmootherD<T> {
   std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
   DBuf<int> off_dev;
   int kind = SGS_COLOR;
+  // block copy of a level made of dense 2 x 2 or 3 x 3 node blocks (the
+  // colour kernel for one right-hand side reads it instead of A)
+  bool bsr = false;
+  DBuf<int> bcp, bcol;
+  DBuf<T> bval;
+  int64_t nblk = 0;
   // gp / ga / nn: the node graph of A when the caller already has it
   void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s,
              const DBuf<int>* gp = nullptr, const DBuf<int>* ga = nullptr, int nn_given = 0) {
@@ -230,12 +236,15 @@ struct SgsD : FieldSmootherD<T> {
     sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
     NF_HIP(hipStreamSynchronize(s));
     kind = sgs_kind(*A, b, nn, nc);
+    bsr = kind == SGS_COLOR && nn >= SGS_BSR_MIN_NODES && sgs_bsr_setup<T>(*A, b, nodes.p, nn, bcp, bcol, bval, nblk, s);
     // a sweep's algorithmic bytes for the solve statistics: every entry and
-    // row bound once, node ids and D^-1, and per right-hand side the rhs, the
-    // own x read and written and the operand x once
+    // row bound once (a block copy: every value, one column per block and two
+    // bounds per node), node ids and D^-1, and per right-hand side the rhs,
+    // the own x read and written and the operand x once
     {
       const double sz = sizeof(T);
       stat_bytes = (double)A->nnz * (sz + 4) + 4.0 * (b + 2) * nn + sz * n;
+      stat_bytes_bsr = (double)A->nnz * sz + 4.0 * nblk + 12.0 * nn + sz * n;
       stat_bytes_x = 4.0 * sz * n;
     }
     // per-launch bytes with the distinct columns of every colour, counted
@@ -249,6 +258,7 @@ struct SgsD : FieldSmootherD<T> {
       for (int c = 0; c < nc; ++c) {
         const double rows = (double)(off[c + 1] - off[c]) * b;
         sweep_bytes += cnnz[c] * (sz + 4) + 4.0 * (b + 2) * (off[c + 1] - off[c]) + rows * sz;
+        sweep_bytes_bsr += cnnz[c] * sz + 4.0 * cnnz[c] / ((double)b * b) + 12.0 * (off[c + 1] - off[c]) + rows * sz;
         sweep_bytes_x += rows * 3 * sz + sz * ccols[c];
       }
     }
@@ -257,19 +267,22 @@ struct SgsD : FieldSmootherD<T> {
   // entries and pointers, node ids and D^-1 (once), and per right-hand side
   // its rhs, own x read and written and each distinct column value read
   double sweep_bytes = 0.0, sweep_bytes_x = 0.0, stat_bytes = 0.0, stat_bytes_x = 0.0;
+  double sweep_bytes_bsr = 0.0, stat_bytes_bsr = 0.0;
   void sweep(bool forward, const T* rhs, int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s) {
     const int nc = (int)off.size() - 1;
-    bytes_count(stat_bytes + nrhs * stat_bytes_x);
+    const bool blocks = bsr && nrhs == 1;
+    bytes_count((blocks ? stat_bytes_bsr : stat_bytes) + nrhs * stat_bytes_x);
     const int slot = prof_begin(s);
-    sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
+    if (blocks) sgs_sweep_bsr<T>(b, nodes.p, bcp.p, bcol.p, bval.p, nblk, off, forward, dinv.p, omega, rhs, x, s);
+    else sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-    const int lanes = kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
-    const int mode = kind == SGS_SWEEP1 ? 7 : kind == SGS_NODE ? 8 : 6;
+    const int lanes = blocks ? 16 : kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
+    const int mode = blocks ? 11 : kind == SGS_SWEEP1 ? 7 : kind == SGS_NODE ? 8 : 6;
     int launches = kind == SGS_SWEEP1 ? 1 : 0;
     if (kind != SGS_SWEEP1)
       for (int c = 0; c < nc; ++c) launches += off[c + 1] > off[c] ? 1 : 0;
     prof_end(slot, s, ((lanes * 16 + b2) * 100 + mode) * 10 + (sizeof(T) == 4 ? 1 : 0),
-             sweep_bytes + nrhs * sweep_bytes_x, launches);
+             (blocks ? sweep_bytes_bsr : sweep_bytes) + nrhs * sweep_bytes_x, launches);
   }
   // half: pre-smoothing sweeps forward only, post-smoothing backward only
   int half = 0;

@@ -364,7 +364,7 @@ def nfield_prof_enable(on):
 
 
 SPMV_MODES = {0: "store", 1: "resid", 2: "add", 3: "sub", 4: "cheb", 5: "dscale", 6: "sgs",
-              7: "sgs_sweep1", 8: "sgs_node", 9: "sgs_dense", 10: "ddgs"}
+              7: "sgs_sweep1", 8: "sgs_node", 9: "sgs_dense", 10: "ddgs", 11: "sgs_bsr"}
 # kernel names as the profiler prints them (single right-hand side)
 KERNEL_NAMES = {m: f"k_spmv<{{lanes}}, {m}, {{t}}>" for m in range(6)}
 KERNEL_NAMES[6] = "k_sgs_color<{lanes}, {rows}, 1, {t}>"
@@ -372,11 +372,12 @@ KERNEL_NAMES[7] = "k_sgs_sweep1<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[8] = "k_sgs_node<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[9] = "k_dense_sweep_apply<1, {t}>"
 KERNEL_NAMES[10] = "k_dd_sweep<{lanes}, {rows}, 1, {t}>"
+KERNEL_NAMES[11] = "k_sgs_color_bsr<{b}, {lanes}, {t}>"
 
 
 def kernel_name(p):
     mode = [k for k, v in SPMV_MODES.items() if v == p["mode"]][0]
-    return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"],
+    return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"], b={2: 2, 4: 3}.get(p["rows"], p["rows"]),
                                      t="float" if p["fp32"] else "double")
 
 

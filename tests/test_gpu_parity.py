@@ -205,6 +205,37 @@ def test_serving_configuration_parity(dev, nel):
     assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
 
 
+def test_sgs_block_copy_parity(dev):
+    """A level of at least 4,096 nodes made of dense 2 x 2 blocks (the
+    plane-strain field on a 64 x 64 grid) relaxes from its block copy for one
+    right-hand side: the preconditioner is the oracle's, and the block kernel
+    is the one that ran; several right-hand sides take the CSR kernel."""
+    from paper_1605_01522_amd import nfield
+    _say("case Gauss-Seidel from the block copy")
+    s = nfgen.tsi2d(nel=64, seed=1)
+    spec = "BGS(AMG[smoother=sgs,omega=0.9])"
+    opts = dict(coarse_max=200, **TSI_OPTS)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(3).standard_normal((2, s.n))
+    nfield.nfield_prof_enable(1)
+    z1 = g.precond_apply(torch.tensor(r[0], device=dev)).cpu().numpy()
+    torch.cuda.synchronize()
+    prof = nfield.nfield_prof_read()
+    nfield.nfield_prof_enable(0)
+    assert any(p["mode"] == "sgs_bsr" for p in prof), [p["mode"] for p in prof]
+    z2 = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    zo = o.precond_apply(r)
+    assert np.linalg.norm(z1 - zo[0]) <= 1e-10 * np.linalg.norm(zo[0])
+    for k in range(2):
+        assert np.linalg.norm(z2[k] - zo[k]) <= 1e-10 * np.linalg.norm(zo[k])
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8)
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8)
+    x = x.cpu().numpy()
+    assert st[0]["status"] == 0 and np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert abs(st[0]["iters"] - so["iters"]) <= 2
+
+
 # ------------------------------------------------------------ edge cases
 def test_single_level_is_exact(dev):
     _say("case single level")
