@@ -9,6 +9,7 @@
 
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -129,6 +130,12 @@ __global__ __launch_bounds__(256) void k_dense_gemvm(const double* __restrict__ 
 
 static thread_local double g_alg_bytes = 0.0;
 void bytes_count(double b) { g_alg_bytes += b; }
+// SpMVs inside a set-up (power iterations, ...) do not read block copies,
+// which other parts of the set-up may be building at the same time: the
+// set-up's results then do not depend on its timing
+static thread_local bool g_in_setup = false;
+void setup_mode(bool on) { g_in_setup = on; }
+bool in_setup() { return g_in_setup; }
 double bytes_counted() { return g_alg_bytes; }
 
 static inline int grid_for(int64_t n, int threads = 256) {
@@ -419,8 +426,11 @@ static double spmv_bytes(SpmvMode mode, const DCsr& A, int nrhs) {
   return b + nrhs * streams * s * A.nr;
 }
 
+template <class T> static bool spmv_bsr(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s);
+
 template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
   if (A.nr <= 0) return;
+  if (spmv_bsr<T>(mode, A, a, s)) return;
   const T* val = csr_values<T>(A);
   const int G = spmv_lanes(A.nr, A.nnz);
   bytes_count(spmv_bytes<T>(mode, A, a.nrhs));
@@ -442,6 +452,104 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
     ++g_prof.used;
   }
 }
+// SpMV from the block copy (one right-hand side; store, residual, add,
+// subtract): G lanes per node taking whole blocks, the node's B row sums
+// reduced across them
+template <int B, int G, int MODE, class T>
+__global__ __launch_bounds__(256) void k_spmv_bsr(int nnodes, const int* __restrict__ ptr, const int* __restrict__ bcol,
+                                                  const T* __restrict__ bval, int64_t nblk, SpmvArgs<T> a) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int u = (int)(gid / G), lane = (int)(gid % G);
+  if (u >= nnodes) return;   // whole groups of G lanes together
+  const int k0 = ptr[u * B] / (B * B), k1 = ptr[(u + 1) * B] / (B * B);
+  const T* __restrict__ x = a.x;
+  T acc[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) acc[q] = 0;
+  for (int k = k0 + lane; k < k1; k += 2 * G) {
+    const int kb = k + G;
+    const bool hb = kb < k1;
+    const int ca = bcol[k], cb = hb ? bcol[kb] : ca;
+    T va[B * B], vb[B * B], xa[B], xb[B];
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) {
+      va[e] = bval[(int64_t)e * nblk + k];
+      vb[e] = hb ? bval[(int64_t)e * nblk + kb] : (T)0;
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      xa[c] = x[(int64_t)ca * B + c];
+      xb[c] = hb ? x[(int64_t)cb * B + c] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        acc[q] += va[q * B + c] * xa[c];
+        acc[q] += vb[q * B + c] * xb[c];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < B; ++q)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, G);
+  T v = acc[0];
+#pragma unroll
+  for (int q = 1; q < B; ++q)
+    if (lane == q) v = acc[q];
+  if (lane >= B) return;
+  const int64_t r = (int64_t)u * B + lane;
+  if (MODE == SPMV_STORE) a.y[r] = v;
+  else if (MODE == SPMV_RESID) a.y[r] = a.b[r] - v;
+  else if (MODE == SPMV_ADD) a.y[r] += v;
+  else if (MODE == SPMV_SUB) a.y[r] -= v;
+}
+
+template <class T> static const T* bsr_values(const DCsr& A);
+template <> const double* bsr_values<double>(const DCsr& A) { return A.bsr_val.p; }
+template <> const float* bsr_values<float>(const DCsr& A) { return A.bsr_val32.p; }
+
+template <class T> static bool spmv_bsr(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
+  const T* bv = bsr_values<T>(A);
+  if (g_in_setup || a.nrhs != 1 || !A.bsr_b || !bv || mode > SPMV_SUB) return false;
+  const int b = A.bsr_b, nnodes = A.nr / b;
+  constexpr int G = 16;
+  const double sz = sizeof(T);
+  const int streams = mode == SPMV_STORE ? 1 : 2;
+  const double bytes = (double)A.nnz * sz + 4.0 * A.bsr_nblk + 4.0 * (nnodes + 1) + sz * A.nc + streams * sz * A.nr;
+  bytes_count(bytes);
+  const bool timed = g_prof.on && !g_prof_quiet && g_prof.used < g_prof.ev.size() / 2;
+  if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
+  const unsigned blocks = (unsigned)cdiv((int64_t)nnodes * G, 256);
+#define NF_SB(BB, MM) \
+  hipLaunchKernelGGL((k_spmv_bsr<BB, G, MM, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.ptr.p, A.bsr_col.p, bv, A.bsr_nblk, a)
+  if (b == 3) {
+    switch (mode) {
+      case SPMV_STORE: NF_SB(3, SPMV_STORE); break;
+      case SPMV_RESID: NF_SB(3, SPMV_RESID); break;
+      case SPMV_ADD: NF_SB(3, SPMV_ADD); break;
+      default: NF_SB(3, SPMV_SUB); break;
+    }
+  } else {
+    switch (mode) {
+      case SPMV_STORE: NF_SB(2, SPMV_STORE); break;
+      case SPMV_RESID: NF_SB(2, SPMV_RESID); break;
+      case SPMV_ADD: NF_SB(2, SPMV_ADD); break;
+      default: NF_SB(2, SPMV_SUB); break;
+    }
+  }
+#undef NF_SB
+  if (timed) {
+    const int b2 = b <= 2 ? 2 : 4;
+    NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
+    g_prof.key.push_back(((G * 16 + b2) * 100 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
+    g_prof.bytes.push_back(bytes);
+    g_prof.count.push_back(1);
+    ++g_prof.used;
+  }
+  return true;
+}
+
 template void spmv<double>(SpmvMode, const DCsr&, const SpmvArgs<double>&, hipStream_t);
 template void spmv<float>(SpmvMode, const DCsr&, const SpmvArgs<float>&, hipStream_t);
 
@@ -1977,26 +2085,39 @@ __global__ __launch_bounds__(256) void k_sgs_color_bsr(int nnodes, const int* __
   if (lane < B) x[(int64_t)node * B + lane] = xo + w * (rv - a);
 }
 
+template <class T> static DBuf<T>& bsr_store(DCsr& A);
+template <> DBuf<double>& bsr_store<double>(DCsr& A) { return A.bsr_val; }
+template <> DBuf<float>& bsr_store<float>(DCsr& A) { return A.bsr_val32; }
+static std::mutex g_bsr_mu;
+
 template <class T>
-bool sgs_bsr_setup(const DCsr& A, int b, const int* nodes, int nnodes, DBuf<int>& bcp, DBuf<int>& bcol, DBuf<T>& bval,
-                   int64_t& nblk, hipStream_t s) {
+bool sgs_bsr_setup(const DCsr& A_, int b, const int* nodes, int nnodes, DBuf<int>& bcp, hipStream_t s) {
+  DCsr& A = const_cast<DCsr&>(A_);   // the copy is kept with the matrix
   if ((b != 2 && b != 3) || nnodes <= 0 || A.nnz <= 0 || A.nr != nnodes * b || A.nc != A.nr) return false;
   if (A.nnz % (b * b) != 0) return false;
-  DBuf<int> bad(1);
-  fill<int>(bad.p, 0, 1, s);
-  const unsigned rows_grid = (unsigned)cdiv((int64_t)A.nr * BSR_COPY_LANES, 256);
-  hipLaunchKernelGGL(k_bsr_dense_check, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, bad.p);
-  int h = 1;
-  NF_HIP(hipMemcpyAsync(&h, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  NF_HIP(hipStreamSynchronize(s));
-  if (h) return false;   // some block not full
-  nblk = A.nnz / (b * b);
+  std::lock_guard<std::mutex> lock(g_bsr_mu);   // smoothers of one matrix set up side by side
+  DBuf<T>& bval = bsr_store<T>(A);
+  if (!bval.p) {
+    DBuf<int> bad(1);
+    fill<int>(bad.p, 0, 1, s);
+    const unsigned rows_grid = (unsigned)cdiv((int64_t)A.nr * BSR_COPY_LANES, 256);
+    hipLaunchKernelGGL(k_bsr_dense_check, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, bad.p);
+    int h = 1;
+    NF_HIP(hipMemcpyAsync(&h, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    NF_HIP(hipStreamSynchronize(s));
+    if (h) return false;   // some block not full
+    const int64_t nblk = A.nnz / (b * b);
+    if (!A.bsr_col.p) A.bsr_col.alloc(nblk);
+    bval.alloc((size_t)nblk * b * b);
+    hipLaunchKernelGGL(k_bsr_dense_copy<T>, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, A.val.p, nblk,
+                       A.bsr_col.p, bval.p);
+    NF_HIP(hipGetLastError());
+    NF_HIP(hipStreamSynchronize(s));   // complete before another stream's smoother may reuse it
+    A.bsr_nblk = nblk;
+    A.bsr_b = b;
+  }
   bcp.alloc((size_t)2 * nnodes);
   hipLaunchKernelGGL(k_bsr_node_bounds, dim3(cdiv(nnodes, 256)), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, bcp.p);
-  bcol.alloc(nblk);
-  bval.alloc((size_t)nblk * b * b);
-  hipLaunchKernelGGL(k_bsr_dense_copy<T>, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, A.val.p, nblk,
-                     bcol.p, bval.p);
   NF_HIP(hipGetLastError());
   return true;
 }
@@ -2019,10 +2140,8 @@ void sgs_sweep_bsr(int b, const int* nodes, const int* bcp, const int* bcol, con
                          bcp + (int64_t)2 * off[c], bcol, bval, nblk, dinv, omega, rhs, x);
   }
 }
-template bool sgs_bsr_setup<double>(const DCsr&, int, const int*, int, DBuf<int>&, DBuf<int>&, DBuf<double>&, int64_t&,
-                                    hipStream_t);
-template bool sgs_bsr_setup<float>(const DCsr&, int, const int*, int, DBuf<int>&, DBuf<int>&, DBuf<float>&, int64_t&,
-                                   hipStream_t);
+template bool sgs_bsr_setup<double>(const DCsr&, int, const int*, int, DBuf<int>&, hipStream_t);
+template bool sgs_bsr_setup<float>(const DCsr&, int, const int*, int, DBuf<int>&, hipStream_t);
 template void sgs_sweep_bsr<double>(int, const int*, const int*, const int*, const double*, int64_t,
                                     const std::vector<int>&, bool, const double*, double, const double*, double*,
                                     hipStream_t);

@@ -16,6 +16,9 @@ constexpr int NRMAX = 8;
 // vectors read and written), accumulated by the launch wrappers; a solve
 // reads the counter before and after to fill nfield_stats.bytes.
 void bytes_count(double b);
+// set-up mode of the calling thread: SpMVs then ignore block copies
+void setup_mode(bool on);
+bool in_setup();
 double bytes_counted();
 
 // ------------------------------------------------------------ vectors
@@ -160,12 +163,12 @@ template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t
 // one sweep over all colours (forward: ascending colour order), nodes grouped
 // by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
 // device as off_dev; cptr from sgs_node_ptrs over the whole list)
-// Levels made of dense b x b node blocks (b = 2 or 3): a block copy for the
-// colour kernel (block row bounds of each listed node, 2 ints per node in
-// list order; one column node per block; values entry-major, nblk blocks);
+// Levels made of dense b x b node blocks (b = 2 or 3): the block copy kept
+// with A (DCsr::bsr_*, built once per precision) and the block row bounds of
+// each listed node for the colour kernel (2 ints per node in list order);
 // false, keeping nothing, when some block of A is not full
 template <class T> bool sgs_bsr_setup(const DCsr& A, int b, const int* nodes, int nnodes, DBuf<int>& bcp,
-                                      DBuf<int>& bcol, DBuf<T>& bval, int64_t& nblk, hipStream_t s);
+                                      hipStream_t s);
 // one sweep over all colours from the block copy (one right-hand side)
 template <class T> void sgs_sweep_bsr(int b, const int* nodes, const int* bcp, const int* bcol, const T* bval,
                                       int64_t nblk, const std::vector<int>& off, bool forward, const T* dinv, T omega,

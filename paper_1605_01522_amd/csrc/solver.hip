@@ -187,12 +187,11 @@ struct SgsD : FieldSmootherD<T> {
   std::vector<int> off;            // colour c owns nodes[off[c], off[c+1])
   DBuf<int> off_dev;
   int kind = SGS_COLOR;
-  // block copy of a level made of dense 2 x 2 or 3 x 3 node blocks (the
-  // colour kernel for one right-hand side reads it instead of A)
+  // a level made of dense 2 x 2 or 3 x 3 node blocks: the colour kernel for
+  // one right-hand side reads A's block copy (bcp: each listed node's block
+  // bounds)
   bool bsr = false;
-  DBuf<int> bcp, bcol;
-  DBuf<T> bval;
-  int64_t nblk = 0;
+  DBuf<int> bcp;
   // gp / ga / nn: the node graph of A when the caller already has it
   void setup(const DCsr* A_, int b_, const double* dinv64, double om, int st, uint64_t seed, hipStream_t s,
              const DBuf<int>* gp = nullptr, const DBuf<int>* ga = nullptr, int nn_given = 0) {
@@ -236,7 +235,8 @@ struct SgsD : FieldSmootherD<T> {
     sgs_node_ptrs(*A, b, nodes.p, nn, cptr.p, s);
     NF_HIP(hipStreamSynchronize(s));
     kind = sgs_kind(*A, b, nn, nc);
-    bsr = kind == SGS_COLOR && nn >= SGS_BSR_MIN_NODES && sgs_bsr_setup<T>(*A, b, nodes.p, nn, bcp, bcol, bval, nblk, s);
+    bsr = kind == SGS_COLOR && nn >= SGS_BSR_MIN_NODES && sgs_bsr_setup<T>(*A, b, nodes.p, nn, bcp, s);
+    const double nblk = bsr ? (double)A->bsr_nblk : 0.0;
     // a sweep's algorithmic bytes for the solve statistics: every entry and
     // row bound once (a block copy: every value, one column per block and two
     // bounds per node), node ids and D^-1, and per right-hand side the rhs,
@@ -273,7 +273,10 @@ struct SgsD : FieldSmootherD<T> {
     const bool blocks = bsr && nrhs == 1;
     bytes_count((blocks ? stat_bytes_bsr : stat_bytes) + nrhs * stat_bytes_x);
     const int slot = prof_begin(s);
-    if (blocks) sgs_sweep_bsr<T>(b, nodes.p, bcp.p, bcol.p, bval.p, nblk, off, forward, dinv.p, omega, rhs, x, s);
+    if (blocks) {
+      const T* bv = sizeof(T) == sizeof(double) ? (const T*)A->bsr_val.p : (const T*)A->bsr_val32.p;
+      sgs_sweep_bsr<T>(b, nodes.p, bcp.p, A->bsr_col.p, bv, A->bsr_nblk, off, forward, dinv.p, omega, rhs, x, s);
+    }
     else sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
     const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
     const int lanes = blocks ? 16 : kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
@@ -935,6 +938,7 @@ static void run_concurrently(nfield_ctx& C, const std::vector<std::function<void
     th.emplace_back([&, k, cols] {
       try {
         g_mbuf_cols = cols;
+        setup_mode(true);
         NF_HIP(hipSetDevice(dev));
         g_pool = &sb[k]->pool;
         g_hsink = &hs[k];
@@ -1755,7 +1759,15 @@ __global__ void k_gather_vals(const double* g, const int* pos, int64_t n, double
   if (i < n) v[i] = g[pos[i]];
 }
 
+// set-up mode for the calling thread while in scope
+struct SetupScope {
+  bool prev;
+  SetupScope() : prev(in_setup()) { setup_mode(true); }
+  ~SetupScope() { setup_mode(prev); }
+};
+
 static void build_tree(nfield_ctx& C, hipStream_t s) {
+  SetupScope scope;
   C.drop_graphs();
   C.root64.reset();
   C.root32.reset();
@@ -1777,8 +1789,11 @@ static void build_tree(nfield_ctx& C, hipStream_t s) {
     NF_HIP(hipGetLastError());
     C.inputs_dropped = false;
   }
-  for (auto& b : C.A.blk)   // FP32 copies of the inputs count as the tree's
-    if (b) b->val32.release();
+  for (auto& b : C.A.blk)   // FP32 and block copies of the inputs count as the tree's
+    if (b) {
+      b->val32.release();
+      b->bsr_release();
+    }
   const size_t live0 = tree_live(C);
   if (C.o.hier_fp32) {
     // FP32 copies of the input blocks are made where an FP32 solver reads them

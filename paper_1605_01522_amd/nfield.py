@@ -377,6 +377,9 @@ KERNEL_NAMES[11] = "k_sgs_color_bsr<{b}, {lanes}, {t}>"
 
 def kernel_name(p):
     mode = [k for k, v in SPMV_MODES.items() if v == p["mode"]][0]
+    if mode < 6 and p["rows"] > 0:   # an SpMV from a matrix's block copy
+        return "k_spmv_bsr<{b}, {lanes}, {m}, {t}>".format(b={2: 2, 4: 3}[p["rows"]], lanes=p["lanes"], m=mode,
+                                                           t="float" if p["fp32"] else "double")
     return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"], b={2: 2, 4: 3}.get(p["rows"], p["rows"]),
                                      t="float" if p["fp32"] else "double")
 
