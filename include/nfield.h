@@ -293,8 +293,9 @@ nfield_status nfield_rebuild(nfield_ctx *ctx, void *hip_stream);
  * workgroup per node (long rows); 9 = the whole symmetric sweep of a small
  * many-colour level as one dense affine map x <- S x + Q b; 10 = a DD(GS)
  * sweep (one workgroup per subdomain); 11 = a launch per colour from the
- * block copy of a level made of dense 2 x 2 or 3 x 3 node blocks; launches,
- * total milliseconds, total
+ * block copy of a level made of dense 2 x 2 or 3 x 3 node blocks.  For
+ * kinds 0-3 and 11 from a block copy, rows_per_node_group is the block
+ * size.  Launches, total milliseconds, total
  * algorithmic bytes (matrix once, operand once, epilogue streams). */
 void nfield_prof_enable(int32_t on);
 int32_t nfield_prof_read(int32_t max, int32_t *key, int64_t *count, double *ms, double *bytes);

@@ -179,17 +179,20 @@ struct DCsr {
   DBuf<double> val;
   DBuf<float> val32;
   // block copy of a matrix made of dense bsr_b x bsr_b node blocks (built by
-  // the Gauss-Seidel set-up of its level; read by that smoother and by
-  // SpMVs with one right-hand side outside the set-up): one column node per
-  // block, values entry-major; the blocks of node u start at ptr[u b] / b^2
+  // the Gauss-Seidel set-up of its level; read by that smoother and by SpMVs
+  // with one right-hand side outside the set-up): bsr_ptr / bsr_col the
+  // block rows and column nodes; node u's values start at bsr_ptr[u] b^2,
+  // entry by entry (entry (q, c) of its blocks in order at offset
+  // (q b + c) times its block count, then the next)
   int bsr_b = 0;
   int64_t bsr_nblk = 0;
-  DBuf<int> bsr_col;
+  DBuf<int> bsr_ptr, bsr_col;
   DBuf<double> bsr_val;
   DBuf<float> bsr_val32;
   void bsr_release() {
     bsr_b = 0;
     bsr_nblk = 0;
+    bsr_ptr.release();
     bsr_col.release();
     bsr_val.release();
     bsr_val32.release();

@@ -452,43 +452,56 @@ template <class T> void spmv(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a,
     ++g_prof.used;
   }
 }
+// Blocks j and (if hb) jb of a node's nu dense B x B blocks against x:
+// their values (nv: the node's values, entry (q, c) of its blocks at
+// nv[(q B + c) nu ..]) and their column nodes' (nc: the node's column nodes)
+// B entries of x, added into the B row sums.  Without a second block the
+// first is loaded twice and its second terms dropped: every load is
+// unconditional, so none waits for another.
+template <int B, class T>
+__device__ __forceinline__ void bsr_block_rows(int j, int jb, bool hb, int nu, const int* __restrict__ nc,
+                                               const T* __restrict__ nv, const T* __restrict__ x, T* acc) {
+  constexpr int S = B * B;
+  const int jj = hb ? jb : j;
+  const int ca = nc[j], cb = nc[jj];
+  T va[S], vb[S], xa[B], xb[B];
+#pragma unroll
+  for (int e = 0; e < S; ++e) {
+    va[e] = nv[e * nu + j];
+    vb[e] = nv[e * nu + jj];
+  }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    xa[c] = x[(int64_t)ca * B + c];
+    xb[c] = x[(int64_t)cb * B + c];
+  }
+#pragma unroll
+  for (int e = 0; e < S; ++e) vb[e] = hb ? vb[e] : (T)0;
+#pragma unroll
+  for (int q = 0; q < B; ++q)
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      acc[q] += va[q * B + c] * xa[c];
+      acc[q] += vb[q * B + c] * xb[c];
+    }
+}
+
 // SpMV from the block copy (one right-hand side; store, residual, add,
 // subtract): G lanes per node taking whole blocks, the node's B row sums
 // reduced across them
 template <int B, int G, int MODE, class T>
-__global__ __launch_bounds__(256) void k_spmv_bsr(int nnodes, const int* __restrict__ ptr, const int* __restrict__ bcol,
-                                                  const T* __restrict__ bval, int64_t nblk, SpmvArgs<T> a) {
+__global__ __launch_bounds__(256) void k_spmv_bsr(int nnodes, const int* __restrict__ bptr, const int* __restrict__ bcol,
+                                                  const T* __restrict__ bval, SpmvArgs<T> a) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int u = (int)(gid / G), lane = (int)(gid % G);
   if (u >= nnodes) return;   // whole groups of G lanes together
-  const int k0 = ptr[u * B] / (B * B), k1 = ptr[(u + 1) * B] / (B * B);
-  const T* __restrict__ x = a.x;
+  const int k0 = bptr[u], k1 = bptr[u + 1];
   T acc[B];
 #pragma unroll
   for (int q = 0; q < B; ++q) acc[q] = 0;
-  for (int k = k0 + lane; k < k1; k += 2 * G) {
-    const int kb = k + G;
-    const bool hb = kb < k1;
-    const int ca = bcol[k], cb = hb ? bcol[kb] : ca;
-    T va[B * B], vb[B * B], xa[B], xb[B];
-#pragma unroll
-    for (int e = 0; e < B * B; ++e) {
-      va[e] = bval[(int64_t)e * nblk + k];
-      vb[e] = hb ? bval[(int64_t)e * nblk + kb] : (T)0;
-    }
-#pragma unroll
-    for (int c = 0; c < B; ++c) {
-      xa[c] = x[(int64_t)ca * B + c];
-      xb[c] = hb ? x[(int64_t)cb * B + c] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < B; ++q)
-#pragma unroll
-      for (int c = 0; c < B; ++c) {
-        acc[q] += va[q * B + c] * xa[c];
-        acc[q] += vb[q * B + c] * xb[c];
-      }
-  }
+  const int nu = k1 - k0;
+  for (int j = lane; j < nu; j += 2 * G)
+    bsr_block_rows<B, T>(j, j + G, j + G < nu, nu, bcol + k0, bval + (int64_t)k0 * B * B, a.x, acc);
 #pragma unroll
   for (int q = 0; q < B; ++q)
 #pragma unroll
@@ -509,40 +522,46 @@ template <class T> static const T* bsr_values(const DCsr& A);
 template <> const double* bsr_values<double>(const DCsr& A) { return A.bsr_val.p; }
 template <> const float* bsr_values<float>(const DCsr& A) { return A.bsr_val32.p; }
 
+template <int B, class T>
+static void spmv_bsr_launch(SpmvMode mode, const DCsr& A, const T* bv, const SpmvArgs<T>& a, hipStream_t s) {
+  constexpr int G = 16;
+  const int nnodes = A.nr / B;
+  const unsigned blocks = (unsigned)cdiv((int64_t)nnodes * G, 256);
+  switch (mode) {
+    case SPMV_STORE:
+      hipLaunchKernelGGL((k_spmv_bsr<B, G, SPMV_STORE, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.bsr_ptr.p,
+                         A.bsr_col.p, bv, a);
+      break;
+    case SPMV_RESID:
+      hipLaunchKernelGGL((k_spmv_bsr<B, G, SPMV_RESID, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.bsr_ptr.p,
+                         A.bsr_col.p, bv, a);
+      break;
+    case SPMV_ADD:
+      hipLaunchKernelGGL((k_spmv_bsr<B, G, SPMV_ADD, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.bsr_ptr.p,
+                         A.bsr_col.p, bv, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv_bsr<B, G, SPMV_SUB, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.bsr_ptr.p,
+                         A.bsr_col.p, bv, a);
+      break;
+  }
+}
+
 template <class T> static bool spmv_bsr(SpmvMode mode, const DCsr& A, const SpmvArgs<T>& a, hipStream_t s) {
   const T* bv = bsr_values<T>(A);
   if (g_in_setup || a.nrhs != 1 || !A.bsr_b || !bv || mode > SPMV_SUB) return false;
   const int b = A.bsr_b, nnodes = A.nr / b;
-  constexpr int G = 16;
   const double sz = sizeof(T);
   const int streams = mode == SPMV_STORE ? 1 : 2;
-  const double bytes = (double)A.nnz * sz + 4.0 * A.bsr_nblk + 4.0 * (nnodes + 1) + sz * A.nc + streams * sz * A.nr;
+  const double bytes = (double)A.bsr_nblk * (b * b * sz + 4) + 4.0 * (nnodes + 1) + sz * A.nc + streams * sz * A.nr;
   bytes_count(bytes);
   const bool timed = g_prof.on && !g_prof_quiet && g_prof.used < g_prof.ev.size() / 2;
   if (timed) NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used], s));
-  const unsigned blocks = (unsigned)cdiv((int64_t)nnodes * G, 256);
-#define NF_SB(BB, MM) \
-  hipLaunchKernelGGL((k_spmv_bsr<BB, G, MM, T>), dim3(blocks), dim3(256), 0, s, nnodes, A.ptr.p, A.bsr_col.p, bv, A.bsr_nblk, a)
-  if (b == 3) {
-    switch (mode) {
-      case SPMV_STORE: NF_SB(3, SPMV_STORE); break;
-      case SPMV_RESID: NF_SB(3, SPMV_RESID); break;
-      case SPMV_ADD: NF_SB(3, SPMV_ADD); break;
-      default: NF_SB(3, SPMV_SUB); break;
-    }
-  } else {
-    switch (mode) {
-      case SPMV_STORE: NF_SB(2, SPMV_STORE); break;
-      case SPMV_RESID: NF_SB(2, SPMV_RESID); break;
-      case SPMV_ADD: NF_SB(2, SPMV_ADD); break;
-      default: NF_SB(2, SPMV_SUB); break;
-    }
-  }
-#undef NF_SB
+  if (b == 2) spmv_bsr_launch<2, T>(mode, A, bv, a, s);
+  else spmv_bsr_launch<3, T>(mode, A, bv, a, s);
   if (timed) {
-    const int b2 = b <= 2 ? 2 : 4;
     NF_HIP(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s));
-    g_prof.key.push_back(((G * 16 + b2) * 100 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
+    g_prof.key.push_back(((16 * 16 + b) * 100 + (int)mode) * 10 + (sizeof(T) == 4 ? 1 : 0));
     g_prof.bytes.push_back(bytes);
     g_prof.count.push_back(1);
     ++g_prof.used;
@@ -1971,16 +1990,18 @@ void dense_sweep_apply(const T* X, int n, const T* x, int64_t ldx, const T* rb, 
     hipLaunchKernelGGL((k_dense_sweep_apply<NRMAX, T>), dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, x, ldx, rb, ldb, y, ldy, nrhs,
                        with_x ? 1 : 0);
 }
-// ---- levels made of dense B x B node blocks (elasticity, B = 2 or 3): a
-// block copy for the colour kernel, one column node per block and its B*B
-// values stored entry-major (value e of every block, then value e + 1), so
-// that the lanes of a node, which take consecutive blocks, read consecutive
-// addresses; the block row bounds of each node in colour order.
-// A matrix is made of dense b x b blocks when every row of a node holds the
-// same block columns in full: row r of node u has the length of the node's
-// first row, and its entries are, block by block, the b consecutive columns
-// of the block column that the first row has there.  Then the entries before
-// node u number b^2 times the blocks before it.
+// ---- block copies of node-blocked matrices.  A level whose matrix is made
+// of dense b x b node blocks (b = 2 or 3: elasticity, velocity) keeps a copy
+// with one column node per block and each node's values together, entry by
+// entry (entry (q, c) of all its blocks, then the next), so that the lanes
+// of a node, which take consecutive blocks, read consecutive addresses, and
+// a colour's launch reads each of its nodes' values as one stretch.
+//
+// The copy comes straight from the CSR.  A matrix passes the check when row r of
+// node u has the length of the node's first row and its entries are, block
+// by block, the b consecutive columns of the block column that the first row
+// has there; the entries before node u then number b^2 times the blocks
+// before it.
 constexpr int BSR_COPY_LANES = 16;   // lanes per row of the check and the copy
 __global__ void k_bsr_dense_check(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
                                   int* __restrict__ bad) {
@@ -1997,31 +2018,36 @@ __global__ void k_bsr_dense_check(int nr, int b, const int* __restrict__ ptr, co
   }
   if (!ok) atomicOr(bad, 1);
 }
-// the block copy of a matrix that passed the check: block (u, k) is number
-// ptr[u b] / b^2 + k; value (q, c) of it goes to bval[(q b + c) nblk + blk]
+// dense copy: block j of node u is number ptr[u b] / b^2 + j; its entry
+// (q, c) goes to the node's values at (q b + c) nu + j (nu: the node's blocks)
 template <class T>
 __global__ void k_bsr_dense_copy(int nr, int b, const int* __restrict__ ptr, const int* __restrict__ col,
-                                 const double* __restrict__ val, int64_t nblk, int* __restrict__ bcol, T* __restrict__ bval) {
+                                 const double* __restrict__ val, int* __restrict__ bcol, T* __restrict__ bval) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int r = (int)(gid / BSR_COPY_LANES), lane = (int)(gid % BSR_COPY_LANES);
   if (r >= nr) return;
   const int u = r / b, q = r % b;
   const int64_t blk0 = ptr[u * b] / (b * b);
-  const int p0 = ptr[r], len = ptr[r + 1] - p0;
+  const int p0 = ptr[r], len = ptr[r + 1] - p0, nu = len / b;
+  T* nv = bval + blk0 * b * b;
   for (int i = lane; i < len; i += BSR_COPY_LANES) {
-    const int64_t blk = blk0 + i / b;
-    const int c = i % b;
-    bval[(int64_t)(q * b + c) * nblk + blk] = (T)val[p0 + i];
-    if (q == 0 && c == 0) bcol[blk] = col[p0 + i] / b;
+    const int j = i / b, c = i % b;
+    nv[(q * b + c) * nu + j] = (T)val[p0 + i];
+    if (q == 0 && c == 0) bcol[blk0 + j] = col[p0 + i] / b;
   }
 }
-__global__ void k_bsr_node_bounds(int nnodes, const int* __restrict__ nodes, int b, const int* __restrict__ ptr,
+__global__ void k_bsr_dense_ptr(int nnodes, int b, const int* __restrict__ ptr, int* __restrict__ bptr) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u <= nnodes) bptr[u] = ptr[u * b] / (b * b);
+}
+// the block row bounds of each listed node, 2 ints per node in list order
+__global__ void k_bsr_node_bounds(int nnodes, const int* __restrict__ nodes, const int* __restrict__ bptr,
                                   int* __restrict__ bcp) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= nnodes) return;
   const int u = nodes[t];
-  bcp[2 * t] = ptr[u * b] / (b * b);
-  bcp[2 * t + 1] = ptr[(u + 1) * b] / (b * b);
+  bcp[2 * t] = bptr[u];
+  bcp[2 * t + 1] = bptr[u + 1];
 }
 
 // One colour of the Gauss-Seidel sweep from the block copy: G lanes per node,
@@ -2033,47 +2059,23 @@ __global__ void k_bsr_node_bounds(int nnodes, const int* __restrict__ nodes, int
 template <int B, int G, class T>
 __global__ __launch_bounds__(256) void k_sgs_color_bsr(int nnodes, const int* __restrict__ nodes,
                                                        const int* __restrict__ bcp, const int* __restrict__ bcol,
-                                                       const T* __restrict__ bval, int64_t nblk,
-                                                       const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
-                                                       T* __restrict__ x) {
+                                                       const T* __restrict__ bval, const T* __restrict__ dinv, T omega,
+                                                       const T* __restrict__ rhs, T* __restrict__ x) {
   const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   const int t = gid / G, lane = gid % G;
   if (t >= nnodes) return;   // whole groups of G lanes together
   const int node = nodes[t];
   const int k0 = bcp[2 * t], k1 = bcp[2 * t + 1];
-  T w = 0, rv = 0, xo = 0;
-  if (lane < B) {
-    const int64_t r = (int64_t)node * B + lane;
-    w = omega * dinv[r];
-    rv = rhs[r];
-    xo = x[r];
-  }
+  // the node's own entries, loaded by every lane (lanes past B repeat the
+  // last row's) so that no load waits on a branch
+  const int64_t r = (int64_t)node * B + (lane < B ? lane : B - 1);
+  const T dv = dinv[r], rv = rhs[r], xo = x[r];
   T acc[B];
 #pragma unroll
   for (int q = 0; q < B; ++q) acc[q] = 0;
-  for (int k = k0 + lane; k < k1; k += 2 * G) {
-    const int kb = k + G;
-    const bool hb = kb < k1;
-    const int ca = bcol[k], cb = hb ? bcol[kb] : ca;
-    T va[B * B], vb[B * B], xa[B], xb[B];
-#pragma unroll
-    for (int e = 0; e < B * B; ++e) {
-      va[e] = bval[(int64_t)e * nblk + k];
-      vb[e] = hb ? bval[(int64_t)e * nblk + kb] : (T)0;
-    }
-#pragma unroll
-    for (int c = 0; c < B; ++c) {
-      xa[c] = x[(int64_t)ca * B + c];
-      xb[c] = hb ? x[(int64_t)cb * B + c] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < B; ++q)
-#pragma unroll
-      for (int c = 0; c < B; ++c) {
-        acc[q] += va[q * B + c] * xa[c];
-        acc[q] += vb[q * B + c] * xb[c];
-      }
-  }
+  const int nu = k1 - k0;
+  for (int j = lane; j < nu; j += 2 * G)
+    bsr_block_rows<B, T>(j, j + G, j + G < nu, nu, bcol + k0, bval + (int64_t)k0 * B * B, x, acc);
 #pragma unroll
   for (int q = 0; q < B; ++q)
 #pragma unroll
@@ -2082,7 +2084,8 @@ __global__ __launch_bounds__(256) void k_sgs_color_bsr(int nnodes, const int* __
 #pragma unroll
   for (int q = 1; q < B; ++q)
     if (lane == q) a = acc[q];
-  if (lane < B) x[(int64_t)node * B + lane] = xo + w * (rv - a);
+  const T w = omega * dv;
+  if (lane < B) x[r] = xo + w * (rv - a);
 }
 
 template <class T> static DBuf<T>& bsr_store(DCsr& A);
@@ -2090,63 +2093,90 @@ template <> DBuf<double>& bsr_store<double>(DCsr& A) { return A.bsr_val; }
 template <> DBuf<float>& bsr_store<float>(DCsr& A) { return A.bsr_val32; }
 static std::mutex g_bsr_mu;
 
-template <class T>
-bool sgs_bsr_setup(const DCsr& A_, int b, const int* nodes, int nnodes, DBuf<int>& bcp, hipStream_t s) {
-  DCsr& A = const_cast<DCsr&>(A_);   // the copy is kept with the matrix
-  if ((b != 2 && b != 3) || nnodes <= 0 || A.nnz <= 0 || A.nr != nnodes * b || A.nc != A.nr) return false;
-  if (A.nnz % (b * b) != 0) return false;
-  std::lock_guard<std::mutex> lock(g_bsr_mu);   // smoothers of one matrix set up side by side
-  DBuf<T>& bval = bsr_store<T>(A);
-  if (!bval.p) {
+// the copy of A in precision T (and its structure, shared by both
+// precisions); false, keeping nothing new, when some node block of A is not
+// full
+template <class T> static bool bsr_build(DCsr& A, int b, hipStream_t s) {
+  if ((b != 2 && b != 3) || A.nnz % ((int64_t)b * b) != 0) return false;
+  const int nnodes = A.nr / b;
+  const unsigned rows_grid = (unsigned)cdiv((int64_t)A.nr * BSR_COPY_LANES, 256);
+  {
     DBuf<int> bad(1);
     fill<int>(bad.p, 0, 1, s);
-    const unsigned rows_grid = (unsigned)cdiv((int64_t)A.nr * BSR_COPY_LANES, 256);
     hipLaunchKernelGGL(k_bsr_dense_check, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, bad.p);
     int h = 1;
     NF_HIP(hipMemcpyAsync(&h, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
     NF_HIP(hipStreamSynchronize(s));
-    if (h) return false;   // some block not full
-    const int64_t nblk = A.nnz / (b * b);
-    if (!A.bsr_col.p) A.bsr_col.alloc(nblk);
-    bval.alloc((size_t)nblk * b * b);
-    hipLaunchKernelGGL(k_bsr_dense_copy<T>, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, A.val.p, nblk,
-                       A.bsr_col.p, bval.p);
-    NF_HIP(hipGetLastError());
-    NF_HIP(hipStreamSynchronize(s));   // complete before another stream's smoother may reuse it
-    A.bsr_nblk = nblk;
-    A.bsr_b = b;
+    if (h) return false;
   }
-  bcp.alloc((size_t)2 * nnodes);
-  hipLaunchKernelGGL(k_bsr_node_bounds, dim3(cdiv(nnodes, 256)), dim3(256), 0, s, nnodes, nodes, b, A.ptr.p, bcp.p);
+  const int64_t nblk = A.nnz / (b * b);
+  DBuf<T>& bval = bsr_store<T>(A);
+  A.bsr_ptr.alloc((size_t)nnodes + 1);
+  hipLaunchKernelGGL(k_bsr_dense_ptr, dim3(cdiv(nnodes + 1, 256)), dim3(256), 0, s, nnodes, b, A.ptr.p, A.bsr_ptr.p);
+  A.bsr_col.alloc(nblk);
+  bval.alloc((size_t)nblk * b * b);
+  hipLaunchKernelGGL(k_bsr_dense_copy<T>, dim3(rows_grid), dim3(256), 0, s, A.nr, b, A.ptr.p, A.col.p, A.val.p,
+                     A.bsr_col.p, bval.p);
+  A.bsr_nblk = nblk;
   NF_HIP(hipGetLastError());
+  NF_HIP(hipStreamSynchronize(s));   // complete before another stream's smoother may read it
+  A.bsr_b = b;
   return true;
 }
 
 template <class T>
-void sgs_sweep_bsr(int b, const int* nodes, const int* bcp, const int* bcol, const T* bval, int64_t nblk,
-                   const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs, T* x, hipStream_t s) {
+bool sgs_bsr_setup(const DCsr& A_, int b, const int* nodes, int nnodes, DBuf<int>& bcp, hipStream_t s) {
+  DCsr& A = const_cast<DCsr&>(A_);   // the copy is kept with the matrix
+  if (b < 2 || b > 3 || nnodes <= 0 || A.nnz <= 0 || A.nr != nnodes * b || A.nc != A.nr) return false;
+  {
+    std::lock_guard<std::mutex> lock(g_bsr_mu);   // smoothers of one matrix set up side by side
+    if (!bsr_store<T>(A).p) {
+      if (A.bsr_b) {   // the other precision's copy: same structure, values again
+        const int b0 = A.bsr_b;
+        A.bsr_b = 0;
+        if (!bsr_build<T>(A, b0, s)) return false;
+      } else if (!bsr_build<T>(A, b, s)) {
+        return false;
+      }
+    }
+  }
+  bcp.alloc((size_t)2 * nnodes);
+  hipLaunchKernelGGL(k_bsr_node_bounds, dim3(cdiv(nnodes, 256)), dim3(256), 0, s, nnodes, nodes, A.bsr_ptr.p, bcp.p);
+  NF_HIP(hipGetLastError());
+  return true;
+}
+
+template <int B, class T>
+static void sgs_bsr_launch(const int* nodes, const int* bcp, const DCsr& A, const T* bv, int m, const T* dinv, T omega,
+                           const T* rhs, T* x, hipStream_t s) {
+  constexpr int G = SGS_BSR_LANES;
+  const unsigned blocks = (unsigned)cdiv((int64_t)m * G, 256);
+  hipLaunchKernelGGL((k_sgs_color_bsr<B, G, T>), dim3(blocks), dim3(256), 0, s, m, nodes, bcp, A.bsr_col.p, bv, dinv,
+                     omega, rhs, x);
+}
+
+template <class T>
+void sgs_sweep_bsr(const DCsr& A, const int* nodes, const int* bcp, const std::vector<int>& off, bool forward,
+                   const T* dinv, T omega, const T* rhs, T* x, hipStream_t s) {
   const int nc = (int)off.size() - 1;
-  constexpr int G = 16;
+  const T* bv = bsr_values<T>(A);
+  NF_CHECK(A.bsr_b && bv, NFIELD_EINVAL, "Gauss-Seidel: the matrix has no block copy");
   for (int i = 0; i < nc; ++i) {
     const int c = forward ? i : nc - 1 - i;
     const int m = off[c + 1] - off[c];
     if (m <= 0) continue;
-    const unsigned blocks = (unsigned)cdiv((int64_t)m * G, 256);
-    if (b == 3)
-      hipLaunchKernelGGL((k_sgs_color_bsr<3, G, T>), dim3(blocks), dim3(256), 0, s, m, nodes + off[c],
-                         bcp + (int64_t)2 * off[c], bcol, bval, nblk, dinv, omega, rhs, x);
-    else
-      hipLaunchKernelGGL((k_sgs_color_bsr<2, G, T>), dim3(blocks), dim3(256), 0, s, m, nodes + off[c],
-                         bcp + (int64_t)2 * off[c], bcol, bval, nblk, dinv, omega, rhs, x);
+    const int* nd = nodes + off[c];
+    const int* bc = bcp + (int64_t)2 * off[c];
+    if (A.bsr_b == 2) sgs_bsr_launch<2, T>(nd, bc, A, bv, m, dinv, omega, rhs, x, s);
+    else sgs_bsr_launch<3, T>(nd, bc, A, bv, m, dinv, omega, rhs, x, s);
   }
 }
 template bool sgs_bsr_setup<double>(const DCsr&, int, const int*, int, DBuf<int>&, hipStream_t);
 template bool sgs_bsr_setup<float>(const DCsr&, int, const int*, int, DBuf<int>&, hipStream_t);
-template void sgs_sweep_bsr<double>(int, const int*, const int*, const int*, const double*, int64_t,
-                                    const std::vector<int>&, bool, const double*, double, const double*, double*,
-                                    hipStream_t);
-template void sgs_sweep_bsr<float>(int, const int*, const int*, const int*, const float*, int64_t,
-                                   const std::vector<int>&, bool, const float*, float, const float*, float*, hipStream_t);
+template void sgs_sweep_bsr<double>(const DCsr&, const int*, const int*, const std::vector<int>&, bool, const double*,
+                                    double, const double*, double*, hipStream_t);
+template void sgs_sweep_bsr<float>(const DCsr&, const int*, const int*, const std::vector<int>&, bool, const float*,
+                                   float, const float*, float*, hipStream_t);
 
 template void dense_sweep_apply<double>(const double*, int, const double*, int64_t, const double*, int64_t, double*, int64_t,
                                         int, bool, hipStream_t);

@@ -143,9 +143,10 @@ int sgs_lanes(const DCsr& A, int b);   // lanes per row of the Gauss-Seidel kern
 // levels), SGS_NODE = one workgroup per node (long rows), SGS_COLOR = one
 // lane group per node, a launch per colour
 enum { SGS_COLOR = 0, SGS_SWEEP1 = 1, SGS_NODE = 2 };
-// levels of at least this many nodes made of dense 2 x 2 or 3 x 3 blocks
-// relax from a block copy (one right-hand side)
+// levels of at least this many nodes with a block copy relax from it (one
+// right-hand side)
 constexpr int SGS_BSR_MIN_NODES = 4096;
+constexpr int SGS_BSR_LANES = 16;   // lanes per node of the block-copy colour kernel
 constexpr int64_t SGS_SWEEP1_MAX_NNZ = 65536;
 constexpr int64_t SGS_SWEEP1_MAX_ROW = 128;
 constexpr int SGS_SWEEP1_MAX_NODES = 65536;
@@ -163,16 +164,15 @@ template <class T> void dense_sweep_apply(const T* X, int n, const T* x, int64_t
 // one sweep over all colours (forward: ascending colour order), nodes grouped
 // by colour with colour c owning nodes[off[c], off[c+1]) (off also on the
 // device as off_dev; cptr from sgs_node_ptrs over the whole list)
-// Levels made of dense b x b node blocks (b = 2 or 3): the block copy kept
-// with A (DCsr::bsr_*, built once per precision) and the block row bounds of
-// each listed node for the colour kernel (2 ints per node in list order);
-// false, keeping nothing, when some block of A is not full
+// The block copy of a level made of dense b x b node blocks (b = 2 or 3) for
+// its Gauss-Seidel colour kernel (kept with A, built once per precision) and
+// the block row bounds of each listed node (2 ints per node in list order);
+// false, keeping nothing new, when some node block of A is not full
 template <class T> bool sgs_bsr_setup(const DCsr& A, int b, const int* nodes, int nnodes, DBuf<int>& bcp,
                                       hipStream_t s);
-// one sweep over all colours from the block copy (one right-hand side)
-template <class T> void sgs_sweep_bsr(int b, const int* nodes, const int* bcp, const int* bcol, const T* bval,
-                                      int64_t nblk, const std::vector<int>& off, bool forward, const T* dinv, T omega,
-                                      const T* rhs, T* x, hipStream_t s);
+// one sweep over all colours from A's block copy (one right-hand side)
+template <class T> void sgs_sweep_bsr(const DCsr& A, const int* nodes, const int* bcp, const std::vector<int>& off,
+                                      bool forward, const T* dinv, T omega, const T* rhs, T* x, hipStream_t s);
 template <class T> void sgs_sweep(const DCsr& A, int b, const int* nodes, const int* cptr, const int* off_dev,
                                   const std::vector<int>& off, bool forward, const T* dinv, T omega, const T* rhs,
                                   int64_t ldr, T* x, int64_t ldx, int nrhs, hipStream_t s);

@@ -236,7 +236,7 @@ struct SgsD : FieldSmootherD<T> {
     NF_HIP(hipStreamSynchronize(s));
     kind = sgs_kind(*A, b, nn, nc);
     bsr = kind == SGS_COLOR && nn >= SGS_BSR_MIN_NODES && sgs_bsr_setup<T>(*A, b, nodes.p, nn, bcp, s);
-    const double nblk = bsr ? (double)A->bsr_nblk : 0.0;
+    const double nblk = bsr ? (double)A->bsr_nblk : 0.0, slots = (double)b * b;
     // a sweep's algorithmic bytes for the solve statistics: every entry and
     // row bound once (a block copy: every value, one column per block and two
     // bounds per node), node ids and D^-1, and per right-hand side the rhs,
@@ -244,7 +244,7 @@ struct SgsD : FieldSmootherD<T> {
     {
       const double sz = sizeof(T);
       stat_bytes = (double)A->nnz * (sz + 4) + 4.0 * (b + 2) * nn + sz * n;
-      stat_bytes_bsr = (double)A->nnz * sz + 4.0 * nblk + 12.0 * nn + sz * n;
+      stat_bytes_bsr = nblk * (slots * sz + 4.0) + 12.0 * nn + sz * n;
       stat_bytes_x = 4.0 * sz * n;
     }
     // per-launch bytes with the distinct columns of every colour, counted
@@ -254,11 +254,21 @@ struct SgsD : FieldSmootherD<T> {
     if (prof_recording()) {
       std::vector<int64_t> cnnz, ccols;
       color_traffic(*A, b, nodes.p, off, cnnz, ccols, s);
+      std::vector<int> hp;
+      if (bsr) {   // blocks of each colour, from the block row bounds
+        hp.resize((size_t)nn + 1);
+        NF_HIP(hipMemcpyAsync(hp.data(), A->bsr_ptr.p, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, s));
+        NF_HIP(hipStreamSynchronize(s));
+      }
       const double sz = sizeof(T);
       for (int c = 0; c < nc; ++c) {
         const double rows = (double)(off[c + 1] - off[c]) * b;
         sweep_bytes += cnnz[c] * (sz + 4) + 4.0 * (b + 2) * (off[c + 1] - off[c]) + rows * sz;
-        sweep_bytes_bsr += cnnz[c] * sz + 4.0 * cnnz[c] / ((double)b * b) + 12.0 * (off[c + 1] - off[c]) + rows * sz;
+        if (bsr) {
+          double blocks = 0.0;
+          for (int t = off[c]; t < off[c + 1]; ++t) blocks += hp[list[t] + 1] - hp[list[t]];
+          sweep_bytes_bsr += blocks * (slots * sz + 4.0) + 12.0 * (off[c + 1] - off[c]) + rows * sz;
+        }
         sweep_bytes_x += rows * 3 * sz + sz * ccols[c];
       }
     }
@@ -273,13 +283,12 @@ struct SgsD : FieldSmootherD<T> {
     const bool blocks = bsr && nrhs == 1;
     bytes_count((blocks ? stat_bytes_bsr : stat_bytes) + nrhs * stat_bytes_x);
     const int slot = prof_begin(s);
-    if (blocks) {
-      const T* bv = sizeof(T) == sizeof(double) ? (const T*)A->bsr_val.p : (const T*)A->bsr_val32.p;
-      sgs_sweep_bsr<T>(b, nodes.p, bcp.p, A->bsr_col.p, bv, A->bsr_nblk, off, forward, dinv.p, omega, rhs, x, s);
-    }
+    if (blocks) sgs_sweep_bsr<T>(*A, nodes.p, bcp.p, off, forward, dinv.p, omega, rhs, x, s);
     else sgs_sweep<T>(*A, b, nodes.p, cptr.p, off_dev.p, off, forward, dinv.p, omega, rhs, ldr, x, ldx, nrhs, s);
-    const int b2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
-    const int lanes = blocks ? 16 : kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
+    // rows field of the key: the node-group size (a power of two), or for a
+    // block copy its block size
+    const int b2 = blocks ? b : b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : 8;
+    const int lanes = blocks ? SGS_BSR_LANES : kind == SGS_NODE ? 256 / b2 : sgs_lanes(*A, b);
     const int mode = blocks ? 11 : kind == SGS_SWEEP1 ? 7 : kind == SGS_NODE ? 8 : 6;
     int launches = kind == SGS_SWEEP1 ? 1 : 0;
     if (kind != SGS_SWEEP1)

@@ -372,15 +372,16 @@ KERNEL_NAMES[7] = "k_sgs_sweep1<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[8] = "k_sgs_node<{lanes}, {rows}, 1, {t}>"
 KERNEL_NAMES[9] = "k_dense_sweep_apply<1, {t}>"
 KERNEL_NAMES[10] = "k_dd_sweep<{lanes}, {rows}, 1, {t}>"
-KERNEL_NAMES[11] = "k_sgs_color_bsr<{b}, {lanes}, {t}>"
 
 
 def kernel_name(p):
     mode = [k for k, v in SPMV_MODES.items() if v == p["mode"]][0]
-    if mode < 6 and p["rows"] > 0:   # an SpMV from a matrix's block copy
-        return "k_spmv_bsr<{b}, {lanes}, {m}, {t}>".format(b={2: 2, 4: 3}[p["rows"]], lanes=p["lanes"], m=mode,
-                                                           t="float" if p["fp32"] else "double")
-    return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"], b={2: 2, 4: 3}.get(p["rows"], p["rows"]),
+    t = "float" if p["fp32"] else "double"
+    if (mode < 6 and p["rows"] > 0) or mode == 11:   # from a matrix's block copy: rows = block size
+        if mode == 11:
+            return f"k_sgs_color_bsr<{p['rows']}, {p['lanes']}, {t}>"
+        return f"k_spmv_bsr<{p['rows']}, {p['lanes']}, {mode}, {t}>"
+    return KERNEL_NAMES[mode].format(lanes=p["lanes"], rows=p["rows"],
                                      t="float" if p["fp32"] else "double")
 
 
