@@ -236,6 +236,8 @@ template void dense_gemvm<float>(const double*, int, const float*, int64_t, floa
 // the loads past p1 masked off, so a lane's share of a typical row (at most 8
 // entries with one right-hand side) costs one round trip for the matrix and
 // one for the gathered x, instead of a chain of single-entry iterations.
+// (Masked, not clamped: a row's tail would otherwise repeat its last entry's
+// loads on most of the U positions; measured slower.)
 template <int G, int NR, class T>
 __device__ __forceinline__ void row_dot(int p0, int p1, const int* __restrict__ col, const T* __restrict__ val,
                                         const T* __restrict__ x, int64_t ldx, int nrhs, T* s) {
@@ -1583,16 +1585,15 @@ int color_nodes(int n, const int* gp, const int* ga, uint64_t /*seed*/, int* col
   return h[3];
 }
 
-// D^-1 scaling, rhs and old x of row r (loaded before the row sum with one
+// D^-1, rhs and old x of row r (loaded before the row sum with one
 // right-hand side; after it with several, where the registers are scarcer)
 template <int NR, class T>
-__device__ __forceinline__ void sgs_row_load(int r, const T* __restrict__ dinv, T omega, const T* __restrict__ rhs,
-                                             int64_t ldr, const T* __restrict__ x, int64_t ldx, int nrhs, T& w, T* rv,
-                                             T* xo) {
-  w = omega * dinv[r];
+__device__ __forceinline__ void sgs_row_load(int r, const T* __restrict__ dinv, const T* __restrict__ rhs, int64_t ldr,
+                                             const T* __restrict__ x, int64_t ldx, int nrhs, T& dv, T* rv, T* xo) {
+  dv = dinv[r];
 #pragma unroll
   for (int k = 0; k < NR; ++k)
-    if (k < nrhs) {
+    if (k == 0 || k < nrhs) {
       rv[k] = rhs[k * ldr + r];
       xo[k] = x[k * ldx + r];
     }
@@ -1613,24 +1614,25 @@ __device__ __forceinline__ void sgs_node(int t, int sub, int b, const int* __res
                                          T omega, const T* __restrict__ rhs, int64_t ldr, T* __restrict__ x, int64_t ldx,
                                          int nrhs) {
   const int q = sub / G, lane = sub % G;
+  const int qc = q < b ? q : b - 1;   // rows past b (b < B2) shadow the last one
   T acc[NR], rv[NR], xo[NR];
-  T w = 0;
-  int r = 0;
+  T dv = 0;
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xo[k] = 0;
-  if (q < b) {
-    const int* cp = cptr + (int64_t)t * (b + 1) + q;
-    const int p0 = cp[0], p1 = cp[1];
-    r = nodes[t] * b + q;
-    if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
-    row_dot<G, NR, T>(p0 + lane, p1, col, val, x, ldx, nrhs, acc);
-  }
+  const int* cp = cptr + (int64_t)t * (b + 1) + qc;
+  const int p0 = cp[0], p1 = cp[1];
+  const int r = nodes[t] * b + qc;
+  // one right-hand side: the row's D^-1, rhs and old x on every lane, loaded
+  // beside the row (unconditional loads wait on no branch)
+  if (NR == 1) sgs_row_load<NR, T>(r, dinv, rhs, ldr, x, ldx, nrhs, dv, rv, xo);
+  row_dot<G, NR, T>(p0 + lane, q < b ? p1 : p0, col, val, x, ldx, nrhs, acc);   // shadow rows: nothing
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
   if (q < b && lane == 0) {
-    if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
+    if (NR > 1) sgs_row_load<NR, T>(r, dinv, rhs, ldr, x, ldx, nrhs, dv, rv, xo);
+    const T w = omega * dv;
 #pragma unroll
     for (int k = 0; k < NR; ++k)
       if (k < nrhs) x[k * ldx + r] = xo[k] + w * (rv[k] - acc[k]);
@@ -1692,25 +1694,24 @@ __global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes,
   static_assert(G * B2 == 256 && G <= 64, "one node per 256-thread workgroup");
   const int t = blockIdx.x;
   const int q = threadIdx.x / G, lane = threadIdx.x % G;
+  const int qc = q < b ? q : b - 1;   // rows past b (b < B2) shadow the last one
   T acc[NR], rv[NR], xo[NR];
-  T w = 0;
-  int r = 0;
+  T dv = 0;
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = rv[k] = xo[k] = 0;
-  if (q < b) {
-    const int* cp = cptr + (int64_t)t * (b + 1) + q;
-    const int p0 = cp[0], p1 = cp[1];
-    r = nodes[t] * b + q;
-    if (NR == 1 && lane == 0) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
-    row_dot<G, NR, T>(p0 + lane, p1, col, val, x, ldx, nrhs, acc);
-  }
+  const int* cp = cptr + (int64_t)t * (b + 1) + qc;
+  const int p0 = cp[0], p1 = cp[1];
+  const int r = nodes[t] * b + qc;
+  if (NR == 1) sgs_row_load<NR, T>(r, dinv, rhs, ldr, x, ldx, nrhs, dv, rv, xo);
+  row_dot<G, NR, T>(p0 + lane, q < b ? p1 : p0, col, val, x, ldx, nrhs, acc);   // shadow rows: nothing
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, G);
   __syncthreads();
   if (q < b && lane == 0) {
-    if (NR > 1) sgs_row_load<NR, T>(r, dinv, omega, rhs, ldr, x, ldx, nrhs, w, rv, xo);
+    if (NR > 1) sgs_row_load<NR, T>(r, dinv, rhs, ldr, x, ldx, nrhs, dv, rv, xo);
+    const T w = omega * dv;
 #pragma unroll
     for (int k = 0; k < NR; ++k)
       if (k < nrhs) x[k * ldx + r] = xo[k] + w * (rv[k] - acc[k]);
