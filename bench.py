@@ -72,11 +72,25 @@ SERVE_SPEC = "BGS(AMG)"
 SERVE_OPTS = dict(sweeps=2, order="bwd", cheb_ratio=8.0)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sgs_color_fsi3d_traffic.md")
+# HBM traffic summaries (FETCH_SIZE / WRITE_SIZE counter runs) of the
+# dominant kernel per workload, and the source segments of that kernel and
+# the helpers it inlines whose digest the summary records
+TRAFFIC_PROFILES = {
+    "fsi3d": (os.path.join(ROOT, "profiles", "k_sgs_color_fsi3d_traffic.md"),
+              [("template <int G, int NR, class T>\n__device__ __forceinline__ void row_dot(",
+                "template <int G, int MODE, int NR, class T>"),
+               ("template <int NR, class T>\n__device__ __forceinline__ void sgs_row_load(",
+                "// A whole sweep over every colour of a small level")]),
+    "lung3d": (os.path.join(ROOT, "profiles", "k_sgs_color_bsr_lung3d_traffic.md"),
+               [("template <int B, class T>\n__device__ __forceinline__ void bsr_block_rows(",
+                 "// SpMV from the block copy"),
+                ("template <int B, int G, class T>\n__global__ __launch_bounds__(256) void k_sgs_color_bsr(",
+                 "template <class T> static DBuf<T>& bsr_store(")]),
+}
 
 
-def kernel_source_digest():
-    """sha256 (first 16 hex digits) of the source of the Gauss-Seidel colour
+def kernel_source_digest(workload="fsi3d"):
+    """sha256 (first 16 hex digits) of the source of a workload's dominant
     kernel and the helpers it inlines."""
     import hashlib
     s = open(os.path.join(ROOT, "paper_1605_01522_amd", "csrc", "kernels.hip")).read()
@@ -84,20 +98,19 @@ def kernel_source_digest():
     def seg(a, b):
         i = s.index(a)
         return s[i:s.index(b, i)]
-    text = seg("template <int G, int NR, class T>\n__device__ __forceinline__ void row_dot(",
-               "template <int G, int MODE, int NR, class T>") + \
-        seg("template <int NR, class T>\n__device__ __forceinline__ void sgs_row_load(",
-            "// A whole sweep over every colour of a small level")
+    text = "".join(seg(a, b) for a, b in TRAFFIC_PROFILES[workload][1])
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
     if it is for this kernel and the kernel's source has not changed since."""
+    if workload not in TRAFFIC_PROFILES:
+        return None
     try:
-        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_PROFILE).read().splitlines()
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_PROFILES[workload][0]).read().splitlines()
                       if line.startswith(("kernel: ", "source_sha256_16: ", "traffic_bytes_per_launch: ")))
-        if fields.get("kernel") != kernel or fields.get("source_sha256_16") != kernel_source_digest():
+        if fields.get("kernel") != kernel or fields.get("source_sha256_16") != kernel_source_digest(workload):
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -242,7 +255,7 @@ def run_workload(name, steps, warmup, seed, precision_form):
     if dom:
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         kname = nfield.kernel_name(dom)
-        traffic = measured_traffic(kname) if name == "fsi3d" else None
+        traffic = measured_traffic(name, kname)
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                         frac=round(achieved / PEAK_HBM_GBS, 4),
                         traffic=None if traffic is None else round(traffic),
