@@ -236,6 +236,32 @@ def test_sgs_block_copy_parity(dev):
     assert abs(st[0]["iters"] - so["iters"]) <= 2
 
 
+def test_sgs_block_copy_fp32_precision_form(dev):
+    """The same level in the precision form: its FP32 block copy relaxes one
+    right-hand side (the kernel that ran is the FP32 block kernel), and
+    flexible GMRES around the FP32 hierarchy reaches the FP64 oracle's
+    solution."""
+    from paper_1605_01522_amd import nfield
+    _say("case Gauss-Seidel from an FP32 block copy (precision form)")
+    s = nfgen.tsi2d(nel=64, seed=1)
+    spec = "BGS(AMG[smoother=sgs,omega=0.9])"
+    opts = dict(coarse_max=200, **TSI_OPTS)
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, hier_fp32=1, **opts)
+    nfield.nfield_prof_enable(1)
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), flexible=1, rtol=1e-8)
+    torch.cuda.synchronize()
+    prof = nfield.nfield_prof_read()
+    nfield.nfield_prof_enable(0)
+    assert any(p["mode"] == "sgs_bsr" and p["fp32"] for p in prof), [(p["mode"], p["fp32"]) for p in prof]
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8)
+    res = np.linalg.norm(s.rhs[0] - s.assembled() @ x) / np.linalg.norm(s.rhs[0])
+    _say(f"  fp32 block copy: iters {st[0]['iters']} (fp64 oracle {so['iters']}), relres {res:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
 # ------------------------------------------------------------ edge cases
 def test_single_level_is_exact(dev):
     _say("case single level")
