@@ -77,7 +77,7 @@ SERVE_OPTS = dict(sweeps=2, order="bwd", cheb_ratio=8.0)
 # the helpers it inlines whose digest the summary records
 TRAFFIC_PROFILES = {
     "fsi3d": (os.path.join(ROOT, "profiles", "k_sgs_color_fsi3d_traffic.md"),
-              [("template <int G, int NR, class T>\n__device__ __forceinline__ void row_dot(",
+              [("template <int G, int NR, class T, int U = (NR == 1 ? 8 : 4)>\n__device__ __forceinline__ void row_dot(",
                 "template <int G, int MODE, int NR, class T>"),
                ("template <int NR, class T>\n__device__ __forceinline__ void sgs_row_load(",
                 "// A whole sweep over every colour of a small level")]),

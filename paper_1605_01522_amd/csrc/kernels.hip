@@ -237,11 +237,11 @@ template void dense_gemvm<float>(const double*, int, const float*, int64_t, floa
 // entries with one right-hand side) costs one round trip for the matrix and
 // one for the gathered x, instead of a chain of single-entry iterations.
 // (Masked, not clamped: a row's tail would otherwise repeat its last entry's
-// loads on most of the U positions; measured slower.)
-template <int G, int NR, class T>
+// loads on most of the U positions; measured slower.)  A larger U takes the
+// same entries in the same order per lane, in fewer rounds.
+template <int G, int NR, class T, int U = (NR == 1 ? 8 : 4)>
 __device__ __forceinline__ void row_dot(int p0, int p1, const int* __restrict__ col, const T* __restrict__ val,
                                         const T* __restrict__ x, int64_t ldx, int nrhs, T* s) {
-  constexpr int U = NR == 1 ? 8 : 4;
   for (int p = p0; p < p1; p += U * G) {
     T v[U];
     int c[U];
@@ -1692,6 +1692,10 @@ __global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes,
                                                   const T* __restrict__ dinv, T omega, const T* __restrict__ rhs, int64_t ldr,
                                                   T* __restrict__ x, int64_t ldx, int nrhs) {
   static_assert(G * B2 == 256 && G <= 64, "one node per 256-thread workgroup");
+  // with 32 lanes per row (8-row nodes: coarse elasticity levels, rows of
+  // 256-512 entries) 16 entries per lane in flight take such a row in one
+  // round instead of two
+  constexpr int SGS_NODE_U = NR == 1 ? (G <= 32 ? 16 : 8) : 4;
   const int t = blockIdx.x;
   const int q = threadIdx.x / G, lane = threadIdx.x % G;
   const int qc = q < b ? q : b - 1;   // rows past b (b < B2) shadow the last one
@@ -1703,7 +1707,7 @@ __global__ __launch_bounds__(256) void k_sgs_node(const int* __restrict__ nodes,
   const int p0 = cp[0], p1 = cp[1];
   const int r = nodes[t] * b + qc;
   if (NR == 1) sgs_row_load<NR, T>(r, dinv, rhs, ldr, x, ldx, nrhs, dv, rv, xo);
-  row_dot<G, NR, T>(p0 + lane, q < b ? p1 : p0, col, val, x, ldx, nrhs, acc);   // shadow rows: nothing
+  row_dot<G, NR, T, SGS_NODE_U>(p0 + lane, q < b ? p1 : p0, col, val, x, ldx, nrhs, acc);   // shadow rows: nothing
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
