@@ -276,7 +276,9 @@ __global__ __launch_bounds__(256) void k_spmv(int nr, const int* __restrict__ pt
   T s[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) s[k] = 0;
-  row_dot<G, NR, T>(p0 + lane, p1, col, val, x, a.ldx, nrhs, s);
+  // a wavefront per row (rows of 256 entries or more on average): 16 entries
+  // per lane in flight, so rows up to 1,024 entries take one round trip
+  row_dot<G, NR, T, (NR == 1 && G == 64) ? 16 : (NR == 1 ? 8 : 4)>(p0 + lane, p1, col, val, x, a.ldx, nrhs, s);
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
