@@ -1319,25 +1319,34 @@ static std::unique_ptr<Solver<T>> build(nfield_ctx& C, const Spec& sp, const Blo
       for (int j = f0; j < f1; ++j)
         if (S->sweeps > 1 || (i == g) != (j == g)) need_fp32<T>(A, i, j, s);
     const int n1 = o[g] - o[f0], n2 = A.size[g];
-    DBuf<double> dt;
-    auto Sm = std::make_shared<DCsr>();
-    simple_parts(A, f0, g, C.o.simplec_mode, dt, *Sm, s);
-    S->dtinv.alloc(n1 > 0 ? n1 : 1);
-    if (sizeof(T) == sizeof(double)) NF_HIP(hipMemcpyAsync(S->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
-    else cast_copy<double, float>(dt.p, (float*)S->dtinv.p, n1, s);
-    auto Bm = std::make_unique<BlockMat>();
-    Bm->N = 1;
-    Bm->size = {n2};
-    Bm->blk = {Sm};
-    if (sizeof(T) == sizeof(float)) prepare_fp32(*Bm, s);
     std::vector<FieldDev> Fs = {F[g]};
     Spec def;
     def.name = n2 <= C.o.schur_direct_max ? "LU" : "AMG";
     const Spec& ssp = sp.kids.size() == 2 ? sp.kids[1] : def;
-    const BlockMat& B1 = *Bm;
+    // the predictor needs only the predictor blocks: its set-up runs beside
+    // the Schur part's, which first forms D~ and S~
+    std::unique_ptr<BlockMat> Bm;
+    SimpleSolverD<T>* Sp = S.get();
+    const int mode = C.o.simplec_mode;
     std::vector<BuildTask<T>> tasks;
     tasks.push_back([&C, &sp, &A, &F, f0, g](hipStream_t st) { return build<T>(C, sp.kids[0], A, F, f0, g, st); });
-    tasks.push_back([&C, &ssp, &B1, &Fs](hipStream_t st) { return build<T>(C, ssp, B1, Fs, 0, 1, st); });
+    tasks.push_back([&C, &ssp, &A, &Fs, &Bm, Sp, f0, g, n1, n2, mode](hipStream_t st) {
+      DBuf<double> dt;
+      auto Sm = std::make_shared<DCsr>();
+      simple_parts(A, f0, g, mode, dt, *Sm, st);
+      Sp->dtinv.alloc(n1 > 0 ? n1 : 1);
+      if (sizeof(T) == sizeof(double))
+        NF_HIP(hipMemcpyAsync(Sp->dtinv.p, dt.p, sizeof(double) * n1, hipMemcpyDeviceToDevice, st));
+      else cast_copy<double, float>(dt.p, (float*)Sp->dtinv.p, n1, st);
+      Bm = std::make_unique<BlockMat>();
+      Bm->N = 1;
+      Bm->size = {n2};
+      Bm->blk = {Sm};
+      if (sizeof(T) == sizeof(float)) prepare_fp32(*Bm, st);
+      auto out = build<T>(C, ssp, *Bm, Fs, 0, 1, st);
+      NF_HIP(hipStreamSynchronize(st));   // dt is freed on return
+      return out;
+    });
     auto kids = build_children<T>(C, tasks, s);
     S->pred = std::move(kids[0]);
     S->schur = std::move(kids[1]);
