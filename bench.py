@@ -125,13 +125,22 @@ def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
     # launch-shape options of the library (columns per launch sequence) do
     # not change the arithmetic and the oracle has none
     opts = {k: v for k, v in opts.items() if k in oracle.DEFAULT_OPTS}
-    t0 = time.perf_counter()
-    o = oracle.Oracle(sys_.fields, sys_.blocks, spec, **opts)
-    t_setup = time.perf_counter() - t0
-    its = max(1, min(budget_its, gpu_iters))
-    t0 = time.perf_counter()
-    _, st = o.gmres(sys_.rhs[0], restart=50, maxit=its, rtol=1e-8)
-    t_its = time.perf_counter() - t0
+    # the (single-threaded) oracle pinned to one of this process's cores
+    allowed = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    core = min(allowed) if allowed else None
+    if core is not None:
+        os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        o = oracle.Oracle(sys_.fields, sys_.blocks, spec, **opts)
+        t_setup = time.perf_counter() - t0
+        its = max(1, min(budget_its, gpu_iters))
+        t0 = time.perf_counter()
+        _, st = o.gmres(sys_.rhs[0], restart=50, maxit=its, rtol=1e-8)
+        t_its = time.perf_counter() - t0
+    finally:
+        if core is not None:
+            os.sched_setaffinity(0, allowed)
     per_it = t_its / max(st["iters"], 1)
     t_solve = t_setup + per_it * gpu_iters
     host = "unknown"
@@ -145,7 +154,7 @@ def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
     return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
                 sample=f"oracle setup ({t_setup:.2f} s) + first {st['iters']} GMRES iterations "
                        f"({t_its:.2f} s) of the same system, scaled to {gpu_iters} iterations",
-                setup_s=t_setup, s_per_iter=per_it, host_cpu=host, host_threads=os.cpu_count())
+                setup_s=t_setup, s_per_iter=per_it, host_cpu=host, host_threads=os.cpu_count(), pinned_core=core)
 
 
 # the paper's own figures (other problems, other hardware): context only
