@@ -117,6 +117,34 @@ def measured_traffic(workload, kernel):
         return None
 
 
+_COPY_GBPS = None
+
+
+def measured_copy_gbps():
+    """A device-to-device copy of a 1 GiB buffer (torch, HIP events on the
+    current stream), bytes read plus written per second: what a plain
+    streaming kernel reaches on this device, beside the nominal peak."""
+    global _COPY_GBPS
+    if _COPY_GBPS is None:
+        import torch
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        _COPY_GBPS = 2 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del a, b
+        torch.cuda.empty_cache()
+    return _COPY_GBPS
+
+
 def cpu_baseline(sys_, spec, opts, gpu_iters, budget_its=20):
     """The CPU oracle on a bounded sample of the same workload: its full setup
     plus the first `budget_its` GMRES iterations, scaled to the GPU's
@@ -265,9 +293,11 @@ def run_workload(name, steps, warmup, seed, precision_form):
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         kname = nfield.kernel_name(dom)
         traffic = measured_traffic(name, kname)
+        copy = measured_copy_gbps()
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                         frac=round(achieved / PEAK_HBM_GBS, 4),
                         traffic=None if traffic is None else round(traffic),
+                        copy_gbps=round(copy, 1), frac_of_copy=round(achieved / copy, 4),
                         kernel=kname,
                         launches=dom["launches"], avg_us=round(1e3 * dom["ms"] / dom["launches"], 2),
                         bytes_per_launch=round(dom["bytes"] / dom["launches"]))
