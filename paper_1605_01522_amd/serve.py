@@ -84,6 +84,7 @@ class Server:
         self.ctx = [OrderedDict() for _ in range(self.workers)]        # key -> (NField, Batch), LRU order
         self.busy_keys = [set() for _ in range(self.workers)]
         self.bytes_est = {}                                             # key -> footprint seen
+        self.bytes_per_dof = 0.0                                        # largest footprint / n seen
         self.pending = {}                                               # (worker, key) -> bytes reserved
         self.last_use = {}                                              # (worker, key) -> use tick
         self.tick = 0
@@ -95,7 +96,14 @@ class Server:
         return sum(c[0].footprint_bytes() for w in self.ctx for c in w.values()) + sum(self.pending.values())
 
     def _estimate(self, key, n):
-        return self.bytes_est.get(key, 4000 * n)
+        """A key's footprint as measured when it was last built; before that,
+        n times the largest footprint per unknown of the contexts built so far
+        (plus 10 %), or 4,000 bytes per unknown before any was built."""
+        if key in self.bytes_est:
+            return self.bytes_est[key]
+        if self.bytes_per_dof > 0.0:
+            return int(1.1 * self.bytes_per_dof * n)
+        return 4000 * n
 
     def _make_room(self, need):
         """Idle contexts to evict, least recently used first, so that `need`
@@ -198,6 +206,7 @@ class Server:
             with self.lock:
                 self.ctx[w][key] = c
                 self.bytes_est[key] = ctx.footprint_bytes()
+                self.bytes_per_dof = max(self.bytes_per_dof, self.bytes_est[key] / max(s.n, 1))
         with self.lock:
             self.ctx[w].move_to_end(key)
             self.tick += 1

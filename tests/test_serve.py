@@ -148,3 +148,15 @@ def test_served_trace_matches_solo_bitwise():
         for k in range(it.req["nrhs"]):
             assert np.linalg.norm(B[k].cpu().numpy() - A @ it.x[k]) < 1e-8 * np.linalg.norm(B[k].cpu().numpy())
     srv.close()
+
+
+def test_estimate_before_a_keys_first_build():
+    """A key not built yet is estimated from the largest footprint per
+    unknown seen so far (plus 10 %), or 4,000 bytes per unknown before any
+    build; a built key uses its own measured footprint."""
+    srv = _server(1 << 40)
+    assert srv._estimate(16, 1600) == 4000 * 1600
+    srv.bytes_est[16] = 3_200_000            # as recorded by a build of key 16 (n = 1,600)
+    srv.bytes_per_dof = 3_200_000 / 1600
+    assert srv._estimate(16, 1600) == 3_200_000
+    assert srv._estimate(32, 3200) == int(1.1 * 2000.0 * 3200)
