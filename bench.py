@@ -404,6 +404,14 @@ def opts_text(opts):
     return ", ".join(parts)
 
 
+def profile_rows(prof, k):
+    """The k kernel variants with the most event time in the profiled pass:
+    launches, time, algorithmic bytes and GB/s, with the kernel's name."""
+    from paper_1605_01522_amd import nfield
+    return [dict(p, kernel=nfield.kernel_name(p), gbps=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1))
+            for p in sorted(prof, key=lambda p: -p["ms"])[:k]]
+
+
 def summary(name, r, steps, seed):
     """Compact record of a secondary workload run."""
     import numpy as np
@@ -416,8 +424,7 @@ def summary(name, r, steps, seed):
                 solve_ms=round(1e3 * float(np.median([t["solve_s"] for t in stats])), 3),
                 gmres_iters=stats[-1]["iters"], relres=r["relres"], footprint_mb=r["footprint_mb"],
                 roofline=r["roofline"], precision_form=r["prec"],
-                spmv_profile=[dict(p, gbps=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1)) for p in
-                              sorted(r["prof"], key=lambda p: -p["ms"])[:4]])
+                spmv_profile=profile_rows(r["prof"], 8))
 
 
 def serving(n_requests=512, seed=0, workers=4, loads=(0.5, 0.8, 1.0, 1.2), no_cache_sample=48):
@@ -577,8 +584,7 @@ def main():
         "relres": relres,
         "roofline": roofline,
         "precision_form": prec,
-        "spmv_profile": [dict(p, gbps=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1)) for p in
-                         sorted(prof, key=lambda p: -p["ms"])[:6]],
+        "spmv_profile": profile_rows(prof, 16),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, W["spec"], W["opts"], iters)
