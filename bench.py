@@ -325,7 +325,9 @@ def tsi_config0(steps=50, warmup=5, seed=0):
     A = s.assembled()
     out = {}
     for spec in ("BGS(AMG)", "AMG(BGS)", "BGS(DDGS[omega=0.79,ddmin=1])"):
-        g = NField(s.fields, s.blocks, spec, sweeps=2, order="bwd", max_rhs=1)
+        # a small, launch-bound system: the preconditioner replayed as a HIP
+        # graph captured after each rebuild (5.9 -> 5.5 ms per BGS(AMG) step)
+        g = NField(s.fields, s.blocks, spec, sweeps=2, order="bwd", max_rhs=1, graphs=1)
         x = torch.zeros_like(b)
         ts, st = [], None
         for k in range(warmup + steps):
@@ -352,7 +354,8 @@ def tsi_config0(steps=50, warmup=5, seed=0):
         g.close()
     return dict(workload=f"tsi2d: n={s.n} dofs, nnz={s.nnz()}, two backward BGS sweeps, degree-2 Chebyshev "
                          f"over [lambda/30, 1.1 lambda], coarse direct solves up to 200 dofs, FP64 GMRES(50) "
-                         f"rtol 1e-8, seed {seed}; a step = rebuild + solve; {steps} steps after {warmup} warm-up",
+                         f"rtol 1e-8, seed {seed}; a step = rebuild + solve (the preconditioner replayed as a HIP "
+                         f"graph); {steps} steps after {warmup} warm-up",
                 **out)
 
 
