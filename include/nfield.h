@@ -35,7 +35,9 @@
  * steps=1]" (symmetric multicolour Gauss-Seidel with damping omega instead of
  * Chebyshev, in the spirit of the damped Gauss-Seidel smoothers of Sec. 7;
  * "half=1": pre-smoothing sweeps the colours forward only, post-smoothing
- * backward only, instead of both sweeping forward then backward),
+ * backward only, instead of both sweeping forward then backward;
+ * "cheb_from=L", L >= 1: levels L and coarser use the Chebyshev smoother of
+ * the hierarchy's degree instead, Gauss-Seidel stays on the finer levels),
  * "AMG[smoother=ddgs,omega=0.79]" (the paper's DD(GS) smoother of Sec. 7:
  * Gauss-Seidel inside subdomains coupled additively; the subdomains are the
  * level's aggregates, relaxed in colour order, one workgroup each),

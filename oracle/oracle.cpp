@@ -1147,6 +1147,7 @@ struct SimpleSolver : Solver {
 struct Spec {
   std::string name;
   int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0, ddmin = 256;
+  int cheb_from = -1;                  // with sgs / ddgs: Chebyshev on the levels l >= cheb_from
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -1190,6 +1191,10 @@ struct Parser {
         else if (k == "ddmin") {
           sp.ddmin = atoi(v.c_str());
           if (sp.ddmin < 1) throw Error(EINVAL_, "spec: bad value " + v);
+        }
+        else if (k == "cheb_from") {
+          sp.cheb_from = atoi(v.c_str());
+          if (sp.cheb_from < 1) throw Error(EINVAL_, "spec: bad value " + v);
         }
         else throw Error(EINVAL_, "spec: unknown parameter " + k);
         if (sp.smoother == -9 || (k == "omega" && !(sp.omega > 0.0 && sp.omega < 2.0)) ||
@@ -1268,8 +1273,10 @@ static std::unique_ptr<Solver> build_amg(Ctx& C, const BlockMat& A, int f0, int 
     M.A = &L.A;
     M.cheb.resize(sub.N);
     const int nchb = M.kind == 1 ? sub.N - 1 : sub.N;
+    // Gauss-Seidel / DD(GS) down to level cheb_from - 1, Chebyshev below
+    const bool sgs_here = sgs && !(amg.cheb_from >= 1 && l >= amg.cheb_from);
     for (int i = 0; i < nchb; ++i) {
-      if (sgs) {
+      if (sgs_here) {
         if (amg.smoother == 2) M.cheb[i].setup_ddgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed, nullptr, amg.ddmin);
         else M.cheb[i].setup_sgs(L.A.at(i, i), L.bs[i], omega, steps, C.o.seed);
         M.cheb[i].half = amg.half;

@@ -736,6 +736,7 @@ struct SimpleSolverD : Solver<T> {
 struct Spec {
   std::string name;
   int sweeps = -1, order = -1, degree = -1, smoother = -1, steps = -1, half = 0, pg = 0, ddmin = 256;
+  int cheb_from = -1;   // Gauss-Seidel / DD(GS) hierarchies: Chebyshev on levels >= cheb_from
   double omega = -1.0;
   std::vector<Spec> kids;
 };
@@ -788,6 +789,9 @@ static Spec parse_spec(const std::string& str) {
         } else if (k == "ddmin") {
           sp.ddmin = atoi(v.c_str());
           NF_CHECK(sp.ddmin >= 1, NFIELD_EINVAL, "spec: ddmin must be >= 1");
+        } else if (k == "cheb_from") {
+          sp.cheb_from = atoi(v.c_str());
+          NF_CHECK(sp.cheb_from >= 1, NFIELD_EINVAL, "spec: cheb_from must be >= 1");
         } else {
           throw NfError(NFIELD_EINVAL, "spec: unknown parameter " + k);
         }
@@ -1146,11 +1150,14 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
     M.order = smoother && smoother->order >= 0 ? smoother->order : C.o.order;
     M.kind = simple ? 1 : 0;
     const int nsm = simple ? sub.N - 1 : sub.N;   // fields with their own smoother
+    // Gauss-Seidel / DD(GS) on this level, or Chebyshev from level cheb_from on
+    const bool cheb_l = amg.cheb_from >= 1 && l >= amg.cheb_from;
+    const bool sgs_l = sgs && !cheb_l, dd_l = dd && !cheb_l;
     for (int i = 0; i < nsm; ++i) {
       NF_CHECK(L.dinv[i] != nullptr, NFIELD_ESINGULAR, "Chebyshev smoother: zero diagonal entry");
-      if (dd && l == 0 && sgs0[i]) {
+      if (dd_l && l == 0 && sgs0[i]) {
         M.cheb.push_back(std::move(sgs0[i]));
-      } else if (dd) {
+      } else if (dd_l) {
         const bool have = i < (int)L.gptr.size() && L.gptr[i] && L.gadj[i];
         const bool hagg = i < (int)L.agg.size() && L.agg[i];
         auto d = std::make_unique<DdgsD<T>>();
@@ -1158,7 +1165,7 @@ static std::unique_ptr<Solver<T>> build_amg(nfield_ctx& C, const BlockMat& A, co
                  have ? L.gadj[i].get() : nullptr, have ? L.nnode[i] : 0, hagg && have ? L.agg[i].get() : nullptr,
                  amg.half, amg.ddmin);
         M.cheb.push_back(std::move(d));
-      } else if (sgs) {
+      } else if (sgs_l) {
         if (l == 0 && sgs0[i]) {
           M.cheb.push_back(std::move(sgs0[i]));
         } else {

@@ -84,5 +84,6 @@ def test_host_validation_rejects_malformed_input():
     assert _setup_code(s.fields, wrong, "BGS(AMG)") == -1
     # malformed specifications
     for spec in ["BGS(AMG", "FOO(AMG)", "BGS[sweeps=0](AMG)", "BGS(AMG))", "BGS[order=up](AMG)",
-                 "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])", "BGS(AMG[degree=0])"]:
+                 "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])", "BGS(AMG[degree=0])",
+                 "BGS(AMG[smoother=sgs,cheb_from=0])"]:
         assert _setup_code(s.fields, s.blocks, spec) == -1, spec

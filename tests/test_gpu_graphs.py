@@ -18,6 +18,9 @@ CASES = [
     ("lung", lambda: nfgen.lung3d(n=8, depth=4, acinus=2, seed=0), "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)",
      dict(split=[0, 0, 1])),
     ("tsi-fp32", lambda: nfgen.tsi2d(nel=24, seed=3), "BGS(AMG)", dict(sweeps=2, order="bwd", hier_fp32=1)),
+    ("lung-cheb-coarse", lambda: nfgen.lung3d(n=16, depth=7, acinus=4, seed=2),
+     "SIMPLE(AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](BGS);LU)",
+     dict(split=[0, 0, 1], simplec_mode=2, coarse_max=200, cheb_ratio=8.0)),
 ]
 
 

@@ -220,15 +220,24 @@ def test_lung_amg_simple_schur_chebyshev_parity(dev):
     assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
 
 
-def test_lung_benchmarked_configuration_parity(dev):
+def _bench_lung():
+    from bench import WORKLOADS
+    W = WORKLOADS["lung3d"]
+    return W["spec"], {k: v for k, v in W["opts"].items() if k != "max_rhs"}
+
+
+@pytest.mark.parametrize("n,depth,coarse_max", [(16, 7, 200), (24, 9, 1000)])
+def test_lung_benchmarked_configuration_parity(dev, n, depth, coarse_max):
     """The lung workload's preconditioner (SIMPLE with D~ = diag(A11) around
-    the monolithic AMG(BGS) with damped Gauss-Seidel, dense S~ inverse)."""
-    _say("case lung benchmarked configuration n=16")
-    s = nfgen.lung3d(n=16, depth=7, acinus=4, seed=2)
-    spec = "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)"
-    opts = dict(simplec_mode=2, coarse_max=1000, **SPLIT)
+    the monolithic AMG(BGS), damped Gauss-Seidel on the finest level and
+    Chebyshev on the coarser ones, dense S~ inverse), on three levels."""
+    _say(f"case lung benchmarked configuration n={n} coarse_max={coarse_max}")
+    s = nfgen.lung3d(n=n, depth=depth, acinus=4, seed=2)
+    spec, opts = _bench_lung()
+    opts["coarse_max"] = coarse_max
     o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
     g = _gpu(s, spec, **opts)
+    assert o.nlevels(0) == g.nlevels(0) == 3
     r = np.random.default_rng(6).standard_normal(s.n)
     zo = o.precond_apply(r)
     zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
@@ -250,8 +259,7 @@ def test_lung_full_size_precond_parity(dev):
     the benchmarked preconditioner against the oracle's."""
     _say("case lung full size (n=64, depth=12, acinus=8) precond")
     s = nfgen.lung3d(n=64, depth=12, acinus=8, seed=0)
-    spec = "SIMPLE(AMG[smoother=sgs,omega=0.79](BGS);LU)"
-    opts = dict(simplec_mode=2, coarse_max=1000, **SPLIT)
+    spec, opts = _bench_lung()
     g = _gpu(s, spec, **opts)
     r = np.random.default_rng(6).standard_normal(s.n)
     zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()

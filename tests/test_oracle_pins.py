@@ -559,7 +559,8 @@ def test_end_to_end_tsi_full_size_vs_sparse_lu():
 # -------------------------------------------------------------- error paths
 def test_errors():
     s = nfgen.tsi2d(nel=4)
-    for spec in ["BGS(AMG", "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])"]:
+    for spec in ["BGS(AMG", "BGS(AMG[smoother=sgs,half=2])", "BGS(AMG[smoother=sgs,omega=0])",
+                 "BGS(AMG[smoother=sgs,cheb_from=0])"]:
         with pytest.raises(oracle.OracleError) as e:
             Oracle(s.fields, s.blocks, spec, sweeps=2)
         assert e.value.code == -1, spec
@@ -860,3 +861,72 @@ def test_ddgs_few_aggregates_is_one_subdomain():
     z_dd1 = Oracle(f, b, "AMG[smoother=ddgs,omega=0.9,half=1,ddmin=1]", coarse_max=30).precond_apply(r)
     assert np.array_equal(z_sgs, z_dd)
     assert np.abs(z_dd1 - z_sgs).max() > 1e-8 * np.abs(z_sgs).max()
+
+
+@pytest.mark.parametrize("half,degree", [(0, 2), (1, 3)])
+def test_cheb_from_vcycle_dense_composition(half, degree):
+    """cheb_from=1: multicolour Gauss-Seidel on the finest level, Chebyshev on
+    the coarser ones.  The preconditioner equals the V(1,1) cycle (Sec. 3.1)
+    composed from dense matrices of the oracle's hierarchy: the colour SOR
+    splittings on level 0, the Chebyshev error polynomial
+    T_k((theta - D^-1 A) / delta) / T_k(theta / delta) of the matrix D^-1 A
+    on level 1 (matrix recurrence), an exact solve on level 2."""
+    s = nfgen.tsi2d(nel=16)
+    omega, ratio, boost = 0.9, 8.0, 1.1
+    spec = f"AMG[smoother=sgs,omega={omega},half={half},cheb_from=1,degree={degree}]"
+    o = Oracle([s.fields[0]], [[s.blocks[0][0]]], spec, coarse_max=20, cheb_ratio=ratio)
+    assert o.nlevels(0) == 3
+    A = [o.matrix(0, l, "A").toarray() for l in range(3)]
+    P = [o.matrix(0, l, "P").toarray() for l in range(2)]
+    R = [o.matrix(0, l, "R").toarray() for l in range(2)]
+    # level 0: forward / backward colour splittings
+    b0 = o.block_size(0, 0)
+    gp, ga = oracle.node_graph(o.matrix(0, 0, "A"), b0)
+    col, _ = oracle.color_nodes(gp, ga, 0)
+    cr = np.repeat(col, b0)
+    D = np.diag(np.diag(A[0]))
+    Lf = np.where(cr[None, :] < cr[:, None], A[0], 0.0)
+    Lb = np.where(cr[None, :] > cr[:, None], A[0], 0.0)
+
+    def fwd(x, b):
+        return np.linalg.solve(D / omega + Lf, b + (D / omega - A[0] + Lf) @ x)
+
+    def bwd(x, b):
+        return np.linalg.solve(D / omega + Lb, b + (D / omega - A[0] + Lb) @ x)
+
+    # level 1: Chebyshev error polynomial of D^-1 A
+    lam = o.lam(0, 1)
+    hi, lo = boost * lam, lam / ratio
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    M1 = np.diag(1.0 / np.diag(A[1])) @ A[1]
+    Y = (th * np.eye(len(M1)) - M1) / de
+    Tm, T = np.eye(len(M1)), Y
+    for _ in range(degree - 1):
+        Tm, T = T, 2 * Y @ T - Tm
+    E1 = T / np.cosh(degree * np.arccosh(th / de))
+
+    def cheb(x, b):
+        xs = np.linalg.solve(A[1], b)
+        return xs - E1 @ (xs - x)
+
+    def vcycle(l, b):
+        if l == 2:
+            return np.linalg.solve(A[2], b)
+        z = np.zeros_like(b)
+        if l == 0:
+            x = fwd(z, b) if half else bwd(fwd(z, b), b)
+        else:
+            x = cheb(z, b)
+        x = x + P[l] @ vcycle(l + 1, R[l] @ (b - A[l] @ x))
+        if l == 0:
+            return bwd(x, b) if half else bwd(fwd(x, b), b)
+        return cheb(x, b)
+
+    n = A[0].shape[0]
+    want = np.stack([vcycle(0, e) for e in np.eye(n)])
+    got = o.precond_apply(np.eye(n))
+    assert np.abs(got - want).max() < 1e-10 * np.abs(want).max()
+    # Chebyshev on level 1 does change the result
+    plain = Oracle([s.fields[0]], [[s.blocks[0][0]]], f"AMG[smoother=sgs,omega={omega},half={half}]",
+                   coarse_max=20, cheb_ratio=ratio).precond_apply(np.eye(n))
+    assert np.abs(plain - got).max() > 1e-6 * np.abs(got).max()
