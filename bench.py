@@ -8,12 +8,16 @@ rtol 1e-8.  value = steps per second (solves/s, setup included, as the
 paper's times include the preconditioner setup).
 
 Besides the main workload the line carries a "lung" record (the lung-like
-saddle system, SIMPLE(AMG(BGS);LU)) and a "serving" record (continuous
-batching of 512 TSI-like requests against sequential plain FP64 solves).
+saddle system, SIMPLE(AMG(BGS);LU)), a "lung_monolithic" record (AMG(SIMPLE)
+with coupled coarse levels on the lung-like system with 8 constraints), the
+TSI-like system's own timing, the coupling-strength sweep and a "serving"
+record (continuous batching of 512 TSI-like requests against sequential
+plain FP64 solves).
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 [--workload fsi3d|tsi2d|lung3d] [--no-cpu-baseline] [--no-precision-form]
-[--no-lung] [--no-serving]
+[--no-lung] [--no-lung-mono] [--no-tsi] [--no-alpha-sweep] [--no-variants]
+[--no-serving]
 """
 import argparse
 import json
@@ -361,6 +365,63 @@ def tsi_config0(steps=50, warmup=5, seed=0):
                 **out)
 
 
+# monolithic AMG over all three lung-like fields with SIMPLE as the level
+# smoother (the multipliers not coarsened, every coarse level carrying the
+# coupling blocks R_i A_ij P_j), on the full-size tissue and a depth-3 airway
+# tree: 8 acinus constraints, a few as in the paper's lung, against the 4,096
+# of the lung3d workload, where the coarse levels have fewer tissue dofs
+# than constraints and AMG(SIMPLE) does not converge
+LUNG_MONO = dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=3, acinus=8, seed=seed),
+                 specs=("AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](SIMPLE)",
+                        "SIMPLE(AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](BGS);LU)"),
+                 opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000, cheb_ratio=8.0, max_rhs=1))
+
+
+def lung_monolithic(steps=5, warmup=1, seed=0):
+    """AMG(SIMPLE) with coupled coarse levels on the lung-like system with 8
+    constraints, beside SIMPLE(AMG(BGS);LU) on the same system: iterations,
+    median step time (rebuild + solve), the hierarchy's level sizes per field
+    and the nonzeros of the coarse coupling blocks tissue-multiplier and
+    airway-multiplier on every level."""
+    import numpy as np
+    import torch
+    from paper_1605_01522_amd.nfield import NField
+    s = LUNG_MONO["make"](seed)
+    b = torch.tensor(s.rhs[0], device="cuda")
+    A = s.assembled()
+    out = {}
+    for spec in LUNG_MONO["specs"]:
+        g = NField(s.fields, s.blocks, spec, **LUNG_MONO["opts"])
+        x = torch.zeros_like(b)
+        ts, st = [], None
+        for k in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.rebuild()
+            x.zero_()
+            _, st = g.gmres_solve(b, x, rtol=1e-8, maxit=1000)
+            torch.cuda.synchronize()
+            if k >= warmup:
+                ts.append(time.perf_counter() - t0)
+        xs = x.cpu().numpy()
+        rec = dict(gmres_iters=st[0]["iters"], status=st[0]["status"],
+                   median_ms_per_step=round(1e3 * float(np.median(ts)), 3),
+                   solves_per_s=round(len(ts) / sum(ts), 2),
+                   setup_ms=round(1e3 * st[0]["setup_s"], 3), solve_ms=round(1e3 * st[0]["solve_s"], 3),
+                   relres=float(np.linalg.norm(s.rhs[0] - A @ xs) / np.linalg.norm(s.rhs[0])),
+                   level_sizes=[[g.level_size(0, l, f) for f in range(g.nfields(0))] for l in range(g.nlevels(0))])
+        if spec.startswith("AMG"):
+            nf = g.nfields(0)
+            rec["coupled_coarse_nnz"] = [[g.matrix(0, l, "A", i, nf - 1).nnz for i in range(nf - 1)]
+                                         for l in range(g.nlevels(0))]
+        out[spec] = rec
+        g.close()
+    return dict(workload=f"lung3d with 8 constraints: n={s.n} dofs ({', '.join(str(f.ndof) for f in s.fields)}), "
+                         f"nnz={s.nnz()}, {opts_text(LUNG_MONO['opts'])}, FP64 GMRES(50) rtol 1e-8, seed {seed}; "
+                         f"a step = rebuild + solve; {steps} steps after {warmup} warm-up",
+                **out)
+
+
 def alpha_sweep(steps=3, seed=0):
     """Coupling-strength sweep on the TSI-like system (the paper's robustness
     experiment, Sec. 7.1): both coupling blocks scale with alpha; per alpha
@@ -547,6 +608,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
     ap.add_argument("--no-tsi", action="store_true", help="skip the TSI-like system's own timing")
     ap.add_argument("--no-alpha-sweep", action="store_true", help="skip the coupling-strength sweep")
+    ap.add_argument("--no-lung-mono", action="store_true",
+                    help="skip AMG(SIMPLE) on the lung-like system with 8 constraints")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FSI-like variants (DD(GS) fluid smoother, Petrov-Galerkin fluid AMG)")
     args = ap.parse_args()
@@ -602,6 +665,8 @@ def main():
         # the paper's own fluid components on the same system, 5 steps each
         out["variants"] = {v: summary(v, run_workload(v, 5, 1, args.seed, False), 5, args.seed)
                            for v in ("fsi3d_dd", "fsi3d_pg")}
+    if not args.no_lung_mono:
+        out["lung_monolithic"] = lung_monolithic(seed=args.seed)
     if not args.no_tsi:
         out["tsi2d"] = tsi_config0(seed=args.seed)
     if not args.no_alpha_sweep:

@@ -304,3 +304,61 @@ def test_lung_precision_form(dev):
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     _say(f"lung precision form: iters {st[0]['iters']} (fp64 oracle {so['iters']}) relres {res:.2e} err {err:.2e}")
     assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
+
+
+def _lung_mono():
+    from bench import LUNG_MONO
+    return LUNG_MONO["specs"][0], {k: v for k, v in LUNG_MONO["opts"].items() if k != "max_rhs"}
+
+
+@pytest.mark.parametrize("n,acinus,coarse_max", [(16, 4, 200), (32, 8, 1000)])
+def test_lung_few_constraints_amg_simple_parity(dev, n, acinus, coarse_max):
+    """AMG(SIMPLE) over all three fields (multipliers not coarsened, the
+    coupling blocks R_i A_ij P_j on every level, a SIMPLE step as the level
+    smoother with Gauss-Seidel / Chebyshev predictor smoothing) on a
+    lung-like system with 8 constraints: hierarchy sizes, the coarse coupling
+    blocks, one preconditioner application and the solve against the oracle."""
+    _say(f"case lung 8 constraints AMG(SIMPLE) n={n}")
+    s = nfgen.lung3d(n=n, depth=3, acinus=acinus, seed=1)
+    spec, opts = _lung_mono()
+    opts["coarse_max"] = coarse_max
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, **opts)
+    assert g.nlevels(0) == o.nlevels(0) == 3
+    for l in range(3):
+        for f in range(3):
+            assert g.level_size(0, l, f) == o.level_size(0, l, f)
+        co, cg = o.matrix(0, l, "A", 0, 2), g.matrix(0, l, "A", 0, 2)
+        assert co.nnz > 0 and cg.nnz == co.nnz
+        assert abs(cg - co).max() <= 1e-12 * abs(co).max()
+    r = np.random.default_rng(8).standard_normal(s.n)
+    zo = o.precond_apply(r)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), rtol=1e-8, maxit=500)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=500)
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    _say(f"lung 8 constraints n={n}: gpu iters {st[0]['iters']} oracle {so['iters']} relres {res:.2e}")
+    assert st[0]["status"] == 0 and so["status"] == 0 and res < 1e-8
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert abs(st[0]["iters"] - so["iters"]) <= 2
+
+
+def test_lung_few_constraints_full_size_precond_parity(dev):
+    """The lung_monolithic bench record's system at full size (811,200 tissue
+    dofs, 8 constraints): one application of AMG(SIMPLE) against the oracle."""
+    _say("case lung 8 constraints full size precond")
+    from bench import LUNG_MONO
+    s = LUNG_MONO["make"](0)
+    spec, opts = _lung_mono()
+    g = _gpu(s, spec, **opts)
+    r = np.random.default_rng(9).standard_normal(s.n)
+    zg = g.precond_apply(torch.tensor(r, device=dev)).cpu().numpy()
+    g.close()
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    zo = o.precond_apply(r)
+    err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    _say(f"lung 8 constraints full size: preconditioner relative difference {err:.2e}")
+    assert err <= 1e-9
