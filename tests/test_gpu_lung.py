@@ -362,3 +362,30 @@ def test_lung_few_constraints_full_size_precond_parity(dev):
     err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
     _say(f"lung 8 constraints full size: preconditioner relative difference {err:.2e}")
     assert err <= 1e-9
+
+
+def test_cheb_from_precision_form_and_limits(dev):
+    """cheb_from in the precision form (FP32 hierarchy, Chebyshev on level 1
+    in FP32) reaches the FP64 oracle's solution; cheb_from beyond the last
+    smoothed level gives the bits of plain Gauss-Seidel."""
+    _say("case lung cheb_from precision form")
+    s = nfgen.lung3d(n=16, depth=7, acinus=4, seed=2)
+    spec, opts = _bench_lung()
+    opts["coarse_max"] = 200
+    o = oracle.Oracle(s.fields, s.blocks, spec, **opts)
+    g = _gpu(s, spec, hier_fp32=1, **opts)
+    A = s.assembled()
+    x, st = g.gmres_solve(torch.tensor(s.rhs[0], device=dev), flexible=1, rtol=1e-8, maxit=500)
+    x = x.cpu().numpy()
+    xo, so = o.gmres(s.rhs[0], rtol=1e-8, maxit=500)
+    res = np.linalg.norm(s.rhs[0] - A @ x) / np.linalg.norm(s.rhs[0])
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"cheb_from precision form: iters {st[0]['iters']} (fp64 oracle {so['iters']}) relres {res:.2e} err {err:.2e}")
+    assert st[0]["status"] == 0 and res < 1e-8 and err < 1e-6
+    # levels 0 and 1 smoothed: cheb_from=2 leaves Gauss-Seidel on both
+    plain = spec.replace(",cheb_from=1,degree=3", "")
+    a = _gpu(s, plain, **opts)
+    b = _gpu(s, spec.replace("cheb_from=1", "cheb_from=2"), **opts)
+    assert a.nlevels(0) == 3
+    r = torch.tensor(np.random.default_rng(12).standard_normal(s.n), device=dev)
+    assert np.array_equal(a.precond_apply(r).cpu().numpy(), b.precond_apply(r).cpu().numpy())
