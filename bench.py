@@ -33,28 +33,27 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     # 3-field FSI-like system: Q1 elastic slab 40x40x8 (S), ALE vector
     # Laplacian (G) and PSPG Q1-Q1 Oseen flow (F) on a 40^3 hex box; degree-1
-    # Chebyshev on S and G, damped multicolour Gauss-Seidel on F (omega 0.85,
-    # forward sweeps before the coarse correction, backward after) and the
-    # SIMPLE diagonal D~ = diag(A11), coarse direct solves up to 2,000 dofs
-    # (the slab's second level, 1,932 dofs) and the degree-1 Chebyshev
-    # interval [lambda/4, 1.1 lambda] on S and G: the fastest of the settings
-    # measured (68 iterations; 69 with omega 0.9, 72 with [lambda/30,
-    # 1.1 lambda], 78 with coarse solves up to 200 dofs; full symmetric
-    # sweeps with omega 0.65 take fewer iterations and more time; the
-    # absolute row sums as D~ more iterations)
+    # Chebyshev on S and G, damped multicolour Gauss-Seidel on F with the
+    # paper's fluid damping omega 0.69, two forward sweeps before the coarse
+    # correction and two backward after (48 iterations, 69.3 ms per step;
+    # one sweep each way with omega 0.85: 68 and 72.4 ms; two each way with
+    # omega 0.8: 46 and 67.1 ms, 0.9: 57, 1.0: no convergence; three each way
+    # 41 iterations and 72.8 ms), the SIMPLE diagonal D~ = diag(A11), coarse
+    # direct solves up to 2,000 dofs (the slab's second level, 1,932 dofs)
+    # and the degree-1 Chebyshev interval [lambda/4, 1.1 lambda] on S and G
     "fsi3d": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
-                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])",
+                  spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.69,half=1,steps=2])",
                   opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # the same system with the paper's own fluid smoother, DD(GS) (one
     # workgroup per aggregate, Gauss-Seidel inside in colour order; levels
     # with fewer than 256 aggregates are one subdomain)
     "fsi3d_dd": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
-                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1])",
+                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.69,half=1,steps=2])",
                      opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # the same system with Petrov-Galerkin transfers on the fluid (the
     # paper's fluid AMG, after Sala and Tuminaro)
     "fsi3d_pg": dict(make=lambda seed: __import__("nfgen").fsi3d(n=40, layers=8, seed=seed),
-                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1,pg=1])",
+                     spec="SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.69,half=1,steps=2,pg=1])",
                      opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0, max_rhs=1)),
     # 2-field thermo-structure-like system on a 32x32 Q1 mesh
     "tsi2d": dict(make=lambda seed: __import__("nfgen").tsi2d(nel=32, seed=seed),
@@ -62,14 +61,17 @@ WORKLOADS = {
     # lung-like saddle system: Q1 tissue on a 64^3 box, airway tree of depth
     # 12, 4096 acinus volume constraints; outer SIMPLE (D~ = diag(A11);
     # the absolute row sums take more iterations) with the monolithic
-    # AMG(BGS) on tissue + airway: damped Gauss-Seidel (omega 0.79) on the
-    # finest level, degree-3 Chebyshev over [lambda/8, 1.1 lambda] on the
-    # coarser one (150 iterations, 309 ms per step, against 154 and 371 ms
-    # with Gauss-Seidel on both: one launch per colour on the coarse tissue
-    # level); a dense inverse of the 4096 x 4096 S~; coarse direct solves up
-    # to 1,000 dofs (three levels; four levels with 200: more set-up)
+    # AMG(BGS) on tissue + airway: damped Gauss-Seidel (the paper's omega
+    # 0.79) on the finest level, two forward sweeps before the coarse
+    # correction and two backward after, degree-3 Chebyshev over
+    # [lambda/8, 1.1 lambda] on the coarser level (127 iterations, 272 ms
+    # per step; one symmetric sweep pair each way: 150 and 308 ms; Gauss-
+    # Seidel on both levels as well: 154 and 371 ms, one launch per colour
+    # on the coarse tissue level); a dense inverse of the 4096 x 4096 S~;
+    # coarse direct solves up to 1,000 dofs (three levels; four levels with
+    # 200: more set-up)
     "lung3d": dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=12, acinus=8, seed=seed),
-                   spec="SIMPLE(AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](BGS);LU)",
+                   spec="SIMPLE(AMG[smoother=sgs,omega=0.79,half=1,steps=2,cheb_from=1,degree=3](BGS);LU)",
                    opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000, cheb_ratio=8.0, max_rhs=1)),
 }
 SERVE_SPEC = "BGS(AMG)"
@@ -372,8 +374,8 @@ def tsi_config0(steps=50, warmup=5, seed=0):
 # of the lung3d workload, where the coarse levels have fewer tissue dofs
 # than constraints and AMG(SIMPLE) does not converge
 LUNG_MONO = dict(make=lambda seed: __import__("nfgen").lung3d(n=64, depth=3, acinus=8, seed=seed),
-                 specs=("AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](SIMPLE)",
-                        "SIMPLE(AMG[smoother=sgs,omega=0.79,cheb_from=1,degree=3](BGS);LU)"),
+                 specs=("AMG[smoother=sgs,omega=0.79,half=1,steps=2,cheb_from=1,degree=3](SIMPLE)",
+                        "SIMPLE(AMG[smoother=sgs,omega=0.79,half=1,steps=2,cheb_from=1,degree=3](BGS);LU)"),
                  opts=dict(split=[0, 0, 1], simplec_mode=2, coarse_max=1000, cheb_ratio=8.0, max_rhs=1))
 
 

@@ -304,18 +304,20 @@ def test_singular_inputs(dev):
 
 # ------------------------------------------------- 3-field FSI-like system
 # the benchmarked configuration, and the ones it was tuned from
-FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])"
+FSI_SPEC = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.69,half=1,steps=2])"
+FSI_SPEC_H1 = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1])"
 FSI_SPEC_FULL = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.65])"
 FSI_SPEC_D2 = "SIMPLE(BGS(AMG);AMG[smoother=sgs,omega=0.69])"
 FSI_OPTS = dict(split=[0, 0, 1], simplec_mode=2, coarse_max=2000, cheb_ratio=4.0)
 FSI_OPTS_ABS = dict(split=[0, 0, 1])
 # the paper's own smoother on the fluid (DD(GS), subdomains = aggregates)
-FSI_SPEC_DD = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.85,half=1,ddmin=1])"
+FSI_SPEC_DD = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=ddgs,omega=0.69,half=1,steps=2,ddmin=1])"
 # Petrov-Galerkin transfers on the fluid (Sec. 7: PG-AMG for the fluid)
-FSI_SPEC_PG = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.85,half=1,pg=1])"
+FSI_SPEC_PG = "SIMPLE(BGS(AMG[degree=1]);AMG[smoother=sgs,omega=0.69,half=1,steps=2,pg=1])"
 
 
-@pytest.mark.parametrize("n,layers,spec,opts", [(6, 2, FSI_SPEC, FSI_OPTS), (6, 2, FSI_SPEC_FULL, FSI_OPTS),
+@pytest.mark.parametrize("n,layers,spec,opts", [(6, 2, FSI_SPEC, FSI_OPTS), (6, 2, FSI_SPEC_H1, FSI_OPTS),
+                                                (6, 2, FSI_SPEC_FULL, FSI_OPTS),
                                                 (6, 2, FSI_SPEC_D2, FSI_OPTS_ABS), (12, 3, FSI_SPEC, FSI_OPTS),
                                                 (12, 3, FSI_SPEC_DD, FSI_OPTS), (16, 4, FSI_SPEC_DD, FSI_OPTS),
                                                 (12, 3, FSI_SPEC_PG, FSI_OPTS), (16, 4, FSI_SPEC_PG, FSI_OPTS)])
